@@ -1,0 +1,124 @@
+"""Projected gradient (BLIP / inexact IPG) reconstruction, FP64.
+
+Test infrastructure only.
+
+Follows eq. blip (with the DCF weighting of eq. blip_dcf) and Algorithm 2:
+    Z     = X^k - mu_k A^H diag(w) (A X^k - Y)
+    X'    = P(Z)                                   (exact matched filter)
+    accept  iff  mu_k < ||X' - X^k||^2 / ||A(X' - X^k)||_W^2     (eq. steprule)
+    else    mu_k <- mu_k / zeta and project again (the gradient is unchanged)
+with X^0 = 0, mu_k reset to the initial mu at every new k (Algorithm 2 sets
+mu_k = mu for every k before any shrinkage), stop after max_iter accepted
+iterations or when the relative decrease of the objective
+f = ||Y - A X||_W^2 falls below rel_tol (Section "Numerical experiments",
+computational cost paragraph).  With w = 1 the weighted norms are the plain
+ones.  Edge readings: Delta X = 0 accepts and stops (fixed point);
+||A Delta X|| = 0 with Delta X != 0 accepts.  The optional non-expansive
+safeguard keeps X^k_v where it is closer to Z_v than the projection
+(footnote to eq. nonexpansive); the optional kappa rescaling multiplies X^1
+and mu by ||Y|| / ||A X^1|| after the first iteration.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import fourier, mf
+
+
+class NoConvergence(RuntimeError):
+    pass
+
+
+def _weighted_sq(r: np.ndarray, w) -> float:
+    a = np.abs(r) ** 2
+    return float(np.sum(a if w is None else np.asarray(w, dtype=np.float64) * a))
+
+
+def project(Z: np.ndarray, atoms: np.ndarray, warm_idx=None, X_prev=None,
+            nonexpansive: bool = False):
+    """Cone projection of a frame-major image Z [S][L][ny][nx]."""
+    S, L, ny, nx = Z.shape
+    Zv = fourier.frame_to_voxel(Z)
+    res = mf.exact_mf(Zv, atoms, warm_idx=warm_idx, want_X=True)
+    Xv = res["X"]
+    if nonexpansive and X_prev is not None:
+        Xp = fourier.frame_to_voxel(X_prev)
+        keep = np.sum(np.abs(Xp - Zv) ** 2, axis=1) < np.sum(np.abs(Xv - Zv) ** 2, axis=1)
+        Xv = np.where(keep[:, None], Xp, Xv)
+        res["kept_previous"] = keep
+    return fourier.voxel_to_frame(Xv, S, ny, nx), res
+
+
+def gradient(X, Y, off, idx, w):
+    S, L, ny, nx = X.shape
+    R = fourier.forward(X, off, idx) - Y
+    WR = R if w is None else np.asarray(w, dtype=np.float64) * R
+    return fourier.adjoint(WR, off, idx, S, L, ny, nx), R
+
+
+def ipg_step(Y, off, idx, atoms, X, mu: float, w=None, warm_idx=None,
+             nonexpansive: bool = False):
+    """One projected-gradient step at a fixed mu.  Returns (X', projection
+    result, stats) with stats = dx2, adx2 (weighted), f_old, f_new."""
+    Y = np.asarray(Y, dtype=np.complex128)
+    X = np.asarray(X, dtype=np.complex128)
+    G, R = gradient(X, Y, off, idx, w)
+    Z = X - mu * G
+    Xn, res = project(Z, atoms, warm_idx=warm_idx, X_prev=X, nonexpansive=nonexpansive)
+    dX = Xn - X
+    AdX = fourier.forward(dX, off, idx)
+    stats = dict(dx2=float(np.sum(np.abs(dX) ** 2)), adx2=_weighted_sq(AdX, w),
+                 f_old=_weighted_sq(R, w),
+                 f_new=_weighted_sq(fourier.forward(Xn, off, idx) - Y, w))
+    res["Z"] = Z
+    return Xn, res, stats
+
+
+def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
+              adaptive: bool = True, max_iter: int = 50, rel_tol: float = 1e-6,
+              max_shrinks: int = 30, X0=None, w=None, kappa: bool = False,
+              nonexpansive: bool = False):
+    """Full reconstruction; dims = (S, L, ny, nx).  Returns (X, idx, gamma,
+    history) where history lists per accepted iteration: f (objective after
+    the step), mu, shrinks, dx2, adx2."""
+    S, L, ny, nx = dims
+    Y = np.asarray(Y, dtype=np.complex128)
+    X = np.zeros(dims, dtype=np.complex128) if X0 is None else np.asarray(X0, dtype=np.complex128).copy()
+    warm = None
+    gamma = np.zeros(S * ny * nx)
+    f = _weighted_sq(fourier.forward(X, off, idx) - Y, w)
+    hist = []
+    mu_init = float(mu0)
+    for k in range(max_iter):
+        G, _ = gradient(X, Y, off, idx, w)
+        mu = mu_init
+        shrinks = 0
+        while True:
+            Z = X - mu * G
+            Xn, res = project(Z, atoms, warm_idx=warm, X_prev=X, nonexpansive=nonexpansive)
+            dX = Xn - X
+            dx2 = float(np.sum(np.abs(dX) ** 2))
+            adx2 = _weighted_sq(fourier.forward(dX, off, idx), w)
+            if (not adaptive) or dx2 == 0.0 or adx2 == 0.0 or mu < dx2 / adx2:
+                break
+            mu /= zeta
+            shrinks += 1
+            if shrinks > max_shrinks:
+                raise NoConvergence(f"step size not accepted after {max_shrinks} shrinks")
+        X = Xn
+        warm = res["idx"]
+        gamma = res["gamma"]
+        if kappa and k == 0:
+            kap = np.sqrt(_weighted_sq(Y, None)) / max(np.sqrt(_weighted_sq(fourier.forward(X, off, idx), None)), 1e-300)
+            X = X * kap
+            gamma = gamma * kap
+            mu_init *= kap
+        f_new = _weighted_sq(fourier.forward(X, off, idx) - Y, w)
+        hist.append(dict(f=f_new, mu=mu, shrinks=shrinks, dx2=dx2, adx2=adx2))
+        if dx2 == 0.0:
+            break
+        if rel_tol and f > 0 and (f - f_new) / f < rel_tol:
+            f = f_new
+            break
+        f = f_new
+    return X, warm, gamma, hist
