@@ -1,0 +1,251 @@
+/*
+ * mrf.h - C ABI of the MI355X matched-filter / projected-gradient library.
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950), the hot path
+ * of iterative MRF reconstruction by projected gradient (BLIP, and the
+ * inexact variants of CoverBLIP; Golbabaee, Chen, Wiaux, Davies, "CoverBLIP:
+ * accelerated and scalable iterative matched-filtering for Magnetic Resonance
+ * Fingerprint reconstruction"):
+ *
+ *     X^{k+1} = P_cone(D)( X^k - mu_k A^H W (A X^k - Y) )          (eq. blip, eq. blip_dcf)
+ *
+ * with A = P_Omega F (per-frame unitary 2-D DFT and k-space subsampling,
+ * eq. forward with one coil) and P_cone(D) the per-voxel matched filter
+ * (eq. exactP / exactPs): nearest normalised atom, then the proton density
+ * gamma_v = max(Re<Z_v, D_j*>/||D_j*||^2, 0).
+ *
+ * Conventions (apply to every entry point):
+ *  - Every call returns mrf_status; MRF_OK is 0 and errors are negative.  No
+ *    C++ exception or abort crosses the ABI.  mrf_last_error() returns a
+ *    thread-local message describing the last failing call of this thread.
+ *  - Pointers documented DEVICE are device (HBM) addresses owned by the
+ *    caller; HOST pointers are host memory owned by the caller.  The library
+ *    owns only its handles (mrf_dict) and the workspace they hold.
+ *  - Complex data is complex64: interleaved (re, im) float pairs.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *    and calls return without waiting, except where a stats pointer is
+ *    given (then the call synchronises the stream to fill it) and the
+ *    solver (which reads three scalars back per step-size trial).
+ *  - Arguments are validated before anything is enqueued; a call that fails
+ *    validation (MRF_E_INVAL) has no side effect.
+ *  - A handle may be used by one host thread at a time.  Concurrent calls on
+ *    one handle race on its workspace.
+ */
+#ifndef MRF_H
+#define MRF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *mrf_stream; /* hipStream_t */
+
+typedef enum {
+  MRF_OK = 0,
+  MRF_E_INVAL = -1,       /* bad argument: null pointer, bad size, bad enum */
+  MRF_E_NOMEM = -2,       /* device allocation failed */
+  MRF_E_HIP = -3,         /* a HIP runtime call failed (message has the HIP error) */
+  MRF_E_UNSUPPORTED = -4, /* valid request this build does not implement */
+  MRF_E_NUMERIC = -5,     /* non-finite input detected (only reported when stats are requested) */
+  MRF_E_NOCONV = -6       /* step size not accepted within max_shrinks (solver) */
+} mrf_status;
+
+/* Thread-local description of the last error ("" if none). */
+const char *mrf_last_error(void);
+/* Library version string. */
+const char *mrf_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Dictionary                                                                */
+/* ------------------------------------------------------------------------ */
+/* The fingerprint dictionary D = {D_j} of eq. fingerprints with its look-up
+ * table of parameters.  The build normalises every atom in FP64 and keeps on
+ * the device: FP32 normalised atoms, 1/||D_j|| (FP32, from FP64), the
+ * parameter table (FP32) and, if asked, BF16 and FP8-E4M3 copies (the FP8
+ * copy with one FP32 scale per atom). */
+typedef struct mrf_dict_s *mrf_dict;
+
+enum {
+  MRF_STORE_BF16 = 1u << 1, /* also keep a BF16 copy (precision MRF_BF16) */
+  MRF_STORE_FP8 = 1u << 2   /* also keep an FP8-E4M3 copy (precision MRF_FP8) */
+};
+enum { MRF_F64 = 0, MRF_F32 = 1 }; /* element type of host atom arrays */
+
+typedef struct {
+  int32_t d;          /* number of atoms, >= 1 */
+  int32_t L;          /* frames per atom (temporal length), >= 1 */
+  int32_t nparam;     /* parameters per atom (e.g. T1, T2[, B1], df), 1..8 */
+  int32_t is_complex; /* 1: complex atoms (d x L complex); 0: real atoms (d x L) */
+  const void *atoms;  /* HOST, row-major d x L (x2 interleaved if complex) */
+  int32_t atoms_dtype;/* MRF_F64 or MRF_F32 */
+  const double *params;     /* HOST d x nparam, the look-up table Theta_j */
+  const int32_t *grid_dims; /* HOST nparam sizes when atoms are the row-major
+                               product grid of the parameters (last fastest),
+                               else NULL */
+  uint32_t flags;           /* MRF_STORE_* */
+} mrf_dict_desc;
+
+/* Upload and normalise a dictionary (eq. fingerprints; atoms normalised as
+ * the search of eq. exactP requires).  An atom of zero norm is rejected
+ * (MRF_E_INVAL).  On success *out is a new handle; the host arrays may be
+ * freed after the call returns (the upload completes before return). */
+mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream stream, mrf_dict *out);
+/* Release the handle and all device memory it owns (NULL is accepted). */
+mrf_status mrf_dict_destroy(mrf_dict D);
+
+typedef struct {
+  int32_t d, L, nparam, is_complex;
+  int32_t K;       /* real contraction length: 2L (complex) or L (real) */
+  int32_t Kp;      /* padded row pitch (elements) of the FP32 atom copy */
+  int32_t Kq;      /* padded row pitch (elements) of the BF16 / FP8 copies */
+  uint32_t flags;
+  int64_t device_bytes; /* device memory held by the handle (excl. workspace) */
+} mrf_dict_info;
+mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info);
+
+/* Copy the device's normalised atoms (precision MRF_FP32: float [d][K],
+ * MRF_BF16: uint16 [d][K], MRF_FP8: uint8 [d][K]) into DEVICE memory `dst`
+ * (row pitch K elements), and for MRF_FP8 the per-atom scales into DEVICE
+ * `scales` [d] (else ignored).  For checks against an independent encoder. */
+mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *dst, float *scales,
+                               mrf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Matched filter P_cone(D) (eq. exactP, eq. exactPs)                         */
+/* ------------------------------------------------------------------------ */
+enum { MRF_EXHAUSTIVE = 0 };
+enum { MRF_FP32 = 0, MRF_BF16 = 1, MRF_FP8 = 2 };
+enum { MRF_VOXEL_MAJOR = 0, MRF_FRAME_MAJOR = 1 };
+
+typedef struct {
+  int32_t method;      /* MRF_EXHAUSTIVE */
+  int32_t precision;   /* candidate scoring: MRF_FP32 (exact argmax), MRF_BF16 or
+                          MRF_FP8 (top-k by reduced-precision score, then FP32 rescore) */
+  int32_t topk;        /* reduced-precision candidates rescored in FP32, 1..8 (0 = 8) */
+  int32_t atom_splits; /* 0 = automatic; else number of atom ranges scored in parallel */
+} mrf_match_opts;
+
+typedef struct {
+  int64_t n;             /* voxels processed */
+  int64_t zero_voxels;   /* voxels with ||Z_v|| = 0 */
+  int64_t nonfinite;     /* voxels with a NaN/Inf entry (idx = -1 for them) */
+  float ms;              /* device time of the call (hipEvents on `stream`) */
+  float score_ms;        /* device time of the candidate-scoring kernel alone */
+  int32_t splits;        /* atom ranges the scoring kernel used */
+} mrf_match_stats;
+
+/* Project n voxels onto cone(D).
+ *   Z        DEVICE complex64.  z_layout MRF_VOXEL_MAJOR: [n][L];
+ *            MRF_FRAME_MAJOR: [n/slice_voxels][L][slice_voxels] (frame images
+ *            of consecutive slices), slice_voxels must divide n.
+ *   warm_idx DEVICE int32 [n] or NULL: index reported for voxels with
+ *            ||Z_v|| = 0 (Algorithm 2's previous estimate); NULL -> 0.
+ *   idx      DEVICE int32 [n]: j* (lowest index among equal scores); -1 for
+ *            non-finite voxels.
+ *   pd       DEVICE float [n] or NULL: gamma_v of eq. exactPs.
+ *   corr     DEVICE float [n] or NULL: Re<Z_v, D_j*>/(||D_j*|| ||Z_v||) (0 if Z_v = 0).
+ *   X_out    DEVICE complex64, same layout as Z, or NULL: gamma_v D_j*.
+ *   params_out DEVICE float [n][nparam] or NULL: Theta_{j*} (look-up table).
+ * For real atoms the contraction uses Re(Z_v) and ||Z_v|| is the complex norm.
+ * Returns MRF_E_UNSUPPORTED for a precision whose copy was not stored. */
+mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t n, const void *Z,
+                     int32_t z_layout, int64_t slice_voxels, const int32_t *warm_idx,
+                     int32_t *idx, float *pd, float *corr, void *X_out, float *params_out,
+                     mrf_match_stats *stats, mrf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Forward model A = P_Omega F (eq. forward, c = 1, S = I)                    */
+/* ------------------------------------------------------------------------ */
+/* Images are frame-major [nslices][L][ny][nx] complex64.  F is the unitary
+ * 2-D DFT of each frame, k-space in unshifted FFT order.  The sampling
+ * pattern is CSR over (slice, frame) pairs p = s*L + t: the samples of pair p
+ * are the flat k-space indices samp_idx[samp_off[p] .. samp_off[p+1]) (ky*nx+kx),
+ * which must be distinct within a pair.  dcf (optional) holds the positive
+ * weights w of the weighted least squares of eq. blip_dcf, one per sample. */
+typedef struct {
+  int32_t nx, ny;          /* powers of two, 16..256 */
+  int32_t L, nslices;      /* >= 1 */
+  int64_t nsamples;        /* M = samp_off[nslices*L] */
+  const int64_t *samp_off; /* DEVICE [nslices*L + 1] */
+  const int32_t *samp_idx; /* DEVICE [M], each in [0, ny*nx) */
+  const float *dcf;        /* DEVICE [M] or NULL (w = 1) */
+} mrf_op;
+
+/* R = A X - Y  (Y NULL: R = A X), samples in CSR order, DEVICE complex64 [M].
+ * If wnorm2 is non-NULL it receives ||R||_W^2 (stream synchronised). */
+mrf_status mrf_op_forward(const mrf_op *A, const void *X, const void *Y, void *R,
+                          double *wnorm2, mrf_stream stream);
+/* G = A^H diag(w) R (apply_dcf != 0) or A^H R, DEVICE complex64 images. */
+mrf_status mrf_op_adjoint(const mrf_op *A, const void *R, int32_t apply_dcf, void *G,
+                          mrf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Projected gradient                                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double dx2;    /* ||X_out - X_in||^2 */
+  double adx2;   /* ||A(X_out - X_in)||_W^2 */
+  double f_in;   /* ||A X_in - Y||_W^2 */
+  double f_out;  /* ||A X_out - Y||_W^2 */
+  float ms;      /* device time of the step */
+} mrf_step_stats;
+
+/* One step of eq. blip / eq. blip_dcf at a fixed step size mu:
+ *   Z = X_in - mu A^H W (A X_in - Y);  X_out = P_cone(D)(Z).
+ * Y DEVICE complex64 [M]; X_in, X_out DEVICE frame-major images (distinct);
+ * idx_in DEVICE int32 [n] or NULL (warm index for zero voxels); idx_out,
+ * pd DEVICE [n] (pd may be NULL).  stats (HOST, may be NULL) receives the
+ * quantities of the step-size rule (eq. steprule) and the objectives. */
+mrf_status mrf_ipg_step(mrf_dict D, const mrf_op *A, const void *Y, const void *X_in,
+                        void *X_out, const int32_t *idx_in, int32_t *idx_out, float *pd,
+                        float mu, const mrf_match_opts *opts, mrf_step_stats *stats,
+                        mrf_stream stream);
+
+typedef struct {
+  float mu0;           /* initial step size of every iteration (Algorithm 2) */
+  float zeta;          /* shrink factor > 1 (eq. steprule rule), e.g. 2 */
+  int32_t adaptive;    /* 1: shrink until mu < ||dX||^2/||A dX||_W^2; 0: fixed mu */
+  int32_t max_iter;    /* accepted iterations, >= 1 (the paper uses 50) */
+  double rel_tol;      /* stop when (f_k - f_{k+1})/f_k < rel_tol; 0 disables */
+  int32_t max_shrinks; /* MRF_E_NOCONV after this many shrinks in one iteration */
+  int32_t kappa;       /* 1: rescale X^1 and mu by ||Y||/||A X^1|| after iteration 1 */
+  mrf_match_opts match;
+} mrf_solve_opts;
+
+typedef struct {
+  int32_t iters;          /* accepted iterations */
+  int32_t total_shrinks;  /* step-size shrinks over all iterations */
+  int32_t cap;            /* capacity of the HOST arrays below (0 if all NULL) */
+  double *f;              /* HOST [cap] or NULL: objective after each iteration */
+  float *mu;              /* HOST [cap] or NULL: accepted step size */
+  int32_t *shrinks;       /* HOST [cap] or NULL: shrinks per iteration */
+  double f0;              /* objective of the initial X */
+  float ms;               /* device time of the whole solve */
+} mrf_solve_stats;
+
+/* Algorithm 2 with the exact projection: X (DEVICE frame-major) holds X^0 on
+ * entry (zero it for the paper's initialisation) and the reconstruction on
+ * return; idx, pd DEVICE [n]; params_out DEVICE [n][nparam] or NULL (the
+ * look-up table applied to the final indices).  Synchronises `stream`. */
+mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
+                         const mrf_solve_opts *opts, void *X, int32_t *idx, float *pd,
+                         float *params_out, mrf_solve_stats *stats, mrf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Reduced-precision encodings                                                */
+/* ------------------------------------------------------------------------ */
+/* Encode `rows` FP32 rows of length K (DEVICE, row pitch in_pitch elements)
+ * to BF16 (round to nearest even; out uint16, pitch out_pitch) or to
+ * FP8-E4M3 with a per-row FP32 scale amax/448 (out uint8 codes of x/scale,
+ * round to nearest even, saturating; scales DEVICE [rows]).  Padding columns
+ * K..out_pitch are written as zero. */
+mrf_status mrf_quantize_rows(const float *in, int64_t rows, int32_t K, int64_t in_pitch,
+                             int32_t precision, void *out, int64_t out_pitch, float *scales,
+                             mrf_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRF_H */

@@ -37,15 +37,21 @@ def normalised_atoms_f32(atoms: np.ndarray) -> np.ndarray:
     return (a.astype(np.float64) / nrm[:, None]).astype(np.float32)
 
 
-def correlations(Z: np.ndarray, atoms: np.ndarray) -> np.ndarray:
-    """c[v, j] = Re<Z_v, D_j> / ||D_j|| in FP64 (matrix product as one step)."""
+def correlations(Z: np.ndarray, atoms: np.ndarray, norms=None) -> np.ndarray:
+    """c[v, j] = Re<Z_v, D_j> / ||D_j|| in FP64 (matrix product as one step).
+
+    Re<Z_v, D_j> = sum_t Re(Z_vt) Re(D_jt) + Im(Z_vt) Im(D_jt); for real atoms
+    only the first sum remains."""
     Z = np.asarray(Z).astype(np.complex128)
     a = np.asarray(atoms)
-    nrm = atom_norms(a)
+    nrm = atom_norms(a) if norms is None else norms
+    zr = np.ascontiguousarray(Z.real)
     if np.iscomplexobj(a):
-        s = (Z.real @ a.real.astype(np.float64).T) + (Z.imag @ a.imag.astype(np.float64).T)
+        zi = np.ascontiguousarray(Z.imag)
+        s = zr @ np.ascontiguousarray(a.real, dtype=np.float64).T
+        s += zi @ np.ascontiguousarray(a.imag, dtype=np.float64).T
     else:
-        s = Z.real @ a.astype(np.float64).T
+        s = zr @ np.ascontiguousarray(a, dtype=np.float64).T
     return s / nrm[None, :]
 
 
@@ -66,7 +72,7 @@ def exact_mf(Z: np.ndarray, atoms: np.ndarray, warm_idx=None, block: int = 2048,
     score = np.zeros(n)
     gap = np.full(n, np.inf)
     for s0 in range(0, n, block):
-        c = correlations(Z[s0:s0 + block], a)
+        c = correlations(Z[s0:s0 + block], a, nrm)
         j = np.argmax(c, axis=1)                 # first maximiser = lowest index
         idx[s0:s0 + block] = j
         best = c[np.arange(c.shape[0]), j]

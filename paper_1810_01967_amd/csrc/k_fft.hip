@@ -1,0 +1,304 @@
+// Forward model kernels for gfx950: batched unitary 2-D DFT of frames (two
+// passes of 1-D radix-2 transforms staged in LDS), sample gather / residual,
+// zero-filled scatter (the adjoint of the sampling), and fixed-order FP64
+// reductions for the step-size rule.
+#include "mrf_internal.h"
+
+namespace mrf {
+
+// ---------------------------------------------------------------------------
+// 1-D FFT of many lines held in LDS
+// ---------------------------------------------------------------------------
+// A block transforms C = 4096/N lines of length N.  Lines are either rows of
+// a frame (consecutive elements) or columns (elements nx apart); the load and
+// store loops put the unit-stride index on consecutive threads so both stay
+// coalesced.  In LDS: bit-reversed placement, then log2(N) in-place
+// decimation-in-time stages.  Twiddles exp(-2 pi i k/N) are computed once per
+// block in FP64 and rounded to FP32.
+template <int N>
+struct FftCfg {
+  static constexpr int C = 4096 / N;
+  static constexpr int LOG = (N == 16) ? 4 : (N == 32) ? 5 : (N == 64) ? 6 : (N == 128) ? 7 : 8;
+};
+
+template <int N, bool COLS>
+__global__ __launch_bounds__(256) void k_fft_lines(float2 *__restrict__ data, int64_t nimg,
+                                                   int ny, int nx, int inverse) {
+  constexpr int C = FftCfg<N>::C;
+  constexpr int LOG = FftCfg<N>::LOG;
+  __shared__ float2 buf[C][N + 1];
+  __shared__ float2 tw[N / 2];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < N / 2; k += 256) {
+    double sn, cs;
+    sincospi(-2.0 * k / N, &sn, &cs);
+    tw[k] = make_float2((float)cs, inverse ? -(float)sn : (float)sn);
+  }
+  // lines of this block: line l -> (image l / lpi, index l % lpi)
+  const int lpi = COLS ? nx : ny;
+  const int64_t nlines = nimg * lpi;
+  const int64_t line0 = (int64_t)blockIdx.x * C;
+  const int64_t npix = (int64_t)nx * ny;
+  const float scale = rsqrtf((float)N);
+  auto addr = [&](int c, int e) -> int64_t {
+    const int64_t l = line0 + c;
+    const int64_t img = l / lpi;
+    const int j = (int)(l - img * lpi);
+    return img * npix + (COLS ? ((int64_t)e * nx + j) : ((int64_t)j * nx + e));
+  };
+  for (int i = tid; i < C * N; i += 256) {
+    int c, e;
+    if (COLS) {
+      e = i / C;
+      c = i - e * C;
+    } else {
+      c = i / N;
+      e = i - c * N;
+    }
+    if (line0 + c >= nlines) continue;
+    const int r = (int)(__builtin_bitreverse32((unsigned)e) >> (32 - LOG));
+    buf[c][r] = data[addr(c, e)];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int st = 0; st < LOG; ++st) {
+    const int m = 1 << st;
+    for (int b = tid; b < C * (N / 2); b += 256) {
+      const int c = b / (N / 2);
+      const int k = b - c * (N / 2);
+      const int g = k >> st, r = k & (m - 1);
+      const int i0 = g * 2 * m + r, i1 = i0 + m;
+      const float2 w = tw[r << (LOG - 1 - st)];
+      const float2 a = buf[c][i0], x = buf[c][i1];
+      const float2 bw = make_float2(x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x);
+      buf[c][i0] = make_float2(a.x + bw.x, a.y + bw.y);
+      buf[c][i1] = make_float2(a.x - bw.x, a.y - bw.y);
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < C * N; i += 256) {
+    int c, e;
+    if (COLS) {
+      e = i / C;
+      c = i - e * C;
+    } else {
+      c = i / N;
+      e = i - c * N;
+    }
+    if (line0 + c >= nlines) continue;
+    const float2 v = buf[c][e];
+    data[addr(c, e)] = make_float2(v.x * scale, v.y * scale);
+  }
+}
+
+template <int N, bool COLS>
+static void fft_pass(float2 *data, int64_t nimg, int ny, int nx, int inverse, hipStream_t s) {
+  constexpr int C = FftCfg<N>::C;
+  const int64_t lines = nimg * (COLS ? nx : ny);
+  const int64_t blocks = (lines + C - 1) / C;
+  hipLaunchKernelGGL((k_fft_lines<N, COLS>), dim3((unsigned)blocks), dim3(256), 0, s, data, nimg,
+                     ny, nx, inverse);
+}
+
+template <bool COLS>
+static void fft_pass_n(int N, float2 *data, int64_t nimg, int ny, int nx, int inverse,
+                       hipStream_t s) {
+  switch (N) {
+    case 16: fft_pass<16, COLS>(data, nimg, ny, nx, inverse, s); break;
+    case 32: fft_pass<32, COLS>(data, nimg, ny, nx, inverse, s); break;
+    case 64: fft_pass<64, COLS>(data, nimg, ny, nx, inverse, s); break;
+    case 128: fft_pass<128, COLS>(data, nimg, ny, nx, inverse, s); break;
+    case 256: fft_pass<256, COLS>(data, nimg, ny, nx, inverse, s); break;
+    default: break;
+  }
+}
+
+void launch_fft2(float2 *data, int64_t nimg, int ny, int nx, int inverse, hipStream_t s) {
+  fft_pass_n<false>(nx, data, nimg, ny, nx, inverse, s);
+  fft_pass_n<true>(ny, data, nimg, ny, nx, inverse, s);
+}
+
+// ---------------------------------------------------------------------------
+// sampling
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum_f64(double x, double *red) {
+  const int tid = threadIdx.x;
+  red[tid] = x;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sample(const float2 *__restrict__ K, int64_t npix,
+                                                const int64_t *__restrict__ off,
+                                                const int32_t *__restrict__ sidx,
+                                                const float2 *__restrict__ Y,
+                                                const float *__restrict__ w,
+                                                float2 *__restrict__ R, double *part, int64_t M) {
+  __shared__ double red[256];
+  const int p = blockIdx.x;
+  const int64_t b = min(max(off[p], (int64_t)0), M), e = min(max(off[p + 1], b), M);
+  const float2 *img = K + (int64_t)p * npix;
+  double acc = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
+    const uint32_t k = (uint32_t)sidx[i];
+    float2 r = k < (uint32_t)npix ? img[k] : make_float2(0.f, 0.f);
+    if (Y) {
+      const float2 y = Y[i];
+      r.x -= y.x;
+      r.y -= y.y;
+    }
+    R[i] = r;
+    const double m = (double)r.x * r.x + (double)r.y * r.y;
+    acc += w ? (double)w[i] * m : m;
+  }
+  const double s = block_sum_f64(acc, red);
+  if (threadIdx.x == 0 && part) part[p] = s;
+}
+
+void launch_sample(const float2 *K, int64_t npix, const int64_t *off, const int32_t *sidx,
+                   const float2 *Y, const float *w, float2 *R, double *part, int npairs,
+                   int64_t M, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample, dim3(npairs), dim3(256), 0, s, K, npix, off, sidx, Y, w, R, part, M);
+}
+
+__global__ __launch_bounds__(256) void k_zero(float4 *p, int64_t n4) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+__global__ void k_zero_bytes(unsigned char *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = 0;
+}
+
+void launch_zero(void *p, int64_t bytes, hipStream_t s) {
+  if (bytes <= 0) return;
+  const int64_t n4 = bytes / 16;
+  if (n4 > 0) {
+    int64_t blocks = (n4 + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s,
+                       reinterpret_cast<float4 *>(p), n4);
+  }
+  const int64_t rem = bytes - n4 * 16;
+  if (rem > 0)
+    hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(256), 0, s,
+                       reinterpret_cast<unsigned char *>(p) + n4 * 16, rem);
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const float2 *__restrict__ R,
+                                                 const float *__restrict__ w,
+                                                 const int64_t *__restrict__ off,
+                                                 const int32_t *__restrict__ sidx,
+                                                 float2 *__restrict__ K, int64_t npix, int64_t M) {
+  const int p = blockIdx.x;
+  const int64_t b = min(max(off[p], (int64_t)0), M), e = min(max(off[p + 1], b), M);
+  float2 *img = K + (int64_t)p * npix;
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
+    const uint32_t k = (uint32_t)sidx[i];
+    if (k >= (uint32_t)npix) continue;
+    float2 r = R[i];
+    if (w) {
+      const float a = w[i];
+      r.x *= a;
+      r.y *= a;
+    }
+    img[k] = r;
+  }
+}
+
+void launch_scatter(const float2 *R, const float *w, const int64_t *off, const int32_t *sidx,
+                    float2 *K, int64_t npix, int npairs, int64_t total, int64_t M, hipStream_t s) {
+  launch_zero(K, total * (int64_t)sizeof(float2), s);
+  hipLaunchKernelGGL(k_scatter, dim3(npairs), dim3(256), 0, s, R, w, off, sidx, K, npix, M);
+}
+
+__global__ __launch_bounds__(256) void k_step_norms(const float2 *__restrict__ R,
+                                                    const float2 *__restrict__ A,
+                                                    const float *__restrict__ w,
+                                                    const int64_t *__restrict__ off, int64_t M,
+                                                    double *part_a, double *part_ra,
+                                                    float2 *R_update) {
+  __shared__ double red[256];
+  const int p = blockIdx.x;
+  const int64_t b = min(max(off[p], (int64_t)0), M), e = min(max(off[p + 1], b), M);
+  double sa = 0.0, sra = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
+    const float2 a = A[i];
+    const float2 r = R[i];
+    const double wi = w ? (double)w[i] : 1.0;
+    sa += wi * ((double)a.x * a.x + (double)a.y * a.y);
+    const double qx = (double)r.x + a.x, qy = (double)r.y + a.y;
+    sra += wi * (qx * qx + qy * qy);
+    if (R_update) R_update[i] = make_float2(r.x + a.x, r.y + a.y);
+  }
+  const double t1 = block_sum_f64(sa, red);
+  if (threadIdx.x == 0) part_a[p] = t1;
+  __syncthreads();
+  const double t2 = block_sum_f64(sra, red);
+  if (threadIdx.x == 0) part_ra[p] = t2;
+}
+
+void launch_step_norms(const float2 *R, const float2 *A, const float *w, const int64_t *off,
+                       int npairs, int64_t M, double *part_a, double *part_ra, float2 *R_update,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_step_norms, dim3(npairs), dim3(256), 0, s, R, A, w, off, M, part_a,
+                     part_ra, R_update);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_sum(const double *__restrict__ part,
+                                                    int64_t count, double *out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) acc += part[i];
+  const double s = block_sum_f64(acc, red);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+void launch_reduce_sum(const double *part, int64_t count, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, part, count, out);
+}
+
+__global__ __launch_bounds__(256) void k_scale(float2 *x, int64_t count, float a) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    float2 v = x[i];
+    x[i] = make_float2(v.x * a, v.y * a);
+  }
+}
+
+void launch_scale(float2 *x, int64_t count, float a, hipStream_t s) {
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks > 0) hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, x, count, a);
+}
+
+}  // namespace mrf
+
+namespace mrf {
+
+__global__ __launch_bounds__(256) void k_norm2(const float2 *__restrict__ x, int64_t count,
+                                               double *part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    const float2 v = x[i];
+    acc += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  const double sum = block_sum_f64(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = sum;
+}
+
+void launch_norm2(const float2 *x, int64_t count, double *part, int *nblocks_out, hipStream_t s) {
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  *nblocks_out = (int)blocks;
+  hipLaunchKernelGGL(k_norm2, dim3((unsigned)blocks), dim3(256), 0, s, x, count, part);
+}
+
+}  // namespace mrf

@@ -1,0 +1,591 @@
+// Matched-filter kernels for gfx950: voxel packing, exhaustive FP32 MFMA
+// scoring with a fused argmax, split merge + rescaling (eq. exactP,
+// eq. exactPs), and the write of gamma_v D_j* back into image layout.
+#include <cfloat>
+
+#include "mrf_internal.h"
+
+namespace mrf {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------
+// packing
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// One wave per voxel row (voxel-major input [n][L] complex64).
+__global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restrict__ Z, int64_t n,
+                                                          int64_t n_pad, int L, int real_atoms,
+                                                          int Kp, float *__restrict__ Zp,
+                                                          float *__restrict__ znorm,
+                                                          unsigned long long *counters) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n_pad) return;
+  float *row = Zp + v * Kp;
+  const int K = real_atoms ? L : 2 * L;
+  if (v >= n) {
+    for (int k = lane; k < Kp; k += 64) row[k] = 0.f;
+    return;
+  }
+  const float2 *z = Z + v * (int64_t)L;
+  double acc = 0.0;
+  for (int t = lane; t < L; t += 64) {
+    const float2 a = z[t];
+    acc += (double)a.x * a.x + (double)a.y * a.y;
+    if (real_atoms) {
+      row[t] = a.x;
+    } else {
+      row[2 * t] = a.x;
+      row[2 * t + 1] = a.y;
+    }
+  }
+  for (int k = K + lane; k < Kp; k += 64) row[k] = 0.f;
+  acc = wave_sum_f64(acc);
+  if (lane == 0) {
+    const bool fin = isfinite(acc);
+    znorm[v] = fin ? (float)sqrt(acc) : -1.f;
+    if (!fin) atomicAdd(&counters[1], 1ull);
+    else if (acc == 0.0) atomicAdd(&counters[0], 1ull);
+  }
+}
+
+// 64 voxels per block; frame tiles of 16 staged in LDS for the transpose.
+template <bool HAS_G>
+__global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restrict__ X,
+                                                          const float2 *__restrict__ G, float mu,
+                                                          int64_t n, int64_t n_pad, int64_t npix,
+                                                          int L, int real_atoms, int Kp,
+                                                          float *__restrict__ Zp,
+                                                          float *__restrict__ znorm,
+                                                          unsigned long long *counters) {
+  __shared__ float2 tile[16][65];
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x;
+  const int vi = tid & 63, fi = tid >> 6;
+  const int64_t v0 = (int64_t)blockIdx.x * 64;
+  const int64_t v = v0 + vi;
+  const bool valid = v < n;
+  const int64_t sl = valid ? v / npix : 0;
+  const int64_t p = valid ? v - sl * npix : 0;
+  double acc = 0.0;
+  // writer mapping: 4 threads per voxel row, each 4 frames
+  const int wv = tid >> 2, wp = tid & 3;
+  const int64_t vw = v0 + wv;
+  for (int t0 = 0; t0 < L; t0 += 16) {
+#pragma unroll
+    for (int f = fi; f < 16; f += 4) {
+      const int t = t0 + f;
+      float2 z = make_float2(0.f, 0.f);
+      if (valid && t < L) {
+        const int64_t e = (sl * L + t) * npix + p;
+        z = X[e];
+        if (HAS_G) {
+          const float2 g = G[e];
+          z.x = z.x - mu * g.x;
+          z.y = z.y - mu * g.y;
+        }
+        acc += (double)z.x * z.x + (double)z.y * z.y;
+      }
+      tile[f][vi] = z;
+    }
+    __syncthreads();
+    if (vw < n_pad) {
+      float *row = Zp + vw * Kp;
+      if (real_atoms) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int t = t0 + wp * 4 + q;
+          if (t < L) row[t] = tile[wp * 4 + q][wv].x;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int t = t0 + wp * 4 + q;
+          if (t < L) {
+            const float2 z = tile[wp * 4 + q][wv];
+            *reinterpret_cast<float2 *>(row + 2 * t) = z;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // zero the padding columns
+  const int K = real_atoms ? L : 2 * L;
+  if (vw < n_pad) {
+    float *row = Zp + vw * Kp;
+    for (int k = K + wp; k < Kp; k += 4) row[k] = 0.f;
+  }
+  red[fi][vi] = acc;
+  __syncthreads();
+  if (fi == 0 && valid) {
+    const double s = red[0][vi] + red[1][vi] + red[2][vi] + red[3][vi];
+    const bool fin = isfinite(s);
+    znorm[v] = fin ? (float)sqrt(s) : -1.f;
+    if (!fin) atomicAdd(&counters[1], 1ull);
+    else if (s == 0.0) atomicAdd(&counters[0], 1ull);
+  }
+}
+
+void launch_pack_voxel_major(const float2 *Z, int64_t n, int64_t n_pad, int L, int real_atoms,
+                             int Kp, float *Zp, float *znorm, unsigned long long *counters,
+                             hipStream_t s) {
+  const int64_t blocks = (n_pad + 3) / 4;
+  hipLaunchKernelGGL(k_pack_voxel_major, dim3((unsigned)blocks), dim3(256), 0, s, Z, n, n_pad, L,
+                     real_atoms, Kp, Zp, znorm, counters);
+}
+
+void launch_pack_frame_major(const float2 *X, const float2 *G, float mu, int64_t n, int64_t n_pad,
+                             int64_t npix, int L, int real_atoms, int Kp, float *Zp, float *znorm,
+                             unsigned long long *counters, hipStream_t s) {
+  const int64_t blocks = (n_pad + 63) / 64;
+  if (G)
+    hipLaunchKernelGGL(k_pack_frame_major<true>, dim3((unsigned)blocks), dim3(256), 0, s, X, G,
+                       mu, n, n_pad, npix, L, real_atoms, Kp, Zp, znorm, counters);
+  else
+    hipLaunchKernelGGL(k_pack_frame_major<false>, dim3((unsigned)blocks), dim3(256), 0, s, X,
+                       nullptr, 0.f, n, n_pad, npix, L, real_atoms, Kp, Zp, znorm, counters);
+}
+
+// ---------------------------------------------------------------------------
+// exhaustive FP32 scoring with fused argmax
+// ---------------------------------------------------------------------------
+// Block tile: 128 atoms x 128 voxels, K chunks of 16, double-buffered LDS.
+// Four waves in a 2 x 2 arrangement, each owning 64 atoms x 64 voxels as
+// 2 x 2 MFMA 32x32x2 tiles.  Atoms are the MFMA rows (A operand) and voxels
+// the columns (B operand), so each lane accumulates one voxel column and 16
+// atom rows per tile: the running per-voxel maximum stays in registers and
+// atoms arrive in increasing index order, so a strict '>' keeps the lowest
+// index among equal scores.
+constexpr int F_BA = 128, F_BV = 128, F_BK = 16, F_LDK = 20;
+
+__device__ __forceinline__ bool better(float s1, int j1, float s0, int j0) {
+  // (s1, j1) beats (s0, j0): higher score, or equal score with a lower valid index
+  return (s1 > s0) || (s1 == s0 && j1 >= 0 && (j0 < 0 || j1 < j0));
+}
+
+__global__ __launch_bounds__(256, 2) void k_score_f32(const float *__restrict__ D,
+                                                      const float *__restrict__ Zp, int d,
+                                                      int ntiles_total, int64_t n, int nvt,
+                                                      int Kp, int splits, int tiles_per_split,
+                                                      float *__restrict__ part_s,
+                                                      int *__restrict__ part_j) {
+  // block -> (voxel tile, atom split); all splits of one voxel tile land on
+  // the same XCD (blocks are dealt to the 8 XCDs round-robin), so they share
+  // the voxel tile through that XCD's L2.
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, local = bid >> 3;
+  const int split = local % splits;
+  const int vt = (local / splits) * 8 + xcd;
+  if (vt >= nvt) return;
+  const int tb = split * tiles_per_split;
+  const int te = min(tb + tiles_per_split, ntiles_total);
+
+  __shared__ float As[2][F_BA][F_LDK];
+  __shared__ float Zs[2][F_BV][F_LDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wa = wave >> 1, wv = wave & 1;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int64_t v0 = (int64_t)vt * F_BV;
+  const int nkc = Kp / F_BK;
+  const int nq = te > tb ? (te - tb) * nkc : 0;
+
+  const int lr = tid >> 2, lc = (tid & 3) * 4;
+  float4 ra0, ra1, rz0, rz1;
+  auto gload = [&](int q) {
+    const int tile = tb + q / nkc, kc = q - (q / nkc) * nkc;
+    const float *a = D + (int64_t)(tile * F_BA + lr) * Kp + kc * F_BK + lc;
+    ra0 = *reinterpret_cast<const float4 *>(a);
+    ra1 = *reinterpret_cast<const float4 *>(a + (int64_t)64 * Kp);
+    const float *z = Zp + (v0 + lr) * Kp + kc * F_BK + lc;
+    rz0 = *reinterpret_cast<const float4 *>(z);
+    rz1 = *reinterpret_cast<const float4 *>(z + (int64_t)64 * Kp);
+  };
+  auto sstore = [&](int buf) {
+    *reinterpret_cast<float4 *>(&As[buf][lr][lc]) = ra0;
+    *reinterpret_cast<float4 *>(&As[buf][lr + 64][lc]) = ra1;
+    *reinterpret_cast<float4 *>(&Zs[buf][lr][lc]) = rz0;
+    *reinterpret_cast<float4 *>(&Zs[buf][lr + 64][lc]) = rz1;
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+  float best[2] = {-INFINITY, -INFINITY};
+  int bidx[2] = {-1, -1};
+
+  if (nq > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int q = 0; q < nq; ++q) {
+    const int buf = q & 1;
+    if (q + 1 < nq) gload(q + 1);
+    float af[2][8], zf[2][8];
+#pragma unroll
+    for (int ma = 0; ma < 2; ++ma) {
+      const float *src = &As[buf][wa * 64 + ma * 32 + l32][h * 8];
+      const float4 x0 = *reinterpret_cast<const float4 *>(src);
+      const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
+      af[ma][0] = x0.x; af[ma][1] = x0.y; af[ma][2] = x0.z; af[ma][3] = x0.w;
+      af[ma][4] = x1.x; af[ma][5] = x1.y; af[ma][6] = x1.z; af[ma][7] = x1.w;
+    }
+#pragma unroll
+    for (int nv = 0; nv < 2; ++nv) {
+      const float *src = &Zs[buf][wv * 64 + nv * 32 + l32][h * 8];
+      const float4 x0 = *reinterpret_cast<const float4 *>(src);
+      const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
+      zf[nv][0] = x0.x; zf[nv][1] = x0.y; zf[nv][2] = x0.z; zf[nv][3] = x0.w;
+      zf[nv][4] = x1.x; zf[nv][5] = x1.y; zf[nv][6] = x1.z; zf[nv][7] = x1.w;
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int ma = 0; ma < 2; ++ma)
+#pragma unroll
+        for (int nv = 0; nv < 2; ++nv)
+          acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[ma][s], zf[nv][s], acc[ma][nv], 0, 0, 0);
+
+    const int kc = q % nkc;
+    if (kc == nkc - 1) {
+      // epilogue of one atom tile: fold 32 atom rows per voxel column
+      const int abase = (tb + q / nkc) * F_BA + wa * 64;
+#pragma unroll
+      for (int nv = 0; nv < 2; ++nv) {
+#pragma unroll
+        for (int ma = 0; ma < 2; ++ma) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+            const float sc = acc[ma][nv][i];
+            if (j < d && sc > best[nv]) {  // NaN never wins
+              best[nv] = sc;
+              bidx[nv] = j;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+    }
+    if (q + 1 < nq) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // combine the two half-waves (rows 4h..4h+3 of each 8-row group)
+#pragma unroll
+  for (int nv = 0; nv < 2; ++nv) {
+    const float ps = __shfl_xor(best[nv], 32, 64);
+    const int pj = __shfl_xor(bidx[nv], 32, 64);
+    if (better(ps, pj, best[nv], bidx[nv])) {
+      best[nv] = ps;
+      bidx[nv] = pj;
+    }
+  }
+  // combine the two atom halves of the block (wa = 0, 1) through LDS
+  float *rs = &As[0][0][0];
+  int *rj = reinterpret_cast<int *>(&Zs[0][0][0]);
+  if (wa == 1 && h == 0) {
+#pragma unroll
+    for (int nv = 0; nv < 2; ++nv) {
+      rs[wv * 64 + nv * 32 + l32] = best[nv];
+      rj[wv * 64 + nv * 32 + l32] = bidx[nv];
+    }
+  }
+  __syncthreads();
+  if (wa == 0 && h == 0) {
+#pragma unroll
+    for (int nv = 0; nv < 2; ++nv) {
+      const int c = wv * 64 + nv * 32 + l32;
+      const float ps = rs[c];
+      const int pj = rj[c];
+      // equal scores resolve to the lower atom index
+      if (better(ps, pj, best[nv], bidx[nv])) {
+        best[nv] = ps;
+        bidx[nv] = pj;
+      }
+      const int64_t v = v0 + c;
+      if (v < n) {
+        part_s[(int64_t)split * n + v] = best[nv];
+        part_j[(int64_t)split * n + v] = bidx[nv];
+      }
+    }
+  }
+}
+
+void launch_score_f32(const float *D, const float *Zp, int d, int64_t d_pad, int64_t n,
+                      int64_t n_pad, int Kp, int splits, float *part_s, int *part_j,
+                      hipStream_t s) {
+  const int ntiles = (int)(d_pad / F_BA);
+  const int nvt = (int)((n + F_BV - 1) / F_BV);
+  (void)n_pad;
+  const int tiles_per_split = (ntiles + splits - 1) / splits;
+  const int nvt8 = (nvt + 7) / 8 * 8;
+  const int64_t blocks = (int64_t)nvt8 * splits;
+  hipLaunchKernelGGL(k_score_f32, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, d, ntiles, n,
+                     nvt, Kp, splits, tiles_per_split, part_s, part_j);
+}
+
+// ---------------------------------------------------------------------------
+// merge + rescale + look-up
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void finish_voxel(int64_t v, float sc, int j, int d, const float *znorm,
+                                             const int32_t *warm, const float *inv_norm,
+                                             const float *params, int nparam, int32_t *idx,
+                                             float *pd, float *corr, float *params_out,
+                                             float *gamma_hat) {
+  const float zn = znorm[v];
+  float g = 0.f, c = 0.f;
+  if (zn < 0.f || j < 0) {
+    j = -1;  // non-finite voxel
+  } else if (zn == 0.f) {
+    j = warm ? warm[v] : 0;
+    if (j < 0 || j >= d) j = 0;  // an out-of-range warm index is not trusted
+  } else {
+    g = fmaxf(sc, 0.f);
+    c = sc / zn;
+  }
+  idx[v] = j;
+  if (pd) pd[v] = j >= 0 ? g * inv_norm[j] : 0.f;
+  if (corr) corr[v] = c;
+  gamma_hat[v] = g;
+  if (params_out)
+    for (int p = 0; p < nparam; ++p)
+      params_out[v * nparam + p] = j >= 0 ? params[(int64_t)j * nparam + p] : 0.f;
+}
+
+__global__ void k_merge_argmax(const float *__restrict__ part_s, const int *__restrict__ part_j,
+                               int splits, int64_t n, int d, const float *znorm, const int32_t *warm,
+                               const float *inv_norm, const float *params, int nparam,
+                               int32_t *idx, float *pd, float *corr, float *params_out,
+                               float *gamma_hat) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  float bs = -INFINITY;
+  int bj = -1;
+  for (int s = 0; s < splits; ++s) {
+    const float ps = part_s[(int64_t)s * n + v];
+    const int pj = part_j[(int64_t)s * n + v];
+    if (pj >= 0 && better(ps, pj, bs, bj)) {
+      bs = ps;
+      bj = pj;
+    }
+  }
+  finish_voxel(v, bs, bj, d, znorm, warm, inv_norm, params, nparam, idx, pd, corr, params_out,
+               gamma_hat);
+}
+
+void launch_merge_argmax(const float *part_s, const int *part_j, int splits, int64_t n, int d,
+                         const float *znorm, const int32_t *warm, const float *inv_norm,
+                         const float *params, int nparam, int32_t *idx, float *pd, float *corr,
+                         float *params_out, float *gamma_hat, hipStream_t s) {
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_merge_argmax, dim3((unsigned)blocks), dim3(256), 0, s, part_s, part_j,
+                     splits, n, d, znorm, warm, inv_norm, params, nparam, idx, pd, corr,
+                     params_out, gamma_hat);
+}
+
+// ---------------------------------------------------------------------------
+// top-k merge + FP32 rescore
+// ---------------------------------------------------------------------------
+// One wave per voxel: merge the splits' candidate lists into the k best
+// (score desc, index asc), then the exact FP32 dot products of those k atoms
+// with the voxel, reduced across lanes in a fixed order.
+__global__ __launch_bounds__(256) void k_merge_rescore(
+    const float *__restrict__ cand_s, const int *__restrict__ cand_j, int splits, int topk,
+    int64_t n, int d, const float *__restrict__ Zp, const float *__restrict__ D, int Kp, int K,
+    const float *znorm, const int32_t *warm, const float *inv_norm, const float *params,
+    int nparam, int32_t *idx, float *pd, float *corr, float *params_out, float *gamma_hat) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n) return;
+  // merged top-k held redundantly by every lane (k <= 8)
+  float ks[8];
+  int kj[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    ks[i] = -FLT_MAX;
+    kj[i] = -1;
+  }
+  for (int s = 0; s < splits; ++s) {
+    const float *cs = cand_s + ((int64_t)s * n + v) * 8;
+    const int *cj = cand_j + ((int64_t)s * n + v) * 8;
+    for (int c = 0; c < 8; ++c) {
+      const int j = cj[c];
+      if (j < 0) continue;
+      const float sc = cs[c];
+      if (!better(sc, j, ks[topk - 1], kj[topk - 1])) continue;
+      // insertion into the sorted list
+      int pos = topk - 1;
+      while (pos > 0 && better(sc, j, ks[pos - 1], kj[pos - 1])) {
+        ks[pos] = ks[pos - 1];
+        kj[pos] = kj[pos - 1];
+        --pos;
+      }
+      ks[pos] = sc;
+      kj[pos] = j;
+    }
+  }
+  // exact rescore of the candidates
+  const float *z = Zp + v * Kp;
+  float bs = -FLT_MAX;
+  int bj = -1;
+  for (int c = 0; c < topk; ++c) {
+    const int j = kj[c];
+    if (j < 0) continue;
+    const float *a = D + (int64_t)j * Kp;
+    float acc = 0.f;
+    for (int k = lane; k < K; k += 64) acc = fmaf(z[k], a[k], acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (better(acc, j, bs, bj)) {
+      bs = acc;
+      bj = j;
+    }
+  }
+  if (lane == 0)
+    finish_voxel(v, bs, bj, d, znorm, warm, inv_norm, params, nparam, idx, pd, corr, params_out,
+                 gamma_hat);
+}
+
+void launch_merge_rescore(const float *cand_s, const int *cand_j, int splits, int topk, int64_t n,
+                          int d, const float *Zp, const float *D, int Kp, int K, const float *znorm,
+                          const int32_t *warm, const float *inv_norm, const float *params,
+                          int nparam, int32_t *idx, float *pd, float *corr, float *params_out,
+                          float *gamma_hat, hipStream_t s) {
+  const int64_t blocks = (n + 3) / 4;
+  hipLaunchKernelGGL(k_merge_rescore, dim3((unsigned)blocks), dim3(256), 0, s, cand_s, cand_j,
+                     splits, topk, n, d, Zp, D, Kp, K, znorm, warm, inv_norm, params, nparam, idx, pd,
+                     corr, params_out, gamma_hat);
+}
+
+// ---------------------------------------------------------------------------
+// X = gamma_hat * Dhat_idx
+// ---------------------------------------------------------------------------
+template <bool FRAME, bool DELTA>
+__global__ __launch_bounds__(256) void k_write_x(const int32_t *__restrict__ idx,
+                                                 const float *__restrict__ gamma_hat,
+                                                 const float *__restrict__ D, int Kp,
+                                                 int real_atoms, int64_t n, int L, int64_t npix,
+                                                 float2 *__restrict__ X,
+                                                 const float2 *__restrict__ X_prev,
+                                                 float2 *__restrict__ dX, double *part) {
+  __shared__ double red[256];
+  const int64_t total = n * L;
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    int64_t v;
+    int t;
+    if (FRAME) {
+      const int64_t pair = e / npix;  // s*L + t
+      const int64_t p = e - pair * npix;
+      const int64_t sl = pair / L;
+      t = (int)(pair - sl * L);
+      v = sl * npix + p;
+    } else {
+      v = e / L;
+      t = (int)(e - v * L);
+    }
+    const int j = idx[v];
+    float2 x = make_float2(0.f, 0.f);
+    if (j >= 0) {
+      const float g = gamma_hat[v];
+      const float *a = D + (int64_t)j * Kp;
+      if (real_atoms) {
+        x.x = g * a[t];
+      } else {
+        const float2 c = *reinterpret_cast<const float2 *>(a + 2 * t);
+        x.x = g * c.x;
+        x.y = g * c.y;
+      }
+    }
+    X[e] = x;
+    if (DELTA) {
+      const float2 xp = X_prev[e];
+      const float2 dd = make_float2(x.x - xp.x, x.y - xp.y);
+      dX[e] = dd;
+      acc += (double)dd.x * dd.x + (double)dd.y * dd.y;
+    }
+  }
+  if (DELTA) {
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  }
+}
+
+void launch_write_x(const int32_t *idx, const float *gamma_hat, const float *D, int Kp,
+                    int real_atoms, int64_t n, int L, int frame_major, int64_t npix, float2 *X,
+                    const float2 *X_prev, float2 *dX, double *part, int *nblocks_out,
+                    hipStream_t s) {
+  const int64_t total = n * (int64_t)L;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (nblocks_out) *nblocks_out = (int)blocks;
+  if (frame_major) {
+    if (X_prev)
+      hipLaunchKernelGGL((k_write_x<true, true>), dim3((unsigned)blocks), dim3(256), 0, s, idx,
+                         gamma_hat, D, Kp, real_atoms, n, L, npix, X, X_prev, dX, part);
+    else
+      hipLaunchKernelGGL((k_write_x<true, false>), dim3((unsigned)blocks), dim3(256), 0, s, idx,
+                         gamma_hat, D, Kp, real_atoms, n, L, npix, X, nullptr, nullptr, nullptr);
+  } else {
+    hipLaunchKernelGGL((k_write_x<false, false>), dim3((unsigned)blocks), dim3(256), 0, s, idx,
+                       gamma_hat, D, Kp, real_atoms, n, L, npix, X, nullptr, nullptr, nullptr);
+  }
+}
+
+}  // namespace mrf
+
+namespace mrf {
+
+__global__ void k_lookup(const int32_t *__restrict__ idx, const float *__restrict__ params,
+                         int nparam, int64_t n, float *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nparam) return;
+  const int64_t v = e / nparam;
+  const int p = (int)(e - v * nparam);
+  const int j = idx[v];
+  out[e] = j >= 0 ? params[(int64_t)j * nparam + p] : 0.f;
+}
+
+void launch_lookup(const int32_t *idx, const float *params, int nparam, int64_t n,
+                   float *params_out, hipStream_t s) {
+  const int64_t total = n * nparam;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_lookup, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, idx,
+                     params, nparam, n, params_out);
+}
+
+__global__ void k_scale_f32(float *x, int64_t count, float a) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256)
+    x[i] *= a;
+}
+
+void launch_scale_f32(float *x, int64_t count, float a, hipStream_t s) {
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks > 0) hipLaunchKernelGGL(k_scale_f32, dim3((unsigned)blocks), dim3(256), 0, s, x, count, a);
+}
+
+}  // namespace mrf

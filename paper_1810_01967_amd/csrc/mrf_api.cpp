@@ -1,0 +1,744 @@
+// Host side of the C ABI: argument validation, dictionary handles and their
+// workspace, and the projected-gradient control loop (Algorithm 2 with the
+// step-size rule eq. steprule).  All device work is enqueued on the caller's
+// stream through the launchers of the kernel files.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "mrf_internal.h"
+
+using namespace mrf;
+
+namespace {
+
+thread_local std::string g_err;
+
+mrf_status fail(mrf_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(MRF_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_CHECK(what)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = hipGetLastError();                                                       \
+    if (e_ != hipSuccess) return fail(MRF_E_HIP, "%s launch failed: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  template <class T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+mrf_status grow(DevBuf &b, size_t bytes) {
+  if (bytes <= b.cap) return MRF_OK;
+  if (b.p) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  const size_t want = bytes < 256 ? 256 : bytes;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return fail(MRF_E_NOMEM, "device allocation of %zu bytes failed: %s", want,
+                hipGetErrorString(e));
+  }
+  b.cap = want;
+  return MRF_OK;
+}
+
+#define TRY(expr)                    \
+  do {                               \
+    mrf_status st_ = (expr);         \
+    if (st_ != MRF_OK) return st_;   \
+  } while (0)
+
+}  // namespace
+
+struct mrf_dict_s {
+  int device = 0;
+  int d = 0, L = 0, nparam = 0, is_complex = 0, K = 0, Kp = 0, Kq = 0;
+  int64_t d_pad = 0;
+  uint32_t flags = 0;
+  std::vector<int32_t> grid_dims;
+  DevBuf dhat, inv_norm, params, dbf16, dfp8, fp8_scale;
+  int64_t bytes = 0;
+  // workspace (grows lazily)
+  DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j;
+  DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;
+  double *host_scal = nullptr;  // pinned readback of reduced scalars
+  ~mrf_dict_s() {
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+};
+
+extern "C" const char *mrf_last_error(void) { return g_err.c_str(); }
+extern "C" const char *mrf_version(void) { return "mrf-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// dictionary
+// ---------------------------------------------------------------------------
+extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream stream,
+                                     mrf_dict *out) {
+  g_err.clear();
+  if (!desc || !out) return fail(MRF_E_INVAL, "mrf_dict_build: null desc or out");
+  *out = nullptr;
+  const mrf_dict_desc &q = *desc;
+  if (q.d < 1 || q.L < 1) return fail(MRF_E_INVAL, "mrf_dict_build: d=%d L=%d must be >= 1", q.d, q.L);
+  if (q.nparam < 1 || q.nparam > 8) return fail(MRF_E_INVAL, "mrf_dict_build: nparam=%d not in 1..8", q.nparam);
+  if (q.is_complex != 0 && q.is_complex != 1) return fail(MRF_E_INVAL, "mrf_dict_build: is_complex must be 0 or 1");
+  if (!q.atoms || !q.params) return fail(MRF_E_INVAL, "mrf_dict_build: null atoms or params");
+  if (q.atoms_dtype != MRF_F64 && q.atoms_dtype != MRF_F32) return fail(MRF_E_INVAL, "mrf_dict_build: bad atoms_dtype");
+  if (q.flags & ~(uint32_t)(MRF_STORE_BF16 | MRF_STORE_FP8)) return fail(MRF_E_INVAL, "mrf_dict_build: unknown flags 0x%x", q.flags);
+  const int64_t K = (int64_t)(q.is_complex ? 2 : 1) * q.L;
+  if (K > (1 << 20)) return fail(MRF_E_INVAL, "mrf_dict_build: L too large");
+  if (q.grid_dims) {
+    int64_t prod = 1;
+    for (int p = 0; p < q.nparam; ++p) {
+      if (q.grid_dims[p] < 1) return fail(MRF_E_INVAL, "mrf_dict_build: grid_dims[%d] < 1", p);
+      prod *= q.grid_dims[p];
+    }
+    if (prod != q.d) return fail(MRF_E_INVAL, "mrf_dict_build: grid_dims product %lld != d %d", (long long)prod, q.d);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto *D = new mrf_dict_s();
+  std::unique_ptr<mrf_dict_s> guard(D);
+  HIP_TRY(hipGetDevice(&D->device));
+  D->d = q.d;
+  D->L = q.L;
+  D->nparam = q.nparam;
+  D->is_complex = q.is_complex;
+  D->K = (int)K;
+  D->Kp = (int)round_up(K, kPitchF32);
+  D->Kq = (int)round_up(K, kPitchLP);
+  D->d_pad = round_up(q.d, kRowPad);
+  D->flags = q.flags;
+  if (q.grid_dims) D->grid_dims.assign(q.grid_dims, q.grid_dims + q.nparam);
+
+  TRY(grow(D->dhat, (size_t)D->d_pad * D->Kp * sizeof(float)));
+  TRY(grow(D->inv_norm, (size_t)q.d * sizeof(float)));
+  TRY(grow(D->params, (size_t)q.d * q.nparam * sizeof(float)));
+  // normalise in FP64 on the host, upload FP32 rows in chunks
+  const int64_t chunk = 8192;
+  std::vector<float> stage((size_t)chunk * D->Kp);
+  std::vector<float> inv((size_t)q.d);
+  for (int64_t r0 = 0; r0 < D->d_pad; r0 += chunk) {
+    const int64_t r1 = std::min<int64_t>(r0 + chunk, D->d_pad);
+    std::fill(stage.begin(), stage.end(), 0.f);
+    for (int64_t j = r0; j < r1; ++j) {
+      if (j >= q.d) continue;
+      double nrm2 = 0.0;
+      if (q.atoms_dtype == MRF_F64) {
+        const double *a = static_cast<const double *>(q.atoms) + j * K;
+        for (int64_t k = 0; k < K; ++k) nrm2 += a[k] * a[k];
+        if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+          return fail(MRF_E_INVAL, "mrf_dict_build: atom %lld has zero or non-finite norm", (long long)j);
+        const double nrm = std::sqrt(nrm2);
+        for (int64_t k = 0; k < K; ++k) stage[(size_t)(j - r0) * D->Kp + k] = (float)(a[k] / nrm);
+        inv[(size_t)j] = (float)(1.0 / nrm);
+      } else {
+        const float *a = static_cast<const float *>(q.atoms) + j * K;
+        for (int64_t k = 0; k < K; ++k) nrm2 += (double)a[k] * a[k];
+        if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+          return fail(MRF_E_INVAL, "mrf_dict_build: atom %lld has zero or non-finite norm", (long long)j);
+        const double nrm = std::sqrt(nrm2);
+        for (int64_t k = 0; k < K; ++k) stage[(size_t)(j - r0) * D->Kp + k] = (float)((double)a[k] / nrm);
+        inv[(size_t)j] = (float)(1.0 / nrm);
+      }
+    }
+    HIP_TRY(hipMemcpy(D->dhat.as<float>() + r0 * D->Kp, stage.data(),
+                      (size_t)(r1 - r0) * D->Kp * sizeof(float), hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMemcpy(D->inv_norm.p, inv.data(), inv.size() * sizeof(float), hipMemcpyHostToDevice));
+  std::vector<float> pf((size_t)q.d * q.nparam);
+  for (size_t i = 0; i < pf.size(); ++i) pf[i] = (float)q.params[i];
+  HIP_TRY(hipMemcpy(D->params.p, pf.data(), pf.size() * sizeof(float), hipMemcpyHostToDevice));
+  D->bytes = (int64_t)(D->dhat.cap + D->inv_norm.cap + D->params.cap);
+  if (q.flags & MRF_STORE_BF16) {
+    TRY(grow(D->dbf16, (size_t)D->d_pad * D->Kq * 2));
+    launch_quantize_rows(D->dhat.as<float>(), D->d_pad, D->K, D->Kp, MRF_BF16, D->dbf16.p, D->Kq,
+                         nullptr, s);
+    LAUNCH_CHECK("quantize_rows(bf16)");
+    D->bytes += (int64_t)D->dbf16.cap;
+  }
+  if (q.flags & MRF_STORE_FP8) {
+    TRY(grow(D->dfp8, (size_t)D->d_pad * D->Kq));
+    TRY(grow(D->fp8_scale, (size_t)D->d_pad * sizeof(float)));
+    launch_quantize_rows(D->dhat.as<float>(), D->d_pad, D->K, D->Kp, MRF_FP8, D->dfp8.p, D->Kq,
+                         D->fp8_scale.as<float>(), s);
+    LAUNCH_CHECK("quantize_rows(fp8)");
+    D->bytes += (int64_t)(D->dfp8.cap + D->fp8_scale.cap);
+  }
+  HIP_TRY(hipHostMalloc((void **)&D->host_scal, 16 * sizeof(double), hipHostMallocDefault));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = guard.release();
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_dict_destroy(mrf_dict D) {
+  g_err.clear();
+  if (!D) return MRF_OK;
+  (void)hipDeviceSynchronize();
+  delete D;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info) {
+  g_err.clear();
+  if (!D || !info) return fail(MRF_E_INVAL, "mrf_dict_query: null argument");
+  info->d = D->d;
+  info->L = D->L;
+  info->nparam = D->nparam;
+  info->is_complex = D->is_complex;
+  info->K = D->K;
+  info->Kp = D->Kp;
+  info->Kq = D->Kq;
+  info->flags = D->flags;
+  info->device_bytes = D->bytes;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *dst, float *scales,
+                                          mrf_stream stream) {
+  g_err.clear();
+  if (!D || !dst) return fail(MRF_E_INVAL, "mrf_dict_copy_atoms: null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision == MRF_FP32) {
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)D->K * 4, D->dhat.p, (size_t)D->Kp * 4, (size_t)D->K * 4,
+                             D->d, hipMemcpyDeviceToDevice, s));
+  } else if (precision == MRF_BF16) {
+    if (!D->dbf16.p) return fail(MRF_E_UNSUPPORTED, "mrf_dict_copy_atoms: no BF16 copy stored");
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)D->K * 2, D->dbf16.p, (size_t)D->Kq * 2,
+                             (size_t)D->K * 2, D->d, hipMemcpyDeviceToDevice, s));
+  } else if (precision == MRF_FP8) {
+    if (!D->dfp8.p) return fail(MRF_E_UNSUPPORTED, "mrf_dict_copy_atoms: no FP8 copy stored");
+    if (!scales) return fail(MRF_E_INVAL, "mrf_dict_copy_atoms: FP8 needs scales");
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)D->K, D->dfp8.p, (size_t)D->Kq, (size_t)D->K, D->d,
+                             hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(scales, D->fp8_scale.p, (size_t)D->d * 4, hipMemcpyDeviceToDevice, s));
+  } else {
+    return fail(MRF_E_INVAL, "mrf_dict_copy_atoms: bad precision %d", precision);
+  }
+  return MRF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// matched filter
+// ---------------------------------------------------------------------------
+namespace {
+
+mrf_status check_opts(const mrf_dict_s *D, const mrf_match_opts *o) {
+  if (!o) return MRF_OK;
+  if (o->method != MRF_EXHAUSTIVE) return fail(MRF_E_UNSUPPORTED, "method %d not supported", o->method);
+  if (o->precision < MRF_FP32 || o->precision > MRF_FP8) return fail(MRF_E_INVAL, "bad precision %d", o->precision);
+  if (o->topk < 0 || o->topk > 8) return fail(MRF_E_INVAL, "topk %d not in 0..8", o->topk);
+  if (o->atom_splits < 0) return fail(MRF_E_INVAL, "atom_splits must be >= 0");
+  if (o->precision == MRF_BF16 && !D->dbf16.p) return fail(MRF_E_UNSUPPORTED, "BF16 scoring needs MRF_STORE_BF16 at build");
+  if (o->precision == MRF_FP8 && !D->dfp8.p) return fail(MRF_E_UNSUPPORTED, "FP8 scoring needs MRF_STORE_FP8 at build");
+  return MRF_OK;
+}
+
+int auto_splits(const mrf_dict_s *D, int64_t n) {
+  const int64_t nvt = (n + 127) / 128;
+  const int64_t nvt8 = (nvt + 7) / 8 * 8;
+  const int64_t ntiles = D->d_pad / 128;
+  int64_t s = (1024 + nvt8 - 1) / nvt8;
+  if (s < 1) s = 1;
+  if (s > ntiles) s = ntiles;
+  if (s > 64) s = 64;
+  return (int)s;
+}
+
+// Score + merge on already packed voxels (ws zp/znorm filled for n rows).
+mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
+                      int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
+                      hipEvent_t ev_s0 = nullptr, hipEvent_t ev_s1 = nullptr,
+                      int *splits_used = nullptr) {
+  const int precision = o ? o->precision : MRF_FP32;
+  int splits = (o && o->atom_splits > 0) ? o->atom_splits : auto_splits(D, n);
+  const int64_t ntiles = D->d_pad / 128;
+  if (splits > ntiles) splits = (int)ntiles;
+  const int64_t n_pad = round_up(n, kRowPad);
+  TRY(grow(D->gamma, (size_t)n * 4));
+  if (splits_used) *splits_used = splits;
+  if (precision == MRF_FP32) {
+    TRY(grow(D->part_s, (size_t)splits * n * 4));
+    TRY(grow(D->part_j, (size_t)splits * n * 4));
+    if (ev_s0) HIP_TRY(hipEventRecord(ev_s0, s));
+    launch_score_f32(D->dhat.as<float>(), D->zp.as<float>(), D->d, D->d_pad, n, n_pad, D->Kp,
+                     splits, D->part_s.as<float>(), D->part_j.as<int>(), s);
+    LAUNCH_CHECK("score_f32");
+    if (ev_s1) HIP_TRY(hipEventRecord(ev_s1, s));
+    launch_merge_argmax(D->part_s.as<float>(), D->part_j.as<int>(), splits, n, D->d,
+                        D->znorm.as<float>(), warm, D->inv_norm.as<float>(),
+                        D->params.as<float>(), D->nparam, idx, pd, corr, params_out,
+                        D->gamma.as<float>(), s);
+    LAUNCH_CHECK("merge_argmax");
+    return MRF_OK;
+  }
+  const int topk = (o && o->topk > 0) ? o->topk : 8;
+  const bool fp8 = precision == MRF_FP8;
+  TRY(grow(D->zq, (size_t)n_pad * D->Kq * (fp8 ? 1 : 2)));
+  if (fp8) TRY(grow(D->zscale, (size_t)n_pad * 4));
+  launch_quantize_rows(D->zp.as<float>(), n_pad, D->K, D->Kp, precision, D->zq.p, D->Kq,
+                       fp8 ? D->zscale.as<float>() : nullptr, s);
+  LAUNCH_CHECK("quantize_rows");
+  TRY(grow(D->cand_s, (size_t)splits * n * 8 * 4));
+  TRY(grow(D->cand_j, (size_t)splits * n * 8 * 4));
+  if (ev_s0) HIP_TRY(hipEventRecord(ev_s0, s));
+  launch_score_lowp(precision, fp8 ? D->dfp8.p : D->dbf16.p, fp8 ? D->fp8_scale.as<float>() : nullptr,
+                    D->zq.p, D->d, D->d_pad, n, n_pad, D->Kq, splits, D->cand_s.as<float>(),
+                    D->cand_j.as<int>(), s);
+  LAUNCH_CHECK("score_lowp");
+  if (ev_s1) HIP_TRY(hipEventRecord(ev_s1, s));
+  launch_merge_rescore(D->cand_s.as<float>(), D->cand_j.as<int>(), splits, topk, n, D->d,
+                       D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->znorm.as<float>(),
+                       warm, D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd,
+                       corr, params_out, D->gamma.as<float>(), s);
+  LAUNCH_CHECK("merge_rescore");
+  return MRF_OK;
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr, c = nullptr, d = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (c) (void)hipEventDestroy(c);
+    if (d) (void)hipEventDestroy(d);
+  }
+};
+
+}  // namespace
+
+extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t n, const void *Z,
+                                int32_t z_layout, int64_t slice_voxels, const int32_t *warm_idx,
+                                int32_t *idx, float *pd, float *corr, void *X_out,
+                                float *params_out, mrf_match_stats *stats, mrf_stream stream) {
+  g_err.clear();
+  if (!D) return fail(MRF_E_INVAL, "mrf_match: null dictionary");
+  TRY(check_opts(D, opts));
+  if (n < 0) return fail(MRF_E_INVAL, "mrf_match: n < 0");
+  if (n > 0 && (!Z || !idx)) return fail(MRF_E_INVAL, "mrf_match: null Z or idx");
+  if (z_layout != MRF_VOXEL_MAJOR && z_layout != MRF_FRAME_MAJOR)
+    return fail(MRF_E_INVAL, "mrf_match: bad z_layout %d", z_layout);
+  if (z_layout == MRF_FRAME_MAJOR && (slice_voxels < 1 || n % slice_voxels != 0))
+    return fail(MRF_E_INVAL, "mrf_match: slice_voxels must divide n for the frame-major layout");
+  if (n > ((int64_t)1 << 31) - 1024) return fail(MRF_E_INVAL, "mrf_match: n too large");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (n == 0) return MRF_OK;
+  const int64_t n_pad = round_up(n, kRowPad);
+  TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
+  TRY(grow(D->znorm, (size_t)n_pad * 4));
+  TRY(grow(D->counters, 2 * sizeof(unsigned long long)));
+  EventPair ev;
+  if (stats) {
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    HIP_TRY(hipEventCreate(&ev.c));
+    HIP_TRY(hipEventCreate(&ev.d));
+    HIP_TRY(hipEventRecord(ev.a, s));
+  }
+  launch_zero(D->counters.p, 16, s);
+  const int real = D->is_complex ? 0 : 1;
+  if (z_layout == MRF_VOXEL_MAJOR)
+    launch_pack_voxel_major(static_cast<const float2 *>(Z), n, n_pad, D->L, real, D->Kp,
+                            D->zp.as<float>(), D->znorm.as<float>(),
+                            D->counters.as<unsigned long long>(), s);
+  else
+    launch_pack_frame_major(static_cast<const float2 *>(Z), nullptr, 0.f, n, n_pad, slice_voxels,
+                            D->L, real, D->Kp, D->zp.as<float>(), D->znorm.as<float>(),
+                            D->counters.as<unsigned long long>(), s);
+  LAUNCH_CHECK("pack");
+  int splits_used = 0;
+  TRY(match_core(D, opts, n, warm_idx, idx, pd, corr, params_out, s, ev.c, ev.d, &splits_used));
+  if (X_out) {
+    launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, real, n, D->L,
+                   z_layout == MRF_FRAME_MAJOR, slice_voxels, static_cast<float2 *>(X_out),
+                   nullptr, nullptr, nullptr, nullptr, s);
+    LAUNCH_CHECK("write_x");
+  }
+  if (stats) {
+    HIP_TRY(hipEventRecord(ev.b, s));
+    unsigned long long cnt[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(cnt, D->counters.p, sizeof cnt, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipEventElapsedTime(&stats->ms, ev.a, ev.b));
+    HIP_TRY(hipEventElapsedTime(&stats->score_ms, ev.c, ev.d));
+    stats->splits = splits_used;
+    stats->n = n;
+    stats->zero_voxels = (int64_t)cnt[0];
+    stats->nonfinite = (int64_t)cnt[1];
+    if (cnt[1] > 0)
+      return fail(MRF_E_NUMERIC, "mrf_match: %llu voxel(s) with non-finite entries", cnt[1]);
+  }
+  return MRF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// forward model
+// ---------------------------------------------------------------------------
+namespace {
+
+bool pow2_in(int x, int lo, int hi) { return x >= lo && x <= hi && (x & (x - 1)) == 0; }
+
+mrf_status check_op(const mrf_op *A) {
+  if (!A) return fail(MRF_E_INVAL, "null operator");
+  if (!pow2_in(A->nx, 16, 256) || !pow2_in(A->ny, 16, 256))
+    return fail(MRF_E_INVAL, "nx=%d ny=%d must be powers of two in 16..256", A->nx, A->ny);
+  if (A->L < 1 || A->nslices < 1) return fail(MRF_E_INVAL, "L and nslices must be >= 1");
+  if (A->nsamples < 0) return fail(MRF_E_INVAL, "nsamples < 0");
+  if (!A->samp_off || (A->nsamples > 0 && !A->samp_idx)) return fail(MRF_E_INVAL, "null sampling arrays");
+  if ((int64_t)A->nslices * A->L > (1 << 30)) return fail(MRF_E_INVAL, "too many frames");
+  return MRF_OK;
+}
+
+// R = A X - Y; partial weighted norms per pair into red[0..npairs).
+mrf_status forward_into(mrf_dict_s *ws, const mrf_op *A, const float2 *X, const float2 *Y,
+                        float2 *R, double *part, hipStream_t s) {
+  const int64_t npix = (int64_t)A->nx * A->ny;
+  const int64_t nimg = (int64_t)A->nslices * A->L;
+  TRY(grow(ws->kbuf, (size_t)nimg * npix * 8));
+  HIP_TRY(hipMemcpyAsync(ws->kbuf.p, X, (size_t)nimg * npix * 8, hipMemcpyDeviceToDevice, s));
+  launch_fft2(ws->kbuf.as<float2>(), nimg, A->ny, A->nx, 0, s);
+  LAUNCH_CHECK("fft2");
+  launch_sample(ws->kbuf.as<float2>(), npix, A->samp_off, A->samp_idx, Y, A->dcf, R, part,
+                (int)nimg, A->nsamples, s);
+  LAUNCH_CHECK("sample");
+  return MRF_OK;
+}
+
+mrf_status adjoint_into(const mrf_op *A, const float2 *R, const float *w, float2 *G,
+                        hipStream_t s) {
+  const int64_t npix = (int64_t)A->nx * A->ny;
+  const int64_t nimg = (int64_t)A->nslices * A->L;
+  launch_scatter(R, w, A->samp_off, A->samp_idx, G, npix, (int)nimg, nimg * npix, A->nsamples, s);
+  LAUNCH_CHECK("scatter");
+  launch_fft2(G, nimg, A->ny, A->nx, 1, s);
+  LAUNCH_CHECK("ifft2");
+  return MRF_OK;
+}
+
+// A thread-local scratch handle for the operator-only entry points.
+// (never freed: its buffers may outlive the HIP runtime at process exit)
+mrf_dict_s &op_scratch() {
+  static thread_local mrf_dict_s *ws = new mrf_dict_s();
+  return *ws;
+}
+
+}  // namespace
+
+extern "C" mrf_status mrf_op_forward(const mrf_op *A, const void *X, const void *Y, void *R,
+                                     double *wnorm2, mrf_stream stream) {
+  g_err.clear();
+  TRY(check_op(A));
+  if (!X || !R) return fail(MRF_E_INVAL, "mrf_op_forward: null X or R");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mrf_dict_s &ws = op_scratch();
+  const int64_t npairs = (int64_t)A->nslices * A->L;
+  TRY(grow(ws.red, (size_t)(npairs + 8) * 8));
+  TRY(forward_into(&ws, A, static_cast<const float2 *>(X), static_cast<const float2 *>(Y),
+                   static_cast<float2 *>(R), ws.red.as<double>(), s));
+  if (wnorm2) {
+    TRY(grow(ws.scal, 64));
+    launch_reduce_sum(ws.red.as<double>(), npairs, ws.scal.as<double>(), s);
+    LAUNCH_CHECK("reduce_sum");
+    HIP_TRY(hipMemcpyAsync(wnorm2, ws.scal.p, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_op_adjoint(const mrf_op *A, const void *R, int32_t apply_dcf, void *G,
+                                     mrf_stream stream) {
+  g_err.clear();
+  TRY(check_op(A));
+  if (!R || !G) return fail(MRF_E_INVAL, "mrf_op_adjoint: null R or G");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return adjoint_into(A, static_cast<const float2 *>(R), apply_dcf ? A->dcf : nullptr,
+                      static_cast<float2 *>(G), s);
+}
+
+// ---------------------------------------------------------------------------
+// projected gradient
+// ---------------------------------------------------------------------------
+namespace {
+
+mrf_status check_step_args(mrf_dict_s *D, const mrf_op *A, const void *Y) {
+  if (!D) return fail(MRF_E_INVAL, "null dictionary");
+  TRY(check_op(A));
+  if (A->L != D->L) return fail(MRF_E_INVAL, "operator L=%d differs from dictionary L=%d", A->L, D->L);
+  if (A->nsamples > 0 && !Y) return fail(MRF_E_INVAL, "null Y");
+  return MRF_OK;
+}
+
+// Given R = A X - Y (workspace rbuf) and G (gbuf): Z = X - mu G, project,
+// write X_new (and dX into kbuf), A dX into abuf, and reduce
+// scal[0] = ||dX||^2, scal[1] = ||A dX||_W^2, scal[2] = ||R + A dX||_W^2.
+mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const float2 *X,
+                 float mu, const int32_t *warm, float2 *X_new, int32_t *idx, float *pd,
+                 float2 *R_update, hipStream_t s) {
+  const int64_t npix = (int64_t)A->nx * A->ny;
+  const int64_t n = (int64_t)A->nslices * npix;
+  const int64_t nimg = (int64_t)A->nslices * A->L;
+  const int64_t n_pad = round_up(n, kRowPad);
+  const int real = D->is_complex ? 0 : 1;
+  TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
+  TRY(grow(D->znorm, (size_t)n_pad * 4));
+  TRY(grow(D->counters, 16));
+  TRY(grow(D->kbuf, (size_t)nimg * npix * 8));
+  TRY(grow(D->abuf, (size_t)(A->nsamples > 0 ? A->nsamples : 1) * 8));
+  TRY(grow(D->red, (size_t)(8192 + 2 * nimg + 8) * 8));
+  TRY(grow(D->scal, 64));
+  launch_zero(D->counters.p, 16, s);
+  launch_pack_frame_major(X, D->gbuf.as<float2>(), mu, n, n_pad, npix, D->L, real, D->Kp,
+                          D->zp.as<float>(), D->znorm.as<float>(),
+                          D->counters.as<unsigned long long>(), s);
+  LAUNCH_CHECK("grad_update_pack");
+  TRY(match_core(D, o, n, warm, idx, pd, nullptr, nullptr, s));
+  double *red = D->red.as<double>();
+  int nb = 0;
+  launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, real, n, D->L, 1, npix,
+                 X_new, X, D->kbuf.as<float2>(), red, &nb, s);
+  LAUNCH_CHECK("write_x");
+  launch_reduce_sum(red, nb, D->scal.as<double>() + 0, s);
+  launch_fft2(D->kbuf.as<float2>(), nimg, A->ny, A->nx, 0, s);
+  LAUNCH_CHECK("fft2(dX)");
+  launch_sample(D->kbuf.as<float2>(), npix, A->samp_off, A->samp_idx, nullptr, A->dcf,
+                D->abuf.as<float2>(), nullptr, (int)nimg, A->nsamples, s);
+  LAUNCH_CHECK("sample(dX)");
+  launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)nimg,
+                    A->nsamples, red + 8192, red + 8192 + nimg, R_update, s);
+  LAUNCH_CHECK("step_norms");
+  launch_reduce_sum(red + 8192, nimg, D->scal.as<double>() + 1, s);
+  launch_reduce_sum(red + 8192 + nimg, nimg, D->scal.as<double>() + 2, s);
+  LAUNCH_CHECK("reduce_sum");
+  return MRF_OK;
+}
+
+// R = A X - Y into rbuf, ||R||_W^2 into scal[3]; G = A^H W R into gbuf.
+mrf_status residual_and_gradient(mrf_dict_s *D, const mrf_op *A, const float2 *X,
+                                 const float2 *Y, bool gradient, hipStream_t s) {
+  const int64_t npix = (int64_t)A->nx * A->ny;
+  const int64_t nimg = (int64_t)A->nslices * A->L;
+  TRY(grow(D->rbuf, (size_t)(A->nsamples > 0 ? A->nsamples : 1) * 8));
+  TRY(grow(D->gbuf, (size_t)nimg * npix * 8));
+  TRY(grow(D->red, (size_t)(8192 + 2 * nimg + 8) * 8));
+  TRY(grow(D->scal, 64));
+  double *red = D->red.as<double>();
+  TRY(forward_into(D, A, X, Y, D->rbuf.as<float2>(), red + 8192, s));
+  launch_reduce_sum(red + 8192, nimg, D->scal.as<double>() + 3, s);
+  LAUNCH_CHECK("reduce_sum");
+  if (gradient) TRY(adjoint_into(A, D->rbuf.as<float2>(), A->dcf, D->gbuf.as<float2>(), s));
+  return MRF_OK;
+}
+
+mrf_status read_scalars(mrf_dict_s *D, int count, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(D->host_scal, D->scal.p, (size_t)count * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MRF_OK;
+}
+
+}  // namespace
+
+extern "C" mrf_status mrf_ipg_step(mrf_dict D, const mrf_op *A, const void *Y, const void *X_in,
+                                   void *X_out, const int32_t *idx_in, int32_t *idx_out,
+                                   float *pd, float mu, const mrf_match_opts *opts,
+                                   mrf_step_stats *stats, mrf_stream stream) {
+  g_err.clear();
+  TRY(check_step_args(D, A, Y));
+  TRY(check_opts(D, opts));
+  if (!X_in || !X_out || !idx_out) return fail(MRF_E_INVAL, "mrf_ipg_step: null X_in, X_out or idx_out");
+  if (X_in == X_out) return fail(MRF_E_INVAL, "mrf_ipg_step: X_in and X_out must differ");
+  if (!std::isfinite(mu)) return fail(MRF_E_INVAL, "mrf_ipg_step: non-finite mu");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  EventPair ev;
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    HIP_TRY(hipEventRecord(ev.a, s));
+  }
+  TRY(residual_and_gradient(D, A, static_cast<const float2 *>(X_in), static_cast<const float2 *>(Y),
+                            true, s));
+  TRY(trial(D, A, opts, static_cast<const float2 *>(X_in), mu, idx_in,
+            static_cast<float2 *>(X_out), idx_out, pd, nullptr, s));
+  if (stats) {
+    HIP_TRY(hipEventRecord(ev.b, s));
+    TRY(read_scalars(D, 4, s));
+    HIP_TRY(hipEventElapsedTime(&stats->ms, ev.a, ev.b));
+    stats->dx2 = D->host_scal[0];
+    stats->adx2 = D->host_scal[1];
+    stats->f_out = D->host_scal[2];
+    stats->f_in = D->host_scal[3];
+  }
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
+                                    const mrf_solve_opts *o, void *X, int32_t *idx, float *pd,
+                                    float *params_out, mrf_solve_stats *stats,
+                                    mrf_stream stream) {
+  g_err.clear();
+  TRY(check_step_args(D, A, Y));
+  if (!o) return fail(MRF_E_INVAL, "mrf_ipg_solve: null options");
+  TRY(check_opts(D, &o->match));
+  if (!X || !idx) return fail(MRF_E_INVAL, "mrf_ipg_solve: null X or idx");
+  if (!(o->mu0 > 0.f) || !std::isfinite(o->mu0)) return fail(MRF_E_INVAL, "mrf_ipg_solve: mu0 must be > 0");
+  if (o->adaptive && !(o->zeta > 1.f)) return fail(MRF_E_INVAL, "mrf_ipg_solve: zeta must be > 1");
+  if (o->max_iter < 1) return fail(MRF_E_INVAL, "mrf_ipg_solve: max_iter must be >= 1");
+  if (o->max_shrinks < 0) return fail(MRF_E_INVAL, "mrf_ipg_solve: max_shrinks must be >= 0");
+  if (stats && stats->cap < 0) return fail(MRF_E_INVAL, "mrf_ipg_solve: stats->cap < 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t npix = (int64_t)A->nx * A->ny;
+  const int64_t n = (int64_t)A->nslices * npix;
+  const int64_t nimg = (int64_t)A->nslices * A->L;
+  const float2 *Yc = static_cast<const float2 *>(Y);
+  TRY(grow(D->xbuf, (size_t)nimg * npix * 8));
+  TRY(grow(D->idxbuf, (size_t)n * 4));
+  TRY(grow(D->pdbuf, (size_t)n * 4));
+  EventPair ev;
+  HIP_TRY(hipEventCreate(&ev.a));
+  HIP_TRY(hipEventCreate(&ev.b));
+  HIP_TRY(hipEventRecord(ev.a, s));
+
+  float2 *cur = static_cast<float2 *>(X), *nxt = D->xbuf.as<float2>();
+  int32_t *idx_cur = idx, *idx_nxt = D->idxbuf.as<int32_t>();
+  float *pd_cur = pd ? pd : D->pdbuf.as<float>();
+  float *pd_nxt = D->pdbuf.as<float>();
+  TRY(grow(D->gbuf, (size_t)nimg * npix * 8));
+  TRY(residual_and_gradient(D, A, cur, Yc, false, s));
+  TRY(read_scalars(D, 4, s));
+  double f = D->host_scal[3];
+  if (stats) {
+    stats->iters = 0;
+    stats->total_shrinks = 0;
+    stats->f0 = f;
+  }
+  bool have_idx = false;
+  float mu_init = o->mu0;
+  for (int k = 0; k < o->max_iter; ++k) {
+    TRY(adjoint_into(A, D->rbuf.as<float2>(), A->dcf, D->gbuf.as<float2>(), s));
+    float mu = mu_init;
+    int shrinks = 0;
+    double dx2 = 0, adx2 = 0, f_new = 0;
+    for (;;) {
+      TRY(trial(D, A, &o->match, cur, mu, have_idx ? idx_cur : nullptr, nxt, idx_nxt,
+                pd ? pd_nxt : nullptr, nullptr, s));
+      TRY(read_scalars(D, 3, s));
+      dx2 = D->host_scal[0];
+      adx2 = D->host_scal[1];
+      f_new = D->host_scal[2];
+      const bool accept = !o->adaptive || dx2 == 0.0 || adx2 == 0.0 || (double)mu < dx2 / adx2;
+      if (accept) break;
+      mu /= o->zeta;
+      ++shrinks;
+      if (shrinks > o->max_shrinks)
+        return fail(MRF_E_NOCONV, "mrf_ipg_solve: step size not accepted after %d shrinks at iteration %d",
+                    o->max_shrinks, k);
+    }
+    // accept: R <- R + A dX (abuf holds A dX), swap iterates
+    launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)nimg,
+                      A->nsamples, D->red.as<double>() + 8192, D->red.as<double>() + 8192 + nimg,
+                      D->rbuf.as<float2>(), s);
+    LAUNCH_CHECK("residual update");
+    std::swap(cur, nxt);
+    std::swap(idx_cur, idx_nxt);
+    if (pd) std::swap(pd_cur, pd_nxt);
+    have_idx = true;
+    if (o->kappa && k == 0) {
+      // kappa = ||Y|| / ||A X^1|| (plain norms), then X^1 <- kappa X^1, mu <- kappa mu
+      mrf_op A0 = *A;
+      A0.dcf = nullptr;
+      double *red = D->red.as<double>();
+      TRY(forward_into(D, &A0, cur, nullptr, D->abuf.as<float2>(), red + 8192, s));
+      launch_reduce_sum(red + 8192, nimg, D->scal.as<double>() + 4, s);
+      int nb = 0;
+      launch_norm2(Yc, A->nsamples, red, &nb, s);
+      launch_reduce_sum(red, nb, D->scal.as<double>() + 5, s);
+      LAUNCH_CHECK("kappa norms");
+      TRY(read_scalars(D, 6, s));
+      const double ax2 = D->host_scal[4], y2 = D->host_scal[5];
+      const float kap = (ax2 > 0.0) ? (float)std::sqrt(y2 / ax2) : 1.f;
+      launch_scale(cur, nimg * npix, kap, s);
+      if (pd) launch_scale_f32(pd_cur, n, kap, s);
+      LAUNCH_CHECK("kappa scale");
+      mu_init *= kap;
+      TRY(residual_and_gradient(D, A, cur, Yc, false, s));
+      TRY(read_scalars(D, 4, s));
+      f_new = D->host_scal[3];
+    }
+    if (stats) {
+      if (k < stats->cap) {
+        if (stats->f) stats->f[k] = f_new;
+        if (stats->mu) stats->mu[k] = mu;
+        if (stats->shrinks) stats->shrinks[k] = shrinks;
+      }
+      stats->iters = k + 1;
+      stats->total_shrinks += shrinks;
+    }
+    const double f_old = f;
+    f = f_new;
+    if (dx2 == 0.0) break;
+    if (o->rel_tol > 0.0 && f_old > 0.0 && (f_old - f_new) / f_old < o->rel_tol) break;
+  }
+  // results into the caller's buffers
+  if (cur != static_cast<float2 *>(X))
+    HIP_TRY(hipMemcpyAsync(X, cur, (size_t)nimg * npix * 8, hipMemcpyDeviceToDevice, s));
+  if (idx_cur != idx) HIP_TRY(hipMemcpyAsync(idx, idx_cur, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+  if (pd && pd_cur != pd) HIP_TRY(hipMemcpyAsync(pd, pd_cur, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+  if (params_out) {
+    launch_lookup(idx, D->params.as<float>(), D->nparam, n, params_out, s);
+    LAUNCH_CHECK("lookup");
+  }
+  HIP_TRY(hipEventRecord(ev.b, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (stats) HIP_TRY(hipEventElapsedTime(&stats->ms, ev.a, ev.b));
+  return MRF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// encodings
+// ---------------------------------------------------------------------------
+extern "C" mrf_status mrf_quantize_rows(const float *in, int64_t rows, int32_t K, int64_t in_pitch,
+                                        int32_t precision, void *out, int64_t out_pitch,
+                                        float *scales, mrf_stream stream) {
+  g_err.clear();
+  if (!in || !out) return fail(MRF_E_INVAL, "mrf_quantize_rows: null in or out");
+  if (rows < 0 || K < 1 || in_pitch < K || out_pitch < K) return fail(MRF_E_INVAL, "mrf_quantize_rows: bad sizes");
+  if (precision != MRF_BF16 && precision != MRF_FP8) return fail(MRF_E_INVAL, "mrf_quantize_rows: precision must be BF16 or FP8");
+  if (precision == MRF_FP8 && !scales) return fail(MRF_E_INVAL, "mrf_quantize_rows: FP8 needs scales");
+  if (rows == 0) return MRF_OK;
+  launch_quantize_rows(in, rows, K, in_pitch, precision, out, out_pitch, scales,
+                       static_cast<hipStream_t>(stream));
+  LAUNCH_CHECK("quantize_rows");
+  return MRF_OK;
+}

@@ -1,0 +1,115 @@
+// Internal declarations shared by the host library and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/mrf.h"
+
+namespace mrf {
+
+// Row pitches: FP32 rows are padded to a multiple of 16 elements (the FP32
+// scoring kernel's K chunk), reduced-precision rows to a multiple of 128
+// (the FP8 MFMA K step; also a multiple of the BF16 one).
+constexpr int kPitchF32 = 16;
+constexpr int kPitchLP = 128;
+// Atom / voxel row counts are padded to multiples of 256 so every tiling of
+// the scoring kernels reads inside the allocation.
+constexpr int kRowPad = 256;
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ---------------------------------------------------------------- matched filter
+// Pack voxel rows into the padded FP32 contraction layout [n_pad][Kp]:
+// complex atoms -> interleaved (re, im) rows of length 2L; real atoms -> Re(Z)
+// rows of length L.  znorm[v] = ||Z_v|| (complex norm, FP64 accumulation),
+// -1 for a non-finite row.  counters[0] += zero rows, counters[1] += non-finite.
+// Frame-major input: Zf[s][L][npix]; with G != nullptr the packed value is
+// X - mu*G (the gradient update of eq. blip), G in the same layout as X.
+void launch_pack_voxel_major(const float2 *Z, int64_t n, int64_t n_pad, int L, int real_atoms,
+                             int Kp, float *Zp, float *znorm, unsigned long long *counters,
+                             hipStream_t s);
+void launch_pack_frame_major(const float2 *X, const float2 *G, float mu, int64_t n, int64_t n_pad,
+                             int64_t npix, int L, int real_atoms, int Kp, float *Zp, float *znorm,
+                             unsigned long long *counters, hipStream_t s);
+
+// Exhaustive FP32 scoring with fused per-voxel argmax.  D: [d_pad][Kp] FP32
+// normalised atoms; Zp: [n_pad][Kp].  Writes per-split (score, index) partials
+// [splits][n].
+void launch_score_f32(const float *D, const float *Zp, int d, int64_t d_pad, int64_t n,
+                      int64_t n_pad, int Kp, int splits, float *part_s, int *part_j,
+                      hipStream_t s);
+
+// Reduced-precision scoring with a fused per-voxel top-k (k <= 8).  Dq/Zq are
+// BF16 (uint16) or FP8-E4M3 (uint8) rows of pitch Kq; dscale (FP8 only) the
+// per-atom scales.  Writes per-split candidate lists [splits][n][8]
+// (score, index), unused slots index -1.
+void launch_score_lowp(int precision, const void *Dq, const float *dscale, const void *Zq,
+                       int d, int64_t d_pad, int64_t n, int64_t n_pad, int Kq, int splits,
+                       float *cand_s, int *cand_j, hipStream_t s);
+
+// Merge the per-split partial argmax, then rescale (eq. exactPs) and look up.
+// gamma_hat[v] = max(score,0) is the multiplier of the normalised atom.
+void launch_merge_argmax(const float *part_s, const int *part_j, int splits, int64_t n, int d,
+                         const float *znorm, const int32_t *warm, const float *inv_norm,
+                         const float *params, int nparam, int32_t *idx, float *pd, float *corr,
+                         float *params_out, float *gamma_hat, hipStream_t s);
+// Merge per-split top-k candidate lists, rescore the k best in FP32 against
+// the FP32 normalised atoms, then rescale and look up as launch_merge_argmax.
+void launch_merge_rescore(const float *cand_s, const int *cand_j, int splits, int topk,
+                          int64_t n, int d, const float *Zp, const float *D, int Kp, int K,
+                          const float *znorm, const int32_t *warm, const float *inv_norm,
+                          const float *params, int nparam, int32_t *idx, float *pd, float *corr,
+                          float *params_out, float *gamma_hat, hipStream_t s);
+
+// X_v = gamma_hat_v * Dhat_{idx_v} (zero where idx < 0), written voxel-major
+// [n][L] or frame-major [S][L][npix].  With X_prev != nullptr (frame-major only)
+// also writes dX = X_new - X_prev into dX and per-block FP64 partial sums of
+// |dX|^2 into part (grid-sized).
+void launch_write_x(const int32_t *idx, const float *gamma_hat, const float *D, int Kp,
+                    int real_atoms, int64_t n, int L, int frame_major, int64_t npix,
+                    float2 *X, const float2 *X_prev, float2 *dX, double *part, int *nblocks_out,
+                    hipStream_t s);
+
+// BF16 / FP8 row encoders (see mrf_quantize_rows).
+void launch_quantize_rows(const float *in, int64_t rows, int K, int64_t in_pitch, int precision,
+                          void *out, int64_t out_pitch, float *scales, hipStream_t s);
+
+// ---------------------------------------------------------------- Fourier operator
+// In-place unitary 2-D DFT of `nimg` frames of ny x nx complex64 (forward:
+// exp(-2 pi i k.r/N), inverse: conjugate), each 1-D pass scaled by 1/sqrt(N).
+void launch_fft2(float2 *data, int64_t nimg, int ny, int nx, int inverse, hipStream_t s);
+// R[i] = K[pair image][idx[i]] - Y[i] (Y may be null); part[p] = sum_i w_i |R_i|^2
+// over the samples of pair p (w = 1 when dcf is null).
+// Sample ranges are clamped to [0, M) and indices outside [0, npix) read as
+// zero (scatter: are skipped), so malformed patterns cannot address outside
+// the buffers.
+void launch_sample(const float2 *K, int64_t npix, const int64_t *off, const int32_t *sidx,
+                   const float2 *Y, const float *w, float2 *R, double *part, int npairs,
+                   int64_t M, hipStream_t s);
+// K zero-filled, then K[pair image][idx[i]] = w_i R_i (w = 1 when null).
+void launch_scatter(const float2 *R, const float *w, const int64_t *off, const int32_t *sidx,
+                    float2 *K, int64_t npix, int npairs, int64_t total, int64_t M, hipStream_t s);
+// part[p] = sum w|A|^2 and part2[p] = sum w|R + A|^2 per pair; optionally R += A.
+void launch_step_norms(const float2 *R, const float2 *A, const float *w, const int64_t *off,
+                       int npairs, int64_t M, double *part_a, double *part_ra, float2 *R_update,
+                       hipStream_t s);
+// out[0] = sum of part[0..count) in a fixed order (one block).
+void launch_reduce_sum(const double *part, int64_t count, double *out, hipStream_t s);
+// y = x * a (complex64, elementwise), used by the kappa rescaling.
+void launch_scale(float2 *x, int64_t count, float a, hipStream_t s);
+void launch_zero(void *p, int64_t bytes, hipStream_t s);
+
+}  // namespace mrf
+
+namespace mrf {
+// params_out[v][p] = params[idx[v]][p] (0 where idx < 0).
+void launch_lookup(const int32_t *idx, const float *params, int nparam, int64_t n,
+                   float *params_out, hipStream_t s);
+// pd[v] *= a, gamma_hat[v] *= a (kappa rescaling of the first iterate).
+void launch_scale_f32(float *x, int64_t count, float a, hipStream_t s);
+// Per-block FP64 partial sums of |x_i|^2 (at most 1024 blocks) into part.
+void launch_norm2(const float2 *x, int64_t count, double *part, int *nblocks_out, hipStream_t s);
+}  // namespace mrf

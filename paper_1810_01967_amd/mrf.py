@@ -1,0 +1,364 @@
+"""Thin ctypes binding of the C ABI in include/mrf.h.
+
+Functions keep the C names (mrf_match, mrf_ipg_step, ...).  They only
+marshal arguments: device buffers are torch CUDA tensors (torch is used for
+device memory and the current stream), every step of the computation runs in
+libmrf.so.  There is no fallback: a missing library or a failing call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrf.so")
+
+MRF_OK = 0
+MRF_E_INVAL, MRF_E_NOMEM, MRF_E_HIP, MRF_E_UNSUPPORTED, MRF_E_NUMERIC, MRF_E_NOCONV = -1, -2, -3, -4, -5, -6
+MRF_STORE_BF16, MRF_STORE_FP8 = 2, 4
+MRF_F64, MRF_F32 = 0, 1
+MRF_EXHAUSTIVE = 0
+MRF_FP32, MRF_BF16, MRF_FP8 = 0, 1, 2
+MRF_VOXEL_MAJOR, MRF_FRAME_MAJOR = 0, 1
+PRECISION = {"fp32": MRF_FP32, "bf16": MRF_BF16, "fp8": MRF_FP8}
+
+EXPORTS = ["mrf_last_error", "mrf_version", "mrf_dict_build", "mrf_dict_destroy", "mrf_dict_query",
+           "mrf_dict_copy_atoms", "mrf_match", "mrf_op_forward", "mrf_op_adjoint", "mrf_ipg_step",
+           "mrf_ipg_solve", "mrf_quantize_rows"]
+
+
+class MrfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"mrf status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+# --------------------------------------------------------------------------- structs
+class DictDesc(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("L", ctypes.c_int32), ("nparam", ctypes.c_int32),
+                ("is_complex", ctypes.c_int32), ("atoms", ctypes.c_void_p),
+                ("atoms_dtype", ctypes.c_int32), ("params", ctypes.c_void_p),
+                ("grid_dims", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+class DictInfo(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("L", ctypes.c_int32), ("nparam", ctypes.c_int32),
+                ("is_complex", ctypes.c_int32), ("K", ctypes.c_int32), ("Kp", ctypes.c_int32),
+                ("Kq", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class MatchOpts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("topk", ctypes.c_int32), ("atom_splits", ctypes.c_int32)]
+
+
+class MatchStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("zero_voxels", ctypes.c_int64),
+                ("nonfinite", ctypes.c_int64), ("ms", ctypes.c_float),
+                ("score_ms", ctypes.c_float), ("splits", ctypes.c_int32)]
+
+
+class Op(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("nslices", ctypes.c_int32), ("nsamples", ctypes.c_int64),
+                ("samp_off", ctypes.c_void_p), ("samp_idx", ctypes.c_void_p),
+                ("dcf", ctypes.c_void_p)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("dx2", ctypes.c_double), ("adx2", ctypes.c_double), ("f_in", ctypes.c_double),
+                ("f_out", ctypes.c_double), ("ms", ctypes.c_float)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("mu0", ctypes.c_float), ("zeta", ctypes.c_float), ("adaptive", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("rel_tol", ctypes.c_double),
+                ("max_shrinks", ctypes.c_int32), ("kappa", ctypes.c_int32),
+                ("match", MatchOpts)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("total_shrinks", ctypes.c_int32),
+                ("cap", ctypes.c_int32), ("f", ctypes.c_void_p), ("mu", ctypes.c_void_p),
+                ("shrinks", ctypes.c_void_p), ("f0", ctypes.c_double), ("ms", ctypes.c_float)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libmrf.so (built in-tree by build.py); raises if it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1810_01967_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.mrf_last_error.restype = ctypes.c_char_p
+        L.mrf_version.restype = ctypes.c_char_p
+        for name in EXPORTS[2:]:
+            getattr(L, name).restype = ctypes.c_int
+        L.mrf_dict_build.argtypes = [ctypes.POINTER(DictDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+        L.mrf_dict_destroy.argtypes = [ctypes.c_void_p]
+        L.mrf_dict_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(DictInfo)]
+        L.mrf_dict_copy_atoms.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]
+        L.mrf_match.argtypes = [ctypes.c_void_p, ctypes.POINTER(MatchOpts), ctypes.c_int64,
+                                ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.POINTER(MatchStats), ctypes.c_void_p]
+        L.mrf_op_forward.argtypes = [ctypes.POINTER(Op), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+        L.mrf_op_adjoint.argtypes = [ctypes.POINTER(Op), ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p]
+        L.mrf_ipg_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(Op), ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float,
+                                   ctypes.POINTER(MatchOpts), ctypes.POINTER(StepStats), ctypes.c_void_p]
+        L.mrf_ipg_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Op), ctypes.c_void_p,
+                                    ctypes.POINTER(SolveOpts), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(SolveStats),
+                                    ctypes.c_void_p]
+        L.mrf_quantize_rows.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+        _LIB = L
+    return _LIB
+
+
+def _check(status):
+    if status != MRF_OK:
+        raise MrfError(status, lib().mrf_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t):
+    """Device pointer of a CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def mrf_version() -> str:
+    return lib().mrf_version().decode()
+
+
+# --------------------------------------------------------------------------- dictionary
+class Dictionary:
+    """Handle of a device dictionary (mrf_dict_build / mrf_dict_destroy)."""
+
+    def __init__(self, atoms, params, grid_dims=None, store_bf16=False, store_fp8=False,
+                 stream=None):
+        atoms = np.asarray(atoms)
+        self.is_complex = bool(np.iscomplexobj(atoms))
+        d, L = atoms.shape
+        if self.is_complex:
+            if atoms.dtype == np.complex64:
+                host = np.ascontiguousarray(atoms).view(np.float32)
+                dt = MRF_F32
+            else:
+                host = np.ascontiguousarray(atoms.astype(np.complex128)).view(np.float64)
+                dt = MRF_F64
+        else:
+            if atoms.dtype == np.float32:
+                host, dt = np.ascontiguousarray(atoms), MRF_F32
+            else:
+                host, dt = np.ascontiguousarray(atoms, dtype=np.float64), MRF_F64
+        params = np.ascontiguousarray(params, dtype=np.float64)
+        if params.ndim == 1:
+            params = params[:, None]
+        self.nparam = params.shape[1]
+        gd = None if grid_dims is None else np.ascontiguousarray(grid_dims, dtype=np.int32)
+        flags = (MRF_STORE_BF16 if store_bf16 else 0) | (MRF_STORE_FP8 if store_fp8 else 0)
+        desc = DictDesc(d, L, self.nparam, int(self.is_complex), host.ctypes.data, dt,
+                        params.ctypes.data, None if gd is None else gd.ctypes.data, flags)
+        h = ctypes.c_void_p()
+        _check(lib().mrf_dict_build(ctypes.byref(desc), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.d, self.L = d, L
+        self.grid_dims = None if gd is None else tuple(int(x) for x in gd)
+
+    def info(self) -> DictInfo:
+        inf = DictInfo()
+        _check(lib().mrf_dict_query(self.handle, ctypes.byref(inf)))
+        return inf
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().mrf_dict_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mrf_dict_copy_atoms(D: Dictionary, precision="fp32", stream=None):
+    torch = _torch()
+    inf = D.info()
+    p = PRECISION[precision]
+    dtype = {MRF_FP32: torch.float32, MRF_BF16: torch.int16, MRF_FP8: torch.uint8}[p]
+    out = torch.empty((inf.d, inf.K), dtype=dtype, device="cuda")
+    scales = torch.empty(inf.d, dtype=torch.float32, device="cuda") if p == MRF_FP8 else None
+    _check(lib().mrf_dict_copy_atoms(D.handle, p, _dev(out), _dev(scales), _stream(stream)))
+    return (out, scales) if p == MRF_FP8 else out
+
+
+def match_opts(precision="fp32", topk=8, atom_splits=0) -> MatchOpts:
+    return MatchOpts(MRF_EXHAUSTIVE, PRECISION[precision], int(topk), int(atom_splits))
+
+
+# --------------------------------------------------------------------------- matched filter
+def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp32", topk=8,
+              atom_splits=0, warm_idx=None, want_pd=True, want_corr=True, want_X=False,
+              want_params=False, stats=False, out=None, stream=None):
+    """Matched filter of the voxels in Z (complex64 CUDA tensor, [n][L] for
+    layout 'voxel', [S][L][...] for 'frame').  Returns a dict of CUDA tensors
+    (idx, pd, corr, X, params) and, with stats=True, a MatchStats."""
+    torch = _torch()
+    if layout == "voxel":
+        n = Z.shape[0]
+        zl, sv = MRF_VOXEL_MAJOR, 0
+    else:
+        sv = int(slice_voxels) if slice_voxels is not None else int(np.prod(Z.shape[2:]))
+        n = int(Z.numel() // D.L)
+        zl = MRF_FRAME_MAJOR
+    o = out if out is not None else {}
+    dev = Z.device
+    if "idx" not in o:
+        o["idx"] = torch.empty(n, dtype=torch.int32, device=dev)
+    if want_pd and "pd" not in o:
+        o["pd"] = torch.empty(n, dtype=torch.float32, device=dev)
+    if want_corr and "corr" not in o:
+        o["corr"] = torch.empty(n, dtype=torch.float32, device=dev)
+    if want_X and "X" not in o:
+        o["X"] = torch.empty_like(Z)
+    if want_params and "params" not in o:
+        o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
+    opts = match_opts(precision, topk, atom_splits)
+    st = MatchStats() if stats else None
+    status = lib().mrf_match(D.handle, ctypes.byref(opts), n, _dev(Z), zl, sv, _dev(warm_idx),
+                             _dev(o["idx"]), _dev(o.get("pd")), _dev(o.get("corr")),
+                             _dev(o.get("X")), _dev(o.get("params")),
+                             ctypes.byref(st) if st is not None else None, _stream(stream))
+    _check(status)
+    if stats:
+        o["stats"] = st
+    return o
+
+
+# --------------------------------------------------------------------------- operator
+class Operator:
+    """mrf_op over device copies of a CSR sampling pattern (see include/mrf.h)."""
+
+    def __init__(self, nx, ny, L, nslices, samp_off, samp_idx, dcf=None):
+        torch = _torch()
+        self.off = torch.as_tensor(np.asarray(samp_off, dtype=np.int64)).cuda()
+        self.idx = torch.as_tensor(np.asarray(samp_idx, dtype=np.int32)).cuda()
+        self.dcf = None if dcf is None else torch.as_tensor(np.asarray(dcf, dtype=np.float32)).cuda()
+        self.nx, self.ny, self.L, self.nslices = int(nx), int(ny), int(L), int(nslices)
+        self.M = int(self.off[-1].item()) if self.off.numel() else 0
+        self.c = Op(self.nx, self.ny, self.L, self.nslices, self.M, _dev(self.off),
+                    _dev(self.idx) if self.idx.numel() else None, _dev(self.dcf))
+
+    @property
+    def n(self):
+        return self.nslices * self.nx * self.ny
+
+    @classmethod
+    def from_sampling(cls, smp):
+        return cls(smp.nx, smp.ny, smp.L, smp.S, smp.off, smp.idx, smp.dcf)
+
+
+def mrf_op_forward(A: Operator, X, Y=None, want_norm=False, stream=None):
+    torch = _torch()
+    R = torch.empty(max(A.M, 1), dtype=torch.complex64, device="cuda")[:A.M]
+    nrm = ctypes.c_double(0.0)
+    _check(lib().mrf_op_forward(ctypes.byref(A.c), _dev(X), _dev(Y), R.data_ptr(),
+                                ctypes.byref(nrm) if want_norm else None, _stream(stream)))
+    return (R, nrm.value) if want_norm else R
+
+
+def mrf_op_adjoint(A: Operator, R, apply_dcf=True, stream=None):
+    torch = _torch()
+    G = torch.empty((A.nslices, A.L, A.ny, A.nx), dtype=torch.complex64, device="cuda")
+    _check(lib().mrf_op_adjoint(ctypes.byref(A.c), R.data_ptr() if A.M else None,
+                                int(bool(apply_dcf)), _dev(G), _stream(stream)))
+    return G
+
+
+# --------------------------------------------------------------------------- projected gradient
+def mrf_ipg_step(D: Dictionary, A: Operator, Y, X_in, mu, idx_in=None, precision="fp32", topk=8,
+                 atom_splits=0, stats=True, stream=None):
+    torch = _torch()
+    X_out = torch.empty_like(X_in)
+    idx = torch.empty(A.n, dtype=torch.int32, device="cuda")
+    pd = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    opts = match_opts(precision, topk, atom_splits)
+    st = StepStats() if stats else None
+    _check(lib().mrf_ipg_step(D.handle, ctypes.byref(A.c), _dev(Y), _dev(X_in), _dev(X_out),
+                              _dev(idx_in), _dev(idx), _dev(pd), float(mu), ctypes.byref(opts),
+                              ctypes.byref(st) if st is not None else None, _stream(stream)))
+    return X_out, idx, pd, st
+
+
+def mrf_ipg_solve(D: Dictionary, A: Operator, Y, X0=None, mu0=1.0, zeta=2.0, adaptive=True,
+                  max_iter=50, rel_tol=1e-6, max_shrinks=30, kappa=False, precision="fp32",
+                  topk=8, atom_splits=0, want_params=True, stream=None):
+    torch = _torch()
+    X = (torch.zeros((A.nslices, A.L, A.ny, A.nx), dtype=torch.complex64, device="cuda")
+         if X0 is None else X0.clone())
+    idx = torch.empty(A.n, dtype=torch.int32, device="cuda")
+    pd = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    params = torch.empty((A.n, D.nparam), dtype=torch.float32, device="cuda") if want_params else None
+    o = SolveOpts(float(mu0), float(zeta), int(bool(adaptive)), int(max_iter), float(rel_tol),
+                  int(max_shrinks), int(bool(kappa)), match_opts(precision, topk, atom_splits))
+    cap = int(max_iter)
+    f = np.zeros(cap, dtype=np.float64)
+    mu = np.zeros(cap, dtype=np.float32)
+    sh = np.zeros(cap, dtype=np.int32)
+    st = SolveStats(0, 0, cap, f.ctypes.data, mu.ctypes.data, sh.ctypes.data, 0.0, 0.0)
+    _check(lib().mrf_ipg_solve(D.handle, ctypes.byref(A.c), _dev(Y), ctypes.byref(o), _dev(X),
+                               _dev(idx), _dev(pd), _dev(params), ctypes.byref(st), _stream(stream)))
+    k = st.iters
+    hist = dict(iters=k, total_shrinks=st.total_shrinks, f0=st.f0, f=f[:k].copy(), mu=mu[:k].copy(),
+                shrinks=sh[:k].copy(), ms=st.ms)
+    return X, idx, pd, params, hist
+
+
+# --------------------------------------------------------------------------- encodings
+def mrf_quantize_rows(x, precision, out_pitch=None, stream=None):
+    """Encode FP32 rows (2-D CUDA tensor) to BF16 (int16 bit patterns) or FP8
+    (uint8 codes + per-row scales)."""
+    torch = _torch()
+    rows, K = x.shape
+    pitch = int(out_pitch or K)
+    p = PRECISION[precision]
+    if p == MRF_BF16:
+        out = torch.empty((rows, pitch), dtype=torch.int16, device="cuda")
+        sc = None
+    else:
+        out = torch.empty((rows, pitch), dtype=torch.uint8, device="cuda")
+        sc = torch.empty(rows, dtype=torch.float32, device="cuda")
+    _check(lib().mrf_quantize_rows(_dev(x), rows, K, x.stride(0), p, _dev(out), pitch, _dev(sc),
+                                   _stream(stream)))
+    return out, sc
