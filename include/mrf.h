@@ -115,16 +115,28 @@ mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *dst, float *
 /* ------------------------------------------------------------------------ */
 /* Matched filter P_cone(D) (eq. exactP, eq. exactPs)                         */
 /* ------------------------------------------------------------------------ */
-enum { MRF_EXHAUSTIVE = 0 };
+enum {
+  MRF_EXHAUSTIVE = 0, /* every atom scored (eq. exactP) */
+  MRF_LEARNED = 1     /* network proposal + exact local search + exhaustive fallback */
+};
 enum { MRF_FP32 = 0, MRF_BF16 = 1, MRF_FP8 = 2 };
 enum { MRF_VOXEL_MAJOR = 0, MRF_FRAME_MAJOR = 1 };
 
+typedef struct mrf_net_s *mrf_net; /* learned proposal network (see below) */
+
 typedef struct {
-  int32_t method;      /* MRF_EXHAUSTIVE */
-  int32_t precision;   /* candidate scoring: MRF_FP32 (exact argmax), MRF_BF16 or
-                          MRF_FP8 (top-k by reduced-precision score, then FP32 rescore) */
+  int32_t method;      /* MRF_EXHAUSTIVE or MRF_LEARNED */
+  int32_t precision;   /* exhaustive scoring: MRF_FP32 (exact argmax), MRF_BF16 or
+                          MRF_FP8 (top-k by reduced-precision score, then FP32 rescore).
+                          The learned path's local search and fallback score in FP32. */
   int32_t topk;        /* reduced-precision candidates rescored in FP32, 1..8 (0 = 8) */
   int32_t atom_splits; /* 0 = automatic; else number of atom ranges scored in parallel */
+  mrf_net net;         /* MRF_LEARNED: trained network (input length = the dictionary's K) */
+  int32_t box_radius;  /* MRF_LEARNED: half-width of the local box per parameter (0 = 3) */
+  float fallback_corr; /* MRF_LEARNED: exhaustive fallback below this normalised
+                          correlation (0 = 0.98; negative disables the fallback) */
+  int32_t recentre;    /* MRF_LEARNED: re-centre rounds when the best atom lies on an
+                          interior face of the box (0 = none) */
 } mrf_match_opts;
 
 typedef struct {
@@ -132,8 +144,14 @@ typedef struct {
   int64_t zero_voxels;   /* voxels with ||Z_v|| = 0 */
   int64_t nonfinite;     /* voxels with a NaN/Inf entry (idx = -1 for them) */
   float ms;              /* device time of the call (hipEvents on `stream`) */
-  float score_ms;        /* device time of the candidate-scoring kernel alone */
+  float score_ms;        /* device time of the candidate-scoring kernel alone
+                            (MRF_LEARNED: of the local-search scoring kernels) */
   int32_t splits;        /* atom ranges the scoring kernel used */
+  int64_t fallbacks;     /* MRF_LEARNED: voxels sent to the exhaustive filter */
+  int64_t recentred;     /* MRF_LEARNED: box re-centrings performed */
+  int64_t local_atoms;   /* MRF_LEARNED: atom rows scored by the local search (incl. padding) */
+  float proposal_ms;     /* MRF_LEARNED: device time of the network and cell mapping */
+  float fallback_ms;     /* MRF_LEARNED: device time of the exhaustive fallback */
 } mrf_match_stats;
 
 /* Project n voxels onto cone(D).
@@ -154,6 +172,81 @@ mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t n, const vo
                      int32_t z_layout, int64_t slice_voxels, const int32_t *warm_idx,
                      int32_t *idx, float *pd, float *corr, void *X_out, float *params_out,
                      mrf_match_stats *stats, mrf_stream stream);
+
+/* Local matched filter around given proposals (the search stage of
+ * MRF_LEARNED): for voxel v the candidates are the atoms of the box
+ * prod_p [cells[v][p] - r, cells[v][p] + r] clipped to the grid (the
+ * dictionary must have grid_dims, nparam <= 4); the answer is the exact
+ * matched filter over that box (lowest index on ties), with opts->recentre
+ * re-centring rounds and the exhaustive FP32 filter as fallback below
+ * opts->fallback_corr.  cells: DEVICE int32 [n][nparam] (modified in place
+ * by re-centring); fallback: DEVICE int32 [n] or NULL (1 where the fallback
+ * decided).  Other arguments as mrf_match; opts->net is ignored. */
+mrf_status mrf_match_local(mrf_dict D, const mrf_match_opts *opts, int64_t n, const void *Z,
+                           int32_t z_layout, int64_t slice_voxels, int32_t *cells,
+                           const int32_t *warm_idx, int32_t *idx, float *pd, float *corr,
+                           int32_t *fallback, void *X_out, float *params_out,
+                           mrf_match_stats *stats, mrf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned proposal network                                                   */
+/* ------------------------------------------------------------------------ */
+/* A multilayer perceptron x -> 256 -> 256 -> nout with exact GELU, mapping a
+ * voxel's normalised signature x = Z_v/||Z_v|| (in the dictionary's
+ * contraction layout: interleaved re/im, or the real part for real atoms) to
+ * standardised parameters u_p = (f_p(theta_p) - mean_p)/std_p (f_p = ln for
+ * positive wide-range parameters).  Weights are FP32 on the device, stored
+ * [out][in] in one array: W1[H][I], b1[H], W2[H][H], b2[H], W3[P][H], b3[P].
+ * The network only proposes a grid cell; the local search decides. */
+mrf_status mrf_net_create(int32_t in_dim, int32_t hidden, int32_t nout, uint64_t seed, mrf_net *out);
+mrf_status mrf_net_destroy(mrf_net net);
+/* Number of FP32 parameters (the length of the arrays below). */
+mrf_status mrf_net_size(mrf_net net, int64_t *count);
+/* HOST arrays of `count` floats (must equal mrf_net_size). */
+mrf_status mrf_net_set_params(mrf_net net, const float *host, int64_t count);
+mrf_status mrf_net_get_params(mrf_net net, float *host, int64_t count);
+mrf_status mrf_net_get_grads(mrf_net net, float *host, int64_t count);
+/* Target standardisation (HOST arrays of nout): mean, std (> 0), log_mask. */
+mrf_status mrf_net_set_standardisation(mrf_net net, const float *mean, const float *stdv,
+                                       const int32_t *log_mask);
+mrf_status mrf_net_get_standardisation(mrf_net net, float *mean, float *stdv, int32_t *log_mask);
+/* Y = net(X): X DEVICE [B][in_dim], Y DEVICE [B][nout] (standardised). */
+mrf_status mrf_net_forward(mrf_net net, const float *X, int64_t B, float *Y, mrf_stream stream);
+/* Mean-squared loss against T (DEVICE [B][nout]) and its gradients (kept in
+ * the net; mrf_net_get_grads reads them).  loss (HOST, may be NULL) forces a
+ * stream synchronisation. */
+mrf_status mrf_net_loss_grad(mrf_net net, const float *X, const float *T, int64_t B, double *loss,
+                             mrf_stream stream);
+/* One Adam update (Kingma and Ba) with the stored gradients. */
+mrf_status mrf_net_adam(mrf_net net, float lr, float beta1, float beta2, float eps,
+                        mrf_stream stream);
+/* Noisy training examples generated on the device from the dictionary:
+ * sample s (global index offset + s) takes atom j ~ U{0..d-1}, SNR ~
+ * U(snr_lo, snr_hi) dB and circular complex Gaussian noise, each draw a
+ * counter-based SplitMix64 value keyed by `seed`; X DEVICE [B][K] rows as the
+ * network input, T DEVICE [B][nout] standardised targets (or NULL), atom
+ * DEVICE [B] (or NULL). */
+mrf_status mrf_net_noisy_batch(mrf_net net, mrf_dict D, uint64_t seed, int64_t offset, int64_t B,
+                               float snr_lo, float snr_hi, float *X, float *T, int32_t *atom,
+                               mrf_stream stream);
+typedef struct {
+  int64_t samples;     /* training-set size (noisy atoms), e.g. 2,000,000 */
+  int32_t batch;       /* e.g. 4096 */
+  int32_t epochs;      /* passes over the training set */
+  float lr;            /* Adam learning rate (cosine-decayed to lr_min) */
+  float lr_min;
+  float snr_lo, snr_hi;/* dB */
+  uint64_t seed;
+} mrf_train_opts;
+typedef struct {
+  int32_t steps;
+  double first_loss, last_loss;  /* mean loss over the first / last 16 steps */
+  float ms;
+} mrf_train_stats;
+/* Train on noisy atoms of D (standardisation set from D's parameter table
+ * if not set).  Synchronises `stream`. */
+mrf_status mrf_net_train(mrf_net net, mrf_dict D, const mrf_train_opts *opts,
+                         mrf_train_stats *stats, mrf_stream stream);
 
 /* ------------------------------------------------------------------------ */
 /* Forward model A = P_Omega F (eq. forward, c = 1, S = I)                    */

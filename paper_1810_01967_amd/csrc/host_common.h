@@ -1,0 +1,131 @@
+// Host-side helpers shared by the C-ABI translation units: error reporting,
+// device buffers that grow on demand, and the handle structures.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "mrf_internal.h"
+
+namespace mrf {
+
+std::string &last_error();
+mrf_status fail(mrf_status st, const char *fmt, ...);
+
+#define HIP_TRY(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return ::mrf::fail(MRF_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_CHECK(what)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = hipGetLastError();                                                       \
+    if (e_ != hipSuccess) return ::mrf::fail(MRF_E_HIP, "%s launch failed: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(expr)                    \
+  do {                               \
+    mrf_status st_ = (expr);         \
+    if (st_ != MRF_OK) return st_;   \
+  } while (0)
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  template <class T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+mrf_status grow(DevBuf &b, size_t bytes);
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr, c = nullptr, d = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (c) (void)hipEventDestroy(c);
+    if (d) (void)hipEventDestroy(d);
+  }
+};
+
+// SplitMix64 finaliser (Steele, Lea, Flood 2014), host copy used to derive
+// the counter-generator keys of the training-data stream.
+inline uint64_t mix64_host(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace mrf
+
+struct mrf_dict_s;
+namespace mrf {
+mrf_status check_learned(const mrf_dict_s *D, const mrf_match_opts *o, bool need_net);
+mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
+                            int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
+                            hipEvent_t ev_s0, hipEvent_t ev_s1, int *splits_used);
+mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
+                         int32_t *idx, float *pd, float *corr, float *params_out, int32_t *cells_in,
+                         int32_t *fallback_out, mrf_match_stats *st, hipStream_t s);
+mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
+                      int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
+                      hipEvent_t ev_s0, hipEvent_t ev_s1, int *splits_used, mrf_match_stats *st);
+mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t slice_voxels,
+                       int64_t n, hipStream_t s);
+mrf_status check_opts(const mrf_dict_s *D, const mrf_match_opts *o);
+}  // namespace mrf
+
+struct mrf_dict_s {
+  int device = 0;
+  int d = 0, L = 0, nparam = 0, is_complex = 0, K = 0, Kp = 0, Kq = 0;
+  int64_t d_pad = 0;
+  uint32_t flags = 0;
+  std::vector<int32_t> grid_dims;
+  std::vector<double> params_host;              // d x nparam
+  std::vector<std::vector<double>> axes_host;   // grid axis values (if grid_dims)
+  mrf::DevBuf dhat, inv_norm, params, dbf16, dfp8, fp8_scale;
+  mrf::DevBuf axes, aoff, dims;                 // device copies of the grid axes
+  int64_t bytes = 0;
+  // workspace (grows lazily)
+  mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j;
+  mrf::DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;
+  mrf::DevBuf inv, h1, h2, yout, cells, best_s, best_j, list_a, list_b, list_c, keys, hist, off, cnt, rows;
+  double *host_scal = nullptr;  // pinned readback of reduced scalars
+  ~mrf_dict_s() {
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+};
+
+struct mrf_net_s {
+  int I = 0, H = 0, P = 0;
+  int64_t nw = 0;
+  int64_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
+  mrf::DevBuf w, g, m, v;
+  float mean[8] = {0}, stdv[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+  int logm[8] = {0};
+  bool has_std = false;
+  mrf::DevBuf dstd;   // device: mean[8], std[8], logm[8] (as int)
+  int64_t t = 0;      // Adam step count
+  // per-batch workspace
+  mrf::DevBuf a1, hb1, a2, hb2, y, dy, da, db, X, T, red, scal;
+  double *host_scal = nullptr;
+  ~mrf_net_s() {
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+};

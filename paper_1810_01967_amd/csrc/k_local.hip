@@ -1,0 +1,440 @@
+// Exact local matched filter around proposed grid cells (gfx950).
+//
+// Voxels are grouped by a coarse cell key (counting sort), so a block of 64
+// consecutive voxels has neighbouring proposals.  The block scores its voxels
+// against every atom of the bounding box of their boxes (gathered rows,
+// FP32 MFMA 32x32x2 as in the exhaustive kernel) and keeps, per voxel, the
+// best atom inside that voxel's own box (strict '>' over atoms in increasing
+// index order: the lowest index wins ties).  Companion kernels flag voxels
+// whose best atom sits on an interior box face (re-centring) or whose
+// normalised correlation is below the fallback threshold, compact those
+// lists, and gather / scatter rows for the exhaustive fallback.
+#include <cfloat>
+
+#include "mrf_internal.h"
+
+namespace mrf {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------
+// grouping
+// ---------------------------------------------------------------------------
+__global__ void k_coarse_keys(const int32_t *__restrict__ list, int64_t cnt,
+                              const int32_t *__restrict__ cells, int P, int shift,
+                              GridDims g, int32_t *__restrict__ keys,
+                              unsigned int *__restrict__ hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int v = list[i];
+  int key = 0;
+  for (int p = 0; p < P; ++p) {
+    const int cd = ((g.dims[p] - 1) >> shift) + 1;
+    int c = cells[(int64_t)v * P + p];
+    c = c < 0 ? 0 : (c >= g.dims[p] ? g.dims[p] - 1 : c);
+    key = key * cd + (c >> shift);
+  }
+  keys[i] = key;
+  atomicAdd(&hist[key], 1u);
+}
+
+// exclusive scan of hist[0..nkeys) into off (one block, chunks of 1024)
+__global__ __launch_bounds__(1024) void k_scan(const unsigned int *__restrict__ hist, int nkeys,
+                                               unsigned int *__restrict__ off) {
+  __shared__ unsigned int buf[1024];
+  __shared__ unsigned int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nkeys; base += 1024) {
+    const int i = base + threadIdx.x;
+    const unsigned int x = i < nkeys ? hist[i] : 0u;
+    buf[threadIdx.x] = x;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const unsigned int y = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0u;
+      __syncthreads();
+      buf[threadIdx.x] += y;
+      __syncthreads();
+    }
+    if (i < nkeys) off[i] = carry + buf[threadIdx.x] - x;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+}
+
+__global__ void k_group_scatter(const int32_t *__restrict__ list, const int32_t *__restrict__ keys,
+                                int64_t cnt, unsigned int *__restrict__ cursor,
+                                int32_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const unsigned int pos = atomicAdd(&cursor[keys[i]], 1u);
+  out[pos] = list[i];
+}
+
+int coarse_key_count(const GridDims &g, int P, int shift) {
+  int64_t k = 1;
+  for (int p = 0; p < P; ++p) k *= ((g.dims[p] - 1) >> shift) + 1;
+  return (int)k;
+}
+
+void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P, int shift,
+                  const GridDims &g, int32_t *keys, unsigned int *hist, unsigned int *off,
+                  int32_t *out, hipStream_t s) {
+  if (cnt <= 0) return;
+  const int nkeys = coarse_key_count(g, P, shift);
+  launch_zero(hist, (int64_t)nkeys * 4, s);
+  const unsigned blocks = (unsigned)((cnt + 255) / 256);
+  hipLaunchKernelGGL(k_coarse_keys, dim3(blocks), dim3(256), 0, s, list, cnt, cells, P, shift, g,
+                     keys, hist);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, nkeys, off);
+  hipLaunchKernelGGL(k_group_scatter, dim3(blocks), dim3(256), 0, s, list, keys, cnt, off, out);
+}
+
+// ---------------------------------------------------------------------------
+// local scoring
+// ---------------------------------------------------------------------------
+constexpr int LS_BA = 128, LS_BV = 64, LS_BK = 16, LS_LD = 20;
+
+__device__ __forceinline__ bool lbetter(float s1, int j1, float s0, int j0) {
+  return (s1 > s0) || (s1 == s0 && j1 >= 0 && (j0 < 0 || j1 < j0));
+}
+
+__global__ __launch_bounds__(256, 2) void k_local_score(
+    const float *__restrict__ D, const float *__restrict__ Zp, int Kp,
+    const int32_t *__restrict__ order, int64_t cnt, const int32_t *__restrict__ cells, int P,
+    GridDims g, int r, float *__restrict__ best_s, int32_t *__restrict__ best_j,
+    unsigned long long *__restrict__ work) {
+  __shared__ float As[2][LS_BA][LS_LD];
+  __shared__ float Zs[2][LS_BV][LS_LD];
+  __shared__ int vid[LS_BV];
+  __shared__ int vlo[LS_BV][4], vhi[LS_BV][4];
+  __shared__ int blo[4], bdim[4];
+  __shared__ int acoord[LS_BA][4];
+  __shared__ int aj[LS_BA];
+  __shared__ float red_s[4][LS_BV];
+  __shared__ int red_j[4][LS_BV];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int64_t v0 = (int64_t)blockIdx.x * LS_BV;
+  // voxels and their clipped boxes
+  if (tid < LS_BV) {
+    const int64_t i = v0 + tid;
+    const int v = i < cnt ? order[i] : -1;
+    vid[tid] = v;
+    for (int p = 0; p < 4; ++p) {
+      int lo = 1, hi = 0;  // empty box for padding lanes / unused parameters
+      if (v >= 0 && p < P) {
+        const int c = cells[(int64_t)v * P + p];
+        lo = max(c - r, 0);
+        hi = min(c + r, g.dims[p] - 1);
+      } else if (p >= P) {
+        lo = 0;
+        hi = 0;
+      }
+      vlo[tid][p] = lo;
+      vhi[tid][p] = hi;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int p = 0; p < 4; ++p) {
+      int lo = 1 << 30, hi = -1;
+      for (int c = 0; c < LS_BV; ++c)
+        if (vid[c] >= 0) {
+          lo = min(lo, vlo[c][p]);
+          hi = max(hi, vhi[c][p]);
+        }
+      if (p >= P || hi < lo) { lo = 0; hi = 0; }
+      blo[p] = lo;
+      bdim[p] = hi - lo + 1;
+    }
+  }
+  __syncthreads();
+  int64_t natoms = 1;
+  for (int p = 0; p < P; ++p) natoms *= bdim[p];
+  const int ntiles = (int)((natoms + LS_BA - 1) / LS_BA);
+  const int nkc = Kp / LS_BK;
+  const int nq = ntiles * nkc;
+  if (tid == 0 && work) atomicAdd(work, (unsigned long long)ntiles * LS_BA);
+
+  auto atom_of = [&](int64_t e, int *sub) -> int {
+    if (e >= natoms) return -1;
+    int j = 0;
+    int64_t rem = e;
+    for (int p = P - 1; p >= 0; --p) {
+      const int q = (int)(rem % bdim[p]);
+      rem /= bdim[p];
+      sub[p] = blo[p] + q;
+    }
+    for (int p = 0; p < P; ++p) j = j * g.dims[p] + sub[p];
+    return j;
+  };
+
+  // loader mapping: atom rows lr and lr + 64, voxel row lr; 4 floats at lc
+  const int lr = tid >> 2, lc = (tid & 3) * 4;
+  int ja0 = -1, ja1 = -1;
+  const int myv = vid[lr < LS_BV ? lr : 0];
+  float4 ra0, ra1, rz;
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto gload = [&](int q) {
+    const int t = q / nkc, kc = q - t * nkc;
+    if (kc == 0) {
+      int sub[4];
+      ja0 = atom_of((int64_t)t * LS_BA + lr, sub);
+      ja1 = atom_of((int64_t)t * LS_BA + lr + 64, sub);
+    }
+    const int k = kc * LS_BK + lc;
+    ra0 = ja0 >= 0 ? *reinterpret_cast<const float4 *>(D + (int64_t)ja0 * Kp + k) : zero4;
+    ra1 = ja1 >= 0 ? *reinterpret_cast<const float4 *>(D + (int64_t)ja1 * Kp + k) : zero4;
+    rz = (lr < LS_BV && myv >= 0) ? *reinterpret_cast<const float4 *>(Zp + (int64_t)myv * Kp + k) : zero4;
+  };
+  auto sstore = [&](int buf) {
+    *reinterpret_cast<float4 *>(&As[buf][lr][lc]) = ra0;
+    *reinterpret_cast<float4 *>(&As[buf][lr + 64][lc]) = ra1;
+    if (lr < LS_BV) *reinterpret_cast<float4 *>(&Zs[buf][lr][lc]) = rz;
+  };
+
+  f32x16 acc[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[b][i] = 0.f;
+  float best[2] = {-INFINITY, -INFINITY};
+  int bidx[2] = {-1, -1};
+
+  if (nq > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int q = 0; q < nq; ++q) {
+    const int buf = q & 1;
+    const int t = q / nkc, kc = q - t * nkc;
+    if (kc == 0 && tid < LS_BA) {
+      int sub[4] = {0, 0, 0, 0};
+      aj[tid] = atom_of((int64_t)t * LS_BA + tid, sub);
+      acoord[tid][0] = sub[0];
+      acoord[tid][1] = sub[1];
+      acoord[tid][2] = sub[2];
+      acoord[tid][3] = sub[3];
+    }
+    if (q + 1 < nq) gload(q + 1);
+    float af[8], zf[2][8];
+    {
+      const float *src = &As[buf][wave * 32 + l32][h * 8];
+      const float4 x0 = *reinterpret_cast<const float4 *>(src);
+      const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
+      af[0] = x0.x; af[1] = x0.y; af[2] = x0.z; af[3] = x0.w;
+      af[4] = x1.x; af[5] = x1.y; af[6] = x1.z; af[7] = x1.w;
+    }
+#pragma unroll
+    for (int nv = 0; nv < 2; ++nv) {
+      const float *src = &Zs[buf][nv * 32 + l32][h * 8];
+      const float4 x0 = *reinterpret_cast<const float4 *>(src);
+      const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
+      zf[nv][0] = x0.x; zf[nv][1] = x0.y; zf[nv][2] = x0.z; zf[nv][3] = x0.w;
+      zf[nv][4] = x1.x; zf[nv][5] = x1.y; zf[nv][6] = x1.z; zf[nv][7] = x1.w;
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int nv = 0; nv < 2; ++nv)
+        acc[nv] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s], zf[nv][s], acc[nv], 0, 0, 0);
+    if (kc == nkc - 1) {
+      if (nkc == 1) __syncthreads();  // aj / acoord written this iteration
+#pragma unroll
+      for (int nv = 0; nv < 2; ++nv) {
+        const int c = nv * 32 + l32;
+        int lo[4], hi[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          lo[p] = vlo[c][p];
+          hi[p] = vhi[c][p];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int row = wave * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+          const int j = aj[row];
+          const float sc = acc[nv][i];
+          bool in = j >= 0;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) in = in && acoord[row][p] >= lo[p] && acoord[row][p] <= hi[p];
+          if (in && sc > best[nv]) {
+            best[nv] = sc;
+            bidx[nv] = j;
+          }
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[b][i] = 0.f;
+    }
+    if (q + 1 < nq) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int nv = 0; nv < 2; ++nv) {
+    const float ps = __shfl_xor(best[nv], 32, 64);
+    const int pj = __shfl_xor(bidx[nv], 32, 64);
+    if (lbetter(ps, pj, best[nv], bidx[nv])) {
+      best[nv] = ps;
+      bidx[nv] = pj;
+    }
+    if (h == 0) {
+      red_s[wave][nv * 32 + l32] = best[nv];
+      red_j[wave][nv * 32 + l32] = bidx[nv];
+    }
+  }
+  __syncthreads();
+  if (tid < LS_BV) {
+    float bs = red_s[0][tid];
+    int bj = red_j[0][tid];
+    for (int w = 1; w < 4; ++w)
+      if (lbetter(red_s[w][tid], red_j[w][tid], bs, bj)) {
+        bs = red_s[w][tid];
+        bj = red_j[w][tid];
+      }
+    const int v = vid[tid];
+    if (v >= 0) {
+      best_s[v] = bs;
+      best_j[v] = bj;
+    }
+  }
+}
+
+void launch_local_score(const float *D, const float *Zp, int Kp, const int32_t *order, int64_t cnt,
+                        const int32_t *cells, int P, const GridDims &g, int r, float *best_s,
+                        int32_t *best_j, unsigned long long *work, hipStream_t s) {
+  if (cnt <= 0) return;
+  const unsigned blocks = (unsigned)((cnt + LS_BV - 1) / LS_BV);
+  hipLaunchKernelGGL(k_local_score, dim3(blocks), dim3(256), 0, s, D, Zp, Kp, order, cnt, cells, P, g,
+                     r, best_s, best_j, work);
+}
+
+// ---------------------------------------------------------------------------
+// re-centring and fallback selection
+// ---------------------------------------------------------------------------
+// For listed voxels: if the best atom lies on a box face that is not a grid
+// edge, append the voxel to `recentre` and move its cell to the best atom.
+__global__ void k_face(const int32_t *__restrict__ list, int64_t cnt, const int32_t *__restrict__ best_j,
+                       int32_t *__restrict__ cells, int P, GridDims g, int r,
+                       int32_t *__restrict__ out, unsigned int *__restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int v = list[i];
+  int j = best_j[v];
+  if (j < 0) return;
+  int sub[4];
+  for (int p = P - 1; p >= 0; --p) {
+    sub[p] = j % g.dims[p];
+    j /= g.dims[p];
+  }
+  bool face = false;
+  for (int p = 0; p < P; ++p) {
+    const int c = cells[(int64_t)v * P + p];
+    face = face || (sub[p] == c - r && sub[p] > 0) || (sub[p] == c + r && sub[p] < g.dims[p] - 1);
+  }
+  if (!face) return;
+  for (int p = 0; p < P; ++p) cells[(int64_t)v * P + p] = sub[p];
+  out[atomicAdd(count, 1u)] = v;
+}
+
+void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
+                 const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_face, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, best_j,
+                     cells, P, g, r, out, count);
+}
+
+// Voxels with a finite, non-zero norm whose normalised correlation is below
+// the threshold (or with no candidate) go to the exhaustive fallback list.
+__global__ void k_select_fallback(int64_t n, const float *__restrict__ best_s,
+                                  const int32_t *__restrict__ best_j, const float *__restrict__ znorm,
+                                  float thr, int32_t *__restrict__ out, unsigned int *__restrict__ count) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const float zn = znorm[v];
+  if (!(zn > 0.f)) return;
+  const float corr = best_s[v] / zn;
+  if (best_j[v] < 0 || !(corr >= thr)) out[atomicAdd(count, 1u)] = (int32_t)v;
+}
+
+void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,
+                            float thr, int32_t *out, unsigned int *count, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_select_fallback, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, best_s,
+                     best_j, znorm, thr, out, count);
+}
+
+// rows[i] = Zp[list[i]] (zero rows up to cnt_pad)
+__global__ void k_gather_rows(const float *__restrict__ Zp, int Kp, const int32_t *__restrict__ list,
+                              int64_t cnt, int64_t cnt_pad, float *__restrict__ out) {
+  const int64_t i = blockIdx.x;
+  if (i >= cnt_pad) return;
+  const float4 *src = i < cnt ? reinterpret_cast<const float4 *>(Zp + (int64_t)list[i] * Kp) : nullptr;
+  float4 *dst = reinterpret_cast<float4 *>(out + i * Kp);
+  for (int k = threadIdx.x; k < Kp / 4; k += blockDim.x)
+    dst[k] = src ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cnt, int64_t cnt_pad,
+                        float *out, hipStream_t s) {
+  if (cnt_pad <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)cnt_pad), dim3(256), 0, s, Zp, Kp, list, cnt,
+                     cnt_pad, out);
+}
+
+// best[list[i]] = merged exhaustive result i (splits merged in order)
+__global__ void k_scatter_best(const int32_t *__restrict__ list, int64_t cnt,
+                               const float *__restrict__ part_s, const int *__restrict__ part_j,
+                               int splits, float *__restrict__ best_s, int32_t *__restrict__ best_j) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  float bs = -INFINITY;
+  int bj = -1;
+  for (int s = 0; s < splits; ++s) {
+    const float ps = part_s[(int64_t)s * cnt + i];
+    const int pj = part_j[(int64_t)s * cnt + i];
+    if (pj >= 0 && lbetter(ps, pj, bs, bj)) {
+      bs = ps;
+      bj = pj;
+    }
+  }
+  const int v = list[i];
+  best_s[v] = bs;
+  best_j[v] = bj;
+}
+
+void launch_scatter_best(const int32_t *list, int64_t cnt, const float *part_s, const int *part_j,
+                         int splits, float *best_s, int32_t *best_j, hipStream_t s) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_scatter_best, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt,
+                     part_s, part_j, splits, best_s, best_j);
+}
+
+__global__ void k_iota(int32_t *x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = (int32_t)i;
+}
+
+void launch_iota(int32_t *x, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
+}
+
+}  // namespace mrf
+
+namespace mrf {
+
+__global__ void k_mark(const int32_t *__restrict__ list, int64_t cnt, int32_t *__restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) flags[list[i]] = 1;
+}
+
+void launch_mark(const int32_t *list, int64_t cnt, int32_t *flags, hipStream_t s) {
+  if (cnt > 0) hipLaunchKernelGGL(k_mark, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, flags);
+}
+
+}  // namespace mrf

@@ -12,13 +12,16 @@
 #include <utility>
 #include <vector>
 
-#include "mrf_internal.h"
+#include "host_common.h"
 
 using namespace mrf;
 
-namespace {
+namespace mrf {
 
-thread_local std::string g_err;
+std::string &last_error() {
+  static thread_local std::string e;
+  return e;
+}
 
 mrf_status fail(mrf_status st, const char *fmt, ...) {
   char buf[512];
@@ -26,33 +29,9 @@ mrf_status fail(mrf_status st, const char *fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_err = buf;
+  last_error() = buf;
   return st;
 }
-
-#define HIP_TRY(call)                                                                       \
-  do {                                                                                      \
-    hipError_t e_ = (call);                                                                 \
-    if (e_ != hipSuccess) return fail(MRF_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
-
-#define LAUNCH_CHECK(what)                                                                   \
-  do {                                                                                       \
-    hipError_t e_ = hipGetLastError();                                                       \
-    if (e_ != hipSuccess) return fail(MRF_E_HIP, "%s launch failed: %s", what, hipGetErrorString(e_)); \
-  } while (0)
-
-struct DevBuf {
-  void *p = nullptr;
-  size_t cap = 0;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-  template <class T>
-  T *as() const {
-    return static_cast<T *>(p);
-  }
-};
 
 mrf_status grow(DevBuf &b, size_t bytes) {
   if (bytes <= b.cap) return MRF_OK;
@@ -74,32 +53,9 @@ mrf_status grow(DevBuf &b, size_t bytes) {
   return MRF_OK;
 }
 
-#define TRY(expr)                    \
-  do {                               \
-    mrf_status st_ = (expr);         \
-    if (st_ != MRF_OK) return st_;   \
-  } while (0)
+}  // namespace mrf
 
-}  // namespace
-
-struct mrf_dict_s {
-  int device = 0;
-  int d = 0, L = 0, nparam = 0, is_complex = 0, K = 0, Kp = 0, Kq = 0;
-  int64_t d_pad = 0;
-  uint32_t flags = 0;
-  std::vector<int32_t> grid_dims;
-  DevBuf dhat, inv_norm, params, dbf16, dfp8, fp8_scale;
-  int64_t bytes = 0;
-  // workspace (grows lazily)
-  DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j;
-  DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;
-  double *host_scal = nullptr;  // pinned readback of reduced scalars
-  ~mrf_dict_s() {
-    if (host_scal) (void)hipHostFree(host_scal);
-  }
-};
-
-extern "C" const char *mrf_last_error(void) { return g_err.c_str(); }
+extern "C" const char *mrf_last_error(void) { return last_error().c_str(); }
 extern "C" const char *mrf_version(void) { return "mrf-mi355x 0.1 (gfx950)"; }
 
 // ---------------------------------------------------------------------------
@@ -107,7 +63,7 @@ extern "C" const char *mrf_version(void) { return "mrf-mi355x 0.1 (gfx950)"; }
 // ---------------------------------------------------------------------------
 extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream stream,
                                      mrf_dict *out) {
-  g_err.clear();
+  last_error().clear();
   if (!desc || !out) return fail(MRF_E_INVAL, "mrf_dict_build: null desc or out");
   *out = nullptr;
   const mrf_dict_desc &q = *desc;
@@ -179,6 +135,30 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
   HIP_TRY(hipMemcpy(D->inv_norm.p, inv.data(), inv.size() * sizeof(float), hipMemcpyHostToDevice));
   std::vector<float> pf((size_t)q.d * q.nparam);
   for (size_t i = 0; i < pf.size(); ++i) pf[i] = (float)q.params[i];
+  D->params_host.assign(q.params, q.params + (size_t)q.d * q.nparam);
+  if (q.grid_dims) {
+    // axis p value i: the parameter p of the atom with sub-index i on axis p, 0 elsewhere
+    std::vector<float> ax;
+    std::vector<int32_t> aoff, dims;
+    D->axes_host.resize(q.nparam);
+    for (int p = 0; p < q.nparam; ++p) {
+      int64_t stride = 1;
+      for (int r = p + 1; r < q.nparam; ++r) stride *= q.grid_dims[r];
+      aoff.push_back((int32_t)ax.size());
+      dims.push_back(q.grid_dims[p]);
+      for (int i = 0; i < q.grid_dims[p]; ++i) {
+        const double v = q.params[(size_t)(i * stride) * q.nparam + p];
+        D->axes_host[p].push_back(v);
+        ax.push_back((float)v);
+      }
+    }
+    TRY(grow(D->axes, ax.size() * 4));
+    TRY(grow(D->aoff, aoff.size() * 4));
+    TRY(grow(D->dims, dims.size() * 4));
+    HIP_TRY(hipMemcpy(D->axes.p, ax.data(), ax.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(D->aoff.p, aoff.data(), aoff.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(D->dims.p, dims.data(), dims.size() * 4, hipMemcpyHostToDevice));
+  }
   HIP_TRY(hipMemcpy(D->params.p, pf.data(), pf.size() * sizeof(float), hipMemcpyHostToDevice));
   D->bytes = (int64_t)(D->dhat.cap + D->inv_norm.cap + D->params.cap);
   if (q.flags & MRF_STORE_BF16) {
@@ -203,7 +183,7 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
 }
 
 extern "C" mrf_status mrf_dict_destroy(mrf_dict D) {
-  g_err.clear();
+  last_error().clear();
   if (!D) return MRF_OK;
   (void)hipDeviceSynchronize();
   delete D;
@@ -211,7 +191,7 @@ extern "C" mrf_status mrf_dict_destroy(mrf_dict D) {
 }
 
 extern "C" mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info) {
-  g_err.clear();
+  last_error().clear();
   if (!D || !info) return fail(MRF_E_INVAL, "mrf_dict_query: null argument");
   info->d = D->d;
   info->L = D->L;
@@ -227,7 +207,7 @@ extern "C" mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info) {
 
 extern "C" mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *dst, float *scales,
                                           mrf_stream stream) {
-  g_err.clear();
+  last_error().clear();
   if (!D || !dst) return fail(MRF_E_INVAL, "mrf_dict_copy_atoms: null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (precision == MRF_FP32) {
@@ -252,11 +232,13 @@ extern "C" mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *d
 // ---------------------------------------------------------------------------
 // matched filter
 // ---------------------------------------------------------------------------
-namespace {
+namespace mrf {
 
 mrf_status check_opts(const mrf_dict_s *D, const mrf_match_opts *o) {
   if (!o) return MRF_OK;
-  if (o->method != MRF_EXHAUSTIVE) return fail(MRF_E_UNSUPPORTED, "method %d not supported", o->method);
+  if (o->method != MRF_EXHAUSTIVE && o->method != MRF_LEARNED)
+    return fail(MRF_E_INVAL, "unknown method %d", o->method);
+  if (o->method == MRF_LEARNED) TRY(check_learned(D, o, true));
   if (o->precision < MRF_FP32 || o->precision > MRF_FP8) return fail(MRF_E_INVAL, "bad precision %d", o->precision);
   if (o->topk < 0 || o->topk > 8) return fail(MRF_E_INVAL, "topk %d not in 0..8", o->topk);
   if (o->atom_splits < 0) return fail(MRF_E_INVAL, "atom_splits must be >= 0");
@@ -277,10 +259,9 @@ int auto_splits(const mrf_dict_s *D, int64_t n) {
 }
 
 // Score + merge on already packed voxels (ws zp/znorm filled for n rows).
-mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
-                      int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
-                      hipEvent_t ev_s0 = nullptr, hipEvent_t ev_s1 = nullptr,
-                      int *splits_used = nullptr) {
+mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
+                            int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
+                            hipEvent_t ev_s0, hipEvent_t ev_s1, int *splits_used) {
   const int precision = o ? o->precision : MRF_FP32;
   int splits = (o && o->atom_splits > 0) ? o->atom_splits : auto_splits(D, n);
   const int64_t ntiles = D->d_pad / 128;
@@ -326,23 +307,42 @@ mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
   return MRF_OK;
 }
 
-struct EventPair {
-  hipEvent_t a = nullptr, b = nullptr, c = nullptr, d = nullptr;
-  ~EventPair() {
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-    if (c) (void)hipEventDestroy(c);
-    if (d) (void)hipEventDestroy(d);
-  }
-};
 
-}  // namespace
+mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
+                      int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
+                      hipEvent_t ev_s0, hipEvent_t ev_s1, int *splits_used, mrf_match_stats *st) {
+  if (o && o->method == MRF_LEARNED)
+    return match_learned(D, o, n, warm, idx, pd, corr, params_out, nullptr, nullptr, st, s);
+  return match_exhaustive(D, o, n, warm, idx, pd, corr, params_out, s, ev_s0, ev_s1, splits_used);
+}
+
+mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t slice_voxels,
+                       int64_t n, hipStream_t s) {
+  const int64_t n_pad = round_up(n, kRowPad);
+  TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
+  TRY(grow(D->znorm, (size_t)n_pad * 4));
+  TRY(grow(D->counters, 64));  // [0] zero rows, [1] non-finite rows, [2] local-search work
+  launch_zero(D->counters.p, 16, s);
+  const int real = D->is_complex ? 0 : 1;
+  if (z_layout == MRF_VOXEL_MAJOR)
+    launch_pack_voxel_major(static_cast<const float2 *>(Z), n, n_pad, D->L, real, D->Kp,
+                            D->zp.as<float>(), D->znorm.as<float>(),
+                            D->counters.as<unsigned long long>(), s);
+  else
+    launch_pack_frame_major(static_cast<const float2 *>(Z), nullptr, 0.f, n, n_pad, slice_voxels,
+                            D->L, real, D->Kp, D->zp.as<float>(), D->znorm.as<float>(),
+                            D->counters.as<unsigned long long>(), s);
+  LAUNCH_CHECK("pack");
+  return MRF_OK;
+}
+
+}  // namespace mrf
 
 extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t n, const void *Z,
                                 int32_t z_layout, int64_t slice_voxels, const int32_t *warm_idx,
                                 int32_t *idx, float *pd, float *corr, void *X_out,
                                 float *params_out, mrf_match_stats *stats, mrf_stream stream) {
-  g_err.clear();
+  last_error().clear();
   if (!D) return fail(MRF_E_INVAL, "mrf_match: null dictionary");
   TRY(check_opts(D, opts));
   if (n < 0) return fail(MRF_E_INVAL, "mrf_match: n < 0");
@@ -355,10 +355,6 @@ extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t 
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (stats) std::memset(stats, 0, sizeof *stats);
   if (n == 0) return MRF_OK;
-  const int64_t n_pad = round_up(n, kRowPad);
-  TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
-  TRY(grow(D->znorm, (size_t)n_pad * 4));
-  TRY(grow(D->counters, 2 * sizeof(unsigned long long)));
   EventPair ev;
   if (stats) {
     HIP_TRY(hipEventCreate(&ev.a));
@@ -367,19 +363,10 @@ extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t 
     HIP_TRY(hipEventCreate(&ev.d));
     HIP_TRY(hipEventRecord(ev.a, s));
   }
-  launch_zero(D->counters.p, 16, s);
   const int real = D->is_complex ? 0 : 1;
-  if (z_layout == MRF_VOXEL_MAJOR)
-    launch_pack_voxel_major(static_cast<const float2 *>(Z), n, n_pad, D->L, real, D->Kp,
-                            D->zp.as<float>(), D->znorm.as<float>(),
-                            D->counters.as<unsigned long long>(), s);
-  else
-    launch_pack_frame_major(static_cast<const float2 *>(Z), nullptr, 0.f, n, n_pad, slice_voxels,
-                            D->L, real, D->Kp, D->zp.as<float>(), D->znorm.as<float>(),
-                            D->counters.as<unsigned long long>(), s);
-  LAUNCH_CHECK("pack");
+  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s));
   int splits_used = 0;
-  TRY(match_core(D, opts, n, warm_idx, idx, pd, corr, params_out, s, ev.c, ev.d, &splits_used));
+  TRY(match_core(D, opts, n, warm_idx, idx, pd, corr, params_out, s, ev.c, ev.d, &splits_used, stats));
   if (X_out) {
     launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, real, n, D->L,
                    z_layout == MRF_FRAME_MAJOR, slice_voxels, static_cast<float2 *>(X_out),
@@ -392,7 +379,7 @@ extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t 
     HIP_TRY(hipMemcpyAsync(cnt, D->counters.p, sizeof cnt, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipEventElapsedTime(&stats->ms, ev.a, ev.b));
-    HIP_TRY(hipEventElapsedTime(&stats->score_ms, ev.c, ev.d));
+    if (!opts || opts->method != MRF_LEARNED) HIP_TRY(hipEventElapsedTime(&stats->score_ms, ev.c, ev.d));
     stats->splits = splits_used;
     stats->n = n;
     stats->zero_voxels = (int64_t)cnt[0];
@@ -458,7 +445,7 @@ mrf_dict_s &op_scratch() {
 
 extern "C" mrf_status mrf_op_forward(const mrf_op *A, const void *X, const void *Y, void *R,
                                      double *wnorm2, mrf_stream stream) {
-  g_err.clear();
+  last_error().clear();
   TRY(check_op(A));
   if (!X || !R) return fail(MRF_E_INVAL, "mrf_op_forward: null X or R");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -479,7 +466,7 @@ extern "C" mrf_status mrf_op_forward(const mrf_op *A, const void *X, const void 
 
 extern "C" mrf_status mrf_op_adjoint(const mrf_op *A, const void *R, int32_t apply_dcf, void *G,
                                      mrf_stream stream) {
-  g_err.clear();
+  last_error().clear();
   TRY(check_op(A));
   if (!R || !G) return fail(MRF_E_INVAL, "mrf_op_adjoint: null R or G");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -513,7 +500,7 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
   const int real = D->is_complex ? 0 : 1;
   TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
   TRY(grow(D->znorm, (size_t)n_pad * 4));
-  TRY(grow(D->counters, 16));
+  TRY(grow(D->counters, 64));
   TRY(grow(D->kbuf, (size_t)nimg * npix * 8));
   TRY(grow(D->abuf, (size_t)(A->nsamples > 0 ? A->nsamples : 1) * 8));
   TRY(grow(D->red, (size_t)(8192 + 2 * nimg + 8) * 8));
@@ -523,7 +510,7 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
                           D->zp.as<float>(), D->znorm.as<float>(),
                           D->counters.as<unsigned long long>(), s);
   LAUNCH_CHECK("grad_update_pack");
-  TRY(match_core(D, o, n, warm, idx, pd, nullptr, nullptr, s));
+  TRY(match_core(D, o, n, warm, idx, pd, nullptr, nullptr, s, nullptr, nullptr, nullptr, nullptr));
   double *red = D->red.as<double>();
   int nb = 0;
   launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, real, n, D->L, 1, npix,
@@ -573,7 +560,7 @@ extern "C" mrf_status mrf_ipg_step(mrf_dict D, const mrf_op *A, const void *Y, c
                                    void *X_out, const int32_t *idx_in, int32_t *idx_out,
                                    float *pd, float mu, const mrf_match_opts *opts,
                                    mrf_step_stats *stats, mrf_stream stream) {
-  g_err.clear();
+  last_error().clear();
   TRY(check_step_args(D, A, Y));
   TRY(check_opts(D, opts));
   if (!X_in || !X_out || !idx_out) return fail(MRF_E_INVAL, "mrf_ipg_step: null X_in, X_out or idx_out");
@@ -607,7 +594,7 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
                                     const mrf_solve_opts *o, void *X, int32_t *idx, float *pd,
                                     float *params_out, mrf_solve_stats *stats,
                                     mrf_stream stream) {
-  g_err.clear();
+  last_error().clear();
   TRY(check_step_args(D, A, Y));
   if (!o) return fail(MRF_E_INVAL, "mrf_ipg_solve: null options");
   TRY(check_opts(D, &o->match));
@@ -731,7 +718,7 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
 extern "C" mrf_status mrf_quantize_rows(const float *in, int64_t rows, int32_t K, int64_t in_pitch,
                                         int32_t precision, void *out, int64_t out_pitch,
                                         float *scales, mrf_stream stream) {
-  g_err.clear();
+  last_error().clear();
   if (!in || !out) return fail(MRF_E_INVAL, "mrf_quantize_rows: null in or out");
   if (rows < 0 || K < 1 || in_pitch < K || out_pitch < K) return fail(MRF_E_INVAL, "mrf_quantize_rows: bad sizes");
   if (precision != MRF_BF16 && precision != MRF_FP8) return fail(MRF_E_INVAL, "mrf_quantize_rows: precision must be BF16 or FP8");

@@ -113,3 +113,55 @@ void launch_scale_f32(float *x, int64_t count, float a, hipStream_t s);
 // Per-block FP64 partial sums of |x_i|^2 (at most 1024 blocks) into part.
 void launch_norm2(const float2 *x, int64_t count, double *part, int *nblocks_out, hipStream_t s);
 }  // namespace mrf
+
+namespace mrf {
+// ---------------------------------------------------------------- learned proposal
+enum { GEMM_STORE = 0, GEMM_GELU = 1, GEMM_GELU_GRAD = 2 };
+struct GemmEpi {
+  int kind = GEMM_STORE;
+  const float *bias = nullptr;     // [N], added after the row scale
+  const float *rowscale = nullptr; // [M] multiplier of the accumulated sum
+  float *pre = nullptr;            // GEMM_GELU: pre-activation written here (ld = ldc)
+  const float *gpre = nullptr;     // GEMM_GELU_GRAD: C = acc * gelu'(gpre) (ld = ldc)
+};
+// C[m][n] = epi(sum_k A(m,k) B(n,k)); A(m,k) = A[m*lda+k] if a_kcontig else
+// A[k*lda+m]; B likewise.  Row-major C with leading dimension ldc.
+void launch_gemm(int M, int N, int K, const float *A, int64_t lda, bool a_kcontig, const float *B,
+                 int64_t ldb, bool b_kcontig, float *C, int64_t ldc, const GemmEpi &epi,
+                 hipStream_t s);
+void launch_mse(const float *y, const float *t, int64_t count, float scale, float *dy, double *part,
+                int *nblocks, hipStream_t s);
+void launch_colsum(const float *x, int rows, int cols, float *out, hipStream_t s);
+void launch_adam(float *w, const float *g, float *m, float *v, int64_t count, float lr, float b1,
+                 float b2, float eps, int64_t t, hipStream_t s);
+void launch_inv_norm(const float *znorm, int64_t n, float *inv, hipStream_t s);
+void launch_noisy_batch(const float *Dhat, int Kp, int L, int real_atoms, int d, const float *params,
+                        int nparam, const float *mean, const float *stdv, const int *logm,
+                        uint64_t key_atom, uint64_t key_snr, uint64_t key_noise, int64_t offset,
+                        int64_t B, float snr_lo, float snr_hi, float *X, int ldx, float *T,
+                        int32_t *atom_out, hipStream_t s);
+void launch_cells(const float *Y, int64_t n, int P, const float *mean, const float *stdv,
+                  const int *logm, const float *axes, const int *aoff, const int *dims, int32_t *cells,
+                  hipStream_t s);
+
+// ---------------------------------------------------------------- local search
+struct GridDims {
+  int dims[4];
+};
+int coarse_key_count(const GridDims &g, int P, int shift);
+void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P, int shift,
+                  const GridDims &g, int32_t *keys, unsigned int *hist, unsigned int *off,
+                  int32_t *out, hipStream_t s);
+void launch_local_score(const float *D, const float *Zp, int Kp, const int32_t *order, int64_t cnt,
+                        const int32_t *cells, int P, const GridDims &g, int r, float *best_s,
+                        int32_t *best_j, unsigned long long *work, hipStream_t s);
+void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
+                 const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s);
+void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,
+                            float thr, int32_t *out, unsigned int *count, hipStream_t s);
+void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cnt, int64_t cnt_pad,
+                        float *out, hipStream_t s);
+void launch_scatter_best(const int32_t *list, int64_t cnt, const float *part_s, const int *part_j,
+                         int splits, float *best_s, int32_t *best_j, hipStream_t s);
+void launch_iota(int32_t *x, int64_t n, hipStream_t s);
+}  // namespace mrf

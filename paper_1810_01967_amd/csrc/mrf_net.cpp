@@ -1,0 +1,636 @@
+// Host side of the learned-proposal path: network handles, training on
+// device-generated noisy atoms, and the proposal -> local search ->
+// re-centring -> exhaustive fallback pipeline used by MRF_LEARNED.
+#include "host_common.h"
+
+using namespace mrf;
+
+namespace {
+
+mrf_status check_net(const mrf_net_s *net) {
+  if (!net) return fail(MRF_E_INVAL, "null network");
+  return MRF_OK;
+}
+
+// Counter-generator keys of the training stream (SplitMix64 of the seed
+// combined with a purpose tag 1, 2, 3).
+void train_keys(uint64_t seed, uint64_t *ka, uint64_t *ks, uint64_t *kn) {
+  const uint64_t base = seed * 0xD1B54A32D192ED03ull;
+  *ka = mix64_host(base + 1);
+  *ks = mix64_host(base + 2);
+  *kn = mix64_host(base + 3);
+}
+
+mrf_status upload_std(mrf_net_s *net) {
+  TRY(grow(net->dstd, 24 * 4));
+  float buf[24];
+  for (int p = 0; p < 8; ++p) {
+    buf[p] = net->mean[p];
+    buf[8 + p] = net->stdv[p];
+    int li = net->logm[p];
+    std::memcpy(&buf[16 + p], &li, 4);
+  }
+  HIP_TRY(hipMemcpy(net->dstd.p, buf, sizeof buf, hipMemcpyHostToDevice));
+  return MRF_OK;
+}
+
+const float *dmean(const mrf_net_s *n) { return n->dstd.as<float>(); }
+const float *dstdv(const mrf_net_s *n) { return n->dstd.as<float>() + 8; }
+const int *dlogm(const mrf_net_s *n) { return reinterpret_cast<const int *>(n->dstd.as<float>() + 16); }
+
+// Standardisation from a dictionary's parameter table: ln for parameters
+// that are positive with max/min >= 4, identity otherwise.
+void std_from_dict(mrf_net_s *net, const mrf_dict_s *D) {
+  for (int p = 0; p < net->P; ++p) {
+    double mn = 1e300, mx = -1e300;
+    for (int j = 0; j < D->d; ++j) {
+      const double v = D->params_host[(size_t)j * D->nparam + p];
+      mn = std::min(mn, v);
+      mx = std::max(mx, v);
+    }
+    const int lg = (mn > 0.0 && mx / mn >= 4.0) ? 1 : 0;
+    double s1 = 0.0, s2 = 0.0;
+    for (int j = 0; j < D->d; ++j) {
+      double v = D->params_host[(size_t)j * D->nparam + p];
+      if (lg) v = std::log(v);
+      s1 += v;
+      s2 += v * v;
+    }
+    const double mean = s1 / D->d;
+    double var = s2 / D->d - mean * mean;
+    if (!(var > 0.0)) var = 1.0;
+    net->mean[p] = (float)mean;
+    net->stdv[p] = (float)std::sqrt(var);
+    net->logm[p] = lg;
+  }
+  net->has_std = true;
+}
+
+mrf_status net_ws(mrf_net_s *net, int64_t B, bool train) {
+  TRY(grow(net->hb1, (size_t)B * net->H * 4));
+  TRY(grow(net->hb2, (size_t)B * net->H * 4));
+  if (train) {
+    TRY(grow(net->a1, (size_t)B * net->H * 4));
+    TRY(grow(net->a2, (size_t)B * net->H * 4));
+    TRY(grow(net->y, (size_t)B * net->P * 4));
+    TRY(grow(net->dy, (size_t)B * net->P * 4));
+    TRY(grow(net->da, (size_t)B * net->H * 4));
+    TRY(grow(net->db, (size_t)B * net->H * 4));
+    TRY(grow(net->red, 512 * 8));
+    TRY(grow(net->scal, 64));
+  }
+  return MRF_OK;
+}
+
+// X [B][I] (ld ldx) -> Y [B][P]; rowscale (or null) multiplies each row's
+// first-layer product (the 1/||Z_v|| of the input normalisation).
+mrf_status net_forward_rows(mrf_net_s *net, const float *X, int64_t ldx, int64_t B,
+                            const float *rowscale, float *Y, float *h1, float *h2, hipStream_t s) {
+  const float *w = net->w.as<float>();
+  GemmEpi e1;
+  e1.kind = GEMM_GELU;
+  e1.bias = w + net->ob1;
+  e1.rowscale = rowscale;
+  launch_gemm((int)B, net->H, net->I, X, ldx, true, w + net->oW1, net->I, true, h1, net->H, e1, s);
+  GemmEpi e2;
+  e2.kind = GEMM_GELU;
+  e2.bias = w + net->ob2;
+  launch_gemm((int)B, net->H, net->H, h1, net->H, true, w + net->oW2, net->H, true, h2, net->H, e2, s);
+  GemmEpi e3;
+  e3.bias = w + net->ob3;
+  launch_gemm((int)B, net->P, net->H, h2, net->H, true, w + net->oW3, net->H, true, Y, net->P, e3, s);
+  LAUNCH_CHECK("net forward");
+  return MRF_OK;
+}
+
+// Loss partial sums into net->red[0..nb), gradients into net->g.
+mrf_status net_loss_grad(mrf_net_s *net, const float *X, const float *T, int64_t B, int *nb,
+                         hipStream_t s) {
+  TRY(net_ws(net, B, true));
+  const int H = net->H, P = net->P, I = net->I;
+  const float *w = net->w.as<float>();
+  float *g = net->g.as<float>();
+  GemmEpi e1;
+  e1.kind = GEMM_GELU;
+  e1.bias = w + net->ob1;
+  e1.pre = net->a1.as<float>();
+  launch_gemm((int)B, H, I, X, I, true, w + net->oW1, I, true, net->hb1.as<float>(), H, e1, s);
+  GemmEpi e2;
+  e2.kind = GEMM_GELU;
+  e2.bias = w + net->ob2;
+  e2.pre = net->a2.as<float>();
+  launch_gemm((int)B, H, H, net->hb1.as<float>(), H, true, w + net->oW2, H, true,
+              net->hb2.as<float>(), H, e2, s);
+  GemmEpi e3;
+  e3.bias = w + net->ob3;
+  launch_gemm((int)B, P, H, net->hb2.as<float>(), H, true, w + net->oW3, H, true,
+              net->y.as<float>(), P, e3, s);
+  launch_mse(net->y.as<float>(), T, B * P, (float)(2.0 / ((double)B * P)), net->dy.as<float>(),
+             net->red.as<double>(), nb, s);
+  GemmEpi plain;
+  // dW3[p][h] = sum_b dy[b][p] h2[b][h]
+  launch_gemm(P, H, (int)B, net->dy.as<float>(), P, false, net->hb2.as<float>(), H, false,
+              g + net->oW3, H, plain, s);
+  launch_colsum(net->dy.as<float>(), (int)B, P, g + net->ob3, s);
+  // da2 = (dy W3) * gelu'(a2)
+  GemmEpi gg2;
+  gg2.kind = GEMM_GELU_GRAD;
+  gg2.gpre = net->a2.as<float>();
+  launch_gemm((int)B, H, P, net->dy.as<float>(), P, true, w + net->oW3, H, false,
+              net->da.as<float>(), H, gg2, s);
+  launch_gemm(H, H, (int)B, net->da.as<float>(), H, false, net->hb1.as<float>(), H, false,
+              g + net->oW2, H, plain, s);
+  launch_colsum(net->da.as<float>(), (int)B, H, g + net->ob2, s);
+  // da1 = (da2 W2) * gelu'(a1)
+  GemmEpi gg1;
+  gg1.kind = GEMM_GELU_GRAD;
+  gg1.gpre = net->a1.as<float>();
+  launch_gemm((int)B, H, H, net->da.as<float>(), H, true, w + net->oW2, H, false,
+              net->db.as<float>(), H, gg1, s);
+  launch_gemm(H, I, (int)B, net->db.as<float>(), H, false, X, I, false, g + net->oW1, I, plain, s);
+  launch_colsum(net->db.as<float>(), (int)B, H, g + net->ob1, s);
+  LAUNCH_CHECK("net backward");
+  return MRF_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+extern "C" mrf_status mrf_net_create(int32_t in_dim, int32_t hidden, int32_t nout, uint64_t seed,
+                                     mrf_net *out) {
+  last_error().clear();
+  if (!out) return fail(MRF_E_INVAL, "mrf_net_create: null out");
+  *out = nullptr;
+  if (in_dim < 1 || hidden < 1 || hidden > 4096 || nout < 1 || nout > 8)
+    return fail(MRF_E_INVAL, "mrf_net_create: bad sizes (in %d hidden %d out %d)", in_dim, hidden, nout);
+  auto *net = new mrf_net_s();
+  std::unique_ptr<mrf_net_s> guard(net);
+  net->I = in_dim;
+  net->H = hidden;
+  net->P = nout;
+  net->oW1 = 0;
+  net->ob1 = (int64_t)hidden * in_dim;
+  net->oW2 = net->ob1 + hidden;
+  net->ob2 = net->oW2 + (int64_t)hidden * hidden;
+  net->oW3 = net->ob2 + hidden;
+  net->ob3 = net->oW3 + (int64_t)nout * hidden;
+  net->nw = net->ob3 + nout;
+  TRY(grow(net->w, net->nw * 4));
+  TRY(grow(net->g, net->nw * 4));
+  TRY(grow(net->m, net->nw * 4));
+  TRY(grow(net->v, net->nw * 4));
+  // He-normal weights N(0, 2/fan_in) from a counter-based stream, zero biases
+  std::vector<float> h((size_t)net->nw, 0.f);
+  const uint64_t key = mix64_host(seed * 0xD1B54A32D192ED03ull + 11);
+  auto normal = [&](uint64_t i) {
+    const double u1 = 1.0 - (double)(mix64_host(key + (2 * i + 1) * 0x9E3779B97F4A7C15ull) >> 11) * 0x1.0p-53;
+    const double u2 = (double)(mix64_host(key + (2 * i + 2) * 0x9E3779B97F4A7C15ull) >> 11) * 0x1.0p-53;
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+  };
+  auto fill = [&](int64_t off, int64_t count, int fan) {
+    const double sd = std::sqrt(2.0 / fan);
+    for (int64_t i = 0; i < count; ++i) h[(size_t)(off + i)] = (float)(sd * normal((uint64_t)(off + i)));
+  };
+  fill(net->oW1, (int64_t)hidden * in_dim, in_dim);
+  fill(net->oW2, (int64_t)hidden * hidden, hidden);
+  fill(net->oW3, (int64_t)nout * hidden, hidden);
+  HIP_TRY(hipMemcpy(net->w.p, h.data(), net->nw * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(net->g.p, 0, net->nw * 4));
+  HIP_TRY(hipMemset(net->m.p, 0, net->nw * 4));
+  HIP_TRY(hipMemset(net->v.p, 0, net->nw * 4));
+  HIP_TRY(hipHostMalloc((void **)&net->host_scal, 16 * sizeof(double), hipHostMallocDefault));
+  TRY(upload_std(net));
+  *out = guard.release();
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_net_destroy(mrf_net net) {
+  last_error().clear();
+  if (!net) return MRF_OK;
+  (void)hipDeviceSynchronize();
+  delete net;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_net_size(mrf_net net, int64_t *count) {
+  last_error().clear();
+  TRY(check_net(net));
+  if (!count) return fail(MRF_E_INVAL, "mrf_net_size: null count");
+  *count = net->nw;
+  return MRF_OK;
+}
+
+static mrf_status net_copy(mrf_net net, float *host, const float *src_host, int64_t count, DevBuf &dev,
+                           bool to_dev) {
+  TRY(check_net(net));
+  if (count != net->nw) return fail(MRF_E_INVAL, "parameter count %lld != %lld", (long long)count, (long long)net->nw);
+  if (to_dev) {
+    if (!src_host) return fail(MRF_E_INVAL, "null host array");
+    HIP_TRY(hipMemcpy(dev.p, src_host, count * 4, hipMemcpyHostToDevice));
+  } else {
+    if (!host) return fail(MRF_E_INVAL, "null host array");
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(host, dev.p, count * 4, hipMemcpyDeviceToHost));
+  }
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_net_set_params(mrf_net net, const float *host, int64_t count) {
+  last_error().clear();
+  TRY(net_copy(net, nullptr, host, count, net->w, true));
+  return MRF_OK;
+}
+extern "C" mrf_status mrf_net_get_params(mrf_net net, float *host, int64_t count) {
+  last_error().clear();
+  return net_copy(net, host, nullptr, count, net->w, false);
+}
+extern "C" mrf_status mrf_net_get_grads(mrf_net net, float *host, int64_t count) {
+  last_error().clear();
+  return net_copy(net, host, nullptr, count, net->g, false);
+}
+
+extern "C" mrf_status mrf_net_set_standardisation(mrf_net net, const float *mean, const float *stdv,
+                                                  const int32_t *log_mask) {
+  last_error().clear();
+  TRY(check_net(net));
+  if (!mean || !stdv || !log_mask) return fail(MRF_E_INVAL, "null standardisation array");
+  for (int p = 0; p < net->P; ++p) {
+    if (!(stdv[p] > 0.f) || !std::isfinite(mean[p])) return fail(MRF_E_INVAL, "bad standardisation");
+    net->mean[p] = mean[p];
+    net->stdv[p] = stdv[p];
+    net->logm[p] = log_mask[p] ? 1 : 0;
+  }
+  net->has_std = true;
+  return upload_std(net);
+}
+
+extern "C" mrf_status mrf_net_get_standardisation(mrf_net net, float *mean, float *stdv,
+                                                  int32_t *log_mask) {
+  last_error().clear();
+  TRY(check_net(net));
+  if (!mean || !stdv || !log_mask) return fail(MRF_E_INVAL, "null standardisation array");
+  for (int p = 0; p < net->P; ++p) {
+    mean[p] = net->mean[p];
+    stdv[p] = net->stdv[p];
+    log_mask[p] = net->logm[p];
+  }
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_net_forward(mrf_net net, const float *X, int64_t B, float *Y,
+                                      mrf_stream stream) {
+  last_error().clear();
+  TRY(check_net(net));
+  if (B < 0 || B > (1 << 30)) return fail(MRF_E_INVAL, "mrf_net_forward: bad B");
+  if (B == 0) return MRF_OK;
+  if (!X || !Y) return fail(MRF_E_INVAL, "mrf_net_forward: null X or Y");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TRY(net_ws(net, B, false));
+  return net_forward_rows(net, X, net->I, B, nullptr, Y, net->hb1.as<float>(), net->hb2.as<float>(), s);
+}
+
+extern "C" mrf_status mrf_net_loss_grad(mrf_net net, const float *X, const float *T, int64_t B,
+                                        double *loss, mrf_stream stream) {
+  last_error().clear();
+  TRY(check_net(net));
+  if (B < 1 || B > (1 << 24)) return fail(MRF_E_INVAL, "mrf_net_loss_grad: bad B");
+  if (!X || !T) return fail(MRF_E_INVAL, "mrf_net_loss_grad: null X or T");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int nb = 0;
+  TRY(net_loss_grad(net, X, T, B, &nb, s));
+  if (loss) {
+    launch_reduce_sum(net->red.as<double>(), nb, net->scal.as<double>(), s);
+    LAUNCH_CHECK("reduce");
+    HIP_TRY(hipMemcpyAsync(net->host_scal, net->scal.p, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *loss = net->host_scal[0] / ((double)B * net->P);
+  }
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_net_adam(mrf_net net, float lr, float beta1, float beta2, float eps,
+                                   mrf_stream stream) {
+  last_error().clear();
+  TRY(check_net(net));
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+    return fail(MRF_E_INVAL, "mrf_net_adam: bad hyper-parameters");
+  net->t += 1;
+  launch_adam(net->w.as<float>(), net->g.as<float>(), net->m.as<float>(), net->v.as<float>(), net->nw,
+              lr, beta1, beta2, eps, net->t, static_cast<hipStream_t>(stream));
+  LAUNCH_CHECK("adam");
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_net_noisy_batch(mrf_net net, mrf_dict D, uint64_t seed, int64_t offset,
+                                          int64_t B, float snr_lo, float snr_hi, float *X, float *T,
+                                          int32_t *atom, mrf_stream stream) {
+  last_error().clear();
+  TRY(check_net(net));
+  if (!D) return fail(MRF_E_INVAL, "null dictionary");
+  if (net->I != D->K || net->P != D->nparam)
+    return fail(MRF_E_INVAL, "network sizes (%d in, %d out) do not fit the dictionary (K %d, %d params)",
+                net->I, net->P, D->K, D->nparam);
+  if (B < 0 || offset < 0 || !X) return fail(MRF_E_INVAL, "mrf_net_noisy_batch: bad arguments");
+  if (!(snr_hi >= snr_lo)) return fail(MRF_E_INVAL, "mrf_net_noisy_batch: snr_hi < snr_lo");
+  if (T && !net->has_std) {
+    std_from_dict(net, D);
+    TRY(upload_std(net));
+  }
+  if (B == 0) return MRF_OK;
+  uint64_t ka, ks, kn;
+  train_keys(seed, &ka, &ks, &kn);
+  launch_noisy_batch(D->dhat.as<float>(), D->Kp, D->L, D->is_complex ? 0 : 1, D->d,
+                     D->params.as<float>(), D->nparam, dmean(net), dstdv(net), dlogm(net), ka, ks, kn,
+                     offset, B, snr_lo, snr_hi, X, D->K, T, atom, static_cast<hipStream_t>(stream));
+  LAUNCH_CHECK("noisy_batch");
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_net_train(mrf_net net, mrf_dict D, const mrf_train_opts *o,
+                                    mrf_train_stats *st, mrf_stream stream) {
+  last_error().clear();
+  TRY(check_net(net));
+  if (!D || !o) return fail(MRF_E_INVAL, "mrf_net_train: null argument");
+  if (net->I != D->K || net->P != D->nparam)
+    return fail(MRF_E_INVAL, "network sizes (%d in, %d out) do not fit the dictionary (K %d, %d params)",
+                net->I, net->P, D->K, D->nparam);
+  if (o->samples < 1 || o->batch < 1 || o->batch > (1 << 20) || o->epochs < 1 || !(o->lr > 0.f) ||
+      !(o->lr_min >= 0.f) || !(o->snr_hi >= o->snr_lo))
+    return fail(MRF_E_INVAL, "mrf_net_train: bad options");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!net->has_std) {
+    std_from_dict(net, D);
+    TRY(upload_std(net));
+  }
+  const int64_t B = o->batch;
+  const int64_t per_epoch = std::max<int64_t>(1, o->samples / B);
+  const int64_t total = per_epoch * o->epochs;
+  TRY(grow(net->X, (size_t)B * net->I * 4));
+  TRY(grow(net->T, (size_t)B * net->P * 4));
+  TRY(net_ws(net, B, true));
+  TRY(grow(net->scal, 64 * 8));
+  uint64_t ka, ks, kn;
+  train_keys(o->seed, &ka, &ks, &kn);
+  EventPair ev;
+  HIP_TRY(hipEventCreate(&ev.a));
+  HIP_TRY(hipEventCreate(&ev.b));
+  HIP_TRY(hipEventRecord(ev.a, s));
+  const int window = (int)std::min<int64_t>(16, total);
+  // per-step losses of the first and last `window` steps land in scal[0..32)
+  for (int64_t step = 0; step < total; ++step) {
+    const int64_t off = (step % per_epoch) * B;
+    launch_noisy_batch(D->dhat.as<float>(), D->Kp, D->L, D->is_complex ? 0 : 1, D->d,
+                       D->params.as<float>(), D->nparam, dmean(net), dstdv(net), dlogm(net), ka, ks, kn,
+                       off, B, o->snr_lo, o->snr_hi, net->X.as<float>(), D->K, net->T.as<float>(),
+                       nullptr, s);
+    int nb = 0;
+    TRY(net_loss_grad(net, net->X.as<float>(), net->T.as<float>(), B, &nb, s));
+    if (step < window) launch_reduce_sum(net->red.as<double>(), nb, net->scal.as<double>() + step, s);
+    else if (step >= total - window)
+      launch_reduce_sum(net->red.as<double>(), nb, net->scal.as<double>() + 16 + (step - (total - window)), s);
+    const double frac = (double)step / (double)std::max<int64_t>(1, total - 1);
+    const float lr = (float)(o->lr_min + 0.5 * (o->lr - o->lr_min) * (1.0 + std::cos(M_PI * frac)));
+    net->t += 1;
+    launch_adam(net->w.as<float>(), net->g.as<float>(), net->m.as<float>(), net->v.as<float>(),
+                net->nw, lr, 0.9f, 0.999f, 1e-8f, net->t, s);
+    LAUNCH_CHECK("train step");
+  }
+  HIP_TRY(hipEventRecord(ev.b, s));
+  std::vector<double> l(32, 0.0);
+  HIP_TRY(hipMemcpyAsync(l.data(), net->scal.p, 32 * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (st) {
+    st->steps = (int32_t)total;
+    double a = 0, b = 0;
+    for (int i = 0; i < window; ++i) {
+      a += l[(size_t)i];
+      b += l[(size_t)(16 + i)];
+    }
+    st->first_loss = a / window / ((double)B * net->P);
+    st->last_loss = b / window / ((double)B * net->P);
+    HIP_TRY(hipEventElapsedTime(&st->ms, ev.a, ev.b));
+  }
+  return MRF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned / local matched filter
+// ---------------------------------------------------------------------------
+namespace mrf {
+
+void launch_mark(const int32_t *list, int64_t cnt, int32_t *flags, hipStream_t s);
+
+mrf_status check_learned(const mrf_dict_s *D, const mrf_match_opts *o, bool need_net) {
+  if (D->grid_dims.empty()) return fail(MRF_E_UNSUPPORTED, "local search needs a product-grid dictionary (grid_dims)");
+  if (D->nparam > 4) return fail(MRF_E_UNSUPPORTED, "local search supports at most 4 parameters");
+  if (o->box_radius < 0 || o->box_radius > 64) return fail(MRF_E_INVAL, "box_radius %d not in 0..64", o->box_radius);
+  if (o->recentre < 0 || o->recentre > 16) return fail(MRF_E_INVAL, "recentre %d not in 0..16", o->recentre);
+  if (!std::isfinite(o->fallback_corr)) return fail(MRF_E_INVAL, "non-finite fallback_corr");
+  if (need_net) {
+    if (!o->net) return fail(MRF_E_INVAL, "MRF_LEARNED needs a network");
+    if (o->net->I != D->K || o->net->P != D->nparam)
+      return fail(MRF_E_INVAL, "network sizes (%d in, %d out) do not fit the dictionary (K %d, %d params)",
+                  o->net->I, o->net->P, D->K, D->nparam);
+    if (!o->net->has_std) return fail(MRF_E_INVAL, "network has no target standardisation (train it first)");
+  }
+  return MRF_OK;
+}
+
+mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
+                         int32_t *idx, float *pd, float *corr, float *params_out, int32_t *cells_in,
+                         int32_t *fallback_out, mrf_match_stats *st, hipStream_t s) {
+  const int P = D->nparam;
+  const int r = o->box_radius > 0 ? o->box_radius : 3;
+  const float thr = o->fallback_corr == 0.f ? 0.98f : o->fallback_corr;
+  GridDims g;
+  for (int p = 0; p < 4; ++p) g.dims[p] = p < P ? D->grid_dims[(size_t)p] : 1;
+  EventPair ev;
+  hipEvent_t e_prop0 = nullptr, e_prop1 = nullptr;
+  if (st) {
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    HIP_TRY(hipEventCreate(&ev.c));
+    HIP_TRY(hipEventCreate(&ev.d));
+    HIP_TRY(hipEventCreate(&e_prop0));
+    HIP_TRY(hipEventCreate(&e_prop1));
+  }
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } eg{e_prop0, e_prop1};
+  TRY(grow(D->gamma, (size_t)n * 4));
+  TRY(grow(D->best_s, (size_t)n * 4));
+  TRY(grow(D->best_j, (size_t)n * 4));
+  TRY(grow(D->list_a, (size_t)n * 4));
+  TRY(grow(D->list_b, (size_t)n * 4));
+  TRY(grow(D->list_c, (size_t)n * 4));
+  TRY(grow(D->keys, (size_t)n * 4));
+  TRY(grow(D->cnt, 64));
+  TRY(grow(D->counters, 64));
+  int32_t *cells = cells_in;
+  if (!cells) {
+    TRY(grow(D->cells, (size_t)n * P * 4));
+    cells = D->cells.as<int32_t>();
+    mrf_net_s *net = o->net;
+    TRY(grow(D->inv, (size_t)n * 4));
+    TRY(grow(D->h1, (size_t)n * net->H * 4));
+    TRY(grow(D->h2, (size_t)n * net->H * 4));
+    TRY(grow(D->yout, (size_t)n * P * 4));
+    if (st) HIP_TRY(hipEventRecord(e_prop0, s));
+    launch_inv_norm(D->znorm.as<float>(), n, D->inv.as<float>(), s);
+    TRY(net_forward_rows(net, D->zp.as<float>(), D->Kp, n, D->inv.as<float>(), D->yout.as<float>(),
+                         D->h1.as<float>(), D->h2.as<float>(), s));
+    launch_cells(D->yout.as<float>(), n, P, dmean(net), dstdv(net), dlogm(net), D->axes.as<float>(),
+                 D->aoff.as<int>(), D->dims.as<int>(), cells, s);
+    LAUNCH_CHECK("cells");
+    if (st) HIP_TRY(hipEventRecord(e_prop1, s));
+  }
+  const int shift = 2;
+  const int nkeys = coarse_key_count(g, P, shift);
+  TRY(grow(D->hist, (size_t)nkeys * 4));
+  TRY(grow(D->off, (size_t)nkeys * 4));
+  unsigned long long *work = D->counters.as<unsigned long long>() + 2;
+  launch_zero(work, 8, s);
+  // round 0: every voxel, grouped by coarse proposal cell
+  int32_t *la = D->list_a.as<int32_t>(), *lb = D->list_b.as<int32_t>(), *lc = D->list_c.as<int32_t>();
+  launch_iota(la, n, s);
+  if (st) HIP_TRY(hipEventRecord(ev.a, s));
+  launch_group(la, n, cells, P, shift, g, D->keys.as<int32_t>(), D->hist.as<unsigned int>(),
+               D->off.as<unsigned int>(), lb, s);
+  launch_local_score(D->dhat.as<float>(), D->zp.as<float>(), D->Kp, lb, n, cells, P, g, r,
+                     D->best_s.as<float>(), D->best_j.as<int32_t>(), work, s);
+  LAUNCH_CHECK("local search");
+  int64_t cnt = n;
+  int64_t recentred = 0;
+  // re-centring rounds over the voxels whose best atom sits on an interior
+  // face of their box: the face test writes the list into lc (and moves the
+  // cells), the grouping sorts it into whichever of la / lb was not scored last
+  int32_t *prev = lb;
+  for (int rd = 0; rd < o->recentre && cnt > 0; ++rd) {
+    unsigned int *count = D->cnt.as<unsigned int>();
+    launch_zero(count, 4, s);
+    launch_face(prev, cnt, D->best_j.as<int32_t>(), cells, P, g, r, lc, count, s);
+    unsigned int hc = 0;
+    HIP_TRY(hipMemcpyAsync(&hc, count, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    cnt = hc;
+    recentred += cnt;
+    if (cnt == 0) break;
+    int32_t *sorted = (prev == lb) ? la : lb;
+    launch_group(lc, cnt, cells, P, shift, g, D->keys.as<int32_t>(), D->hist.as<unsigned int>(),
+                 D->off.as<unsigned int>(), sorted, s);
+    launch_local_score(D->dhat.as<float>(), D->zp.as<float>(), D->Kp, sorted, cnt, cells, P, g, r,
+                       D->best_s.as<float>(), D->best_j.as<int32_t>(), work, s);
+    LAUNCH_CHECK("local search (re-centre)");
+    prev = sorted;
+  }
+  if (st) HIP_TRY(hipEventRecord(ev.b, s));
+  // exhaustive fallback below the correlation threshold
+  int64_t nfb = 0;
+  if (fallback_out) launch_zero(fallback_out, n * 4, s);
+  if (st) HIP_TRY(hipEventRecord(ev.c, s));
+  if (thr >= 0.f) {
+    unsigned int *count = D->cnt.as<unsigned int>();
+    launch_zero(count, 4, s);
+    launch_select_fallback(n, D->best_s.as<float>(), D->best_j.as<int32_t>(), D->znorm.as<float>(), thr,
+                           la, count, s);
+    unsigned int hc = 0;
+    HIP_TRY(hipMemcpyAsync(&hc, count, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    nfb = hc;
+    if (nfb > 0) {
+      const int64_t cnt_pad = round_up(nfb, kRowPad);
+      TRY(grow(D->rows, (size_t)cnt_pad * D->Kp * 4));
+      launch_gather_rows(D->zp.as<float>(), D->Kp, la, nfb, cnt_pad, D->rows.as<float>(), s);
+      mrf_match_opts eo{};
+      eo.method = MRF_EXHAUSTIVE;
+      eo.precision = MRF_FP32;
+      int splits = 0;
+      {
+        const int64_t nvt = (nfb + 127) / 128;
+        const int64_t nvt8 = (nvt + 7) / 8 * 8;
+        int64_t sp = (1024 + nvt8 - 1) / nvt8;
+        sp = std::max<int64_t>(1, std::min<int64_t>(sp, std::min<int64_t>(64, D->d_pad / 128)));
+        splits = (int)sp;
+      }
+      TRY(grow(D->part_s, (size_t)splits * nfb * 4));
+      TRY(grow(D->part_j, (size_t)splits * nfb * 4));
+      launch_score_f32(D->dhat.as<float>(), D->rows.as<float>(), D->d, D->d_pad, nfb, cnt_pad, D->Kp,
+                       splits, D->part_s.as<float>(), D->part_j.as<int>(), s);
+      launch_scatter_best(la, nfb, D->part_s.as<float>(), D->part_j.as<int>(), splits,
+                          D->best_s.as<float>(), D->best_j.as<int32_t>(), s);
+      if (fallback_out) launch_mark(la, nfb, fallback_out, s);
+      LAUNCH_CHECK("fallback");
+    }
+  }
+  if (st) HIP_TRY(hipEventRecord(ev.d, s));
+  launch_merge_argmax(D->best_s.as<float>(), D->best_j.as<int>(), 1, n, D->d, D->znorm.as<float>(), warm,
+                      D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr, params_out,
+                      D->gamma.as<float>(), s);
+  LAUNCH_CHECK("merge");
+  if (st) {
+    unsigned long long wk = 0;
+    HIP_TRY(hipMemcpyAsync(&wk, work, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    st->fallbacks = nfb;
+    st->recentred = recentred;
+    st->local_atoms = (int64_t)wk;
+    HIP_TRY(hipEventElapsedTime(&st->score_ms, ev.a, ev.b));
+    HIP_TRY(hipEventElapsedTime(&st->fallback_ms, ev.c, ev.d));
+    if (!cells_in) HIP_TRY(hipEventElapsedTime(&st->proposal_ms, e_prop0, e_prop1));
+  }
+  return MRF_OK;
+}
+
+}  // namespace mrf
+
+extern "C" mrf_status mrf_match_local(mrf_dict D, const mrf_match_opts *opts, int64_t n, const void *Z,
+                                      int32_t z_layout, int64_t slice_voxels, int32_t *cells,
+                                      const int32_t *warm_idx, int32_t *idx, float *pd, float *corr,
+                                      int32_t *fallback, void *X_out, float *params_out,
+                                      mrf_match_stats *stats, mrf_stream stream) {
+  last_error().clear();
+  if (!D || !opts) return fail(MRF_E_INVAL, "mrf_match_local: null dictionary or options");
+  TRY(check_learned(D, opts, false));
+  if (n < 0) return fail(MRF_E_INVAL, "mrf_match_local: n < 0");
+  if (n > 0 && (!Z || !idx || !cells)) return fail(MRF_E_INVAL, "mrf_match_local: null Z, cells or idx");
+  if (z_layout != MRF_VOXEL_MAJOR && z_layout != MRF_FRAME_MAJOR)
+    return fail(MRF_E_INVAL, "mrf_match_local: bad z_layout %d", z_layout);
+  if (z_layout == MRF_FRAME_MAJOR && (slice_voxels < 1 || n % slice_voxels != 0))
+    return fail(MRF_E_INVAL, "mrf_match_local: slice_voxels must divide n");
+  if (n > ((int64_t)1 << 31) - 1024) return fail(MRF_E_INVAL, "mrf_match_local: n too large");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (n == 0) return MRF_OK;
+  EventPair ev;
+  if (stats) {
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    HIP_TRY(hipEventRecord(ev.a, s));
+  }
+  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s));
+  TRY(match_learned(D, opts, n, warm_idx, idx, pd, corr, params_out, cells, fallback, stats, s));
+  if (X_out) {
+    launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, D->is_complex ? 0 : 1, n, D->L,
+                   z_layout == MRF_FRAME_MAJOR, slice_voxels, static_cast<float2 *>(X_out), nullptr,
+                   nullptr, nullptr, nullptr, s);
+    LAUNCH_CHECK("write_x");
+  }
+  if (stats) {
+    HIP_TRY(hipEventRecord(ev.b, s));
+    unsigned long long cnt[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(cnt, D->counters.p, sizeof cnt, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipEventElapsedTime(&stats->ms, ev.a, ev.b));
+    stats->n = n;
+    stats->zero_voxels = (int64_t)cnt[0];
+    stats->nonfinite = (int64_t)cnt[1];
+    if (cnt[1] > 0) return fail(MRF_E_NUMERIC, "mrf_match_local: %llu voxel(s) with non-finite entries", cnt[1]);
+  }
+  return MRF_OK;
+}

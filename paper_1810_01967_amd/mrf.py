@@ -19,14 +19,17 @@ MRF_OK = 0
 MRF_E_INVAL, MRF_E_NOMEM, MRF_E_HIP, MRF_E_UNSUPPORTED, MRF_E_NUMERIC, MRF_E_NOCONV = -1, -2, -3, -4, -5, -6
 MRF_STORE_BF16, MRF_STORE_FP8 = 2, 4
 MRF_F64, MRF_F32 = 0, 1
-MRF_EXHAUSTIVE = 0
+MRF_EXHAUSTIVE, MRF_LEARNED = 0, 1
 MRF_FP32, MRF_BF16, MRF_FP8 = 0, 1, 2
 MRF_VOXEL_MAJOR, MRF_FRAME_MAJOR = 0, 1
 PRECISION = {"fp32": MRF_FP32, "bf16": MRF_BF16, "fp8": MRF_FP8}
 
 EXPORTS = ["mrf_last_error", "mrf_version", "mrf_dict_build", "mrf_dict_destroy", "mrf_dict_query",
-           "mrf_dict_copy_atoms", "mrf_match", "mrf_op_forward", "mrf_op_adjoint", "mrf_ipg_step",
-           "mrf_ipg_solve", "mrf_quantize_rows"]
+           "mrf_dict_copy_atoms", "mrf_match", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
+           "mrf_net_size", "mrf_net_set_params", "mrf_net_get_params", "mrf_net_get_grads",
+           "mrf_net_set_standardisation", "mrf_net_get_standardisation", "mrf_net_forward",
+           "mrf_net_loss_grad", "mrf_net_adam", "mrf_net_noisy_batch", "mrf_net_train",
+           "mrf_op_forward", "mrf_op_adjoint", "mrf_ipg_step", "mrf_ipg_solve", "mrf_quantize_rows"]
 
 
 class MrfError(RuntimeError):
@@ -53,13 +56,29 @@ class DictInfo(ctypes.Structure):
 
 class MatchOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("topk", ctypes.c_int32), ("atom_splits", ctypes.c_int32)]
+                ("topk", ctypes.c_int32), ("atom_splits", ctypes.c_int32),
+                ("net", ctypes.c_void_p), ("box_radius", ctypes.c_int32),
+                ("fallback_corr", ctypes.c_float), ("recentre", ctypes.c_int32)]
 
 
 class MatchStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("zero_voxels", ctypes.c_int64),
                 ("nonfinite", ctypes.c_int64), ("ms", ctypes.c_float),
-                ("score_ms", ctypes.c_float), ("splits", ctypes.c_int32)]
+                ("score_ms", ctypes.c_float), ("splits", ctypes.c_int32),
+                ("fallbacks", ctypes.c_int64), ("recentred", ctypes.c_int64),
+                ("local_atoms", ctypes.c_int64), ("proposal_ms", ctypes.c_float),
+                ("fallback_ms", ctypes.c_float)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int64), ("batch", ctypes.c_int32), ("epochs", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("lr_min", ctypes.c_float), ("snr_lo", ctypes.c_float),
+                ("snr_hi", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class TrainStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("first_loss", ctypes.c_double),
+                ("last_loss", ctypes.c_double), ("ms", ctypes.c_float)]
 
 
 class Op(ctypes.Structure):
@@ -110,6 +129,27 @@ def lib():
                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.POINTER(MatchStats), ctypes.c_void_p]
+        L.mrf_match_local.argtypes = [ctypes.c_void_p, ctypes.POINTER(MatchOpts), ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(MatchStats), ctypes.c_void_p]
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        L.mrf_net_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+        L.mrf_net_destroy.argtypes = [vp]
+        L.mrf_net_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.mrf_net_set_params.argtypes = [vp, vp, i64]
+        L.mrf_net_get_params.argtypes = [vp, vp, i64]
+        L.mrf_net_get_grads.argtypes = [vp, vp, i64]
+        L.mrf_net_set_standardisation.argtypes = [vp, vp, vp, vp]
+        L.mrf_net_get_standardisation.argtypes = [vp, vp, vp, vp]
+        L.mrf_net_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.mrf_net_loss_grad.argtypes = [vp, vp, vp, i64, ctypes.POINTER(ctypes.c_double), vp]
+        L.mrf_net_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
+        L.mrf_net_noisy_batch.argtypes = [vp, vp, ctypes.c_uint64, i64, i64, ctypes.c_float,
+                                          ctypes.c_float, vp, vp, vp, vp]
+        L.mrf_net_train.argtypes = [vp, vp, ctypes.POINTER(TrainOpts), ctypes.POINTER(TrainStats), vp]
         L.mrf_op_forward.argtypes = [ctypes.POINTER(Op), ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
         L.mrf_op_adjoint.argtypes = [ctypes.POINTER(Op), ctypes.c_void_p, ctypes.c_int32,
@@ -223,14 +263,19 @@ def mrf_dict_copy_atoms(D: Dictionary, precision="fp32", stream=None):
     return (out, scales) if p == MRF_FP8 else out
 
 
-def match_opts(precision="fp32", topk=8, atom_splits=0) -> MatchOpts:
-    return MatchOpts(MRF_EXHAUSTIVE, PRECISION[precision], int(topk), int(atom_splits))
+def match_opts(precision="fp32", topk=8, atom_splits=0, net=None, box_radius=3, fallback_corr=0.98,
+               recentre=0) -> MatchOpts:
+    method = MRF_LEARNED if net is not None else MRF_EXHAUSTIVE
+    return MatchOpts(method, PRECISION[precision], int(topk), int(atom_splits),
+                     None if net is None else net.handle, int(box_radius), float(fallback_corr),
+                     int(recentre))
 
 
 # --------------------------------------------------------------------------- matched filter
 def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp32", topk=8,
               atom_splits=0, warm_idx=None, want_pd=True, want_corr=True, want_X=False,
-              want_params=False, stats=False, out=None, stream=None):
+              want_params=False, stats=False, out=None, stream=None, net=None, box_radius=3,
+              fallback_corr=0.98, recentre=0):
     """Matched filter of the voxels in Z (complex64 CUDA tensor, [n][L] for
     layout 'voxel', [S][L][...] for 'frame').  Returns a dict of CUDA tensors
     (idx, pd, corr, X, params) and, with stats=True, a MatchStats."""
@@ -254,7 +299,7 @@ def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp
         o["X"] = torch.empty_like(Z)
     if want_params and "params" not in o:
         o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
-    opts = match_opts(precision, topk, atom_splits)
+    opts = match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre)
     st = MatchStats() if stats else None
     status = lib().mrf_match(D.handle, ctypes.byref(opts), n, _dev(Z), zl, sv, _dev(warm_idx),
                              _dev(o["idx"]), _dev(o.get("pd")), _dev(o.get("corr")),
@@ -264,6 +309,141 @@ def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp
     if stats:
         o["stats"] = st
     return o
+
+
+def mrf_match_local(D: Dictionary, Z, cells, layout="voxel", slice_voxels=None, box_radius=3,
+                    fallback_corr=0.98, recentre=0, warm_idx=None, want_X=False, want_params=False,
+                    stats=False, stream=None):
+    """Local matched filter around given proposal cells (int32 CUDA tensor
+    [n][nparam], modified in place by re-centring)."""
+    torch = _torch()
+    if layout == "voxel":
+        n, zl, sv = Z.shape[0], MRF_VOXEL_MAJOR, 0
+    else:
+        sv = int(slice_voxels) if slice_voxels is not None else int(np.prod(Z.shape[2:]))
+        n, zl = int(Z.numel() // D.L), MRF_FRAME_MAJOR
+    dev = Z.device
+    o = {"idx": torch.empty(n, dtype=torch.int32, device=dev),
+         "pd": torch.empty(n, dtype=torch.float32, device=dev),
+         "corr": torch.empty(n, dtype=torch.float32, device=dev),
+         "fallback": torch.empty(n, dtype=torch.int32, device=dev)}
+    if want_X:
+        o["X"] = torch.empty_like(Z)
+    if want_params:
+        o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
+    opts = match_opts("fp32", 8, 0, None, box_radius, fallback_corr, recentre)
+    st = MatchStats() if stats else None
+    _check(lib().mrf_match_local(D.handle, ctypes.byref(opts), n, _dev(Z), zl, sv, _dev(cells),
+                                 _dev(warm_idx), _dev(o["idx"]), _dev(o["pd"]), _dev(o["corr"]),
+                                 _dev(o["fallback"]), _dev(o.get("X")), _dev(o.get("params")),
+                                 ctypes.byref(st) if st is not None else None, _stream(stream)))
+    if stats:
+        o["stats"] = st
+    return o
+
+
+# --------------------------------------------------------------------------- network
+class Net:
+    """Handle of a learned proposal network (mrf_net_create / mrf_net_destroy)."""
+
+    def __init__(self, in_dim, nout, hidden=256, seed=0):
+        h = ctypes.c_void_p()
+        _check(lib().mrf_net_create(int(in_dim), int(hidden), int(nout), int(seed), ctypes.byref(h)))
+        self.handle = h
+        self.in_dim, self.hidden, self.nout = int(in_dim), int(hidden), int(nout)
+        c = ctypes.c_int64()
+        _check(lib().mrf_net_size(h, ctypes.byref(c)))
+        self.size = c.value
+
+    def offsets(self):
+        I, H, P = self.in_dim, self.hidden, self.nout
+        o = {"W1": (0, (H, I))}
+        o["b1"] = (H * I, (H,))
+        o["W2"] = (H * I + H, (H, H))
+        o["b2"] = (H * I + H + H * H, (H,))
+        o["W3"] = (H * I + 2 * H + H * H, (P, H))
+        o["b3"] = (H * I + 2 * H + H * H + P * H, (P,))
+        return o
+
+    def get_params(self):
+        a = np.empty(self.size, dtype=np.float32)
+        _check(lib().mrf_net_get_params(self.handle, a.ctypes.data, self.size))
+        return a
+
+    def set_params(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        _check(lib().mrf_net_set_params(self.handle, a.ctypes.data, a.size))
+
+    def get_grads(self):
+        a = np.empty(self.size, dtype=np.float32)
+        _check(lib().mrf_net_get_grads(self.handle, a.ctypes.data, self.size))
+        return a
+
+    def unpack(self, flat):
+        return {k: np.asarray(flat[o:o + int(np.prod(sh))]).reshape(sh) for k, (o, sh) in self.offsets().items()}
+
+    def set_standardisation(self, mean, std, log_mask):
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(std, dtype=np.float32)
+        lm = np.ascontiguousarray(log_mask, dtype=np.int32)
+        _check(lib().mrf_net_set_standardisation(self.handle, m.ctypes.data, s.ctypes.data, lm.ctypes.data))
+
+    def get_standardisation(self):
+        m = np.empty(self.nout, np.float32)
+        s = np.empty(self.nout, np.float32)
+        lm = np.empty(self.nout, np.int32)
+        _check(lib().mrf_net_get_standardisation(self.handle, m.ctypes.data, s.ctypes.data, lm.ctypes.data))
+        return m, s, lm
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().mrf_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mrf_net_forward(net: Net, X, stream=None):
+    torch = _torch()
+    Y = torch.empty((X.shape[0], net.nout), dtype=torch.float32, device="cuda")
+    _check(lib().mrf_net_forward(net.handle, _dev(X), X.shape[0], _dev(Y), _stream(stream)))
+    return Y
+
+
+def mrf_net_loss_grad(net: Net, X, T, stream=None):
+    loss = ctypes.c_double()
+    _check(lib().mrf_net_loss_grad(net.handle, _dev(X), _dev(T), X.shape[0], ctypes.byref(loss),
+                                   _stream(stream)))
+    return loss.value
+
+
+def mrf_net_adam(net: Net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().mrf_net_adam(net.handle, lr, beta1, beta2, eps, _stream(stream)))
+
+
+def mrf_net_noisy_batch(net: Net, D: Dictionary, seed, offset, B, snr_lo=15.0, snr_hi=40.0,
+                        stream=None):
+    torch = _torch()
+    K = D.info().K
+    X = torch.empty((B, K), dtype=torch.float32, device="cuda")
+    T = torch.empty((B, net.nout), dtype=torch.float32, device="cuda")
+    A = torch.empty(B, dtype=torch.int32, device="cuda")
+    _check(lib().mrf_net_noisy_batch(net.handle, D.handle, int(seed), int(offset), int(B), snr_lo,
+                                     snr_hi, _dev(X), _dev(T), _dev(A), _stream(stream)))
+    return X, T, A
+
+
+def mrf_net_train(net: Net, D: Dictionary, samples=2_000_000, batch=4096, epochs=4, lr=1e-3,
+                  lr_min=1e-5, snr_lo=15.0, snr_hi=40.0, seed=1, stream=None):
+    o = TrainOpts(int(samples), int(batch), int(epochs), float(lr), float(lr_min), float(snr_lo),
+                  float(snr_hi), int(seed))
+    st = TrainStats()
+    _check(lib().mrf_net_train(net.handle, D.handle, ctypes.byref(o), ctypes.byref(st), _stream(stream)))
+    return dict(steps=st.steps, first_loss=st.first_loss, last_loss=st.last_loss, ms=st.ms)
 
 
 # --------------------------------------------------------------------------- operator

@@ -46,7 +46,8 @@ def test_struct_layout_matches_header(m, tmp_path):
     structs = {"mrf_dict_desc": m.mrf.DictDesc, "mrf_dict_info": m.mrf.DictInfo,
                "mrf_match_opts": m.mrf.MatchOpts, "mrf_match_stats": m.mrf.MatchStats,
                "mrf_op": m.mrf.Op, "mrf_step_stats": m.mrf.StepStats,
-               "mrf_solve_opts": m.mrf.SolveOpts, "mrf_solve_stats": m.mrf.SolveStats}
+               "mrf_solve_opts": m.mrf.SolveOpts, "mrf_solve_stats": m.mrf.SolveStats,
+               "mrf_train_opts": m.mrf.TrainOpts, "mrf_train_stats": m.mrf.TrainStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -1,0 +1,189 @@
+"""GPU parity of the learned-proposal path: the on-device training-data
+generator against its counter-based definition, the network's forward pass,
+gradients and Adam step against the FP64 oracle on the same weights and
+batch, the local search + fallback against the oracle on the same proposal
+cells, and what a trained network gains over proposals without it."""
+import numpy as np
+import pytest
+
+from gpu_helpers import banner, c64, dev, host
+from oracle import local, mf, mlp
+from synth import grids, rng, workloads
+
+pytestmark = pytest.mark.gpu
+
+MASK = (1 << 64) - 1
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1810_01967_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def small_dict():
+    return workloads.bssfp_dictionary(L=60, n_t1=20, n_t2=20, n_df=9, seed=2)
+
+
+def _u01(key, i):
+    with np.errstate(over="ignore"):
+        z = rng.mix64(np.uint64(key) + (np.asarray(i, dtype=np.uint64) + np.uint64(1)) * rng.GOLDEN)
+    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
+def _ref_batch(seed, offset, B, Dhat_rows, L, real, params32, mean, std, logm, lo, hi):
+    """The training generator written from its definition (SplitMix64 counter
+    draws keyed by mix64(seed*0xD1B54A32D192ED03 + tag), Box-Muller)."""
+    base = (int(seed) * 0xD1B54A32D192ED03) & MASK
+    ka, ks, kn = (int(rng.mix64(np.array([(base + t) & MASK], dtype=np.uint64))[0]) for t in (1, 2, 3))
+    gs = offset + np.arange(B, dtype=np.int64)
+    d = Dhat_rows.shape[0]
+    j = np.minimum((_u01(ka, gs) * d).astype(np.int64), d - 1)
+    snr = lo + (hi - lo) * _u01(ks, gs)
+    sig = np.sqrt(10.0 ** (-snr / 10.0) / L * 0.5)
+    c = gs[:, None] * L + np.arange(L)[None, :]
+    v1 = 1.0 - _u01(kn, 2 * c)
+    v2 = _u01(kn, 2 * c + 1)
+    rr = np.sqrt(-2.0 * np.log(v1))
+    nre = sig[:, None] * rr * np.cos(2 * np.pi * v2)
+    nim = sig[:, None] * rr * np.sin(2 * np.pi * v2)
+    a = Dhat_rows[j].astype(np.float64)
+    if real:
+        xr, xi = a + nre, nim
+        X = xr
+    else:
+        xr, xi = a[:, 0::2] + nre, a[:, 1::2] + nim
+        X = np.empty((B, 2 * L))
+        X[:, 0::2], X[:, 1::2] = xr, xi
+    X = X / np.sqrt(np.sum(xr ** 2 + xi ** 2, axis=1))[:, None]
+    th = params32[j].astype(np.float64)
+    th = np.where(np.asarray(logm)[None, :] > 0, np.log(th), th)
+    T = (th - mean[None, :]) / std[None, :]
+    return X, T, j
+
+
+@pytest.mark.parametrize("kind", ["bssfp", "fisp"])
+def test_noisy_batch_matches_definition(m, small_dict, kind):
+    banner(f"noisy training batch generator {kind}")
+    Dd = small_dict if kind == "bssfp" else workloads.fisp_dictionary(L=100, n_t1=20, n_t2=25)
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    K = D.info().K
+    net = m.Net(K, Dd.params.shape[1], hidden=32, seed=1)
+    X, T, A = m.mrf_net_noisy_batch(net, D, seed=77, offset=1000, B=300, snr_lo=15.0, snr_hi=40.0)
+    mean, std, logm = net.get_standardisation()
+    Dhat = host(m.mrf_dict_copy_atoms(D, "fp32"))
+    Xr, Tr, jr = _ref_batch(77, 1000, 300, Dhat, Dd.L, not Dd.is_complex, Dd.params.astype(np.float32),
+                            mean.astype(np.float64), std.astype(np.float64), logm, 15.0, 40.0)
+    np.testing.assert_array_equal(host(A), jr)
+    np.testing.assert_allclose(host(X), Xr, rtol=2e-5, atol=2e-6)
+    np.testing.assert_allclose(host(T), Tr, rtol=1e-5, atol=1e-5)
+
+
+def _random_params(net, seed, scale=1.0):
+    prm = {}
+    for k, (o, sh) in net.offsets().items():
+        fan = sh[1] if len(sh) == 2 else 1
+        s = scale * np.sqrt(2.0 / fan) if len(sh) == 2 else 0.1
+        prm[k] = rng.normal(seed, k, int(np.prod(sh))).reshape(sh) * s
+    flat = np.zeros(net.size, dtype=np.float32)
+    for k, (o, sh) in net.offsets().items():
+        flat[o:o + int(np.prod(sh))] = prm[k].reshape(-1).astype(np.float32)
+    return flat
+
+
+@pytest.mark.parametrize("I,H,P,B", [(120, 256, 3, 777), (200, 64, 4, 130)])
+def test_net_forward_gradients_adam_vs_oracle(m, I, H, P, B):
+    banner(f"network forward / gradients / Adam I={I} H={H} P={P} B={B}")
+    net = m.Net(I, P, hidden=H, seed=3)
+    flat = _random_params(net, 5)
+    net.set_params(flat)
+    prm = {k: v.astype(np.float64) for k, v in net.unpack(flat).items()}
+    X = rng.normal(6, "x", B * I).reshape(B, I).astype(np.float32) / np.sqrt(I)
+    T = rng.normal(6, "t", B * P).reshape(B, P).astype(np.float32)
+    Y = host(m.mrf_net_forward(net, dev(X)))
+    Yr, _ = mlp.forward(prm, X.astype(np.float64))
+    np.testing.assert_allclose(Y, Yr, rtol=1e-4, atol=1e-5)
+    loss = m.mrf_net_loss_grad(net, dev(X), dev(T))
+    lr_, gr = mlp.loss_and_grads(prm, X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - lr_) < 1e-5 * lr_
+    g = net.unpack(net.get_grads())
+    for k in mlp.NAMES:
+        ref = gr[k]
+        err = np.linalg.norm(g[k] - ref) / max(np.linalg.norm(ref), 1e-30)
+        assert err < 2e-4, (k, err)
+    # one Adam step from zero moments on the device's gradients
+    m.mrf_net_adam(net, lr=1e-3)
+    new = net.unpack(net.get_params())
+    st = {"m": {k: np.zeros_like(prm[k]) for k in mlp.NAMES}, "v": {k: np.zeros_like(prm[k]) for k in mlp.NAMES}}
+    ref_new = mlp.adam_step(prm, {k: g[k].astype(np.float64) for k in mlp.NAMES}, st, 1, lr=1e-3)
+    for k in mlp.NAMES:
+        np.testing.assert_allclose(new[k], ref_new[k], rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("recentre", [0, 2])
+def test_local_search_vs_oracle(m, small_dict, recentre):
+    """Proposal cells from the test (the generating atom's cell moved by up to
+    +-4 per parameter): the GPU local search, re-centring and fallback
+    against the oracle on the same cells."""
+    banner(f"local search vs oracle recentre={recentre}")
+    Dd = small_dict
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    n = 1500
+    Z, j, pd, snr = workloads.random_voxels(Dd, n, seed=8, snr_db_range=(5.0, 40.0))
+    Z = c64(Z)
+    sub = grids.grid_sub(j, Dd.grid_dims)
+    shift = np.stack([rng.randint(8, f"sh{p}", n, 9) - 4 for p in range(3)], axis=1)
+    cells = np.clip(sub + shift, 0, np.array(Dd.grid_dims) - 1).astype(np.int32)
+    Z[5] = 0.0  # a zero voxel
+    out = m.mrf_match_local(D, dev(Z), dev(cells), box_radius=3, fallback_corr=0.98,
+                            recentre=recentre, stats=True)
+    ref = local.local_match(Z.astype(np.complex128), Dd.atoms, Dd.grid_dims, cells, r=3,
+                            threshold=0.98, recentre=recentre)
+    gidx = host(out["idx"]).astype(np.int64)
+    fb = host(out["fallback"]).astype(bool)
+    nz = np.ones(n, bool)
+    nz[5] = False
+    diff = (gidx != ref["idx"]) & nz
+    print(f"recentre={recentre}: fallbacks gpu {fb.sum()} oracle {ref['fallback'][nz].sum()}, "
+          f"index differences {diff.sum()}, recentred {out['stats'].recentred}")
+    # differences may only come from FP32-vs-FP64 near-ties (inside a box or
+    # at the fallback threshold)
+    assert diff.sum() <= max(2, n // 500)
+    np.testing.assert_array_equal(fb[nz] & ~diff[nz], ref["fallback"][nz] & ~diff[nz])
+    assert gidx[5] == 0 and host(out["pd"])[5] == 0.0
+
+
+def test_trained_network_gain(m, small_dict):
+    """Train on noisy atoms, then the learned path against the exhaustive
+    oracle, and against the same local search fed with a proposal that
+    ignores the voxel (the grid centre): the network's gain is a far lower
+    fallback rate at the same accuracy."""
+    banner("train network + learned match vs exhaustive")
+    Dd = small_dict
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    K = D.info().K
+    net = m.Net(K, 3, hidden=256, seed=11)
+    tr = m.mrf_net_train(net, D, samples=262144, batch=4096, epochs=3, lr=1e-3, lr_min=1e-5,
+                         snr_lo=15.0, snr_hi=40.0, seed=12)
+    print(f"training: {tr}")
+    assert tr["last_loss"] < 0.1 * tr["first_loss"]
+    n = 4000
+    Z, j, pd, snr = workloads.random_voxels(Dd, n, seed=9, snr_db_range=(20.0, 40.0))
+    Z = c64(Z)
+    out = m.mrf_match(D, dev(Z), net=net, box_radius=3, fallback_corr=0.98, recentre=2, stats=True)
+    gidx = host(out["idx"]).astype(np.int64)
+    ex = mf.exact_mf(Z.astype(np.complex128), Dd.atoms)
+    ok = mf.index_ok(Z.astype(np.complex128), Dd.atoms, gidx, tol=1e-6)
+    mism = 1.0 - np.mean(ok)
+    st = out["stats"]
+    centre = np.tile((np.array(Dd.grid_dims) // 2).astype(np.int32), (n, 1))
+    base = m.mrf_match_local(D, dev(Z), dev(centre), box_radius=3, fallback_corr=0.98, recentre=0,
+                             stats=True)
+    print(f"learned: mismatch {mism:.5f}, fallbacks {st.fallbacks}, recentred {st.recentred}; "
+          f"centre proposal: fallbacks {base['stats'].fallbacks}")
+    assert mism <= 0.005
+    assert st.fallbacks < 0.1 * base["stats"].fallbacks
