@@ -179,14 +179,16 @@ def _torch():
     return torch
 
 
-def _dev(t):
-    """Device pointer of a CUDA tensor (None -> NULL)."""
+def _dev(t, dtype=None):
+    """Device pointer of a CUDA tensor (None -> NULL), checking its dtype."""
     if t is None:
         return None
     if not t.is_cuda:
         raise ValueError("expected a device tensor")
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
     return t.data_ptr()
 
 
@@ -301,7 +303,8 @@ def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp
         o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
     opts = match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre)
     st = MatchStats() if stats else None
-    status = lib().mrf_match(D.handle, ctypes.byref(opts), n, _dev(Z), zl, sv, _dev(warm_idx),
+    status = lib().mrf_match(D.handle, ctypes.byref(opts), n, _dev(Z, torch.complex64), zl, sv,
+                             _dev(warm_idx, torch.int32),
                              _dev(o["idx"]), _dev(o.get("pd")), _dev(o.get("corr")),
                              _dev(o.get("X")), _dev(o.get("params")),
                              ctypes.byref(st) if st is not None else None, _stream(stream))
@@ -333,8 +336,8 @@ def mrf_match_local(D: Dictionary, Z, cells, layout="voxel", slice_voxels=None, 
         o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
     opts = match_opts("fp32", 8, 0, None, box_radius, fallback_corr, recentre)
     st = MatchStats() if stats else None
-    _check(lib().mrf_match_local(D.handle, ctypes.byref(opts), n, _dev(Z), zl, sv, _dev(cells),
-                                 _dev(warm_idx), _dev(o["idx"]), _dev(o["pd"]), _dev(o["corr"]),
+    _check(lib().mrf_match_local(D.handle, ctypes.byref(opts), n, _dev(Z, torch.complex64), zl, sv,
+                                 _dev(cells, torch.int32), _dev(warm_idx, torch.int32), _dev(o["idx"]), _dev(o["pd"]), _dev(o["corr"]),
                                  _dev(o["fallback"]), _dev(o.get("X")), _dev(o.get("params")),
                                  ctypes.byref(st) if st is not None else None, _stream(stream)))
     if stats:
@@ -410,13 +413,15 @@ class Net:
 def mrf_net_forward(net: Net, X, stream=None):
     torch = _torch()
     Y = torch.empty((X.shape[0], net.nout), dtype=torch.float32, device="cuda")
-    _check(lib().mrf_net_forward(net.handle, _dev(X), X.shape[0], _dev(Y), _stream(stream)))
+    torch = _torch()
+    _check(lib().mrf_net_forward(net.handle, _dev(X, torch.float32), X.shape[0], _dev(Y), _stream(stream)))
     return Y
 
 
 def mrf_net_loss_grad(net: Net, X, T, stream=None):
     loss = ctypes.c_double()
-    _check(lib().mrf_net_loss_grad(net.handle, _dev(X), _dev(T), X.shape[0], ctypes.byref(loss),
+    torch = _torch()
+    _check(lib().mrf_net_loss_grad(net.handle, _dev(X, torch.float32), _dev(T, torch.float32), X.shape[0], ctypes.byref(loss),
                                    _stream(stream)))
     return loss.value
 

@@ -102,7 +102,7 @@ def test_net_forward_gradients_adam_vs_oracle(m, I, H, P, B):
     flat = _random_params(net, 5)
     net.set_params(flat)
     prm = {k: v.astype(np.float64) for k, v in net.unpack(flat).items()}
-    X = rng.normal(6, "x", B * I).reshape(B, I).astype(np.float32) / np.sqrt(I)
+    X = (rng.normal(6, "x", B * I).reshape(B, I) / np.sqrt(I)).astype(np.float32)
     T = rng.normal(6, "t", B * P).reshape(B, P).astype(np.float32)
     Y = host(m.mrf_net_forward(net, dev(X)))
     Yr, _ = mlp.forward(prm, X.astype(np.float64))
