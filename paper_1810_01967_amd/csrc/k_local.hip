@@ -9,6 +9,7 @@
 // whose best atom sits on an interior box face (re-centring) or whose
 // normalised correlation is below the fallback threshold, compact those
 // lists, and gather / scatter rows for the exhaustive fallback.
+#include <algorithm>
 #include <cfloat>
 
 #include "mrf_internal.h"
@@ -38,29 +39,49 @@ __global__ void k_coarse_keys(const int32_t *__restrict__ list, int64_t cnt,
   atomicAdd(&hist[key], 1u);
 }
 
-// exclusive scan of hist[0..nkeys) into off (one block, chunks of 1024)
+// Exclusive scans of hist[0..nkeys) (one block, chunks of 1024): off[k] (the
+// first sorted position of key k), cursor[k] = off[k] (consumed by the
+// scatter), and toff[k] = the first tile of key k, where key k owns
+// ceil(hist[k] / 64) tiles; toff[nkeys] = the number of tiles.
 __global__ __launch_bounds__(1024) void k_scan(const unsigned int *__restrict__ hist, int nkeys,
-                                               unsigned int *__restrict__ off) {
-  __shared__ unsigned int buf[1024];
-  __shared__ unsigned int carry;
-  if (threadIdx.x == 0) carry = 0;
+                                               unsigned int *__restrict__ off,
+                                               unsigned int *__restrict__ cursor,
+                                               unsigned int *__restrict__ toff) {
+  __shared__ unsigned int buf[1024], tbuf[1024];
+  __shared__ unsigned int carry, tcarry;
+  if (threadIdx.x == 0) {
+    carry = 0;
+    tcarry = 0;
+  }
   __syncthreads();
   for (int base = 0; base < nkeys; base += 1024) {
     const int i = base + threadIdx.x;
     const unsigned int x = i < nkeys ? hist[i] : 0u;
+    const unsigned int tx = (x + 63u) / 64u;
     buf[threadIdx.x] = x;
+    tbuf[threadIdx.x] = tx;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
       const unsigned int y = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0u;
+      const unsigned int ty = threadIdx.x >= (unsigned)o ? tbuf[threadIdx.x - o] : 0u;
       __syncthreads();
       buf[threadIdx.x] += y;
+      tbuf[threadIdx.x] += ty;
       __syncthreads();
     }
-    if (i < nkeys) off[i] = carry + buf[threadIdx.x] - x;
+    if (i < nkeys) {
+      off[i] = carry + buf[threadIdx.x] - x;
+      cursor[i] = off[i];
+      toff[i] = tcarry + tbuf[threadIdx.x] - tx;
+    }
     __syncthreads();
-    if (threadIdx.x == 1023) carry += buf[1023];
+    if (threadIdx.x == 1023) {
+      carry += buf[1023];
+      tcarry += tbuf[1023];
+    }
     __syncthreads();
   }
+  if (threadIdx.x == 0) toff[nkeys] = tcarry;
 }
 
 __global__ void k_group_scatter(const int32_t *__restrict__ list, const int32_t *__restrict__ keys,
@@ -79,16 +100,15 @@ int coarse_key_count(const GridDims &g, int P, int shift) {
 }
 
 void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P, int shift,
-                  const GridDims &g, int32_t *keys, unsigned int *hist, unsigned int *off,
-                  int32_t *out, hipStream_t s) {
+                  const GridDims &g, int32_t *keys, GroupBufs gb, int32_t *out, hipStream_t s) {
   if (cnt <= 0) return;
   const int nkeys = coarse_key_count(g, P, shift);
-  launch_zero(hist, (int64_t)nkeys * 4, s);
+  launch_zero(gb.hist, (int64_t)nkeys * 4, s);
   const unsigned blocks = (unsigned)((cnt + 255) / 256);
   hipLaunchKernelGGL(k_coarse_keys, dim3(blocks), dim3(256), 0, s, list, cnt, cells, P, shift, g,
-                     keys, hist);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, nkeys, off);
-  hipLaunchKernelGGL(k_group_scatter, dim3(blocks), dim3(256), 0, s, list, keys, cnt, off, out);
+                     keys, gb.hist);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, gb.hist, nkeys, gb.off, gb.cursor, gb.toff);
+  hipLaunchKernelGGL(k_group_scatter, dim3(blocks), dim3(256), 0, s, list, keys, cnt, gb.cursor, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -102,8 +122,8 @@ __device__ __forceinline__ bool lbetter(float s1, int j1, float s0, int j0) {
 
 __global__ __launch_bounds__(256, 2) void k_local_score(
     const float *__restrict__ D, const float *__restrict__ Zp, int Kp,
-    const int32_t *__restrict__ order, int64_t cnt, const int32_t *__restrict__ cells, int P,
-    GridDims g, int r, float *__restrict__ best_s, int32_t *__restrict__ best_j,
+    const int32_t *__restrict__ order, GroupBufs gb, int nkeys, const int32_t *__restrict__ cells,
+    int P, GridDims g, int r, float *__restrict__ best_s, int32_t *__restrict__ best_j,
     unsigned long long *__restrict__ work) {
   __shared__ float As[2][LS_BA][LS_LD];
   __shared__ float Zs[2][LS_BV][LS_LD];
@@ -117,11 +137,22 @@ __global__ __launch_bounds__(256, 2) void k_local_score(
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
-  const int64_t v0 = (int64_t)blockIdx.x * LS_BV;
+  // tile T belongs to the key k with toff[k] <= T < toff[k+1]; its voxels are
+  // sorted positions off[k] + 64 (T - toff[k]) .. (at most 64, never beyond key k)
+  const unsigned int T = blockIdx.x;
+  if (T >= gb.toff[nkeys]) return;
+  int lo_k = 0, hi_k = nkeys - 1;
+  while (lo_k < hi_k) {
+    const int mid = (lo_k + hi_k + 1) >> 1;
+    if (gb.toff[mid] <= T) lo_k = mid; else hi_k = mid - 1;
+  }
+  const int key = lo_k;
+  const int64_t v0 = (int64_t)gb.off[key] + 64ll * (T - gb.toff[key]);
+  const int64_t vend = (int64_t)gb.off[key] + gb.hist[key];
   // voxels and their clipped boxes
   if (tid < LS_BV) {
     const int64_t i = v0 + tid;
-    const int v = i < cnt ? order[i] : -1;
+    const int v = i < vend ? order[i] : -1;
     vid[tid] = v;
     for (int p = 0; p < 4; ++p) {
       int lo = 1, hi = 0;  // empty box for padding lanes / unused parameters
@@ -306,12 +337,13 @@ __global__ __launch_bounds__(256, 2) void k_local_score(
 }
 
 void launch_local_score(const float *D, const float *Zp, int Kp, const int32_t *order, int64_t cnt,
-                        const int32_t *cells, int P, const GridDims &g, int r, float *best_s,
-                        int32_t *best_j, unsigned long long *work, hipStream_t s) {
+                        GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r,
+                        float *best_s, int32_t *best_j, unsigned long long *work, hipStream_t s) {
   if (cnt <= 0) return;
-  const unsigned blocks = (unsigned)((cnt + LS_BV - 1) / LS_BV);
-  hipLaunchKernelGGL(k_local_score, dim3(blocks), dim3(256), 0, s, D, Zp, Kp, order, cnt, cells, P, g,
-                     r, best_s, best_j, work);
+  // tiles = sum_k ceil(hist[k]/64) <= ceil(cnt/64) + min(nkeys, cnt); extra blocks exit at once
+  const int64_t blocks = (cnt + LS_BV - 1) / LS_BV + std::min<int64_t>(nkeys, cnt);
+  hipLaunchKernelGGL(k_local_score, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, Kp, order, gb,
+                     nkeys, cells, P, g, r, best_s, best_j, work);
 }
 
 // ---------------------------------------------------------------------------

@@ -148,13 +148,20 @@ void launch_cells(const float *Y, int64_t n, int P, const float *mean, const flo
 struct GridDims {
   int dims[4];
 };
+// Counting-sort buffers of the voxel grouping: per coarse key its count
+// (hist), first sorted position (off), scatter cursor, and first tile
+// (toff, nkeys + 1 entries: toff[nkeys] = number of tiles).
+struct GroupBufs {
+  unsigned int *hist, *off, *cursor, *toff;
+};
 int coarse_key_count(const GridDims &g, int P, int shift);
 void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P, int shift,
-                  const GridDims &g, int32_t *keys, unsigned int *hist, unsigned int *off,
-                  int32_t *out, hipStream_t s);
+                  const GridDims &g, int32_t *keys, GroupBufs gb, int32_t *out, hipStream_t s);
+// Local search over the grouped list: one block per tile of <= 64 voxels of
+// one coarse key.
 void launch_local_score(const float *D, const float *Zp, int Kp, const int32_t *order, int64_t cnt,
-                        const int32_t *cells, int P, const GridDims &g, int r, float *best_s,
-                        int32_t *best_j, unsigned long long *work, hipStream_t s);
+                        GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r,
+                        float *best_s, int32_t *best_j, unsigned long long *work, hipStream_t s);
 void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
                  const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s);
 void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,

@@ -492,17 +492,20 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   }
   const int shift = 2;
   const int nkeys = coarse_key_count(g, P, shift);
-  TRY(grow(D->hist, (size_t)nkeys * 4));
-  TRY(grow(D->off, (size_t)nkeys * 4));
+  TRY(grow(D->hist, (size_t)(4 * nkeys + 8) * 4));
+  GroupBufs gb;
+  gb.hist = D->hist.as<unsigned int>();
+  gb.off = gb.hist + nkeys;
+  gb.cursor = gb.off + nkeys;
+  gb.toff = gb.cursor + nkeys;
   unsigned long long *work = D->counters.as<unsigned long long>() + 2;
   launch_zero(work, 8, s);
   // round 0: every voxel, grouped by coarse proposal cell
   int32_t *la = D->list_a.as<int32_t>(), *lb = D->list_b.as<int32_t>(), *lc = D->list_c.as<int32_t>();
   launch_iota(la, n, s);
   if (st) HIP_TRY(hipEventRecord(ev.a, s));
-  launch_group(la, n, cells, P, shift, g, D->keys.as<int32_t>(), D->hist.as<unsigned int>(),
-               D->off.as<unsigned int>(), lb, s);
-  launch_local_score(D->dhat.as<float>(), D->zp.as<float>(), D->Kp, lb, n, cells, P, g, r,
+  launch_group(la, n, cells, P, shift, g, D->keys.as<int32_t>(), gb, lb, s);
+  launch_local_score(D->dhat.as<float>(), D->zp.as<float>(), D->Kp, lb, n, gb, nkeys, cells, P, g, r,
                      D->best_s.as<float>(), D->best_j.as<int32_t>(), work, s);
   LAUNCH_CHECK("local search");
   int64_t cnt = n;
@@ -522,10 +525,9 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     recentred += cnt;
     if (cnt == 0) break;
     int32_t *sorted = (prev == lb) ? la : lb;
-    launch_group(lc, cnt, cells, P, shift, g, D->keys.as<int32_t>(), D->hist.as<unsigned int>(),
-                 D->off.as<unsigned int>(), sorted, s);
-    launch_local_score(D->dhat.as<float>(), D->zp.as<float>(), D->Kp, sorted, cnt, cells, P, g, r,
-                       D->best_s.as<float>(), D->best_j.as<int32_t>(), work, s);
+    launch_group(lc, cnt, cells, P, shift, g, D->keys.as<int32_t>(), gb, sorted, s);
+    launch_local_score(D->dhat.as<float>(), D->zp.as<float>(), D->Kp, sorted, cnt, gb, nkeys, cells, P,
+                       g, r, D->best_s.as<float>(), D->best_j.as<int32_t>(), work, s);
     LAUNCH_CHECK("local search (re-centre)");
     prev = sorted;
   }
