@@ -145,13 +145,14 @@ typedef struct {
   int64_t nonfinite;     /* voxels with a NaN/Inf entry (idx = -1 for them) */
   float ms;              /* device time of the call (hipEvents on `stream`) */
   float score_ms;        /* device time of the candidate-scoring kernel alone
-                            (MRF_LEARNED: of the local-search scoring kernels) */
+                            (MRF_LEARNED: the first local-search scoring kernel) */
   int32_t splits;        /* atom ranges the scoring kernel used */
   int64_t fallbacks;     /* MRF_LEARNED: voxels sent to the exhaustive filter */
   int64_t recentred;     /* MRF_LEARNED: box re-centrings performed */
   int64_t local_atoms;   /* MRF_LEARNED: atom rows scored by the local search (incl. padding) */
   float proposal_ms;     /* MRF_LEARNED: device time of the network and cell mapping */
   float fallback_ms;     /* MRF_LEARNED: device time of the exhaustive fallback */
+  float search_ms;       /* MRF_LEARNED: device time of grouping, local search and re-centring */
 } mrf_match_stats;
 
 /* Project n voxels onto cone(D).

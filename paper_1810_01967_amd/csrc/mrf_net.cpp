@@ -447,8 +447,10 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   GridDims g;
   for (int p = 0; p < 4; ++p) g.dims[p] = p < P ? D->grid_dims[(size_t)p] : 1;
   EventPair ev;
-  hipEvent_t e_prop0 = nullptr, e_prop1 = nullptr;
+  hipEvent_t e_prop0 = nullptr, e_prop1 = nullptr, e_ls0 = nullptr, e_ls1 = nullptr;
   if (st) {
+    HIP_TRY(hipEventCreate(&e_ls0));
+    HIP_TRY(hipEventCreate(&e_ls1));
     HIP_TRY(hipEventCreate(&ev.a));
     HIP_TRY(hipEventCreate(&ev.b));
     HIP_TRY(hipEventCreate(&ev.c));
@@ -457,12 +459,14 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     HIP_TRY(hipEventCreate(&e_prop1));
   }
   struct EvGuard {
-    hipEvent_t a, b;
+    hipEvent_t a, b, c, d;
     ~EvGuard() {
       if (a) (void)hipEventDestroy(a);
       if (b) (void)hipEventDestroy(b);
+      if (c) (void)hipEventDestroy(c);
+      if (d) (void)hipEventDestroy(d);
     }
-  } eg{e_prop0, e_prop1};
+  } eg{e_prop0, e_prop1, e_ls0, e_ls1};
   TRY(grow(D->gamma, (size_t)n * 4));
   TRY(grow(D->best_s, (size_t)n * 4));
   TRY(grow(D->best_j, (size_t)n * 4));
@@ -505,8 +509,10 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   launch_iota(la, n, s);
   if (st) HIP_TRY(hipEventRecord(ev.a, s));
   launch_group(la, n, cells, P, shift, g, D->keys.as<int32_t>(), gb, lb, s);
+  if (st) HIP_TRY(hipEventRecord(e_ls0, s));
   launch_local_score(D->dhat.as<float>(), D->zp.as<float>(), D->Kp, lb, n, gb, nkeys, cells, P, g, r,
                      D->best_s.as<float>(), D->best_j.as<int32_t>(), work, s);
+  if (st) HIP_TRY(hipEventRecord(e_ls1, s));
   LAUNCH_CHECK("local search");
   int64_t cnt = n;
   int64_t recentred = 0;
@@ -582,7 +588,8 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     st->fallbacks = nfb;
     st->recentred = recentred;
     st->local_atoms = (int64_t)wk;
-    HIP_TRY(hipEventElapsedTime(&st->score_ms, ev.a, ev.b));
+    HIP_TRY(hipEventElapsedTime(&st->search_ms, ev.a, ev.b));
+    HIP_TRY(hipEventElapsedTime(&st->score_ms, e_ls0, e_ls1));
     HIP_TRY(hipEventElapsedTime(&st->fallback_ms, ev.c, ev.d));
     if (!cells_in) HIP_TRY(hipEventElapsedTime(&st->proposal_ms, e_prop0, e_prop1));
   }

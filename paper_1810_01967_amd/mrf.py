@@ -67,7 +67,7 @@ class MatchStats(ctypes.Structure):
                 ("score_ms", ctypes.c_float), ("splits", ctypes.c_int32),
                 ("fallbacks", ctypes.c_int64), ("recentred", ctypes.c_int64),
                 ("local_atoms", ctypes.c_int64), ("proposal_ms", ctypes.c_float),
-                ("fallback_ms", ctypes.c_float)]
+                ("fallback_ms", ctypes.c_float), ("search_ms", ctypes.c_float)]
 
 
 class TrainOpts(ctypes.Structure):
