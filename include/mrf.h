@@ -68,8 +68,9 @@ const char *mrf_version(void);
 typedef struct mrf_dict_s *mrf_dict;
 
 enum {
-  MRF_STORE_BF16 = 1u << 1, /* also keep a BF16 copy (precision MRF_BF16) */
-  MRF_STORE_FP8 = 1u << 2   /* also keep an FP8-E4M3 copy (precision MRF_FP8) */
+  MRF_STORE_BF16 = 1u << 1,     /* also keep a BF16 copy (precision MRF_BF16) */
+  MRF_STORE_FP8 = 1u << 2,      /* also keep an FP8-E4M3 copy (precision MRF_FP8) */
+  MRF_BUILD_COVERTREE = 1u << 3 /* build the cover tree of the normalised atoms (MRF_COVERTREE) */
 };
 enum { MRF_F64 = 0, MRF_F32 = 1 }; /* element type of host atom arrays */
 
@@ -112,12 +113,34 @@ mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info);
 mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *dst, float *scales,
                                mrf_stream stream);
 
+/* Cover tree (Section "Cover trees"), built at mrf_dict_build with
+ * MRF_BUILD_COVERTREE on the host in FP64 over the normalised atoms, exactly
+ * equal atoms merged into the lowest index: greedy nested nets (root atom 0,
+ * sigma = max_j ||D_0 - D_j||; level i+1 keeps S_i and adds, scanning atoms
+ * in increasing index, every atom farther than sigma 2^-(i+1) from all nodes
+ * already in S_{i+1}; a new node's parent is its nearest node of S_i, ties to
+ * the lower index), with the exact maxdist of every (level, node). */
+typedef struct {
+  int32_t unique_atoms;   /* atoms after merging exact duplicates */
+  int32_t imax;           /* deepest level */
+  int64_t entries;        /* (level, node) pairs stored for the traversal */
+  double sigma;           /* root coverage radius */
+} mrf_tree_info;
+mrf_status mrf_dict_tree_info(mrf_dict D, mrf_tree_info *info);
+/* HOST arrays of unique_atoms entries: rep (lowest dictionary index of each
+ * unique atom), ins_level (level at which it became a node), parent (its
+ * parent, a unique index, -1 for the root); maxdist HOST [entries] in the
+ * order level-major, nodes ascending within a level (or NULL). */
+mrf_status mrf_dict_tree_export(mrf_dict D, int32_t *rep, int32_t *ins_level, int32_t *parent,
+                                float *maxdist);
+
 /* ------------------------------------------------------------------------ */
 /* Matched filter P_cone(D) (eq. exactP, eq. exactPs)                         */
 /* ------------------------------------------------------------------------ */
 enum {
   MRF_EXHAUSTIVE = 0, /* every atom scored (eq. exactP) */
-  MRF_LEARNED = 1     /* network proposal + exact local search + exhaustive fallback */
+  MRF_LEARNED = 1,    /* network proposal + exact local search + exhaustive fallback */
+  MRF_COVERTREE = 2   /* cover-tree (1+eps)-ANNS (Algorithm 1) on Z_v/||Z_v||, warm-started */
 };
 enum { MRF_FP32 = 0, MRF_BF16 = 1, MRF_FP8 = 2 };
 enum { MRF_VOXEL_MAJOR = 0, MRF_FRAME_MAJOR = 1 };
@@ -137,6 +160,9 @@ typedef struct {
                           correlation (0 = 0.98; negative disables the fallback) */
   int32_t recentre;    /* MRF_LEARNED: re-centre rounds when the best atom lies on an
                           interior face of the box (0 = none) */
+  float eps;           /* MRF_COVERTREE: search inaccuracy eps >= 0 (Definition 3.1) */
+  int32_t tree_capacity; /* MRF_COVERTREE: candidate-set capacity per query (0 = 1024);
+                            queries that outgrow it use the exhaustive filter */
 } mrf_match_opts;
 
 typedef struct {
@@ -152,15 +178,18 @@ typedef struct {
   int64_t local_atoms;   /* MRF_LEARNED: atom rows scored by the local search (incl. padding) */
   float proposal_ms;     /* MRF_LEARNED: device time of the network and cell mapping */
   float fallback_ms;     /* MRF_LEARNED: device time of the exhaustive fallback */
-  float search_ms;       /* MRF_LEARNED: device time of grouping, local search and re-centring */
+  float search_ms;       /* MRF_LEARNED / MRF_COVERTREE: device time of the search stage */
+  int64_t distance_evals;/* MRF_COVERTREE: distances computed (self-children excluded) */
+  int32_t tree_levels;   /* MRF_COVERTREE: level launches */
 } mrf_match_stats;
 
 /* Project n voxels onto cone(D).
  *   Z        DEVICE complex64.  z_layout MRF_VOXEL_MAJOR: [n][L];
  *            MRF_FRAME_MAJOR: [n/slice_voxels][L][slice_voxels] (frame images
  *            of consecutive slices), slice_voxels must divide n.
- *   warm_idx DEVICE int32 [n] or NULL: index reported for voxels with
- *            ||Z_v|| = 0 (Algorithm 2's previous estimate); NULL -> 0.
+ *   warm_idx DEVICE int32 [n] or NULL: Algorithm 2's previous estimate: the
+ *            index reported for voxels with ||Z_v|| = 0, and the cover tree's
+ *            warm start q_c; NULL -> 0 (the root).
  *   idx      DEVICE int32 [n]: j* (lowest index among equal scores); -1 for
  *            non-finite voxels.
  *   pd       DEVICE float [n] or NULL: gamma_v of eq. exactPs.

@@ -12,6 +12,7 @@
 #include <utility>
 #include <vector>
 
+#include "covertree.h"
 #include "mrf_internal.h"
 
 namespace mrf {
@@ -89,6 +90,10 @@ mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
 mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t slice_voxels,
                        int64_t n, hipStream_t s);
 mrf_status check_opts(const mrf_dict_s *D, const mrf_match_opts *o);
+mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
+                      int32_t *idx, float *pd, float *corr, float *params_out, mrf_match_stats *st,
+                      hipStream_t s);
+mrf_status upload_tree(mrf_dict_s *D, const double *Xnorm);
 }  // namespace mrf
 
 struct mrf_dict_s {
@@ -106,6 +111,12 @@ struct mrf_dict_s {
   mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j;
   mrf::DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;
   mrf::DevBuf inv, h1, h2, yout, cells, best_s, best_j, list_a, list_b, list_c, keys, hist, off, cnt, rows;
+  // cover tree (host copy for export, device arrays for the traversal)
+  bool has_tree = false;
+  mrf::HostTree tree;
+  int64_t tree_entries = 0;
+  mrf::DevBuf t_node, t_rep, t_uniq, t_cb, t_ce, t_md, t_self;
+  mrf::DevBuf ts_active, ts_qc, ts_cnt, ts_flags, ts_dmin, ts_Qe0, ts_Qe1, ts_Qd0, ts_Qd1, ts_evals;
   double *host_scal = nullptr;  // pinned readback of reduced scalars
   ~mrf_dict_s() {
     if (host_scal) (void)hipHostFree(host_scal);

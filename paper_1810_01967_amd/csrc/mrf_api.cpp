@@ -72,7 +72,8 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
   if (q.is_complex != 0 && q.is_complex != 1) return fail(MRF_E_INVAL, "mrf_dict_build: is_complex must be 0 or 1");
   if (!q.atoms || !q.params) return fail(MRF_E_INVAL, "mrf_dict_build: null atoms or params");
   if (q.atoms_dtype != MRF_F64 && q.atoms_dtype != MRF_F32) return fail(MRF_E_INVAL, "mrf_dict_build: bad atoms_dtype");
-  if (q.flags & ~(uint32_t)(MRF_STORE_BF16 | MRF_STORE_FP8)) return fail(MRF_E_INVAL, "mrf_dict_build: unknown flags 0x%x", q.flags);
+  if (q.flags & ~(uint32_t)(MRF_STORE_BF16 | MRF_STORE_FP8 | MRF_BUILD_COVERTREE))
+    return fail(MRF_E_INVAL, "mrf_dict_build: unknown flags 0x%x", q.flags);
   const int64_t K = (int64_t)(q.is_complex ? 2 : 1) * q.L;
   if (K > (1 << 20)) return fail(MRF_E_INVAL, "mrf_dict_build: L too large");
   if (q.grid_dims) {
@@ -105,6 +106,9 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
   const int64_t chunk = 8192;
   std::vector<float> stage((size_t)chunk * D->Kp);
   std::vector<float> inv((size_t)q.d);
+  const bool tree = (q.flags & MRF_BUILD_COVERTREE) != 0;
+  std::vector<double> xnorm;  // FP64 normalised rows for the cover tree
+  if (tree) xnorm.resize((size_t)q.d * K);
   for (int64_t r0 = 0; r0 < D->d_pad; r0 += chunk) {
     const int64_t r1 = std::min<int64_t>(r0 + chunk, D->d_pad);
     std::fill(stage.begin(), stage.end(), 0.f);
@@ -118,6 +122,8 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
           return fail(MRF_E_INVAL, "mrf_dict_build: atom %lld has zero or non-finite norm", (long long)j);
         const double nrm = std::sqrt(nrm2);
         for (int64_t k = 0; k < K; ++k) stage[(size_t)(j - r0) * D->Kp + k] = (float)(a[k] / nrm);
+        if (tree)
+          for (int64_t k = 0; k < K; ++k) xnorm[(size_t)(j * K + k)] = a[k] / nrm;
         inv[(size_t)j] = (float)(1.0 / nrm);
       } else {
         const float *a = static_cast<const float *>(q.atoms) + j * K;
@@ -126,6 +132,8 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
           return fail(MRF_E_INVAL, "mrf_dict_build: atom %lld has zero or non-finite norm", (long long)j);
         const double nrm = std::sqrt(nrm2);
         for (int64_t k = 0; k < K; ++k) stage[(size_t)(j - r0) * D->Kp + k] = (float)((double)a[k] / nrm);
+        if (tree)
+          for (int64_t k = 0; k < K; ++k) xnorm[(size_t)(j * K + k)] = (double)a[k] / nrm;
         inv[(size_t)j] = (float)(1.0 / nrm);
       }
     }
@@ -176,6 +184,7 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
     LAUNCH_CHECK("quantize_rows(fp8)");
     D->bytes += (int64_t)(D->dfp8.cap + D->fp8_scale.cap);
   }
+  if (tree) TRY(upload_tree(D, xnorm.data()));
   HIP_TRY(hipHostMalloc((void **)&D->host_scal, 16 * sizeof(double), hipHostMallocDefault));
   HIP_TRY(hipStreamSynchronize(s));
   *out = guard.release();
@@ -236,9 +245,15 @@ namespace mrf {
 
 mrf_status check_opts(const mrf_dict_s *D, const mrf_match_opts *o) {
   if (!o) return MRF_OK;
-  if (o->method != MRF_EXHAUSTIVE && o->method != MRF_LEARNED)
+  if (o->method != MRF_EXHAUSTIVE && o->method != MRF_LEARNED && o->method != MRF_COVERTREE)
     return fail(MRF_E_INVAL, "unknown method %d", o->method);
   if (o->method == MRF_LEARNED) TRY(check_learned(D, o, true));
+  if (o->method == MRF_COVERTREE) {
+    if (!D->has_tree) return fail(MRF_E_UNSUPPORTED, "MRF_COVERTREE needs MRF_BUILD_COVERTREE at build");
+    if (!(o->eps >= 0.f) || !std::isfinite(o->eps)) return fail(MRF_E_INVAL, "eps must be >= 0");
+    if (o->tree_capacity < 0 || o->tree_capacity > (1 << 16)) return fail(MRF_E_INVAL, "bad tree_capacity");
+    if (D->Kp % 4 != 0) return fail(MRF_E_INVAL, "internal pitch");
+  }
   if (o->precision < MRF_FP32 || o->precision > MRF_FP8) return fail(MRF_E_INVAL, "bad precision %d", o->precision);
   if (o->topk < 0 || o->topk > 8) return fail(MRF_E_INVAL, "topk %d not in 0..8", o->topk);
   if (o->atom_splits < 0) return fail(MRF_E_INVAL, "atom_splits must be >= 0");
@@ -313,6 +328,7 @@ mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
                       hipEvent_t ev_s0, hipEvent_t ev_s1, int *splits_used, mrf_match_stats *st) {
   if (o && o->method == MRF_LEARNED)
     return match_learned(D, o, n, warm, idx, pd, corr, params_out, nullptr, nullptr, st, s);
+  if (o && o->method == MRF_COVERTREE) return match_tree(D, o, n, warm, idx, pd, corr, params_out, st, s);
   return match_exhaustive(D, o, n, warm, idx, pd, corr, params_out, s, ev_s0, ev_s1, splits_used);
 }
 
@@ -379,7 +395,7 @@ extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t 
     HIP_TRY(hipMemcpyAsync(cnt, D->counters.p, sizeof cnt, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipEventElapsedTime(&stats->ms, ev.a, ev.b));
-    if (!opts || opts->method != MRF_LEARNED) HIP_TRY(hipEventElapsedTime(&stats->score_ms, ev.c, ev.d));
+    if (!opts || opts->method == MRF_EXHAUSTIVE) HIP_TRY(hipEventElapsedTime(&stats->score_ms, ev.c, ev.d));
     stats->splits = splits_used;
     stats->n = n;
     stats->zero_voxels = (int64_t)cnt[0];

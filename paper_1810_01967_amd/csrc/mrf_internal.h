@@ -172,3 +172,34 @@ void launch_scatter_best(const int32_t *list, int64_t cnt, const float *part_s, 
                          int splits, float *best_s, int32_t *best_j, hipStream_t s);
 void launch_iota(int32_t *x, int64_t n, hipStream_t s);
 }  // namespace mrf
+
+namespace mrf {
+// ---------------------------------------------------------------- cover tree
+struct TreeDev {
+  const float *dhat;          // FP32 normalised atoms [d_pad][Kp]
+  const int32_t *node;        // per entry: unique atom
+  const int32_t *rep;         // unique atom -> dictionary row
+  const int32_t *uniq_of;     // dictionary row -> unique atom
+  const int32_t *child_begin, *child_end;
+  const float *maxdist;
+  const uint8_t *is_self;
+  int d;
+  float sigma;
+  int imax;
+};
+struct TreeState {
+  int32_t *active, *qc, *cnt, *flags;
+  float *dmin;
+  int32_t *Qe;   // current candidate entries [n][cap]
+  float *Qd;     // their distances
+  int cap;
+  unsigned long long *evals;
+};
+void launch_tree_init(const TreeDev &t, const float *Zp, int Kp, const float *znorm, const int32_t *warm,
+                      int64_t n, const TreeState &st, hipStream_t s);
+void launch_tree_level(const TreeDev &t, const float *Zp, int Kp, const float *znorm, int64_t n, int level,
+                       float inv_eps, const TreeState &st, int32_t *Qe2, float *Qd2, hipStream_t s);
+void launch_tree_finish(const TreeDev &t, const float *Zp, int Kp, int K, const float *znorm, int64_t n,
+                        const TreeState &st, float *best_s, int32_t *best_j, hipStream_t s);
+void launch_tree_select(const TreeState &st, int64_t n, int32_t *out, unsigned int *count, hipStream_t s);
+}  // namespace mrf

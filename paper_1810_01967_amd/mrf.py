@@ -17,15 +17,15 @@ LIB_PATH = os.path.join(HERE, "libmrf.so")
 
 MRF_OK = 0
 MRF_E_INVAL, MRF_E_NOMEM, MRF_E_HIP, MRF_E_UNSUPPORTED, MRF_E_NUMERIC, MRF_E_NOCONV = -1, -2, -3, -4, -5, -6
-MRF_STORE_BF16, MRF_STORE_FP8 = 2, 4
+MRF_STORE_BF16, MRF_STORE_FP8, MRF_BUILD_COVERTREE = 2, 4, 8
 MRF_F64, MRF_F32 = 0, 1
-MRF_EXHAUSTIVE, MRF_LEARNED = 0, 1
+MRF_EXHAUSTIVE, MRF_LEARNED, MRF_COVERTREE = 0, 1, 2
 MRF_FP32, MRF_BF16, MRF_FP8 = 0, 1, 2
 MRF_VOXEL_MAJOR, MRF_FRAME_MAJOR = 0, 1
 PRECISION = {"fp32": MRF_FP32, "bf16": MRF_BF16, "fp8": MRF_FP8}
 
 EXPORTS = ["mrf_last_error", "mrf_version", "mrf_dict_build", "mrf_dict_destroy", "mrf_dict_query",
-           "mrf_dict_copy_atoms", "mrf_match", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
+           "mrf_dict_copy_atoms", "mrf_dict_tree_info", "mrf_dict_tree_export", "mrf_match", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
            "mrf_net_size", "mrf_net_set_params", "mrf_net_get_params", "mrf_net_get_grads",
            "mrf_net_set_standardisation", "mrf_net_get_standardisation", "mrf_net_forward",
            "mrf_net_loss_grad", "mrf_net_adam", "mrf_net_noisy_batch", "mrf_net_train",
@@ -58,7 +58,8 @@ class MatchOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("topk", ctypes.c_int32), ("atom_splits", ctypes.c_int32),
                 ("net", ctypes.c_void_p), ("box_radius", ctypes.c_int32),
-                ("fallback_corr", ctypes.c_float), ("recentre", ctypes.c_int32)]
+                ("fallback_corr", ctypes.c_float), ("recentre", ctypes.c_int32),
+                ("eps", ctypes.c_float), ("tree_capacity", ctypes.c_int32)]
 
 
 class MatchStats(ctypes.Structure):
@@ -67,7 +68,13 @@ class MatchStats(ctypes.Structure):
                 ("score_ms", ctypes.c_float), ("splits", ctypes.c_int32),
                 ("fallbacks", ctypes.c_int64), ("recentred", ctypes.c_int64),
                 ("local_atoms", ctypes.c_int64), ("proposal_ms", ctypes.c_float),
-                ("fallback_ms", ctypes.c_float), ("search_ms", ctypes.c_float)]
+                ("fallback_ms", ctypes.c_float), ("search_ms", ctypes.c_float),
+                ("distance_evals", ctypes.c_int64), ("tree_levels", ctypes.c_int32)]
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("unique_atoms", ctypes.c_int32), ("imax", ctypes.c_int32),
+                ("entries", ctypes.c_int64), ("sigma", ctypes.c_double)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -129,6 +136,9 @@ def lib():
                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.POINTER(MatchStats), ctypes.c_void_p]
+        L.mrf_dict_tree_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(TreeInfo)]
+        L.mrf_dict_tree_export.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]
         L.mrf_match_local.argtypes = [ctypes.c_void_p, ctypes.POINTER(MatchOpts), ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -207,7 +217,7 @@ class Dictionary:
     """Handle of a device dictionary (mrf_dict_build / mrf_dict_destroy)."""
 
     def __init__(self, atoms, params, grid_dims=None, store_bf16=False, store_fp8=False,
-                 stream=None):
+                 cover_tree=False, stream=None):
         atoms = np.asarray(atoms)
         self.is_complex = bool(np.iscomplexobj(atoms))
         d, L = atoms.shape
@@ -228,7 +238,8 @@ class Dictionary:
             params = params[:, None]
         self.nparam = params.shape[1]
         gd = None if grid_dims is None else np.ascontiguousarray(grid_dims, dtype=np.int32)
-        flags = (MRF_STORE_BF16 if store_bf16 else 0) | (MRF_STORE_FP8 if store_fp8 else 0)
+        flags = ((MRF_STORE_BF16 if store_bf16 else 0) | (MRF_STORE_FP8 if store_fp8 else 0)
+                 | (MRF_BUILD_COVERTREE if cover_tree else 0))
         desc = DictDesc(d, L, self.nparam, int(self.is_complex), host.ctypes.data, dt,
                         params.ctypes.data, None if gd is None else gd.ctypes.data, flags)
         h = ctypes.c_void_p()
@@ -241,6 +252,22 @@ class Dictionary:
         inf = DictInfo()
         _check(lib().mrf_dict_query(self.handle, ctypes.byref(inf)))
         return inf
+
+    def tree_info(self) -> TreeInfo:
+        inf = TreeInfo()
+        _check(lib().mrf_dict_tree_info(self.handle, ctypes.byref(inf)))
+        return inf
+
+    def tree_export(self):
+        inf = self.tree_info()
+        u = inf.unique_atoms
+        rep = np.empty(u, np.int32)
+        lev = np.empty(u, np.int32)
+        par = np.empty(u, np.int32)
+        md = np.empty(inf.entries, np.float32)
+        _check(lib().mrf_dict_tree_export(self.handle, rep.ctypes.data, lev.ctypes.data, par.ctypes.data,
+                                          md.ctypes.data))
+        return dict(rep=rep, ins_level=lev, parent=par, maxdist=md, sigma=inf.sigma, imax=inf.imax)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -266,18 +293,21 @@ def mrf_dict_copy_atoms(D: Dictionary, precision="fp32", stream=None):
 
 
 def match_opts(precision="fp32", topk=8, atom_splits=0, net=None, box_radius=3, fallback_corr=0.98,
-               recentre=0) -> MatchOpts:
-    method = MRF_LEARNED if net is not None else MRF_EXHAUSTIVE
+               recentre=0, eps=None, tree_capacity=0) -> MatchOpts:
+    if eps is not None:
+        method = MRF_COVERTREE
+    else:
+        method = MRF_LEARNED if net is not None else MRF_EXHAUSTIVE
     return MatchOpts(method, PRECISION[precision], int(topk), int(atom_splits),
                      None if net is None else net.handle, int(box_radius), float(fallback_corr),
-                     int(recentre))
+                     int(recentre), float(eps or 0.0), int(tree_capacity))
 
 
 # --------------------------------------------------------------------------- matched filter
 def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp32", topk=8,
               atom_splits=0, warm_idx=None, want_pd=True, want_corr=True, want_X=False,
               want_params=False, stats=False, out=None, stream=None, net=None, box_radius=3,
-              fallback_corr=0.98, recentre=0):
+              fallback_corr=0.98, recentre=0, eps=None, tree_capacity=0):
     """Matched filter of the voxels in Z (complex64 CUDA tensor, [n][L] for
     layout 'voxel', [S][L][...] for 'frame').  Returns a dict of CUDA tensors
     (idx, pd, corr, X, params) and, with stats=True, a MatchStats."""
@@ -301,7 +331,8 @@ def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp
         o["X"] = torch.empty_like(Z)
     if want_params and "params" not in o:
         o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
-    opts = match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre)
+    opts = match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre, eps,
+                      tree_capacity)
     st = MatchStats() if stats else None
     status = lib().mrf_match(D.handle, ctypes.byref(opts), n, _dev(Z, torch.complex64), zl, sv,
                              _dev(warm_idx, torch.int32),
@@ -334,7 +365,7 @@ def mrf_match_local(D: Dictionary, Z, cells, layout="voxel", slice_voxels=None, 
         o["X"] = torch.empty_like(Z)
     if want_params:
         o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
-    opts = match_opts("fp32", 8, 0, None, box_radius, fallback_corr, recentre)
+    opts = match_opts("fp32", 8, 0, None, box_radius, fallback_corr, recentre, None, 0)
     st = MatchStats() if stats else None
     _check(lib().mrf_match_local(D.handle, ctypes.byref(opts), n, _dev(Z, torch.complex64), zl, sv,
                                  _dev(cells, torch.int32), _dev(warm_idx, torch.int32), _dev(o["idx"]), _dev(o["pd"]), _dev(o["corr"]),

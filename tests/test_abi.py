@@ -47,7 +47,8 @@ def test_struct_layout_matches_header(m, tmp_path):
                "mrf_match_opts": m.mrf.MatchOpts, "mrf_match_stats": m.mrf.MatchStats,
                "mrf_op": m.mrf.Op, "mrf_step_stats": m.mrf.StepStats,
                "mrf_solve_opts": m.mrf.SolveOpts, "mrf_solve_stats": m.mrf.SolveStats,
-               "mrf_train_opts": m.mrf.TrainOpts, "mrf_train_stats": m.mrf.TrainStats}
+               "mrf_train_opts": m.mrf.TrainOpts, "mrf_train_stats": m.mrf.TrainStats,
+               "mrf_tree_info": m.mrf.TreeInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -81,7 +82,7 @@ def test_validation_fails_before_device_work(m):
     desc = m.mrf.DictDesc(4, 3, 1, 0, atoms.ctypes.data, 0, params.ctypes.data, gd.ctypes.data, 0)
     assert L.mrf_dict_build(ctypes.byref(desc), None, ctypes.byref(h)) == m.mrf.MRF_E_INVAL
     assert b"grid_dims" in L.mrf_last_error()
-    opts = m.mrf.MatchOpts(0, 0, 8, 0)
+    opts = m.mrf.MatchOpts(0, 0, 8, 0, None, 3, 0.98, 0, 0.0, 0)
     assert L.mrf_match(None, ctypes.byref(opts), 1, None, 0, 0, None, None, None, None, None, None,
                        None, None) == m.mrf.MRF_E_INVAL
     bad = m.mrf.Op(48, 64, 10, 1, 0, None, None, None)      # 48 is not a power of two
