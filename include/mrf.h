@@ -70,7 +70,9 @@ typedef struct mrf_dict_s *mrf_dict;
 enum {
   MRF_STORE_BF16 = 1u << 1,     /* also keep a BF16 copy (precision MRF_BF16) */
   MRF_STORE_FP8 = 1u << 2,      /* also keep an FP8-E4M3 copy (precision MRF_FP8) */
-  MRF_BUILD_COVERTREE = 1u << 3 /* build the cover tree of the normalised atoms (MRF_COVERTREE) */
+  MRF_BUILD_COVERTREE = 1u << 3 /* build the cover tree of the normalised atoms (MRF_COVERTREE);
+                                   real rows of at most 2048 values (L <= 1024 complex),
+                                   else MRF_E_UNSUPPORTED */
 };
 enum { MRF_F64 = 0, MRF_F32 = 1 }; /* element type of host atom arrays */
 

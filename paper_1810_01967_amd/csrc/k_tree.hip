@@ -1,8 +1,9 @@
 // Cover-tree (1+eps)-approximate nearest-neighbour search (Algorithm 1) for
 // a batch of queries on gfx950, level-synchronous: one launch per tree
-// level, one wavefront per query.  Each lane computes the full FP32 distance
-// ||p - x_c|| of one child (self-children reuse their parent's distance), the
-// wave reduces the argmin (ties: lower atom) and compacts the refined
+// level, one wavefront per query.  The wave computes the FP32 distances
+// ||p - x_c|| of a query's children one at a time with coalesced row reads
+// (self-children reuse their parent's distance), reduces the argmin (ties:
+// lower atom) and compacts the refined
 // candidate set Q_{i+1} = {q : ||p - q|| <= d_min + maxdist(q)} with ballots.
 // Queries whose candidate set outgrows the per-query capacity are flagged
 // for the exhaustive filter.
@@ -25,6 +26,28 @@ __device__ __forceinline__ float lane_dist(const float *__restrict__ p, const fl
     s = fmaf(d2, d2, s);
     s = fmaf(d3, d3, s);
   }
+  return sqrtf(s);
+}
+
+// Cooperative distance: the wave splits the row into float4 slices (lane,
+// lane + 64, ...); ps holds this lane's slices of the query times 1/||Z||.
+constexpr int TQ = kTreeMaxK / 256;  // float4 slices per lane held in registers
+__device__ __forceinline__ float wave_dist(const float4 (&ps)[TQ], const float *__restrict__ x, int K4, int lane) {
+  const float4 *x4 = reinterpret_cast<const float4 *>(x);
+  float s = 0.f;
+#pragma unroll
+  for (int q = 0; q < TQ; ++q) {
+    const int k = lane + 64 * q;
+    if (k < K4) {
+      const float4 b = x4[k];
+      const float d0 = ps[q].x - b.x, d1 = ps[q].y - b.y, d2 = ps[q].z - b.z, d3 = ps[q].w - b.w;
+      s = fmaf(d0, d0, s);
+      s = fmaf(d1, d1, s);
+      s = fmaf(d2, d2, s);
+      s = fmaf(d3, d3, s);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   return sqrtf(s);
 }
 
@@ -108,6 +131,23 @@ __global__ __launch_bounds__(256) void k_tree_level(TreeDev t, const float *__re
   const float *Qd = st.Qd + v * st.cap;
   int32_t *Oe = Qe2 + v * st.cap;
   float *Od = Qd2 + v * st.cap;
+  float4 ps[TQ];
+  {
+    const float4 *p4 = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+      const int k = lane + 64 * q;
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (k < Kp / 4) {
+        a = p4[k];
+        a.x *= inv;
+        a.y *= inv;
+        a.z *= inv;
+        a.w *= inv;
+      }
+      ps[q] = a;
+    }
+  }
   int out = 0;
   bool overflow = false;
   unsigned long long evals = 0;
@@ -117,16 +157,26 @@ __global__ __launch_bounds__(256) void k_tree_level(TreeDev t, const float *__re
     const int cb = t.child_begin[e], ce = t.child_end[e];
     for (int c0 = cb; c0 < ce; c0 += 64) {
       const int c = c0 + lane;
-      float dc = INFINITY;
+      const int nc = min(64, ce - c0);
       int node = 0x7fffffff;
+      bool self = false;
       if (c < ce) {
         node = t.node[c];
-        if (t.is_self[c]) {
-          dc = dq;
+        self = t.is_self[c] != 0;
+      }
+      // distances of the chunk's children, one child per wave-wide pass
+      float dc = INFINITY;
+      for (int k = 0; k < nc; ++k) {
+        const int nk = __shfl(node, k, 64);
+        const bool sk = __shfl((int)self, k, 64) != 0;
+        float dk;
+        if (sk) {
+          dk = dq;
         } else {
-          dc = lane_dist(p, t.dhat + (int64_t)t.rep[node] * Kp, Kp / 4, inv);
+          dk = wave_dist(ps, t.dhat + (int64_t)t.rep[nk] * Kp, Kp / 4, lane);
           ++evals;
         }
+        if (lane == k) dc = dk;
       }
       float bd = dc;
       int bn = node;
@@ -171,7 +221,6 @@ __global__ __launch_bounds__(256) void k_tree_level(TreeDev t, const float *__re
     }
     kept += __popcll(m);
   }
-  for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o, 64);
   if (lane == 0) {
     st.dmin[v] = dmin;
     st.qc[v] = qc;

@@ -107,6 +107,8 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
   std::vector<float> stage((size_t)chunk * D->Kp);
   std::vector<float> inv((size_t)q.d);
   const bool tree = (q.flags & MRF_BUILD_COVERTREE) != 0;
+  if (tree && D->Kp > kTreeMaxK)
+    return fail(MRF_E_UNSUPPORTED, "mrf_dict_build: cover tree supports rows of at most %d reals", kTreeMaxK);
   std::vector<double> xnorm;  // FP64 normalised rows for the cover tree
   if (tree) xnorm.resize((size_t)q.d * K);
   for (int64_t r0 = 0; r0 < D->d_pad; r0 += chunk) {

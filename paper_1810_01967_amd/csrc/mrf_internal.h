@@ -14,6 +14,9 @@ namespace mrf {
 // scoring kernel's K chunk), reduced-precision rows to a multiple of 128
 // (the FP8 MFMA K step; also a multiple of the BF16 one).
 constexpr int kPitchF32 = 16;
+// Longest padded FP32 row the cover-tree traversal keeps in registers
+// (64 lanes x 8 float4 slices).
+constexpr int kTreeMaxK = 2048;
 constexpr int kPitchLP = 128;
 // Atom / voxel row counts are padded to multiples of 256 so every tiling of
 // the scoring kernels reads inside the allocation.
