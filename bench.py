@@ -10,8 +10,10 @@ whole projection, inputs resident in HBM:
     / top-k, split merge, [FP32 rescore,] rescaling and look-up;
   * learned: voxel packing, network proposal, cell mapping, grouping, local
     search, re-centring, exhaustive fallback, rescaling and look-up.
-Dictionary generation, upload and network training are outside the timed
-region (training time is reported).  The headline value is the learned
+Dictionary generation, upload, cover-tree build and network training are
+outside the timed region (their times are reported).  The cover-tree
+comparator (Algorithm 1, batched) is timed the same way over an eps sweep
+with its recall@1 against the exhaustive FP32 filter.  The headline value is the learned
 path when its index mismatch against the exhaustive FP32 filter is at most
 0.1 %, else the exhaustive FP32 path.
 
@@ -49,8 +51,11 @@ def parse():
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--recentre", type=int, default=2)
+    ap.add_argument("--learned-precisions", default="bf16x3,fp32",
+                    help="local-search arithmetic(s) of the learned path")
+    ap.add_argument("--tree", type=int, default=1, help="build the cover tree and run the eps sweep")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="time the FP64 oracle on a sample")
-    ap.add_argument("--cpu-sample", type=int, default=4096, help="voxels in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=32768, help="voxels in the oracle sample")
     ap.add_argument("--splits", type=int, default=0, help="atom splits (0 = library default)")
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -82,19 +87,20 @@ def main():
     n, d, K = args.n, Dd.d, 2 * Dd.L
     flops = 2.0 * n * d * K               # algorithmic: one real MAC per (voxel, atom, real dim)
 
-    def run(steps, warmup, **kw):
+    def run(steps, warmup, D_=None, **kw):
+        DD = D if D_ is None else D_
         o = {}
         for _ in range(warmup):
-            o = m.mrf_match(D, Zd, atom_splits=args.splits, want_corr=False, out=o, stats=True, **kw)
+            o = m.mrf_match(DD, Zd, atom_splits=args.splits, want_corr=False, out=o, stats=True, **kw)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         st = []
         ev0.record()
         for _ in range(steps):
-            o = m.mrf_match(D, Zd, atom_splits=args.splits, want_corr=False, out=o, stats=True, **kw)
+            o = m.mrf_match(DD, Zd, atom_splits=args.splits, want_corr=False, out=o, stats=True, **kw)
             s = o["stats"]
             st.append((s.score_ms, s.proposal_ms, s.fallback_ms, s.fallbacks, s.recentred, s.local_atoms,
-                       s.search_ms))
+                       s.search_ms, s.first_box_atoms))
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / steps
@@ -102,6 +108,7 @@ def main():
 
     ms32, st32, o32 = run(args.steps, args.warmup, precision="fp32")
     idx32 = o32["idx"].cpu().numpy()
+    answers = {"exhaustive_fp32": (idx32, o32["pd"].cpu().numpy())}   # checked against FP64 on the sample
     score_ms32 = float(st32[0])
     log(f"exhaustive fp32: {ms32:.3f} ms/step, scoring kernel {score_ms32:.3f} ms, "
         f"splits {o32['stats'].splits}")
@@ -113,6 +120,7 @@ def main():
         for p in ("bf16", "fp8"):
             vms, vst, vo = run(max(3, args.steps // 2), 1, precision=p)
             vidx = vo["idx"].cpu().numpy()
+            answers[f"exhaustive_{p}"] = (vidx, vo["pd"].cpu().numpy())
             variants[p] = {"voxels_per_s": n / (vms * 1e-3), "ms_per_step": vms,
                            "score_kernel_ms": float(vst[0]),
                            "mfma_frac": flops / (float(vst[0]) * 1e-3) / 1e12 / PEAK[p],
@@ -127,40 +135,73 @@ def main():
                              lr=1e-3, lr_min=1e-5, snr_lo=15.0, snr_hi=40.0, seed=12)
         log(f"network trained in {time.time() - t2:.1f}s ({tr['steps']} steps, loss "
             f"{tr['first_loss']:.4f} -> {tr['last_loss']:.5f})")
-        lms, lst, lo = run(args.steps, args.warmup, net=net, box_radius=3, fallback_corr=0.98,
-                           recentre=args.recentre)
-        lidx = lo["idx"].cpu().numpy()
-        mism = float(np.mean(lidx != idx32))
-        box_flops = 2.0 * K * n * 343          # the +-3 box of 7^3 atoms per voxel
-        learned = {"voxels_per_s": n / (lms * 1e-3), "ms_per_step": lms,
-                   "index_mismatch_vs_exhaustive_fp32": mism,
-                   "local_score_kernel_ms": float(lst[0]), "local_search_ms": float(lst[6]),
-                   "proposal_ms": float(lst[1]),
-                   "fallback_ms": float(lst[2]), "fallbacks_per_step": float(lst[3]),
-                   "recentred_per_step": float(lst[4]), "local_atoms_scored": float(lst[5]),
-                   "speedup_vs_exhaustive_fp32": ms32 / lms,
-                   "training": {"samples": args.train_samples, "epochs": args.train_epochs,
+        learned = {"training": {"samples": args.train_samples, "epochs": args.train_epochs,
                                 "steps": tr["steps"], "seconds": tr["ms"] / 1e3,
-                                "loss_first": tr["first_loss"], "loss_last": tr["last_loss"]},
-                   "box_flop_per_step": box_flops}
+                                "loss_first": tr["first_loss"], "loss_last": tr["last_loss"]}}
         fastest = min([ms32] + [v["ms_per_step"] for v in variants.values()
                                 if v["index_mismatch_vs_fp32"] <= 1e-3])
-        learned["speedup_vs_fastest_exhaustive_within_0.1pct"] = fastest / lms
-        log(f"learned: {lms:.3f} ms/step (local search {lst[6]:.3f}, first scoring kernel {lst[0]:.3f}, "
-            f"proposal {lst[1]:.3f}, fallback "
-            f"{lst[2]:.3f} ms, {lst[3]:.0f} fallbacks, {lst[4]:.0f} re-centred), mismatch {mism:.5f}")
+        for lp in args.learned_precisions.split(","):
+            lms, lst, lo = run(args.steps, args.warmup, net=net, box_radius=3, fallback_corr=0.98,
+                               recentre=args.recentre, precision=lp)
+            lidx = lo["idx"].cpu().numpy()
+            answers[f"learned_{lp}"] = (lidx, lo["pd"].cpu().numpy())
+            mism = float(np.mean(lidx != idx32))
+            # algorithmic work of the first local-search launch: 2 K flops per
+            # (voxel, atom of its clipped box)
+            box_flops = 2.0 * K * float(lst[7])
+            learned[lp] = {"voxels_per_s": n / (lms * 1e-3), "ms_per_step": lms,
+                           "index_mismatch_vs_exhaustive_fp32": mism,
+                           "local_score_kernel_ms": float(lst[0]), "local_search_ms": float(lst[6]),
+                           "proposal_ms": float(lst[1]),
+                           "fallback_ms": float(lst[2]), "fallbacks_per_step": float(lst[3]),
+                           "recentred_per_step": float(lst[4]), "local_atoms_scored": float(lst[5]),
+                           "first_launch_box_atoms": float(lst[7]),
+                           "speedup_vs_exhaustive_fp32": ms32 / lms,
+                           "speedup_vs_fastest_exhaustive_within_0.1pct": fastest / lms,
+                           "box_flop_first_launch": box_flops}
+            log(f"learned ({lp}): {lms:.3f} ms/step (local search {lst[6]:.3f}, first scoring kernel "
+                f"{lst[0]:.3f}, proposal {lst[1]:.3f}, fallback {lst[2]:.3f} ms, {lst[3]:.0f} fallbacks, "
+                f"{lst[4]:.0f} re-centred, {lst[7] / n:.1f} box atoms per voxel), mismatch {mism:.5f}")
 
-    use_learned = learned is not None and learned["index_mismatch_vs_exhaustive_fp32"] <= 1e-3
-    if use_learned:
-        ms, path, dt = learned["ms_per_step"], "learned-proposal+local-search (FP32 MFMA)", "f32"
-        # dominant kernel: the first local-search scoring launch; its algorithmic
-        # work is the +-3 box search of every voxel
-        kern_ms = learned["local_score_kernel_ms"]
-        achieved = learned["box_flop_per_step"] / (kern_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp32"], "traffic": None,
-                "kernel": "k_local_score (first round)",
-                "algorithmic_flop_per_launch": learned["box_flop_per_step"], "kernel_ms": kern_ms}
+    tree = None
+    if args.tree:
+        t3 = time.time()
+        DT = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims, cover_tree=True)
+        tb = time.time() - t3
+        ti = DT.tree_info()
+        log(f"cover tree built in {tb:.1f}s: {ti.unique_atoms} unique atoms, {ti.imax + 1} levels, "
+            f"{ti.entries} entries")
+        tree = {"build_seconds": tb, "levels": ti.imax + 1, "entries": int(ti.entries), "sweep": []}
+        for eps in (0.0, 0.1, 0.2, 0.4, 0.8, 1.6):
+            tms, tst, to = run(max(3, args.steps // 2), 1, D_=DT, eps=eps)
+            tidx = to["idx"].cpu().numpy()
+            answers[f"cover_tree_eps{eps}"] = (tidx, to["pd"].cpu().numpy())
+            evals = to["stats"].distance_evals / n
+            row = {"eps": eps, "voxels_per_s": n / (tms * 1e-3), "ms_per_step": tms,
+                   "search_ms": float(tst[6]), "recall_at_1_vs_exhaustive_fp32": float(np.mean(tidx == idx32)),
+                   "distance_evals_per_voxel": evals, "distance_reduction_vs_exhaustive": d / evals,
+                   "fallbacks": int(to["stats"].fallbacks)}
+            tree["sweep"].append(row)
+            log(f"cover tree eps={eps}: {tms:.3f} ms/step, recall@1 {row['recall_at_1_vs_exhaustive_fp32']:.4f}, "
+                f"{evals:.0f} distances per voxel, {row['fallbacks']} fallbacks")
+        del DT
+
+    ok = [lp for lp in args.learned_precisions.split(",")
+          if learned is not None and learned[lp]["index_mismatch_vs_exhaustive_fp32"] <= 1e-3]
+    if ok:
+        lp = min(ok, key=lambda p: learned[p]["ms_per_step"])
+        L_ = learned[lp]
+        ms = L_["ms_per_step"]
+        path = f"learned-proposal+local-search ({'split-BF16 MFMA' if lp == 'bf16x3' else 'FP32 MFMA'})"
+        dt = "bf16x3" if lp == "bf16x3" else "f32"
+        pk = PEAK["bf16"] if lp == "bf16x3" else PEAK["fp32"]
+        # dominant kernel: the first local-search scoring launch
+        kern_ms = L_["local_score_kernel_ms"]
+        achieved = L_["box_flop_first_launch"] / (kern_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": pk, "unit": "TFLOP/s",
+                "frac": achieved / pk, "traffic": None,
+                "kernel": f"k_local_score<{'split-BF16' if lp == 'bf16x3' else 'FP32'}> (first launch)",
+                "algorithmic_flop_per_launch": L_["box_flop_first_launch"], "kernel_ms": kern_ms}
     else:
         ms, path, dt = ms32, "exhaustive FP32 MFMA", "f32"
         achieved = flops / (score_ms32 * 1e-3) / 1e12
@@ -189,6 +230,8 @@ def main():
     }
     if learned is not None:
         res["learned"] = learned
+    if tree is not None:
+        res["cover_tree"] = tree
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -198,14 +241,17 @@ def main():
         torch.cuda.synchronize()
         res["copy_calibration_bytes"] = {"read": 1 << 30, "write": 1 << 30}
     if args.cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(Dd, Z, args.cpu_sample)
+        res["cpu_baseline"], res["vs_fp64_oracle_on_sample"] = cpu_baseline(Dd, Z, args.cpu_sample, answers)
     print(json.dumps(res), flush=True)
     return 0
 
 
-def cpu_baseline(Dd, Z, sample):
+def cpu_baseline(Dd, Z, sample, answers):
     """The FP64 oracle (exact matched filter, numpy) on the first `sample`
-    voxels of the same workload, on the host cores."""
+    voxels of the same workload, on the host cores; its answers also grade
+    every GPU path on that sample: strict index mismatch, mismatch outside
+    near-ties (a GPU index is accepted when its normalised correlation is
+    within 1e-6 of the maximum), and T1 / T2 / PD relative errors."""
     from oracle import mf
     try:
         import threadpoolctl
@@ -215,12 +261,28 @@ def cpu_baseline(Dd, Z, sample):
         cores = os.cpu_count() or 1
     Zs = Z[:sample].astype(np.complex128)
     t = time.time()
-    mf.exact_mf(Zs, Dd.atoms)
+    ref = mf.exact_mf(Zs, Dd.atoms)
     dt = time.time() - t
     log(f"cpu oracle: {sample} voxels in {dt:.1f}s on {cores} threads")
-    return {"value": sample / dt, "unit": "voxels/s", "cores": int(cores), "kind": "oracle",
+    base = {"value": sample / dt, "unit": "voxels/s", "cores": int(cores), "kind": "oracle",
             "sample": f"first {sample} of the 65,536 voxels, FP64 numpy oracle (exact matched "
                       f"filter over all 100,800 atoms, BLAS matrix product), {dt:.1f} s"}
+    nrm = mf.atom_norms(Dd.atoms)
+    near = int(np.sum(ref["gap"] < 1e-6))
+    grade = {"voxels": sample, "near_ties": near}
+    for name, (idx, pd) in answers.items():
+        j = idx[:sample].astype(np.int64)
+        # normalised correlation of the GPU's atom, in FP64
+        c = np.real(np.sum(Zs * np.conj(Dd.atoms[j]), axis=1)) / nrm[j] / np.maximum(ref["znorm"], 1e-300)
+        ok = c >= ref["corr"] - 1e-6
+        tr = Dd.params[ref["idx"], :2]
+        relp = np.abs(Dd.params[j, :2] - tr) / tr
+        pde = np.abs(pd[:sample].astype(np.float64) - ref["gamma"]) / np.maximum(ref["gamma"], 1e-12)
+        grade[name] = {"index_mismatch": float(np.mean(j != ref["idx"])),
+                       "index_mismatch_outside_near_ties": float(np.mean(~ok)),
+                       "t1_rel_err_max": float(relp[:, 0].max()), "t2_rel_err_max": float(relp[:, 1].max()),
+                       "pd_rel_err_median": float(np.median(pde)), "pd_rel_err_max": float(pde.max())}
+    return base, grade
 
 
 if __name__ == "__main__":

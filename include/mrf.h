@@ -109,8 +109,9 @@ typedef struct {
 mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info);
 
 /* Copy the device's normalised atoms (precision MRF_FP32: float [d][K],
- * MRF_BF16: uint16 [d][K], MRF_FP8: uint8 [d][K]) into DEVICE memory `dst`
- * (row pitch K elements), and for MRF_FP8 the per-atom scales into DEVICE
+ * MRF_BF16: uint16 [d][K], MRF_FP8: uint8 [d][K], MRF_BF16X3: uint16
+ * [d][2K] = hi K then lo K per row) into DEVICE memory `dst`
+ * (row pitch K elements, 2K for MRF_BF16X3), and for MRF_FP8 the per-atom scales into DEVICE
  * `scales` [d] (else ignored).  For checks against an independent encoder. */
 mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *dst, float *scales,
                                mrf_stream stream);
@@ -144,7 +145,15 @@ enum {
   MRF_LEARNED = 1,    /* network proposal + exact local search + exhaustive fallback */
   MRF_COVERTREE = 2   /* cover-tree (1+eps)-ANNS (Algorithm 1) on Z_v/||Z_v||, warm-started */
 };
-enum { MRF_FP32 = 0, MRF_BF16 = 1, MRF_FP8 = 2 };
+enum {
+  MRF_FP32 = 0,
+  MRF_BF16 = 1,
+  MRF_FP8 = 2,
+  MRF_BF16X3 = 3 /* split BF16: x = hi + lo (both BF16, hi = RNE(x), lo = RNE(x - hi)) and
+                    <z, a> ~ hi.hi + hi.lo + lo.hi on BF16 MFMA with FP32 accumulation;
+                    per-term error <= 3 * 2^-16 |z_k a_k|, i.e. scores within
+                    4.6e-5 ||Z|| of exact, typically ~1e-7 (close to FP32) */
+};
 enum { MRF_VOXEL_MAJOR = 0, MRF_FRAME_MAJOR = 1 };
 
 typedef struct mrf_net_s *mrf_net; /* learned proposal network (see below) */
@@ -153,7 +162,8 @@ typedef struct {
   int32_t method;      /* MRF_EXHAUSTIVE or MRF_LEARNED */
   int32_t precision;   /* exhaustive scoring: MRF_FP32 (exact argmax), MRF_BF16 or
                           MRF_FP8 (top-k by reduced-precision score, then FP32 rescore).
-                          The learned path's local search and fallback score in FP32. */
+                          MRF_LEARNED: local search in MRF_FP32 or MRF_BF16X3 (the
+                          exhaustive fallback scores in FP32). */
   int32_t topk;        /* reduced-precision candidates rescored in FP32, 1..8 (0 = 8) */
   int32_t atom_splits; /* 0 = automatic; else number of atom ranges scored in parallel */
   mrf_net net;         /* MRF_LEARNED: trained network (input length = the dictionary's K) */
@@ -183,6 +193,8 @@ typedef struct {
   float search_ms;       /* MRF_LEARNED / MRF_COVERTREE: device time of the search stage */
   int64_t distance_evals;/* MRF_COVERTREE: distances computed (self-children excluded) */
   int32_t tree_levels;   /* MRF_COVERTREE: level launches */
+  int64_t first_box_atoms; /* MRF_LEARNED: sum over the voxels of the first local-search
+                              launch of their clipped box sizes (2 K flops each) */
 } mrf_match_stats;
 
 /* Project n voxels onto cone(D).

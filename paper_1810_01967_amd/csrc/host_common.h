@@ -94,21 +94,24 @@ mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
                       int32_t *idx, float *pd, float *corr, float *params_out, mrf_match_stats *st,
                       hipStream_t s);
 mrf_status upload_tree(mrf_dict_s *D, const double *Xnorm);
+mrf_status ensure_x3(mrf_dict_s *D, hipStream_t s);
 }  // namespace mrf
 
 struct mrf_dict_s {
   int device = 0;
   int d = 0, L = 0, nparam = 0, is_complex = 0, K = 0, Kp = 0, Kq = 0;
+  int Kx = 0;  // pitch (elements) of each split-BF16 plane: K rounded up to 32
   int64_t d_pad = 0;
   uint32_t flags = 0;
   std::vector<int32_t> grid_dims;
   std::vector<double> params_host;              // d x nparam
   std::vector<std::vector<double>> axes_host;   // grid axis values (if grid_dims)
   mrf::DevBuf dhat, inv_norm, params, dbf16, dfp8, fp8_scale;
+  mrf::DevBuf dx3;                              // split-BF16 atoms [d_pad][hi Kx | lo Kx] (built on first use)
   mrf::DevBuf axes, aoff, dims;                 // device copies of the grid axes
   int64_t bytes = 0;
   // workspace (grows lazily)
-  mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j;
+  mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j, zx3;
   mrf::DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;
   mrf::DevBuf inv, h1, h2, yout, cells, best_s, best_j, list_a, list_b, list_c, keys, hist, off, cnt, rows;
   // cover tree (host copy for export, device arrays for the traversal)

@@ -114,22 +114,75 @@ void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P,
 // ---------------------------------------------------------------------------
 // local scoring
 // ---------------------------------------------------------------------------
-constexpr int LS_BA = 128, LS_BV = 64, LS_BK = 16, LS_LD = 20;
+constexpr int LS_BA = 128, LS_BV = 64;
+// FP32 operands: K chunks of 16, LDS rows of 20 floats.  Split-BF16 operands:
+// K chunks of 32 per plane, LDS rows of [hi 32 | lo 32 | pad 8] BF16.
+constexpr int LS_BK32 = 16, LS_LD32 = 20;
+constexpr int LS_BKX = 32, LS_LDX = 72;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ bool lbetter(float s1, int j1, float s0, int j0) {
   return (s1 > s0) || (s1 == s0 && j1 >= 0 && (j0 < 0 || j1 < j0));
 }
 
-__global__ __launch_bounds__(256, 2) void k_local_score(
-    const float *__restrict__ D, const float *__restrict__ Zp, int Kp,
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Split FP32 rows [rows][Kp] into BF16 planes [rows][hi Kx | lo Kx]:
+// hi = RNE(x), lo = RNE(x - hi); columns Kp..Kx-1 are zero.
+__global__ void k_split_x3(const float *__restrict__ src, int Kp, int64_t rows, int Kx,
+                           uint16_t *__restrict__ dst) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one group of 4 columns
+  const int64_t per_row = Kx / 4;
+  if (q >= rows * per_row) return;
+  const int64_t row = q / per_row;
+  const int k = (int)(q - row * per_row) * 4;
+  float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (k < Kp) x = *reinterpret_cast<const float4 *>(src + row * Kp + k);
+  const float xs[4] = {x.x, x.y, x.z, x.w};
+  uint16_t hi[4], lo[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    hi[i] = bf16_rne(xs[i]);
+    lo[i] = bf16_rne(xs[i] - __uint_as_float((uint32_t)hi[i] << 16));
+  }
+  uint16_t *d = dst + row * 2 * Kx + k;
+  *reinterpret_cast<uint2 *>(d) = make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
+  *reinterpret_cast<uint2 *>(d + Kx) =
+      make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+}
+
+void launch_split_x3(const float *src, int Kp, int64_t rows, int Kx, uint16_t *dst, hipStream_t s) {
+  if (rows <= 0) return;
+  const int64_t work = rows * (Kx / 4);
+  hipLaunchKernelGGL(k_split_x3, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, src, Kp, rows, Kx, dst);
+}
+
+// X3 = false: FP32 rows (pitch Kp), v_mfma_f32_32x32x2f32.
+// X3 = true: split-BF16 rows [hi | lo] (pitch 2 Kx), three v_mfma_f32_32x32x16_bf16
+// per step (hi.hi + hi.lo + lo.hi) accumulated in FP32.
+template <bool X3>
+__global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
+    const void *__restrict__ Dv, const void *__restrict__ Zv, int pitch,
     const int32_t *__restrict__ order, GroupBufs gb, int nkeys, const int32_t *__restrict__ cells,
     int P, GridDims g, int r, float *__restrict__ best_s, int32_t *__restrict__ best_j,
-    unsigned long long *__restrict__ work) {
-  __shared__ float As[2][LS_BA][LS_LD];
-  __shared__ float Zs[2][LS_BV][LS_LD];
+    unsigned long long *__restrict__ work, unsigned long long *__restrict__ boxsum) {
+  constexpr int BK = X3 ? LS_BKX : LS_BK32;
+  constexpr int A_ELEMS = X3 ? LS_BA * LS_LDX : LS_BA * LS_LD32;  // per buffer, in operand units
+  constexpr int Z_ELEMS = X3 ? LS_BV * LS_LDX : LS_BV * LS_LD32;
+  constexpr int EB = X3 ? 2 : 4;  // bytes per element
+  // LDS buffers: FP32 double-buffers its stages; split BF16 (twice the bytes
+  // per stage) keeps one buffer, so that more blocks share a CU
+  constexpr int NBUF = X3 ? 1 : 2;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[NBUF * (A_ELEMS + Z_ELEMS) * EB];
   __shared__ int vid[LS_BV];
   __shared__ int vlo[LS_BV][4], vhi[LS_BV][4];
   __shared__ int blo[4], bdim[4];
+  __shared__ unsigned int bmag[4];  // floor(2^32 / bdim) for the multiply-high division
   __shared__ int acoord[LS_BA][4];
   __shared__ int aj[LS_BA];
   __shared__ float red_s[4][LS_BV];
@@ -180,51 +233,117 @@ __global__ __launch_bounds__(256, 2) void k_local_score(
       if (p >= P || hi < lo) { lo = 0; hi = 0; }
       blo[p] = lo;
       bdim[p] = hi - lo + 1;
+      const unsigned long long m = 0x100000000ull / (unsigned long long)(hi - lo + 1);
+      bmag[p] = m > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned int)m;
+    }
+    if (boxsum) {
+      unsigned long long vol = 0;
+      for (int c = 0; c < LS_BV; ++c)
+        if (vid[c] >= 0) {
+          unsigned long long b = 1;
+          for (int p = 0; p < P; ++p) b *= (unsigned long long)(vhi[c][p] - vlo[c][p] + 1);
+          vol += b;
+        }
+      atomicAdd(boxsum, vol);
     }
   }
   __syncthreads();
   int64_t natoms = 1;
   for (int p = 0; p < P; ++p) natoms *= bdim[p];
   const int ntiles = (int)((natoms + LS_BA - 1) / LS_BA);
-  const int nkc = Kp / LS_BK;
+  const int nkc = pitch / BK;
   const int nq = ntiles * nkc;
   if (tid == 0 && work) atomicAdd(work, (unsigned long long)ntiles * LS_BA);
 
-  auto atom_of = [&](int64_t e, int *sub) -> int {
-    if (e >= natoms) return -1;
-    int j = 0;
-    int64_t rem = e;
-    for (int p = P - 1; p >= 0; --p) {
-      const int q = (int)(rem % bdim[p]);
-      rem /= bdim[p];
-      sub[p] = blo[p] + q;
+  // bounding-box element e -> dictionary index (-1 beyond the box) and its
+  // grid coordinates; natoms < 2^31, and floor(e * m / 2^32) with
+  // m = floor(2^32 / d) is the quotient or one less, fixed by one correction
+  struct AtomPos {
+    int j;
+    int c[4];
+  };
+  auto atom_of = [&](int e) -> AtomPos {
+    AtomPos a{-1, {0, 0, 0, 0}};
+    if ((int64_t)e >= natoms) return a;
+    unsigned int rem = (unsigned int)e;
+#pragma unroll
+    for (int p = 3; p >= 0; --p) {
+      if (p < P) {
+        const unsigned int d = (unsigned int)bdim[p];
+        unsigned int q = __umulhi(rem, bmag[p]);
+        unsigned int rr = rem - q * d;
+        if (rr >= d) {
+          ++q;
+          rr -= d;
+        }
+        a.c[p] = blo[p] + (int)rr;
+        rem = q;
+      }
     }
-    for (int p = 0; p < P; ++p) j = j * g.dims[p] + sub[p];
-    return j;
+    int j = 0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      if (p < P) j = j * g.dims[p] + a.c[p];
+    a.j = j;
+    return a;
   };
 
-  // loader mapping: atom rows lr and lr + 64, voxel row lr; 4 floats at lc
-  const int lr = tid >> 2, lc = (tid & 3) * 4;
-  int ja0 = -1, ja1 = -1;
-  const int myv = vid[lr < LS_BV ? lr : 0];
-  float4 ra0, ra1, rz;
-  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  // Loader.  FP32: atom rows lr and lr + 64, voxel row lr; 4 floats at lc.
+  // X3: part = tid & 7 picks plane (part >> 2) and 8-element slice (part & 3);
+  // atom rows tid/8 + 32 i (i < 4), voxel rows tid/8 + 32 i (i < 2).
+  const int lr = X3 ? (tid >> 3) : (tid >> 2);
+  const int lc = X3 ? ((tid & 7) >> 2) * 32 + (tid & 3) * 8 : (tid & 3) * 4;  // LDS column
+  const int gc = X3 ? ((tid & 7) >> 2) * pitch + (tid & 3) * 8 : (tid & 3) * 4;  // row offset in global
+  constexpr int NA = X3 ? 4 : 2, NZ = X3 ? 2 : 1;
+  constexpr int ASTEP = X3 ? 32 : 64, ZSTEP = 32;
+  constexpr int LD = X3 ? LS_LDX : LS_LD32;
+  constexpr int RSTRIDE = X3 ? 2 : 1;  // row pitch in units of `pitch`
+  int ja[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) ja[i] = -1;
+  int zv[NZ];
+#pragma unroll
+  for (int i = 0; i < NZ; ++i) {
+    const int row = lr + ZSTEP * i;
+    zv[i] = row < LS_BV ? vid[row] : -1;
+  }
+  uint4 ra[NA], rz[NZ];
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  typedef const __attribute__((address_space(1))) u32x4 *gptr;
+  const int64_t rowb = (int64_t)RSTRIDE * pitch * EB;  // bytes per operand row
+  const unsigned char *Db = static_cast<const unsigned char *>(Dv);
+  const unsigned char *Zb = static_cast<const unsigned char *>(Zv);
+  // rows outside the tile load row 0 (always valid) and are zeroed after the
+  // load, so every load is unconditional
   auto gload = [&](int q) {
     const int t = q / nkc, kc = q - t * nkc;
     if (kc == 0) {
-      int sub[4];
-      ja0 = atom_of((int64_t)t * LS_BA + lr, sub);
-      ja1 = atom_of((int64_t)t * LS_BA + lr + 64, sub);
+#pragma unroll
+      for (int i = 0; i < NA; ++i) ja[i] = atom_of(t * LS_BA + lr + ASTEP * i).j;
     }
-    const int k = kc * LS_BK + lc;
-    ra0 = ja0 >= 0 ? *reinterpret_cast<const float4 *>(D + (int64_t)ja0 * Kp + k) : zero4;
-    ra1 = ja1 >= 0 ? *reinterpret_cast<const float4 *>(D + (int64_t)ja1 * Kp + k) : zero4;
-    rz = (lr < LS_BV && myv >= 0) ? *reinterpret_cast<const float4 *>(Zp + (int64_t)myv * Kp + k) : zero4;
+    const int64_t kb = ((int64_t)kc * BK + gc) * EB;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const u32x4 x = *(gptr)(Db + (int64_t)max(ja[i], 0) * rowb + kb);
+      ra[i] = ja[i] >= 0 ? make_uint4(x.x, x.y, x.z, x.w) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+      const u32x4 x = *(gptr)(Zb + (int64_t)max(zv[i], 0) * rowb + kb);
+      rz[i] = zv[i] >= 0 ? make_uint4(x.x, x.y, x.z, x.w) : make_uint4(0u, 0u, 0u, 0u);
+    }
   };
   auto sstore = [&](int buf) {
-    *reinterpret_cast<float4 *>(&As[buf][lr][lc]) = ra0;
-    *reinterpret_cast<float4 *>(&As[buf][lr + 64][lc]) = ra1;
-    if (lr < LS_BV) *reinterpret_cast<float4 *>(&Zs[buf][lr][lc]) = rz;
+    unsigned char *As = smem + (size_t)buf * A_ELEMS * EB;
+    unsigned char *Zs = smem + (size_t)(NBUF * A_ELEMS + buf * Z_ELEMS) * EB;
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+      *reinterpret_cast<uint4 *>(As + ((lr + ASTEP * i) * LD + lc) * EB) = ra[i];
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+      const int row = lr + ZSTEP * i;
+      if (row < LS_BV) *reinterpret_cast<uint4 *>(Zs + (row * LD + lc) * EB) = rz[i];
+    }
   };
 
   f32x16 acc[2];
@@ -241,38 +360,60 @@ __global__ __launch_bounds__(256, 2) void k_local_score(
   }
   __syncthreads();
   for (int q = 0; q < nq; ++q) {
-    const int buf = q & 1;
+    const int buf = NBUF == 2 ? (q & 1) : 0;
     const int t = q / nkc, kc = q - t * nkc;
     if (kc == 0 && tid < LS_BA) {
-      int sub[4] = {0, 0, 0, 0};
-      aj[tid] = atom_of((int64_t)t * LS_BA + tid, sub);
-      acoord[tid][0] = sub[0];
-      acoord[tid][1] = sub[1];
-      acoord[tid][2] = sub[2];
-      acoord[tid][3] = sub[3];
+      const AtomPos a = atom_of(t * LS_BA + tid);
+      aj[tid] = a.j;
+      acoord[tid][0] = a.c[0];
+      acoord[tid][1] = a.c[1];
+      acoord[tid][2] = a.c[2];
+      acoord[tid][3] = a.c[3];
     }
     if (q + 1 < nq) gload(q + 1);
-    float af[8], zf[2][8];
-    {
-      const float *src = &As[buf][wave * 32 + l32][h * 8];
-      const float4 x0 = *reinterpret_cast<const float4 *>(src);
-      const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
-      af[0] = x0.x; af[1] = x0.y; af[2] = x0.z; af[3] = x0.w;
-      af[4] = x1.x; af[5] = x1.y; af[6] = x1.z; af[7] = x1.w;
+    if constexpr (X3) {
+      const __bf16 *As = reinterpret_cast<const __bf16 *>(smem) + (size_t)buf * A_ELEMS;
+      const __bf16 *Zs = reinterpret_cast<const __bf16 *>(smem) + (size_t)(NBUF * A_ELEMS + buf * Z_ELEMS);
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const __bf16 *ar = As + (wave * 32 + l32) * LS_LDX + ks * 16 + h * 8;
+        const bf16x8 ahi = *reinterpret_cast<const bf16x8 *>(ar);
+        const bf16x8 alo = *reinterpret_cast<const bf16x8 *>(ar + 32);
+#pragma unroll
+        for (int nv = 0; nv < 2; ++nv) {
+          const __bf16 *zr = Zs + (nv * 32 + l32) * LS_LDX + ks * 16 + h * 8;
+          const bf16x8 zhi = *reinterpret_cast<const bf16x8 *>(zr);
+          const bf16x8 zlo = *reinterpret_cast<const bf16x8 *>(zr + 32);
+          acc[nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, zhi, acc[nv], 0, 0, 0);
+          acc[nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, zlo, acc[nv], 0, 0, 0);
+          acc[nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, zhi, acc[nv], 0, 0, 0);
+        }
+      }
+    } else {
+      const float *As = reinterpret_cast<const float *>(smem) + (size_t)buf * A_ELEMS;
+      const float *Zs = reinterpret_cast<const float *>(smem) + (size_t)(NBUF * A_ELEMS + buf * Z_ELEMS);
+      float af[8], zf[2][8];
+      {
+        const float *src = As + (wave * 32 + l32) * LS_LD32 + h * 8;
+        const float4 x0 = *reinterpret_cast<const float4 *>(src);
+        const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
+        af[0] = x0.x; af[1] = x0.y; af[2] = x0.z; af[3] = x0.w;
+        af[4] = x1.x; af[5] = x1.y; af[6] = x1.z; af[7] = x1.w;
+      }
+#pragma unroll
+      for (int nv = 0; nv < 2; ++nv) {
+        const float *src = Zs + (nv * 32 + l32) * LS_LD32 + h * 8;
+        const float4 x0 = *reinterpret_cast<const float4 *>(src);
+        const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
+        zf[nv][0] = x0.x; zf[nv][1] = x0.y; zf[nv][2] = x0.z; zf[nv][3] = x0.w;
+        zf[nv][4] = x1.x; zf[nv][5] = x1.y; zf[nv][6] = x1.z; zf[nv][7] = x1.w;
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int nv = 0; nv < 2; ++nv)
+          acc[nv] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s], zf[nv][s], acc[nv], 0, 0, 0);
     }
-#pragma unroll
-    for (int nv = 0; nv < 2; ++nv) {
-      const float *src = &Zs[buf][nv * 32 + l32][h * 8];
-      const float4 x0 = *reinterpret_cast<const float4 *>(src);
-      const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
-      zf[nv][0] = x0.x; zf[nv][1] = x0.y; zf[nv][2] = x0.z; zf[nv][3] = x0.w;
-      zf[nv][4] = x1.x; zf[nv][5] = x1.y; zf[nv][6] = x1.z; zf[nv][7] = x1.w;
-    }
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-#pragma unroll
-      for (int nv = 0; nv < 2; ++nv)
-        acc[nv] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s], zf[nv][s], acc[nv], 0, 0, 0);
     if (kc == nkc - 1) {
       if (nkc == 1) __syncthreads();  // aj / acoord written this iteration
 #pragma unroll
@@ -303,7 +444,8 @@ __global__ __launch_bounds__(256, 2) void k_local_score(
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[b][i] = 0.f;
     }
-    if (q + 1 < nq) sstore(buf ^ 1);
+    if (NBUF == 1) __syncthreads();  // every wave is done with the single buffer
+    if (q + 1 < nq) sstore(NBUF == 2 ? buf ^ 1 : 0);
     __syncthreads();
   }
 #pragma unroll
@@ -336,14 +478,19 @@ __global__ __launch_bounds__(256, 2) void k_local_score(
   }
 }
 
-void launch_local_score(const float *D, const float *Zp, int Kp, const int32_t *order, int64_t cnt,
+void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const int32_t *order, int64_t cnt,
                         GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r,
-                        float *best_s, int32_t *best_j, unsigned long long *work, hipStream_t s) {
+                        float *best_s, int32_t *best_j, unsigned long long *work, unsigned long long *boxsum,
+                        hipStream_t s) {
   if (cnt <= 0) return;
   // tiles = sum_k ceil(hist[k]/64) <= ceil(cnt/64) + min(nkeys, cnt); extra blocks exit at once
   const int64_t blocks = (cnt + LS_BV - 1) / LS_BV + std::min<int64_t>(nkeys, cnt);
-  hipLaunchKernelGGL(k_local_score, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, Kp, order, gb,
-                     nkeys, cells, P, g, r, best_s, best_j, work);
+  if (x3)
+    hipLaunchKernelGGL(k_local_score<true>, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order, gb,
+                       nkeys, cells, P, g, r, best_s, best_j, work, boxsum);
+  else
+    hipLaunchKernelGGL(k_local_score<false>, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order, gb,
+                       nkeys, cells, P, g, r, best_s, best_j, work, boxsum);
 }
 
 // ---------------------------------------------------------------------------

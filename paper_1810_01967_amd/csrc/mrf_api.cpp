@@ -94,6 +94,7 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
   D->is_complex = q.is_complex;
   D->K = (int)K;
   D->Kp = (int)round_up(K, kPitchF32);
+  D->Kx = (int)round_up(K, 32);
   D->Kq = (int)round_up(K, kPitchLP);
   D->d_pad = round_up(q.d, kRowPad);
   D->flags = q.flags;
@@ -234,6 +235,12 @@ extern "C" mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *d
     HIP_TRY(hipMemcpy2DAsync(dst, (size_t)D->K, D->dfp8.p, (size_t)D->Kq, (size_t)D->K, D->d,
                              hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(scales, D->fp8_scale.p, (size_t)D->d * 4, hipMemcpyDeviceToDevice, s));
+  } else if (precision == MRF_BF16X3) {
+    TRY(ensure_x3(D, s));
+    for (int plane = 0; plane < 2; ++plane)
+      HIP_TRY(hipMemcpy2DAsync(static_cast<uint16_t *>(dst) + (size_t)plane * D->K, (size_t)D->K * 4,
+                               D->dx3.as<uint16_t>() + (size_t)plane * D->Kx, (size_t)D->Kx * 4,
+                               (size_t)D->K * 2, D->d, hipMemcpyDeviceToDevice, s));
   } else {
     return fail(MRF_E_INVAL, "mrf_dict_copy_atoms: bad precision %d", precision);
   }
@@ -256,7 +263,11 @@ mrf_status check_opts(const mrf_dict_s *D, const mrf_match_opts *o) {
     if (o->tree_capacity < 0 || o->tree_capacity > (1 << 16)) return fail(MRF_E_INVAL, "bad tree_capacity");
     if (D->Kp % 4 != 0) return fail(MRF_E_INVAL, "internal pitch");
   }
-  if (o->precision < MRF_FP32 || o->precision > MRF_FP8) return fail(MRF_E_INVAL, "bad precision %d", o->precision);
+  if (o->precision < MRF_FP32 || o->precision > MRF_BF16X3) return fail(MRF_E_INVAL, "bad precision %d", o->precision);
+  if (o->method == MRF_LEARNED && o->precision != MRF_FP32 && o->precision != MRF_BF16X3)
+    return fail(MRF_E_INVAL, "MRF_LEARNED scores in MRF_FP32 or MRF_BF16X3");
+  if (o->method == MRF_EXHAUSTIVE && o->precision == MRF_BF16X3)
+    return fail(MRF_E_UNSUPPORTED, "MRF_BF16X3 is available for the local search (MRF_LEARNED)");
   if (o->topk < 0 || o->topk > 8) return fail(MRF_E_INVAL, "topk %d not in 0..8", o->topk);
   if (o->atom_splits < 0) return fail(MRF_E_INVAL, "atom_splits must be >= 0");
   if (o->precision == MRF_BF16 && !D->dbf16.p) return fail(MRF_E_UNSUPPORTED, "BF16 scoring needs MRF_STORE_BF16 at build");

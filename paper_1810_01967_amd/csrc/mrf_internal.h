@@ -161,10 +161,15 @@ int coarse_key_count(const GridDims &g, int P, int shift);
 void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P, int shift,
                   const GridDims &g, int32_t *keys, GroupBufs gb, int32_t *out, hipStream_t s);
 // Local search over the grouped list: one block per tile of <= 64 voxels of
-// one coarse key.
-void launch_local_score(const float *D, const float *Zp, int Kp, const int32_t *order, int64_t cnt,
+// one coarse key.  x3 = false: FP32 rows of pitch `pitch`; x3 = true:
+// split-BF16 rows [hi pitch | lo pitch].
+void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const int32_t *order, int64_t cnt,
                         GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r,
-                        float *best_s, int32_t *best_j, unsigned long long *work, hipStream_t s);
+                        float *best_s, int32_t *best_j, unsigned long long *work, unsigned long long *boxsum,
+                        hipStream_t s);
+// FP32 rows [rows][Kp] -> split-BF16 rows [rows][hi Kx | lo Kx] (hi = RNE(x),
+// lo = RNE(x - hi), zero beyond Kp).
+void launch_split_x3(const float *src, int Kp, int64_t rows, int Kx, uint16_t *dst, hipStream_t s);
 void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
                  const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s);
 void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,

@@ -438,6 +438,15 @@ mrf_status check_learned(const mrf_dict_s *D, const mrf_match_opts *o, bool need
   return MRF_OK;
 }
 
+mrf_status ensure_x3(mrf_dict_s *D, hipStream_t s) {
+  if (D->dx3.p) return MRF_OK;
+  TRY(grow(D->dx3, (size_t)D->d_pad * 2 * D->Kx * 2));
+  launch_split_x3(D->dhat.as<float>(), D->Kp, D->d_pad, D->Kx, D->dx3.as<uint16_t>(), s);
+  LAUNCH_CHECK("split atoms");
+  D->bytes += (int64_t)D->d_pad * 2 * D->Kx * 2;
+  return MRF_OK;
+}
+
 mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
                          int32_t *idx, float *pd, float *corr, float *params_out, int32_t *cells_in,
                          int32_t *fallback_out, mrf_match_stats *st, hipStream_t s) {
@@ -502,16 +511,26 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   gb.off = gb.hist + nkeys;
   gb.cursor = gb.off + nkeys;
   gb.toff = gb.cursor + nkeys;
-  unsigned long long *work = D->counters.as<unsigned long long>() + 2;
-  launch_zero(work, 8, s);
+  unsigned long long *work = D->counters.as<unsigned long long>() + 2;  // [0] scored rows, [1] first-launch boxes
+  launch_zero(work, 16, s);
   // round 0: every voxel, grouped by coarse proposal cell
   int32_t *la = D->list_a.as<int32_t>(), *lb = D->list_b.as<int32_t>(), *lc = D->list_c.as<int32_t>();
   launch_iota(la, n, s);
+  const bool x3 = o->precision == MRF_BF16X3;
+  if (x3) TRY(ensure_x3(D, s));
   if (st) HIP_TRY(hipEventRecord(ev.a, s));
+  if (x3) {
+    TRY(grow(D->zx3, (size_t)n * 2 * D->Kx * 2));
+    launch_split_x3(D->zp.as<float>(), D->Kp, n, D->Kx, D->zx3.as<uint16_t>(), s);
+    LAUNCH_CHECK("split voxels");
+  }
+  const void *Dop = x3 ? D->dx3.p : D->dhat.p;
+  const void *Zop = x3 ? D->zx3.p : D->zp.p;
+  const int pitch = x3 ? D->Kx : D->Kp;
   launch_group(la, n, cells, P, shift, g, D->keys.as<int32_t>(), gb, lb, s);
   if (st) HIP_TRY(hipEventRecord(e_ls0, s));
-  launch_local_score(D->dhat.as<float>(), D->zp.as<float>(), D->Kp, lb, n, gb, nkeys, cells, P, g, r,
-                     D->best_s.as<float>(), D->best_j.as<int32_t>(), work, s);
+  launch_local_score(Dop, Zop, pitch, x3, lb, n, gb, nkeys, cells, P, g, r, D->best_s.as<float>(),
+                     D->best_j.as<int32_t>(), work, work + 1, s);
   if (st) HIP_TRY(hipEventRecord(e_ls1, s));
   LAUNCH_CHECK("local search");
   int64_t cnt = n;
@@ -532,8 +551,8 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     if (cnt == 0) break;
     int32_t *sorted = (prev == lb) ? la : lb;
     launch_group(lc, cnt, cells, P, shift, g, D->keys.as<int32_t>(), gb, sorted, s);
-    launch_local_score(D->dhat.as<float>(), D->zp.as<float>(), D->Kp, sorted, cnt, gb, nkeys, cells, P,
-                       g, r, D->best_s.as<float>(), D->best_j.as<int32_t>(), work, s);
+    launch_local_score(Dop, Zop, pitch, x3, sorted, cnt, gb, nkeys, cells, P, g, r, D->best_s.as<float>(),
+                       D->best_j.as<int32_t>(), work, nullptr, s);
     LAUNCH_CHECK("local search (re-centre)");
     prev = sorted;
   }
@@ -582,12 +601,13 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
                       D->gamma.as<float>(), s);
   LAUNCH_CHECK("merge");
   if (st) {
-    unsigned long long wk = 0;
-    HIP_TRY(hipMemcpyAsync(&wk, work, 8, hipMemcpyDeviceToHost, s));
+    unsigned long long wk[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(wk, work, 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     st->fallbacks = nfb;
     st->recentred = recentred;
-    st->local_atoms = (int64_t)wk;
+    st->local_atoms = (int64_t)wk[0];
+    st->first_box_atoms = (int64_t)wk[1];
     HIP_TRY(hipEventElapsedTime(&st->search_ms, ev.a, ev.b));
     HIP_TRY(hipEventElapsedTime(&st->score_ms, e_ls0, e_ls1));
     HIP_TRY(hipEventElapsedTime(&st->fallback_ms, ev.c, ev.d));
@@ -606,6 +626,8 @@ extern "C" mrf_status mrf_match_local(mrf_dict D, const mrf_match_opts *opts, in
   last_error().clear();
   if (!D || !opts) return fail(MRF_E_INVAL, "mrf_match_local: null dictionary or options");
   TRY(check_learned(D, opts, false));
+  if (opts->precision != MRF_FP32 && opts->precision != MRF_BF16X3)
+    return fail(MRF_E_INVAL, "mrf_match_local: precision must be MRF_FP32 or MRF_BF16X3");
   if (n < 0) return fail(MRF_E_INVAL, "mrf_match_local: n < 0");
   if (n > 0 && (!Z || !idx || !cells)) return fail(MRF_E_INVAL, "mrf_match_local: null Z, cells or idx");
   if (z_layout != MRF_VOXEL_MAJOR && z_layout != MRF_FRAME_MAJOR)

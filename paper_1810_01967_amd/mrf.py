@@ -20,9 +20,9 @@ MRF_E_INVAL, MRF_E_NOMEM, MRF_E_HIP, MRF_E_UNSUPPORTED, MRF_E_NUMERIC, MRF_E_NOC
 MRF_STORE_BF16, MRF_STORE_FP8, MRF_BUILD_COVERTREE = 2, 4, 8
 MRF_F64, MRF_F32 = 0, 1
 MRF_EXHAUSTIVE, MRF_LEARNED, MRF_COVERTREE = 0, 1, 2
-MRF_FP32, MRF_BF16, MRF_FP8 = 0, 1, 2
+MRF_FP32, MRF_BF16, MRF_FP8, MRF_BF16X3 = 0, 1, 2, 3
 MRF_VOXEL_MAJOR, MRF_FRAME_MAJOR = 0, 1
-PRECISION = {"fp32": MRF_FP32, "bf16": MRF_BF16, "fp8": MRF_FP8}
+PRECISION = {"fp32": MRF_FP32, "bf16": MRF_BF16, "fp8": MRF_FP8, "bf16x3": MRF_BF16X3}
 
 EXPORTS = ["mrf_last_error", "mrf_version", "mrf_dict_build", "mrf_dict_destroy", "mrf_dict_query",
            "mrf_dict_copy_atoms", "mrf_dict_tree_info", "mrf_dict_tree_export", "mrf_match", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
@@ -69,7 +69,8 @@ class MatchStats(ctypes.Structure):
                 ("fallbacks", ctypes.c_int64), ("recentred", ctypes.c_int64),
                 ("local_atoms", ctypes.c_int64), ("proposal_ms", ctypes.c_float),
                 ("fallback_ms", ctypes.c_float), ("search_ms", ctypes.c_float),
-                ("distance_evals", ctypes.c_int64), ("tree_levels", ctypes.c_int32)]
+                ("distance_evals", ctypes.c_int64), ("tree_levels", ctypes.c_int32),
+                ("first_box_atoms", ctypes.c_int64)]
 
 
 class TreeInfo(ctypes.Structure):
@@ -285,8 +286,8 @@ def mrf_dict_copy_atoms(D: Dictionary, precision="fp32", stream=None):
     torch = _torch()
     inf = D.info()
     p = PRECISION[precision]
-    dtype = {MRF_FP32: torch.float32, MRF_BF16: torch.int16, MRF_FP8: torch.uint8}[p]
-    out = torch.empty((inf.d, inf.K), dtype=dtype, device="cuda")
+    dtype = {MRF_FP32: torch.float32, MRF_BF16: torch.int16, MRF_FP8: torch.uint8, MRF_BF16X3: torch.int16}[p]
+    out = torch.empty((inf.d, 2 * inf.K if p == MRF_BF16X3 else inf.K), dtype=dtype, device="cuda")
     scales = torch.empty(inf.d, dtype=torch.float32, device="cuda") if p == MRF_FP8 else None
     _check(lib().mrf_dict_copy_atoms(D.handle, p, _dev(out), _dev(scales), _stream(stream)))
     return (out, scales) if p == MRF_FP8 else out
@@ -347,7 +348,7 @@ def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp
 
 def mrf_match_local(D: Dictionary, Z, cells, layout="voxel", slice_voxels=None, box_radius=3,
                     fallback_corr=0.98, recentre=0, warm_idx=None, want_X=False, want_params=False,
-                    stats=False, stream=None):
+                    stats=False, stream=None, precision="fp32"):
     """Local matched filter around given proposal cells (int32 CUDA tensor
     [n][nparam], modified in place by re-centring)."""
     torch = _torch()
@@ -365,7 +366,7 @@ def mrf_match_local(D: Dictionary, Z, cells, layout="voxel", slice_voxels=None, 
         o["X"] = torch.empty_like(Z)
     if want_params:
         o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
-    opts = match_opts("fp32", 8, 0, None, box_radius, fallback_corr, recentre, None, 0)
+    opts = match_opts(precision, 8, 0, None, box_radius, fallback_corr, recentre, None, 0)
     st = MatchStats() if stats else None
     _check(lib().mrf_match_local(D.handle, ctypes.byref(opts), n, _dev(Z, torch.complex64), zl, sv,
                                  _dev(cells, torch.int32), _dev(warm_idx, torch.int32), _dev(o["idx"]), _dev(o["pd"]), _dev(o["corr"]),

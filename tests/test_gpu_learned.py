@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from gpu_helpers import banner, c64, dev, host
-from oracle import local, mf, mlp
+from oracle import quant, local, mf, mlp
 from synth import grids, rng, workloads
 
 pytestmark = pytest.mark.gpu
@@ -124,12 +124,35 @@ def test_net_forward_gradients_adam_vs_oracle(m, I, H, P, B):
         np.testing.assert_allclose(new[k], ref_new[k], rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("recentre", [0, 2])
-def test_local_search_vs_oracle(m, small_dict, recentre):
+def test_split_bf16_planes_bit_exact(m, small_dict):
+    """The split-BF16 atom planes: hi = RNE_bf16(x), lo = RNE_bf16(x - hi) of
+    the FP32 normalised atoms, bit for bit against the oracle's encoder."""
+    banner("split-BF16 atom planes vs oracle encoder")
+    Dd = small_dict
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    K = D.info().K
+    a32 = host(m.mrf_dict_copy_atoms(D, "fp32")).astype(np.float32)
+    x3 = host(m.mrf_dict_copy_atoms(D, "bf16x3")).view(np.uint16)
+    hi = quant.bf16_round(a32)
+    lo = quant.bf16_round((a32 - hi).astype(np.float32))
+    bits = lambda x: (x.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    assert np.all((hi.view(np.uint32) & 0xFFFF) == 0) and np.all((lo.view(np.uint32) & 0xFFFF) == 0)
+    np.testing.assert_array_equal(x3[:, :K], bits(hi))
+    np.testing.assert_array_equal(x3[:, K:], bits(lo))
+    # the split carries 16 significant bits: |x - hi - lo| <= 2^-16 |x|
+    r = np.abs(a32.astype(np.float64) - hi - lo)
+    assert np.all(r <= 2.0 ** -16 * np.abs(a32) + 1e-45)
+
+
+@pytest.mark.parametrize("recentre,precision", [(0, "fp32"), (2, "fp32"), (0, "bf16x3"), (2, "bf16x3")])
+def test_local_search_vs_oracle(m, small_dict, recentre, precision):
     """Proposal cells from the test (the generating atom's cell moved by up to
     +-4 per parameter): the GPU local search, re-centring and fallback
-    against the oracle on the same cells."""
-    banner(f"local search vs oracle recentre={recentre}")
+    against the oracle on the same cells.  A differing index must be a
+    near-tie: its FP64 normalised correlation within the arithmetic's error
+    bound of the box maximum (FP32: 1e-5; split BF16: 3 * 2^-16 per product,
+    summed, 4.6e-5)."""
+    banner(f"local search vs oracle recentre={recentre} precision={precision}")
     Dd = small_dict
     D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
     n = 1500
@@ -140,7 +163,7 @@ def test_local_search_vs_oracle(m, small_dict, recentre):
     cells = np.clip(sub + shift, 0, np.array(Dd.grid_dims) - 1).astype(np.int32)
     Z[5] = 0.0  # a zero voxel
     out = m.mrf_match_local(D, dev(Z), dev(cells), box_radius=3, fallback_corr=0.98,
-                            recentre=recentre, stats=True)
+                            recentre=recentre, stats=True, precision=precision)
     ref = local.local_match(Z.astype(np.complex128), Dd.atoms, Dd.grid_dims, cells, r=3,
                             threshold=0.98, recentre=recentre)
     gidx = host(out["idx"]).astype(np.int64)
@@ -150,9 +173,19 @@ def test_local_search_vs_oracle(m, small_dict, recentre):
     diff = (gidx != ref["idx"]) & nz
     print(f"recentre={recentre}: fallbacks gpu {fb.sum()} oracle {ref['fallback'][nz].sum()}, "
           f"index differences {diff.sum()}, recentred {out['stats'].recentred}")
-    # differences may only come from FP32-vs-FP64 near-ties (inside a box or
-    # at the fallback threshold)
+    # differences may only come from near-ties (inside a box or at the
+    # fallback threshold)
     assert diff.sum() <= max(2, n // 500)
+    tol = 1e-5 if precision == "fp32" else 4.6e-5
+    Zc = Z.astype(np.complex128)
+    nrm = np.linalg.norm(Dd.atoms, axis=1)
+    zn = np.linalg.norm(Zc, axis=1)
+    for v in np.flatnonzero(diff):
+        if fb[v] or ref["fallback"][v]:
+            continue  # a threshold near-tie: one side fell back
+        cg = np.real(np.vdot(Dd.atoms[gidx[v]], Zc[v])) / nrm[gidx[v]] / zn[v]
+        cr = np.real(np.vdot(Dd.atoms[ref["idx"][v]], Zc[v])) / nrm[ref["idx"][v]] / zn[v]
+        assert cg >= cr - tol, (v, cg, cr)
     np.testing.assert_array_equal(fb[nz] & ~diff[nz], ref["fallback"][nz] & ~diff[nz])
     assert gidx[5] == 0 and host(out["pd"])[5] == 0.0
 
