@@ -256,6 +256,12 @@ mrf_status mrf_net_set_standardisation(mrf_net net, const float *mean, const flo
 mrf_status mrf_net_get_standardisation(mrf_net net, float *mean, float *stdv, int32_t *log_mask);
 /* Y = net(X): X DEVICE [B][in_dim], Y DEVICE [B][nout] (standardised). */
 mrf_status mrf_net_forward(mrf_net net, const float *X, int64_t B, float *Y, mrf_stream stream);
+/* The inference form MRF_LEARNED uses for its proposal (hidden width 256,
+ * in_dim a multiple of 8, else MRF_E_UNSUPPORTED): X, W1 and W2 rounded to
+ * BF16 (nearest, ties to even), products accumulated in FP32, the first
+ * hidden layer rounded to BF16 after its GELU, the second kept in FP32, the
+ * output layer in FP32.  Same arguments as mrf_net_forward. */
+mrf_status mrf_net_forward_bf16(mrf_net net, const float *X, int64_t B, float *Y, mrf_stream stream);
 /* Mean-squared loss against T (DEVICE [B][nout]) and its gradients (kept in
  * the net; mrf_net_get_grads reads them).  loss (HOST, may be NULL) forces a
  * stream synchronisation. */

@@ -45,6 +45,22 @@ def forward(params, X):
     return y, (X, a1, h1, a2, h2)
 
 
+def forward_bf16(params, X, round_hidden=True):
+    """Inference form with BF16 operands: X, W1 and W2 rounded to the nearest
+    BF16 (ties to even); a BF16 x BF16 product is exact, sums are taken in
+    FP64 here; h1 is rounded to BF16 after its GELU (round_hidden), h2 and
+    the output layer stay in full precision (W3, b1, b2, b3 unrounded)."""
+    from oracle.quant import bf16_round
+    r = lambda a: bf16_round(np.asarray(a, dtype=np.float32)).astype(np.float64)
+    a1 = r(X) @ r(params["W1"]).T + params["b1"]
+    h1 = gelu(a1)
+    if round_hidden:
+        h1 = r(h1)
+    a2 = h1 @ r(params["W2"]).T + params["b2"]
+    h2 = gelu(a2)
+    return h2 @ np.asarray(params["W3"], dtype=np.float64).T + params["b3"]
+
+
 def loss_and_grads(params, X, T):
     """MSE loss (mean over B*P) and its gradients w.r.t. every parameter."""
     y, (X, a1, h1, a2, h2) = forward(params, X)

@@ -95,6 +95,9 @@ mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
                       hipStream_t s);
 mrf_status upload_tree(mrf_dict_s *D, const double *Xnorm);
 mrf_status ensure_x3(mrf_dict_s *D, hipStream_t s);
+bool net_bf16_ok(const mrf_net_s *net, int64_t K, int64_t ldx);
+mrf_status net_forward_bf16(mrf_net_s *net, const float *X, int64_t ldx, int64_t K, int64_t B,
+                            const float *rowscale, float *Y, uint16_t *h1, hipStream_t s);
 }  // namespace mrf
 
 struct mrf_dict_s {
@@ -138,6 +141,7 @@ struct mrf_net_s {
   int64_t t = 0;      // Adam step count
   // per-batch workspace
   mrf::DevBuf a1, hb1, a2, hb2, y, dy, da, db, X, T, red, scal;
+  mrf::DevBuf wb;     // BF16 copies of W1 [H][round_up(I, 32)] and W2 [H][H] for inference
   double *host_scal = nullptr;
   ~mrf_net_s() {
     if (host_scal) (void)hipHostFree(host_scal);

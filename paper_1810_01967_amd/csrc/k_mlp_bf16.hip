@@ -1,0 +1,198 @@
+// BF16 inference of the proposal network on gfx950 (v_mfma_f32_32x32x16_bf16,
+// FP32 accumulation), for hidden width 256:
+//   layer 1: h1 = GELU(x W1^T + b1), x = rowscale * X rounded to BF16, W1 in
+//            BF16; h1 is written in BF16;
+//   layer 2: h2 = GELU(h1 W2^T + b2) kept in FP32 and the output layer
+//            y = h2 W3^T + b3 (FP32 W3) fused into the same block.
+// A block computes 64 rows x all 256 hidden units: four waves, each 64 rows x
+// 64 units (2 x 2 tiles of 32 x 32), K staged through LDS in chunks of 32.
+#include <cmath>
+
+#include "mrf_internal.h"
+
+namespace mrf {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int MB_M = 64;    // rows per block
+constexpr int MB_H = 256;   // hidden units (= block columns)
+constexpr int MB_BK = 32;   // K per stage
+constexpr int MB_LD = 40;   // LDS row pitch in BF16 (32 + 8 pad)
+constexpr int MB_HLD = 260; // LDS row pitch of the FP32 h2 tile
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu_exact(float a) { return 0.5f * a * (1.f + erff(a * 0.70710678118654752f)); }
+
+// FP32 [rows][cols] (leading dimension lds) -> BF16 [rows][ldd], zero beyond cols.
+__global__ void k_to_bf16(const float *__restrict__ src, int rows, int cols, int64_t lds,
+                          uint16_t *__restrict__ dst, int ldd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * ldd) return;
+  const int64_t r = i / ldd;
+  const int c = (int)(i - r * ldd);
+  dst[i] = c < cols ? to_bf16(src[r * lds + c]) : (uint16_t)0;
+}
+
+void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t *dst, int ldd, hipStream_t s) {
+  const int64_t n = (int64_t)rows * ldd;
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, rows, cols, lds, dst, ldd);
+}
+
+// LAYER1 = true: A = FP32 rows X (pitch ldx, K valid columns, K % 8 == 0,
+// ldx % 4 == 0) times rowscale, W = W1 BF16 [256][Kx]; writes H1 BF16 [B][256].
+// LAYER1 = false: A = H1 BF16 [B][256], W = W2 BF16 [256][256]; writes Y [B][P].
+template <bool LAYER1>
+__global__ __launch_bounds__(256, 2) void k_mlp_bf16(int64_t B, const float *__restrict__ X, int64_t ldx, int K,
+                                                     int Kx, const float *__restrict__ rowscale,
+                                                     const uint16_t *__restrict__ H1in,
+                                                     const uint16_t *__restrict__ W, const float *__restrict__ bias,
+                                                     uint16_t *__restrict__ H1out, const float *__restrict__ W3,
+                                                     const float *__restrict__ b3, int P, float *__restrict__ Y) {
+  constexpr int STAGE = (MB_M + MB_H) * MB_LD;  // BF16 elements per stage
+  constexpr int SMEM = LAYER1 ? 2 * STAGE * 2 : (MB_M * MB_HLD * 4 > 2 * STAGE * 2 ? MB_M * MB_HLD * 4 : 2 * STAGE * 2);
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int64_t m0 = (int64_t)blockIdx.x * MB_M;
+  const int nk = (LAYER1 ? Kx : MB_H) / MB_BK;
+  const int ldw = LAYER1 ? Kx : MB_H;
+
+  // loader: thread t covers row t/4 (A) and rows t/4 + 64 i (W), 8 elements at (t & 3) * 8
+  const int lr = tid >> 2, lc = (tid & 3) * 8;
+  const int64_t arow = m0 + lr;
+  const bool avalid = arow < B;
+  const float sc = (LAYER1 && avalid) ? (rowscale ? rowscale[arow] : 1.f) : 0.f;
+  uint4 ra, rw[4];
+  auto gload = [&](int kc) {
+    const int k = kc * MB_BK + lc;
+    if constexpr (LAYER1) {
+      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (avalid && k < K) {
+        const float4 x0 = *reinterpret_cast<const float4 *>(X + arow * ldx + k);
+        const float4 x1 = *reinterpret_cast<const float4 *>(X + arow * ldx + k + 4);
+        v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
+        v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+      }
+      uint32_t p[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        p[i] = (uint32_t)to_bf16(v[2 * i] * sc) | ((uint32_t)to_bf16(v[2 * i + 1] * sc) << 16);
+      ra = make_uint4(p[0], p[1], p[2], p[3]);
+    } else {
+      ra = avalid ? *reinterpret_cast<const uint4 *>(H1in + arow * MB_H + k) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      rw[i] = *reinterpret_cast<const uint4 *>(W + (int64_t)(lr + 64 * i) * ldw + k);
+  };
+  auto sstore = [&](int buf) {
+    uint16_t *S = reinterpret_cast<uint16_t *>(smem) + buf * STAGE;
+    *reinterpret_cast<uint4 *>(S + lr * MB_LD + lc) = ra;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) *reinterpret_cast<uint4 *>(S + (MB_M + lr + 64 * i) * MB_LD + lc) = rw[i];
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) gload(kc + 1);
+    const __bf16 *S = reinterpret_cast<const __bf16 *>(smem) + buf * STAGE;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf16x8 a[2], w[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+        a[mi] = *reinterpret_cast<const bf16x8 *>(S + (mi * 32 + l32) * MB_LD + ks * 16 + h * 8);
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+        w[ni] = *reinterpret_cast<const bf16x8 *>(S + (MB_M + wave * 64 + ni * 32 + l32) * MB_LD + ks * 16 + h * 8);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], w[ni], acc[mi][ni], 0, 0, 0);
+    }
+    if (kc + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  // output element (row 8 (i / 4) + 4 h + (i % 4) of tile mi, unit l32 of tile ni)
+  if constexpr (LAYER1) {
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+      const int n = wave * 64 + ni * 32 + l32;
+      const float bn = bias[n];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int64_t m = m0 + mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+          if (m < B) H1out[m * MB_H + n] = to_bf16(gelu_exact(acc[mi][ni][i] + bn));
+        }
+    }
+  } else {
+    float *Hs = reinterpret_cast<float *>(smem);
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+      const int n = wave * 64 + ni * 32 + l32;
+      const float bn = bias[n];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          Hs[(mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3)) * MB_HLD + n] = gelu_exact(acc[mi][ni][i] + bn);
+    }
+    __syncthreads();
+    // y[m][p]: thread t sums units [64 (t & 3), +64) of row t / 4 in a fixed
+    // order, then the four partial sums are added in a fixed order
+    const int row = tid >> 2, part = tid & 3;
+    float yp[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) yp[p] = 0.f;
+    for (int c = 0; c < 64; ++c) {
+      const int n = part * 64 + c;
+      const float hv = Hs[row * MB_HLD + n];
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p < P) yp[p] = fmaf(hv, W3[p * MB_H + n], yp[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const float q1 = __shfl_down(yp[p], 1, 64);
+      const float q2 = __shfl_down(yp[p], 2, 64);
+      const float q3 = __shfl_down(yp[p], 3, 64);
+      yp[p] = ((yp[p] + q1) + q2) + q3;
+    }
+    const int64_t m = m0 + row;
+    if (part == 0 && m < B)
+      for (int p = 0; p < P; ++p) Y[m * P + p] = yp[p] + b3[p];
+  }
+}
+
+void launch_mlp_bf16(int64_t B, const float *X, int64_t ldx, int K, int Kx, const float *rowscale,
+                     const uint16_t *W1b, const float *b1, uint16_t *H1, const uint16_t *W2b, const float *b2,
+                     const float *W3, const float *b3, int P, float *Y, hipStream_t s) {
+  if (B <= 0) return;
+  const unsigned blocks = (unsigned)((B + MB_M - 1) / MB_M);
+  hipLaunchKernelGGL(k_mlp_bf16<true>, dim3(blocks), dim3(256), 0, s, B, X, ldx, K, Kx, rowscale, nullptr, W1b, b1,
+                     H1, nullptr, nullptr, P, nullptr);
+  hipLaunchKernelGGL(k_mlp_bf16<false>, dim3(blocks), dim3(256), 0, s, B, nullptr, (int64_t)0, MB_H, MB_H, nullptr,
+                     H1, W2b, b2, nullptr, W3, b3, P, Y);
+}
+
+}  // namespace mrf

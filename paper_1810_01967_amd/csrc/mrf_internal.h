@@ -167,6 +167,12 @@ void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const
                         GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r,
                         float *best_s, int32_t *best_j, unsigned long long *work, unsigned long long *boxsum,
                         hipStream_t s);
+// BF16 inference of a hidden-256 network (layer 1 writes BF16 H1 [B][256],
+// layer 2 fuses the output layer into Y [B][P]).
+void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t *dst, int ldd, hipStream_t s);
+void launch_mlp_bf16(int64_t B, const float *X, int64_t ldx, int K, int Kx, const float *rowscale,
+                     const uint16_t *W1b, const float *b1, uint16_t *H1, const uint16_t *W2b, const float *b2,
+                     const float *W3, const float *b3, int P, float *Y, hipStream_t s);
 // FP32 rows [rows][Kp] -> split-BF16 rows [rows][hi Kx | lo Kx] (hi = RNE(x),
 // lo = RNE(x - hi), zero beyond Kp).
 void launch_split_x3(const float *src, int Kp, int64_t rows, int Kx, uint16_t *dst, hipStream_t s);

@@ -291,6 +291,44 @@ extern "C" mrf_status mrf_net_forward(mrf_net net, const float *X, int64_t B, fl
   return net_forward_rows(net, X, net->I, B, nullptr, Y, net->hb1.as<float>(), net->hb2.as<float>(), s);
 }
 
+namespace mrf {
+
+bool net_bf16_ok(const mrf_net_s *net, int64_t K, int64_t ldx) {
+  return net->H == 256 && net->P <= 8 && K % 8 == 0 && ldx % 4 == 0 && K <= round_up(net->I, 32);
+}
+
+// X: [B][ldx] FP32 with K readable columns (columns >= I meet zero weights).
+mrf_status net_forward_bf16(mrf_net_s *net, const float *X, int64_t ldx, int64_t K, int64_t B,
+                            const float *rowscale, float *Y, uint16_t *h1, hipStream_t s) {
+  const int H = net->H, I = net->I;
+  const int Kx = (int)round_up(I, 32);
+  TRY(grow(net->wb, ((size_t)H * Kx + (size_t)H * H) * 2));
+  const float *w = net->w.as<float>();
+  uint16_t *w1b = net->wb.as<uint16_t>(), *w2b = w1b + (size_t)H * Kx;
+  launch_to_bf16(w + net->oW1, H, I, I, w1b, Kx, s);
+  launch_to_bf16(w + net->oW2, H, H, H, w2b, H, s);
+  launch_mlp_bf16(B, X, ldx, (int)K, Kx, rowscale, w1b, w + net->ob1, h1, w2b, w + net->ob2, w + net->oW3,
+                  w + net->ob3, net->P, Y, s);
+  LAUNCH_CHECK("net forward (bf16)");
+  return MRF_OK;
+}
+
+}  // namespace mrf
+
+extern "C" mrf_status mrf_net_forward_bf16(mrf_net net, const float *X, int64_t B, float *Y,
+                                           mrf_stream stream) {
+  last_error().clear();
+  TRY(check_net(net));
+  if (B < 0 || B > (1 << 30)) return fail(MRF_E_INVAL, "mrf_net_forward_bf16: bad B");
+  if (!net_bf16_ok(net, net->I, net->I))
+    return fail(MRF_E_UNSUPPORTED, "mrf_net_forward_bf16: needs hidden width 256 and in_dim a multiple of 8");
+  if (B == 0) return MRF_OK;
+  if (!X || !Y) return fail(MRF_E_INVAL, "mrf_net_forward_bf16: null X or Y");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TRY(net_ws(net, B, false));
+  return net_forward_bf16(net, X, net->I, net->I, B, nullptr, Y, net->hb1.as<uint16_t>(), s);
+}
+
 extern "C" mrf_status mrf_net_loss_grad(mrf_net net, const float *X, const float *T, int64_t B,
                                         double *loss, mrf_stream stream) {
   last_error().clear();
@@ -496,8 +534,12 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     TRY(grow(D->yout, (size_t)n * P * 4));
     if (st) HIP_TRY(hipEventRecord(e_prop0, s));
     launch_inv_norm(D->znorm.as<float>(), n, D->inv.as<float>(), s);
-    TRY(net_forward_rows(net, D->zp.as<float>(), D->Kp, n, D->inv.as<float>(), D->yout.as<float>(),
-                         D->h1.as<float>(), D->h2.as<float>(), s));
+    if (net_bf16_ok(net, D->Kp, D->Kp))
+      TRY(net_forward_bf16(net, D->zp.as<float>(), D->Kp, D->Kp, n, D->inv.as<float>(), D->yout.as<float>(),
+                           D->h1.as<uint16_t>(), s));
+    else
+      TRY(net_forward_rows(net, D->zp.as<float>(), D->Kp, n, D->inv.as<float>(), D->yout.as<float>(),
+                           D->h1.as<float>(), D->h2.as<float>(), s));
     launch_cells(D->yout.as<float>(), n, P, dmean(net), dstdv(net), dlogm(net), D->axes.as<float>(),
                  D->aoff.as<int>(), D->dims.as<int>(), cells, s);
     LAUNCH_CHECK("cells");

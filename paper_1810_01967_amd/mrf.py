@@ -28,6 +28,7 @@ EXPORTS = ["mrf_last_error", "mrf_version", "mrf_dict_build", "mrf_dict_destroy"
            "mrf_dict_copy_atoms", "mrf_dict_tree_info", "mrf_dict_tree_export", "mrf_match", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
            "mrf_net_size", "mrf_net_set_params", "mrf_net_get_params", "mrf_net_get_grads",
            "mrf_net_set_standardisation", "mrf_net_get_standardisation", "mrf_net_forward",
+           "mrf_net_forward_bf16",
            "mrf_net_loss_grad", "mrf_net_adam", "mrf_net_noisy_batch", "mrf_net_train",
            "mrf_op_forward", "mrf_op_adjoint", "mrf_ipg_step", "mrf_ipg_solve", "mrf_quantize_rows"]
 
@@ -156,6 +157,7 @@ def lib():
         L.mrf_net_set_standardisation.argtypes = [vp, vp, vp, vp]
         L.mrf_net_get_standardisation.argtypes = [vp, vp, vp, vp]
         L.mrf_net_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.mrf_net_forward_bf16.argtypes = [vp, vp, i64, vp, vp]
         L.mrf_net_loss_grad.argtypes = [vp, vp, vp, i64, ctypes.POINTER(ctypes.c_double), vp]
         L.mrf_net_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
         L.mrf_net_noisy_batch.argtypes = [vp, vp, ctypes.c_uint64, i64, i64, ctypes.c_float,
@@ -442,11 +444,13 @@ class Net:
             pass
 
 
-def mrf_net_forward(net: Net, X, stream=None):
+def mrf_net_forward(net: Net, X, stream=None, bf16=False):
+    """Y = net(X) in FP32, or (bf16=True) in the BF16 inference form the
+    learned match uses for its proposal."""
     torch = _torch()
     Y = torch.empty((X.shape[0], net.nout), dtype=torch.float32, device="cuda")
-    torch = _torch()
-    _check(lib().mrf_net_forward(net.handle, _dev(X, torch.float32), X.shape[0], _dev(Y), _stream(stream)))
+    fn = lib().mrf_net_forward_bf16 if bf16 else lib().mrf_net_forward
+    _check(fn(net.handle, _dev(X, torch.float32), X.shape[0], _dev(Y), _stream(stream)))
     return Y
 
 

@@ -40,6 +40,21 @@ def test_library_exports_every_declared_symbol(m):
     assert set(m.mrf.EXPORTS) == set(_declared())
 
 
+def test_binding_declares_every_argument(m):
+    """Every entry point the binding calls has ctypes argtypes whose count
+    matches the header: without them ctypes passes a Python int as a 32-bit
+    C int, which silently truncates 64-bit device pointers and sizes."""
+    text = open(HEADER).read()
+    L = m.lib()
+    for name, params in re.findall(r"^\s*(?:mrf_status|const char \*)\s*(mrf_\w+)\s*\(([^;]*?)\);", text, re.M | re.S):
+        nparam = 0 if params.strip() in ("", "void") else params.count(",") + 1
+        at = getattr(L, name).argtypes
+        if nparam == 0:
+            continue
+        assert at is not None, f"{name}: no argtypes"
+        assert len(at) == nparam, f"{name}: {len(at)} argtypes, header has {nparam} parameters"
+
+
 def test_struct_layout_matches_header(m, tmp_path):
     """Compile the header with the host C compiler and compare sizeof/offsetof
     with the ctypes mirrors of the binding."""

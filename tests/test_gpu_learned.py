@@ -124,6 +124,35 @@ def test_net_forward_gradients_adam_vs_oracle(m, I, H, P, B):
         np.testing.assert_allclose(new[k], ref_new[k], rtol=1e-5, atol=1e-6)
 
 
+@pytest.mark.parametrize("I,B", [(120, 777), (1000, 300)])
+def test_net_forward_bf16_vs_oracle(m, I, B):
+    """The BF16 inference form against the oracle's: FP32 accumulation of
+    exact BF16 products differs from FP64 sums by ~1e-6, which can move a
+    hidden value across a BF16 rounding boundary; each such move shifts y by
+    at most half a BF16 spacing times the layer gains.  So: nearly every
+    output within 1e-4, all within the bound of every hidden entry moving."""
+    banner(f"network forward BF16 inference I={I} B={B}")
+    H, P = 256, 3
+    net = m.Net(I, P, hidden=H, seed=3)
+    flat = _random_params(net, 5)
+    net.set_params(flat)
+    prm = {k: v.astype(np.float64) for k, v in net.unpack(flat).items()}
+    X = (rng.normal(6, "x", B * I).reshape(B, I) / np.sqrt(I)).astype(np.float32)
+    Y = host(m.mrf_net_forward(net, dev(X), bf16=True)).astype(np.float64)
+    Yr = mlp.forward_bf16(prm, X.astype(np.float64))
+    _, (_, a1, h1, _, _) = mlp.forward(prm, X.astype(np.float64))
+    gain = (np.abs(prm["W3"]) @ np.abs(prm["W2"])).max(axis=0)
+    bound = 1.13 * 2.0 ** -7 * (np.abs(h1) @ gain) + 1e-4   # one BF16 spacing per hidden entry
+    err = np.abs(Y - Yr)
+    print(f"max |y - y_oracle| {err.max():.2e}; fraction > 1e-4: {np.mean(err > 1e-4):.4f}")
+    assert np.all(err <= bound[:, None])
+    assert np.mean(err > 1e-4) <= 0.01
+    # and the FP32 forward stays the training-precision reference
+    Y32 = host(m.mrf_net_forward(net, dev(X))).astype(np.float64)
+    Yf, _ = mlp.forward(prm, X.astype(np.float64))
+    np.testing.assert_allclose(Y32, Yf, rtol=1e-4, atol=1e-5)
+
+
 def test_split_bf16_planes_bit_exact(m, small_dict):
     """The split-BF16 atom planes: hi = RNE_bf16(x), lo = RNE_bf16(x - hi) of
     the FP32 normalised atoms, bit for bit against the oracle's encoder."""

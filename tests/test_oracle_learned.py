@@ -30,6 +30,26 @@ def test_gelu_identities():
     assert np.max(np.abs(num - mlp.gelu_grad(a))) < 1e-8
 
 
+def test_bf16_forward_special_cases():
+    """The BF16 inference form: on operands already representable in BF16
+    (multiples of 2^-6 of magnitude < 2) and without the hidden rounding it
+    is the FP64 forward; the hidden rounding moves each h1 entry by at most
+    half a BF16 spacing (2^-9 relative), so y moves by at most
+    2^-9 sum_n |h1_n| max_p sum_j |W3_pj| |W2_jn| * max gelu' (< 1.13)."""
+    I, H, P, B = 16, 8, 3, 11
+    q = lambda a: np.round(np.asarray(a) * 64) / 64
+    prm = _params(7, I, H, P)
+    prm["W1"], prm["W2"] = q(np.clip(prm["W1"], -1.9, 1.9)), q(np.clip(prm["W2"], -1.9, 1.9))
+    X = q(np.clip(rng.normal(7, "x", B * I).reshape(B, I), -1.9, 1.9))
+    y, (_, a1, h1, _, _) = mlp.forward(prm, X)
+    np.testing.assert_allclose(mlp.forward_bf16(prm, X, round_hidden=False), y, rtol=0, atol=1e-13)
+    yb = mlp.forward_bf16(prm, X)
+    gain = (np.abs(prm["W3"]) @ np.abs(prm["W2"])).max(axis=0)        # [H]
+    bound = 1.13 * 2.0 ** -9 * (np.abs(h1) @ gain) + 1e-13
+    assert np.all(np.abs(yb - y) <= bound[:, None])
+    assert np.any(np.abs(yb - y) > 1e-12)                               # the rounding acts
+
+
 def test_mlp_gradients_central_differences():
     I, H, P, B = 7, 5, 3, 6
     prm = _params(1, I, H, P)
