@@ -110,7 +110,7 @@ struct mrf_dict_s {
   std::vector<double> params_host;              // d x nparam
   std::vector<std::vector<double>> axes_host;   // grid axis values (if grid_dims)
   mrf::DevBuf dhat, inv_norm, params, dbf16, dfp8, fp8_scale;
-  mrf::DevBuf dx3;                              // split-BF16 atoms [d_pad][hi Kx | lo Kx] (built on first use)
+  mrf::DevBuf dx3;                              // split-BF16 atoms [d_pad][Kx/32][hi 32 | lo 32] (built on first use)
   mrf::DevBuf axes, aoff, dims;                 // device copies of the grid axes
   int64_t bytes = 0;
   // workspace (grows lazily)

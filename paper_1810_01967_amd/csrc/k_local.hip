@@ -132,8 +132,9 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
   return (uint16_t)(u >> 16);
 }
 
-// Split FP32 rows [rows][Kp] into BF16 planes [rows][hi Kx | lo Kx]:
-// hi = RNE(x), lo = RNE(x - hi); columns Kp..Kx-1 are zero.
+// Split FP32 rows [rows][Kp] into BF16 hi = RNE(x), lo = RNE(x - hi),
+// stored per row as Kx/32 chunks [hi 32 | lo 32] (one 128-byte line per
+// chunk, so a K-step of 32 reads whole lines); columns Kp..Kx-1 are zero.
 __global__ void k_split_x3(const float *__restrict__ src, int Kp, int64_t rows, int Kx,
                            uint16_t *__restrict__ dst) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one group of 4 columns
@@ -150,10 +151,28 @@ __global__ void k_split_x3(const float *__restrict__ src, int Kp, int64_t rows, 
     hi[i] = bf16_rne(xs[i]);
     lo[i] = bf16_rne(xs[i] - __uint_as_float((uint32_t)hi[i] << 16));
   }
-  uint16_t *d = dst + row * 2 * Kx + k;
+  uint16_t *d = dst + row * 2 * Kx + (k >> 5) * 64 + (k & 31);
   *reinterpret_cast<uint2 *>(d) = make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
-  *reinterpret_cast<uint2 *>(d + Kx) =
+  *reinterpret_cast<uint2 *>(d + 32) =
       make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+}
+
+// Chunked split rows -> [rows][hi K | lo K] (for export).
+__global__ void k_unsplit_x3(const uint16_t *__restrict__ src, int64_t rows, int Kx, int K,
+                             uint16_t *__restrict__ dst) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= rows * K) return;
+  const int64_t row = q / K;
+  const int k = (int)(q - row * K);
+  const uint16_t *r = src + row * 2 * Kx + (k >> 5) * 64 + (k & 31);
+  dst[row * 2 * K + k] = r[0];
+  dst[row * 2 * K + K + k] = r[32];
+}
+
+void launch_unsplit_x3(const uint16_t *src, int64_t rows, int Kx, int K, uint16_t *dst, hipStream_t s) {
+  if (rows <= 0) return;
+  const int64_t work = rows * K;
+  hipLaunchKernelGGL(k_unsplit_x3, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, src, rows, Kx, K, dst);
 }
 
 void launch_split_x3(const float *src, int Kp, int64_t rows, int Kx, uint16_t *dst, hipStream_t s) {
@@ -163,7 +182,7 @@ void launch_split_x3(const float *src, int Kp, int64_t rows, int Kx, uint16_t *d
 }
 
 // X3 = false: FP32 rows (pitch Kp), v_mfma_f32_32x32x2f32.
-// X3 = true: split-BF16 rows [hi | lo] (pitch 2 Kx), three v_mfma_f32_32x32x16_bf16
+// X3 = true: split-BF16 rows of chunks [hi 32 | lo 32] (pitch 2 Kx), three v_mfma_f32_32x32x16_bf16
 // per step (hi.hi + hi.lo + lo.hi) accumulated in FP32.
 template <bool X3>
 __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
@@ -293,7 +312,8 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
   // atom rows tid/8 + 32 i (i < 4), voxel rows tid/8 + 32 i (i < 2).
   const int lr = X3 ? (tid >> 3) : (tid >> 2);
   const int lc = X3 ? ((tid & 7) >> 2) * 32 + (tid & 3) * 8 : (tid & 3) * 4;  // LDS column
-  const int gc = X3 ? ((tid & 7) >> 2) * pitch + (tid & 3) * 8 : (tid & 3) * 4;  // row offset in global
+  const int gc = X3 ? ((tid & 7) >> 2) * 32 + (tid & 3) * 8 : (tid & 3) * 4;  // offset in the stage's chunk
+  constexpr int KSTRIDE = X3 ? 2 * LS_BKX : LS_BK32;                            // row elements per stage
   constexpr int NA = X3 ? 4 : 2, NZ = X3 ? 2 : 1;
   constexpr int ASTEP = X3 ? 32 : 64, ZSTEP = 32;
   constexpr int LD = X3 ? LS_LDX : LS_LD32;
@@ -321,7 +341,7 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
 #pragma unroll
       for (int i = 0; i < NA; ++i) ja[i] = atom_of(t * LS_BA + lr + ASTEP * i).j;
     }
-    const int64_t kb = ((int64_t)kc * BK + gc) * EB;
+    const int64_t kb = ((int64_t)kc * KSTRIDE + gc) * EB;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const u32x4 x = *(gptr)(Db + (int64_t)max(ja[i], 0) * rowb + kb);

@@ -237,10 +237,8 @@ extern "C" mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *d
     HIP_TRY(hipMemcpyAsync(scales, D->fp8_scale.p, (size_t)D->d * 4, hipMemcpyDeviceToDevice, s));
   } else if (precision == MRF_BF16X3) {
     TRY(ensure_x3(D, s));
-    for (int plane = 0; plane < 2; ++plane)
-      HIP_TRY(hipMemcpy2DAsync(static_cast<uint16_t *>(dst) + (size_t)plane * D->K, (size_t)D->K * 4,
-                               D->dx3.as<uint16_t>() + (size_t)plane * D->Kx, (size_t)D->Kx * 4,
-                               (size_t)D->K * 2, D->d, hipMemcpyDeviceToDevice, s));
+    launch_unsplit_x3(D->dx3.as<uint16_t>(), D->d, D->Kx, D->K, static_cast<uint16_t *>(dst), s);
+    LAUNCH_CHECK("copy split atoms");
   } else {
     return fail(MRF_E_INVAL, "mrf_dict_copy_atoms: bad precision %d", precision);
   }

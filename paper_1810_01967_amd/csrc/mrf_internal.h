@@ -162,7 +162,7 @@ void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P,
                   const GridDims &g, int32_t *keys, GroupBufs gb, int32_t *out, hipStream_t s);
 // Local search over the grouped list: one block per tile of <= 64 voxels of
 // one coarse key.  x3 = false: FP32 rows of pitch `pitch`; x3 = true:
-// split-BF16 rows [hi pitch | lo pitch].
+// split-BF16 rows of pitch/32 chunks [hi 32 | lo 32].
 void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const int32_t *order, int64_t cnt,
                         GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r,
                         float *best_s, int32_t *best_j, unsigned long long *work, unsigned long long *boxsum,
@@ -173,9 +173,10 @@ void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t 
 void launch_mlp_bf16(int64_t B, const float *X, int64_t ldx, int K, int Kx, const float *rowscale,
                      const uint16_t *W1b, const float *b1, uint16_t *H1, const uint16_t *W2b, const float *b2,
                      const float *W3, const float *b3, int P, float *Y, hipStream_t s);
-// FP32 rows [rows][Kp] -> split-BF16 rows [rows][hi Kx | lo Kx] (hi = RNE(x),
-// lo = RNE(x - hi), zero beyond Kp).
+// FP32 rows [rows][Kp] -> split-BF16 rows of Kx/32 chunks [hi 32 | lo 32]
+// (hi = RNE(x), lo = RNE(x - hi), zero beyond Kp); and back to [rows][hi K | lo K].
 void launch_split_x3(const float *src, int Kp, int64_t rows, int Kx, uint16_t *dst, hipStream_t s);
+void launch_unsplit_x3(const uint16_t *src, int64_t rows, int Kx, int K, uint16_t *dst, hipStream_t s);
 void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
                  const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s);
 void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,
