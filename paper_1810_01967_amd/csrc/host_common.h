@@ -116,7 +116,7 @@ struct mrf_dict_s {
   // workspace (grows lazily)
   mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j, zx3;
   mrf::DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;
-  mrf::DevBuf inv, h1, h2, yout, cells, best_s, best_j, list_a, list_b, list_c, keys, hist, off, cnt, rows;
+  mrf::DevBuf inv, h1, h2, yout, cells, best_s, best_j, bestkey, list_a, list_b, list_c, keys, hist, off, cnt, rows;
   // cover tree (host copy for export, device arrays for the traversal)
   bool has_tree = false;
   mrf::HostTree tree;

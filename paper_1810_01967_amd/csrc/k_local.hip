@@ -181,6 +181,44 @@ void launch_split_x3(const float *src, int Kp, int64_t rows, int Kx, uint16_t *d
   hipLaunchKernelGGL(k_split_x3, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, src, Kp, rows, Kx, dst);
 }
 
+// (score, atom) -> 64-bit key ordered as (score, then lower atom): the score
+// bits mapped to an order-preserving unsigned integer in the high half,
+// 0xFFFFFFFF - atom in the low half.  Key 0 means no candidate.
+__device__ __forceinline__ unsigned long long pack_best(float s, int j) {
+  unsigned int u = __float_as_uint(s);
+  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned int)j);
+}
+
+// mode 0: keys of the listed voxels (all voxels if list is null) set to 0;
+// mode 1: keys unpacked into best_s / best_j (-inf / -1 for key 0).
+__global__ void k_best_keys(const int32_t *__restrict__ list, int64_t cnt, unsigned long long *__restrict__ keys,
+                            float *__restrict__ best_s, int32_t *__restrict__ best_j, int mode) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int64_t v = list ? list[i] : i;
+  if (mode == 0) {
+    keys[v] = 0ull;
+    return;
+  }
+  const unsigned long long k = keys[v];
+  if (k == 0ull) {
+    best_s[v] = -INFINITY;
+    best_j[v] = -1;
+    return;
+  }
+  const unsigned int u = (unsigned int)(k >> 32);
+  best_s[v] = __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+  best_j[v] = (int32_t)(0xFFFFFFFFu - (unsigned int)(k & 0xFFFFFFFFull));
+}
+
+void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys, float *best_s, int32_t *best_j,
+                      int mode, hipStream_t s) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_best_keys, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, keys, best_s,
+                     best_j, mode);
+}
+
 // X3 = false: FP32 rows (pitch Kp), v_mfma_f32_32x32x2f32.
 // X3 = true: split-BF16 rows of chunks [hi 32 | lo 32] (pitch 2 Kx), three v_mfma_f32_32x32x16_bf16
 // per step (hi.hi + hi.lo + lo.hi) accumulated in FP32.
@@ -188,7 +226,7 @@ template <bool X3>
 __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
     const void *__restrict__ Dv, const void *__restrict__ Zv, int pitch,
     const int32_t *__restrict__ order, GroupBufs gb, int nkeys, const int32_t *__restrict__ cells,
-    int P, GridDims g, int r, float *__restrict__ best_s, int32_t *__restrict__ best_j,
+    int P, GridDims g, int r, int max_at, unsigned long long *__restrict__ bestkey,
     unsigned long long *__restrict__ work, unsigned long long *__restrict__ boxsum) {
   constexpr int BK = X3 ? LS_BKX : LS_BK32;
   constexpr int A_ELEMS = X3 ? LS_BA * LS_LDX : LS_BA * LS_LD32;  // per buffer, in operand units
@@ -209,9 +247,11 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
-  // tile T belongs to the key k with toff[k] <= T < toff[k+1]; its voxels are
-  // sorted positions off[k] + 64 (T - toff[k]) .. (at most 64, never beyond key k)
-  const unsigned int T = blockIdx.x;
+  // block = (voxel tile T, atom tile `at` of the tile's bounding box).  Tile T
+  // belongs to the key k with toff[k] <= T < toff[k+1]; its voxels are sorted
+  // positions off[k] + 64 (T - toff[k]) .. (at most 64, never beyond key k)
+  const unsigned int T = blockIdx.x / (unsigned)max_at;
+  const int at = (int)(blockIdx.x - T * (unsigned)max_at);
   if (T >= gb.toff[nkeys]) return;
   int lo_k = 0, hi_k = nkeys - 1;
   while (lo_k < hi_k) {
@@ -229,7 +269,9 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
     for (int p = 0; p < 4; ++p) {
       int lo = 1, hi = 0;  // empty box for padding lanes / unused parameters
       if (v >= 0 && p < P) {
-        const int c = cells[(int64_t)v * P + p];
+        // cells clamped to the grid (as the coarse key is): the tile's
+        // bounding box then spans at most 2^shift + 2r cells per parameter
+        const int c = min(max(cells[(int64_t)v * P + p], 0), g.dims[p] - 1);
         lo = max(c - r, 0);
         hi = min(c + r, g.dims[p] - 1);
       } else if (p >= P) {
@@ -255,7 +297,7 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
       const unsigned long long m = 0x100000000ull / (unsigned long long)(hi - lo + 1);
       bmag[p] = m > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned int)m;
     }
-    if (boxsum) {
+    if (boxsum && at == 0) {
       unsigned long long vol = 0;
       for (int c = 0; c < LS_BV; ++c)
         if (vid[c] >= 0) {
@@ -270,9 +312,10 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
   int64_t natoms = 1;
   for (int p = 0; p < P; ++p) natoms *= bdim[p];
   const int ntiles = (int)((natoms + LS_BA - 1) / LS_BA);
+  if (at >= ntiles) return;  // block-uniform: bdim is shared
   const int nkc = pitch / BK;
-  const int nq = ntiles * nkc;
-  if (tid == 0 && work) atomicAdd(work, (unsigned long long)ntiles * LS_BA);
+  const int nq = nkc;
+  if (tid == 0 && work) atomicAdd(work, (unsigned long long)LS_BA);
 
   // bounding-box element e -> dictionary index (-1 beyond the box) and its
   // grid coordinates; natoms < 2^31, and floor(e * m / 2^32) with
@@ -336,7 +379,7 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
   // rows outside the tile load row 0 (always valid) and are zeroed after the
   // load, so every load is unconditional
   auto gload = [&](int q) {
-    const int t = q / nkc, kc = q - t * nkc;
+    const int t = at, kc = q;
     if (kc == 0) {
 #pragma unroll
       for (int i = 0; i < NA; ++i) ja[i] = atom_of(t * LS_BA + lr + ASTEP * i).j;
@@ -381,7 +424,7 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
   __syncthreads();
   for (int q = 0; q < nq; ++q) {
     const int buf = NBUF == 2 ? (q & 1) : 0;
-    const int t = q / nkc, kc = q - t * nkc;
+    const int t = at, kc = q;
     if (kc == 0 && tid < LS_BA) {
       const AtomPos a = atom_of(t * LS_BA + tid);
       aj[tid] = a.j;
@@ -491,26 +534,29 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
         bj = red_j[w][tid];
       }
     const int v = vid[tid];
-    if (v >= 0) {
-      best_s[v] = bs;
-      best_j[v] = bj;
-    }
+    if (v >= 0 && bj >= 0) atomicMax(&bestkey[v], pack_best(bs, bj));
   }
 }
 
 void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const int32_t *order, int64_t cnt,
-                        GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r,
-                        float *best_s, int32_t *best_j, unsigned long long *work, unsigned long long *boxsum,
+                        GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r, int shift,
+                        unsigned long long *bestkey, unsigned long long *work, unsigned long long *boxsum,
                         hipStream_t s) {
   if (cnt <= 0) return;
-  // tiles = sum_k ceil(hist[k]/64) <= ceil(cnt/64) + min(nkeys, cnt); extra blocks exit at once
-  const int64_t blocks = (cnt + LS_BV - 1) / LS_BV + std::min<int64_t>(nkeys, cnt);
+  // tiles = sum_k ceil(hist[k]/64) <= ceil(cnt/64) + min(nkeys, cnt); a tile's
+  // voxels share a coarse cell, so its bounding box spans at most 2^shift + 2r
+  // cells per parameter: max_at atom tiles; surplus blocks exit at once
+  const int64_t tiles = (cnt + LS_BV - 1) / LS_BV + std::min<int64_t>(nkeys, cnt);
+  int64_t bbox = 1;
+  for (int p = 0; p < P; ++p) bbox *= std::min<int64_t>(g.dims[p], (1 << shift) + 2 * (int64_t)r);
+  const int max_at = (int)((bbox + LS_BA - 1) / LS_BA);
+  const int64_t blocks = tiles * max_at;
   if (x3)
     hipLaunchKernelGGL(k_local_score<true>, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order, gb,
-                       nkeys, cells, P, g, r, best_s, best_j, work, boxsum);
+                       nkeys, cells, P, g, r, max_at, bestkey, work, boxsum);
   else
     hipLaunchKernelGGL(k_local_score<false>, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order, gb,
-                       nkeys, cells, P, g, r, best_s, best_j, work, boxsum);
+                       nkeys, cells, P, g, r, max_at, bestkey, work, boxsum);
 }
 
 // ---------------------------------------------------------------------------

@@ -163,10 +163,17 @@ void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P,
 // Local search over the grouped list: one block per tile of <= 64 voxels of
 // one coarse key.  x3 = false: FP32 rows of pitch `pitch`; x3 = true:
 // split-BF16 rows of pitch/32 chunks [hi 32 | lo 32].
+// One block per (tile, atom tile of the tile's bounding box); per-voxel
+// maxima merge into `bestkey` by atomicMax on (score, lower atom) keys (zero
+// them first, unpack after with launch_best_keys).
 void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const int32_t *order, int64_t cnt,
-                        GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r,
-                        float *best_s, int32_t *best_j, unsigned long long *work, unsigned long long *boxsum,
+                        GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r, int shift,
+                        unsigned long long *bestkey, unsigned long long *work, unsigned long long *boxsum,
                         hipStream_t s);
+// mode 0: zero the keys of the listed voxels (all if list is null); mode 1:
+// unpack them into best_s / best_j (-inf / -1 where no candidate).
+void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys, float *best_s, int32_t *best_j,
+                      int mode, hipStream_t s);
 // BF16 inference of a hidden-256 network (layer 1 writes BF16 H1 [B][256],
 // layer 2 fuses the output layer into Y [B][P]).
 void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t *dst, int ldd, hipStream_t s);

@@ -571,8 +571,11 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   const int pitch = x3 ? D->Kx : D->Kp;
   launch_group(la, n, cells, P, shift, g, D->keys.as<int32_t>(), gb, lb, s);
   if (st) HIP_TRY(hipEventRecord(e_ls0, s));
-  launch_local_score(Dop, Zop, pitch, x3, lb, n, gb, nkeys, cells, P, g, r, D->best_s.as<float>(),
-                     D->best_j.as<int32_t>(), work, work + 1, s);
+  TRY(grow(D->bestkey, (size_t)n * 8));
+  unsigned long long *bkey = D->bestkey.as<unsigned long long>();
+  launch_best_keys(nullptr, n, bkey, nullptr, nullptr, 0, s);
+  launch_local_score(Dop, Zop, pitch, x3, lb, n, gb, nkeys, cells, P, g, r, shift, bkey, work, work + 1, s);
+  launch_best_keys(nullptr, n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s);
   if (st) HIP_TRY(hipEventRecord(e_ls1, s));
   LAUNCH_CHECK("local search");
   int64_t cnt = n;
@@ -593,8 +596,9 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     if (cnt == 0) break;
     int32_t *sorted = (prev == lb) ? la : lb;
     launch_group(lc, cnt, cells, P, shift, g, D->keys.as<int32_t>(), gb, sorted, s);
-    launch_local_score(Dop, Zop, pitch, x3, sorted, cnt, gb, nkeys, cells, P, g, r, D->best_s.as<float>(),
-                       D->best_j.as<int32_t>(), work, nullptr, s);
+    launch_best_keys(sorted, cnt, bkey, nullptr, nullptr, 0, s);
+    launch_local_score(Dop, Zop, pitch, x3, sorted, cnt, gb, nkeys, cells, P, g, r, shift, bkey, work, nullptr, s);
+    launch_best_keys(sorted, cnt, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s);
     LAUNCH_CHECK("local search (re-centre)");
     prev = sorted;
   }
