@@ -4,8 +4,9 @@
 //            BF16; h1 is written in BF16;
 //   layer 2: h2 = GELU(h1 W2^T + b2) kept in FP32 and the output layer
 //            y = h2 W3^T + b3 (FP32 W3) fused into the same block.
-// A block computes 64 rows x all 256 hidden units: four waves, each 64 rows x
-// 64 units (2 x 2 tiles of 32 x 32), K staged through LDS in chunks of 32.
+// A block computes all 256 hidden units of 128 rows (layer 1, eight waves) or
+// 64 rows (layer 2, four waves); each wave owns 64 rows x 64 units (2 x 2
+// tiles of 32 x 32); K is staged through LDS in chunks of 32.
 #include <cmath>
 
 #include "mrf_internal.h"
@@ -15,7 +16,6 @@ namespace mrf {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int MB_M = 64;    // rows per block
 constexpr int MB_H = 256;   // hidden units (= block columns)
 constexpr int MB_BK = 32;   // K per stage
 constexpr int MB_LD = 40;   // LDS row pitch in BF16 (32 + 8 pad)
@@ -48,27 +48,31 @@ void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t 
 // ldx % 4 == 0) times rowscale, W = W1 BF16 [256][Kx]; writes H1 BF16 [B][256].
 // LAYER1 = false: A = H1 BF16 [B][256], W = W2 BF16 [256][256]; writes Y [B][P].
 template <bool LAYER1>
-__global__ __launch_bounds__(256, 2) void k_mlp_bf16(int64_t B, const float *__restrict__ X, int64_t ldx, int K,
+__global__ __launch_bounds__(LAYER1 ? 512 : 256, LAYER1 ? 1 : 2) void k_mlp_bf16(int64_t B, const float *__restrict__ X, int64_t ldx, int K,
                                                      int Kx, const float *__restrict__ rowscale,
                                                      const uint16_t *__restrict__ H1in,
                                                      const uint16_t *__restrict__ W, const float *__restrict__ bias,
                                                      uint16_t *__restrict__ H1out, const float *__restrict__ W3,
                                                      const float *__restrict__ b3, int P, float *__restrict__ Y) {
+  constexpr int MB_M = LAYER1 ? 128 : 64;       // rows per block
+  constexpr int NT = LAYER1 ? 512 : 256;        // threads per block
+  constexpr int NW = MB_H * 4 / NT;             // W chunks of 8 per thread per stage
   constexpr int STAGE = (MB_M + MB_H) * MB_LD;  // BF16 elements per stage
-  constexpr int SMEM = LAYER1 ? 2 * STAGE * 2 : (MB_M * MB_HLD * 4 > 2 * STAGE * 2 ? MB_M * MB_HLD * 4 : 2 * STAGE * 2);
+  constexpr int SMEM = LAYER1 ? 2 * STAGE * 2 : (64 * MB_HLD * 4 > 2 * STAGE * 2 ? 64 * MB_HLD * 4 : 2 * STAGE * 2);
   __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
+  const int wr = (wave >> 2) * 64, wn = (wave & 3) * 64;  // the wave's rows and units
   const int64_t m0 = (int64_t)blockIdx.x * MB_M;
   const int nk = (LAYER1 ? Kx : MB_H) / MB_BK;
   const int ldw = LAYER1 ? Kx : MB_H;
 
-  // loader: thread t covers row t/4 (A) and rows t/4 + 64 i (W), 8 elements at (t & 3) * 8
+  // loader: thread t covers row t/4 (A) and rows t/4 + (NT/4) i (W), 8 elements at (t & 3) * 8
   const int lr = tid >> 2, lc = (tid & 3) * 8;
   const int64_t arow = m0 + lr;
   const bool avalid = arow < B;
   const float sc = (LAYER1 && avalid) ? (rowscale ? rowscale[arow] : 1.f) : 0.f;
-  uint4 ra, rw[4];
+  uint4 ra, rw[NW];
   auto gload = [&](int kc) {
     const int k = kc * MB_BK + lc;
     if constexpr (LAYER1) {
@@ -88,14 +92,14 @@ __global__ __launch_bounds__(256, 2) void k_mlp_bf16(int64_t B, const float *__r
       ra = avalid ? *reinterpret_cast<const uint4 *>(H1in + arow * MB_H + k) : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      rw[i] = *reinterpret_cast<const uint4 *>(W + (int64_t)(lr + 64 * i) * ldw + k);
+    for (int i = 0; i < NW; ++i)
+      rw[i] = *reinterpret_cast<const uint4 *>(W + (int64_t)(lr + (NT / 4) * i) * ldw + k);
   };
   auto sstore = [&](int buf) {
     uint16_t *S = reinterpret_cast<uint16_t *>(smem) + buf * STAGE;
     *reinterpret_cast<uint4 *>(S + lr * MB_LD + lc) = ra;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) *reinterpret_cast<uint4 *>(S + (MB_M + lr + 64 * i) * MB_LD + lc) = rw[i];
+    for (int i = 0; i < NW; ++i) *reinterpret_cast<uint4 *>(S + (MB_M + lr + (NT / 4) * i) * MB_LD + lc) = rw[i];
   };
 
   f32x16 acc[2][2];
@@ -118,10 +122,10 @@ __global__ __launch_bounds__(256, 2) void k_mlp_bf16(int64_t B, const float *__r
       bf16x8 a[2], w[2];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
-        a[mi] = *reinterpret_cast<const bf16x8 *>(S + (mi * 32 + l32) * MB_LD + ks * 16 + h * 8);
+        a[mi] = *reinterpret_cast<const bf16x8 *>(S + (wr + mi * 32 + l32) * MB_LD + ks * 16 + h * 8);
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni)
-        w[ni] = *reinterpret_cast<const bf16x8 *>(S + (MB_M + wave * 64 + ni * 32 + l32) * MB_LD + ks * 16 + h * 8);
+        w[ni] = *reinterpret_cast<const bf16x8 *>(S + (MB_M + wn + ni * 32 + l32) * MB_LD + ks * 16 + h * 8);
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -135,13 +139,13 @@ __global__ __launch_bounds__(256, 2) void k_mlp_bf16(int64_t B, const float *__r
   if constexpr (LAYER1) {
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) {
-      const int n = wave * 64 + ni * 32 + l32;
+      const int n = wn + ni * 32 + l32;
       const float bn = bias[n];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          const int64_t m = m0 + mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+          const int64_t m = m0 + wr + mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
           if (m < B) H1out[m * MB_H + n] = to_bf16(gelu_exact(acc[mi][ni][i] + bn));
         }
     }
@@ -149,13 +153,13 @@ __global__ __launch_bounds__(256, 2) void k_mlp_bf16(int64_t B, const float *__r
     float *Hs = reinterpret_cast<float *>(smem);
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) {
-      const int n = wave * 64 + ni * 32 + l32;
+      const int n = wn + ni * 32 + l32;
       const float bn = bias[n];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
-          Hs[(mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3)) * MB_HLD + n] = gelu_exact(acc[mi][ni][i] + bn);
+          Hs[(wr + mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3)) * MB_HLD + n] = gelu_exact(acc[mi][ni][i] + bn);
     }
     __syncthreads();
     // y[m][p]: thread t sums units [64 (t & 3), +64) of row t / 4 in a fixed
@@ -188,11 +192,10 @@ void launch_mlp_bf16(int64_t B, const float *X, int64_t ldx, int K, int Kx, cons
                      const uint16_t *W1b, const float *b1, uint16_t *H1, const uint16_t *W2b, const float *b2,
                      const float *W3, const float *b3, int P, float *Y, hipStream_t s) {
   if (B <= 0) return;
-  const unsigned blocks = (unsigned)((B + MB_M - 1) / MB_M);
-  hipLaunchKernelGGL(k_mlp_bf16<true>, dim3(blocks), dim3(256), 0, s, B, X, ldx, K, Kx, rowscale, nullptr, W1b, b1,
-                     H1, nullptr, nullptr, P, nullptr);
-  hipLaunchKernelGGL(k_mlp_bf16<false>, dim3(blocks), dim3(256), 0, s, B, nullptr, (int64_t)0, MB_H, MB_H, nullptr,
-                     H1, W2b, b2, nullptr, W3, b3, P, Y);
+  hipLaunchKernelGGL(k_mlp_bf16<true>, dim3((unsigned)((B + 127) / 128)), dim3(512), 0, s, B, X, ldx, K, Kx,
+                     rowscale, nullptr, W1b, b1, H1, nullptr, nullptr, P, nullptr);
+  hipLaunchKernelGGL(k_mlp_bf16<false>, dim3((unsigned)((B + 63) / 64)), dim3(256), 0, s, B, nullptr, (int64_t)0,
+                     MB_H, MB_H, nullptr, H1, W2b, b2, nullptr, W3, b3, P, Y);
 }
 
 }  // namespace mrf
