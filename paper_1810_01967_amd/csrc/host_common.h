@@ -141,6 +141,7 @@ struct mrf_net_s {
   int64_t t = 0;      // Adam step count
   // per-batch workspace
   mrf::DevBuf a1, hb1, a2, hb2, y, dy, da, db, X, T, red, scal;
+  mrf::DevBuf gpart;  // split-K partial sums of the weight gradients
   mrf::DevBuf wb;     // BF16 copies of W1 [H][round_up(I, 32)] and W2 [H][H] for inference
   double *host_scal = nullptr;
   ~mrf_net_s() {

@@ -24,10 +24,13 @@ __device__ __forceinline__ float gelu_grad_f(float a) {
 // ---------------------------------------------------------------------------
 constexpr int G_T = 64, G_BK = 16, G_LD = 20;
 
+// Split K: block z of grid.z sums k in [z kchunk, (z+1) kchunk) into
+// C + z cstride (plain store; the partial sums are added by k_sum_parts).
 template <bool AK, bool BK>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *__restrict__ A,
                                               int64_t lda, const float *__restrict__ B, int64_t ldb,
-                                              float *__restrict__ C, int64_t ldc, GemmEpi epi) {
+                                              float *__restrict__ C, int64_t ldc, GemmEpi epi, int kchunk,
+                                              int64_t cstride) {
   __shared__ float As[G_T][G_LD];
   __shared__ float Bs[G_T][G_LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -37,7 +40,10 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *
   f32x16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  for (int k0 = 0; k0 < K; k0 += G_BK) {
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  C += blockIdx.z * cstride;
+  for (int k0 = kb; k0 < ke; k0 += G_BK) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = tid + 256 * q;
@@ -45,12 +51,12 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *
       if (AK) { r = i >> 4; c = i & 15; } else { c = i >> 6; r = i & 63; }
       const int gm = m0 + r, gk = k0 + c;
       float va = 0.f;
-      if (gm < M && gk < K) va = AK ? A[(int64_t)gm * lda + gk] : A[(int64_t)gk * lda + gm];
+      if (gm < M && gk < ke) va = AK ? A[(int64_t)gm * lda + gk] : A[(int64_t)gk * lda + gm];
       As[r][c] = va;
       if (BK) { r = i >> 4; c = i & 15; } else { c = i >> 6; r = i & 63; }
       const int gn = n0 + r, gk2 = k0 + c;
       float vb = 0.f;
-      if (gn < N && gk2 < K) vb = BK ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn];
+      if (gn < N && gk2 < ke) vb = BK ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn];
       Bs[r][c] = vb;
     }
     __syncthreads();
@@ -77,19 +83,49 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *
   }
 }
 
+static void gemm_dispatch(dim3 grid, int M, int N, int K, const float *A, int64_t lda, bool a_kcontig,
+                          const float *B, int64_t ldb, bool b_kcontig, float *C, int64_t ldc, const GemmEpi &epi,
+                          int kchunk, int64_t cstride, hipStream_t s) {
+  if (a_kcontig && b_kcontig)
+    hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, epi, kchunk,
+                       cstride);
+  else if (a_kcontig)
+    hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, epi, kchunk,
+                       cstride);
+  else if (b_kcontig)
+    hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, epi, kchunk,
+                       cstride);
+  else
+    hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, epi, kchunk,
+                       cstride);
+}
+
 void launch_gemm(int M, int N, int K, const float *A, int64_t lda, bool a_kcontig, const float *B,
                  int64_t ldb, bool b_kcontig, float *C, int64_t ldc, const GemmEpi &epi,
                  hipStream_t s) {
   if (M <= 0 || N <= 0) return;
   dim3 grid((unsigned)((N + G_T - 1) / G_T), (unsigned)((M + G_T - 1) / G_T));
-  if (a_kcontig && b_kcontig)
-    hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, epi);
-  else if (a_kcontig)
-    hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, epi);
-  else if (b_kcontig)
-    hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, epi);
-  else
-    hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, epi);
+  gemm_dispatch(grid, M, N, K, A, lda, a_kcontig, B, ldb, b_kcontig, C, ldc, epi, K, 0, s);
+}
+
+// out[i] = sum_z part[z][i] (z in order)
+__global__ void k_sum_parts(const float *__restrict__ part, int splits, int64_t count, float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float acc = 0.f;
+  for (int z = 0; z < splits; ++z) acc += part[z * count + i];
+  out[i] = acc;
+}
+
+void launch_gemm_splitk(int M, int N, int K, const float *A, int64_t lda, bool a_kcontig, const float *B,
+                        int64_t ldb, bool b_kcontig, float *C, int splits, float *part, hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  const int kchunk = (int)round_up((K + splits - 1) / splits, G_BK);
+  splits = (K + kchunk - 1) / kchunk;
+  dim3 grid((unsigned)((N + G_T - 1) / G_T), (unsigned)((M + G_T - 1) / G_T), (unsigned)splits);
+  const int64_t count = (int64_t)M * N;
+  gemm_dispatch(grid, M, N, K, A, lda, a_kcontig, B, ldb, b_kcontig, part, N, GemmEpi(), kchunk, count, s);
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part, splits, count, C);
 }
 
 // ---------------------------------------------------------------------------
@@ -123,17 +159,28 @@ void launch_mse(const float *y, const float *t, int64_t count, float scale, floa
   hipLaunchKernelGGL(k_mse, dim3((unsigned)b), dim3(256), 0, s, y, t, count, scale, dy, part);
 }
 
-// out[n] = sum_b x[b][n] (fixed order over b)
-__global__ void k_colsum(const float *__restrict__ x, int rows, int cols, float *__restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// out[n] = sum_b x[b][n] in a fixed order: a block of 1024 threads takes 16
+// columns; thread (g, c) sums rows g, g + 64, g + 128, ... of column c, then
+// the 64 partial sums of a column are added in order of g.
+__global__ __launch_bounds__(1024) void k_colsum(const float *__restrict__ x, int rows, int cols,
+                                                 float *__restrict__ out) {
+  __shared__ float part[64][17];
+  const int cl = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int c = blockIdx.x * 16 + cl;
   float acc = 0.f;
-  for (int r = 0; r < rows; ++r) acc += x[(int64_t)r * cols + c];
-  out[c] = acc;
+  if (c < cols)
+    for (int r = g; r < rows; r += 64) acc += x[(int64_t)r * cols + c];
+  part[g][cl] = acc;
+  __syncthreads();
+  if (threadIdx.x < 16 && c < cols) {
+    float t = 0.f;
+    for (int i = 0; i < 64; ++i) t += part[i][cl];
+    out[c] = t;
+  }
 }
 
 void launch_colsum(const float *x, int rows, int cols, float *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, x, rows, cols, out);
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((cols + 15) / 16)), dim3(1024), 0, s, x, rows, cols, out);
 }
 
 __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,

@@ -132,6 +132,10 @@ struct GemmEpi {
 void launch_gemm(int M, int N, int K, const float *A, int64_t lda, bool a_kcontig, const float *B,
                  int64_t ldb, bool b_kcontig, float *C, int64_t ldc, const GemmEpi &epi,
                  hipStream_t s);
+// C[M][N] (ldc = N) = sum_k A(m,k) B(n,k) with K split over `splits` blocks
+// whose partial sums (workspace part, splits * M * N floats) are added in order.
+void launch_gemm_splitk(int M, int N, int K, const float *A, int64_t lda, bool a_kcontig, const float *B,
+                        int64_t ldb, bool b_kcontig, float *C, int splits, float *part, hipStream_t s);
 void launch_mse(const float *y, const float *t, int64_t count, float scale, float *dy, double *part,
                 int *nblocks, hipStream_t s);
 void launch_colsum(const float *x, int rows, int cols, float *out, hipStream_t s);

@@ -127,10 +127,13 @@ mrf_status net_loss_grad(mrf_net_s *net, const float *X, const float *T, int64_t
               net->y.as<float>(), P, e3, s);
   launch_mse(net->y.as<float>(), T, B * P, (float)(2.0 / ((double)B * P)), net->dy.as<float>(),
              net->red.as<double>(), nb, s);
-  GemmEpi plain;
+  // weight gradients: long sums over the batch, split over blocks
+  const int ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(16, B / 256));
+  TRY(grow(net->gpart, (size_t)ksplit * std::max<int64_t>((int64_t)H * I, (int64_t)H * H) * 4));
+  float *gpart = net->gpart.as<float>();
   // dW3[p][h] = sum_b dy[b][p] h2[b][h]
-  launch_gemm(P, H, (int)B, net->dy.as<float>(), P, false, net->hb2.as<float>(), H, false,
-              g + net->oW3, H, plain, s);
+  launch_gemm_splitk(P, H, (int)B, net->dy.as<float>(), P, false, net->hb2.as<float>(), H, false, g + net->oW3,
+                     ksplit, gpart, s);
   launch_colsum(net->dy.as<float>(), (int)B, P, g + net->ob3, s);
   // da2 = (dy W3) * gelu'(a2)
   GemmEpi gg2;
@@ -138,8 +141,8 @@ mrf_status net_loss_grad(mrf_net_s *net, const float *X, const float *T, int64_t
   gg2.gpre = net->a2.as<float>();
   launch_gemm((int)B, H, P, net->dy.as<float>(), P, true, w + net->oW3, H, false,
               net->da.as<float>(), H, gg2, s);
-  launch_gemm(H, H, (int)B, net->da.as<float>(), H, false, net->hb1.as<float>(), H, false,
-              g + net->oW2, H, plain, s);
+  launch_gemm_splitk(H, H, (int)B, net->da.as<float>(), H, false, net->hb1.as<float>(), H, false, g + net->oW2,
+                     ksplit, gpart, s);
   launch_colsum(net->da.as<float>(), (int)B, H, g + net->ob2, s);
   // da1 = (da2 W2) * gelu'(a1)
   GemmEpi gg1;
@@ -147,7 +150,7 @@ mrf_status net_loss_grad(mrf_net_s *net, const float *X, const float *T, int64_t
   gg1.gpre = net->a1.as<float>();
   launch_gemm((int)B, H, H, net->da.as<float>(), H, true, w + net->oW2, H, false,
               net->db.as<float>(), H, gg1, s);
-  launch_gemm(H, I, (int)B, net->db.as<float>(), H, false, X, I, false, g + net->oW1, I, plain, s);
+  launch_gemm_splitk(H, I, (int)B, net->db.as<float>(), H, false, X, I, false, g + net->oW1, ksplit, gpart, s);
   launch_colsum(net->db.as<float>(), (int)B, H, g + net->ob1, s);
   LAUNCH_CHECK("net backward");
   return MRF_OK;
