@@ -250,8 +250,13 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
   // block = (voxel tile T, atom tile `at` of the tile's bounding box).  Tile T
   // belongs to the key k with toff[k] <= T < toff[k+1]; its voxels are sorted
   // positions off[k] + 64 (T - toff[k]) .. (at most 64, never beyond key k)
-  const unsigned int T = blockIdx.x / (unsigned)max_at;
-  const int at = (int)(blockIdx.x - T * (unsigned)max_at);
+  // Workgroups are dealt to the 8 XCDs round-robin (block b on XCD b % 8):
+  // block b = x + 8 j handles tile T = x + 8 (j / max_at) and atom tile
+  // j % max_at, so all atom tiles of a tile run on one XCD, one after the
+  // other, and its voxel rows stay in that XCD's L2.
+  const unsigned int xcd = blockIdx.x & 7u, jx = blockIdx.x >> 3;
+  const unsigned int T = xcd + 8u * (jx / (unsigned)max_at);
+  const int at = (int)(jx % (unsigned)max_at);
   if (T >= gb.toff[nkeys]) return;
   int lo_k = 0, hi_k = nkeys - 1;
   while (lo_k < hi_k) {
@@ -550,7 +555,7 @@ void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const
   int64_t bbox = 1;
   for (int p = 0; p < P; ++p) bbox *= std::min<int64_t>(g.dims[p], (1 << shift) + 2 * (int64_t)r);
   const int max_at = (int)((bbox + LS_BA - 1) / LS_BA);
-  const int64_t blocks = tiles * max_at;
+  const int64_t blocks = (tiles + 7) / 8 * 8 * max_at;  // tiles padded to a multiple of the 8 XCDs
   if (x3)
     hipLaunchKernelGGL(k_local_score<true>, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order, gb,
                        nkeys, cells, P, g, r, max_at, bestkey, work, boxsum);
