@@ -115,6 +115,7 @@ void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P,
 // local scoring
 // ---------------------------------------------------------------------------
 constexpr int LS_BA = 128, LS_BV = 64;
+constexpr unsigned int LS_RUN = 4;  // consecutive tiles per XCD run
 // FP32 operands: K chunks of 16, LDS rows of 20 floats.  Split-BF16 operands:
 // K chunks of 32 per plane, LDS rows of [hi 32 | lo 32 | pad 8] BF16.
 constexpr int LS_BK32 = 16, LS_LD32 = 20;
@@ -250,12 +251,15 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
   // block = (voxel tile T, atom tile `at` of the tile's bounding box).  Tile T
   // belongs to the key k with toff[k] <= T < toff[k+1]; its voxels are sorted
   // positions off[k] + 64 (T - toff[k]) .. (at most 64, never beyond key k)
-  // Workgroups are dealt to the 8 XCDs round-robin (block b on XCD b % 8):
-  // block b = x + 8 j handles tile T = x + 8 (j / max_at) and atom tile
-  // j % max_at, so all atom tiles of a tile run on one XCD, one after the
-  // other, and its voxel rows stay in that XCD's L2.
+  // Workgroups are dealt to the 8 XCDs round-robin (block b on XCD b % 8).
+  // Block b = x + 8 j takes the q-th tile of XCD x, q = j / max_at, and its
+  // atom tile j % max_at; XCD x owns runs of LS_RUN consecutive tiles (runs
+  // x, x + 8, ...).  So all atom tiles of a tile run on one XCD one after the
+  // other (its voxel rows stay in that L2), and consecutive tiles there are
+  // neighbouring coarse cells whose bounding boxes share atom rows.
   const unsigned int xcd = blockIdx.x & 7u, jx = blockIdx.x >> 3;
-  const unsigned int T = xcd + 8u * (jx / (unsigned)max_at);
+  const unsigned int q = jx / (unsigned)max_at;
+  const unsigned int T = ((q / LS_RUN) * 8u + xcd) * LS_RUN + q % LS_RUN;
   const int at = (int)(jx % (unsigned)max_at);
   if (T >= gb.toff[nkeys]) return;
   int lo_k = 0, hi_k = nkeys - 1;
@@ -266,11 +270,13 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
   const int key = lo_k;
   const int64_t v0 = (int64_t)gb.off[key] + 64ll * (T - gb.toff[key]);
   const int64_t vend = (int64_t)gb.off[key] + gb.hist[key];
-  // voxels and their clipped boxes
+  // voxels and their clipped boxes (wave 0, one lane per voxel slot); the
+  // bounding box and the box volumes by wave reductions
   if (tid < LS_BV) {
     const int64_t i = v0 + tid;
     const int v = i < vend ? order[i] : -1;
     vid[tid] = v;
+    unsigned long long vol = v >= 0 ? 1ull : 0ull;
     for (int p = 0; p < 4; ++p) {
       int lo = 1, hi = 0;  // empty box for padding lanes / unused parameters
       if (v >= 0 && p < P) {
@@ -279,38 +285,32 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
         const int c = min(max(cells[(int64_t)v * P + p], 0), g.dims[p] - 1);
         lo = max(c - r, 0);
         hi = min(c + r, g.dims[p] - 1);
+        vol *= (unsigned long long)(hi - lo + 1);
       } else if (p >= P) {
         lo = 0;
         hi = 0;
       }
       vlo[tid][p] = lo;
       vhi[tid][p] = hi;
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int p = 0; p < 4; ++p) {
-      int lo = 1 << 30, hi = -1;
-      for (int c = 0; c < LS_BV; ++c)
-        if (vid[c] >= 0) {
-          lo = min(lo, vlo[c][p]);
-          hi = max(hi, vhi[c][p]);
+      int mlo = v >= 0 ? lo : (1 << 30), mhi = v >= 0 ? hi : -1;
+      for (int o = 32; o > 0; o >>= 1) {
+        mlo = min(mlo, __shfl_xor(mlo, o, 64));
+        mhi = max(mhi, __shfl_xor(mhi, o, 64));
+      }
+      if (tid == 0) {
+        if (p >= P || mhi < mlo) {
+          mlo = 0;
+          mhi = 0;
         }
-      if (p >= P || hi < lo) { lo = 0; hi = 0; }
-      blo[p] = lo;
-      bdim[p] = hi - lo + 1;
-      const unsigned long long m = 0x100000000ull / (unsigned long long)(hi - lo + 1);
-      bmag[p] = m > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned int)m;
+        blo[p] = mlo;
+        bdim[p] = mhi - mlo + 1;
+        const unsigned long long m = 0x100000000ull / (unsigned long long)(mhi - mlo + 1);
+        bmag[p] = m > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned int)m;
+      }
     }
     if (boxsum && at == 0) {
-      unsigned long long vol = 0;
-      for (int c = 0; c < LS_BV; ++c)
-        if (vid[c] >= 0) {
-          unsigned long long b = 1;
-          for (int p = 0; p < P; ++p) b *= (unsigned long long)(vhi[c][p] - vlo[c][p] + 1);
-          vol += b;
-        }
-      atomicAdd(boxsum, vol);
+      for (int o = 32; o > 0; o >>= 1) vol += __shfl_xor(vol, o, 64);
+      if (tid == 0) atomicAdd(boxsum, vol);
     }
   }
   __syncthreads();
@@ -555,7 +555,7 @@ void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const
   int64_t bbox = 1;
   for (int p = 0; p < P; ++p) bbox *= std::min<int64_t>(g.dims[p], (1 << shift) + 2 * (int64_t)r);
   const int max_at = (int)((bbox + LS_BA - 1) / LS_BA);
-  const int64_t blocks = (tiles + 7) / 8 * 8 * max_at;  // tiles padded to a multiple of the 8 XCDs
+  const int64_t blocks = (tiles + 8 * LS_RUN - 1) / (8 * LS_RUN) * (8 * LS_RUN) * max_at;  // whole runs on all XCDs
   if (x3)
     hipLaunchKernelGGL(k_local_score<true>, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order, gb,
                        nkeys, cells, P, g, r, max_at, bestkey, work, boxsum);
