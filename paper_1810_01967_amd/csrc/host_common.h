@@ -103,7 +103,7 @@ mrf_status net_forward_bf16(mrf_net_s *net, const float *X, int64_t ldx, int64_t
 struct mrf_dict_s {
   int device = 0;
   int d = 0, L = 0, nparam = 0, is_complex = 0, K = 0, Kp = 0, Kq = 0;
-  int Kx = 0;  // pitch (elements) of each split-BF16 plane: K rounded up to 32
+  int Kx = 0;  // split-BF16 row: Kx/32 chunks [hi 32 | lo 32]; K rounded up to 32
   int64_t d_pad = 0;
   uint32_t flags = 0;
   std::vector<int32_t> grid_dims;

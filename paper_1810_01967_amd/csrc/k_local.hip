@@ -117,9 +117,11 @@ void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P,
 constexpr int LS_BA = 128, LS_BV = 64;
 constexpr unsigned int LS_RUN = 4;  // consecutive tiles per XCD run
 // FP32 operands: K chunks of 16, LDS rows of 20 floats.  Split-BF16 operands:
-// K chunks of 32 per plane, LDS rows of [hi 32 | lo 32 | pad 8] BF16.
+// K stages of LS_XC chunks of 32, LDS rows of LS_XC x [hi 32 | lo 32] + pad 8 BF16.
 constexpr int LS_BK32 = 16, LS_LD32 = 20;
-constexpr int LS_BKX = 32, LS_LDX = 72;
+constexpr int LS_XC = 1;                            // 32-element chunks per stage
+constexpr int LS_BKX = 32 * LS_XC, LS_LDX = 64 * LS_XC + 8;
+static_assert(LS_BKX == kX3Stage, "split rows are padded to one stage");
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -356,14 +358,18 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
   };
 
   // Loader.  FP32: atom rows lr and lr + 64, voxel row lr; 4 floats at lc.
-  // X3: part = tid & 7 picks plane (part >> 2) and 8-element slice (part & 3);
-  // atom rows tid/8 + 32 i (i < 4), voxel rows tid/8 + 32 i (i < 2).
-  const int lr = X3 ? (tid >> 3) : (tid >> 2);
-  const int lc = X3 ? ((tid & 7) >> 2) * 32 + (tid & 3) * 8 : (tid & 3) * 4;  // LDS column
-  const int gc = X3 ? ((tid & 7) >> 2) * 32 + (tid & 3) * 8 : (tid & 3) * 4;  // offset in the stage's chunk
-  constexpr int KSTRIDE = X3 ? 2 * LS_BKX : LS_BK32;                            // row elements per stage
-  constexpr int NA = X3 ? 4 : 2, NZ = X3 ? 2 : 1;
-  constexpr int ASTEP = X3 ? 32 : 64, ZSTEP = 32;
+  // X3: a stage row is LS_XC chunks [hi 32 | lo 32] = 8 LS_XC pieces of 16 B;
+  // piece = tid % (8 LS_XC) picks the chunk (piece / 8), the plane
+  // (piece / 4 % 2) and the 8-element slice (piece % 4); atom rows
+  // tid / (8 LS_XC) + ASTEP i, voxel rows likewise.
+  constexpr int PPR = 8 * LS_XC;  // X3 pieces per stage row
+  const int piece = tid % PPR;
+  const int lr = X3 ? (tid / PPR) : (tid >> 2);
+  const int lc = X3 ? (piece >> 3) * 64 + ((piece >> 2) & 1) * 32 + (piece & 3) * 8 : (tid & 3) * 4;  // LDS column
+  const int gc = lc;                                             // offset in the stage's row segment
+  constexpr int KSTRIDE = X3 ? 2 * LS_BKX : LS_BK32;             // row elements per stage
+  constexpr int ASTEP = X3 ? 256 / PPR : 64, ZSTEP = X3 ? 256 / PPR : 32;
+  constexpr int NA = X3 ? LS_BA / ASTEP : 2, NZ = X3 ? LS_BV / ZSTEP : 1;
   constexpr int LD = X3 ? LS_LDX : LS_LD32;
   constexpr int RSTRIDE = X3 ? 2 : 1;  // row pitch in units of `pitch`
   int ja[NA];
@@ -443,13 +449,14 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
       const __bf16 *As = reinterpret_cast<const __bf16 *>(smem) + (size_t)buf * A_ELEMS;
       const __bf16 *Zs = reinterpret_cast<const __bf16 *>(smem) + (size_t)(NBUF * A_ELEMS + buf * Z_ELEMS);
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        const __bf16 *ar = As + (wave * 32 + l32) * LS_LDX + ks * 16 + h * 8;
+      for (int ks = 0; ks < 2 * LS_XC; ++ks) {
+        const int ko = (ks >> 1) * 64 + (ks & 1) * 16 + h * 8;  // hi of chunk ks/2, half ks%2
+        const __bf16 *ar = As + (wave * 32 + l32) * LS_LDX + ko;
         const bf16x8 ahi = *reinterpret_cast<const bf16x8 *>(ar);
         const bf16x8 alo = *reinterpret_cast<const bf16x8 *>(ar + 32);
 #pragma unroll
         for (int nv = 0; nv < 2; ++nv) {
-          const __bf16 *zr = Zs + (nv * 32 + l32) * LS_LDX + ks * 16 + h * 8;
+          const __bf16 *zr = Zs + (nv * 32 + l32) * LS_LDX + ko;
           const bf16x8 zhi = *reinterpret_cast<const bf16x8 *>(zr);
           const bf16x8 zlo = *reinterpret_cast<const bf16x8 *>(zr + 32);
           acc[nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, zhi, acc[nv], 0, 0, 0);

@@ -94,7 +94,7 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
   D->is_complex = q.is_complex;
   D->K = (int)K;
   D->Kp = (int)round_up(K, kPitchF32);
-  D->Kx = (int)round_up(K, 32);
+  D->Kx = (int)round_up(K, kX3Stage);
   D->Kq = (int)round_up(K, kPitchLP);
   D->d_pad = round_up(q.d, kRowPad);
   D->flags = q.flags;

@@ -17,6 +17,9 @@ constexpr int kPitchF32 = 16;
 // Longest padded FP32 row the cover-tree traversal keeps in registers
 // (64 lanes x 8 float4 slices).
 constexpr int kTreeMaxK = 2048;
+// Elements per plane of one split-BF16 local-search stage; split rows are
+// padded to a multiple of it.
+constexpr int kX3Stage = 32;
 constexpr int kPitchLP = 128;
 // Atom / voxel row counts are padded to multiples of 256 so every tiling of
 // the scoring kernels reads inside the allocation.
