@@ -41,8 +41,13 @@ def _sub(j, dims):
     return list(reversed(out))
 
 
-def local_match(Z, atoms, dims, cells, r=3, threshold=0.98, recentre=0):
-    """Returns dict(idx, score, corr, fallback [bool], rounds [int]) per voxel."""
+def local_match(Z, atoms, dims, cells, r=3, threshold=0.98, recentre=0, warm=None):
+    """Returns dict(idx, score, corr, fallback [bool], rounds [int]) per voxel.
+
+    warm (optional, [n] atom indices): the previous iterate's atom competes
+    with the box's best under the same order (higher score, then lower
+    index) before the fallback test, so the projection is never worse than
+    the warm start (the non-expansive safeguard of the inexact projection)."""
     Z = np.asarray(Z).astype(np.complex128)
     n = Z.shape[0]
     nrm = mf.atom_norms(atoms)
@@ -65,6 +70,11 @@ def local_match(Z, atoms, dims, cells, r=3, threshold=0.98, recentre=0):
                 break
             cell = sub
             rounds[v] = rd + 1
+        if warm is not None and znorm[v] > 0 and 0 <= int(warm[v]) < atoms.shape[0]:
+            w = int(warm[v])
+            cw = float(mf.correlations(Z[v:v + 1], atoms[w:w + 1], nrm[w:w + 1])[0, 0])
+            if cw > score[v] or (cw == score[v] and w < idx[v]):
+                idx[v], score[v] = w, cw
     corr = np.where(znorm > 0, score / np.where(znorm > 0, znorm, 1.0), 0.0)
     fb = corr < threshold
     if np.any(fb):

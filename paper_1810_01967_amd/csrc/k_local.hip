@@ -571,6 +571,43 @@ void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const
                        nkeys, cells, P, g, r, max_at, bestkey, work, boxsum);
 }
 
+// Non-expansive safeguard of the inexact projection: the previous iterate's
+// atom (the warm index) competes with the local search's best under the same
+// order (score, then lower index).  One wave per voxel, FP32 dot product in a
+// fixed order.
+__global__ __launch_bounds__(256) void k_warm_best(const int32_t *__restrict__ warm, int64_t n, int d,
+                                                   const float *__restrict__ Zp, const float *__restrict__ Dhat,
+                                                   int Kp, const float *__restrict__ znorm,
+                                                   float *__restrict__ best_s, int32_t *__restrict__ best_j) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n) return;
+  const int w = warm[v];
+  if (w < 0 || w >= d || !(znorm[v] > 0.f)) return;
+  const float4 *z = reinterpret_cast<const float4 *>(Zp + v * Kp);
+  const float4 *a = reinterpret_cast<const float4 *>(Dhat + (int64_t)w * Kp);
+  float acc = 0.f;
+  for (int k = lane; k < Kp / 4; k += 64) {
+    const float4 x = z[k], y = a[k];
+    acc = fmaf(x.x, y.x, acc);
+    acc = fmaf(x.y, y.y, acc);
+    acc = fmaf(x.z, y.z, acc);
+    acc = fmaf(x.w, y.w, acc);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0 && lbetter(acc, w, best_s[v], best_j[v])) {
+    best_s[v] = acc;
+    best_j[v] = w;
+  }
+}
+
+void launch_warm_best(const int32_t *warm, int64_t n, int d, const float *Zp, const float *Dhat, int Kp,
+                      const float *znorm, float *best_s, int32_t *best_j, hipStream_t s) {
+  if (n <= 0 || !warm) return;
+  hipLaunchKernelGGL(k_warm_best, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, warm, n, d, Zp, Dhat, Kp, znorm,
+                     best_s, best_j);
+}
+
 // ---------------------------------------------------------------------------
 // re-centring and fallback selection
 // ---------------------------------------------------------------------------

@@ -191,6 +191,9 @@ void launch_mlp_bf16(int64_t B, const float *X, int64_t ldx, int K, int Kx, cons
 // (hi = RNE(x), lo = RNE(x - hi), zero beyond Kp); and back to [rows][hi K | lo K].
 void launch_split_x3(const float *src, int Kp, int64_t rows, int Kx, uint16_t *dst, hipStream_t s);
 void launch_unsplit_x3(const uint16_t *src, int64_t rows, int Kx, int K, uint16_t *dst, hipStream_t s);
+// best <- the warm atom where it scores higher (ties: lower index).
+void launch_warm_best(const int32_t *warm, int64_t n, int d, const float *Zp, const float *Dhat, int Kp,
+                      const float *znorm, float *best_s, int32_t *best_j, hipStream_t s);
 void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
                  const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s);
 void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,

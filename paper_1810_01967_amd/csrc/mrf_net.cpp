@@ -605,6 +605,10 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     LAUNCH_CHECK("local search (re-centre)");
     prev = sorted;
   }
+  // the previous atom competes (non-expansive safeguard of the inexact projection)
+  launch_warm_best(warm, n, D->d, D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->znorm.as<float>(),
+                   D->best_s.as<float>(), D->best_j.as<int32_t>(), s);
+  LAUNCH_CHECK("warm start");
   if (st) HIP_TRY(hipEventRecord(ev.b, s));
   // exhaustive fallback below the correlation threshold
   int64_t nfb = 0;

@@ -544,7 +544,11 @@ def mrf_ipg_step(D: Dictionary, A: Operator, Y, X_in, mu, idx_in=None, precision
 
 def mrf_ipg_solve(D: Dictionary, A: Operator, Y, X0=None, mu0=1.0, zeta=2.0, adaptive=True,
                   max_iter=50, rel_tol=1e-6, max_shrinks=30, kappa=False, precision="fp32",
-                  topk=8, atom_splits=0, want_params=True, stream=None):
+                  topk=8, atom_splits=0, want_params=True, stream=None, net=None, box_radius=3,
+                  fallback_corr=0.98, recentre=0, eps=None, tree_capacity=0):
+    """Algorithm 2.  The projection is exhaustive (default), learned (net
+    given: proposal + local search + fallback, warm-started by the previous
+    iterate's atoms) or the cover tree (eps given)."""
     torch = _torch()
     X = (torch.zeros((A.nslices, A.L, A.ny, A.nx), dtype=torch.complex64, device="cuda")
          if X0 is None else X0.clone())
@@ -552,7 +556,9 @@ def mrf_ipg_solve(D: Dictionary, A: Operator, Y, X0=None, mu0=1.0, zeta=2.0, ada
     pd = torch.empty(A.n, dtype=torch.float32, device="cuda")
     params = torch.empty((A.n, D.nparam), dtype=torch.float32, device="cuda") if want_params else None
     o = SolveOpts(float(mu0), float(zeta), int(bool(adaptive)), int(max_iter), float(rel_tol),
-                  int(max_shrinks), int(bool(kappa)), match_opts(precision, topk, atom_splits))
+                  int(max_shrinks), int(bool(kappa)),
+                  match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre, eps,
+                             tree_capacity))
     cap = int(max_iter)
     f = np.zeros(cap, dtype=np.float64)
     mu = np.zeros(cap, dtype=np.float32)

@@ -219,6 +219,34 @@ def test_local_search_vs_oracle(m, small_dict, recentre, precision):
     assert gidx[5] == 0 and host(out["pd"])[5] == 0.0
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_local_search_warm_start_vs_oracle(m, small_dict, precision):
+    """The warm atom competes with the box's best (non-expansive safeguard):
+    warm indices are the exact answer for half the voxels and random atoms
+    for the rest; cells far from the answer for a third of the voxels."""
+    banner(f"local search with warm start vs oracle precision={precision}")
+    Dd = small_dict
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    n = 900
+    Z, j, pd, snr = workloads.random_voxels(Dd, n, seed=31, snr_db_range=(10.0, 40.0))
+    Z = c64(Z)
+    ex = mf.exact_mf(Z.astype(np.complex128), Dd.atoms)
+    warm = np.where(np.arange(n) % 2 == 0, ex["idx"], rng.randint(31, "warm", n, Dd.d)).astype(np.int32)
+    sub = grids.grid_sub(j, Dd.grid_dims)
+    far = np.where((np.arange(n) % 3 == 0)[:, None], 0, sub)
+    cells = np.clip(far, 0, np.array(Dd.grid_dims) - 1).astype(np.int32)
+    out = m.mrf_match_local(D, dev(Z), dev(cells), box_radius=3, fallback_corr=0.98, recentre=0,
+                            warm_idx=dev(warm), precision=precision)
+    ref = local.local_match(Z.astype(np.complex128), Dd.atoms, Dd.grid_dims, cells, r=3, threshold=0.98,
+                            recentre=0, warm=warm)
+    gidx = host(out["idx"]).astype(np.int64)
+    diff = gidx != ref["idx"]
+    print(f"index differences {diff.sum()} of {n}")
+    assert diff.sum() <= max(2, n // 500)
+    ok = mf.index_ok(Z.astype(np.complex128), Dd.atoms, gidx[::2], tol=1e-5)
+    assert np.all(ok)   # where the warm atom is the exact answer the result is exact
+
+
 def test_trained_network_gain(m, small_dict):
     """Train on noisy atoms, then the learned path against the exhaustive
     oracle, and against the same local search fed with a proposal that

@@ -146,3 +146,20 @@ def test_local_search_recentre_walks_to_the_optimum():
     r3 = local.local_match(Z, D.atoms, dims, cells, r=3, threshold=-1.0, recentre=3)
     assert np.mean(r0["idx"] == j) < 0.5
     np.testing.assert_array_equal(r3["idx"], j)
+
+
+def test_local_search_warm_start_safeguard():
+    """With a warm index the local search is never worse than the warm atom:
+    a box far from the optimum plus the exact answer as warm start gives the
+    exact matched filter; a poor warm atom changes nothing."""
+    D = workloads.fisp_dictionary(L=30, n_t1=12, n_t2=14)
+    Z, j, pd, snr = workloads.random_voxels(D, 40, seed=9, snr_db_range=(20.0, 40.0))
+    ex = mf.exact_mf(Z, D.atoms)
+    far = np.zeros((40, 2), dtype=np.int64)                 # boxes in the grid corner
+    far[:, 0] = np.where(grids.grid_sub(ex["idx"], D.grid_dims)[:, 0] > 6, 0, 11)
+    out = local.local_match(Z, D.atoms, D.grid_dims, far, r=1, threshold=-1.0, warm=ex["idx"])
+    np.testing.assert_array_equal(out["idx"], ex["idx"])
+    base = local.local_match(Z, D.atoms, D.grid_dims, far, r=1, threshold=-1.0)
+    worst = np.argmin(mf.correlations(Z, D.atoms), axis=1)
+    out2 = local.local_match(Z, D.atoms, D.grid_dims, far, r=1, threshold=-1.0, warm=worst)
+    np.testing.assert_array_equal(out2["idx"], base["idx"])
