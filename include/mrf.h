@@ -366,6 +366,8 @@ typedef struct {
   int32_t *shrinks;       /* HOST [cap] or NULL: shrinks per iteration */
   double f0;              /* objective of the initial X */
   float ms;               /* device time of the whole solve */
+  int64_t fallbacks;      /* MRF_LEARNED: voxels sent to the exhaustive filter, summed
+                             over every projection of the solve (step-size trials included) */
 } mrf_solve_stats;
 
 /* Algorithm 2 with the exact projection: X (DEVICE frame-major) holds X^0 on

@@ -113,6 +113,7 @@ struct mrf_dict_s {
   mrf::DevBuf dx3;                              // split-BF16 atoms [d_pad][Kx/32][hi 32 | lo 32] (built on first use)
   mrf::DevBuf axes, aoff, dims;                 // device copies of the grid axes
   int64_t bytes = 0;
+  int64_t fallback_total = 0;  // voxels sent to the exhaustive fallback by the learned path (all calls)
   // workspace (grows lazily)
   mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j, zx3;
   mrf::DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;

@@ -652,10 +652,12 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
   TRY(residual_and_gradient(D, A, cur, Yc, false, s));
   TRY(read_scalars(D, 4, s));
   double f = D->host_scal[3];
+  const int64_t fallback_start = D->fallback_total;
   if (stats) {
     stats->iters = 0;
     stats->total_shrinks = 0;
     stats->f0 = f;
+    stats->fallbacks = 0;
   }
   bool have_idx = false;
   float mu_init = o->mu0;
@@ -718,6 +720,7 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
       }
       stats->iters = k + 1;
       stats->total_shrinks += shrinks;
+      stats->fallbacks = D->fallback_total - fallback_start;
     }
     const double f_old = f;
     f = f_new;

@@ -623,6 +623,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     HIP_TRY(hipMemcpyAsync(&hc, count, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     nfb = hc;
+    D->fallback_total += nfb;
     if (nfb > 0) {
       const int64_t cnt_pad = round_up(nfb, kRowPad);
       TRY(grow(D->rows, (size_t)cnt_pad * D->Kp * 4));

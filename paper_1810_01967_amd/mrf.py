@@ -112,7 +112,8 @@ class SolveOpts(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("total_shrinks", ctypes.c_int32),
                 ("cap", ctypes.c_int32), ("f", ctypes.c_void_p), ("mu", ctypes.c_void_p),
-                ("shrinks", ctypes.c_void_p), ("f0", ctypes.c_double), ("ms", ctypes.c_float)]
+                ("shrinks", ctypes.c_void_p), ("f0", ctypes.c_double), ("ms", ctypes.c_float),
+                ("fallbacks", ctypes.c_int64)]
 
 
 _LIB = None
@@ -563,12 +564,12 @@ def mrf_ipg_solve(D: Dictionary, A: Operator, Y, X0=None, mu0=1.0, zeta=2.0, ada
     f = np.zeros(cap, dtype=np.float64)
     mu = np.zeros(cap, dtype=np.float32)
     sh = np.zeros(cap, dtype=np.int32)
-    st = SolveStats(0, 0, cap, f.ctypes.data, mu.ctypes.data, sh.ctypes.data, 0.0, 0.0)
+    st = SolveStats(0, 0, cap, f.ctypes.data, mu.ctypes.data, sh.ctypes.data, 0.0, 0.0, 0)
     _check(lib().mrf_ipg_solve(D.handle, ctypes.byref(A.c), _dev(Y), ctypes.byref(o), _dev(X),
                                _dev(idx), _dev(pd), _dev(params), ctypes.byref(st), _stream(stream)))
     k = st.iters
     hist = dict(iters=k, total_shrinks=st.total_shrinks, f0=st.f0, f=f[:k].copy(), mu=mu[:k].copy(),
-                shrinks=sh[:k].copy(), ms=st.ms)
+                shrinks=sh[:k].copy(), ms=st.ms, fallbacks=st.fallbacks)
     return X, idx, pd, params, hist
 
 

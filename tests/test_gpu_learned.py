@@ -243,7 +243,7 @@ def test_local_search_warm_start_vs_oracle(m, small_dict, precision):
     diff = gidx != ref["idx"]
     print(f"index differences {diff.sum()} of {n}")
     assert diff.sum() <= max(2, n // 500)
-    ok = mf.index_ok(Z.astype(np.complex128), Dd.atoms, gidx[::2], tol=1e-5)
+    ok = mf.index_ok(Z[::2].astype(np.complex128), Dd.atoms, gidx[::2], tol=1e-5)
     assert np.all(ok)   # where the warm atom is the exact answer the result is exact
 
 
