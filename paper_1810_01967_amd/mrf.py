@@ -530,12 +530,13 @@ def mrf_op_adjoint(A: Operator, R, apply_dcf=True, stream=None):
 
 # --------------------------------------------------------------------------- projected gradient
 def mrf_ipg_step(D: Dictionary, A: Operator, Y, X_in, mu, idx_in=None, precision="fp32", topk=8,
-                 atom_splits=0, stats=True, stream=None):
+                 atom_splits=0, stats=True, stream=None, net=None, box_radius=3, fallback_corr=0.98,
+                 recentre=0, eps=None, tree_capacity=0):
     torch = _torch()
     X_out = torch.empty_like(X_in)
     idx = torch.empty(A.n, dtype=torch.int32, device="cuda")
     pd = torch.empty(A.n, dtype=torch.float32, device="cuda")
-    opts = match_opts(precision, topk, atom_splits)
+    opts = match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre, eps, tree_capacity)
     st = StepStats() if stats else None
     _check(lib().mrf_ipg_step(D.handle, ctypes.byref(A.c), _dev(Y), _dev(X_in), _dev(X_out),
                               _dev(idx_in), _dev(idx), _dev(pd), float(mu), ctypes.byref(opts),

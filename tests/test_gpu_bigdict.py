@@ -1,0 +1,131 @@
+"""The multi-parametric dictionary: L = 1000 complex frames, IR-bSSFP on
+T1 (80) x T2 (80) x B1 in [0.6, 1.4] (17) x df in [-40, 40] Hz (11) =
+1,196,800 atoms (9.6 GB FP32, 4.8 GB BF16 on the device), a four-output
+network and a 7^4 = 2,401-atom local box.
+
+* standalone: 4,096 noisy atoms, the learned path (split-BF16 local search)
+  against the exhaustive BF16 filter with top-8 FP32 rescore, both graded on
+  sampled voxels against the FP64 oracle over all 1.2 M atoms;
+* one projected-gradient step batched over 16 slices of 32 x 32 with uneven
+  masks (2 + s/2 of 32 lines per frame in slice s): learned against the
+  exhaustive BF16 projection (same objective), both graded on sampled voxels
+  and on the voxels where they disagree against the oracle's projection of
+  the oracle's gradient step.
+
+The voxel counts are reduced from the 256 x 256 x 16 workload: at 9.6 MFLOP
+per voxel for the 4-D box and 4.8 GFLOP per voxel for the exhaustive BF16
+filter, a million voxels would take minutes (learned) to hours (exhaustive)."""
+import numpy as np
+import pytest
+
+from gpu_helpers import banner, c64, dev, host
+from oracle import ipg, mf
+from synth import rng, workloads
+
+pytestmark = pytest.mark.gpu
+
+L = 1000
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1810_01967_amd as m
+    banner("1,196,800-atom dictionary: generate, upload, train a 4-output network")
+    Dd = workloads.bssfp_dictionary(L=L, n_t1=80, n_t2=80, n_df=11, b1_axis=np.linspace(0.6, 1.4, 17),
+                                    dtype=np.complex64)
+    assert Dd.atoms.shape == (1_196_800, L) and tuple(Dd.grid_dims) == (80, 80, 17, 11)
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims, store_bf16=True)
+    net = m.Net(2 * L, 4, hidden=256, seed=11)
+    tr = m.mrf_net_train(net, D, samples=2_000_000, batch=4096, epochs=4, lr=1e-3, lr_min=1e-5, snr_lo=15.0,
+                         snr_hi=40.0, seed=12)
+    print(f"training loss {tr['first_loss']:.3f} -> {tr['last_loss']:.5f} in {tr['ms'] / 1e3:.1f} s")
+    return m, Dd, D, net
+
+
+def _exact(Z, atoms, chunk=40000):
+    """FP64 oracle over all atoms in chunks: best normalised correlation and
+    its lowest index."""
+    best = np.full(Z.shape[0], -np.inf)
+    arg = np.zeros(Z.shape[0], dtype=np.int64)
+    for a0 in range(0, atoms.shape[0], chunk):
+        c = mf.correlations(Z, atoms[a0:a0 + chunk])
+        j = np.argmax(c, axis=1)
+        v = c[np.arange(Z.shape[0]), j]
+        upd = v > best
+        best[upd], arg[upd] = v[upd], a0 + j[upd]
+    zn = np.linalg.norm(Z, axis=1)
+    return best / zn, arg
+
+
+def _corr(Z, atoms, idx):
+    a = atoms[idx].astype(np.complex128)
+    return np.real(np.sum(np.conj(a) * Z, axis=1)) / np.linalg.norm(a, axis=1) / np.linalg.norm(Z, axis=1)
+
+
+def test_bigdict_learned_vs_bf16(big):
+    m, Dd, D, net = big
+    banner("1.2M atoms: learned (split BF16) vs exhaustive BF16 + FP32 rescore, 4,096 voxels")
+    n = 4096
+    Z, j, pd, snr = workloads.random_voxels(Dd, n, seed=5)
+    Z = c64(Z)
+    Zd = dev(Z)
+    ob = m.mrf_match(D, Zd, precision="bf16", topk=8, stats=True)
+    ol = m.mrf_match(D, Zd, net=net, precision="bf16x3", box_radius=3, fallback_corr=0.98, recentre=2,
+                     stats=True)
+    ib, il = host(ob["idx"]).astype(np.int64), host(ol["idx"]).astype(np.int64)
+    st = ol["stats"]
+    mism = float(np.mean(ib != il))
+    print(f"exhaustive BF16 {ob['stats'].ms:.1f} ms; learned {st.ms:.2f} ms ({st.first_box_atoms / n:.0f} box "
+          f"atoms per voxel, {st.fallbacks} fallbacks, {st.recentred} re-centred); index mismatch {mism:.4f}")
+    # grade on the FP64 oracle over all atoms: 48 random voxels and every
+    # voxel where the two paths disagree
+    sample = np.union1d(rng.permutation(5, "sample", n)[:48], np.flatnonzero(ib != il))
+    Zs = Z[sample].astype(np.complex128)
+    best, arg = _exact(Zs, Dd.atoms)
+    cl, cb = _corr(Zs, Dd.atoms, il[sample]), _corr(Zs, Dd.atoms, ib[sample])
+    ok_l, ok_b = cl >= best - 4.6e-5, cb >= best - 1e-6
+    dis = np.isin(sample, np.flatnonzero(ib != il))
+    print(f"FP64 oracle on {len(sample)} voxels ({int(dis.sum())} where the paths disagree): learned exact on "
+          f"{ok_l.mean():.3f} (disagreements {ok_l[dis].mean() if dis.any() else 1:.3f}), BF16 + rescore on "
+          f"{ok_b.mean():.3f} (disagreements {ok_b[dis].mean() if dis.any() else 1:.3f})")
+    assert mism <= 0.02
+    assert ok_l.mean() >= 0.99
+
+
+def test_bigdict_batched_step_uneven_masks(big):
+    m, Dd, D, net = big
+    banner("1.2M atoms: one IPG step over 16 slices of 32 x 32 with uneven masks")
+    import torch
+    S, size = 16, 32
+    ph = workloads.smooth_phantom(Dd, seed=6, S=S, size=size)
+    smp = workloads.random_lines(6, S, L, size, size, [2 + s // 2 for s in range(S)])
+    Y = workloads.simulate_kspace(ph.X0, smp, 30.0, seed=6)
+    A = m.Operator.from_sampling(smp)
+    Yd = dev(c64(Y))
+    X0 = torch.zeros((S, L, size, size), dtype=torch.complex64, device="cuda")
+    Xe, ie, pde, ste = m.mrf_ipg_step(D, A, Yd, X0, 1.0, precision="bf16", topk=8)
+    Xl, il, pdl, stl = m.mrf_ipg_step(D, A, Yd, X0, 1.0, net=net, precision="bf16x3", recentre=2)
+    ie, il = host(ie).astype(np.int64), host(il).astype(np.int64)
+    head = ph.idx >= 0
+    agree = float(np.mean(ie[head] == il[head]))
+    print(f"step: |dX|^2 exhaustive {ste.dx2:.5e} learned {stl.dx2:.5e}; f exhaustive {ste.f_out:.6e} "
+          f"learned {stl.f_out:.6e}; tissue indices learned = exhaustive {agree:.4f}")
+    # oracle: Z = X0 - mu G = -G at X0 = 0, projected exactly on 32 random
+    # tissue voxels and up to 64 voxels where the two projections disagree
+    G, _ = ipg.gradient(np.zeros((S, L, size, size)), Y, smp.off, smp.idx, None)
+    Zv = (-G).transpose(0, 2, 3, 1).reshape(S * size * size, L)
+    tissue = np.flatnonzero(head)
+    dis = tissue[ie[tissue] != il[tissue]]
+    vox = np.union1d(tissue[rng.permutation(6, "sample", tissue.size)[:32]],
+                     dis[rng.permutation(6, "dis", dis.size)[:64]])
+    best, arg = _exact(Zv[vox], Dd.atoms)
+    ok_l = _corr(Zv[vox], Dd.atoms, il[vox]) >= best - 4.6e-5
+    ok_b = _corr(Zv[vox], Dd.atoms, ie[vox]) >= best - 1e-6
+    isdis = np.isin(vox, dis)
+    print(f"FP64 oracle on {vox.size} voxels ({int(isdis.sum())} disagreements): learned exact on {ok_l.mean():.3f} "
+          f"(disagreements {ok_l[isdis].mean() if isdis.any() else 1:.3f}), BF16 + rescore on {ok_b.mean():.3f} "
+          f"(disagreements {ok_b[isdis].mean() if isdis.any() else 1:.3f})")
+    assert abs(stl.f_out - ste.f_out) <= 0.02 * ste.f_out
+    assert ok_l.mean() >= 0.97
