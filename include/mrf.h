@@ -160,10 +160,11 @@ typedef struct mrf_net_s *mrf_net; /* learned proposal network (see below) */
 
 typedef struct {
   int32_t method;      /* MRF_EXHAUSTIVE or MRF_LEARNED */
-  int32_t precision;   /* exhaustive scoring: MRF_FP32 (exact argmax), MRF_BF16 or
-                          MRF_FP8 (top-k by reduced-precision score, then FP32 rescore).
-                          MRF_LEARNED: local search in MRF_FP32 or MRF_BF16X3 (the
-                          exhaustive fallback scores in FP32). */
+  int32_t precision;   /* exhaustive scoring: MRF_FP32 or MRF_BF16X3 (exact argmax of
+                          the scores in that arithmetic), MRF_BF16 or MRF_FP8 (top-k
+                          by reduced-precision score, then FP32 rescore).
+                          MRF_LEARNED: local search and exhaustive fallback in
+                          MRF_FP32 or MRF_BF16X3. */
   int32_t topk;        /* reduced-precision candidates rescored in FP32, 1..8 (0 = 8) */
   int32_t atom_splits; /* 0 = automatic; else number of atom ranges scored in parallel */
   mrf_net net;         /* MRF_LEARNED: trained network (input length = the dictionary's K) */

@@ -95,6 +95,7 @@ mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
                       hipStream_t s);
 mrf_status upload_tree(mrf_dict_s *D, const double *Xnorm);
 mrf_status ensure_x3(mrf_dict_s *D, hipStream_t s);
+int auto_splits_x3(const mrf_dict_s *D, int64_t n);
 bool net_bf16_ok(const mrf_net_s *net, int64_t K, int64_t ldx);
 mrf_status net_forward_bf16(mrf_net_s *net, const float *X, int64_t ldx, int64_t K, int64_t B,
                             const float *rowscale, float *Y, uint16_t *h1, hipStream_t s);

@@ -264,8 +264,6 @@ mrf_status check_opts(const mrf_dict_s *D, const mrf_match_opts *o) {
   if (o->precision < MRF_FP32 || o->precision > MRF_BF16X3) return fail(MRF_E_INVAL, "bad precision %d", o->precision);
   if (o->method == MRF_LEARNED && o->precision != MRF_FP32 && o->precision != MRF_BF16X3)
     return fail(MRF_E_INVAL, "MRF_LEARNED scores in MRF_FP32 or MRF_BF16X3");
-  if (o->method == MRF_EXHAUSTIVE && o->precision == MRF_BF16X3)
-    return fail(MRF_E_UNSUPPORTED, "MRF_BF16X3 is available for the local search (MRF_LEARNED)");
   if (o->topk < 0 || o->topk > 8) return fail(MRF_E_INVAL, "topk %d not in 0..8", o->topk);
   if (o->atom_splits < 0) return fail(MRF_E_INVAL, "atom_splits must be >= 0");
   if (o->precision == MRF_BF16 && !D->dbf16.p) return fail(MRF_E_UNSUPPORTED, "BF16 scoring needs MRF_STORE_BF16 at build");
@@ -284,6 +282,19 @@ int auto_splits(const mrf_dict_s *D, int64_t n) {
   return (int)s;
 }
 
+// Atom splits of the split-BF16 filter (256-atom tiles, 128-voxel tiles):
+// about 1,024 blocks.
+int auto_splits_x3(const mrf_dict_s *D, int64_t n) {
+  const int64_t nvt = (round_up(n, kRowPad) + 127) / 128;
+  const int64_t nvt8 = (nvt + 7) / 8 * 8;
+  const int64_t ntiles = D->d_pad / 256;
+  int64_t s = (1024 + nvt8 - 1) / nvt8;
+  if (s < 1) s = 1;
+  if (s > ntiles) s = ntiles;
+  if (s > 64) s = 64;
+  return (int)s;
+}
+
 // Score + merge on already packed voxels (ws zp/znorm filled for n rows).
 mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
                             int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
@@ -295,6 +306,26 @@ mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, c
   const int64_t n_pad = round_up(n, kRowPad);
   TRY(grow(D->gamma, (size_t)n * 4));
   if (splits_used) *splits_used = splits;
+  if (precision == MRF_BF16X3) {
+    // split BF16: voxel rows split per call, atom rows once per dictionary
+    TRY(ensure_x3(D, s));
+    int xs = (o && o->atom_splits > 0) ? o->atom_splits : auto_splits_x3(D, n);
+    if (splits_used) *splits_used = xs;
+    TRY(grow(D->zx3, (size_t)n_pad * 2 * D->Kx * 2));
+    TRY(grow(D->part_s, (size_t)xs * n * 4));
+    TRY(grow(D->part_j, (size_t)xs * n * 4));
+    if (ev_s0) HIP_TRY(hipEventRecord(ev_s0, s));
+    launch_split_x3(D->zp.as<float>(), D->Kp, n_pad, D->Kx, D->zx3.as<uint16_t>(), s);
+    launch_score_x3(D->dx3.as<uint16_t>(), D->zx3.as<uint16_t>(), D->d, D->d_pad, n, n_pad, D->Kx, xs,
+                    D->part_s.as<float>(), D->part_j.as<int>(), s);
+    LAUNCH_CHECK("score_x3");
+    if (ev_s1) HIP_TRY(hipEventRecord(ev_s1, s));
+    launch_merge_argmax(D->part_s.as<float>(), D->part_j.as<int>(), xs, n, D->d, D->znorm.as<float>(), warm,
+                        D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr, params_out,
+                        D->gamma.as<float>(), s);
+    LAUNCH_CHECK("merge_argmax");
+    return MRF_OK;
+  }
   if (precision == MRF_FP32) {
     TRY(grow(D->part_s, (size_t)splits * n * 4));
     TRY(grow(D->part_j, (size_t)splits * n * 4));

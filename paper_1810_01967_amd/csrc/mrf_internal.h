@@ -181,6 +181,11 @@ void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const
 // unpack them into best_s / best_j (-inf / -1 where no candidate).
 void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys, float *best_s, int32_t *best_j,
                       int mode, hipStream_t s);
+// Exhaustive split-BF16 scoring with fused argmax per atom split (Dx split
+// atoms [d_pad][2 Kx], Zx split voxels [n_pad][2 Kx]); merged by
+// launch_merge_argmax like the FP32 filter.
+void launch_score_x3(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t n, int64_t n_pad,
+                     int Kx, int splits, float *part_s, int *part_j, hipStream_t s);
 // BF16 inference of a hidden-256 network (layer 1 writes BF16 H1 [B][256],
 // layer 2 fuses the output layer into Y [B][P]).
 void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t *dst, int ldd, hipStream_t s);

@@ -626,23 +626,29 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     D->fallback_total += nfb;
     if (nfb > 0) {
       const int64_t cnt_pad = round_up(nfb, kRowPad);
-      TRY(grow(D->rows, (size_t)cnt_pad * D->Kp * 4));
-      launch_gather_rows(D->zp.as<float>(), D->Kp, la, nfb, cnt_pad, D->rows.as<float>(), s);
-      mrf_match_opts eo{};
-      eo.method = MRF_EXHAUSTIVE;
-      eo.precision = MRF_FP32;
+      TRY(grow(D->rows, (size_t)cnt_pad * std::max(D->Kp, D->Kx) * 4));
       int splits = 0;
-      {
+      if (x3) {
+        // split rows are 2 Kx BF16 = Kx words: gathered as rows of Kx floats
+        launch_gather_rows(reinterpret_cast<const float *>(D->zx3.p), D->Kx, la, nfb, cnt_pad,
+                           D->rows.as<float>(), s);
+        splits = auto_splits_x3(D, nfb);
+        TRY(grow(D->part_s, (size_t)splits * nfb * 4));
+        TRY(grow(D->part_j, (size_t)splits * nfb * 4));
+        launch_score_x3(D->dx3.as<uint16_t>(), D->rows.as<uint16_t>(), D->d, D->d_pad, nfb, cnt_pad, D->Kx,
+                        splits, D->part_s.as<float>(), D->part_j.as<int>(), s);
+      } else {
+        launch_gather_rows(D->zp.as<float>(), D->Kp, la, nfb, cnt_pad, D->rows.as<float>(), s);
         const int64_t nvt = (nfb + 127) / 128;
         const int64_t nvt8 = (nvt + 7) / 8 * 8;
         int64_t sp = (1024 + nvt8 - 1) / nvt8;
         sp = std::max<int64_t>(1, std::min<int64_t>(sp, std::min<int64_t>(64, D->d_pad / 128)));
         splits = (int)sp;
+        TRY(grow(D->part_s, (size_t)splits * nfb * 4));
+        TRY(grow(D->part_j, (size_t)splits * nfb * 4));
+        launch_score_f32(D->dhat.as<float>(), D->rows.as<float>(), D->d, D->d_pad, nfb, cnt_pad, D->Kp,
+                         splits, D->part_s.as<float>(), D->part_j.as<int>(), s);
       }
-      TRY(grow(D->part_s, (size_t)splits * nfb * 4));
-      TRY(grow(D->part_j, (size_t)splits * nfb * 4));
-      launch_score_f32(D->dhat.as<float>(), D->rows.as<float>(), D->d, D->d_pad, nfb, cnt_pad, D->Kp,
-                       splits, D->part_s.as<float>(), D->part_j.as<int>(), s);
       launch_scatter_best(la, nfb, D->part_s.as<float>(), D->part_j.as<int>(), splits,
                           D->best_s.as<float>(), D->best_j.as<int32_t>(), s);
       if (fallback_out) launch_mark(la, nfb, fallback_out, s);

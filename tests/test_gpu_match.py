@@ -30,19 +30,25 @@ def _rand_complex(seed, tag, shape):
     return g[..., 0] + 1j * g[..., 1]
 
 
-def check_against_oracle(Z64, atoms, out, params=None, pd_rtol=2e-5, x_atol=None):
+# split BF16 (x = hi + lo, products hi.hi + hi.lo + lo.hi): a score is within
+# 3 * 2^-16 sum_k |z_k a_k| <= 4.6e-5 ||Z|| of exact; PD, corr and X follow it
+X3_TOL = dict(near_tie=4.6e-5, pd_rtol=1e-4, corr_rtol=1e-4)
+
+
+def check_against_oracle(Z64, atoms, out, params=None, pd_rtol=2e-5, x_atol=None, near_tie=NEAR_TIE,
+                         corr_rtol=1e-5):
     """Compare GPU outputs with the oracle on the same (widened) inputs."""
     ref = mf.exact_mf(Z64, atoms, want_X=x_atol is not None)
     idx = host(out["idx"]).astype(np.int64)
     diff = idx != ref["idx"]
     if np.any(diff):
-        ok = mf.index_ok(Z64[diff], atoms, idx[diff], tol=NEAR_TIE)
+        ok = mf.index_ok(Z64[diff], atoms, idx[diff], tol=near_tie)
         assert np.all(ok), f"{np.sum(~ok)} index mismatches beyond the near-tie rule"
     same = ~diff
     pd = host(out["pd"])
     np.testing.assert_allclose(pd[same], ref["gamma"][same], rtol=pd_rtol, atol=1e-6 * max(1.0, ref["gamma"].max()))
     if "corr" in out:
-        np.testing.assert_allclose(host(out["corr"])[same], ref["corr"][same], rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(host(out["corr"])[same], ref["corr"][same], rtol=corr_rtol, atol=1e-6)
     if params is not None and "params" in out:
         got = host(out["params"])
         np.testing.assert_array_equal(got[same], params[idx[same]].astype(np.float32))
@@ -52,19 +58,27 @@ def check_against_oracle(Z64, atoms, out, params=None, pd_rtol=2e-5, x_atol=None
     return ref, int(diff.sum())
 
 
-def test_match_tiny_complex(m):
-    banner("match tiny complex d=200 L=40 n=300")
+def _tol(precision, x_atol):
+    if precision == "fp32":
+        return dict(x_atol=x_atol)
+    return dict(X3_TOL, x_atol=None if x_atol is None else 5 * x_atol)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_match_tiny_complex(m, precision):
+    banner(f"match tiny complex d=200 L=40 n=300 {precision}")
     d, L, n = 200, 40, 300
     atoms = _rand_complex(21, "a", (d, L)) * rng.uniform(21, "s", d, 0.5, 2.0)[:, None]
     params = np.stack([np.arange(d), 2 * np.arange(d)], axis=1).astype(np.float64)
     D = m.Dictionary(atoms, params)
     Z = c64(_rand_complex(21, "z", (n, L)))
-    out = m.mrf_match(D, dev(Z), want_X=True, want_params=True)
-    check_against_oracle(Z.astype(np.complex128), atoms, out, params, x_atol=2e-5)
+    out = m.mrf_match(D, dev(Z), want_X=True, want_params=True, precision=precision)
+    check_against_oracle(Z.astype(np.complex128), atoms, out, params, **_tol(precision, 2e-5))
 
 
-def test_match_ragged_real(m):
-    banner("match ragged real FISP d=333 L=37 n=1000")
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_match_ragged_real(m, precision):
+    banner(f"match ragged real FISP d=333 L=37 n=1000 {precision}")
     full = workloads.fisp_dictionary(L=37, n_t1=9, n_t2=37)
     atoms = full.atoms[:333]
     params = full.params[:333]
@@ -72,22 +86,23 @@ def test_match_ragged_real(m):
     j = rng.randint(22, "j", 1000, 333)
     Z = c64(rng.uniform(22, "pd", 1000, 0.3, 1.0)[:, None] * atoms[j]
             + 0.05 * _rand_complex(22, "noise", (1000, 37)))
-    out = m.mrf_match(D, dev(Z), want_X=True, want_params=True)
-    check_against_oracle(Z.astype(np.complex128), atoms, out, params, x_atol=2e-5)
+    out = m.mrf_match(D, dev(Z), want_X=True, want_params=True, precision=precision)
+    check_against_oracle(Z.astype(np.complex128), atoms, out, params, **_tol(precision, 2e-5))
 
 
-def test_match_fisp_dictionary_noiseless_exact(m):
-    banner("match FISP d=2000 L=100 n=4096 noiseless")
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_match_fisp_dictionary_noiseless_exact(m, precision):
+    banner(f"match FISP d=2000 L=100 n=4096 noiseless {precision}")
     Dd = workloads.fisp_dictionary(L=100)
     D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
     j = rng.randint(23, "j", 4096, Dd.d)
     pd = rng.uniform(23, "pd", 4096, 0.3, 1.0)
     Z = c64(pd[:, None] * Dd.atoms[j])
-    out = m.mrf_match(D, dev(Z), want_params=True)
-    ref, nd = check_against_oracle(Z.astype(np.complex128), Dd.atoms, out, Dd.params)
+    out = m.mrf_match(D, dev(Z), want_params=True, precision=precision)
+    ref, nd = check_against_oracle(Z.astype(np.complex128), Dd.atoms, out, Dd.params, **_tol(precision, None))
     idx = host(out["idx"])
     assert np.mean(idx == j) == 1.0
-    np.testing.assert_allclose(host(out["pd"]), pd, rtol=2e-6)
+    np.testing.assert_allclose(host(out["pd"]), pd, rtol=2e-6 if precision == "fp32" else 5e-5)
 
 
 def test_match_special_voxels(m):
@@ -162,19 +177,21 @@ def test_match_empty_and_validation(m):
     assert e.value.status == -4
 
 
-def test_match_full_size_sampled(m):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_match_full_size_sampled(m, precision):
     """Headline shapes: 256x256 voxels, L=500 complex, 60x60x28 = 100,800
     atoms; the oracle checks 1024 sampled voxels one by one."""
-    banner("match full size n=65536 d=100800 L=500 (sampled oracle)")
+    banner(f"match full size n=65536 d=100800 L=500 (sampled oracle) {precision}")
     Dd = workloads.bssfp_dictionary(L=500)
     D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
     Z, jtrue, pd, snr = workloads.random_voxels(Dd, 65536, seed=2)
     Z = c64(Z)
-    out = m.mrf_match(D, dev(Z), want_params=True, stats=True)
+    out = m.mrf_match(D, dev(Z), want_params=True, stats=True, precision=precision)
     idx = host(out["idx"])
     assert out["stats"].nonfinite == 0
     sample = rng.permutation(2, "sample", 65536)[:1024]
     sub = {k: v[dev(sample.astype(np.int64))] for k, v in out.items() if k in ("idx", "pd", "corr", "params")}
-    ref, nd = check_against_oracle(Z[sample].astype(np.complex128), Dd.atoms, sub, Dd.params)
-    print(f"full-size: {nd} near-tie differences in 1024 sampled voxels; "
+    ref, nd = check_against_oracle(Z[sample].astype(np.complex128), Dd.atoms, sub, Dd.params,
+                                   **_tol(precision, None))
+    print(f"full-size {precision}: {nd} near-tie differences in 1024 sampled voxels; "
           f"recovered generating atom {np.mean(idx == jtrue):.4f}; {out['stats'].ms:.1f} ms")
