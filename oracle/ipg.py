@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fourier, mf
+from . import fourier, mf, subspace
 
 
 class NoConvergence(RuntimeError):
@@ -49,27 +49,42 @@ def project(Z: np.ndarray, atoms: np.ndarray, warm_idx=None, X_prev=None,
     return fourier.voxel_to_frame(Xv, S, ny, nx), res
 
 
-def gradient(X, Y, off, idx, w):
+def op_forward(X, off, idx, V=None):
+    """A X, or with a temporal subspace V (eq. CS1) A(expand(X))."""
+    return fourier.forward(X if V is None else subspace.expand(X, V), off, idx)
+
+
+def op_adjoint(R, off, idx, S, L, ny, nx, V=None):
+    """A^H R over L frames, compressed by V^H when V is given."""
+    G = fourier.adjoint(R, off, idx, S, L if V is None else V.shape[0], ny, nx)
+    return G if V is None else subspace.compress(G, V)
+
+
+def gradient(X, Y, off, idx, w, V=None):
+    """A^H W (A X - Y) and the residual; with V: the compressed gradient of
+    eq. gradupdate, compress(A^H W (A expand(X) - Y))."""
     S, L, ny, nx = X.shape
-    R = fourier.forward(X, off, idx) - Y
+    R = op_forward(X, off, idx, V) - Y
     WR = R if w is None else np.asarray(w, dtype=np.float64) * R
-    return fourier.adjoint(WR, off, idx, S, L, ny, nx), R
+    return op_adjoint(WR, off, idx, S, L, ny, nx, V), R
 
 
 def ipg_step(Y, off, idx, atoms, X, mu: float, w=None, warm_idx=None,
-             nonexpansive: bool = False):
+             nonexpansive: bool = False, V=None):
     """One projected-gradient step at a fixed mu.  Returns (X', projection
-    result, stats) with stats = dx2, adx2 (weighted), f_old, f_new."""
+    result, stats) with stats = dx2, adx2 (weighted), f_old, f_new.  With a
+    temporal subspace V, X has s compressed frames, atoms are the compressed
+    atoms and dx2 is the compressed norm (the compressed step rule)."""
     Y = np.asarray(Y, dtype=np.complex128)
     X = np.asarray(X, dtype=np.complex128)
-    G, R = gradient(X, Y, off, idx, w)
+    G, R = gradient(X, Y, off, idx, w, V)
     Z = X - mu * G
     Xn, res = project(Z, atoms, warm_idx=warm_idx, X_prev=X, nonexpansive=nonexpansive)
     dX = Xn - X
-    AdX = fourier.forward(dX, off, idx)
+    AdX = op_forward(dX, off, idx, V)
     stats = dict(dx2=float(np.sum(np.abs(dX) ** 2)), adx2=_weighted_sq(AdX, w),
                  f_old=_weighted_sq(R, w),
-                 f_new=_weighted_sq(fourier.forward(Xn, off, idx) - Y, w))
+                 f_new=_weighted_sq(op_forward(Xn, off, idx, V) - Y, w))
     res["Z"] = Z
     return Xn, res, stats
 
@@ -77,20 +92,21 @@ def ipg_step(Y, off, idx, atoms, X, mu: float, w=None, warm_idx=None,
 def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
               adaptive: bool = True, max_iter: int = 50, rel_tol: float = 1e-6,
               max_shrinks: int = 30, X0=None, w=None, kappa: bool = False,
-              nonexpansive: bool = False):
-    """Full reconstruction; dims = (S, L, ny, nx).  Returns (X, idx, gamma,
-    history) where history lists per accepted iteration: f (objective after
-    the step), mu, shrinks, dx2, adx2."""
+              nonexpansive: bool = False, V=None):
+    """Full reconstruction; dims = (S, L, ny, nx) (L = s compressed frames
+    when a temporal subspace V is given).  Returns (X, idx, gamma, history)
+    where history lists per accepted iteration: f (objective after the
+    step), mu, shrinks, dx2, adx2."""
     S, L, ny, nx = dims
     Y = np.asarray(Y, dtype=np.complex128)
     X = np.zeros(dims, dtype=np.complex128) if X0 is None else np.asarray(X0, dtype=np.complex128).copy()
     warm = None
     gamma = np.zeros(S * ny * nx)
-    f = _weighted_sq(fourier.forward(X, off, idx) - Y, w)
+    f = _weighted_sq(op_forward(X, off, idx, V) - Y, w)
     hist = []
     mu_init = float(mu0)
     for k in range(max_iter):
-        G, _ = gradient(X, Y, off, idx, w)
+        G, _ = gradient(X, Y, off, idx, w, V)
         mu = mu_init
         shrinks = 0
         while True:
@@ -98,7 +114,7 @@ def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
             Xn, res = project(Z, atoms, warm_idx=warm, X_prev=X, nonexpansive=nonexpansive)
             dX = Xn - X
             dx2 = float(np.sum(np.abs(dX) ** 2))
-            adx2 = _weighted_sq(fourier.forward(dX, off, idx), w)
+            adx2 = _weighted_sq(op_forward(dX, off, idx, V), w)
             if (not adaptive) or dx2 == 0.0 or adx2 == 0.0 or mu < dx2 / adx2:
                 break
             mu /= zeta
@@ -109,11 +125,11 @@ def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
         warm = res["idx"]
         gamma = res["gamma"]
         if kappa and k == 0:
-            kap = np.sqrt(_weighted_sq(Y, None)) / max(np.sqrt(_weighted_sq(fourier.forward(X, off, idx), None)), 1e-300)
+            kap = np.sqrt(_weighted_sq(Y, None)) / max(np.sqrt(_weighted_sq(op_forward(X, off, idx, V), None)), 1e-300)
             X = X * kap
             gamma = gamma * kap
             mu_init *= kap
-        f_new = _weighted_sq(fourier.forward(X, off, idx) - Y, w)
+        f_new = _weighted_sq(op_forward(X, off, idx, V) - Y, w)
         hist.append(dict(f=f_new, mu=mu, shrinks=shrinks, dx2=dx2, adx2=adx2))
         if dx2 == 0.0:
             break
