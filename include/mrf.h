@@ -105,6 +105,9 @@ typedef struct {
   int32_t Kq;      /* padded row pitch (elements) of the BF16 / FP8 copies */
   uint32_t flags;
   int64_t device_bytes; /* device memory held by the handle (excl. workspace) */
+  int32_t L_full;       /* compressed dictionary (mrf_dict_compress): frames of the
+                           uncompressed atoms, else 0 */
+  int32_t reserved;
 } mrf_dict_info;
 mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info);
 
@@ -115,6 +118,36 @@ mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info);
  * `scales` [d] (else ignored).  For checks against an independent encoder. */
 mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *dst, float *scales,
                                mrf_stream stream);
+
+/* Temporal subspace compression (Section "Dimension-reduced subspace
+ * matched-filtering", eq. CS1 and the compressed updates eq. gradupdate,
+ * eq. gradcompression).  From a dictionary of L frames, builds a new handle
+ * *out whose atoms are Dtilde_j = V^H Dhat_j (s complex frames, normalised
+ * again in FP64 as mrf_dict_build does, same parameters and grid), where V
+ * (L x s, orthonormal columns) holds the s dominant eigenvectors of
+ * sum_j Dhat_j Dhat_j^H over the FP32 normalised atoms of D widened to
+ * FP64, in decreasing eigenvalue order, each multiplied by the unit phase
+ * that makes its entry of largest magnitude (the lowest row among equal
+ * magnitudes) real and positive.  The Gram matrix, its eigenvectors and the
+ * compressed atoms are computed on the device in FP64 (rocBLAS zherk and
+ * zgemm, rocSOLVER zheevd); the handle keeps V (FP64 on the host, FP32 on
+ * the device).  `flags` are the MRF_STORE_* / MRF_BUILD_COVERTREE flags of
+ * the new handle.
+ *
+ * With a compressed handle, mrf_match projects compressed voxels (s
+ * frames) and mrf_ipg_step / mrf_ipg_solve take images of s compressed
+ * frames per slice with an operator of L frames: the forward model is
+ * A(V X~) and the gradient V^H A^H W (A V X~ - Y); the step rule uses the
+ * compressed norm ||X~' - X~||^2 (equal to the full one, V having
+ * orthonormal columns).  The call synchronises `stream`.  Errors:
+ * MRF_E_INVAL (null handle, s outside 1..min(L, 512), unknown flags, a
+ * compressed atom of zero norm), MRF_E_UNSUPPORTED (D already compressed),
+ * MRF_E_NUMERIC (eigensolver failure), MRF_E_NOMEM, MRF_E_HIP. */
+mrf_status mrf_dict_compress(mrf_dict D, int32_t s, uint32_t flags, mrf_stream stream, mrf_dict *out);
+/* V of a compressed handle into HOST `V` [L_full][s] complex (interleaved
+ * FP64 pairs, row t = frame t) and its eigenvalues into HOST `lam` [s]
+ * (descending); either may be NULL.  MRF_E_INVAL if C is not compressed. */
+mrf_status mrf_dict_subspace(mrf_dict C, double *V, double *lam);
 
 /* Cover tree (Section "Cover trees"), built at mrf_dict_build with
  * MRF_BUILD_COVERTREE on the host in FP64 over the normalised atoms, exactly
@@ -341,7 +374,12 @@ typedef struct {
  * Y DEVICE complex64 [M]; X_in, X_out DEVICE frame-major images (distinct);
  * idx_in DEVICE int32 [n] or NULL (warm index for zero voxels); idx_out,
  * pd DEVICE [n] (pd may be NULL).  stats (HOST, may be NULL) receives the
- * quantities of the step-size rule (eq. steprule) and the objectives. */
+ * quantities of the step-size rule (eq. steprule) and the objectives.
+ * The images have D's frame count: A->L for an uncompressed D; for a
+ * compressed D (mrf_dict_compress, A->L equal to its L_full) they hold the
+ * s compressed frames X~ and the step is eq. gradupdate: A X means
+ * A(V X~), the gradient is V^H A^H W (A V X~ - Y) and dx2 is the compressed
+ * norm.  MRF_E_INVAL if A->L differs from D's (uncompressed) frames. */
 mrf_status mrf_ipg_step(mrf_dict D, const mrf_op *A, const void *Y, const void *X_in,
                         void *X_out, const int32_t *idx_in, int32_t *idx_out, float *pd,
                         float mu, const mrf_match_opts *opts, mrf_step_stats *stats,
@@ -371,7 +409,8 @@ typedef struct {
                              over every projection of the solve (step-size trials included) */
 } mrf_solve_stats;
 
-/* Algorithm 2 with the exact projection: X (DEVICE frame-major) holds X^0 on
+/* Algorithm 2 with the exact projection: X (DEVICE frame-major, D's frame
+ * count as in mrf_ipg_step: compressed frames for a compressed D) holds X^0 on
  * entry (zero it for the paper's initialisation) and the reconstruction on
  * return; idx, pd DEVICE [n]; params_out DEVICE [n][nparam] or NULL (the
  * look-up table applied to the final indices).  Synchronises `stream`. */

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmrf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["mrf_api.cpp", "mrf_net.cpp", "mrf_tree.cpp", "covertree.cpp", "k_tree.hip", "k_mf.hip", "k_lowp.hip", "k_fft.hip", "k_mlp.hip", "k_mlp_bf16.hip", "k_local.hip", "k_score_x3.hip"]
+SOURCES = ["mrf_api.cpp", "mrf_net.cpp", "mrf_tree.cpp", "covertree.cpp", "k_tree.hip", "k_mf.hip", "k_lowp.hip", "k_fft.hip", "k_mlp.hip", "k_mlp_bf16.hip", "k_local.hip", "k_score_x3.hip", "k_subspace.hip",
+           "mrf_subspace.cpp"]
 ARCH = os.environ.get("MRF_OFFLOAD_ARCH", "gfx950")
 
 
@@ -43,7 +44,8 @@ def build(verbose: bool = False) -> str:
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -118,6 +118,11 @@ struct mrf_dict_s {
   // workspace (grows lazily)
   mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j, zx3;
   mrf::DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;
+  // temporal subspace (a compressed dictionary: atoms V^H Dhat_j of L = s frames)
+  int Lfull = 0;                    // frames of the uncompressed dictionary, 0 if not compressed
+  mrf::DevBuf Vs;                   // V, FP32 complex [Lfull][L]
+  std::vector<double> V_host, lam;  // V (FP64 complex [Lfull][L], interleaved) and its eigenvalues
+  mrf::DevBuf kfull;                // full-frame k-space of the compressed adjoint
   mrf::DevBuf inv, h1, h2, yout, cells, best_s, best_j, bestkey, list_a, list_b, list_c, keys, hist, off, cnt, rows;
   // cover tree (host copy for export, device arrays for the traversal)
   bool has_tree = false;

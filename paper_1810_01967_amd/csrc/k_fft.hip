@@ -2,6 +2,7 @@
 // passes of 1-D radix-2 transforms staged in LDS), sample gather / residual,
 // zero-filled scatter (the adjoint of the sampling), and fixed-order FP64
 // reductions for the step-size rule.
+#include "k_reduce.h"
 #include "mrf_internal.h"
 
 namespace mrf {
@@ -121,16 +122,6 @@ void launch_fft2(float2 *data, int64_t nimg, int ny, int nx, int inverse, hipStr
 // ---------------------------------------------------------------------------
 // sampling
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum_f64(double x, double *red) {
-  const int tid = threadIdx.x;
-  red[tid] = x;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
-    __syncthreads();
-  }
-  return red[0];
-}
 
 __global__ __launch_bounds__(256) void k_sample(const float2 *__restrict__ K, int64_t npix,
                                                 const int64_t *__restrict__ off,

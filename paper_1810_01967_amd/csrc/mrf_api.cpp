@@ -214,6 +214,8 @@ extern "C" mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info) {
   info->Kq = D->Kq;
   info->flags = D->flags;
   info->device_bytes = D->bytes;
+  info->L_full = D->Lfull;
+  info->reserved = 0;
   return MRF_OK;
 }
 
@@ -466,28 +468,52 @@ mrf_status check_op(const mrf_op *A) {
   return MRF_OK;
 }
 
-// R = A X - Y; partial weighted norms per pair into red[0..npairs).
+// R = A X - Y; partial weighted norms per (slice, frame) pair into
+// part[0..npairs).  With a temporally compressed dictionary Dsub (Lfull > 0)
+// X holds Dsub->L compressed frames per slice: its images are transformed and
+// each sample combines them with V (eq. gradcompression).
 mrf_status forward_into(mrf_dict_s *ws, const mrf_op *A, const float2 *X, const float2 *Y,
-                        float2 *R, double *part, hipStream_t s) {
+                        float2 *R, double *part, hipStream_t s, const mrf_dict_s *Dsub = nullptr) {
   const int64_t npix = (int64_t)A->nx * A->ny;
-  const int64_t nimg = (int64_t)A->nslices * A->L;
+  const bool sub = Dsub && Dsub->Lfull > 0;
+  const int64_t nimg = (int64_t)A->nslices * (sub ? Dsub->L : A->L);
+  const int64_t npairs = (int64_t)A->nslices * A->L;
   TRY(grow(ws->kbuf, (size_t)nimg * npix * 8));
   HIP_TRY(hipMemcpyAsync(ws->kbuf.p, X, (size_t)nimg * npix * 8, hipMemcpyDeviceToDevice, s));
   launch_fft2(ws->kbuf.as<float2>(), nimg, A->ny, A->nx, 0, s);
   LAUNCH_CHECK("fft2");
-  launch_sample(ws->kbuf.as<float2>(), npix, A->samp_off, A->samp_idx, Y, A->dcf, R, part,
-                (int)nimg, A->nsamples, s);
+  if (sub)
+    launch_sample_sub(ws->kbuf.as<float2>(), npix, A->L, Dsub->L, Dsub->Vs.as<float2>(), A->samp_off,
+                      A->samp_idx, Y, A->dcf, R, part, (int)npairs, A->nsamples, s);
+  else
+    launch_sample(ws->kbuf.as<float2>(), npix, A->samp_off, A->samp_idx, Y, A->dcf, R, part,
+                  (int)npairs, A->nsamples, s);
   LAUNCH_CHECK("sample");
   return MRF_OK;
 }
 
+// G = A^H diag(w) R over the full frames, compressed by V^H when Dsub is a
+// compressed dictionary (the full-frame k-space goes through Dsub's
+// workspace, then per pixel sum_t conj(V[t, k]) K_t, then the inverse
+// transforms of the compressed frames).
 mrf_status adjoint_into(const mrf_op *A, const float2 *R, const float *w, float2 *G,
-                        hipStream_t s) {
+                        hipStream_t s, mrf_dict_s *Dsub = nullptr) {
   const int64_t npix = (int64_t)A->nx * A->ny;
-  const int64_t nimg = (int64_t)A->nslices * A->L;
-  launch_scatter(R, w, A->samp_off, A->samp_idx, G, npix, (int)nimg, nimg * npix, A->nsamples, s);
+  const int64_t npairs = (int64_t)A->nslices * A->L;
+  if (Dsub && Dsub->Lfull > 0) {
+    TRY(grow(Dsub->kfull, (size_t)npairs * npix * 8));
+    launch_scatter(R, w, A->samp_off, A->samp_idx, Dsub->kfull.as<float2>(), npix, (int)npairs, npairs * npix,
+                   A->nsamples, s);
+    LAUNCH_CHECK("scatter");
+    launch_compress_frames(Dsub->kfull.as<float2>(), npix, A->nslices, A->L, Dsub->L, Dsub->Vs.as<float2>(), G, s);
+    LAUNCH_CHECK("compress frames");
+    launch_fft2(G, (int64_t)A->nslices * Dsub->L, A->ny, A->nx, 1, s);
+    LAUNCH_CHECK("ifft2");
+    return MRF_OK;
+  }
+  launch_scatter(R, w, A->samp_off, A->samp_idx, G, npix, (int)npairs, npairs * npix, A->nsamples, s);
   LAUNCH_CHECK("scatter");
-  launch_fft2(G, nimg, A->ny, A->nx, 1, s);
+  launch_fft2(G, npairs, A->ny, A->nx, 1, s);
   LAUNCH_CHECK("ifft2");
   return MRF_OK;
 }
@@ -540,7 +566,8 @@ namespace {
 mrf_status check_step_args(mrf_dict_s *D, const mrf_op *A, const void *Y) {
   if (!D) return fail(MRF_E_INVAL, "null dictionary");
   TRY(check_op(A));
-  if (A->L != D->L) return fail(MRF_E_INVAL, "operator L=%d differs from dictionary L=%d", A->L, D->L);
+  const int L = D->Lfull > 0 ? D->Lfull : D->L;
+  if (A->L != L) return fail(MRF_E_INVAL, "operator L=%d differs from the dictionary's frames L=%d", A->L, L);
   if (A->nsamples > 0 && !Y) return fail(MRF_E_INVAL, "null Y");
   return MRF_OK;
 }
@@ -553,7 +580,8 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
                  float2 *R_update, hipStream_t s) {
   const int64_t npix = (int64_t)A->nx * A->ny;
   const int64_t n = (int64_t)A->nslices * npix;
-  const int64_t nimg = (int64_t)A->nslices * A->L;
+  const int64_t nimg = (int64_t)A->nslices * D->L;     // image frames (compressed frames if Lfull > 0)
+  const int64_t npairs = (int64_t)A->nslices * A->L;  // sampled (slice, frame) pairs
   const int64_t n_pad = round_up(n, kRowPad);
   const int real = D->is_complex ? 0 : 1;
   TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
@@ -561,7 +589,7 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
   TRY(grow(D->counters, 64));
   TRY(grow(D->kbuf, (size_t)nimg * npix * 8));
   TRY(grow(D->abuf, (size_t)(A->nsamples > 0 ? A->nsamples : 1) * 8));
-  TRY(grow(D->red, (size_t)(8192 + 2 * nimg + 8) * 8));
+  TRY(grow(D->red, (size_t)(8192 + 2 * npairs + 8) * 8));
   TRY(grow(D->scal, 64));
   launch_zero(D->counters.p, 16, s);
   launch_pack_frame_major(X, D->gbuf.as<float2>(), mu, n, n_pad, npix, D->L, real, D->Kp,
@@ -577,14 +605,18 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
   launch_reduce_sum(red, nb, D->scal.as<double>() + 0, s);
   launch_fft2(D->kbuf.as<float2>(), nimg, A->ny, A->nx, 0, s);
   LAUNCH_CHECK("fft2(dX)");
-  launch_sample(D->kbuf.as<float2>(), npix, A->samp_off, A->samp_idx, nullptr, A->dcf,
-                D->abuf.as<float2>(), nullptr, (int)nimg, A->nsamples, s);
+  if (D->Lfull > 0)
+    launch_sample_sub(D->kbuf.as<float2>(), npix, A->L, D->L, D->Vs.as<float2>(), A->samp_off, A->samp_idx,
+                      nullptr, A->dcf, D->abuf.as<float2>(), nullptr, (int)npairs, A->nsamples, s);
+  else
+    launch_sample(D->kbuf.as<float2>(), npix, A->samp_off, A->samp_idx, nullptr, A->dcf,
+                  D->abuf.as<float2>(), nullptr, (int)npairs, A->nsamples, s);
   LAUNCH_CHECK("sample(dX)");
-  launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)nimg,
-                    A->nsamples, red + 8192, red + 8192 + nimg, R_update, s);
+  launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)npairs,
+                    A->nsamples, red + 8192, red + 8192 + npairs, R_update, s);
   LAUNCH_CHECK("step_norms");
-  launch_reduce_sum(red + 8192, nimg, D->scal.as<double>() + 1, s);
-  launch_reduce_sum(red + 8192 + nimg, nimg, D->scal.as<double>() + 2, s);
+  launch_reduce_sum(red + 8192, npairs, D->scal.as<double>() + 1, s);
+  launch_reduce_sum(red + 8192 + npairs, npairs, D->scal.as<double>() + 2, s);
   LAUNCH_CHECK("reduce_sum");
   return MRF_OK;
 }
@@ -593,16 +625,17 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
 mrf_status residual_and_gradient(mrf_dict_s *D, const mrf_op *A, const float2 *X,
                                  const float2 *Y, bool gradient, hipStream_t s) {
   const int64_t npix = (int64_t)A->nx * A->ny;
-  const int64_t nimg = (int64_t)A->nslices * A->L;
+  const int64_t nimg = (int64_t)A->nslices * D->L;
+  const int64_t npairs = (int64_t)A->nslices * A->L;
   TRY(grow(D->rbuf, (size_t)(A->nsamples > 0 ? A->nsamples : 1) * 8));
   TRY(grow(D->gbuf, (size_t)nimg * npix * 8));
-  TRY(grow(D->red, (size_t)(8192 + 2 * nimg + 8) * 8));
+  TRY(grow(D->red, (size_t)(8192 + 2 * npairs + 8) * 8));
   TRY(grow(D->scal, 64));
   double *red = D->red.as<double>();
-  TRY(forward_into(D, A, X, Y, D->rbuf.as<float2>(), red + 8192, s));
-  launch_reduce_sum(red + 8192, nimg, D->scal.as<double>() + 3, s);
+  TRY(forward_into(D, A, X, Y, D->rbuf.as<float2>(), red + 8192, s, D));
+  launch_reduce_sum(red + 8192, npairs, D->scal.as<double>() + 3, s);
   LAUNCH_CHECK("reduce_sum");
-  if (gradient) TRY(adjoint_into(A, D->rbuf.as<float2>(), A->dcf, D->gbuf.as<float2>(), s));
+  if (gradient) TRY(adjoint_into(A, D->rbuf.as<float2>(), A->dcf, D->gbuf.as<float2>(), s, D));
   return MRF_OK;
 }
 
@@ -665,7 +698,8 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t npix = (int64_t)A->nx * A->ny;
   const int64_t n = (int64_t)A->nslices * npix;
-  const int64_t nimg = (int64_t)A->nslices * A->L;
+  const int64_t nimg = (int64_t)A->nslices * D->L;     // image frames (compressed frames if Lfull > 0)
+  const int64_t npairs = (int64_t)A->nslices * A->L;  // sampled (slice, frame) pairs
   const float2 *Yc = static_cast<const float2 *>(Y);
   TRY(grow(D->xbuf, (size_t)nimg * npix * 8));
   TRY(grow(D->idxbuf, (size_t)n * 4));
@@ -693,7 +727,7 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
   bool have_idx = false;
   float mu_init = o->mu0;
   for (int k = 0; k < o->max_iter; ++k) {
-    TRY(adjoint_into(A, D->rbuf.as<float2>(), A->dcf, D->gbuf.as<float2>(), s));
+    TRY(adjoint_into(A, D->rbuf.as<float2>(), A->dcf, D->gbuf.as<float2>(), s, D));
     float mu = mu_init;
     int shrinks = 0;
     double dx2 = 0, adx2 = 0, f_new = 0;
@@ -713,8 +747,8 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
                     o->max_shrinks, k);
     }
     // accept: R <- R + A dX (abuf holds A dX), swap iterates
-    launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)nimg,
-                      A->nsamples, D->red.as<double>() + 8192, D->red.as<double>() + 8192 + nimg,
+    launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)npairs,
+                      A->nsamples, D->red.as<double>() + 8192, D->red.as<double>() + 8192 + npairs,
                       D->rbuf.as<float2>(), s);
     LAUNCH_CHECK("residual update");
     std::swap(cur, nxt);
@@ -726,8 +760,8 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
       mrf_op A0 = *A;
       A0.dcf = nullptr;
       double *red = D->red.as<double>();
-      TRY(forward_into(D, &A0, cur, nullptr, D->abuf.as<float2>(), red + 8192, s));
-      launch_reduce_sum(red + 8192, nimg, D->scal.as<double>() + 4, s);
+      TRY(forward_into(D, &A0, cur, nullptr, D->abuf.as<float2>(), red + 8192, s, D));
+      launch_reduce_sum(red + 8192, npairs, D->scal.as<double>() + 4, s);
       int nb = 0;
       launch_norm2(Yc, A->nsamples, red, &nb, s);
       launch_reduce_sum(red, nb, D->scal.as<double>() + 5, s);

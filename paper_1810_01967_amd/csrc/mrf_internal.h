@@ -21,6 +21,9 @@ constexpr int kTreeMaxK = 2048;
 // padded to a multiple of it.
 constexpr int kX3Stage = 32;
 constexpr int kPitchLP = 128;
+// Largest temporal subspace dimension of a compressed dictionary (the V row
+// of one frame is staged in LDS by the compressed sampler).
+constexpr int kMaxSubspace = 512;
 // Atom / voxel row counts are padded to multiples of 256 so every tiling of
 // the scoring kernels reads inside the allocation.
 constexpr int kRowPad = 256;
@@ -98,6 +101,17 @@ void launch_sample(const float2 *K, int64_t npix, const int64_t *off, const int3
 // K zero-filled, then K[pair image][idx[i]] = w_i R_i (w = 1 when null).
 void launch_scatter(const float2 *R, const float *w, const int64_t *off, const int32_t *sidx,
                     float2 *K, int64_t npix, int npairs, int64_t total, int64_t M, hipStream_t s);
+// Temporal subspace (V: FP32 complex [L][sdim], frame-major rows).
+// out[r][t] = row r of the FP32 normalised atoms widened to FP64 complex.
+void launch_widen(const float *dhat, int Kp, int is_complex, int64_t rows, int L, double2 *out, hipStream_t s);
+// As launch_sample, with the pair image formed from the sdim compressed
+// k-space images of its slice, Kc [S][sdim][npix]: sum_k V[t, k] Kc_k.
+void launch_sample_sub(const float2 *Kc, int64_t npix, int L, int sdim, const float2 *V, const int64_t *off,
+                       const int32_t *sidx, const float2 *Y, const float *w, float2 *R, double *part, int npairs,
+                       int64_t M, hipStream_t s);
+// Kc [S][sdim][npix] = per pixel sum_t conj(V[t, k]) Kfull [S][L][npix].
+void launch_compress_frames(const float2 *Kfull, int64_t npix, int S, int L, int sdim, const float2 *V, float2 *Kc,
+                            hipStream_t s);
 // part[p] = sum w|A|^2 and part2[p] = sum w|R + A|^2 per pair; optionally R += A.
 void launch_step_norms(const float2 *R, const float2 *A, const float *w, const int64_t *off,
                        int npairs, int64_t M, double *part_a, double *part_ra, float2 *R_update,

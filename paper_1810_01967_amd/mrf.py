@@ -25,7 +25,7 @@ MRF_VOXEL_MAJOR, MRF_FRAME_MAJOR = 0, 1
 PRECISION = {"fp32": MRF_FP32, "bf16": MRF_BF16, "fp8": MRF_FP8, "bf16x3": MRF_BF16X3}
 
 EXPORTS = ["mrf_last_error", "mrf_version", "mrf_dict_build", "mrf_dict_destroy", "mrf_dict_query",
-           "mrf_dict_copy_atoms", "mrf_dict_tree_info", "mrf_dict_tree_export", "mrf_match", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
+           "mrf_dict_copy_atoms", "mrf_dict_compress", "mrf_dict_subspace", "mrf_dict_tree_info", "mrf_dict_tree_export", "mrf_match", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
            "mrf_net_size", "mrf_net_set_params", "mrf_net_get_params", "mrf_net_get_grads",
            "mrf_net_set_standardisation", "mrf_net_get_standardisation", "mrf_net_forward",
            "mrf_net_forward_bf16",
@@ -52,7 +52,7 @@ class DictInfo(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("L", ctypes.c_int32), ("nparam", ctypes.c_int32),
                 ("is_complex", ctypes.c_int32), ("K", ctypes.c_int32), ("Kp", ctypes.c_int32),
                 ("Kq", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("L_full", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class MatchOpts(ctypes.Structure):
@@ -135,6 +135,9 @@ def lib():
         L.mrf_dict_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(DictInfo)]
         L.mrf_dict_copy_atoms.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]
+        L.mrf_dict_compress.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]
+        L.mrf_dict_subspace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.mrf_match.argtypes = [ctypes.c_void_p, ctypes.POINTER(MatchOpts), ctypes.c_int64,
                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -250,7 +253,28 @@ class Dictionary:
         _check(lib().mrf_dict_build(ctypes.byref(desc), _stream(stream), ctypes.byref(h)))
         self.handle = h
         self.d, self.L = d, L
+        self.L_full = 0
         self.grid_dims = None if gd is None else tuple(int(x) for x in gd)
+
+    def compress(self, s, store_bf16=False, store_fp8=False, cover_tree=False, stream=None) -> "Dictionary":
+        """mrf_dict_compress: a new dictionary of the s-frame compressed atoms
+        V^H Dhat_j (V = the s dominant eigenvectors of sum_j Dhat_j Dhat_j^H)."""
+        flags = ((MRF_STORE_BF16 if store_bf16 else 0) | (MRF_STORE_FP8 if store_fp8 else 0)
+                 | (MRF_BUILD_COVERTREE if cover_tree else 0))
+        h = ctypes.c_void_p()
+        _check(lib().mrf_dict_compress(self.handle, int(s), flags, _stream(stream), ctypes.byref(h)))
+        C = Dictionary.__new__(Dictionary)
+        C.handle = h
+        C.is_complex, C.nparam, C.d, C.L, C.L_full = True, self.nparam, self.d, int(s), self.L
+        C.grid_dims = self.grid_dims
+        return C
+
+    def subspace(self):
+        """(V [L_full][s] complex128, eigenvalues [s]) of a compressed dictionary."""
+        V = np.empty((self.L_full, self.L), dtype=np.complex128)
+        lam = np.empty(self.L, dtype=np.float64)
+        _check(lib().mrf_dict_subspace(self.handle, V.ctypes.data, lam.ctypes.data))
+        return V, lam
 
     def info(self) -> DictInfo:
         inf = DictInfo()
@@ -552,7 +576,7 @@ def mrf_ipg_solve(D: Dictionary, A: Operator, Y, X0=None, mu0=1.0, zeta=2.0, ada
     given: proposal + local search + fallback, warm-started by the previous
     iterate's atoms) or the cover tree (eps given)."""
     torch = _torch()
-    X = (torch.zeros((A.nslices, A.L, A.ny, A.nx), dtype=torch.complex64, device="cuda")
+    X = (torch.zeros((A.nslices, D.L, A.ny, A.nx), dtype=torch.complex64, device="cuda")
          if X0 is None else X0.clone())
     idx = torch.empty(A.n, dtype=torch.int32, device="cuda")
     pd = torch.empty(A.n, dtype=torch.float32, device="cuda")
