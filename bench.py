@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--learned-precisions", default="bf16x3,fp32",
                     help="local-search arithmetic(s) of the learned path")
     ap.add_argument("--tree", type=int, default=1, help="build the cover tree and run the eps sweep")
+    ap.add_argument("--subspace", default="20,200",
+                    help="temporal subspace sizes s for the compressed matched filter ('' to skip)")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="time the FP64 oracle on a sample")
     ap.add_argument("--cpu-sample", type=int, default=32768, help="voxels in the oracle sample")
     ap.add_argument("--splits", type=int, default=0, help="atom splits (0 = library default)")
@@ -215,6 +217,43 @@ def main():
                 f"{evals:.0f} distances per voxel, {row['fallbacks']} fallbacks")
         del DT
 
+    subspace = None
+    if args.subspace:
+        subspace = []
+        for sdim in [int(x) for x in args.subspace.split(",") if x]:
+            t4 = time.time()
+            C = D.compress(sdim)
+            torch.cuda.synchronize()
+            tb = time.time() - t4
+            V, lam = C.subspace()
+            # voxels arrive compressed (Z~ = V^H Z per voxel), prepared on the host
+            Zc = torch.from_numpy((Z @ V.conj().astype(np.complex64)).astype(np.complex64)).cuda()
+            row = {"s": sdim, "build_seconds": tb,
+                   "energy_kept": float(lam.sum() / d)}
+            for p in ("fp32", "bf16x3"):
+                o = {}
+                for _ in range(2):
+                    o = m.mrf_match(C, Zc, precision=p, want_corr=False, out=o)
+                torch.cuda.synchronize()
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ksteps = max(3, args.steps)
+                ev0.record()
+                for _ in range(ksteps):
+                    o = m.mrf_match(C, Zc, precision=p, want_corr=False, out=o)
+                ev1.record()
+                torch.cuda.synchronize()
+                cms = ev0.elapsed_time(ev1) / ksteps
+                cidx = o["idx"].cpu().numpy()
+                answers[f"subspace{sdim}_{p}"] = (cidx, o["pd"].cpu().numpy())
+                row[p] = {"voxels_per_s": n / (cms * 1e-3), "ms_per_step": cms,
+                          "index_agreement_vs_full_fp32": float(np.mean(cidx == idx32)),
+                          "recovered_generating_atom": float(np.mean(cidx == jtrue))}
+                log(f"subspace s={sdim} {p}: {cms:.3f} ms/step, agreement with the full filter "
+                    f"{row[p]['index_agreement_vs_full_fp32']:.4f}, generating atom "
+                    f"{row[p]['recovered_generating_atom']:.4f}")
+            subspace.append(row)
+            del C, Zc
+
     ok = [lp for lp in args.learned_precisions.split(",")
           if learned is not None and learned[lp]["index_mismatch_vs_exhaustive_fp32"] <= 1e-3]
     if ok:
@@ -270,6 +309,8 @@ def main():
         res["learned"] = learned
     if tree is not None:
         res["cover_tree"] = tree
+    if subspace is not None:
+        res["subspace"] = subspace
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

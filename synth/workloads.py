@@ -321,18 +321,45 @@ def spiral_sampling(S: int, L: int, ny: int, nx: int, frac: float = 0.05,
 # ----------------------------------------------------------------------------
 # measurements
 # ----------------------------------------------------------------------------
-def simulate_kspace(X0: np.ndarray, smp: Sampling, snr_db: float, seed: int):
-    """Y = P_Omega F X0 + xi (eq. forward with S = I), F the unitary 2-D DFT
-    per frame.  Noise: circular complex Gaussian with per-sample variance
-    (||P_Omega F X0||^2 / M) 10^(-SNR/10).  Returns complex128 [M]."""
-    S, L, ny, nx = X0.shape
-    Y = np.empty(smp.M, dtype=np.complex128)
+def coil_maps(seed: int, S: int, c: int, ny: int, nx: int) -> np.ndarray:
+    """Smooth synthetic receive-coil sensitivities [S][c][ny][nx] complex128:
+    coil q sits on a ring around the field of view (angle 2 pi q / c plus a
+    seeded jitter, per slice), with a Gaussian magnitude profile of width
+    0.45 FOV and a smooth phase (constant + linear ramp); the maps are
+    normalised to unit sum of squares at every pixel (sum_q |S_q|^2 = 1)."""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    y = (yy - ny / 2.0) / ny
+    x = (xx - nx / 2.0) / nx
+    out = np.empty((S, c, ny, nx), dtype=np.complex128)
     for s in range(S):
-        k = np.fft.fft2(X0[s], norm="ortho").reshape(L, ny * nx)
-        for t in range(L):
-            p = s * L + t
-            Y[smp.off[p]:smp.off[p + 1]] = k[t, smp.idx[smp.off[p]:smp.off[p + 1]]]
+        u = rng.uniform(seed, f"coils-s{s}", 4 * c).reshape(c, 4)
+        for q in range(c):
+            ang = 2.0 * np.pi * q / c + 0.3 * (u[q, 0] - 0.5)
+            cy, cx = 0.6 * np.sin(ang), 0.6 * np.cos(ang)
+            mag = np.exp(-((y - cy) ** 2 + (x - cx) ** 2) / (2.0 * 0.45 ** 2))
+            ph = 2.0 * np.pi * u[q, 1] + 2.0 * (u[q, 2] - 0.5) * y + 2.0 * (u[q, 3] - 0.5) * x
+            out[s, q] = mag * np.exp(1j * ph)
+        out[s] /= np.sqrt(np.sum(np.abs(out[s]) ** 2, axis=0, keepdims=True))
+    return out
+
+
+def simulate_kspace(X0: np.ndarray, smp: Sampling, snr_db: float, seed: int, smaps=None):
+    """Y = P_Omega F S X0 + xi (eq. forward; S = I without coil maps), F the
+    unitary 2-D DFT per frame.  Noise: circular complex Gaussian with
+    per-sample variance (||P_Omega F S X0||^2 / (c M)) 10^(-SNR/10).
+    Returns complex128 [M], or [c][M] (coil-major) with maps [S][c][ny][nx]."""
+    S, L, ny, nx = X0.shape
+    c = 1 if smaps is None else smaps.shape[1]
+    Y = np.empty((c, smp.M), dtype=np.complex128)
+    for q in range(c):
+        for s in range(S):
+            img = X0[s] if smaps is None else smaps[s, q][None] * X0[s]
+            k = np.fft.fft2(img, norm="ortho").reshape(L, ny * nx)
+            for t in range(L):
+                p = s * L + t
+                Y[q, smp.off[p]:smp.off[p + 1]] = k[t, smp.idx[smp.off[p]:smp.off[p + 1]]]
     if snr_db is not None and np.isfinite(snr_db):
-        sig2 = np.sum(np.abs(Y) ** 2) / max(smp.M, 1) * 10.0 ** (-snr_db / 10.0)
-        Y = Y + rng.complex_gaussian(seed, "kspace-noise", (smp.M,), sig2)
-    return Y
+        sig2 = np.sum(np.abs(Y) ** 2) / max(c * smp.M, 1) * 10.0 ** (-snr_db / 10.0)
+        Y = Y + (rng.complex_gaussian(seed, "kspace-noise", (smp.M,), sig2)[None] if c == 1
+                 else rng.complex_gaussian(seed, "kspace-noise-coils", (c, smp.M), sig2))
+    return Y[0] if smaps is None else Y
