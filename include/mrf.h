@@ -333,28 +333,39 @@ mrf_status mrf_net_train(mrf_net net, mrf_dict D, const mrf_train_opts *opts,
                          mrf_train_stats *stats, mrf_stream stream);
 
 /* ------------------------------------------------------------------------ */
-/* Forward model A = P_Omega F (eq. forward, c = 1, S = I)                    */
+/* Forward model A = P_Omega F S (eq. forward)                                */
 /* ------------------------------------------------------------------------ */
 /* Images are frame-major [nslices][L][ny][nx] complex64.  F is the unitary
  * 2-D DFT of each frame, k-space in unshifted FFT order.  The sampling
  * pattern is CSR over (slice, frame) pairs p = s*L + t: the samples of pair p
  * are the flat k-space indices samp_idx[samp_off[p] .. samp_off[p+1]) (ky*nx+kx),
  * which must be distinct within a pair.  dcf (optional) holds the positive
- * weights w of the weighted least squares of eq. blip_dcf, one per sample. */
+ * weights w of the weighted least squares of eq. blip_dcf, one per sample.
+ * S: with ncoils = 0, S = I (one coil whose sensitivity is absorbed in X);
+ * with ncoils = c >= 1, S maps each frame to its c copies multiplied pixel-wise
+ * by the coil sensitivity maps smaps (the same maps for every frame), and
+ * the pattern of each (slice, frame) samples every coil.  Sample arrays
+ * (Y, R) then hold c*M values, coil-major ([c][M]); the dcf weights apply
+ * to every coil. */
 typedef struct {
   int32_t nx, ny;          /* powers of two, 16..256 */
   int32_t L, nslices;      /* >= 1 */
-  int64_t nsamples;        /* M = samp_off[nslices*L] */
+  int64_t nsamples;        /* M = samp_off[nslices*L] (per coil) */
   const int64_t *samp_off; /* DEVICE [nslices*L + 1] */
   const int32_t *samp_idx; /* DEVICE [M], each in [0, ny*nx) */
   const float *dcf;        /* DEVICE [M] or NULL (w = 1) */
+  int32_t ncoils;          /* 0: S = I; c in 1..64: coil maps below */
+  int32_t reserved;        /* 0 */
+  const void *smaps;       /* DEVICE complex64 [nslices][c][ny][nx] (ncoils >= 1), else ignored */
 } mrf_op;
 
-/* R = A X - Y  (Y NULL: R = A X), samples in CSR order, DEVICE complex64 [M].
+/* R = A X - Y  (Y NULL: R = A X), samples in CSR order (coil-major with
+ * coils), DEVICE complex64 [max(ncoils,1) * M].
  * If wnorm2 is non-NULL it receives ||R||_W^2 (stream synchronised). */
 mrf_status mrf_op_forward(const mrf_op *A, const void *X, const void *Y, void *R,
                           double *wnorm2, mrf_stream stream);
-/* G = A^H diag(w) R (apply_dcf != 0) or A^H R, DEVICE complex64 images. */
+/* G = A^H diag(w) R (apply_dcf != 0) or A^H R, DEVICE complex64 images
+ * (with coils: sum_q conj(S_q) F^H P_Omega^T R_q). */
 mrf_status mrf_op_adjoint(const mrf_op *A, const void *R, int32_t apply_dcf, void *G,
                           mrf_stream stream);
 
@@ -371,8 +382,8 @@ typedef struct {
 
 /* One step of eq. blip / eq. blip_dcf at a fixed step size mu:
  *   Z = X_in - mu A^H W (A X_in - Y);  X_out = P_cone(D)(Z).
- * Y DEVICE complex64 [M]; X_in, X_out DEVICE frame-major images (distinct);
- * idx_in DEVICE int32 [n] or NULL (warm index for zero voxels); idx_out,
+ * Y DEVICE complex64 [max(ncoils,1) * M] (coil-major); X_in, X_out DEVICE
+ * frame-major images (distinct); idx_in DEVICE int32 [n] or NULL (warm index for zero voxels); idx_out,
  * pd DEVICE [n] (pd may be NULL).  stats (HOST, may be NULL) receives the
  * quantities of the step-size rule (eq. steprule) and the objectives.
  * The images have D's frame count: A->L for an uncompressed D; for a

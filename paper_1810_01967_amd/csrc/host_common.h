@@ -123,6 +123,7 @@ struct mrf_dict_s {
   mrf::DevBuf Vs;                   // V, FP32 complex [Lfull][L]
   std::vector<double> V_host, lam;  // V (FP64 complex [Lfull][L], interleaved) and its eigenvalues
   mrf::DevBuf kfull;                // full-frame k-space of the compressed adjoint
+  mrf::DevBuf cbuf;                 // per-coil images (coil maps)
   mrf::DevBuf inv, h1, h2, yout, cells, best_s, best_j, bestkey, list_a, list_b, list_c, keys, hist, off, cnt, rows;
   // cover tree (host copy for export, device arrays for the traversal)
   bool has_tree = false;

@@ -128,32 +128,34 @@ __global__ __launch_bounds__(256) void k_sample(const float2 *__restrict__ K, in
                                                 const int32_t *__restrict__ sidx,
                                                 const float2 *__restrict__ Y,
                                                 const float *__restrict__ w,
-                                                float2 *__restrict__ R, double *part, int64_t M) {
+                                                float2 *__restrict__ R, double *part, int64_t M, int L,
+                                                int ncoil) {
   __shared__ double red[256];
-  const int p = blockIdx.x;
-  const int64_t b = min(max(off[p], (int64_t)0), M), e = min(max(off[p + 1], b), M);
-  const float2 *img = K + (int64_t)p * npix;
+  const int pv = blockIdx.x;
+  const VPair vp = vpair(pv, L, ncoil, M);
+  const int64_t b = min(max(off[vp.p], (int64_t)0), M), e = min(max(off[vp.p + 1], b), M);
+  const float2 *img = K + (int64_t)pv * npix;
   double acc = 0.0;
   for (int64_t i = b + threadIdx.x; i < e; i += 256) {
     const uint32_t k = (uint32_t)sidx[i];
     float2 r = k < (uint32_t)npix ? img[k] : make_float2(0.f, 0.f);
     if (Y) {
-      const float2 y = Y[i];
+      const float2 y = Y[vp.qoff + i];
       r.x -= y.x;
       r.y -= y.y;
     }
-    R[i] = r;
+    R[vp.qoff + i] = r;
     const double m = (double)r.x * r.x + (double)r.y * r.y;
     acc += w ? (double)w[i] * m : m;
   }
   const double s = block_sum_f64(acc, red);
-  if (threadIdx.x == 0 && part) part[p] = s;
+  if (threadIdx.x == 0 && part) part[pv] = s;
 }
 
 void launch_sample(const float2 *K, int64_t npix, const int64_t *off, const int32_t *sidx,
-                   const float2 *Y, const float *w, float2 *R, double *part, int npairs,
-                   int64_t M, hipStream_t s) {
-  hipLaunchKernelGGL(k_sample, dim3(npairs), dim3(256), 0, s, K, npix, off, sidx, Y, w, R, part, M);
+                   const float2 *Y, const float *w, float2 *R, double *part, int nvpairs,
+                   int64_t M, int L, int ncoil, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample, dim3(nvpairs), dim3(256), 0, s, K, npix, off, sidx, Y, w, R, part, M, L, ncoil);
 }
 
 __global__ __launch_bounds__(256) void k_zero(float4 *p, int64_t n4) {
@@ -184,14 +186,16 @@ __global__ __launch_bounds__(256) void k_scatter(const float2 *__restrict__ R,
                                                  const float *__restrict__ w,
                                                  const int64_t *__restrict__ off,
                                                  const int32_t *__restrict__ sidx,
-                                                 float2 *__restrict__ K, int64_t npix, int64_t M) {
-  const int p = blockIdx.x;
-  const int64_t b = min(max(off[p], (int64_t)0), M), e = min(max(off[p + 1], b), M);
-  float2 *img = K + (int64_t)p * npix;
+                                                 float2 *__restrict__ K, int64_t npix, int64_t M, int L,
+                                                 int ncoil) {
+  const int pv = blockIdx.x;
+  const VPair vp = vpair(pv, L, ncoil, M);
+  const int64_t b = min(max(off[vp.p], (int64_t)0), M), e = min(max(off[vp.p + 1], b), M);
+  float2 *img = K + (int64_t)pv * npix;
   for (int64_t i = b + threadIdx.x; i < e; i += 256) {
     const uint32_t k = (uint32_t)sidx[i];
     if (k >= (uint32_t)npix) continue;
-    float2 r = R[i];
+    float2 r = R[vp.qoff + i];
     if (w) {
       const float a = w[i];
       r.x *= a;
@@ -202,42 +206,98 @@ __global__ __launch_bounds__(256) void k_scatter(const float2 *__restrict__ R,
 }
 
 void launch_scatter(const float2 *R, const float *w, const int64_t *off, const int32_t *sidx,
-                    float2 *K, int64_t npix, int npairs, int64_t total, int64_t M, hipStream_t s) {
+                    float2 *K, int64_t npix, int nvpairs, int64_t total, int64_t M, int L, int ncoil,
+                    hipStream_t s) {
   launch_zero(K, total * (int64_t)sizeof(float2), s);
-  hipLaunchKernelGGL(k_scatter, dim3(npairs), dim3(256), 0, s, R, w, off, sidx, K, npix, M);
+  hipLaunchKernelGGL(k_scatter, dim3(nvpairs), dim3(256), 0, s, R, w, off, sidx, K, npix, M, L, ncoil);
 }
 
 __global__ __launch_bounds__(256) void k_step_norms(const float2 *__restrict__ R,
                                                     const float2 *__restrict__ A,
                                                     const float *__restrict__ w,
                                                     const int64_t *__restrict__ off, int64_t M,
-                                                    double *part_a, double *part_ra,
+                                                    int L, int ncoil, double *part_a, double *part_ra,
                                                     float2 *R_update) {
   __shared__ double red[256];
-  const int p = blockIdx.x;
-  const int64_t b = min(max(off[p], (int64_t)0), M), e = min(max(off[p + 1], b), M);
+  const int pv = blockIdx.x;
+  const VPair vp = vpair(pv, L, ncoil, M);
+  const int64_t b = min(max(off[vp.p], (int64_t)0), M), e = min(max(off[vp.p + 1], b), M);
   double sa = 0.0, sra = 0.0;
   for (int64_t i = b + threadIdx.x; i < e; i += 256) {
-    const float2 a = A[i];
-    const float2 r = R[i];
+    const float2 a = A[vp.qoff + i];
+    const float2 r = R[vp.qoff + i];
     const double wi = w ? (double)w[i] : 1.0;
     sa += wi * ((double)a.x * a.x + (double)a.y * a.y);
     const double qx = (double)r.x + a.x, qy = (double)r.y + a.y;
     sra += wi * (qx * qx + qy * qy);
-    if (R_update) R_update[i] = make_float2(r.x + a.x, r.y + a.y);
+    if (R_update) R_update[vp.qoff + i] = make_float2(r.x + a.x, r.y + a.y);
   }
   const double t1 = block_sum_f64(sa, red);
-  if (threadIdx.x == 0) part_a[p] = t1;
+  if (threadIdx.x == 0) part_a[pv] = t1;
   __syncthreads();
   const double t2 = block_sum_f64(sra, red);
-  if (threadIdx.x == 0) part_ra[p] = t2;
+  if (threadIdx.x == 0) part_ra[pv] = t2;
 }
 
 void launch_step_norms(const float2 *R, const float2 *A, const float *w, const int64_t *off,
-                       int npairs, int64_t M, double *part_a, double *part_ra, float2 *R_update,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_step_norms, dim3(npairs), dim3(256), 0, s, R, A, w, off, M, part_a,
+                       int nvpairs, int64_t M, int L, int ncoil, double *part_a, double *part_ra,
+                       float2 *R_update, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_norms, dim3(nvpairs), dim3(256), 0, s, R, A, w, off, M, L, ncoil, part_a,
                      part_ra, R_update);
+}
+
+// ---------------------------------------------------------------------------
+// coil sensitivities (eq. forward, c coils)
+// ---------------------------------------------------------------------------
+// out [S][c][F][npix] = S_q (pixel-wise) x X [S][F][npix]
+__global__ __launch_bounds__(256) void k_coil_expand(const float2 *__restrict__ X,
+                                                     const float2 *__restrict__ maps, int64_t npix, int F,
+                                                     int ncoil, int64_t total, float2 *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int64_t pix = e % npix;
+  const int64_t r = e / npix;  // (sl * c + q) * F + f
+  const int f = (int)(r % F);
+  const int64_t vs = r / F;
+  const int64_t sl = vs / ncoil;
+  const float2 m = maps[vs * npix + pix], x = X[(sl * F + f) * npix + pix];
+  out[e] = make_float2(m.x * x.x - m.y * x.y, m.x * x.y + m.y * x.x);
+}
+
+void launch_coil_expand(const float2 *X, const float2 *maps, int S, int ncoil, int F, int64_t npix, float2 *out,
+                        hipStream_t s) {
+  const int64_t total = (int64_t)S * ncoil * F * npix;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_coil_expand, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X, maps, npix, F,
+                     ncoil, total, out);
+}
+
+// G [S][F][npix] = sum_q conj(S_q) x Gc [S][c][F][npix], coils in increasing order
+__global__ __launch_bounds__(256) void k_coil_combine(const float2 *__restrict__ Gc,
+                                                      const float2 *__restrict__ maps, int64_t npix, int F,
+                                                      int ncoil, int64_t total, float2 *__restrict__ G) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int64_t pix = e % npix;
+  const int64_t r = e / npix;  // sl * F + f
+  const int f = (int)(r % F);
+  const int64_t sl = r / F;
+  float gx = 0.f, gy = 0.f;
+  for (int q = 0; q < ncoil; ++q) {
+    const int64_t vs = sl * ncoil + q;
+    const float2 m = maps[vs * npix + pix], g = Gc[(vs * F + f) * npix + pix];
+    gx = fmaf(m.x, g.x, fmaf(m.y, g.y, gx));
+    gy = fmaf(m.x, g.y, fmaf(-m.y, g.x, gy));
+  }
+  G[e] = make_float2(gx, gy);
+}
+
+void launch_coil_combine(const float2 *Gc, const float2 *maps, int S, int ncoil, int F, int64_t npix, float2 *G,
+                         hipStream_t s) {
+  const int64_t total = (int64_t)S * F * npix;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_coil_combine, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, Gc, maps, npix, F,
+                     ncoil, total, G);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_sum(const double *__restrict__ part,

@@ -1,4 +1,5 @@
-// Fixed-order block reduction shared by the sampling kernels.
+// Helpers shared by the sampling kernels: a fixed-order block reduction and
+// the map from a virtual (slice, coil, frame) pair to its sampling pattern.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -15,6 +16,19 @@ __device__ __forceinline__ double block_sum_f64(double x, double *red) {
     __syncthreads();
   }
   return red[0];
+}
+
+// Virtual pair pv = (slice * ncoil + coil) * L + frame: the CSR pair
+// slice * L + frame whose pattern every coil shares, and the offset of the
+// coil's samples in coil-major sample arrays ([ncoil][M]).
+struct VPair {
+  int p;
+  int64_t qoff;
+};
+__device__ __forceinline__ VPair vpair(int pv, int L, int ncoil, int64_t M) {
+  const int vs = pv / L, t = pv - vs * L;
+  const int sl = vs / ncoil, q = vs - sl * ncoil;
+  return {sl * L + t, (int64_t)q * M};
 }
 
 }  // namespace mrf

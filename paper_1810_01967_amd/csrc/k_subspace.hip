@@ -5,8 +5,8 @@
 //     Gram matrix and the compressed atoms are formed in FP64);
 //   * k_sample_sub: the compressed forward operator at the samples, y_i =
 //     sum_k V[t_i, k] Kc_k(kappa_i) over the s compressed k-space images of
-//     the sample's slice (fixed order), minus Y, with per-(slice, frame)
-//     weighted squared norms as in the uncompressed sampler;
+//     the sample's (slice, coil) (fixed order), minus Y, with per-(slice,
+//     coil, frame) weighted squared norms as in the uncompressed sampler;
 //   * k_compress_frames: per pixel, Kc_k = sum_t conj(V[t, k]) K_t over the L
 //     full frames (fixed order), 32 compressed frames per thread.
 #include "k_reduce.h"
@@ -35,15 +35,16 @@ __global__ __launch_bounds__(256) void k_sample_sub(const float2 *__restrict__ K
                                                     const float2 *__restrict__ V, const int64_t *__restrict__ off,
                                                     const int32_t *__restrict__ sidx, const float2 *__restrict__ Y,
                                                     const float *__restrict__ w, float2 *__restrict__ R,
-                                                    double *part, int64_t M) {
+                                                    double *part, int64_t M, int ncoil) {
   __shared__ double red[256];
   __shared__ float2 vrow[kMaxSubspace];
-  const int p = blockIdx.x;  // (slice, frame) pair
-  const int sl = p / L, t = p - sl * L;
+  const int pv = blockIdx.x;  // virtual (slice, coil, frame) pair
+  const VPair vp = vpair(pv, L, ncoil, M);
+  const int vs = pv / L, t = pv - vs * L;
   for (int k = threadIdx.x; k < sdim; k += 256) vrow[k] = V[(int64_t)t * sdim + k];
   __syncthreads();
-  const int64_t b = min(max(off[p], (int64_t)0), M), e = min(max(off[p + 1], b), M);
-  const float2 *img = Kc + (int64_t)sl * sdim * npix;
+  const int64_t b = min(max(off[vp.p], (int64_t)0), M), e = min(max(off[vp.p + 1], b), M);
+  const float2 *img = Kc + (int64_t)vs * sdim * npix;
   double acc = 0.0;
   for (int64_t i = b + threadIdx.x; i < e; i += 256) {
     const uint32_t kap = (uint32_t)sidx[i];
@@ -56,23 +57,23 @@ __global__ __launch_bounds__(256) void k_sample_sub(const float2 *__restrict__ K
       }
     }
     if (Y) {
-      const float2 y = Y[i];
+      const float2 y = Y[vp.qoff + i];
       r.x -= y.x;
       r.y -= y.y;
     }
-    R[i] = r;
+    R[vp.qoff + i] = r;
     const double m2 = (double)r.x * r.x + (double)r.y * r.y;
     acc += w ? (double)w[i] * m2 : m2;
   }
   const double sum = block_sum_f64(acc, red);
-  if (threadIdx.x == 0 && part) part[p] = sum;
+  if (threadIdx.x == 0 && part) part[pv] = sum;
 }
 
 void launch_sample_sub(const float2 *Kc, int64_t npix, int L, int sdim, const float2 *V, const int64_t *off,
-                       const int32_t *sidx, const float2 *Y, const float *w, float2 *R, double *part, int npairs,
-                       int64_t M, hipStream_t s) {
-  hipLaunchKernelGGL(k_sample_sub, dim3(npairs), dim3(256), 0, s, Kc, npix, L, sdim, V, off, sidx, Y, w, R, part,
-                     M);
+                       const int32_t *sidx, const float2 *Y, const float *w, float2 *R, double *part, int nvpairs,
+                       int64_t M, int ncoil, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_sub, dim3(nvpairs), dim3(256), 0, s, Kc, npix, L, sdim, V, off, sidx, Y, w, R, part,
+                     M, ncoil);
 }
 
 constexpr int SUB_KC = 32;  // compressed frames per block of k_compress_frames

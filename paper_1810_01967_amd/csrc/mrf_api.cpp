@@ -464,57 +464,95 @@ mrf_status check_op(const mrf_op *A) {
   if (A->L < 1 || A->nslices < 1) return fail(MRF_E_INVAL, "L and nslices must be >= 1");
   if (A->nsamples < 0) return fail(MRF_E_INVAL, "nsamples < 0");
   if (!A->samp_off || (A->nsamples > 0 && !A->samp_idx)) return fail(MRF_E_INVAL, "null sampling arrays");
-  if ((int64_t)A->nslices * A->L > (1 << 30)) return fail(MRF_E_INVAL, "too many frames");
+  if (A->ncoils < 0 || A->ncoils > 64) return fail(MRF_E_INVAL, "ncoils=%d not in 0..64", A->ncoils);
+  if (A->ncoils >= 1 && !A->smaps) return fail(MRF_E_INVAL, "ncoils=%d needs smaps", A->ncoils);
+  if ((int64_t)A->nslices * std::max(A->ncoils, 1) * A->L > (1 << 30)) return fail(MRF_E_INVAL, "too many frames");
   return MRF_OK;
 }
 
-// R = A X - Y; partial weighted norms per (slice, frame) pair into
-// part[0..npairs).  With a temporally compressed dictionary Dsub (Lfull > 0)
-// X holds Dsub->L compressed frames per slice: its images are transformed and
-// each sample combines them with V (eq. gradcompression).
+// Sizes of the operator: coils (1 without maps), the maps, the virtual
+// (slice, coil, frame) pairs and the coil-major sample count.
+struct OpDims {
+  int64_t npix;
+  int nc;
+  const float2 *maps;
+  int64_t nvpairs;
+  int64_t nsamp;
+};
+OpDims dims_of(const mrf_op *A) {
+  OpDims o;
+  o.npix = (int64_t)A->nx * A->ny;
+  o.nc = A->ncoils >= 1 ? A->ncoils : 1;
+  o.maps = A->ncoils >= 1 ? static_cast<const float2 *>(A->smaps) : nullptr;
+  o.nvpairs = (int64_t)A->nslices * o.nc * A->L;
+  o.nsamp = (int64_t)o.nc * A->nsamples;
+  return o;
+}
+
+// R = A X - Y; partial weighted norms per virtual (slice, coil, frame) pair
+// into part[0..nvpairs).  With coil maps the images are first expanded to
+// their c weighted copies.  With a temporally compressed dictionary Dsub
+// (Lfull > 0) X holds Dsub->L compressed frames per slice: their images are
+// transformed and each sample combines them with V (eq. gradcompression).
 mrf_status forward_into(mrf_dict_s *ws, const mrf_op *A, const float2 *X, const float2 *Y,
                         float2 *R, double *part, hipStream_t s, const mrf_dict_s *Dsub = nullptr) {
-  const int64_t npix = (int64_t)A->nx * A->ny;
+  const OpDims o = dims_of(A);
   const bool sub = Dsub && Dsub->Lfull > 0;
-  const int64_t nimg = (int64_t)A->nslices * (sub ? Dsub->L : A->L);
-  const int64_t npairs = (int64_t)A->nslices * A->L;
-  TRY(grow(ws->kbuf, (size_t)nimg * npix * 8));
-  HIP_TRY(hipMemcpyAsync(ws->kbuf.p, X, (size_t)nimg * npix * 8, hipMemcpyDeviceToDevice, s));
-  launch_fft2(ws->kbuf.as<float2>(), nimg, A->ny, A->nx, 0, s);
+  const int F = sub ? Dsub->L : A->L;                     // image frames per slice
+  const int64_t nkimg = (int64_t)A->nslices * o.nc * F;   // k-space images
+  TRY(grow(ws->kbuf, (size_t)nkimg * o.npix * 8));
+  if (o.maps) {
+    launch_coil_expand(X, o.maps, A->nslices, o.nc, F, o.npix, ws->kbuf.as<float2>(), s);
+    LAUNCH_CHECK("coil expand");
+  } else {
+    HIP_TRY(hipMemcpyAsync(ws->kbuf.p, X, (size_t)nkimg * o.npix * 8, hipMemcpyDeviceToDevice, s));
+  }
+  launch_fft2(ws->kbuf.as<float2>(), nkimg, A->ny, A->nx, 0, s);
   LAUNCH_CHECK("fft2");
   if (sub)
-    launch_sample_sub(ws->kbuf.as<float2>(), npix, A->L, Dsub->L, Dsub->Vs.as<float2>(), A->samp_off,
-                      A->samp_idx, Y, A->dcf, R, part, (int)npairs, A->nsamples, s);
+    launch_sample_sub(ws->kbuf.as<float2>(), o.npix, A->L, Dsub->L, Dsub->Vs.as<float2>(), A->samp_off,
+                      A->samp_idx, Y, A->dcf, R, part, (int)o.nvpairs, A->nsamples, o.nc, s);
   else
-    launch_sample(ws->kbuf.as<float2>(), npix, A->samp_off, A->samp_idx, Y, A->dcf, R, part,
-                  (int)npairs, A->nsamples, s);
+    launch_sample(ws->kbuf.as<float2>(), o.npix, A->samp_off, A->samp_idx, Y, A->dcf, R, part, (int)o.nvpairs,
+                  A->nsamples, A->L, o.nc, s);
   LAUNCH_CHECK("sample");
   return MRF_OK;
 }
 
-// G = A^H diag(w) R over the full frames, compressed by V^H when Dsub is a
-// compressed dictionary (the full-frame k-space goes through Dsub's
-// workspace, then per pixel sum_t conj(V[t, k]) K_t, then the inverse
-// transforms of the compressed frames).
-mrf_status adjoint_into(const mrf_op *A, const float2 *R, const float *w, float2 *G,
-                        hipStream_t s, mrf_dict_s *Dsub = nullptr) {
-  const int64_t npix = (int64_t)A->nx * A->ny;
-  const int64_t npairs = (int64_t)A->nslices * A->L;
-  if (Dsub && Dsub->Lfull > 0) {
-    TRY(grow(Dsub->kfull, (size_t)npairs * npix * 8));
-    launch_scatter(R, w, A->samp_off, A->samp_idx, Dsub->kfull.as<float2>(), npix, (int)npairs, npairs * npix,
-                   A->nsamples, s);
-    LAUNCH_CHECK("scatter");
-    launch_compress_frames(Dsub->kfull.as<float2>(), npix, A->nslices, A->L, Dsub->L, Dsub->Vs.as<float2>(), G, s);
-    LAUNCH_CHECK("compress frames");
-    launch_fft2(G, (int64_t)A->nslices * Dsub->L, A->ny, A->nx, 1, s);
-    LAUNCH_CHECK("ifft2");
-    return MRF_OK;
+// G = A^H diag(w) R: samples scattered into the (slice, coil) full-frame
+// k-space, compressed by V^H when Dsub is a compressed dictionary, inverse
+// transforms of the (compressed) frames, then coils combined with conj(S_q).
+// Workspace from ws (kfull, cbuf).
+mrf_status adjoint_into(mrf_dict_s *ws, const mrf_op *A, const float2 *R, const float *w, float2 *G,
+                        hipStream_t s, const mrf_dict_s *Dsub = nullptr) {
+  const OpDims o = dims_of(A);
+  const bool sub = Dsub && Dsub->Lfull > 0;
+  const int F = sub ? Dsub->L : A->L;
+  const int64_t nkimg = (int64_t)A->nslices * o.nc * F;  // images before the coil combination
+  float2 *Gc = G;
+  if (o.maps) {
+    TRY(grow(ws->cbuf, (size_t)nkimg * o.npix * 8));
+    Gc = ws->cbuf.as<float2>();
   }
-  launch_scatter(R, w, A->samp_off, A->samp_idx, G, npix, (int)npairs, npairs * npix, A->nsamples, s);
-  LAUNCH_CHECK("scatter");
-  launch_fft2(G, npairs, A->ny, A->nx, 1, s);
+  if (sub) {
+    TRY(grow(ws->kfull, (size_t)o.nvpairs * o.npix * 8));
+    launch_scatter(R, w, A->samp_off, A->samp_idx, ws->kfull.as<float2>(), o.npix, (int)o.nvpairs,
+                   o.nvpairs * o.npix, A->nsamples, A->L, o.nc, s);
+    LAUNCH_CHECK("scatter");
+    launch_compress_frames(ws->kfull.as<float2>(), o.npix, A->nslices * o.nc, A->L, Dsub->L,
+                           Dsub->Vs.as<float2>(), Gc, s);
+    LAUNCH_CHECK("compress frames");
+  } else {
+    launch_scatter(R, w, A->samp_off, A->samp_idx, Gc, o.npix, (int)o.nvpairs, o.nvpairs * o.npix, A->nsamples,
+                   A->L, o.nc, s);
+    LAUNCH_CHECK("scatter");
+  }
+  launch_fft2(Gc, nkimg, A->ny, A->nx, 1, s);
   LAUNCH_CHECK("ifft2");
+  if (o.maps) {
+    launch_coil_combine(Gc, o.maps, A->nslices, o.nc, F, o.npix, G, s);
+    LAUNCH_CHECK("coil combine");
+  }
   return MRF_OK;
 }
 
@@ -534,13 +572,13 @@ extern "C" mrf_status mrf_op_forward(const mrf_op *A, const void *X, const void 
   if (!X || !R) return fail(MRF_E_INVAL, "mrf_op_forward: null X or R");
   hipStream_t s = static_cast<hipStream_t>(stream);
   mrf_dict_s &ws = op_scratch();
-  const int64_t npairs = (int64_t)A->nslices * A->L;
-  TRY(grow(ws.red, (size_t)(npairs + 8) * 8));
+  const int64_t nvpairs = dims_of(A).nvpairs;
+  TRY(grow(ws.red, (size_t)(nvpairs + 8) * 8));
   TRY(forward_into(&ws, A, static_cast<const float2 *>(X), static_cast<const float2 *>(Y),
                    static_cast<float2 *>(R), ws.red.as<double>(), s));
   if (wnorm2) {
     TRY(grow(ws.scal, 64));
-    launch_reduce_sum(ws.red.as<double>(), npairs, ws.scal.as<double>(), s);
+    launch_reduce_sum(ws.red.as<double>(), nvpairs, ws.scal.as<double>(), s);
     LAUNCH_CHECK("reduce_sum");
     HIP_TRY(hipMemcpyAsync(wnorm2, ws.scal.p, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -554,7 +592,7 @@ extern "C" mrf_status mrf_op_adjoint(const mrf_op *A, const void *R, int32_t app
   TRY(check_op(A));
   if (!R || !G) return fail(MRF_E_INVAL, "mrf_op_adjoint: null R or G");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return adjoint_into(A, static_cast<const float2 *>(R), apply_dcf ? A->dcf : nullptr,
+  return adjoint_into(&op_scratch(), A, static_cast<const float2 *>(R), apply_dcf ? A->dcf : nullptr,
                       static_cast<float2 *>(G), s);
 }
 
@@ -578,18 +616,21 @@ mrf_status check_step_args(mrf_dict_s *D, const mrf_op *A, const void *Y) {
 mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const float2 *X,
                  float mu, const int32_t *warm, float2 *X_new, int32_t *idx, float *pd,
                  float2 *R_update, hipStream_t s) {
-  const int64_t npix = (int64_t)A->nx * A->ny;
+  const OpDims od = dims_of(A);
+  const int64_t npix = od.npix;
   const int64_t n = (int64_t)A->nslices * npix;
-  const int64_t nimg = (int64_t)A->nslices * D->L;     // image frames (compressed frames if Lfull > 0)
-  const int64_t npairs = (int64_t)A->nslices * A->L;  // sampled (slice, frame) pairs
+  const int64_t nimg = (int64_t)A->nslices * D->L;   // image frames (compressed frames if Lfull > 0)
+  const int64_t nkimg = nimg * od.nc;                // k-space images (slice, coil, frame)
+  const int64_t nvp = od.nvpairs;                    // sampled (slice, coil, frame) pairs
   const int64_t n_pad = round_up(n, kRowPad);
   const int real = D->is_complex ? 0 : 1;
   TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
   TRY(grow(D->znorm, (size_t)n_pad * 4));
   TRY(grow(D->counters, 64));
   TRY(grow(D->kbuf, (size_t)nimg * npix * 8));
-  TRY(grow(D->abuf, (size_t)(A->nsamples > 0 ? A->nsamples : 1) * 8));
-  TRY(grow(D->red, (size_t)(8192 + 2 * npairs + 8) * 8));
+  if (od.maps) TRY(grow(D->cbuf, (size_t)nkimg * npix * 8));
+  TRY(grow(D->abuf, (size_t)(od.nsamp > 0 ? od.nsamp : 1) * 8));
+  TRY(grow(D->red, (size_t)(8192 + 2 * nvp + 8) * 8));
   TRY(grow(D->scal, 64));
   launch_zero(D->counters.p, 16, s);
   launch_pack_frame_major(X, D->gbuf.as<float2>(), mu, n, n_pad, npix, D->L, real, D->Kp,
@@ -603,20 +644,27 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
                  X_new, X, D->kbuf.as<float2>(), red, &nb, s);
   LAUNCH_CHECK("write_x");
   launch_reduce_sum(red, nb, D->scal.as<double>() + 0, s);
-  launch_fft2(D->kbuf.as<float2>(), nimg, A->ny, A->nx, 0, s);
+  // A dX: dX sits in kbuf (coil copies in cbuf with coil maps)
+  float2 *K = D->kbuf.as<float2>();
+  if (od.maps) {
+    launch_coil_expand(D->kbuf.as<float2>(), od.maps, A->nslices, od.nc, D->L, npix, D->cbuf.as<float2>(), s);
+    LAUNCH_CHECK("coil expand(dX)");
+    K = D->cbuf.as<float2>();
+  }
+  launch_fft2(K, nkimg, A->ny, A->nx, 0, s);
   LAUNCH_CHECK("fft2(dX)");
   if (D->Lfull > 0)
-    launch_sample_sub(D->kbuf.as<float2>(), npix, A->L, D->L, D->Vs.as<float2>(), A->samp_off, A->samp_idx,
-                      nullptr, A->dcf, D->abuf.as<float2>(), nullptr, (int)npairs, A->nsamples, s);
+    launch_sample_sub(K, npix, A->L, D->L, D->Vs.as<float2>(), A->samp_off, A->samp_idx, nullptr, A->dcf,
+                      D->abuf.as<float2>(), nullptr, (int)nvp, A->nsamples, od.nc, s);
   else
-    launch_sample(D->kbuf.as<float2>(), npix, A->samp_off, A->samp_idx, nullptr, A->dcf,
-                  D->abuf.as<float2>(), nullptr, (int)npairs, A->nsamples, s);
+    launch_sample(K, npix, A->samp_off, A->samp_idx, nullptr, A->dcf, D->abuf.as<float2>(), nullptr, (int)nvp,
+                  A->nsamples, A->L, od.nc, s);
   LAUNCH_CHECK("sample(dX)");
-  launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)npairs,
-                    A->nsamples, red + 8192, red + 8192 + npairs, R_update, s);
+  launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)nvp, A->nsamples,
+                    A->L, od.nc, red + 8192, red + 8192 + nvp, R_update, s);
   LAUNCH_CHECK("step_norms");
-  launch_reduce_sum(red + 8192, npairs, D->scal.as<double>() + 1, s);
-  launch_reduce_sum(red + 8192 + npairs, npairs, D->scal.as<double>() + 2, s);
+  launch_reduce_sum(red + 8192, nvp, D->scal.as<double>() + 1, s);
+  launch_reduce_sum(red + 8192 + nvp, nvp, D->scal.as<double>() + 2, s);
   LAUNCH_CHECK("reduce_sum");
   return MRF_OK;
 }
@@ -624,18 +672,17 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
 // R = A X - Y into rbuf, ||R||_W^2 into scal[3]; G = A^H W R into gbuf.
 mrf_status residual_and_gradient(mrf_dict_s *D, const mrf_op *A, const float2 *X,
                                  const float2 *Y, bool gradient, hipStream_t s) {
-  const int64_t npix = (int64_t)A->nx * A->ny;
+  const OpDims od = dims_of(A);
   const int64_t nimg = (int64_t)A->nslices * D->L;
-  const int64_t npairs = (int64_t)A->nslices * A->L;
-  TRY(grow(D->rbuf, (size_t)(A->nsamples > 0 ? A->nsamples : 1) * 8));
-  TRY(grow(D->gbuf, (size_t)nimg * npix * 8));
-  TRY(grow(D->red, (size_t)(8192 + 2 * npairs + 8) * 8));
+  TRY(grow(D->rbuf, (size_t)(od.nsamp > 0 ? od.nsamp : 1) * 8));
+  TRY(grow(D->gbuf, (size_t)nimg * od.npix * 8));
+  TRY(grow(D->red, (size_t)(8192 + 2 * od.nvpairs + 8) * 8));
   TRY(grow(D->scal, 64));
   double *red = D->red.as<double>();
   TRY(forward_into(D, A, X, Y, D->rbuf.as<float2>(), red + 8192, s, D));
-  launch_reduce_sum(red + 8192, npairs, D->scal.as<double>() + 3, s);
+  launch_reduce_sum(red + 8192, od.nvpairs, D->scal.as<double>() + 3, s);
   LAUNCH_CHECK("reduce_sum");
-  if (gradient) TRY(adjoint_into(A, D->rbuf.as<float2>(), A->dcf, D->gbuf.as<float2>(), s, D));
+  if (gradient) TRY(adjoint_into(D, A, D->rbuf.as<float2>(), A->dcf, D->gbuf.as<float2>(), s, D));
   return MRF_OK;
 }
 
@@ -698,8 +745,9 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t npix = (int64_t)A->nx * A->ny;
   const int64_t n = (int64_t)A->nslices * npix;
-  const int64_t nimg = (int64_t)A->nslices * D->L;     // image frames (compressed frames if Lfull > 0)
-  const int64_t npairs = (int64_t)A->nslices * A->L;  // sampled (slice, frame) pairs
+  const int64_t nimg = (int64_t)A->nslices * D->L;  // image frames (compressed frames if Lfull > 0)
+  const OpDims od = dims_of(A);
+  const int64_t nvp = od.nvpairs;                   // sampled (slice, coil, frame) pairs
   const float2 *Yc = static_cast<const float2 *>(Y);
   TRY(grow(D->xbuf, (size_t)nimg * npix * 8));
   TRY(grow(D->idxbuf, (size_t)n * 4));
@@ -727,7 +775,7 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
   bool have_idx = false;
   float mu_init = o->mu0;
   for (int k = 0; k < o->max_iter; ++k) {
-    TRY(adjoint_into(A, D->rbuf.as<float2>(), A->dcf, D->gbuf.as<float2>(), s, D));
+    TRY(adjoint_into(D, A, D->rbuf.as<float2>(), A->dcf, D->gbuf.as<float2>(), s, D));
     float mu = mu_init;
     int shrinks = 0;
     double dx2 = 0, adx2 = 0, f_new = 0;
@@ -747,8 +795,8 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
                     o->max_shrinks, k);
     }
     // accept: R <- R + A dX (abuf holds A dX), swap iterates
-    launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)npairs,
-                      A->nsamples, D->red.as<double>() + 8192, D->red.as<double>() + 8192 + npairs,
+    launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)nvp, A->nsamples,
+                      A->L, od.nc, D->red.as<double>() + 8192, D->red.as<double>() + 8192 + nvp,
                       D->rbuf.as<float2>(), s);
     LAUNCH_CHECK("residual update");
     std::swap(cur, nxt);
@@ -761,9 +809,9 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
       A0.dcf = nullptr;
       double *red = D->red.as<double>();
       TRY(forward_into(D, &A0, cur, nullptr, D->abuf.as<float2>(), red + 8192, s, D));
-      launch_reduce_sum(red + 8192, npairs, D->scal.as<double>() + 4, s);
+      launch_reduce_sum(red + 8192, nvp, D->scal.as<double>() + 4, s);
       int nb = 0;
-      launch_norm2(Yc, A->nsamples, red, &nb, s);
+      launch_norm2(Yc, od.nsamp, red, &nb, s);
       launch_reduce_sum(red, nb, D->scal.as<double>() + 5, s);
       LAUNCH_CHECK("kappa norms");
       TRY(read_scalars(D, 6, s));

@@ -90,26 +90,42 @@ void launch_quantize_rows(const float *in, int64_t rows, int K, int64_t in_pitch
 // In-place unitary 2-D DFT of `nimg` frames of ny x nx complex64 (forward:
 // exp(-2 pi i k.r/N), inverse: conjugate), each 1-D pass scaled by 1/sqrt(N).
 void launch_fft2(float2 *data, int64_t nimg, int ny, int nx, int inverse, hipStream_t s);
-// R[i] = K[pair image][idx[i]] - Y[i] (Y may be null); part[p] = sum_i w_i |R_i|^2
-// over the samples of pair p (w = 1 when dcf is null).
+// Sampling with c coils: the images are [S][c][L][npix] and the virtual
+// pairs pv = (slice * c + coil) * L + frame share the CSR pattern of pair
+// slice * L + frame; sample arrays (Y, R, A) are coil-major [c][M] while
+// the weights w [M] are shared by all coils (c = 1: the single-coil case).
+// R[i] = K[pv image][idx[i]] - Y[i] (Y may be null); part[pv] = sum_i w_i |R_i|^2
+// over the samples of virtual pair pv (w = 1 when dcf is null).
 // Sample ranges are clamped to [0, M) and indices outside [0, npix) read as
 // zero (scatter: are skipped), so malformed patterns cannot address outside
 // the buffers.
 void launch_sample(const float2 *K, int64_t npix, const int64_t *off, const int32_t *sidx,
-                   const float2 *Y, const float *w, float2 *R, double *part, int npairs,
-                   int64_t M, hipStream_t s);
-// K zero-filled, then K[pair image][idx[i]] = w_i R_i (w = 1 when null).
+                   const float2 *Y, const float *w, float2 *R, double *part, int nvpairs,
+                   int64_t M, int L, int ncoil, hipStream_t s);
+// K zero-filled (total complex elements), then K[pv image][idx[i]] = w_i R_i (w = 1 when null).
 void launch_scatter(const float2 *R, const float *w, const int64_t *off, const int32_t *sidx,
-                    float2 *K, int64_t npix, int npairs, int64_t total, int64_t M, hipStream_t s);
+                    float2 *K, int64_t npix, int nvpairs, int64_t total, int64_t M, int L, int ncoil,
+                    hipStream_t s);
+// part_a[pv] = sum w|A|^2 and part_ra[pv] = sum w|R + A|^2 per virtual pair; optionally R += A.
+void launch_step_norms(const float2 *R, const float2 *A, const float *w, const int64_t *off,
+                       int nvpairs, int64_t M, int L, int ncoil, double *part_a, double *part_ra,
+                       float2 *R_update, hipStream_t s);
+// Coil sensitivities maps [S][c][npix]: out [S][c][F][npix] = S_q X_f, and
+// G [S][F][npix] = sum_q conj(S_q) Gc [S][c][F][npix] (coils in order).
+void launch_coil_expand(const float2 *X, const float2 *maps, int S, int ncoil, int F, int64_t npix, float2 *out,
+                        hipStream_t s);
+void launch_coil_combine(const float2 *Gc, const float2 *maps, int S, int ncoil, int F, int64_t npix, float2 *G,
+                         hipStream_t s);
 // Temporal subspace (V: FP32 complex [L][sdim], frame-major rows).
 // out[r][t] = row r of the FP32 normalised atoms widened to FP64 complex.
 void launch_widen(const float *dhat, int Kp, int is_complex, int64_t rows, int L, double2 *out, hipStream_t s);
 // As launch_sample, with the pair image formed from the sdim compressed
-// k-space images of its slice, Kc [S][sdim][npix]: sum_k V[t, k] Kc_k.
+// k-space images of its (slice, coil), Kc [S][c][sdim][npix]: sum_k V[t, k] Kc_k.
 void launch_sample_sub(const float2 *Kc, int64_t npix, int L, int sdim, const float2 *V, const int64_t *off,
-                       const int32_t *sidx, const float2 *Y, const float *w, float2 *R, double *part, int npairs,
-                       int64_t M, hipStream_t s);
-// Kc [S][sdim][npix] = per pixel sum_t conj(V[t, k]) Kfull [S][L][npix].
+                       const int32_t *sidx, const float2 *Y, const float *w, float2 *R, double *part, int nvpairs,
+                       int64_t M, int ncoil, hipStream_t s);
+// Kc [S][sdim][npix] = per pixel sum_t conj(V[t, k]) Kfull [S][L][npix]
+// (S counts virtual slices: slice x coil).
 void launch_compress_frames(const float2 *Kfull, int64_t npix, int S, int L, int sdim, const float2 *V, float2 *Kc,
                             hipStream_t s);
 // part[p] = sum w|A|^2 and part2[p] = sum w|R + A|^2 per pair; optionally R += A.

@@ -94,7 +94,8 @@ class Op(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("nslices", ctypes.c_int32), ("nsamples", ctypes.c_int64),
                 ("samp_off", ctypes.c_void_p), ("samp_idx", ctypes.c_void_p),
-                ("dcf", ctypes.c_void_p)]
+                ("dcf", ctypes.c_void_p), ("ncoils", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("smaps", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -516,28 +517,45 @@ def mrf_net_train(net: Net, D: Dictionary, samples=2_000_000, batch=4096, epochs
 class Operator:
     """mrf_op over device copies of a CSR sampling pattern (see include/mrf.h)."""
 
-    def __init__(self, nx, ny, L, nslices, samp_off, samp_idx, dcf=None):
+    def __init__(self, nx, ny, L, nslices, samp_off, samp_idx, dcf=None, smaps=None):
+        """smaps: coil sensitivity maps [nslices][c][ny][nx] (complex), or None
+        for one coil with S = I; with c coils the sample arrays are [c][M]."""
         torch = _torch()
         self.off = torch.as_tensor(np.asarray(samp_off, dtype=np.int64)).cuda()
         self.idx = torch.as_tensor(np.asarray(samp_idx, dtype=np.int32)).cuda()
         self.dcf = None if dcf is None else torch.as_tensor(np.asarray(dcf, dtype=np.float32)).cuda()
         self.nx, self.ny, self.L, self.nslices = int(nx), int(ny), int(L), int(nslices)
         self.M = int(self.off[-1].item()) if self.off.numel() else 0
+        self.smaps = None
+        self.ncoils = 0
+        if smaps is not None:
+            sm = np.ascontiguousarray(np.asarray(smaps).astype(np.complex64))
+            assert sm.ndim == 4 and sm.shape[0] == self.nslices and sm.shape[2:] == (self.ny, self.nx)
+            self.smaps = torch.from_numpy(sm).cuda()
+            self.ncoils = int(sm.shape[1])
         self.c = Op(self.nx, self.ny, self.L, self.nslices, self.M, _dev(self.off),
-                    _dev(self.idx) if self.idx.numel() else None, _dev(self.dcf))
+                    _dev(self.idx) if self.idx.numel() else None, _dev(self.dcf), self.ncoils, 0,
+                    _dev(self.smaps))
 
     @property
     def n(self):
         return self.nslices * self.nx * self.ny
 
+    @property
+    def nsamp(self):
+        """Samples per sample array: M, or c*M with c coils (coil-major)."""
+        return max(self.ncoils, 1) * self.M
+
     @classmethod
-    def from_sampling(cls, smp):
-        return cls(smp.nx, smp.ny, smp.L, smp.S, smp.off, smp.idx, smp.dcf)
+    def from_sampling(cls, smp, smaps=None):
+        return cls(smp.nx, smp.ny, smp.L, smp.S, smp.off, smp.idx, smp.dcf, smaps=smaps)
 
 
 def mrf_op_forward(A: Operator, X, Y=None, want_norm=False, stream=None):
     torch = _torch()
-    R = torch.empty(max(A.M, 1), dtype=torch.complex64, device="cuda")[:A.M]
+    R = torch.empty(max(A.nsamp, 1), dtype=torch.complex64, device="cuda")[:A.nsamp]
+    if A.ncoils:
+        R = R.view(A.ncoils, A.M)
     nrm = ctypes.c_double(0.0)
     _check(lib().mrf_op_forward(ctypes.byref(A.c), _dev(X), _dev(Y), R.data_ptr(),
                                 ctypes.byref(nrm) if want_norm else None, _stream(stream)))
