@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fourier, mf, subspace
+from . import fourier, mf, phase, subspace
 
 
 class NoConvergence(RuntimeError):
@@ -36,11 +36,13 @@ def _weighted_sq(r: np.ndarray, w) -> float:
 
 
 def project(Z: np.ndarray, atoms: np.ndarray, warm_idx=None, X_prev=None,
-            nonexpansive: bool = False):
-    """Cone projection of a frame-major image Z [S][L][ny][nx]."""
+            nonexpansive: bool = False, u=None):
+    """Cone projection of a frame-major image Z [S][L][ny][nx]; with a phase
+    vector u, the phase-aligned projection (atoms are then the aligned ones)."""
     S, L, ny, nx = Z.shape
     Zv = fourier.frame_to_voxel(Z)
-    res = mf.exact_mf(Zv, atoms, warm_idx=warm_idx, want_X=True)
+    res = (mf.exact_mf(Zv, atoms, warm_idx=warm_idx, want_X=True) if u is None
+           else phase.project_aligned(Zv, atoms, u, warm_idx=warm_idx))
     Xv = res["X"]
     if nonexpansive and X_prev is not None:
         Xp = fourier.frame_to_voxel(X_prev)
@@ -77,17 +79,18 @@ def gradient(X, Y, off, idx, w, V=None, smaps=None):
 
 
 def ipg_step(Y, off, idx, atoms, X, mu: float, w=None, warm_idx=None,
-             nonexpansive: bool = False, V=None, smaps=None):
+             nonexpansive: bool = False, V=None, smaps=None, u=None):
     """One projected-gradient step at a fixed mu.  Returns (X', projection
     result, stats) with stats = dx2, adx2 (weighted), f_old, f_new.  With a
     temporal subspace V, X has s compressed frames, atoms are the compressed
     atoms and dx2 is the compressed norm (the compressed step rule).  With
-    coil maps, Y is [c][M]."""
+    coil maps, Y is [c][M].  With a phase vector u the projection is the
+    phase-aligned one (complex PD) over aligned atoms."""
     Y = np.asarray(Y, dtype=np.complex128)
     X = np.asarray(X, dtype=np.complex128)
     G, R = gradient(X, Y, off, idx, w, V, smaps)
     Z = X - mu * G
-    Xn, res = project(Z, atoms, warm_idx=warm_idx, X_prev=X, nonexpansive=nonexpansive)
+    Xn, res = project(Z, atoms, warm_idx=warm_idx, X_prev=X, nonexpansive=nonexpansive, u=u)
     dX = Xn - X
     AdX = op_forward(dX, off, idx, V, smaps)
     stats = dict(dx2=float(np.sum(np.abs(dX) ** 2)), adx2=_weighted_sq(AdX, w),
@@ -100,7 +103,7 @@ def ipg_step(Y, off, idx, atoms, X, mu: float, w=None, warm_idx=None,
 def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
               adaptive: bool = True, max_iter: int = 50, rel_tol: float = 1e-6,
               max_shrinks: int = 30, X0=None, w=None, kappa: bool = False,
-              nonexpansive: bool = False, V=None, smaps=None):
+              nonexpansive: bool = False, V=None, smaps=None, u=None):
     """Full reconstruction; dims = (S, L, ny, nx) (L = s compressed frames
     when a temporal subspace V is given).  Returns (X, idx, gamma, history)
     where history lists per accepted iteration: f (objective after the
@@ -119,7 +122,7 @@ def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
         shrinks = 0
         while True:
             Z = X - mu * G
-            Xn, res = project(Z, atoms, warm_idx=warm, X_prev=X, nonexpansive=nonexpansive)
+            Xn, res = project(Z, atoms, warm_idx=warm, X_prev=X, nonexpansive=nonexpansive, u=u)
             dX = Xn - X
             dx2 = float(np.sum(np.abs(dX) ** 2))
             adx2 = _weighted_sq(op_forward(dX, off, idx, V, smaps), w)
