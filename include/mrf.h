@@ -107,7 +107,7 @@ typedef struct {
   int64_t device_bytes; /* device memory held by the handle (excl. workspace) */
   int32_t L_full;       /* compressed dictionary (mrf_dict_compress): frames of the
                            uncompressed atoms, else 0 */
-  int32_t reserved;
+  int32_t phase_aligned; /* 1 for a phase-aligned dictionary (mrf_dict_align) */
 } mrf_dict_info;
 mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info);
 
@@ -144,6 +144,24 @@ mrf_status mrf_dict_copy_atoms(mrf_dict D, int32_t precision, void *dst, float *
  * compressed atom of zero norm), MRF_E_UNSUPPORTED (D already compressed),
  * MRF_E_NUMERIC (eigensolver failure), MRF_E_NOMEM, MRF_E_HIP. */
 mrf_status mrf_dict_compress(mrf_dict D, int32_t s, uint32_t flags, mrf_stream stream, mrf_dict *out);
+/* Phase alignment for a complex proton density (Section "CoverBLIP
+ * algorithm", the phase-alignment paragraph).  Builds a new handle *out of
+ * aligned atoms f_j Dhat_j: with u the first principal direction of D (the
+ * dominant eigenvector of sum_j Dhat_j Dhat_j^H with the phase convention
+ * of mrf_dict_compress; for a compressed D the first compressed coordinate)
+ * and c_j = u^H Dhat_j, f_j = conj(c_j)/|c_j| for complex atoms and the sign
+ * of Re c_j for real atoms (which stay real); f_j = 1 where c_j = 0.  Every
+ * matcher and the projected-gradient entry points then run the aligned
+ * projection: theta_v = angle(u^H Z_v), the search on Z_v e^{-i theta_v}
+ * against the aligned atoms, gamma_v as in eq. exactPs and
+ * X_v = gamma_v e^{i theta_v} f_j* Dhat_j*, i.e. the complex PD
+ * rho_v = gamma_v e^{i theta_v} f_j* (pd reports |rho_v| = gamma_v; its
+ * phase through mrf_match_opts.pd_phase).  A compressed D keeps its V.
+ * `flags` are the MRF_STORE_* / MRF_BUILD_COVERTREE flags of the new handle.
+ * Synchronises `stream`.  Errors: MRF_E_INVAL (null handle, unknown flags),
+ * MRF_E_UNSUPPORTED (D already aligned), MRF_E_NUMERIC, MRF_E_NOMEM,
+ * MRF_E_HIP. */
+mrf_status mrf_dict_align(mrf_dict D, uint32_t flags, mrf_stream stream, mrf_dict *out);
 /* V of a compressed handle into HOST `V` [L_full][s] complex (interleaved
  * FP64 pairs, row t = frame t) and its eigenvalues into HOST `lam` [s]
  * (descending); either may be NULL.  MRF_E_INVAL if C is not compressed. */
@@ -209,6 +227,10 @@ typedef struct {
   float eps;           /* MRF_COVERTREE: search inaccuracy eps >= 0 (Definition 3.1) */
   int32_t tree_capacity; /* MRF_COVERTREE: candidate-set capacity per query (0 = 1024);
                             queries that outgrow it use the exhaustive filter */
+  float *pd_phase;       /* DEVICE float [n] or NULL, mrf_match only: the phase (radians) of
+                            the complex PD rho_v on the normalised atom Dhat_j* with a
+                            phase-aligned dictionary (mrf_dict_align), 0 otherwise; the
+                            projected-gradient entry points ignore it (their X carries it) */
 } mrf_match_opts;
 
 typedef struct {

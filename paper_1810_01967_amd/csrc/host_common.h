@@ -124,6 +124,11 @@ struct mrf_dict_s {
   std::vector<double> V_host, lam;  // V (FP64 complex [Lfull][L], interleaved) and its eigenvalues
   mrf::DevBuf kfull;                // full-frame k-space of the compressed adjoint
   mrf::DevBuf cbuf;                 // per-coil images (coil maps)
+  // phase alignment (complex PD): first principal direction u [L] (FP32
+  // complex), per-atom alignment factors f_j [d] (aligned atom = f_j Dhat_j),
+  // per-voxel factors e^{i theta_v} of the last packing
+  int align = 0;
+  mrf::DevBuf u1, afac, vphase;
   mrf::DevBuf inv, h1, h2, yout, cells, best_s, best_j, bestkey, list_a, list_b, list_c, keys, hist, off, cnt, rows;
   // cover tree (host copy for export, device arrays for the traversal)
   bool has_tree = false;

@@ -22,7 +22,8 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
                                                           int64_t n_pad, int L, int real_atoms,
                                                           int Kp, float *__restrict__ Zp,
                                                           float *__restrict__ znorm,
-                                                          unsigned long long *counters) {
+                                                          unsigned long long *counters,
+                                                          const float2 *__restrict__ vphase) {
   const int lane = threadIdx.x & 63;
   const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (v >= n_pad) return;
@@ -33,9 +34,11 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
     return;
   }
   const float2 *z = Z + v * (int64_t)L;
+  const float2 e = vphase ? vphase[v] : make_float2(1.f, 0.f);  // rotate by conj(e)
   double acc = 0.0;
   for (int t = lane; t < L; t += 64) {
-    const float2 a = z[t];
+    const float2 z0 = z[t];
+    const float2 a = vphase ? make_float2(e.x * z0.x + e.y * z0.y, e.x * z0.y - e.y * z0.x) : z0;
     acc += (double)a.x * a.x + (double)a.y * a.y;
     if (real_atoms) {
       row[t] = a.x;
@@ -62,7 +65,8 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
                                                           int L, int real_atoms, int Kp,
                                                           float *__restrict__ Zp,
                                                           float *__restrict__ znorm,
-                                                          unsigned long long *counters) {
+                                                          unsigned long long *counters,
+                                                          const float2 *__restrict__ vphase) {
   __shared__ float2 tile[16][65];
   __shared__ double red[4][64];
   const int tid = threadIdx.x;
@@ -72,6 +76,7 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
   const bool valid = v < n;
   const int64_t sl = valid ? v / npix : 0;
   const int64_t p = valid ? v - sl * npix : 0;
+  const float2 ev = (vphase && valid) ? vphase[v] : make_float2(1.f, 0.f);  // rotate by conj(ev)
   double acc = 0.0;
   // writer mapping: 4 threads per voxel row, each 4 frames
   const int wv = tid >> 2, wp = tid & 3;
@@ -89,6 +94,7 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
           z.x = z.x - mu * g.x;
           z.y = z.y - mu * g.y;
         }
+        if (vphase) z = make_float2(ev.x * z.x + ev.y * z.y, ev.x * z.y - ev.y * z.x);
         acc += (double)z.x * z.x + (double)z.y * z.y;
       }
       tile[f][vi] = z;
@@ -134,22 +140,22 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
 
 void launch_pack_voxel_major(const float2 *Z, int64_t n, int64_t n_pad, int L, int real_atoms,
                              int Kp, float *Zp, float *znorm, unsigned long long *counters,
-                             hipStream_t s) {
+                             hipStream_t s, const float2 *vphase) {
   const int64_t blocks = (n_pad + 3) / 4;
   hipLaunchKernelGGL(k_pack_voxel_major, dim3((unsigned)blocks), dim3(256), 0, s, Z, n, n_pad, L,
-                     real_atoms, Kp, Zp, znorm, counters);
+                     real_atoms, Kp, Zp, znorm, counters, vphase);
 }
 
 void launch_pack_frame_major(const float2 *X, const float2 *G, float mu, int64_t n, int64_t n_pad,
                              int64_t npix, int L, int real_atoms, int Kp, float *Zp, float *znorm,
-                             unsigned long long *counters, hipStream_t s) {
+                             unsigned long long *counters, hipStream_t s, const float2 *vphase) {
   const int64_t blocks = (n_pad + 63) / 64;
   if (G)
     hipLaunchKernelGGL(k_pack_frame_major<true>, dim3((unsigned)blocks), dim3(256), 0, s, X, G,
-                       mu, n, n_pad, npix, L, real_atoms, Kp, Zp, znorm, counters);
+                       mu, n, n_pad, npix, L, real_atoms, Kp, Zp, znorm, counters, vphase);
   else
     hipLaunchKernelGGL(k_pack_frame_major<false>, dim3((unsigned)blocks), dim3(256), 0, s, X,
-                       nullptr, 0.f, n, n_pad, npix, L, real_atoms, Kp, Zp, znorm, counters);
+                       nullptr, 0.f, n, n_pad, npix, L, real_atoms, Kp, Zp, znorm, counters, vphase);
 }
 
 // ---------------------------------------------------------------------------
@@ -483,7 +489,8 @@ __global__ __launch_bounds__(256) void k_write_x(const int32_t *__restrict__ idx
                                                  int real_atoms, int64_t n, int L, int64_t npix,
                                                  float2 *__restrict__ X,
                                                  const float2 *__restrict__ X_prev,
-                                                 float2 *__restrict__ dX, double *part) {
+                                                 float2 *__restrict__ dX, double *part,
+                                                 const float2 *__restrict__ vphase) {
   __shared__ double red[256];
   const int64_t total = n * L;
   double acc = 0.0;
@@ -513,6 +520,10 @@ __global__ __launch_bounds__(256) void k_write_x(const int32_t *__restrict__ idx
         x.x = g * c.x;
         x.y = g * c.y;
       }
+      if (vphase) {  // phase-aligned projection: X_v = gamma e^{i theta_v} Dhat^a_j
+        const float2 ph = vphase[v];
+        x = make_float2(ph.x * x.x - ph.y * x.y, ph.x * x.y + ph.y * x.x);
+      }
     }
     X[e] = x;
     if (DELTA) {
@@ -536,7 +547,7 @@ __global__ __launch_bounds__(256) void k_write_x(const int32_t *__restrict__ idx
 void launch_write_x(const int32_t *idx, const float *gamma_hat, const float *D, int Kp,
                     int real_atoms, int64_t n, int L, int frame_major, int64_t npix, float2 *X,
                     const float2 *X_prev, float2 *dX, double *part, int *nblocks_out,
-                    hipStream_t s) {
+                    hipStream_t s, const float2 *vphase) {
   const int64_t total = n * (int64_t)L;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 8192) blocks = 8192;
@@ -544,13 +555,13 @@ void launch_write_x(const int32_t *idx, const float *gamma_hat, const float *D, 
   if (frame_major) {
     if (X_prev)
       hipLaunchKernelGGL((k_write_x<true, true>), dim3((unsigned)blocks), dim3(256), 0, s, idx,
-                         gamma_hat, D, Kp, real_atoms, n, L, npix, X, X_prev, dX, part);
+                         gamma_hat, D, Kp, real_atoms, n, L, npix, X, X_prev, dX, part, vphase);
     else
       hipLaunchKernelGGL((k_write_x<true, false>), dim3((unsigned)blocks), dim3(256), 0, s, idx,
-                         gamma_hat, D, Kp, real_atoms, n, L, npix, X, nullptr, nullptr, nullptr);
+                         gamma_hat, D, Kp, real_atoms, n, L, npix, X, nullptr, nullptr, nullptr, vphase);
   } else {
     hipLaunchKernelGGL((k_write_x<false, false>), dim3((unsigned)blocks), dim3(256), 0, s, idx,
-                       gamma_hat, D, Kp, real_atoms, n, L, npix, X, nullptr, nullptr, nullptr);
+                       gamma_hat, D, Kp, real_atoms, n, L, npix, X, nullptr, nullptr, nullptr, vphase);
   }
 }
 

@@ -215,7 +215,7 @@ extern "C" mrf_status mrf_dict_query(mrf_dict D, mrf_dict_info *info) {
   info->flags = D->flags;
   info->device_bytes = D->bytes;
   info->L_full = D->Lfull;
-  info->reserved = 0;
+  info->phase_aligned = D->align;
   return MRF_OK;
 }
 
@@ -384,14 +384,25 @@ mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t s
   TRY(grow(D->counters, 64));  // [0] zero rows, [1] non-finite rows, [2] local-search work
   launch_zero(D->counters.p, 16, s);
   const int real = D->is_complex ? 0 : 1;
+  const float2 *vph = nullptr;
+  if (D->align) {  // phase-aligned dictionary: voxel phases first, packed rotated
+    TRY(grow(D->vphase, (size_t)n * 8));
+    if (z_layout == MRF_VOXEL_MAJOR)
+      launch_voxel_phase(static_cast<const float2 *>(Z), n, D->L, D->u1.as<float2>(), D->vphase.as<float2>(), s);
+    else
+      launch_voxel_phase_frames(static_cast<const float2 *>(Z), nullptr, 0.f, n, slice_voxels, D->L,
+                                D->u1.as<float2>(), D->vphase.as<float2>(), s);
+    LAUNCH_CHECK("voxel phase");
+    vph = D->vphase.as<float2>();
+  }
   if (z_layout == MRF_VOXEL_MAJOR)
     launch_pack_voxel_major(static_cast<const float2 *>(Z), n, n_pad, D->L, real, D->Kp,
                             D->zp.as<float>(), D->znorm.as<float>(),
-                            D->counters.as<unsigned long long>(), s);
+                            D->counters.as<unsigned long long>(), s, vph);
   else
     launch_pack_frame_major(static_cast<const float2 *>(Z), nullptr, 0.f, n, n_pad, slice_voxels,
                             D->L, real, D->Kp, D->zp.as<float>(), D->znorm.as<float>(),
-                            D->counters.as<unsigned long long>(), s);
+                            D->counters.as<unsigned long long>(), s, vph);
   LAUNCH_CHECK("pack");
   return MRF_OK;
 }
@@ -427,11 +438,19 @@ extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t 
   TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s));
   int splits_used = 0;
   TRY(match_core(D, opts, n, warm_idx, idx, pd, corr, params_out, s, ev.c, ev.d, &splits_used, stats));
+  const float2 *vph = D->align ? D->vphase.as<float2>() : nullptr;
   if (X_out) {
     launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, real, n, D->L,
                    z_layout == MRF_FRAME_MAJOR, slice_voxels, static_cast<float2 *>(X_out),
-                   nullptr, nullptr, nullptr, nullptr, s);
+                   nullptr, nullptr, nullptr, nullptr, s, vph);
     LAUNCH_CHECK("write_x");
+  }
+  if (opts && opts->pd_phase) {
+    if (vph)
+      launch_pd_phase(idx, vph, D->afac.as<float2>(), n, opts->pd_phase, s);
+    else
+      launch_zero(opts->pd_phase, n * (int64_t)sizeof(float), s);  // real, non-negative PD
+    LAUNCH_CHECK("pd phase");
   }
   if (stats) {
     HIP_TRY(hipEventRecord(ev.b, s));
@@ -633,15 +652,23 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
   TRY(grow(D->red, (size_t)(8192 + 2 * nvp + 8) * 8));
   TRY(grow(D->scal, 64));
   launch_zero(D->counters.p, 16, s);
+  const float2 *vph = nullptr;
+  if (D->align) {  // phase-aligned projection of Z = X - mu G
+    TRY(grow(D->vphase, (size_t)n * 8));
+    launch_voxel_phase_frames(X, D->gbuf.as<float2>(), mu, n, npix, D->L, D->u1.as<float2>(),
+                              D->vphase.as<float2>(), s);
+    LAUNCH_CHECK("voxel phase");
+    vph = D->vphase.as<float2>();
+  }
   launch_pack_frame_major(X, D->gbuf.as<float2>(), mu, n, n_pad, npix, D->L, real, D->Kp,
                           D->zp.as<float>(), D->znorm.as<float>(),
-                          D->counters.as<unsigned long long>(), s);
+                          D->counters.as<unsigned long long>(), s, vph);
   LAUNCH_CHECK("grad_update_pack");
   TRY(match_core(D, o, n, warm, idx, pd, nullptr, nullptr, s, nullptr, nullptr, nullptr, nullptr));
   double *red = D->red.as<double>();
   int nb = 0;
   launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, real, n, D->L, 1, npix,
-                 X_new, X, D->kbuf.as<float2>(), red, &nb, s);
+                 X_new, X, D->kbuf.as<float2>(), red, &nb, s, vph);
   LAUNCH_CHECK("write_x");
   launch_reduce_sum(red, nb, D->scal.as<double>() + 0, s);
   // A dX: dX sits in kbuf (coil copies in cbuf with coil maps)

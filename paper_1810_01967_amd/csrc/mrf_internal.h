@@ -37,12 +37,23 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // -1 for a non-finite row.  counters[0] += zero rows, counters[1] += non-finite.
 // Frame-major input: Zf[s][L][npix]; with G != nullptr the packed value is
 // X - mu*G (the gradient update of eq. blip), G in the same layout as X.
+// vphase (optional, [n]): unit factors e^{i theta_v}; each voxel is packed
+// rotated by conj(vphase[v]) (phase-aligned projection).
 void launch_pack_voxel_major(const float2 *Z, int64_t n, int64_t n_pad, int L, int real_atoms,
                              int Kp, float *Zp, float *znorm, unsigned long long *counters,
-                             hipStream_t s);
+                             hipStream_t s, const float2 *vphase = nullptr);
 void launch_pack_frame_major(const float2 *X, const float2 *G, float mu, int64_t n, int64_t n_pad,
                              int64_t npix, int L, int real_atoms, int Kp, float *Zp, float *znorm,
-                             unsigned long long *counters, hipStream_t s);
+                             unsigned long long *counters, hipStream_t s, const float2 *vphase = nullptr);
+// Phase alignment: vphase[v] = c_v/|c_v| with c_v = u^H Z_v accumulated in
+// FP64 ((1, 0) where c_v is 0 or not finite); Z voxel-major [n][L], or
+// frame-major X - mu G (G may be null) over slices of npix voxels.
+void launch_voxel_phase(const float2 *Z, int64_t n, int L, const float2 *u, float2 *vphase, hipStream_t s);
+void launch_voxel_phase_frames(const float2 *X, const float2 *G, float mu, int64_t n, int64_t npix, int L,
+                               const float2 *u, float2 *vphase, hipStream_t s);
+// out[v] = arg(vphase[v] * afac[idx[v]]) (0 where idx < 0): the phase of the complex PD.
+void launch_pd_phase(const int32_t *idx, const float2 *vphase, const float2 *afac, int64_t n, float *out,
+                     hipStream_t s);
 
 // Exhaustive FP32 scoring with fused per-voxel argmax.  D: [d_pad][Kp] FP32
 // normalised atoms; Zp: [n_pad][Kp].  Writes per-split (score, index) partials
@@ -80,7 +91,7 @@ void launch_merge_rescore(const float *cand_s, const int *cand_j, int splits, in
 void launch_write_x(const int32_t *idx, const float *gamma_hat, const float *D, int Kp,
                     int real_atoms, int64_t n, int L, int frame_major, int64_t npix,
                     float2 *X, const float2 *X_prev, float2 *dX, double *part, int *nblocks_out,
-                    hipStream_t s);
+                    hipStream_t s, const float2 *vphase = nullptr);
 
 // BF16 / FP8 row encoders (see mrf_quantize_rows).
 void launch_quantize_rows(const float *in, int64_t rows, int K, int64_t in_pitch, int precision,

@@ -709,7 +709,7 @@ extern "C" mrf_status mrf_match_local(mrf_dict D, const mrf_match_opts *opts, in
   if (X_out) {
     launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, D->is_complex ? 0 : 1, n, D->L,
                    z_layout == MRF_FRAME_MAJOR, slice_voxels, static_cast<float2 *>(X_out), nullptr,
-                   nullptr, nullptr, nullptr, s);
+                   nullptr, nullptr, nullptr, s, D->align ? D->vphase.as<float2>() : nullptr);
     LAUNCH_CHECK("write_x");
   }
   if (stats) {

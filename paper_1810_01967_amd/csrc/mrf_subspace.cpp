@@ -1,4 +1,6 @@
-// Temporal subspace compression of a dictionary (Section "Dimension-reduced
+// Temporal subspace compression and phase alignment of a dictionary.
+//
+// Compression (Section "Dimension-reduced
 // subspace matched-filtering", eq. CS1): V_s = the s dominant eigenvectors of
 // sum_j Dhat_j Dhat_j^H over the device's FP32 normalised atoms widened to
 // FP64, each multiplied by the unit phase that makes its entry of largest
@@ -10,6 +12,13 @@
 // The Gram matrix (zherk over row chunks), its eigendecomposition (zheevd)
 // and the compression (zgemm) run on the device in FP64 through
 // rocBLAS / rocSOLVER: a one-off build step, not part of the iteration.
+//
+// Phase alignment (Section "CoverBLIP algorithm", the phase-alignment
+// paragraph): with u the first principal direction (the first compressed
+// coordinate for a compressed dictionary), each atom is rotated so that its
+// coefficient u^H Dhat_j becomes real non-negative (real atoms: flipped by
+// the sign), and the handle keeps u and the factors for the voxel alignment
+// of every projection.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -44,26 +53,19 @@ constexpr int64_t kChunkRows = 32768;
 
 }  // namespace
 
-extern "C" mrf_status mrf_dict_compress(mrf_dict D, int32_t s_dim, uint32_t flags, mrf_stream stream,
-                                        mrf_dict *out) {
-  last_error().clear();
-  if (!D || !out) return fail(MRF_E_INVAL, "mrf_dict_compress: null argument");
-  if (D->Lfull > 0) return fail(MRF_E_UNSUPPORTED, "mrf_dict_compress: dictionary is already compressed");
+namespace {
+
+// The s dominant eigenvectors of sum_j Dhat_j Dhat_j^H over D's FP32
+// normalised atoms widened to FP64 (column-major L x s in Vcol, row-major
+// interleaved [L][s] in Vh, eigenvalues in lam, decreasing), each with the
+// phase that makes its largest-magnitude entry real positive.
+mrf_status dominant_basis(mrf_dict_s *D, int s_dim, hipStream_t st, rocblas_handle h,
+                          std::vector<std::complex<double>> &Vcol, std::vector<double> &Vh,
+                          std::vector<double> &lam) {
   const int L = D->L;
-  if (s_dim < 1 || s_dim > L || s_dim > kMaxSubspace)
-    return fail(MRF_E_INVAL, "mrf_dict_compress: s=%d not in 1..min(L=%d, %d)", s_dim, L, kMaxSubspace);
-  if (flags & ~(uint32_t)(MRF_STORE_BF16 | MRF_STORE_FP8 | MRF_BUILD_COVERTREE))
-    return fail(MRF_E_INVAL, "mrf_dict_compress: unknown flags 0x%x", flags);
-  hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t d = D->d;
   const int64_t chunk = std::min<int64_t>(kChunkRows, d);
-
-  Blas blas;
-  BLAS_TRY(rocblas_create_handle(&blas.h));
-  BLAS_TRY(rocblas_set_stream(blas.h, st));
-  BLAS_TRY(rocblas_set_pointer_mode(blas.h, rocblas_pointer_mode_host));
-
-  DevBuf W, G, ev, E, info, Vc, Out;
+  DevBuf W, G, ev, E, info;
   TRY(grow(W, (size_t)chunk * L * sizeof(double2)));
   TRY(grow(G, (size_t)L * L * sizeof(double2)));
   TRY(grow(ev, (size_t)L * sizeof(double)));
@@ -78,7 +80,7 @@ extern "C" mrf_status mrf_dict_compress(mrf_dict D, int32_t s_dim, uint32_t flag
     LAUNCH_CHECK("widen");
     if (r0 == 0) HIP_TRY(hipMemsetAsync(G.p, 0, (size_t)L * L * sizeof(double2), st));
     const double one = 1.0, beta = r0 == 0 ? 0.0 : 1.0;
-    BLAS_TRY(rocblas_zherk(blas.h, rocblas_fill_lower, rocblas_operation_none, L, (rocblas_int)rows, &one,
+    BLAS_TRY(rocblas_zherk(h, rocblas_fill_lower, rocblas_operation_none, L, (rocblas_int)rows, &one,
                            W.as<rocblas_double_complex>(), L, &beta, G.as<rocblas_double_complex>(), L));
   }
   // sanity: trace(G) = sum_j ||Dhat_j||^2, which is d up to FP32 rounding
@@ -89,7 +91,7 @@ extern "C" mrf_status mrf_dict_compress(mrf_dict D, int32_t s_dim, uint32_t flag
   for (int t = 0; t < L; ++t) trace += U[(size_t)t * L + t].real();
   const std::vector<std::complex<double>> Gh = U;
   if (!(std::fabs(trace - (double)d) <= 1e-4 * (double)d))
-    return fail(MRF_E_NUMERIC, "mrf_dict_compress: Gram trace %.9g differs from the atom count %lld", trace,
+    return fail(MRF_E_NUMERIC, "dictionary basis: Gram trace %.9g differs from the atom count %lld", trace,
                 (long long)d);
   // Eigendecomposition (ascending eigenvalues, eigenvectors in the columns):
   // QR iteration (zheev) first; each result is checked (all selected columns
@@ -136,15 +138,15 @@ extern "C" mrf_status mrf_dict_compress(mrf_dict D, int32_t s_dim, uint32_t flag
     rocblas_int inf = 0;
     const char *name = method == 0 ? "zheev" : method == 1 ? "zheevd" : "zheevj";
     if (method == 0) {
-      BLAS_TRY(rocsolver_zheev(blas.h, rocblas_evect_original, rocblas_fill_lower, L, G.as<rocblas_double_complex>(),
+      BLAS_TRY(rocsolver_zheev(h, rocblas_evect_original, rocblas_fill_lower, L, G.as<rocblas_double_complex>(),
                                L, ev.as<double>(), E.as<double>(), info.as<rocblas_int>()));
     } else if (method == 1) {
-      BLAS_TRY(rocsolver_zheevd(blas.h, rocblas_evect_original, rocblas_fill_lower, L,
+      BLAS_TRY(rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_lower, L,
                                 G.as<rocblas_double_complex>(), L, ev.as<double>(), E.as<double>(),
                                 info.as<rocblas_int>()));
     } else {
       TRY(grow(E, (size_t)std::max(L, 2) * sizeof(double)));
-      BLAS_TRY(rocsolver_zheevj(blas.h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_lower, L,
+      BLAS_TRY(rocsolver_zheevj(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_lower, L,
                                 G.as<rocblas_double_complex>(), L, 0.0, E.as<double>(), 100,
                                 E.as<rocblas_int>() + 2, ev.as<double>(), info.as<rocblas_int>()));
     }
@@ -160,11 +162,12 @@ extern "C" mrf_status mrf_dict_compress(mrf_dict D, int32_t s_dim, uint32_t flag
     }
     ok = validate(name);
   }
-  if (!ok) return fail(MRF_E_NUMERIC, "mrf_dict_compress: no eigensolver result passed the checks (%s)", why.c_str());
+  if (!ok) return fail(MRF_E_NUMERIC, "dictionary basis: no eigensolver result passed the checks (%s)", why.c_str());
 
   // eigenvalues ascending -> the s largest in descending order, phase fixed
-  std::vector<double> Vh((size_t)L * s_dim * 2), lam((size_t)s_dim);
-  std::vector<std::complex<double>> Vcol((size_t)L * s_dim);  // column-major L x s for the compression
+  Vh.assign((size_t)L * s_dim * 2, 0.0);
+  lam.assign((size_t)s_dim, 0.0);
+  Vcol.assign((size_t)L * s_dim, 0.0);
   for (int k = 0; k < s_dim; ++k) {
     const int c = L - 1 - k;
     lam[(size_t)k] = lam_all[(size_t)c];
@@ -188,19 +191,32 @@ extern "C" mrf_status mrf_dict_compress(mrf_dict D, int32_t s_dim, uint32_t flag
     }
   }
 
+  return MRF_OK;
+}
+
+// At [d][s] (interleaved FP64 complex) = V^H Dhat_j for every atom, V the
+// column-major L x s matrix Vcol; the first and last rows are checked against
+// a host FP64 product.
+mrf_status project_rows(mrf_dict_s *D, const std::vector<std::complex<double>> &Vcol, int s_dim, hipStream_t st,
+                        rocblas_handle h, std::vector<double> &At) {
+  const int L = D->L;
+  const int64_t d = D->d;
+  const int64_t chunk = std::min<int64_t>(kChunkRows, d);
+  DevBuf W, Vc, Out;
+  TRY(grow(W, (size_t)chunk * L * sizeof(double2)));
   // Dtilde_j = V^H Dhat_j: (s x L) op C times the L x rows chunk, column-major
   // s x rows = row-major [rows][s]
   TRY(grow(Vc, Vcol.size() * sizeof(double2)));
   TRY(grow(Out, (size_t)chunk * s_dim * sizeof(double2)));
   HIP_TRY(hipMemcpyAsync(Vc.p, Vcol.data(), Vcol.size() * sizeof(double2), hipMemcpyHostToDevice, st));
-  std::vector<double> At((size_t)d * s_dim * 2);
+  At.assign((size_t)d * s_dim * 2, 0.0);
   const rocblas_double_complex one_c(1.0, 0.0), zero_c(0.0, 0.0);
   for (int64_t r0 = 0; r0 < d; r0 += chunk) {
     const int64_t rows = std::min<int64_t>(chunk, d - r0);
     launch_widen(D->dhat.as<float>() + r0 * D->Kp, D->Kp, D->is_complex, rows, L, W.as<double2>(), st);
     LAUNCH_CHECK("widen");
     HIP_TRY(hipMemsetAsync(Out.p, 0, (size_t)rows * s_dim * sizeof(double2), st));
-    BLAS_TRY(rocblas_zgemm(blas.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, s_dim,
+    BLAS_TRY(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, s_dim,
                            (rocblas_int)rows, L, &one_c, Vc.as<rocblas_double_complex>(), L,
                            W.as<rocblas_double_complex>(), L, &zero_c, Out.as<rocblas_double_complex>(),
                            s_dim));
@@ -211,8 +227,7 @@ extern "C" mrf_status mrf_dict_compress(mrf_dict D, int32_t s_dim, uint32_t flag
 
   for (size_t i = 0; i < At.size(); ++i)
     if (!std::isfinite(At[i]))
-      return fail(MRF_E_NUMERIC, "mrf_dict_compress: non-finite compressed atom value at %zu (lambda_0 %.6g)", i,
-                  lam[0]);
+      return fail(MRF_E_NUMERIC, "dictionary projection: non-finite coordinate at %zu", i);
   // the first and last compressed atoms against a host FP64 product
   for (int64_t j : {(int64_t)0, d - 1}) {
     std::vector<float> row((size_t)D->K);
@@ -227,10 +242,37 @@ extern "C" mrf_status mrf_dict_compress(mrf_dict D, int32_t s_dim, uint32_t flag
       }
       const double *g = At.data() + ((size_t)j * s_dim + k) * 2;
       if (!(std::abs(acc - std::complex<double>(g[0], g[1])) <= 1e-10))
-        return fail(MRF_E_NUMERIC, "mrf_dict_compress: compressed atom %lld coordinate %d is (%.9g, %.9g), host (%.9g, %.9g)",
+        return fail(MRF_E_NUMERIC, "dictionary projection: atom %lld coordinate %d is (%.9g, %.9g), host (%.9g, %.9g)",
                     (long long)j, k, g[0], g[1], acc.real(), acc.imag());
     }
   }
+  return MRF_OK;
+}
+
+}  // namespace
+
+extern "C" mrf_status mrf_dict_compress(mrf_dict D, int32_t s_dim, uint32_t flags, mrf_stream stream,
+                                        mrf_dict *out) {
+  last_error().clear();
+  if (!D || !out) return fail(MRF_E_INVAL, "mrf_dict_compress: null argument");
+  if (D->Lfull > 0) return fail(MRF_E_UNSUPPORTED, "mrf_dict_compress: dictionary is already compressed");
+  if (D->align)
+    return fail(MRF_E_UNSUPPORTED, "mrf_dict_compress: compress first, then align (dictionary is phase-aligned)");
+  const int L = D->L;
+  if (s_dim < 1 || s_dim > L || s_dim > kMaxSubspace)
+    return fail(MRF_E_INVAL, "mrf_dict_compress: s=%d not in 1..min(L=%d, %d)", s_dim, L, kMaxSubspace);
+  if (flags & ~(uint32_t)(MRF_STORE_BF16 | MRF_STORE_FP8 | MRF_BUILD_COVERTREE))
+    return fail(MRF_E_INVAL, "mrf_dict_compress: unknown flags 0x%x", flags);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Blas blas;
+  BLAS_TRY(rocblas_create_handle(&blas.h));
+  BLAS_TRY(rocblas_set_stream(blas.h, st));
+  BLAS_TRY(rocblas_set_pointer_mode(blas.h, rocblas_pointer_mode_host));
+
+  std::vector<std::complex<double>> Vcol;
+  std::vector<double> Vh, lam, At;
+  TRY(dominant_basis(D, s_dim, st, blas.h, Vcol, Vh, lam));
+  TRY(project_rows(D, Vcol, s_dim, st, blas.h, At));
   mrf_dict_desc q{};
   q.d = D->d;
   q.L = s_dim;
@@ -252,6 +294,106 @@ extern "C" mrf_status mrf_dict_compress(mrf_dict D, int32_t s_dim, uint32_t flag
   TRY(grow(C->Vs, vf.size() * sizeof(float)));
   HIP_TRY(hipMemcpy(C->Vs.p, vf.data(), vf.size() * sizeof(float), hipMemcpyHostToDevice));
   C->bytes += (int64_t)C->Vs.cap;
+  *out = guard.release();
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_dict_align(mrf_dict D, uint32_t flags, mrf_stream stream, mrf_dict *out) {
+  last_error().clear();
+  if (!D || !out) return fail(MRF_E_INVAL, "mrf_dict_align: null argument");
+  if (D->align) return fail(MRF_E_UNSUPPORTED, "mrf_dict_align: dictionary is already phase-aligned");
+  if (flags & ~(uint32_t)(MRF_STORE_BF16 | MRF_STORE_FP8 | MRF_BUILD_COVERTREE))
+    return fail(MRF_E_INVAL, "mrf_dict_align: unknown flags 0x%x", flags);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int L = D->L;
+  const int64_t d = D->d;
+  Blas blas;
+  BLAS_TRY(rocblas_create_handle(&blas.h));
+  BLAS_TRY(rocblas_set_stream(blas.h, st));
+  BLAS_TRY(rocblas_set_pointer_mode(blas.h, rocblas_pointer_mode_host));
+  // u: the first principal direction (the first compressed coordinate of a
+  // compressed dictionary, whose basis starts with it)
+  std::vector<std::complex<double>> u;
+  if (D->Lfull > 0) {
+    u.assign((size_t)L, 0.0);
+    u[0] = 1.0;
+  } else {
+    std::vector<double> Vh, lam;
+    TRY(dominant_basis(D, 1, st, blas.h, u, Vh, lam));
+  }
+  std::vector<double> c;
+  TRY(project_rows(D, u, 1, st, blas.h, c));
+  // alignment factors f_j and the aligned rows (FP64) of the FP32 normalised atoms
+  std::vector<std::complex<double>> f((size_t)d);
+  for (int64_t j = 0; j < d; ++j) {
+    const std::complex<double> cj(c[2 * j], c[2 * j + 1]);
+    const double m = std::abs(cj);
+    if (D->is_complex)
+      f[(size_t)j] = m > 0.0 ? std::conj(cj) / m : std::complex<double>(1.0, 0.0);
+    else
+      f[(size_t)j] = cj.real() < 0.0 ? -1.0 : 1.0;
+  }
+  const int K = D->K;
+  std::vector<double> atoms((size_t)d * K);
+  {
+    const int64_t chunk = 65536;
+    std::vector<float> rows((size_t)std::min<int64_t>(chunk, d) * D->Kp);
+    for (int64_t r0 = 0; r0 < d; r0 += chunk) {
+      const int64_t nr = std::min<int64_t>(chunk, d - r0);
+      HIP_TRY(hipMemcpy(rows.data(), D->dhat.as<float>() + r0 * D->Kp, (size_t)nr * D->Kp * sizeof(float),
+                        hipMemcpyDeviceToHost));
+      for (int64_t r = 0; r < nr; ++r) {
+        const float *a = rows.data() + (size_t)r * D->Kp;
+        double *o = atoms.data() + (size_t)(r0 + r) * K;
+        const std::complex<double> fj = f[(size_t)(r0 + r)];
+        if (D->is_complex) {
+          for (int t = 0; t < L; ++t) {
+            const std::complex<double> x = std::complex<double>(a[2 * t], a[2 * t + 1]) * fj;
+            o[2 * t] = x.real();
+            o[2 * t + 1] = x.imag();
+          }
+        } else {
+          for (int t = 0; t < L; ++t) o[t] = (double)a[t] * fj.real();
+        }
+      }
+    }
+  }
+  mrf_dict_desc q{};
+  q.d = D->d;
+  q.L = L;
+  q.nparam = D->nparam;
+  q.is_complex = D->is_complex;
+  q.atoms = atoms.data();
+  q.atoms_dtype = MRF_F64;
+  q.params = D->params_host.data();
+  q.grid_dims = D->grid_dims.empty() ? nullptr : D->grid_dims.data();
+  q.flags = flags;
+  mrf_dict C = nullptr;
+  TRY(mrf_dict_build(&q, stream, &C));
+  std::unique_ptr<mrf_dict_s> guard(C);
+  C->align = 1;
+  std::vector<float> uf((size_t)L * 2), ff((size_t)d * 2);
+  for (int t = 0; t < L; ++t) {
+    uf[2 * t] = (float)u[(size_t)t].real();
+    uf[2 * t + 1] = (float)u[(size_t)t].imag();
+  }
+  for (int64_t j = 0; j < d; ++j) {
+    ff[2 * j] = (float)f[(size_t)j].real();
+    ff[2 * j + 1] = (float)f[(size_t)j].imag();
+  }
+  TRY(grow(C->u1, uf.size() * sizeof(float)));
+  TRY(grow(C->afac, ff.size() * sizeof(float)));
+  HIP_TRY(hipMemcpy(C->u1.p, uf.data(), uf.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(C->afac.p, ff.data(), ff.size() * sizeof(float), hipMemcpyHostToDevice));
+  C->bytes += (int64_t)(C->u1.cap + C->afac.cap);
+  if (D->Lfull > 0) {  // keep the temporal subspace of a compressed dictionary
+    C->Lfull = D->Lfull;
+    C->V_host = D->V_host;
+    C->lam = D->lam;
+    TRY(grow(C->Vs, D->V_host.size() * sizeof(float)));
+    HIP_TRY(hipMemcpy(C->Vs.p, D->Vs.p, D->V_host.size() * sizeof(float), hipMemcpyDeviceToDevice));
+    C->bytes += (int64_t)C->Vs.cap;
+  }
   *out = guard.release();
   return MRF_OK;
 }

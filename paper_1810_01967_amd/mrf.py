@@ -25,7 +25,7 @@ MRF_VOXEL_MAJOR, MRF_FRAME_MAJOR = 0, 1
 PRECISION = {"fp32": MRF_FP32, "bf16": MRF_BF16, "fp8": MRF_FP8, "bf16x3": MRF_BF16X3}
 
 EXPORTS = ["mrf_last_error", "mrf_version", "mrf_dict_build", "mrf_dict_destroy", "mrf_dict_query",
-           "mrf_dict_copy_atoms", "mrf_dict_compress", "mrf_dict_subspace", "mrf_dict_tree_info", "mrf_dict_tree_export", "mrf_match", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
+           "mrf_dict_copy_atoms", "mrf_dict_compress", "mrf_dict_subspace", "mrf_dict_align", "mrf_dict_tree_info", "mrf_dict_tree_export", "mrf_match", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
            "mrf_net_size", "mrf_net_set_params", "mrf_net_get_params", "mrf_net_get_grads",
            "mrf_net_set_standardisation", "mrf_net_get_standardisation", "mrf_net_forward",
            "mrf_net_forward_bf16",
@@ -52,7 +52,7 @@ class DictInfo(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("L", ctypes.c_int32), ("nparam", ctypes.c_int32),
                 ("is_complex", ctypes.c_int32), ("K", ctypes.c_int32), ("Kp", ctypes.c_int32),
                 ("Kq", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("device_bytes", ctypes.c_int64), ("L_full", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_int64), ("L_full", ctypes.c_int32), ("phase_aligned", ctypes.c_int32)]
 
 
 class MatchOpts(ctypes.Structure):
@@ -60,7 +60,8 @@ class MatchOpts(ctypes.Structure):
                 ("topk", ctypes.c_int32), ("atom_splits", ctypes.c_int32),
                 ("net", ctypes.c_void_p), ("box_radius", ctypes.c_int32),
                 ("fallback_corr", ctypes.c_float), ("recentre", ctypes.c_int32),
-                ("eps", ctypes.c_float), ("tree_capacity", ctypes.c_int32)]
+                ("eps", ctypes.c_float), ("tree_capacity", ctypes.c_int32),
+                ("pd_phase", ctypes.c_void_p)]
 
 
 class MatchStats(ctypes.Structure):
@@ -139,6 +140,8 @@ def lib():
         L.mrf_dict_compress.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_void_p)]
         L.mrf_dict_subspace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.mrf_dict_align.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_void_p)]
         L.mrf_match.argtypes = [ctypes.c_void_p, ctypes.POINTER(MatchOpts), ctypes.c_int64,
                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -255,6 +258,7 @@ class Dictionary:
         self.handle = h
         self.d, self.L = d, L
         self.L_full = 0
+        self.aligned = False
         self.grid_dims = None if gd is None else tuple(int(x) for x in gd)
 
     def compress(self, s, store_bf16=False, store_fp8=False, cover_tree=False, stream=None) -> "Dictionary":
@@ -267,6 +271,21 @@ class Dictionary:
         C = Dictionary.__new__(Dictionary)
         C.handle = h
         C.is_complex, C.nparam, C.d, C.L, C.L_full = True, self.nparam, self.d, int(s), self.L
+        C.aligned = False
+        C.grid_dims = self.grid_dims
+        return C
+
+    def align(self, store_bf16=False, store_fp8=False, cover_tree=False, stream=None) -> "Dictionary":
+        """mrf_dict_align: a new dictionary of phase-aligned atoms for the
+        complex-PD projection (keeps the temporal subspace of a compressed one)."""
+        flags = ((MRF_STORE_BF16 if store_bf16 else 0) | (MRF_STORE_FP8 if store_fp8 else 0)
+                 | (MRF_BUILD_COVERTREE if cover_tree else 0))
+        h = ctypes.c_void_p()
+        _check(lib().mrf_dict_align(self.handle, flags, _stream(stream), ctypes.byref(h)))
+        C = Dictionary.__new__(Dictionary)
+        C.handle = h
+        C.is_complex, C.nparam, C.d, C.L, C.L_full = self.is_complex, self.nparam, self.d, self.L, self.L_full
+        C.aligned = True
         C.grid_dims = self.grid_dims
         return C
 
@@ -329,17 +348,17 @@ def match_opts(precision="fp32", topk=8, atom_splits=0, net=None, box_radius=3, 
         method = MRF_LEARNED if net is not None else MRF_EXHAUSTIVE
     return MatchOpts(method, PRECISION[precision], int(topk), int(atom_splits),
                      None if net is None else net.handle, int(box_radius), float(fallback_corr),
-                     int(recentre), float(eps or 0.0), int(tree_capacity))
+                     int(recentre), float(eps or 0.0), int(tree_capacity), None)
 
 
 # --------------------------------------------------------------------------- matched filter
 def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp32", topk=8,
               atom_splits=0, warm_idx=None, want_pd=True, want_corr=True, want_X=False,
               want_params=False, stats=False, out=None, stream=None, net=None, box_radius=3,
-              fallback_corr=0.98, recentre=0, eps=None, tree_capacity=0):
+              fallback_corr=0.98, recentre=0, eps=None, tree_capacity=0, want_pd_phase=False):
     """Matched filter of the voxels in Z (complex64 CUDA tensor, [n][L] for
     layout 'voxel', [S][L][...] for 'frame').  Returns a dict of CUDA tensors
-    (idx, pd, corr, X, params) and, with stats=True, a MatchStats."""
+    (idx, pd, corr, X, params, pd_phase) and, with stats=True, a MatchStats."""
     torch = _torch()
     if layout == "voxel":
         n = Z.shape[0]
@@ -362,6 +381,10 @@ def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp
         o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
     opts = match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre, eps,
                       tree_capacity)
+    if want_pd_phase:
+        if "pd_phase" not in o:
+            o["pd_phase"] = torch.empty(n, dtype=torch.float32, device=dev)
+        opts.pd_phase = _dev(o["pd_phase"])
     st = MatchStats() if stats else None
     status = lib().mrf_match(D.handle, ctypes.byref(opts), n, _dev(Z, torch.complex64), zl, sv,
                              _dev(warm_idx, torch.int32),

@@ -321,6 +321,19 @@ def spiral_sampling(S: int, L: int, ny: int, nx: int, frac: float = 0.05,
 # ----------------------------------------------------------------------------
 # measurements
 # ----------------------------------------------------------------------------
+def pd_phase_map(seed: int, S: int, ny: int, nx: int, max_ramp: float = 2.0) -> np.ndarray:
+    """A smooth PD phase map [S][ny][nx] (radians): a seeded constant plus a
+    linear ramp of at most ``max_ramp`` radians across the field of view in
+    each direction, per slice (complex-PD phantoms: X0 * exp(1j * map))."""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    out = np.empty((S, ny, nx))
+    for s in range(S):
+        u = rng.uniform(seed, f"pdphase-s{s}", 3)
+        out[s] = (2.0 * np.pi * (u[0] - 0.5) + max_ramp * (u[1] - 0.5) * 2.0 * yy / ny
+                  + max_ramp * (u[2] - 0.5) * 2.0 * xx / nx)
+    return out
+
+
 def coil_maps(seed: int, S: int, c: int, ny: int, nx: int) -> np.ndarray:
     """Smooth synthetic receive-coil sensitivities [S][c][ny][nx] complex128:
     coil q sits on a ring around the field of view (angle 2 pi q / c plus a
