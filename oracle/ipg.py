@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fourier, mf, phase, subspace
+from . import fourier, mf, nudft, phase, subspace
 
 
 class NoConvergence(RuntimeError):
@@ -52,34 +52,41 @@ def project(Z: np.ndarray, atoms: np.ndarray, warm_idx=None, X_prev=None,
     return fourier.voxel_to_frame(Xv, S, ny, nx), res
 
 
-def op_forward(X, off, idx, V=None, smaps=None):
+def op_forward(X, off, idx, V=None, smaps=None, coords=None):
     """A X, or with a temporal subspace V (eq. CS1) A(expand(X)); with coil
-    maps smaps [S][c][ny][nx] the samples are coil-major [c][M]."""
+    maps smaps [S][c][ny][nx] the samples are coil-major [c][M]; with
+    non-Cartesian coordinates (idx unused) F is the non-uniform DFT."""
     Xf = X if V is None else subspace.expand(X, V)
+    if coords is not None:
+        return nudft.forward(Xf, off, coords) if smaps is None else nudft.forward_coils(Xf, off, coords, smaps)
     return fourier.forward(Xf, off, idx) if smaps is None else fourier.forward_coils(Xf, off, idx, smaps)
 
 
-def op_adjoint(R, off, idx, S, L, ny, nx, V=None, smaps=None):
+def op_adjoint(R, off, idx, S, L, ny, nx, V=None, smaps=None, coords=None):
     """A^H R over L frames (coils combined with conj(S_q) when smaps is
     given), compressed by V^H when V is given."""
     Lf = L if V is None else V.shape[0]
-    G = (fourier.adjoint(R, off, idx, S, Lf, ny, nx) if smaps is None
-         else fourier.adjoint_coils(R, off, idx, S, Lf, ny, nx, smaps))
+    if coords is not None:
+        G = (nudft.adjoint(R, off, coords, S, Lf, ny, nx) if smaps is None
+             else nudft.adjoint_coils(R, off, coords, S, Lf, ny, nx, smaps))
+    else:
+        G = (fourier.adjoint(R, off, idx, S, Lf, ny, nx) if smaps is None
+             else fourier.adjoint_coils(R, off, idx, S, Lf, ny, nx, smaps))
     return G if V is None else subspace.compress(G, V)
 
 
-def gradient(X, Y, off, idx, w, V=None, smaps=None):
+def gradient(X, Y, off, idx, w, V=None, smaps=None, coords=None):
     """A^H W (A X - Y) and the residual; with V: the compressed gradient of
     eq. gradupdate, compress(A^H W (A expand(X) - Y)).  The weights w [M]
     apply to every coil's samples."""
     S, L, ny, nx = X.shape
-    R = op_forward(X, off, idx, V, smaps) - Y
+    R = op_forward(X, off, idx, V, smaps, coords) - Y
     WR = R if w is None else np.asarray(w, dtype=np.float64) * R
-    return op_adjoint(WR, off, idx, S, L, ny, nx, V, smaps), R
+    return op_adjoint(WR, off, idx, S, L, ny, nx, V, smaps, coords), R
 
 
 def ipg_step(Y, off, idx, atoms, X, mu: float, w=None, warm_idx=None,
-             nonexpansive: bool = False, V=None, smaps=None, u=None):
+             nonexpansive: bool = False, V=None, smaps=None, u=None, coords=None):
     """One projected-gradient step at a fixed mu.  Returns (X', projection
     result, stats) with stats = dx2, adx2 (weighted), f_old, f_new.  With a
     temporal subspace V, X has s compressed frames, atoms are the compressed
@@ -88,14 +95,14 @@ def ipg_step(Y, off, idx, atoms, X, mu: float, w=None, warm_idx=None,
     phase-aligned one (complex PD) over aligned atoms."""
     Y = np.asarray(Y, dtype=np.complex128)
     X = np.asarray(X, dtype=np.complex128)
-    G, R = gradient(X, Y, off, idx, w, V, smaps)
+    G, R = gradient(X, Y, off, idx, w, V, smaps, coords)
     Z = X - mu * G
     Xn, res = project(Z, atoms, warm_idx=warm_idx, X_prev=X, nonexpansive=nonexpansive, u=u)
     dX = Xn - X
-    AdX = op_forward(dX, off, idx, V, smaps)
+    AdX = op_forward(dX, off, idx, V, smaps, coords)
     stats = dict(dx2=float(np.sum(np.abs(dX) ** 2)), adx2=_weighted_sq(AdX, w),
                  f_old=_weighted_sq(R, w),
-                 f_new=_weighted_sq(op_forward(Xn, off, idx, V, smaps) - Y, w))
+                 f_new=_weighted_sq(op_forward(Xn, off, idx, V, smaps, coords) - Y, w))
     res["Z"] = Z
     return Xn, res, stats
 
@@ -103,7 +110,7 @@ def ipg_step(Y, off, idx, atoms, X, mu: float, w=None, warm_idx=None,
 def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
               adaptive: bool = True, max_iter: int = 50, rel_tol: float = 1e-6,
               max_shrinks: int = 30, X0=None, w=None, kappa: bool = False,
-              nonexpansive: bool = False, V=None, smaps=None, u=None):
+              nonexpansive: bool = False, V=None, smaps=None, u=None, coords=None):
     """Full reconstruction; dims = (S, L, ny, nx) (L = s compressed frames
     when a temporal subspace V is given).  Returns (X, idx, gamma, history)
     where history lists per accepted iteration: f (objective after the
@@ -113,11 +120,11 @@ def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
     X = np.zeros(dims, dtype=np.complex128) if X0 is None else np.asarray(X0, dtype=np.complex128).copy()
     warm = None
     gamma = np.zeros(S * ny * nx)
-    f = _weighted_sq(op_forward(X, off, idx, V, smaps) - Y, w)
+    f = _weighted_sq(op_forward(X, off, idx, V, smaps, coords) - Y, w)
     hist = []
     mu_init = float(mu0)
     for k in range(max_iter):
-        G, _ = gradient(X, Y, off, idx, w, V, smaps)
+        G, _ = gradient(X, Y, off, idx, w, V, smaps, coords)
         mu = mu_init
         shrinks = 0
         while True:
@@ -125,7 +132,7 @@ def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
             Xn, res = project(Z, atoms, warm_idx=warm, X_prev=X, nonexpansive=nonexpansive, u=u)
             dX = Xn - X
             dx2 = float(np.sum(np.abs(dX) ** 2))
-            adx2 = _weighted_sq(op_forward(dX, off, idx, V, smaps), w)
+            adx2 = _weighted_sq(op_forward(dX, off, idx, V, smaps, coords), w)
             if (not adaptive) or dx2 == 0.0 or adx2 == 0.0 or mu < dx2 / adx2:
                 break
             mu /= zeta
@@ -136,12 +143,12 @@ def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
         warm = res["idx"]
         gamma = res["gamma"]
         if kappa and k == 0:
-            kap = np.sqrt(_weighted_sq(Y, None)) / max(np.sqrt(_weighted_sq(op_forward(X, off, idx, V, smaps), None)),
+            kap = np.sqrt(_weighted_sq(Y, None)) / max(np.sqrt(_weighted_sq(op_forward(X, off, idx, V, smaps, coords), None)),
                                                        1e-300)
             X = X * kap
             gamma = gamma * kap
             mu_init *= kap
-        f_new = _weighted_sq(op_forward(X, off, idx, V, smaps) - Y, w)
+        f_new = _weighted_sq(op_forward(X, off, idx, V, smaps, coords) - Y, w)
         hist.append(dict(f=f_new, mu=mu, shrinks=shrinks, dx2=dx2, adx2=adx2))
         if dx2 == 0.0:
             break

@@ -356,6 +356,101 @@ def coil_maps(seed: int, S: int, c: int, ny: int, nx: int) -> np.ndarray:
     return out
 
 
+@dataclass
+class Trajectory:
+    """Non-Cartesian sampling: per (slice, frame) pair p the samples
+    off[p]..off[p+1] at k-space coordinates coords [M][2] = (ky, kx) in
+    cycles per pixel (FP32 values, in [-0.5, 0.5)), with density
+    compensation weights dcf [M]."""
+    off: np.ndarray
+    coords: np.ndarray
+    dcf: np.ndarray | None
+    S: int
+    L: int
+    ny: int
+    nx: int
+
+    @property
+    def M(self):
+        return int(self.off[-1])
+
+
+def _voronoi_areas(pts: np.ndarray, rmax: float) -> np.ndarray:
+    """Area of each point's Voronoi cell within the disc of radius rmax
+    (bounded by a ring of guard points; vertices outside the disc are pulled
+    onto its boundary, an approximate clipping), for density compensation."""
+    from scipy.spatial import Voronoi
+    ng = 64
+    ang = 2.0 * np.pi * np.arange(ng) / ng
+    guard = 1.5 * rmax * np.stack([np.sin(ang), np.cos(ang)], axis=1)
+    vor = Voronoi(np.concatenate([pts, guard]))
+    areas = np.empty(len(pts))
+    for i in range(len(pts)):
+        reg = vor.regions[vor.point_region[i]]
+        poly = vor.vertices[reg]
+        # clip the polygon to the disc by pulling vertices outside it onto the circle
+        rad = np.hypot(poly[:, 0], poly[:, 1])
+        poly = np.where((rad > rmax)[:, None], poly * (rmax / np.maximum(rad, 1e-300))[:, None], poly)
+        x, y = poly[:, 1], poly[:, 0]
+        areas[i] = 0.5 * abs(np.dot(x, np.roll(y, -1)) - np.dot(y, np.roll(x, -1)))
+    return areas
+
+
+def spiral_trajectory(S: int, L: int, ny: int, nx: int, frac: float = 0.05, rot_deg: float = 7.5,
+                      turns: float = 8.0, power: float = 2.0, with_dcf: bool = True) -> Trajectory:
+    """Variable-density spiral readouts off the Cartesian grid: one arm per
+    frame, k(u) = 0.5 u^power exp(i (2 pi turns u + theta_t)) cycles per pixel
+    (denser near the centre), theta_t rotating by rot_deg per frame (the
+    in-vivo readout's rotation), round(frac * ny * nx) points per arm evenly in
+    u (the first one at the centre), coordinates rounded to FP32; Voronoi
+    density compensation (cell areas within the sampled disc) normalised to
+    mean 1 per frame."""
+    npts = max(2, int(round(frac * ny * nx)))
+    u = np.linspace(0.0, 1.0, npts, endpoint=False) + 0.5 / npts
+    r = 0.5 * u ** power
+    rows, wts = [], []
+    for _s in range(S):
+        for t in range(L):
+            ph = 2.0 * np.pi * turns * u + np.deg2rad(rot_deg) * t
+            k = np.stack([r * np.sin(ph), r * np.cos(ph)], axis=1).astype(np.float32)
+            k = np.where(k >= 0.5, np.float32(-0.5), k)       # keep [-0.5, 0.5)
+            rows.append(k)
+            if with_dcf:
+                a = _voronoi_areas(k.astype(np.float64), 0.5)
+                wts.append(a / a.mean())
+    off = np.zeros(S * L + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(r_) for r_ in rows])
+    coords = np.concatenate(rows).astype(np.float32)
+    dcf = np.concatenate(wts) if with_dcf else None
+    return Trajectory(off, coords, dcf, S, L, ny, nx)
+
+
+def simulate_kspace_nc(X0: np.ndarray, tr: Trajectory, snr_db, seed: int, smaps=None):
+    """Y = P_Omega F S X0 + xi for non-Cartesian coordinates, F the exact
+    non-uniform DFT y(k) = (ny nx)^(-1/2) sum_r x_r exp(-2 pi i k . r) over
+    pixels r = (ry, rx) in [0, ny) x [0, nx) (on grid frequencies k = kappa/n
+    it is the unitary DFT).  Noise as in simulate_kspace.  Returns [M] or
+    [c][M]."""
+    S, L, ny, nx = X0.shape
+    c = 1 if smaps is None else smaps.shape[1]
+    ry, rx = np.mgrid[0:ny, 0:nx]
+    ry, rx = ry.reshape(-1).astype(np.float64), rx.reshape(-1).astype(np.float64)
+    Y = np.empty((c, tr.M), dtype=np.complex128)
+    for q in range(c):
+        for s in range(S):
+            for t in range(L):
+                p = s * L + t
+                k = tr.coords[tr.off[p]:tr.off[p + 1]].astype(np.float64)
+                E = np.exp(-2j * np.pi * (np.outer(k[:, 0], ry) + np.outer(k[:, 1], rx)))
+                img = X0[s, t] if smaps is None else smaps[s, q] * X0[s, t]
+                Y[q, tr.off[p]:tr.off[p + 1]] = E @ img.reshape(-1) / np.sqrt(ny * nx)
+    if snr_db is not None and np.isfinite(snr_db):
+        sig2 = np.sum(np.abs(Y) ** 2) / max(c * tr.M, 1) * 10.0 ** (-snr_db / 10.0)
+        Y = Y + (rng.complex_gaussian(seed, "kspace-noise", (tr.M,), sig2)[None] if c == 1
+                 else rng.complex_gaussian(seed, "kspace-noise-coils", (c, tr.M), sig2))
+    return Y[0] if smaps is None else Y
+
+
 def simulate_kspace(X0: np.ndarray, smp: Sampling, snr_db: float, seed: int, smaps=None):
     """Y = P_Omega F S X0 + xi (eq. forward; S = I without coil maps), F the
     unitary 2-D DFT per frame.  Noise: circular complex Gaussian with
