@@ -18,11 +18,14 @@ from __future__ import annotations
 import numpy as np
 
 
-def _matrix(k: np.ndarray, ny: int, nx: int) -> np.ndarray:
-    ry, rx = np.mgrid[0:ny, 0:nx]
+def _factors(k: np.ndarray, ny: int, nx: int):
+    """exp(-2 pi i ky ry) [m][ny] and exp(-2 pi i kx rx) [m][nx]: the
+    exponential of the sum is the product of these two, so y = sum_ry
+    ey[ry] sum_rx ex[rx] X[ry][rx]."""
     k = np.asarray(k, dtype=np.float64)
-    arg = np.outer(k[:, 0], ry.reshape(-1)) + np.outer(k[:, 1], rx.reshape(-1))
-    return np.exp(-2j * np.pi * arg) / np.sqrt(ny * nx)
+    ey = np.exp(-2j * np.pi * np.outer(k[:, 0], np.arange(ny)))
+    ex = np.exp(-2j * np.pi * np.outer(k[:, 1], np.arange(nx)))
+    return ey, ex
 
 
 def forward(X: np.ndarray, off: np.ndarray, coords: np.ndarray) -> np.ndarray:
@@ -32,20 +35,21 @@ def forward(X: np.ndarray, off: np.ndarray, coords: np.ndarray) -> np.ndarray:
     for s in range(S):
         for t in range(L):
             p = s * L + t
-            E = _matrix(coords[off[p]:off[p + 1]], ny, nx)
-            out[off[p]:off[p + 1]] = E @ np.asarray(X[s, t], dtype=np.complex128).reshape(-1)
+            ey, ex = _factors(coords[off[p]:off[p + 1]], ny, nx)
+            rows = ey @ np.asarray(X[s, t], dtype=np.complex128)          # [m][nx]: sum over ry
+            out[off[p]:off[p + 1]] = np.sum(rows * ex, axis=1) / np.sqrt(ny * nx)
     return out
 
 
 def adjoint(R: np.ndarray, off: np.ndarray, coords: np.ndarray, S: int, L: int, ny: int, nx: int) -> np.ndarray:
-    """A^H(R): samples [M] -> frame-major image [S][L][ny][nx]."""
+    """A^H(R): X[ry][rx] = (ny nx)^(-1/2) sum_i conj(ey_i[ry] ex_i[rx]) R_i."""
     R = np.asarray(R, dtype=np.complex128)
     out = np.empty((S, L, ny, nx), dtype=np.complex128)
     for s in range(S):
         for t in range(L):
             p = s * L + t
-            E = _matrix(coords[off[p]:off[p + 1]], ny, nx)
-            out[s, t] = (E.conj().T @ R[off[p]:off[p + 1]]).reshape(ny, nx)
+            ey, ex = _factors(coords[off[p]:off[p + 1]], ny, nx)
+            out[s, t] = ey.conj().T @ (R[off[p]:off[p + 1], None] * ex.conj()) / np.sqrt(ny * nx)
     return out
 
 
