@@ -369,6 +369,27 @@ mrf_status mrf_net_train(mrf_net net, mrf_dict D, const mrf_train_opts *opts,
  * the pattern of each (slice, frame) samples every coil.  Sample arrays
  * (Y, R) then hold c*M values, coil-major ([c][M]); the dcf weights apply
  * to every coil. */
+/* Non-Cartesian sampling (Section "In-vivo data with variable-density
+ * spiral acquisition": F in eq. forward is a non-uniform Fourier transform).
+ * A plan holds the trajectory of nslices*L (slice, frame) pairs: the
+ * samples of pair p are coords[samp_off[p] .. samp_off[p+1]), each (ky, kx)
+ * in cycles per pixel (|ky|, |kx| <= 1024; the transform is 1-periodic in
+ * them).  The operator it defines is the non-uniform DFT
+ *     y(k) = (ny nx)^(-1/2) sum_{ry<ny, rx<nx} X[ry][rx] exp(-2 pi i (ky ry + kx rx)),
+ * which at grid frequencies (kappa_y/ny, kappa_x/nx) is the unitary DFT of
+ * the Cartesian operator.  It is computed by gridding on the 2x
+ * oversampled grid with the "exponential of semicircle" kernel of `width`
+ * fine cells (4..8, 0 = 7; relative error about 10^-(width-1)) and a
+ * deterministic gather for the adjoint.  samp_off and coords are HOST
+ * arrays copied by the call.  Errors: MRF_E_INVAL (sizes, offsets not
+ * running from 0 to nsamples, coordinates not finite or beyond 1024),
+ * MRF_E_NOMEM,
+ * MRF_E_HIP. */
+typedef struct mrf_nufft_s *mrf_nufft;
+mrf_status mrf_nufft_create(int32_t nx, int32_t ny, int32_t L, int32_t nslices, int64_t nsamples,
+                            const int64_t *samp_off, const float *coords, int32_t width, mrf_nufft *out);
+mrf_status mrf_nufft_destroy(mrf_nufft plan);
+
 typedef struct {
   int32_t nx, ny;          /* powers of two, 16..256 */
   int32_t L, nslices;      /* >= 1 */
@@ -379,6 +400,9 @@ typedef struct {
   int32_t ncoils;          /* 0: S = I; c in 1..64: coil maps below */
   int32_t reserved;        /* 0 */
   const void *smaps;       /* DEVICE complex64 [nslices][c][ny][nx] (ncoils >= 1), else ignored */
+  mrf_nufft nufft;         /* NULL: Cartesian samples at samp_idx; else the non-Cartesian plan
+                              (same nx, ny, L, nslices, nsamples; samp_off must hold the plan's
+                              offsets on the device; samp_idx is ignored) */
 } mrf_op;
 
 /* R = A X - Y  (Y NULL: R = A X), samples in CSR order (coil-major with

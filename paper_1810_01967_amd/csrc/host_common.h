@@ -124,6 +124,7 @@ struct mrf_dict_s {
   std::vector<double> V_host, lam;  // V (FP64 complex [Lfull][L], interleaved) and its eigenvalues
   mrf::DevBuf kfull;                // full-frame k-space of the compressed adjoint
   mrf::DevBuf cbuf;                 // per-coil images (coil maps)
+  mrf::DevBuf nbuf, nbuf2;          // oversampled grids of the non-uniform FFT
   // phase alignment (complex PD): first principal direction u [L] (FP32
   // complex), per-atom alignment factors f_j [d] (aligned atom = f_j Dhat_j),
   // per-voxel factors e^{i theta_v} of the last packing
@@ -140,6 +141,13 @@ struct mrf_dict_s {
   ~mrf_dict_s() {
     if (host_scal) (void)hipHostFree(host_scal);
   }
+};
+
+struct mrf_nufft_s {
+  int nx = 0, ny = 0, L = 0, nslices = 0, W = 7;
+  float beta = 0.f;
+  int64_t M = 0;
+  mrf::DevBuf off, coords, bperm, boff, dy, dx;
 };
 
 struct mrf_net_s {

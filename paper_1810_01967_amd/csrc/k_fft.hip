@@ -19,7 +19,7 @@ namespace mrf {
 template <int N>
 struct FftCfg {
   static constexpr int C = 4096 / N;
-  static constexpr int LOG = (N == 16) ? 4 : (N == 32) ? 5 : (N == 64) ? 6 : (N == 128) ? 7 : 8;
+  static constexpr int LOG = (N == 16) ? 4 : (N == 32) ? 5 : (N == 64) ? 6 : (N == 128) ? 7 : (N == 256) ? 8 : 9;
 };
 
 template <int N, bool COLS>
@@ -110,6 +110,7 @@ static void fft_pass_n(int N, float2 *data, int64_t nimg, int ny, int nx, int in
     case 64: fft_pass<64, COLS>(data, nimg, ny, nx, inverse, s); break;
     case 128: fft_pass<128, COLS>(data, nimg, ny, nx, inverse, s); break;
     case 256: fft_pass<256, COLS>(data, nimg, ny, nx, inverse, s); break;
+    case 512: fft_pass<512, COLS>(data, nimg, ny, nx, inverse, s); break;
     default: break;
   }
 }

@@ -482,7 +482,14 @@ mrf_status check_op(const mrf_op *A) {
     return fail(MRF_E_INVAL, "nx=%d ny=%d must be powers of two in 16..256", A->nx, A->ny);
   if (A->L < 1 || A->nslices < 1) return fail(MRF_E_INVAL, "L and nslices must be >= 1");
   if (A->nsamples < 0) return fail(MRF_E_INVAL, "nsamples < 0");
-  if (!A->samp_off || (A->nsamples > 0 && !A->samp_idx)) return fail(MRF_E_INVAL, "null sampling arrays");
+  if (!A->samp_off) return fail(MRF_E_INVAL, "null sampling offsets");
+  if (A->nufft) {
+    const mrf_nufft_s *P = A->nufft;
+    if (P->nx != A->nx || P->ny != A->ny || P->L != A->L || P->nslices != A->nslices || P->M != A->nsamples)
+      return fail(MRF_E_INVAL, "operator sizes differ from its non-uniform FFT plan");
+  } else if (A->nsamples > 0 && !A->samp_idx) {
+    return fail(MRF_E_INVAL, "null sampling arrays");
+  }
   if (A->ncoils < 0 || A->ncoils > 64) return fail(MRF_E_INVAL, "ncoils=%d not in 0..64", A->ncoils);
   if (A->ncoils >= 1 && !A->smaps) return fail(MRF_E_INVAL, "ncoils=%d needs smaps", A->ncoils);
   if ((int64_t)A->nslices * std::max(A->ncoils, 1) * A->L > (1 << 30)) return fail(MRF_E_INVAL, "too many frames");
@@ -508,17 +515,102 @@ OpDims dims_of(const mrf_op *A) {
   return o;
 }
 
+// Images img [S'][F][npix] (S' = slices x coils; overwritten by the
+// Cartesian path) to samples: R = (A img) - Y at every virtual pair, with
+// per-pair weighted norms into part.  F = Dsub->L compressed frames when Dsub
+// is a compressed dictionary (each sample then combines them with its
+// frame's row of V), else A->L.  Cartesian: FFT in place, gather;
+// non-Cartesian: pad onto the oversampled grids (ws->nbuf), FFT, interpolate.
+mrf_status transform_sample(mrf_dict_s *ws, const mrf_op *A, const OpDims &o, float2 *img, int F,
+                            const mrf_dict_s *Dsub, const float2 *Y, float2 *R, double *part, hipStream_t s) {
+  const bool sub = Dsub && Dsub->Lfull > 0;
+  const int64_t nkimg = (int64_t)A->nslices * o.nc * F;
+  const float2 *V = sub ? Dsub->Vs.as<float2>() : nullptr;
+  if (A->nufft) {
+    const mrf_nufft_s *P = A->nufft;
+    TRY(grow(ws->nbuf, (size_t)nkimg * 4 * o.npix * 8));
+    launch_nufft_pad(img, nkimg, A->ny, A->nx, P->dy.as<float>(), P->dx.as<float>(), ws->nbuf.as<float2>(), s);
+    LAUNCH_CHECK("nufft pad");
+    launch_fft2(ws->nbuf.as<float2>(), nkimg, 2 * A->ny, 2 * A->nx, 0, s);
+    LAUNCH_CHECK("fft2 (oversampled)");
+    launch_nufft_interp(ws->nbuf.as<float2>(), A->ny, A->nx, P->W, P->beta, P->off.as<int64_t>(),
+                        P->coords.as<float2>(), Y, A->dcf, R, part, (int)o.nvpairs, A->nsamples, A->L, o.nc, V,
+                        sub ? Dsub->L : 1, s);
+    LAUNCH_CHECK("nufft interp");
+    return MRF_OK;
+  }
+  launch_fft2(img, nkimg, A->ny, A->nx, 0, s);
+  LAUNCH_CHECK("fft2");
+  if (sub)
+    launch_sample_sub(img, o.npix, A->L, Dsub->L, V, A->samp_off, A->samp_idx, Y, A->dcf, R, part, (int)o.nvpairs,
+                      A->nsamples, o.nc, s);
+  else
+    launch_sample(img, o.npix, A->samp_off, A->samp_idx, Y, A->dcf, R, part, (int)o.nvpairs, A->nsamples, A->L,
+                  o.nc, s);
+  LAUNCH_CHECK("sample");
+  return MRF_OK;
+}
+
+// Weighted samples w R to images out [S'][F][npix] (before the coil
+// combination): scatter into the zero-filled k-space of every virtual pair
+// (non-Cartesian: spread onto its oversampled grid), V^H over the frames for
+// a compressed dictionary, inverse transforms (non-Cartesian: then crop and
+// deapodise).  Workspace: ws->kfull, ws->nbuf, ws->nbuf2.
+mrf_status scatter_transform(mrf_dict_s *ws, const mrf_op *A, const OpDims &o, const float2 *R, const float *w,
+                             const mrf_dict_s *Dsub, float2 *out, hipStream_t s) {
+  const bool sub = Dsub && Dsub->Lfull > 0;
+  const int F = sub ? Dsub->L : A->L;
+  const int Sv = A->nslices * o.nc;
+  const int64_t nkimg = (int64_t)Sv * F;
+  const float2 *V = sub ? Dsub->Vs.as<float2>() : nullptr;
+  if (A->nufft) {
+    const mrf_nufft_s *P = A->nufft;
+    const int64_t plane = 4 * o.npix;
+    TRY(grow(ws->nbuf, (size_t)o.nvpairs * plane * 8));
+    launch_nufft_spread(R, w, P->off.as<int64_t>(), P->coords.as<float2>(), P->bperm.as<int32_t>(),
+                        P->boff.as<int32_t>(), A->ny, A->nx, P->W, P->beta, A->nsamples, A->L, o.nc, o.nvpairs,
+                        ws->nbuf.as<float2>(), s);
+    LAUNCH_CHECK("nufft spread");
+    float2 *grid = ws->nbuf.as<float2>();
+    if (sub) {
+      TRY(grow(ws->nbuf2, (size_t)nkimg * plane * 8));
+      launch_compress_frames(grid, plane, Sv, A->L, Dsub->L, V, ws->nbuf2.as<float2>(), s);
+      LAUNCH_CHECK("compress frames");
+      grid = ws->nbuf2.as<float2>();
+    }
+    launch_fft2(grid, nkimg, 2 * A->ny, 2 * A->nx, 1, s);
+    LAUNCH_CHECK("ifft2 (oversampled)");
+    launch_nufft_crop(grid, nkimg, A->ny, A->nx, P->dy.as<float>(), P->dx.as<float>(), out, s);
+    LAUNCH_CHECK("nufft crop");
+    return MRF_OK;
+  }
+  if (sub) {
+    TRY(grow(ws->kfull, (size_t)o.nvpairs * o.npix * 8));
+    launch_scatter(R, w, A->samp_off, A->samp_idx, ws->kfull.as<float2>(), o.npix, (int)o.nvpairs,
+                   o.nvpairs * o.npix, A->nsamples, A->L, o.nc, s);
+    LAUNCH_CHECK("scatter");
+    launch_compress_frames(ws->kfull.as<float2>(), o.npix, Sv, A->L, Dsub->L, V, out, s);
+    LAUNCH_CHECK("compress frames");
+  } else {
+    launch_scatter(R, w, A->samp_off, A->samp_idx, out, o.npix, (int)o.nvpairs, o.nvpairs * o.npix, A->nsamples,
+                   A->L, o.nc, s);
+    LAUNCH_CHECK("scatter");
+  }
+  launch_fft2(out, nkimg, A->ny, A->nx, 1, s);
+  LAUNCH_CHECK("ifft2");
+  return MRF_OK;
+}
+
 // R = A X - Y; partial weighted norms per virtual (slice, coil, frame) pair
 // into part[0..nvpairs).  With coil maps the images are first expanded to
 // their c weighted copies.  With a temporally compressed dictionary Dsub
-// (Lfull > 0) X holds Dsub->L compressed frames per slice: their images are
-// transformed and each sample combines them with V (eq. gradcompression).
+// (Lfull > 0) X holds Dsub->L compressed frames per slice (eq. gradcompression).
 mrf_status forward_into(mrf_dict_s *ws, const mrf_op *A, const float2 *X, const float2 *Y,
                         float2 *R, double *part, hipStream_t s, const mrf_dict_s *Dsub = nullptr) {
   const OpDims o = dims_of(A);
   const bool sub = Dsub && Dsub->Lfull > 0;
   const int F = sub ? Dsub->L : A->L;                     // image frames per slice
-  const int64_t nkimg = (int64_t)A->nslices * o.nc * F;   // k-space images
+  const int64_t nkimg = (int64_t)A->nslices * o.nc * F;   // images after the coil expansion
   TRY(grow(ws->kbuf, (size_t)nkimg * o.npix * 8));
   if (o.maps) {
     launch_coil_expand(X, o.maps, A->nslices, o.nc, F, o.npix, ws->kbuf.as<float2>(), s);
@@ -526,48 +618,22 @@ mrf_status forward_into(mrf_dict_s *ws, const mrf_op *A, const float2 *X, const 
   } else {
     HIP_TRY(hipMemcpyAsync(ws->kbuf.p, X, (size_t)nkimg * o.npix * 8, hipMemcpyDeviceToDevice, s));
   }
-  launch_fft2(ws->kbuf.as<float2>(), nkimg, A->ny, A->nx, 0, s);
-  LAUNCH_CHECK("fft2");
-  if (sub)
-    launch_sample_sub(ws->kbuf.as<float2>(), o.npix, A->L, Dsub->L, Dsub->Vs.as<float2>(), A->samp_off,
-                      A->samp_idx, Y, A->dcf, R, part, (int)o.nvpairs, A->nsamples, o.nc, s);
-  else
-    launch_sample(ws->kbuf.as<float2>(), o.npix, A->samp_off, A->samp_idx, Y, A->dcf, R, part, (int)o.nvpairs,
-                  A->nsamples, A->L, o.nc, s);
-  LAUNCH_CHECK("sample");
-  return MRF_OK;
+  return transform_sample(ws, A, o, ws->kbuf.as<float2>(), F, Dsub, Y, R, part, s);
 }
 
-// G = A^H diag(w) R: samples scattered into the (slice, coil) full-frame
-// k-space, compressed by V^H when Dsub is a compressed dictionary, inverse
-// transforms of the (compressed) frames, then coils combined with conj(S_q).
-// Workspace from ws (kfull, cbuf).
+// G = A^H diag(w) R, coils combined with conj(S_q).
 mrf_status adjoint_into(mrf_dict_s *ws, const mrf_op *A, const float2 *R, const float *w, float2 *G,
                         hipStream_t s, const mrf_dict_s *Dsub = nullptr) {
   const OpDims o = dims_of(A);
   const bool sub = Dsub && Dsub->Lfull > 0;
   const int F = sub ? Dsub->L : A->L;
-  const int64_t nkimg = (int64_t)A->nslices * o.nc * F;  // images before the coil combination
+  const int64_t nkimg = (int64_t)A->nslices * o.nc * F;
   float2 *Gc = G;
   if (o.maps) {
     TRY(grow(ws->cbuf, (size_t)nkimg * o.npix * 8));
     Gc = ws->cbuf.as<float2>();
   }
-  if (sub) {
-    TRY(grow(ws->kfull, (size_t)o.nvpairs * o.npix * 8));
-    launch_scatter(R, w, A->samp_off, A->samp_idx, ws->kfull.as<float2>(), o.npix, (int)o.nvpairs,
-                   o.nvpairs * o.npix, A->nsamples, A->L, o.nc, s);
-    LAUNCH_CHECK("scatter");
-    launch_compress_frames(ws->kfull.as<float2>(), o.npix, A->nslices * o.nc, A->L, Dsub->L,
-                           Dsub->Vs.as<float2>(), Gc, s);
-    LAUNCH_CHECK("compress frames");
-  } else {
-    launch_scatter(R, w, A->samp_off, A->samp_idx, Gc, o.npix, (int)o.nvpairs, o.nvpairs * o.npix, A->nsamples,
-                   A->L, o.nc, s);
-    LAUNCH_CHECK("scatter");
-  }
-  launch_fft2(Gc, nkimg, A->ny, A->nx, 1, s);
-  LAUNCH_CHECK("ifft2");
+  TRY(scatter_transform(ws, A, o, R, w, Dsub, Gc, s));
   if (o.maps) {
     launch_coil_combine(Gc, o.maps, A->nslices, o.nc, F, o.npix, G, s);
     LAUNCH_CHECK("coil combine");
@@ -678,15 +744,7 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
     LAUNCH_CHECK("coil expand(dX)");
     K = D->cbuf.as<float2>();
   }
-  launch_fft2(K, nkimg, A->ny, A->nx, 0, s);
-  LAUNCH_CHECK("fft2(dX)");
-  if (D->Lfull > 0)
-    launch_sample_sub(K, npix, A->L, D->L, D->Vs.as<float2>(), A->samp_off, A->samp_idx, nullptr, A->dcf,
-                      D->abuf.as<float2>(), nullptr, (int)nvp, A->nsamples, od.nc, s);
-  else
-    launch_sample(K, npix, A->samp_off, A->samp_idx, nullptr, A->dcf, D->abuf.as<float2>(), nullptr, (int)nvp,
-                  A->nsamples, A->L, od.nc, s);
-  LAUNCH_CHECK("sample(dX)");
+  TRY(transform_sample(D, A, od, K, D->L, D, nullptr, D->abuf.as<float2>(), nullptr, s));
   launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)nvp, A->nsamples,
                     A->L, od.nc, red + 8192, red + 8192 + nvp, R_update, s);
   LAUNCH_CHECK("step_norms");

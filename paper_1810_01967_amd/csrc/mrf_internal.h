@@ -127,6 +127,25 @@ void launch_coil_expand(const float2 *X, const float2 *maps, int S, int ncoil, i
                         hipStream_t s);
 void launch_coil_combine(const float2 *Gc, const float2 *maps, int S, int ncoil, int F, int64_t npix, float2 *G,
                          hipStream_t s);
+// Non-uniform FFT (gridding on the 2x oversampled grid, kernel width W,
+// "exponential of semicircle" parameter beta).  pad: images [nimg][ny][nx]
+// -> fine grids [nimg][2ny][2nx] (centred, times the deapodisation dy dx);
+// crop: the reverse; interp: samples of every virtual pair from its fine
+// grid (V non-null: from the sdim compressed fine grids of its (slice,
+// coil)); spread: the adjoint of interp into [nvpairs][2ny][2nx] (samples
+// of each pair sorted by 8 x 8 fine-cell bins: bperm [M], boff
+// [npairs][nbins + 1] offsets within the pair).
+void launch_nufft_pad(const float2 *X, int64_t nimg, int ny, int nx, const float *dy, const float *dx, float2 *out,
+                      hipStream_t s);
+void launch_nufft_crop(const float2 *K, int64_t nimg, int ny, int nx, const float *dy, const float *dx, float2 *X,
+                       hipStream_t s);
+void launch_nufft_interp(const float2 *K, int ny, int nx, int W, float beta, const int64_t *off,
+                         const float2 *coords, const float2 *Y, const float *w, float2 *R, double *part,
+                         int nvpairs, int64_t M, int L, int ncoil, const float2 *V, int sdim, hipStream_t s);
+void launch_nufft_spread(const float2 *R, const float *w, const int64_t *off, const float2 *coords,
+                         const int32_t *bperm, const int32_t *boff, int ny, int nx, int W, float beta, int64_t M,
+                         int L, int ncoil, int64_t nvpairs, float2 *out, hipStream_t s);
+
 // Temporal subspace (V: FP32 complex [L][sdim], frame-major rows).
 // out[r][t] = row r of the FP32 normalised atoms widened to FP64 complex.
 void launch_widen(const float *dhat, int Kp, int is_complex, int64_t rows, int L, double2 *out, hipStream_t s);

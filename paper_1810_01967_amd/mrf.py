@@ -30,7 +30,8 @@ EXPORTS = ["mrf_last_error", "mrf_version", "mrf_dict_build", "mrf_dict_destroy"
            "mrf_net_set_standardisation", "mrf_net_get_standardisation", "mrf_net_forward",
            "mrf_net_forward_bf16",
            "mrf_net_loss_grad", "mrf_net_adam", "mrf_net_noisy_batch", "mrf_net_train",
-           "mrf_op_forward", "mrf_op_adjoint", "mrf_ipg_step", "mrf_ipg_solve", "mrf_quantize_rows"]
+           "mrf_op_forward", "mrf_op_adjoint", "mrf_ipg_step", "mrf_ipg_solve", "mrf_quantize_rows",
+           "mrf_nufft_create", "mrf_nufft_destroy"]
 
 
 class MrfError(RuntimeError):
@@ -96,7 +97,7 @@ class Op(ctypes.Structure):
                 ("nslices", ctypes.c_int32), ("nsamples", ctypes.c_int64),
                 ("samp_off", ctypes.c_void_p), ("samp_idx", ctypes.c_void_p),
                 ("dcf", ctypes.c_void_p), ("ncoils", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("smaps", ctypes.c_void_p)]
+                ("smaps", ctypes.c_void_p), ("nufft", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -142,6 +143,10 @@ def lib():
         L.mrf_dict_subspace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.mrf_dict_align.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                                      ctypes.POINTER(ctypes.c_void_p)]
+        L.mrf_nufft_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.mrf_nufft_destroy.argtypes = [ctypes.c_void_p]
         L.mrf_match.argtypes = [ctypes.c_void_p, ctypes.POINTER(MatchOpts), ctypes.c_int64,
                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -537,14 +542,41 @@ def mrf_net_train(net: Net, D: Dictionary, samples=2_000_000, batch=4096, epochs
 
 
 # --------------------------------------------------------------------------- operator
+class Nufft:
+    """Non-uniform FFT plan of a non-Cartesian trajectory (mrf_nufft_create)."""
+
+    def __init__(self, nx, ny, L, nslices, samp_off, coords, width=0):
+        off = np.ascontiguousarray(samp_off, dtype=np.int64)
+        k = np.ascontiguousarray(coords, dtype=np.float32)
+        h = ctypes.c_void_p()
+        _check(lib().mrf_nufft_create(int(nx), int(ny), int(L), int(nslices), int(off[-1]), off.ctypes.data,
+                                      k.ctypes.data, int(width), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().mrf_nufft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Operator:
     """mrf_op over device copies of a CSR sampling pattern (see include/mrf.h)."""
 
-    def __init__(self, nx, ny, L, nslices, samp_off, samp_idx, dcf=None, smaps=None):
+    def __init__(self, nx, ny, L, nslices, samp_off, samp_idx, dcf=None, smaps=None, nufft=None):
         """smaps: coil sensitivity maps [nslices][c][ny][nx] (complex), or None
-        for one coil with S = I; with c coils the sample arrays are [c][M]."""
+        for one coil with S = I; with c coils the sample arrays are [c][M].
+        nufft: a Nufft plan for non-Cartesian samples (samp_idx unused)."""
         torch = _torch()
         self.off = torch.as_tensor(np.asarray(samp_off, dtype=np.int64)).cuda()
+        self.nufft = nufft
+        if samp_idx is None:
+            samp_idx = np.zeros(0, dtype=np.int32)
         self.idx = torch.as_tensor(np.asarray(samp_idx, dtype=np.int32)).cuda()
         self.dcf = None if dcf is None else torch.as_tensor(np.asarray(dcf, dtype=np.float32)).cuda()
         self.nx, self.ny, self.L, self.nslices = int(nx), int(ny), int(L), int(nslices)
@@ -558,7 +590,7 @@ class Operator:
             self.ncoils = int(sm.shape[1])
         self.c = Op(self.nx, self.ny, self.L, self.nslices, self.M, _dev(self.off),
                     _dev(self.idx) if self.idx.numel() else None, _dev(self.dcf), self.ncoils, 0,
-                    _dev(self.smaps))
+                    _dev(self.smaps), None if nufft is None else nufft.handle)
 
     @property
     def n(self):
@@ -572,6 +604,13 @@ class Operator:
     @classmethod
     def from_sampling(cls, smp, smaps=None):
         return cls(smp.nx, smp.ny, smp.L, smp.S, smp.off, smp.idx, smp.dcf, smaps=smaps)
+
+    @classmethod
+    def from_trajectory(cls, tr, smaps=None, width=0, dcf=True):
+        """Non-Cartesian operator of a trajectory (coords [M][2] (ky, kx) in
+        cycles per pixel, CSR offsets per (slice, frame))."""
+        plan = Nufft(tr.nx, tr.ny, tr.L, tr.S, tr.off, tr.coords, width)
+        return cls(tr.nx, tr.ny, tr.L, tr.S, tr.off, None, tr.dcf if dcf else None, smaps=smaps, nufft=plan)
 
 
 def mrf_op_forward(A: Operator, X, Y=None, want_norm=False, stream=None):
