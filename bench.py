@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--learned-precisions", default="bf16x3,fp32",
                     help="local-search arithmetic(s) of the learned path")
     ap.add_argument("--tree", type=int, default=1, help="build the cover tree and run the eps sweep")
+    ap.add_argument("--iteration", type=int, default=1,
+                    help="time projected-gradient steps: Cartesian 1 / 4 coils, spiral non-uniform FFT with "
+                         "6 coils and DCF (also compressed, s = 200), phase-aligned")
     ap.add_argument("--subspace", default="20,200",
                     help="temporal subspace sizes s for the compressed matched filter ('' to skip)")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="time the FP64 oracle on a sample")
@@ -254,6 +257,10 @@ def main():
             subspace.append(row)
             del C, Zc
 
+    iteration = None
+    if args.iteration:
+        iteration = iteration_bench(m, torch, D, Dd, net if args.learned else None, args)
+
     ok = [lp for lp in args.learned_precisions.split(",")
           if learned is not None and learned[lp]["index_mismatch_vs_exhaustive_fp32"] <= 1e-3]
     if ok:
@@ -311,6 +318,8 @@ def main():
         res["cover_tree"] = tree
     if subspace is not None:
         res["subspace"] = subspace
+    if iteration is not None:
+        res["iteration"] = iteration
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -323,6 +332,69 @@ def main():
         res["cpu_baseline"], res["vs_fp64_oracle_on_sample"] = cpu_baseline(Dd, Z, args.cpu_sample, answers)
     print(json.dumps(res), flush=True)
     return 0
+
+
+def iteration_bench(m, torch, D, Dd, net, args):
+    """Projected-gradient steps (eq. blip / eq. blip_dcf) on the headline
+    dictionary (100,800 atoms, L = 500) with the exhaustive split-BF16
+    projection (and the learned one on the Cartesian case): ms per step, and
+    the operator alone (A then A^H) per step.  Inputs: smooth bSSFP phantoms,
+    k-space simulated on the host with noise at 30 dB."""
+    from synth import workloads
+    out = {}
+    t0 = time.time()
+    ph256 = workloads.smooth_phantom(Dd, seed=7, S=1, size=256)
+    smp = workloads.random_lines(7, 1, Dd.L, 256, 256, 26)
+    sm4 = workloads.coil_maps(7, 1, 4, 256, 256)
+    ph128 = workloads.smooth_phantom(Dd, seed=8, S=1, size=128)
+    tr = workloads.spiral_trajectory(1, Dd.L, 128, 128, frac=1.0 / 48)
+    sm6 = workloads.coil_maps(8, 1, 6, 128, 128)
+    Ycart = workloads.simulate_kspace(ph256.X0, smp, 30.0, 7)
+    Y4 = workloads.simulate_kspace(ph256.X0, smp, 30.0, 7, smaps=sm4)
+    Ysp = workloads.simulate_kspace_nc(ph128.X0, tr, 30.0, 8, smaps=sm6)
+    log(f"iteration inputs generated in {time.time() - t0:.1f}s")
+    Dc = D.compress(200)
+    Da = D.align()
+    A1 = m.Operator.from_sampling(smp)
+    A4 = m.Operator.from_sampling(smp, smaps=sm4)
+    As = m.Operator.from_trajectory(tr, smaps=sm6)
+    cases = [("cartesian_256_1coil", D, A1, Ycart, 256, Dd.L, {}),
+             ("cartesian_256_4coils", D, A4, Y4, 256, Dd.L, {}),
+             ("cartesian_256_1coil_phase_aligned", Da, A1, Ycart, 256, Dd.L, {}),
+             ("spiral_128_6coils_dcf_nufft", D, As, Ysp, 128, Dd.L, {}),
+             ("spiral_128_6coils_dcf_nufft_s200", Dc, As, Ysp, 128, 200, {})]
+    if net is not None:
+        cases.insert(1, ("cartesian_256_1coil_learned", D, A1, Ycart, 256, Dd.L,
+                         {"net": net, "recentre": args.recentre}))
+    for name, DD, A, Y, size, F, kw in cases:
+        Yd = torch.from_numpy(np.ascontiguousarray(Y.astype(np.complex64))).cuda()
+        X = torch.zeros((1, F, size, size), dtype=torch.complex64, device="cuda")
+        X1, _, _, _ = m.mrf_ipg_step(DD, A, Yd, X, 1.0, precision="bf16x3", stats=False, **kw)
+        torch.cuda.synchronize()
+        steps = 3
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            X2, _, _, st = m.mrf_ipg_step(DD, A, Yd, X1, 1.0, precision="bf16x3", stats=False, **kw)
+        ev1.record()
+        torch.cuda.synchronize()
+        step_ms = ev0.elapsed_time(ev1) / steps
+        # the operator alone: forward of the full-frame image, then the adjoint
+        Xf = torch.zeros((1, Dd.L, size, size), dtype=torch.complex64, device="cuda")
+        m.mrf_op_forward(A, Xf)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(steps):
+            R = m.mrf_op_forward(A, Xf, Yd)
+            m.mrf_op_adjoint(A, R)
+        ev1.record()
+        torch.cuda.synchronize()
+        op_ms = ev0.elapsed_time(ev1) / steps
+        out[name] = {"ms_per_step": step_ms, "operator_ms_full_frames": op_ms, "voxels": size * size,
+                     "frames": F, "samples_per_coil": int(A.M), "coils": max(A.ncoils, 1),
+                     "projection": "learned + split-BF16 local search" if "net" in kw else "exhaustive split BF16"}
+        log(f"iteration {name}: {step_ms:.2f} ms per step, operator (A, A^H on {Dd.L} frames) {op_ms:.2f} ms")
+    return out
 
 
 def cpu_baseline(Dd, Z, sample, answers):

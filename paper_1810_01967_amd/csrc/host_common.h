@@ -125,6 +125,7 @@ struct mrf_dict_s {
   mrf::DevBuf kfull;                // full-frame k-space of the compressed adjoint
   mrf::DevBuf cbuf;                 // per-coil images (coil maps)
   mrf::DevBuf nbuf, nbuf2;          // oversampled grids of the non-uniform FFT
+  mrf::DevBuf xfull;                // full-frame images of a compressed iterate (non-uniform FFT)
   // phase alignment (complex PD): first principal direction u [L] (FP32
   // complex), per-atom alignment factors f_j [d] (aligned atom = f_j Dhat_j),
   // per-voxel factors e^{i theta_v} of the last packing

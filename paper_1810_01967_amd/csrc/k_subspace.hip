@@ -121,6 +121,54 @@ __global__ __launch_bounds__(256) void k_compress_frames(const float2 *__restric
     if (kk < kn) dst[(int64_t)(k0 + kk) * npix] = make_float2(ar[kk], ai[kk]);
 }
 
+// X [S][L][npix] = per pixel sum_k V[t, k] Xc [S][sdim][npix]: 32 frames per
+// thread, V read at wave-uniform addresses, compressed frames in order.
+__global__ __launch_bounds__(256) void k_expand_frames(const float2 *__restrict__ Xc, int64_t npix, int L, int sdim,
+                                                       const float2 *__restrict__ V, float2 *__restrict__ X) {
+  const int nchunk = (L + SUB_KC - 1) / SUB_KC;
+  const int64_t tiles = (npix + 255) / 256;
+  const int64_t bid = blockIdx.x;
+  const int chunk = (int)(bid % nchunk);
+  const int64_t rest = bid / nchunk;
+  const int64_t tile = rest % tiles;
+  const int sl = (int)(rest / tiles);
+  const int t0 = chunk * SUB_KC;
+  const int tn = min(SUB_KC, L - t0);
+  const int64_t pix = tile * 256 + threadIdx.x;
+  if (pix >= npix) return;
+  float ar[SUB_KC], ai[SUB_KC];
+#pragma unroll
+  for (int tt = 0; tt < SUB_KC; ++tt) {
+    ar[tt] = 0.f;
+    ai[tt] = 0.f;
+  }
+  const float2 *src = Xc + (int64_t)sl * sdim * npix + pix;
+  for (int k = 0; k < sdim; ++k) {
+    const float2 x = src[(int64_t)k * npix];
+#pragma unroll
+    for (int tt = 0; tt < SUB_KC; ++tt) {
+      if (tt < tn) {
+        const float2 v = V[(int64_t)(t0 + tt) * sdim + k];  // v * x
+        ar[tt] = fmaf(v.x, x.x, fmaf(-v.y, x.y, ar[tt]));
+        ai[tt] = fmaf(v.x, x.y, fmaf(v.y, x.x, ai[tt]));
+      }
+    }
+  }
+  float2 *dst = X + (int64_t)sl * L * npix + pix;
+#pragma unroll
+  for (int tt = 0; tt < SUB_KC; ++tt)
+    if (tt < tn) dst[(int64_t)(t0 + tt) * npix] = make_float2(ar[tt], ai[tt]);
+}
+
+void launch_expand_frames(const float2 *Xc, int64_t npix, int S, int L, int sdim, const float2 *V, float2 *X,
+                          hipStream_t s) {
+  const int nchunk = (L + SUB_KC - 1) / SUB_KC;
+  const int64_t tiles = (npix + 255) / 256;
+  const int64_t blocks = (int64_t)S * tiles * nchunk;
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_expand_frames, dim3((unsigned)blocks), dim3(256), 0, s, Xc, npix, L, sdim, V, X);
+}
+
 void launch_compress_frames(const float2 *Kfull, int64_t npix, int S, int L, int sdim, const float2 *V, float2 *Kc,
                             hipStream_t s) {
   const int nchunk = (sdim + SUB_KC - 1) / SUB_KC;

@@ -609,14 +609,25 @@ mrf_status forward_into(mrf_dict_s *ws, const mrf_op *A, const float2 *X, const 
                         float2 *R, double *part, hipStream_t s, const mrf_dict_s *Dsub = nullptr) {
   const OpDims o = dims_of(A);
   const bool sub = Dsub && Dsub->Lfull > 0;
-  const int F = sub ? Dsub->L : A->L;                     // image frames per slice
-  const int64_t nkimg = (int64_t)A->nslices * o.nc * F;   // images after the coil expansion
+  int F = sub ? Dsub->L : A->L;  // image frames per slice
+  const float2 *src = X;
+  if (sub && A->nufft) {
+    // non-uniform F: the per-sample interpolation dominates, so V acts in the
+    // image domain (X = V X~ per pixel) and the transform runs on the L frames
+    TRY(grow(ws->xfull, (size_t)A->nslices * A->L * o.npix * 8));
+    launch_expand_frames(X, o.npix, A->nslices, A->L, Dsub->L, Dsub->Vs.as<float2>(), ws->xfull.as<float2>(), s);
+    LAUNCH_CHECK("expand frames");
+    src = ws->xfull.as<float2>();
+    F = A->L;
+    Dsub = nullptr;
+  }
+  const int64_t nkimg = (int64_t)A->nslices * o.nc * F;  // images after the coil expansion
   TRY(grow(ws->kbuf, (size_t)nkimg * o.npix * 8));
   if (o.maps) {
-    launch_coil_expand(X, o.maps, A->nslices, o.nc, F, o.npix, ws->kbuf.as<float2>(), s);
+    launch_coil_expand(src, o.maps, A->nslices, o.nc, F, o.npix, ws->kbuf.as<float2>(), s);
     LAUNCH_CHECK("coil expand");
   } else {
-    HIP_TRY(hipMemcpyAsync(ws->kbuf.p, X, (size_t)nkimg * o.npix * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws->kbuf.p, src, (size_t)nkimg * o.npix * 8, hipMemcpyDeviceToDevice, s));
   }
   return transform_sample(ws, A, o, ws->kbuf.as<float2>(), F, Dsub, Y, R, part, s);
 }
@@ -626,6 +637,13 @@ mrf_status adjoint_into(mrf_dict_s *ws, const mrf_op *A, const float2 *R, const 
                         hipStream_t s, const mrf_dict_s *Dsub = nullptr) {
   const OpDims o = dims_of(A);
   const bool sub = Dsub && Dsub->Lfull > 0;
+  if (sub && A->nufft) {  // the full-frame adjoint, then V^H per pixel (see forward_into)
+    TRY(grow(ws->xfull, (size_t)A->nslices * A->L * o.npix * 8));
+    TRY(adjoint_into(ws, A, R, w, ws->xfull.as<float2>(), s, nullptr));
+    launch_compress_frames(ws->xfull.as<float2>(), o.npix, A->nslices, A->L, Dsub->L, Dsub->Vs.as<float2>(), G, s);
+    LAUNCH_CHECK("compress frames");
+    return MRF_OK;
+  }
   const int F = sub ? Dsub->L : A->L;
   const int64_t nkimg = (int64_t)A->nslices * o.nc * F;
   float2 *Gc = G;
@@ -705,7 +723,6 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
   const int64_t npix = od.npix;
   const int64_t n = (int64_t)A->nslices * npix;
   const int64_t nimg = (int64_t)A->nslices * D->L;   // image frames (compressed frames if Lfull > 0)
-  const int64_t nkimg = nimg * od.nc;                // k-space images (slice, coil, frame)
   const int64_t nvp = od.nvpairs;                    // sampled (slice, coil, frame) pairs
   const int64_t n_pad = round_up(n, kRowPad);
   const int real = D->is_complex ? 0 : 1;
@@ -713,7 +730,6 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
   TRY(grow(D->znorm, (size_t)n_pad * 4));
   TRY(grow(D->counters, 64));
   TRY(grow(D->kbuf, (size_t)nimg * npix * 8));
-  if (od.maps) TRY(grow(D->cbuf, (size_t)nkimg * npix * 8));
   TRY(grow(D->abuf, (size_t)(od.nsamp > 0 ? od.nsamp : 1) * 8));
   TRY(grow(D->red, (size_t)(8192 + 2 * nvp + 8) * 8));
   TRY(grow(D->scal, 64));
@@ -737,14 +753,26 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
                  X_new, X, D->kbuf.as<float2>(), red, &nb, s, vph);
   LAUNCH_CHECK("write_x");
   launch_reduce_sum(red, nb, D->scal.as<double>() + 0, s);
-  // A dX: dX sits in kbuf (coil copies in cbuf with coil maps)
+  // A dX: dX sits in kbuf (full frames in xfull for a compressed iterate
+  // under the non-uniform F, coil copies in cbuf with coil maps)
   float2 *K = D->kbuf.as<float2>();
+  int F = D->L;
+  const mrf_dict_s *tsub = D;
+  if (D->Lfull > 0 && A->nufft) {
+    TRY(grow(D->xfull, (size_t)A->nslices * A->L * npix * 8));
+    launch_expand_frames(K, npix, A->nslices, A->L, D->L, D->Vs.as<float2>(), D->xfull.as<float2>(), s);
+    LAUNCH_CHECK("expand frames(dX)");
+    K = D->xfull.as<float2>();
+    F = A->L;
+    tsub = nullptr;
+  }
   if (od.maps) {
-    launch_coil_expand(D->kbuf.as<float2>(), od.maps, A->nslices, od.nc, D->L, npix, D->cbuf.as<float2>(), s);
+    TRY(grow(D->cbuf, (size_t)A->nslices * od.nc * F * npix * 8));
+    launch_coil_expand(K, od.maps, A->nslices, od.nc, F, npix, D->cbuf.as<float2>(), s);
     LAUNCH_CHECK("coil expand(dX)");
     K = D->cbuf.as<float2>();
   }
-  TRY(transform_sample(D, A, od, K, D->L, D, nullptr, D->abuf.as<float2>(), nullptr, s));
+  TRY(transform_sample(D, A, od, K, F, tsub, nullptr, D->abuf.as<float2>(), nullptr, s));
   launch_step_norms(D->rbuf.as<float2>(), D->abuf.as<float2>(), A->dcf, A->samp_off, (int)nvp, A->nsamples,
                     A->L, od.nc, red + 8192, red + 8192 + nvp, R_update, s);
   LAUNCH_CHECK("step_norms");

@@ -154,6 +154,9 @@ void launch_widen(const float *dhat, int Kp, int is_complex, int64_t rows, int L
 void launch_sample_sub(const float2 *Kc, int64_t npix, int L, int sdim, const float2 *V, const int64_t *off,
                        const int32_t *sidx, const float2 *Y, const float *w, float2 *R, double *part, int nvpairs,
                        int64_t M, int ncoil, hipStream_t s);
+// X [S][L][npix] = per pixel sum_k V[t, k] Xc [S][sdim][npix].
+void launch_expand_frames(const float2 *Xc, int64_t npix, int S, int L, int sdim, const float2 *V, float2 *X,
+                          hipStream_t s);
 // Kc [S][sdim][npix] = per pixel sum_t conj(V[t, k]) Kfull [S][L][npix]
 // (S counts virtual slices: slice x coil).
 void launch_compress_frames(const float2 *Kfull, int64_t npix, int S, int L, int sdim, const float2 *V, float2 *Kc,

@@ -433,17 +433,17 @@ def simulate_kspace_nc(X0: np.ndarray, tr: Trajectory, snr_db, seed: int, smaps=
     [c][M]."""
     S, L, ny, nx = X0.shape
     c = 1 if smaps is None else smaps.shape[1]
-    ry, rx = np.mgrid[0:ny, 0:nx]
-    ry, rx = ry.reshape(-1).astype(np.float64), rx.reshape(-1).astype(np.float64)
     Y = np.empty((c, tr.M), dtype=np.complex128)
-    for q in range(c):
-        for s in range(S):
-            for t in range(L):
-                p = s * L + t
-                k = tr.coords[tr.off[p]:tr.off[p + 1]].astype(np.float64)
-                E = np.exp(-2j * np.pi * (np.outer(k[:, 0], ry) + np.outer(k[:, 1], rx)))
+    for s in range(S):
+        for t in range(L):
+            p = s * L + t
+            k = tr.coords[tr.off[p]:tr.off[p + 1]].astype(np.float64)
+            # exp(-2 pi i (ky ry + kx rx)) evaluated as the product of its two factors
+            ey = np.exp(-2j * np.pi * k[:, 0:1] * np.arange(ny)[None, :])
+            ex = np.exp(-2j * np.pi * k[:, 1:2] * np.arange(nx)[None, :])
+            for q in range(c):
                 img = X0[s, t] if smaps is None else smaps[s, q] * X0[s, t]
-                Y[q, tr.off[p]:tr.off[p + 1]] = E @ img.reshape(-1) / np.sqrt(ny * nx)
+                Y[q, tr.off[p]:tr.off[p + 1]] = np.sum((ey @ img) * ex, axis=1) / np.sqrt(ny * nx)
     if snr_db is not None and np.isfinite(snr_db):
         sig2 = np.sum(np.abs(Y) ** 2) / max(c * tr.M, 1) * 10.0 ** (-snr_db / 10.0)
         Y = Y + (rng.complex_gaussian(seed, "kspace-noise", (tr.M,), sig2)[None] if c == 1
