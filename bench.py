@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--recentre", type=int, default=2)
+    ap.add_argument("--box-radius", type=int, default=2, help="local-search box radius (grid cells)")
     ap.add_argument("--learned-precisions", default="bf16x3,fp32",
                     help="local-search arithmetic(s) of the learned path")
     ap.add_argument("--tree", type=int, default=1, help="build the cover tree and run the eps sweep")
@@ -175,7 +176,7 @@ def main():
         fastest = min([ms32] + [v["ms_per_step"] for v in variants.values()
                                 if v["index_mismatch_vs_fp32"] <= 1e-3])
         for lp in args.learned_precisions.split(","):
-            lms, lst, lo = run(args.steps, args.warmup, net=net, box_radius=3, fallback_corr=0.98,
+            lms, lst, lo = run(args.steps, args.warmup, net=net, box_radius=args.box_radius, fallback_corr=0.98,
                                recentre=args.recentre, precision=lp)
             lidx = lo["idx"].cpu().numpy()
             answers[f"learned_{lp}"] = (lidx, lo["pd"].cpu().numpy())

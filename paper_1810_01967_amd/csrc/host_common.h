@@ -88,7 +88,7 @@ mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
                       int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
                       hipEvent_t ev_s0, hipEvent_t ev_s1, int *splits_used, mrf_match_stats *st);
 mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t slice_voxels,
-                       int64_t n, hipStream_t s);
+                       int64_t n, hipStream_t s, bool want_x3 = false);
 mrf_status check_opts(const mrf_dict_s *D, const mrf_match_opts *o);
 mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
                       int32_t *idx, float *pd, float *corr, float *params_out, mrf_match_stats *st,
@@ -117,6 +117,7 @@ struct mrf_dict_s {
   int64_t fallback_total = 0;  // voxels sent to the exhaustive fallback by the learned path (all calls)
   // workspace (grows lazily)
   mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j, zx3;
+  bool zx3_fresh = false;  // zx3 holds the split rows of the current packing (written by the pack)
   mrf::DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;
   // temporal subspace (a compressed dictionary: atoms V^H Dhat_j of L = s frames)
   int Lfull = 0;                    // frames of the uncompressed dictionary, 0 if not compressed

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cfloat>
 
+#include "k_split.h"
 #include "mrf_internal.h"
 
 namespace mrf {
@@ -129,11 +130,6 @@ __device__ __forceinline__ bool lbetter(float s1, int j1, float s0, int j0) {
   return (s1 > s0) || (s1 == s0 && j1 >= 0 && (j0 < 0 || j1 < j0));
 }
 
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
 
 // Split FP32 rows [rows][Kp] into BF16 hi = RNE(x), lo = RNE(x - hi),
 // stored per row as Kx/32 chunks [hi 32 | lo 32] (one 128-byte line per
@@ -150,10 +146,7 @@ __global__ void k_split_x3(const float *__restrict__ src, int Kp, int64_t rows, 
   const float xs[4] = {x.x, x.y, x.z, x.w};
   uint16_t hi[4], lo[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    hi[i] = bf16_rne(xs[i]);
-    lo[i] = bf16_rne(xs[i] - __uint_as_float((uint32_t)hi[i] << 16));
-  }
+  for (int i = 0; i < 4; ++i) split_bf16(xs[i], hi[i], lo[i]);
   uint16_t *d = dst + row * 2 * Kx + (k >> 5) * 64 + (k & 31);
   *reinterpret_cast<uint2 *>(d) = make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
   *reinterpret_cast<uint2 *>(d + 32) =

@@ -3,6 +3,7 @@
 // eq. exactPs), and the write of gamma_v D_j* back into image layout.
 #include <cfloat>
 
+#include "k_split.h"
 #include "mrf_internal.h"
 
 namespace mrf {
@@ -23,14 +24,18 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
                                                           int Kp, float *__restrict__ Zp,
                                                           float *__restrict__ znorm,
                                                           unsigned long long *counters,
-                                                          const float2 *__restrict__ vphase) {
+                                                          const float2 *__restrict__ vphase,
+                                                          uint16_t *__restrict__ zx3, int Kx) {
   const int lane = threadIdx.x & 63;
   const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (v >= n_pad) return;
   float *row = Zp + v * Kp;
+  uint16_t *xrow = zx3 ? zx3 + v * 2 * Kx : nullptr;
   const int K = real_atoms ? L : 2 * L;
   if (v >= n) {
     for (int k = lane; k < Kp; k += 64) row[k] = 0.f;
+    if (xrow)
+      for (int k = lane; k < 2 * Kx; k += 64) xrow[k] = 0;
     return;
   }
   const float2 *z = Z + v * (int64_t)L;
@@ -46,8 +51,28 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
       row[2 * t] = a.x;
       row[2 * t + 1] = a.y;
     }
+    if (xrow) {  // split BF16 row, fused
+      if (real_atoms) {
+        uint16_t h, l;
+        split_bf16(a.x, h, l);
+        xrow[split_off(t)] = h;
+        xrow[split_off(t) + 32] = l;
+      } else {
+        uint16_t h0, l0, h1, l1;
+        split_bf16(a.x, h0, l0);
+        split_bf16(a.y, h1, l1);
+        const int64_t o = split_off(2 * t);
+        *reinterpret_cast<uint32_t *>(xrow + o) = h0 | ((uint32_t)h1 << 16);
+        *reinterpret_cast<uint32_t *>(xrow + o + 32) = l0 | ((uint32_t)l1 << 16);
+      }
+    }
   }
   for (int k = K + lane; k < Kp; k += 64) row[k] = 0.f;
+  if (xrow)
+    for (int k = K + lane; k < Kx; k += 64) {
+      xrow[split_off(k)] = 0;
+      xrow[split_off(k) + 32] = 0;
+    }
   acc = wave_sum_f64(acc);
   if (lane == 0) {
     const bool fin = isfinite(acc);
@@ -66,7 +91,8 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
                                                           float *__restrict__ Zp,
                                                           float *__restrict__ znorm,
                                                           unsigned long long *counters,
-                                                          const float2 *__restrict__ vphase) {
+                                                          const float2 *__restrict__ vphase,
+                                                          uint16_t *__restrict__ zx3, int Kx) {
   __shared__ float2 tile[16][65];
   __shared__ double red[4][64];
   const int tid = threadIdx.x;
@@ -102,11 +128,21 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
     __syncthreads();
     if (vw < n_pad) {
       float *row = Zp + vw * Kp;
+      uint16_t *xrow = zx3 ? zx3 + vw * 2 * Kx : nullptr;
       if (real_atoms) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int t = t0 + wp * 4 + q;
-          if (t < L) row[t] = tile[wp * 4 + q][wv].x;
+          if (t < L) {
+            const float x = tile[wp * 4 + q][wv].x;
+            row[t] = x;
+            if (xrow) {
+              uint16_t h, l;
+              split_bf16(x, h, l);
+              xrow[split_off(t)] = h;
+              xrow[split_off(t) + 32] = l;
+            }
+          }
         }
       } else {
 #pragma unroll
@@ -115,6 +151,14 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
           if (t < L) {
             const float2 z = tile[wp * 4 + q][wv];
             *reinterpret_cast<float2 *>(row + 2 * t) = z;
+            if (xrow) {
+              uint16_t h0, l0, h1, l1;
+              split_bf16(z.x, h0, l0);
+              split_bf16(z.y, h1, l1);
+              const int64_t o = split_off(2 * t);
+              *reinterpret_cast<uint32_t *>(xrow + o) = h0 | ((uint32_t)h1 << 16);
+              *reinterpret_cast<uint32_t *>(xrow + o + 32) = l0 | ((uint32_t)l1 << 16);
+            }
           }
         }
       }
@@ -126,6 +170,13 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
   if (vw < n_pad) {
     float *row = Zp + vw * Kp;
     for (int k = K + wp; k < Kp; k += 4) row[k] = 0.f;
+    if (zx3) {
+      uint16_t *xrow = zx3 + vw * 2 * Kx;
+      for (int k = K + wp; k < Kx; k += 4) {
+        xrow[split_off(k)] = 0;
+        xrow[split_off(k) + 32] = 0;
+      }
+    }
   }
   red[fi][vi] = acc;
   __syncthreads();
@@ -140,22 +191,23 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
 
 void launch_pack_voxel_major(const float2 *Z, int64_t n, int64_t n_pad, int L, int real_atoms,
                              int Kp, float *Zp, float *znorm, unsigned long long *counters,
-                             hipStream_t s, const float2 *vphase) {
+                             hipStream_t s, const float2 *vphase, uint16_t *zx3, int Kx) {
   const int64_t blocks = (n_pad + 3) / 4;
   hipLaunchKernelGGL(k_pack_voxel_major, dim3((unsigned)blocks), dim3(256), 0, s, Z, n, n_pad, L,
-                     real_atoms, Kp, Zp, znorm, counters, vphase);
+                     real_atoms, Kp, Zp, znorm, counters, vphase, zx3, Kx);
 }
 
 void launch_pack_frame_major(const float2 *X, const float2 *G, float mu, int64_t n, int64_t n_pad,
                              int64_t npix, int L, int real_atoms, int Kp, float *Zp, float *znorm,
-                             unsigned long long *counters, hipStream_t s, const float2 *vphase) {
+                             unsigned long long *counters, hipStream_t s, const float2 *vphase, uint16_t *zx3,
+                             int Kx) {
   const int64_t blocks = (n_pad + 63) / 64;
   if (G)
     hipLaunchKernelGGL(k_pack_frame_major<true>, dim3((unsigned)blocks), dim3(256), 0, s, X, G,
-                       mu, n, n_pad, npix, L, real_atoms, Kp, Zp, znorm, counters, vphase);
+                       mu, n, n_pad, npix, L, real_atoms, Kp, Zp, znorm, counters, vphase, zx3, Kx);
   else
     hipLaunchKernelGGL(k_pack_frame_major<false>, dim3((unsigned)blocks), dim3(256), 0, s, X,
-                       nullptr, 0.f, n, n_pad, npix, L, real_atoms, Kp, Zp, znorm, counters, vphase);
+                       nullptr, 0.f, n, n_pad, npix, L, real_atoms, Kp, Zp, znorm, counters, vphase, zx3, Kx);
 }
 
 // ---------------------------------------------------------------------------

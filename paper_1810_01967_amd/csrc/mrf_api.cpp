@@ -317,7 +317,7 @@ mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, c
     TRY(grow(D->part_s, (size_t)xs * n * 4));
     TRY(grow(D->part_j, (size_t)xs * n * 4));
     if (ev_s0) HIP_TRY(hipEventRecord(ev_s0, s));
-    launch_split_x3(D->zp.as<float>(), D->Kp, n_pad, D->Kx, D->zx3.as<uint16_t>(), s);
+    if (!D->zx3_fresh) launch_split_x3(D->zp.as<float>(), D->Kp, n_pad, D->Kx, D->zx3.as<uint16_t>(), s);
     launch_score_x3(D->dx3.as<uint16_t>(), D->zx3.as<uint16_t>(), D->d, D->d_pad, n, n_pad, D->Kx, xs,
                     D->part_s.as<float>(), D->part_j.as<int>(), s);
     LAUNCH_CHECK("score_x3");
@@ -377,9 +377,15 @@ mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
 }
 
 mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t slice_voxels,
-                       int64_t n, hipStream_t s) {
+                       int64_t n, hipStream_t s, bool want_x3) {
   const int64_t n_pad = round_up(n, kRowPad);
   TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
+  D->zx3_fresh = false;
+  uint16_t *zx3 = nullptr;
+  if (want_x3) {  // split-BF16 rows written by the packing itself
+    TRY(grow(D->zx3, (size_t)n_pad * 2 * D->Kx * 2));
+    zx3 = D->zx3.as<uint16_t>();
+  }
   TRY(grow(D->znorm, (size_t)n_pad * 4));
   TRY(grow(D->counters, 64));  // [0] zero rows, [1] non-finite rows, [2] local-search work
   launch_zero(D->counters.p, 16, s);
@@ -398,12 +404,13 @@ mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t s
   if (z_layout == MRF_VOXEL_MAJOR)
     launch_pack_voxel_major(static_cast<const float2 *>(Z), n, n_pad, D->L, real, D->Kp,
                             D->zp.as<float>(), D->znorm.as<float>(),
-                            D->counters.as<unsigned long long>(), s, vph);
+                            D->counters.as<unsigned long long>(), s, vph, zx3, D->Kx);
   else
     launch_pack_frame_major(static_cast<const float2 *>(Z), nullptr, 0.f, n, n_pad, slice_voxels,
                             D->L, real, D->Kp, D->zp.as<float>(), D->znorm.as<float>(),
-                            D->counters.as<unsigned long long>(), s, vph);
+                            D->counters.as<unsigned long long>(), s, vph, zx3, D->Kx);
   LAUNCH_CHECK("pack");
+  D->zx3_fresh = want_x3;
   return MRF_OK;
 }
 
@@ -435,7 +442,8 @@ extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t 
     HIP_TRY(hipEventRecord(ev.a, s));
   }
   const int real = D->is_complex ? 0 : 1;
-  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s));
+  const bool want_x3 = opts && opts->precision == MRF_BF16X3 && opts->method != MRF_COVERTREE;
+  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s, want_x3));
   int splits_used = 0;
   TRY(match_core(D, opts, n, warm_idx, idx, pd, corr, params_out, s, ev.c, ev.d, &splits_used, stats));
   const float2 *vph = D->align ? D->vphase.as<float2>() : nullptr;
@@ -742,10 +750,14 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
     LAUNCH_CHECK("voxel phase");
     vph = D->vphase.as<float2>();
   }
+  const bool want_x3 = o && o->precision == MRF_BF16X3 && o->method != MRF_COVERTREE;
+  if (want_x3) TRY(grow(D->zx3, (size_t)n_pad * 2 * D->Kx * 2));
   launch_pack_frame_major(X, D->gbuf.as<float2>(), mu, n, n_pad, npix, D->L, real, D->Kp,
                           D->zp.as<float>(), D->znorm.as<float>(),
-                          D->counters.as<unsigned long long>(), s, vph);
+                          D->counters.as<unsigned long long>(), s, vph,
+                          want_x3 ? D->zx3.as<uint16_t>() : nullptr, D->Kx);
   LAUNCH_CHECK("grad_update_pack");
+  D->zx3_fresh = want_x3;
   TRY(match_core(D, o, n, warm, idx, pd, nullptr, nullptr, s, nullptr, nullptr, nullptr, nullptr));
   double *red = D->red.as<double>();
   int nb = 0;

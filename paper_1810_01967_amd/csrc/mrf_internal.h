@@ -38,13 +38,16 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // Frame-major input: Zf[s][L][npix]; with G != nullptr the packed value is
 // X - mu*G (the gradient update of eq. blip), G in the same layout as X.
 // vphase (optional, [n]): unit factors e^{i theta_v}; each voxel is packed
-// rotated by conj(vphase[v]) (phase-aligned projection).
+// rotated by conj(vphase[v]) (phase-aligned projection).  zx3 (optional):
+// also the split-BF16 rows [n_pad][2 Kx] of the packed rows (the encoding of
+// k_split_x3, zero beyond K and for rows n..n_pad).
 void launch_pack_voxel_major(const float2 *Z, int64_t n, int64_t n_pad, int L, int real_atoms,
                              int Kp, float *Zp, float *znorm, unsigned long long *counters,
-                             hipStream_t s, const float2 *vphase = nullptr);
+                             hipStream_t s, const float2 *vphase = nullptr, uint16_t *zx3 = nullptr, int Kx = 0);
 void launch_pack_frame_major(const float2 *X, const float2 *G, float mu, int64_t n, int64_t n_pad,
                              int64_t npix, int L, int real_atoms, int Kp, float *Zp, float *znorm,
-                             unsigned long long *counters, hipStream_t s, const float2 *vphase = nullptr);
+                             unsigned long long *counters, hipStream_t s, const float2 *vphase = nullptr,
+                             uint16_t *zx3 = nullptr, int Kx = 0);
 // Phase alignment: vphase[v] = c_v/|c_v| with c_v = u^H Z_v accumulated in
 // FP64 ((1, 0) where c_v is 0 or not finite); Z voxel-major [n][L], or
 // frame-major X - mu G (G may be null) over slices of npix voxels.

@@ -564,7 +564,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   const bool x3 = o->precision == MRF_BF16X3;
   if (x3) TRY(ensure_x3(D, s));
   if (st) HIP_TRY(hipEventRecord(ev.a, s));
-  if (x3) {
+  if (x3 && !D->zx3_fresh) {
     TRY(grow(D->zx3, (size_t)n * 2 * D->Kx * 2));
     launch_split_x3(D->zp.as<float>(), D->Kp, n, D->Kx, D->zx3.as<uint16_t>(), s);
     LAUNCH_CHECK("split voxels");
@@ -704,7 +704,7 @@ extern "C" mrf_status mrf_match_local(mrf_dict D, const mrf_match_opts *opts, in
     HIP_TRY(hipEventCreate(&ev.b));
     HIP_TRY(hipEventRecord(ev.a, s));
   }
-  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s));
+  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s, opts && opts->precision == MRF_BF16X3));
   TRY(match_learned(D, opts, n, warm_idx, idx, pd, corr, params_out, cells, fallback, stats, s));
   if (X_out) {
     launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, D->is_complex ? 0 : 1, n, D->L,
