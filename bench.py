@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--learned", type=int, default=1, help="train the network and time the learned path")
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--train-epochs", type=int, default=4)
-    ap.add_argument("--recentre", type=int, default=2)
+    ap.add_argument("--recentre", type=int, default=1, help="re-centring rounds of the local search")
     ap.add_argument("--box-radius", type=int, default=2, help="local-search box radius (grid cells)")
     ap.add_argument("--learned-precisions", default="bf16x3,fp32",
                     help="local-search arithmetic(s) of the learned path")

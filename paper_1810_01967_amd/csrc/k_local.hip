@@ -116,7 +116,10 @@ void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P,
 // local scoring
 // ---------------------------------------------------------------------------
 constexpr int LS_BA = 128, LS_BV = 64;
-constexpr unsigned int LS_RUN = 4;  // consecutive tiles per XCD run
+#ifndef MRF_LS_RUN
+#define MRF_LS_RUN 4
+#endif
+constexpr unsigned int LS_RUN = MRF_LS_RUN;  // consecutive tiles per XCD run (a tuning constant)
 // FP32 operands: K chunks of 16, LDS rows of 20 floats.  Split-BF16 operands:
 // K stages of LS_XC chunks of 32, LDS rows of LS_XC x [hi 32 | lo 32] + pad 8 BF16.
 constexpr int LS_BK32 = 16, LS_LD32 = 20;
