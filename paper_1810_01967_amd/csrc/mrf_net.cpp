@@ -548,7 +548,10 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     LAUNCH_CHECK("cells");
     if (st) HIP_TRY(hipEventRecord(e_prop1, s));
   }
-  const int shift = 2;
+#ifndef MRF_LS_SHIFT
+#define MRF_LS_SHIFT 2
+#endif
+  const int shift = MRF_LS_SHIFT;  // coarse cells of 2^shift grid steps per parameter (a tuning constant)
   const int nkeys = coarse_key_count(g, P, shift);
   TRY(grow(D->hist, (size_t)(4 * nkeys + 8) * 4));
   GroupBufs gb;
