@@ -4,9 +4,10 @@
 //            BF16; h1 is written in BF16;
 //   layer 2: h2 = GELU(h1 W2^T + b2) kept in FP32 and the output layer
 //            y = h2 W3^T + b3 (FP32 W3) fused into the same block.
-// A block computes all 256 hidden units of 128 rows (layer 1, eight waves) or
-// 64 rows (layer 2, four waves); each wave owns 64 rows x 64 units (2 x 2
-// tiles of 32 x 32); K is staged through LDS in chunks of 32.
+// A block computes all 256 hidden units of 256 rows (layer 1, sixteen waves)
+// or 128 rows (layer 2, eight waves, its FP32 h2 tile in LDS); each wave owns
+// 64 rows x 64 units (2 x 2 tiles of 32 x 32); K is staged through LDS in
+// chunks of 32.  Larger row tiles read the weights fewer times.
 #include <cmath>
 
 #include "mrf_internal.h"
@@ -20,6 +21,13 @@ constexpr int MB_H = 256;   // hidden units (= block columns)
 constexpr int MB_BK = 32;   // K per stage
 constexpr int MB_LD = 40;   // LDS row pitch in BF16 (32 + 8 pad)
 constexpr int MB_HLD = 260; // LDS row pitch of the FP32 h2 tile
+// rows per block of the two launches (tuning constants: 4 threads per row)
+#ifndef MRF_MLP_M1
+#define MRF_MLP_M1 256
+#endif
+#ifndef MRF_MLP_M2
+#define MRF_MLP_M2 128
+#endif
 
 __device__ __forceinline__ uint16_t to_bf16(float x) {
   uint32_t u = __float_as_uint(x);
@@ -47,18 +55,18 @@ void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t 
 // LAYER1 = true: A = FP32 rows X (pitch ldx, K valid columns, K % 8 == 0,
 // ldx % 4 == 0) times rowscale, W = W1 BF16 [256][Kx]; writes H1 BF16 [B][256].
 // LAYER1 = false: A = H1 BF16 [B][256], W = W2 BF16 [256][256]; writes Y [B][P].
-template <bool LAYER1>
-__global__ __launch_bounds__(LAYER1 ? 512 : 256, LAYER1 ? 1 : 2) void k_mlp_bf16(int64_t B, const float *__restrict__ X, int64_t ldx, int K,
+template <bool LAYER1, int MB_M>
+__global__ __launch_bounds__(4 * MB_M) void k_mlp_bf16(int64_t B, const float *__restrict__ X, int64_t ldx, int K,
                                                      int Kx, const float *__restrict__ rowscale,
                                                      const uint16_t *__restrict__ H1in,
                                                      const uint16_t *__restrict__ W, const float *__restrict__ bias,
                                                      uint16_t *__restrict__ H1out, const float *__restrict__ W3,
                                                      const float *__restrict__ b3, int P, float *__restrict__ Y) {
-  constexpr int MB_M = LAYER1 ? 128 : 64;       // rows per block
-  constexpr int NT = LAYER1 ? 512 : 256;        // threads per block
+  // MB_M rows per block, one wave per 64 rows x 64 units
+  constexpr int NT = 4 * MB_M;                  // threads per block
   constexpr int NW = MB_H * 4 / NT;             // W chunks of 8 per thread per stage
   constexpr int STAGE = (MB_M + MB_H) * MB_LD;  // BF16 elements per stage
-  constexpr int SMEM = LAYER1 ? 2 * STAGE * 2 : (64 * MB_HLD * 4 > 2 * STAGE * 2 ? 64 * MB_HLD * 4 : 2 * STAGE * 2);
+  constexpr int SMEM = LAYER1 ? 2 * STAGE * 2 : (MB_M * MB_HLD * 4 > 2 * STAGE * 2 ? MB_M * MB_HLD * 4 : 2 * STAGE * 2);
   __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
@@ -192,10 +200,11 @@ void launch_mlp_bf16(int64_t B, const float *X, int64_t ldx, int K, int Kx, cons
                      const uint16_t *W1b, const float *b1, uint16_t *H1, const uint16_t *W2b, const float *b2,
                      const float *W3, const float *b3, int P, float *Y, hipStream_t s) {
   if (B <= 0) return;
-  hipLaunchKernelGGL(k_mlp_bf16<true>, dim3((unsigned)((B + 127) / 128)), dim3(512), 0, s, B, X, ldx, K, Kx,
-                     rowscale, nullptr, W1b, b1, H1, nullptr, nullptr, P, nullptr);
-  hipLaunchKernelGGL(k_mlp_bf16<false>, dim3((unsigned)((B + 63) / 64)), dim3(256), 0, s, B, nullptr, (int64_t)0,
-                     MB_H, MB_H, nullptr, H1, W2b, b2, nullptr, W3, b3, P, Y);
+  constexpr int M1 = MRF_MLP_M1, M2 = MRF_MLP_M2;
+  hipLaunchKernelGGL((k_mlp_bf16<true, M1>), dim3((unsigned)((B + M1 - 1) / M1)), dim3(4 * M1), 0, s, B, X, ldx, K,
+                     Kx, rowscale, nullptr, W1b, b1, H1, nullptr, nullptr, P, nullptr);
+  hipLaunchKernelGGL((k_mlp_bf16<false, M2>), dim3((unsigned)((B + M2 - 1) / M2)), dim3(4 * M2), 0, s, B, nullptr,
+                     (int64_t)0, MB_H, MB_H, nullptr, H1, W2b, b2, nullptr, W3, b3, P, Y);
 }
 
 }  // namespace mrf
