@@ -233,7 +233,10 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
   constexpr int EB = X3 ? 2 : 4;  // bytes per element
   // LDS buffers: FP32 double-buffers its stages; split BF16 (twice the bytes
   // per stage) keeps one buffer, so that more blocks share a CU
-  constexpr int NBUF = X3 ? 1 : 2;
+#ifndef MRF_LS_X3_NBUF
+#define MRF_LS_X3_NBUF 1
+#endif
+  constexpr int NBUF = X3 ? MRF_LS_X3_NBUF : 2;
   __shared__ __attribute__((aligned(16))) unsigned char smem[NBUF * (A_ELEMS + Z_ELEMS) * EB];
   __shared__ int vid[LS_BV];
   __shared__ int vlo[LS_BV][4], vhi[LS_BV][4];
