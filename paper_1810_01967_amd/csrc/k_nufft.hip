@@ -19,7 +19,7 @@
 
 namespace mrf {
 
-constexpr int NUFFT_BIN = 8;
+constexpr int NUFFT_BIN = kNufftBin;
 
 __device__ __forceinline__ float es_kernel(float z, float beta) {
   const float q = 1.f - z * z;

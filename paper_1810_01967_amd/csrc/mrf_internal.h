@@ -24,6 +24,9 @@ constexpr int kPitchLP = 128;
 // Largest temporal subspace dimension of a compressed dictionary (the V row
 // of one frame is staged in LDS by the compressed sampler).
 constexpr int kMaxSubspace = 512;
+// Bin size (oversampled-grid cells per dimension) of the non-uniform FFT's
+// sample sorting, shared by the plan builder and the spreading kernel.
+constexpr int kNufftBin = 8;
 // Atom / voxel row counts are padded to multiples of 256 so every tiling of
 // the scoring kernels reads inside the allocation.
 constexpr int kRowPad = 256;

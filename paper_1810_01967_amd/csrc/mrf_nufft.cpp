@@ -12,30 +12,11 @@
 #include <vector>
 
 #include "host_common.h"
+#include "nufft_host.h"
 
 using namespace mrf;
 
 namespace {
-
-constexpr int kBin = 8;
-
-double es(double z, double beta) {
-  const double q = 1.0 - z * z;
-  return q > 0.0 ? std::exp(beta * (std::sqrt(q) - 1.0)) : 0.0;
-}
-
-// phihat(xi) = 2 int_0^{W/2} phi(u) cos(2 pi u xi) du, phi(u) = es(2u/W)
-double phihat(double xi, int W, double beta) {
-  const int nq = 4096;
-  const double h = 0.5 * W / nq;
-  double acc = 0.0;
-  for (int i = 0; i <= nq; ++i) {
-    const double u = i * h;
-    const double f = es(2.0 * u / W, beta) * std::cos(2.0 * M_PI * u * xi);
-    acc += f * ((i == 0 || i == nq) ? 1.0 : (i & 1) ? 4.0 : 2.0);
-  }
-  return 2.0 * acc * h / 3.0;
-}
 
 bool pow2_in(int x, int lo, int hi) { return x >= lo && x <= hi && (x & (x - 1)) == 0; }
 
@@ -72,36 +53,15 @@ extern "C" mrf_status mrf_nufft_create(int32_t nx, int32_t ny, int32_t L, int32_
   P->W = W;
   P->beta = (float)(2.30 * W);
   P->M = nsamples;
-  const int Ny = 2 * ny, Nx = 2 * nx, nby = Ny / kBin, nbx = Nx / kBin, nb = nby * nbx;
+  const int Ny = 2 * ny, Nx = 2 * nx;
   // bins: samples of each pair sorted by the bin of their fine position (mod N)
-  std::vector<int32_t> bperm((size_t)std::max<int64_t>(nsamples, 1));
-  std::vector<int32_t> boff((size_t)npairs * (nb + 1));
-  std::vector<int32_t> key;
-  for (int64_t p = 0; p < npairs; ++p) {
-    const int64_t b = samp_off[p], e = samp_off[p + 1];
-    key.assign((size_t)(e - b), 0);
-    for (int64_t i = b; i < e; ++i) {
-      double uy = (double)coords[2 * i] * Ny, ux = (double)coords[2 * i + 1] * Nx;
-      uy -= std::floor(uy / Ny) * Ny;
-      ux -= std::floor(ux / Nx) * Nx;
-      const int by = std::min(nby - 1, std::max(0, (int)(uy / kBin)));
-      const int bx = std::min(nbx - 1, std::max(0, (int)(ux / kBin)));
-      key[(size_t)(i - b)] = by * nbx + bx;
-    }
-    std::vector<int32_t> ord((size_t)(e - b));
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t c) { return key[(size_t)a] < key[(size_t)c]; });
-    int32_t *bo = boff.data() + (size_t)p * (nb + 1);
-    std::fill(bo, bo + nb + 1, 0);
-    for (int64_t r = 0; r < e - b; ++r) {
-      bperm[(size_t)(b + r)] = (int32_t)(b + ord[(size_t)r]);
-      ++bo[key[(size_t)ord[(size_t)r]] + 1];
-    }
-    for (int q = 0; q < nb; ++q) bo[q + 1] += bo[q];
-  }
+  std::vector<int32_t> bperm, boff;
+  nufft_host::bin_samples(samp_off, npairs, coords, Ny, Nx, kNufftBin, bperm, boff);
   std::vector<float> dy((size_t)ny), dx((size_t)nx);
-  for (int a = 0; a < ny; ++a) dy[(size_t)a] = (float)(std::sqrt(2.0) / phihat((double)(a - ny / 2) / Ny, W, 2.30 * W));
-  for (int a = 0; a < nx; ++a) dx[(size_t)a] = (float)(std::sqrt(2.0) / phihat((double)(a - nx / 2) / Nx, W, 2.30 * W));
+  for (int a = 0; a < ny; ++a)
+    dy[(size_t)a] = (float)(std::sqrt(2.0) / nufft_host::phihat((double)(a - ny / 2) / Ny, W, 2.30 * W));
+  for (int a = 0; a < nx; ++a)
+    dx[(size_t)a] = (float)(std::sqrt(2.0) / nufft_host::phihat((double)(a - nx / 2) / Nx, W, 2.30 * W));
   TRY(grow(P->off, (size_t)(npairs + 1) * 8));
   TRY(grow(P->coords, (size_t)std::max<int64_t>(nsamples, 1) * 8));
   TRY(grow(P->bperm, bperm.size() * 4));
