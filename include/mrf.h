@@ -9,10 +9,14 @@
  *
  *     X^{k+1} = P_cone(D)( X^k - mu_k A^H W (A X^k - Y) )          (eq. blip, eq. blip_dcf)
  *
- * with A = P_Omega F (per-frame unitary 2-D DFT and k-space subsampling,
- * eq. forward with one coil) and P_cone(D) the per-voxel matched filter
- * (eq. exactP / exactPs): nearest normalised atom, then the proton density
- * gamma_v = max(Re<Z_v, D_j*>/||D_j*||^2, 0).
+ * with A = P_Omega F S (eq. forward: per-frame unitary 2-D DFT on a Cartesian
+ * grid or a non-uniform Fourier transform for spiral readouts, k-space
+ * subsampling, optional coil sensitivities S) and P_cone(D) the per-voxel
+ * matched filter (eq. exactP / exactPs): nearest normalised atom, then the
+ * proton density gamma_v = max(Re<Z_v, D_j*>/||D_j*||^2, 0) — exhaustive,
+ * by a learned proposal with an exact local search, or by the cover tree;
+ * optionally in the temporal subspace of the dictionary (eq. CS1) and with
+ * a complex proton density by phase alignment.
  *
  * Conventions (apply to every entry point):
  *  - Every call returns mrf_status; MRF_OK is 0 and errors are negative.  No
