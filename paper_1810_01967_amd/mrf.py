@@ -486,6 +486,22 @@ class Net:
         _check(lib().mrf_net_get_standardisation(self.handle, m.ctypes.data, s.ctypes.data, lm.ctypes.data))
         return m, s, lm
 
+    def save(self, path):
+        """Weights and output standardisation to a .npz file (no pickles)."""
+        m, sd, lm = self.get_standardisation()
+        np.savez(path, dims=np.array([self.in_dim, self.hidden, self.nout], dtype=np.int64),
+                 params=self.get_params(), mean=m, std=sd, log_mask=lm)
+
+    @classmethod
+    def load(cls, path):
+        """A network saved by save()."""
+        with np.load(path, allow_pickle=False) as f:
+            I, H, P = (int(x) for x in f["dims"])
+            net = cls(I, P, hidden=H)
+            net.set_params(f["params"])
+            net.set_standardisation(f["mean"], f["std"], f["log_mask"])
+        return net
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().mrf_net_destroy(self.handle)

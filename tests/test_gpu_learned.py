@@ -277,3 +277,19 @@ def test_trained_network_gain(m, small_dict):
           f"centre proposal: fallbacks {base['stats'].fallbacks}")
     assert mism <= 0.005
     assert st.fallbacks < 0.1 * base["stats"].fallbacks
+
+
+def test_net_save_load_round_trip(m, tmp_path):
+    """A saved network loads with the same weights, standardisation and
+    (bit-identical) outputs."""
+    import torch
+    net = m.Net(64, 3, hidden=256, seed=17)
+    net.set_standardisation([1.0, 2.0, -3.0], [0.5, 1.5, 2.0], [1, 1, 0])
+    path = tmp_path / "net.npz"
+    net.save(path)
+    net2 = m.Net.load(path)
+    np.testing.assert_array_equal(net2.get_params(), net.get_params())
+    for a, b in zip(net2.get_standardisation(), net.get_standardisation()):
+        np.testing.assert_array_equal(a, b)
+    x = torch.from_numpy(rng.normal(17, "x", 300 * 64).reshape(300, 64).astype(np.float32)).cuda()
+    np.testing.assert_array_equal(host(m.mrf_net_forward(net2, x)), host(m.mrf_net_forward(net, x)))
