@@ -199,6 +199,7 @@ def main():
                 f"{lst[4]:.0f} re-centred, {lst[7] / n:.1f} box atoms per voxel), mismatch {mism:.5f}")
 
     tree = None
+    DT = None
     if args.tree:
         t3 = time.time()
         DT = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims, cover_tree=True)
@@ -219,7 +220,6 @@ def main():
             tree["sweep"].append(row)
             log(f"cover tree eps={eps}: {tms:.3f} ms/step, recall@1 {row['recall_at_1_vs_exhaustive_fp32']:.4f}, "
                 f"{evals:.0f} distances per voxel, {row['fallbacks']} fallbacks")
-        del DT
 
     subspace = None
     if args.subspace:
@@ -260,7 +260,7 @@ def main():
 
     iteration = None
     if args.iteration:
-        iteration = iteration_bench(m, torch, D, Dd, net if args.learned else None, args)
+        iteration = iteration_bench(m, torch, D, Dd, net if args.learned else None, args, DT)
 
     ok = [lp for lp in args.learned_precisions.split(",")
           if learned is not None and learned[lp]["index_mismatch_vs_exhaustive_fp32"] <= 1e-3]
@@ -335,7 +335,7 @@ def main():
     return 0
 
 
-def iteration_bench(m, torch, D, Dd, net, args):
+def iteration_bench(m, torch, D, Dd, net, args, DT=None):
     """Projected-gradient steps (eq. blip / eq. blip_dcf) on the headline
     dictionary (100,800 atoms, L = 500) with the exhaustive split-BF16
     projection (and the learned one on the Cartesian case): ms per step, and
@@ -367,6 +367,9 @@ def iteration_bench(m, torch, D, Dd, net, args):
     if net is not None:
         cases.insert(1, ("cartesian_256_1coil_learned", D, A1, Ycart, 256, Dd.L,
                          {"net": net, "recentre": args.recentre}))
+        if DT is not None:  # the same dictionary with its cover tree: tree fallback (eps = 0, exact)
+            cases.insert(2, ("cartesian_256_1coil_learned_tree_fallback", DT, A1, Ycart, 256, Dd.L,
+                             {"net": net, "recentre": args.recentre, "eps": 0.0}))
     for name, DD, A, Y, size, F, kw in cases:
         Yd = torch.from_numpy(np.ascontiguousarray(Y.astype(np.complex64))).cuda()
         X = torch.zeros((1, F, size, size), dtype=torch.complex64, device="cuda")
@@ -391,10 +394,19 @@ def iteration_bench(m, torch, D, Dd, net, args):
         ev1.record()
         torch.cuda.synchronize()
         op_ms = ev0.elapsed_time(ev1) / steps
+        extra = {}
+        if "net" in kw:  # how many voxels of an iterate the fallback search takes
+            _, _, _, _, h = m.mrf_ipg_solve(DD, A, Yd, X0=X1, mu0=1.0, adaptive=False, max_iter=steps, rel_tol=0.0,
+                                            precision="bf16x3", **kw)
+            extra = {"fallbacks_per_step": h["fallbacks"] / steps,
+                     "fallback_fraction": h["fallbacks"] / steps / (size * size)}
         out[name] = {"ms_per_step": step_ms, "operator_ms_full_frames": op_ms, "voxels": size * size,
                      "frames": F, "samples_per_coil": int(A.M), "coils": max(A.ncoils, 1),
-                     "projection": "learned + split-BF16 local search" if "net" in kw else "exhaustive split BF16"}
-        log(f"iteration {name}: {step_ms:.2f} ms per step, operator (A, A^H on {Dd.L} frames) {op_ms:.2f} ms")
+                     "projection": ("exhaustive split BF16" if "net" not in kw else
+                                    "learned + split-BF16 local search + " +
+                                    ("cover-tree fallback" if "eps" in kw else "exhaustive fallback")), **extra}
+        log(f"iteration {name}: {step_ms:.2f} ms per step, operator (A, A^H on {Dd.L} frames) {op_ms:.2f} ms"
+            + (f", fallback fraction {extra['fallback_fraction']:.3f}" if extra else ""))
     return out
 
 

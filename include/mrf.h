@@ -197,7 +197,9 @@ mrf_status mrf_dict_tree_export(mrf_dict D, int32_t *rep, int32_t *ins_level, in
 /* ------------------------------------------------------------------------ */
 enum {
   MRF_EXHAUSTIVE = 0, /* every atom scored (eq. exactP) */
-  MRF_LEARNED = 1,    /* network proposal + exact local search + exhaustive fallback */
+  MRF_LEARNED = 1,    /* network proposal + exact local search + fallback: the cover tree
+                         (eps >= 0, warm-started at the local best) when the dictionary
+                         holds one, else (or with eps < 0) the exhaustive filter */
   MRF_COVERTREE = 2   /* cover-tree (1+eps)-ANNS (Algorithm 1) on Z_v/||Z_v||, warm-started */
 };
 enum {
@@ -224,13 +226,16 @@ typedef struct {
   int32_t atom_splits; /* 0 = automatic; else number of atom ranges scored in parallel */
   mrf_net net;         /* MRF_LEARNED: trained network (input length = the dictionary's K) */
   int32_t box_radius;  /* MRF_LEARNED: half-width of the local box per parameter (0 = 3) */
-  float fallback_corr; /* MRF_LEARNED: exhaustive fallback below this normalised
+  float fallback_corr; /* MRF_LEARNED: fallback search below this normalised
                           correlation (0 = 0.98; negative disables the fallback) */
   int32_t recentre;    /* MRF_LEARNED: re-centre rounds when the best atom lies on an
                           interior face of the box (0 = none) */
-  float eps;           /* MRF_COVERTREE: search inaccuracy eps >= 0 (Definition 3.1) */
-  int32_t tree_capacity; /* MRF_COVERTREE: candidate-set capacity per query (0 = 1024);
-                            queries that outgrow it use the exhaustive filter */
+  float eps;           /* MRF_COVERTREE: search inaccuracy eps >= 0 (Definition 3.1;
+                          0 = exact).  MRF_LEARNED with a dictionary holding a tree:
+                          eps >= 0 sends the fallback voxels to the cover tree with this
+                          eps, eps < 0 to the exhaustive filter; NaN and +inf are errors */
+  int32_t tree_capacity; /* MRF_COVERTREE and the tree fallback: candidate-set capacity per
+                            query (0 = 1024); queries that outgrow it use the exhaustive filter */
   float *pd_phase;       /* DEVICE float [n] or NULL, mrf_match only: the phase (radians) of
                             the complex PD rho_v on the normalised atom Dhat_j* with a
                             phase-aligned dictionary (mrf_dict_align), 0 otherwise; the
@@ -245,13 +250,14 @@ typedef struct {
   float score_ms;        /* device time of the candidate-scoring kernel alone
                             (MRF_LEARNED: the first local-search scoring kernel) */
   int32_t splits;        /* atom ranges the scoring kernel used */
-  int64_t fallbacks;     /* MRF_LEARNED: voxels sent to the exhaustive filter */
+  int64_t fallbacks;     /* MRF_LEARNED: voxels sent to the fallback search */
   int64_t recentred;     /* MRF_LEARNED: box re-centrings performed */
   int64_t local_atoms;   /* MRF_LEARNED: atom rows scored by the local search (incl. padding) */
   float proposal_ms;     /* MRF_LEARNED: device time of the network and cell mapping */
-  float fallback_ms;     /* MRF_LEARNED: device time of the exhaustive fallback */
+  float fallback_ms;     /* MRF_LEARNED: device time of the fallback search */
   float search_ms;       /* MRF_LEARNED / MRF_COVERTREE: device time of the search stage */
-  int64_t distance_evals;/* MRF_COVERTREE: distances computed (self-children excluded) */
+  int64_t distance_evals;/* MRF_COVERTREE, and MRF_LEARNED with the tree fallback: distances
+                            computed by the tree search (self-children excluded) */
   int32_t tree_levels;   /* MRF_COVERTREE: level launches */
   int64_t first_box_atoms; /* MRF_LEARNED: sum over the voxels of the first local-search
                               launch of their clipped box sizes (2 K flops each) */
@@ -466,7 +472,7 @@ typedef struct {
   int32_t *shrinks;       /* HOST [cap] or NULL: shrinks per iteration */
   double f0;              /* objective of the initial X */
   float ms;               /* device time of the whole solve */
-  int64_t fallbacks;      /* MRF_LEARNED: voxels sent to the exhaustive filter, summed
+  int64_t fallbacks;      /* MRF_LEARNED: voxels sent to the fallback search, summed
                              over every projection of the solve (step-size trials included) */
 } mrf_solve_stats;
 

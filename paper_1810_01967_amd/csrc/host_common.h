@@ -94,6 +94,13 @@ mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
                       int32_t *idx, float *pd, float *corr, float *params_out, mrf_match_stats *st,
                       hipStream_t s);
 mrf_status upload_tree(mrf_dict_s *D, const double *Xnorm);
+// Algorithm 1 for n query rows Q (pitch Kp, norms qnorm, warm-start atoms or
+// NULL) into out_s / out_j (scores as the merge expects); queries whose
+// candidate set overflows the capacity go to the exhaustive FP32 filter
+// (work buffers ovf, rows, ps, pj; their count into *n_overflow).
+mrf_status tree_search(mrf_dict_s *D, const float *Q, const float *qnorm, const int32_t *warm, int64_t n,
+                       float eps, int cap, float *out_s, int32_t *out_j, DevBuf &ovf, DevBuf &rows, DevBuf &ps,
+                       DevBuf &pj, int64_t *n_overflow, hipStream_t s);
 mrf_status ensure_x3(mrf_dict_s *D, hipStream_t s);
 int auto_splits_x3(const mrf_dict_s *D, int64_t n);
 bool net_bf16_ok(const mrf_net_s *net, int64_t K, int64_t ldx);
@@ -139,6 +146,7 @@ struct mrf_dict_s {
   int64_t tree_entries = 0;
   mrf::DevBuf t_node, t_rep, t_uniq, t_cb, t_ce, t_md, t_self;
   mrf::DevBuf ts_active, ts_qc, ts_cnt, ts_flags, ts_dmin, ts_Qe0, ts_Qe1, ts_Qd0, ts_Qd1, ts_evals;
+  mrf::DevBuf fb_rows, fb_norm, fb_warm, fb_s, fb_j;  // learned-path fallback through the cover tree
   double *host_scal = nullptr;  // pinned readback of reduced scalars
   ~mrf_dict_s() {
     if (host_scal) (void)hipHostFree(host_scal);

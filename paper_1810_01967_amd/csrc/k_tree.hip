@@ -262,6 +262,26 @@ __global__ void k_tree_select(const TreeState st, int64_t n, int32_t *__restrict
   if (v < n && st.flags[v]) out[atomicAdd(count, 1u)] = (int32_t)v;
 }
 
+// Queries of a subset (the learned path's fallback list): norms and warm
+// atoms (the local search's best, clamped to the dictionary) gathered.
+__global__ void k_gather_queries(const int32_t *__restrict__ list, int64_t cnt, const float *__restrict__ znorm,
+                                 const int32_t *__restrict__ best_j, int d, float *__restrict__ qnorm,
+                                 int32_t *__restrict__ qwarm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int v = list[i];
+  qnorm[i] = znorm[v];
+  const int j = best_j[v];
+  qwarm[i] = (j >= 0 && j < d) ? j : 0;
+}
+
+void launch_gather_queries(const int32_t *list, int64_t cnt, const float *znorm, const int32_t *best_j, int d,
+                           float *qnorm, int32_t *qwarm, hipStream_t s) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_gather_queries, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, znorm,
+                     best_j, d, qnorm, qwarm);
+}
+
 void launch_tree_init(const TreeDev &t, const float *Zp, int Kp, const float *znorm, const int32_t *warm,
                       int64_t n, const TreeState &st, hipStream_t s) {
   hipLaunchKernelGGL(k_tree_init, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, t, Zp, Kp, znorm, warm, n, st);

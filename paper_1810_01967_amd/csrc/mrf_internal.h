@@ -308,4 +308,7 @@ void launch_tree_level(const TreeDev &t, const float *Zp, int Kp, const float *z
 void launch_tree_finish(const TreeDev &t, const float *Zp, int Kp, int K, const float *znorm, int64_t n,
                         const TreeState &st, float *best_s, int32_t *best_j, hipStream_t s);
 void launch_tree_select(const TreeState &st, int64_t n, int32_t *out, unsigned int *count, hipStream_t s);
+// qnorm[i] = znorm[list[i]], qwarm[i] = best_j[list[i]] (0 if outside [0, d)).
+void launch_gather_queries(const int32_t *list, int64_t cnt, const float *znorm, const int32_t *best_j, int d,
+                           float *qnorm, int32_t *qwarm, hipStream_t s);
 }  // namespace mrf

@@ -469,6 +469,9 @@ mrf_status check_learned(const mrf_dict_s *D, const mrf_match_opts *o, bool need
   if (o->box_radius < 0 || o->box_radius > 64) return fail(MRF_E_INVAL, "box_radius %d not in 0..64", o->box_radius);
   if (o->recentre < 0 || o->recentre > 16) return fail(MRF_E_INVAL, "recentre %d not in 0..16", o->recentre);
   if (!std::isfinite(o->fallback_corr)) return fail(MRF_E_INVAL, "non-finite fallback_corr");
+  if (D->has_tree && (std::isnan(o->eps) || (std::isinf(o->eps) && o->eps > 0.f)))
+    return fail(MRF_E_INVAL, "eps of the cover-tree fallback must be finite (negative: exhaustive fallback)");
+  if (D->has_tree && o->tree_capacity < 0) return fail(MRF_E_INVAL, "tree_capacity < 0");
   if (need_net) {
     if (!o->net) return fail(MRF_E_INVAL, "MRF_LEARNED needs a network");
     if (o->net->I != D->K || o->net->P != D->nparam)
@@ -615,6 +618,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   if (st) HIP_TRY(hipEventRecord(ev.b, s));
   // exhaustive fallback below the correlation threshold
   int64_t nfb = 0;
+  bool tree_ran = false;
   if (fallback_out) launch_zero(fallback_out, n * 4, s);
   if (st) HIP_TRY(hipEventRecord(ev.c, s));
   if (thr >= 0.f) {
@@ -627,7 +631,31 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     HIP_TRY(hipStreamSynchronize(s));
     nfb = hc;
     D->fallback_total += nfb;
-    if (nfb > 0) {
+    if (nfb > 0 && D->has_tree && o->eps >= 0.f) {
+      // the cover tree (Algorithm 1, inaccuracy eps; eps = 0 is exact)
+      // warm-started at each voxel's local best, on the FP32 rows
+      const int64_t cnt_pad = round_up(nfb, kRowPad);
+      TRY(grow(D->fb_rows, (size_t)cnt_pad * D->Kp * 4));
+      TRY(grow(D->fb_norm, (size_t)nfb * 4));
+      TRY(grow(D->fb_warm, (size_t)nfb * 4));
+      TRY(grow(D->fb_s, (size_t)nfb * 4));
+      TRY(grow(D->fb_j, (size_t)nfb * 4));
+      launch_gather_rows(D->zp.as<float>(), D->Kp, la, nfb, cnt_pad, D->fb_rows.as<float>(), s);
+      launch_gather_queries(la, nfb, D->znorm.as<float>(), D->best_j.as<int32_t>(), D->d, D->fb_norm.as<float>(),
+                            D->fb_warm.as<int32_t>(), s);
+      LAUNCH_CHECK("fallback queries");
+      const int cap = o->tree_capacity > 0 ? o->tree_capacity : 1024;
+      TRY(grow(D->ts_evals, 64));
+      launch_zero(D->ts_evals.p, 8, s);
+      tree_ran = true;
+      TRY(tree_search(D, D->fb_rows.as<float>(), D->fb_norm.as<float>(), D->fb_warm.as<int32_t>(), nfb, o->eps, cap,
+                      D->fb_s.as<float>(), D->fb_j.as<int32_t>(), D->list_c, D->rows, D->part_s, D->part_j, nullptr,
+                      s));
+      launch_scatter_best(la, nfb, D->fb_s.as<float>(), D->fb_j.as<int>(), 1, D->best_s.as<float>(),
+                          D->best_j.as<int32_t>(), s);
+      if (fallback_out) launch_mark(la, nfb, fallback_out, s);
+      LAUNCH_CHECK("fallback (cover tree)");
+    } else if (nfb > 0) {
       const int64_t cnt_pad = round_up(nfb, kRowPad);
       TRY(grow(D->rows, (size_t)cnt_pad * std::max(D->Kp, D->Kx) * 4));
       int splits = 0;
@@ -664,13 +692,15 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
                       D->gamma.as<float>(), s);
   LAUNCH_CHECK("merge");
   if (st) {
-    unsigned long long wk[2] = {0, 0};
+    unsigned long long wk[2] = {0, 0}, ev_count = 0;
     HIP_TRY(hipMemcpyAsync(wk, work, 16, hipMemcpyDeviceToHost, s));
+    if (tree_ran) HIP_TRY(hipMemcpyAsync(&ev_count, D->ts_evals.p, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     st->fallbacks = nfb;
     st->recentred = recentred;
     st->local_atoms = (int64_t)wk[0];
     st->first_box_atoms = (int64_t)wk[1];
+    st->distance_evals = (int64_t)ev_count;
     HIP_TRY(hipEventElapsedTime(&st->search_ms, ev.a, ev.b));
     HIP_TRY(hipEventElapsedTime(&st->score_ms, e_ls0, e_ls1));
     HIP_TRY(hipEventElapsedTime(&st->fallback_ms, ev.c, ev.d));

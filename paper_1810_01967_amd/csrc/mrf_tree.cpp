@@ -42,13 +42,9 @@ mrf_status upload_tree(mrf_dict_s *D, const double *Xnorm) {
   return MRF_OK;
 }
 
-mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
-                      int32_t *idx, float *pd, float *corr, float *params_out, mrf_match_stats *st,
-                      hipStream_t s) {
-  const int cap = o->tree_capacity > 0 ? o->tree_capacity : 1024;
-  TRY(grow(D->gamma, (size_t)n * 4));
-  TRY(grow(D->best_s, (size_t)n * 4));
-  TRY(grow(D->best_j, (size_t)n * 4));
+mrf_status tree_search(mrf_dict_s *D, const float *Q, const float *qnorm, const int32_t *warm, int64_t n,
+                       float eps, int cap, float *out_s, int32_t *out_j, DevBuf &ovf, DevBuf &rows, DevBuf &ps,
+                       DevBuf &pj, int64_t *n_overflow, hipStream_t s) {
   TRY(grow(D->ts_active, (size_t)n * 4));
   TRY(grow(D->ts_qc, (size_t)n * 4));
   TRY(grow(D->ts_cnt, (size_t)n * 4));
@@ -59,7 +55,7 @@ mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
   TRY(grow(D->ts_Qd0, (size_t)n * cap * 4));
   TRY(grow(D->ts_Qd1, (size_t)n * cap * 4));
   TRY(grow(D->ts_evals, 64));
-  TRY(grow(D->list_a, (size_t)n * 4));
+  TRY(grow(ovf, (size_t)n * 4));
   TRY(grow(D->cnt, 64));
   TreeDev t;
   t.dhat = D->dhat.as<float>();
@@ -83,51 +79,63 @@ mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
   ts.Qd = D->ts_Qd0.as<float>();
   ts.cap = cap;
   ts.evals = D->ts_evals.as<unsigned long long>();
-  EventPair ev;
-  if (st) {
-    HIP_TRY(hipEventCreate(&ev.a));
-    HIP_TRY(hipEventCreate(&ev.b));
-    HIP_TRY(hipEventRecord(ev.a, s));
-  }
-  launch_zero(ts.evals, 8, s);
-  launch_tree_init(t, D->zp.as<float>(), D->Kp, D->znorm.as<float>(), warm, n, ts, s);
+  launch_tree_init(t, Q, D->Kp, qnorm, warm, n, ts, s);
   LAUNCH_CHECK("tree init");
-  const float inv_eps = o->eps > 0.f ? 1.f / o->eps : INFINITY;
+  const float inv_eps = eps > 0.f ? 1.f / eps : INFINITY;
   int32_t *qe_next = D->ts_Qe1.as<int32_t>();
   float *qd_next = D->ts_Qd1.as<float>();
   for (int level = 0; level < t.imax; ++level) {
-    launch_tree_level(t, D->zp.as<float>(), D->Kp, D->znorm.as<float>(), n, level, inv_eps, ts, qe_next,
-                      qd_next, s);
+    launch_tree_level(t, Q, D->Kp, qnorm, n, level, inv_eps, ts, qe_next, qd_next, s);
     LAUNCH_CHECK("tree level");
     std::swap(ts.Qe, qe_next);
     std::swap(ts.Qd, qd_next);
   }
-  launch_tree_finish(t, D->zp.as<float>(), D->Kp, D->K, D->znorm.as<float>(), n, ts, D->best_s.as<float>(),
-                     D->best_j.as<int32_t>(), s);
+  launch_tree_finish(t, Q, D->Kp, D->K, qnorm, n, ts, out_s, out_j, s);
   LAUNCH_CHECK("tree finish");
   // queries whose candidate set overflowed: exhaustive filter
   unsigned int *count = D->cnt.as<unsigned int>();
   launch_zero(count, 4, s);
-  launch_tree_select(ts, n, D->list_a.as<int32_t>(), count, s);
+  launch_tree_select(ts, n, ovf.as<int32_t>(), count, s);
   unsigned int hc = 0;
   HIP_TRY(hipMemcpyAsync(&hc, count, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const int64_t nfb = hc;
   if (nfb > 0) {
     const int64_t cnt_pad = round_up(nfb, kRowPad);
-    TRY(grow(D->rows, (size_t)cnt_pad * D->Kp * 4));
-    launch_gather_rows(D->zp.as<float>(), D->Kp, D->list_a.as<int32_t>(), nfb, cnt_pad, D->rows.as<float>(), s);
+    TRY(grow(rows, (size_t)cnt_pad * D->Kp * 4));
+    launch_gather_rows(Q, D->Kp, ovf.as<int32_t>(), nfb, cnt_pad, rows.as<float>(), s);
     const int64_t nvt = (nfb + 127) / 128, nvt8 = (nvt + 7) / 8 * 8;
     int64_t sp = (1024 + nvt8 - 1) / nvt8;
     sp = std::max<int64_t>(1, std::min<int64_t>(sp, std::min<int64_t>(64, D->d_pad / 128)));
-    TRY(grow(D->part_s, (size_t)sp * nfb * 4));
-    TRY(grow(D->part_j, (size_t)sp * nfb * 4));
-    launch_score_f32(D->dhat.as<float>(), D->rows.as<float>(), D->d, D->d_pad, nfb, cnt_pad, D->Kp, (int)sp,
-                     D->part_s.as<float>(), D->part_j.as<int>(), s);
-    launch_scatter_best(D->list_a.as<int32_t>(), nfb, D->part_s.as<float>(), D->part_j.as<int>(), (int)sp,
-                        D->best_s.as<float>(), D->best_j.as<int32_t>(), s);
+    TRY(grow(ps, (size_t)sp * nfb * 4));
+    TRY(grow(pj, (size_t)sp * nfb * 4));
+    launch_score_f32(D->dhat.as<float>(), rows.as<float>(), D->d, D->d_pad, nfb, cnt_pad, D->Kp, (int)sp,
+                     ps.as<float>(), pj.as<int>(), s);
+    launch_scatter_best(ovf.as<int32_t>(), nfb, ps.as<float>(), pj.as<int>(), (int)sp, out_s, out_j, s);
     LAUNCH_CHECK("tree fallback");
   }
+  if (n_overflow) *n_overflow = nfb;
+  return MRF_OK;
+}
+
+mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
+                      int32_t *idx, float *pd, float *corr, float *params_out, mrf_match_stats *st,
+                      hipStream_t s) {
+  const int cap = o->tree_capacity > 0 ? o->tree_capacity : 1024;
+  TRY(grow(D->gamma, (size_t)n * 4));
+  TRY(grow(D->best_s, (size_t)n * 4));
+  TRY(grow(D->best_j, (size_t)n * 4));
+  TRY(grow(D->ts_evals, 64));
+  EventPair ev;
+  if (st) {
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    HIP_TRY(hipEventRecord(ev.a, s));
+  }
+  launch_zero(D->ts_evals.p, 8, s);
+  int64_t nfb = 0;
+  TRY(tree_search(D, D->zp.as<float>(), D->znorm.as<float>(), warm, n, o->eps, cap, D->best_s.as<float>(),
+                  D->best_j.as<int32_t>(), D->list_a, D->rows, D->part_s, D->part_j, &nfb, s));
   launch_merge_argmax(D->best_s.as<float>(), D->best_j.as<int>(), 1, n, D->d, D->znorm.as<float>(), warm,
                       D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr, params_out,
                       D->gamma.as<float>(), s);
@@ -135,12 +143,12 @@ mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
   if (st) {
     HIP_TRY(hipEventRecord(ev.b, s));
     unsigned long long ev_count = 0;
-    HIP_TRY(hipMemcpyAsync(&ev_count, ts.evals, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&ev_count, D->ts_evals.p, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipEventElapsedTime(&st->search_ms, ev.a, ev.b));
     st->distance_evals = (int64_t)ev_count;
     st->fallbacks = nfb;
-    st->tree_levels = t.imax;
+    st->tree_levels = D->tree.imax;
   }
   return MRF_OK;
 }

@@ -347,13 +347,18 @@ def mrf_dict_copy_atoms(D: Dictionary, precision="fp32", stream=None):
 
 def match_opts(precision="fp32", topk=8, atom_splits=0, net=None, box_radius=3, fallback_corr=0.98,
                recentre=0, eps=None, tree_capacity=0) -> MatchOpts:
-    if eps is not None:
-        method = MRF_COVERTREE
+    # a network selects the learned path (a given eps then sends its fallback
+    # voxels to the dictionary's cover tree, None keeps the exhaustive
+    # fallback); eps alone selects the cover tree
+    if net is not None:
+        method = MRF_LEARNED
+        e = -1.0 if eps is None else float(eps)
     else:
-        method = MRF_LEARNED if net is not None else MRF_EXHAUSTIVE
+        method = MRF_COVERTREE if eps is not None else MRF_EXHAUSTIVE
+        e = float(eps or 0.0)
     return MatchOpts(method, PRECISION[precision], int(topk), int(atom_splits),
                      None if net is None else net.handle, int(box_radius), float(fallback_corr),
-                     int(recentre), float(eps or 0.0), int(tree_capacity), None)
+                     int(recentre), e, int(tree_capacity), None)
 
 
 # --------------------------------------------------------------------------- matched filter

@@ -293,3 +293,51 @@ def test_net_save_load_round_trip(m, tmp_path):
         np.testing.assert_array_equal(a, b)
     x = torch.from_numpy(rng.normal(17, "x", 300 * 64).reshape(300, 64).astype(np.float32)).cuda()
     np.testing.assert_array_equal(host(m.mrf_net_forward(net2, x)), host(m.mrf_net_forward(net, x)))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_learned_with_cover_tree_fallback(m, precision):
+    """With a cover tree in the dictionary the learned path re-searches its
+    low-correlation voxels with Algorithm 1 (eps = 0: exact), warm-started at
+    the local best: indices against the FP64 oracle outside near-ties, and the
+    same answers as the learned path with the exhaustive fallback."""
+    banner(f"learned path, cover-tree fallback, {precision}")
+    Dd = workloads.bssfp_dictionary(L=100, n_t1=20, n_t2=20, n_df=9, seed=2)
+    Dt = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims, cover_tree=True)
+    De = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    net = m.Net(2 * Dd.L, 3, hidden=128, seed=5)
+    m.mrf_net_train(net, De, samples=200_000, batch=2048, epochs=2, lr=1e-3, lr_min=1e-5, snr_lo=20.0, snr_hi=40.0,
+                    seed=6)
+    # low-SNR voxels: many fall below the correlation threshold
+    Z, jt, pd, snr = workloads.random_voxels(Dd, 3000, seed=9, snr_db_range=(0.0, 20.0))
+    Zd = dev(c64(Z))
+    ot = m.mrf_match(Dt, Zd, net=net, precision=precision, recentre=1, eps=0.0, stats=True)
+    oe = m.mrf_match(De, Zd, net=net, precision=precision, recentre=1, stats=True)
+    it, ie = host(ot["idx"]).astype(np.int64), host(oe["idx"]).astype(np.int64)
+    print(f"fallbacks {ot['stats'].fallbacks} (tree) / {oe['stats'].fallbacks} (exhaustive); "
+          f"index differences {int(np.sum(it != ie))}")
+    assert ot["stats"].fallbacks > 100
+    assert ot["stats"].fallbacks == oe["stats"].fallbacks
+    assert ot["stats"].distance_evals > 0 and oe["stats"].distance_evals == 0
+    # no eps: a dictionary holding a tree keeps the exhaustive fallback
+    on = m.mrf_match(Dt, Zd, net=net, precision=precision, recentre=1, stats=True)
+    assert on["stats"].distance_evals == 0
+    np.testing.assert_array_equal(host(on["idx"]), host(oe["idx"]))
+    Zc = Z.astype(np.complex128)
+    diff = it != ie
+    if diff.any():                      # both fallbacks exact: they may differ only on near-ties
+        assert np.all(mf.index_ok(Zc[diff], Dd.atoms, it[diff], tol=1e-5))
+        assert np.all(mf.index_ok(Zc[diff], Dd.atoms, ie[diff], tol=1e-5))
+    np.testing.assert_allclose(host(ot["pd"])[~diff], host(oe["pd"])[~diff], rtol=1e-5, atol=1e-7)
+    # a threshold above 1 sends every voxel to the tree: the result is then the
+    # exact matched filter (the voxels kept by the local search above carry the
+    # learned path's own approximation and are not held to this)
+    oa = m.mrf_match(Dt, Zd, net=net, precision=precision, recentre=1, fallback_corr=2.0, eps=0.0, stats=True)
+    ia = host(oa["idx"]).astype(np.int64)
+    print(f"all-fallback: {oa['stats'].fallbacks} fallbacks")
+    assert oa["stats"].fallbacks == len(ia)
+    assert np.all(mf.index_ok(Zc, Dd.atoms, ia, tol=1e-5))
+    g = mf.exact_mf(Zc, Dd.atoms)
+    same = ia == g["idx"]
+    assert same.mean() > 0.99
+    np.testing.assert_allclose(host(oa["pd"])[same], g["gamma"][same], rtol=1e-4, atol=1e-6)
