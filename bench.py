@@ -370,16 +370,19 @@ def iteration_bench(m, torch, D, Dd, net, args, DT=None):
         if DT is not None:  # the same dictionary with its cover tree: tree fallback (eps = 0, exact)
             cases.insert(2, ("cartesian_256_1coil_learned_tree_fallback", DT, A1, Ycart, 256, Dd.L,
                              {"net": net, "recentre": args.recentre, "eps": 0.0}))
+    if DT is not None:  # CoverBLIP: the cover tree as the projection (Algorithm 1 inside Algorithm 2)
+        for eps in (0.0, 0.4):
+            cases.append((f"cartesian_256_1coil_covertree_eps{eps:g}", DT, A1, Ycart, 256, Dd.L, {"eps": eps}))
     for name, DD, A, Y, size, F, kw in cases:
         Yd = torch.from_numpy(np.ascontiguousarray(Y.astype(np.complex64))).cuda()
         X = torch.zeros((1, F, size, size), dtype=torch.complex64, device="cuda")
-        X1, _, _, _ = m.mrf_ipg_step(DD, A, Yd, X, 1.0, precision="bf16x3", stats=False, **kw)
+        X1, I1, _, _ = m.mrf_ipg_step(DD, A, Yd, X, 1.0, precision="bf16x3", stats=False, **kw)
         torch.cuda.synchronize()
         steps = 3
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
-        for _ in range(steps):
-            X2, _, _, st = m.mrf_ipg_step(DD, A, Yd, X1, 1.0, precision="bf16x3", stats=False, **kw)
+        for _ in range(steps):  # warm-started at the previous iterate's atoms, as inside a solve
+            X2, _, _, st = m.mrf_ipg_step(DD, A, Yd, X1, 1.0, idx_in=I1, precision="bf16x3", stats=False, **kw)
         ev1.record()
         torch.cuda.synchronize()
         step_ms = ev0.elapsed_time(ev1) / steps
@@ -395,18 +398,22 @@ def iteration_bench(m, torch, D, Dd, net, args, DT=None):
         torch.cuda.synchronize()
         op_ms = ev0.elapsed_time(ev1) / steps
         extra = {}
-        if "net" in kw:  # how many voxels of an iterate the fallback search takes
+        if "net" in kw or "eps" in kw:  # fallback share and tree distance counts along a solve
             _, _, _, _, h = m.mrf_ipg_solve(DD, A, Yd, X0=X1, mu0=1.0, adaptive=False, max_iter=steps, rel_tol=0.0,
                                             precision="bf16x3", **kw)
-            extra = {"fallbacks_per_step": h["fallbacks"] / steps,
-                     "fallback_fraction": h["fallbacks"] / steps / (size * size)}
+            if "net" in kw:
+                extra = {"fallbacks_per_step": h["fallbacks"] / steps,
+                         "fallback_fraction": h["fallbacks"] / steps / (size * size)}
+            if h["distance_evals"]:
+                extra["distance_evals_per_voxel_per_iteration"] = h["distance_evals"] / steps / (size * size)
         out[name] = {"ms_per_step": step_ms, "operator_ms_full_frames": op_ms, "voxels": size * size,
                      "frames": F, "samples_per_coil": int(A.M), "coils": max(A.ncoils, 1),
-                     "projection": ("exhaustive split BF16" if "net" not in kw else
+                     "projection": (("cover tree, eps = %g (Algorithm 1)" % kw["eps"] if "eps" in kw else
+                                     "exhaustive split BF16") if "net" not in kw else
                                     "learned + split-BF16 local search + " +
                                     ("cover-tree fallback" if "eps" in kw else "exhaustive fallback")), **extra}
         log(f"iteration {name}: {step_ms:.2f} ms per step, operator (A, A^H on {Dd.L} frames) {op_ms:.2f} ms"
-            + (f", fallback fraction {extra['fallback_fraction']:.3f}" if extra else ""))
+            + "".join(f", {k} {v:.3f}" for k, v in extra.items()))
     return out
 
 

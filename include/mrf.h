@@ -434,6 +434,8 @@ typedef struct {
   double f_in;   /* ||A X_in - Y||_W^2 */
   double f_out;  /* ||A X_out - Y||_W^2 */
   float ms;      /* device time of the step */
+  int64_t distance_evals; /* cover-tree projection (MRF_COVERTREE, or the tree fallback of
+                             MRF_LEARNED): distances computed by the tree search */
 } mrf_step_stats;
 
 /* One step of eq. blip / eq. blip_dcf at a fixed step size mu:
@@ -474,6 +476,8 @@ typedef struct {
   float ms;               /* device time of the whole solve */
   int64_t fallbacks;      /* MRF_LEARNED: voxels sent to the fallback search, summed
                              over every projection of the solve (step-size trials included) */
+  int64_t distance_evals; /* cover-tree projections: tree distances computed, summed over
+                             every projection of the solve (step-size trials included) */
 } mrf_solve_stats;
 
 /* Algorithm 2 with the exact projection: X (DEVICE frame-major, D's frame

@@ -47,9 +47,15 @@ class CoverTree:
 
     def children(self, i, q):
         """Children of node q of level i: nodes of level i+1 whose parent is q
-        (q itself among them)."""
-        par = self.parent[i + 1]
-        return sorted(c for c, p in par.items() if p == q)
+        (q itself among them), in increasing index."""
+        if not hasattr(self, "_kids"):
+            self._kids = {}
+        if i not in self._kids:          # grouped once per level (bookkeeping only)
+            g = {}
+            for c, p in self.parent[i + 1].items():
+                g.setdefault(p, []).append(c)
+            self._kids[i] = {p: sorted(cs) for p, cs in g.items()}
+        return self._kids[i].get(q, [])
 
 
 def unique_atoms(atoms_hat):
@@ -170,3 +176,68 @@ def search(t, p, eps, q_init=None):
         Qi = {c: dc for c, dc in Q.items() if dc <= dmin + t.maxdist[i + 1][c]}
         i += 1
     return qc, dmin, evals
+
+
+def atom_rows(atoms):
+    """Normalised atoms as the real rows the tree is built on: (Re, Im)
+    interleaved per frame for complex atoms, the atoms themselves for real
+    ones."""
+    a = np.asarray(atoms)
+    a = a / np.linalg.norm(a, axis=1, keepdims=True)
+    if np.iscomplexobj(a):
+        b = np.empty((a.shape[0], 2 * a.shape[1]))
+        b[:, 0::2], b[:, 1::2] = a.real, a.imag
+        return b
+    return a.astype(np.float64)
+
+
+def query_rows(Z, complex_atoms):
+    """Z_v / ||Z_v|| in the atoms' row layout (the real part for real atoms,
+    whose score Re<Z, D_j> only sees it); rows with ||Z_v|| = 0 stay zero."""
+    Z = np.asarray(Z).astype(np.complex128)
+    if complex_atoms:
+        q = np.empty((Z.shape[0], 2 * Z.shape[1]))
+        q[:, 0::2], q[:, 1::2] = Z.real, Z.imag
+    else:
+        q = Z.real.copy()
+    nz = np.linalg.norm(Z, axis=1)
+    return q / np.where(nz > 0, nz, 1.0)[:, None]
+
+
+def tree_mf(Z, atoms, t, eps, warm_idx=None):
+    """The cone projection of Algorithm 2 with the exact argmax replaced by
+    Algorithm 1 (Section "CoverBLIP algorithm"): per voxel, the
+    (1+eps)-approximate nearest normalised atom to Z_v / ||Z_v|| (on the
+    unit sphere the nearest atom is the one of largest Re<Z_v, Dhat_j>),
+    warm-started at the atom of the previous estimate (the root when there is
+    none).  t must be built from atom_rows(atoms).  The PD and X follow as
+    for the exact filter: gamma = max(Re<Z_v, D_j>, 0) / ||D_j||^2,
+    X_v = gamma D_j; a zero voxel keeps its warm index (0 without one) and
+    gets gamma = 0.  Returns the keys of mf.exact_mf (idx, gamma, score, X)
+    and evals (distance evaluations per voxel)."""
+    Z = np.asarray(Z).astype(np.complex128)
+    a = np.asarray(atoms)
+    rows = atom_rows(a)
+    uniq = {}
+    for u, j in enumerate(t.rep):                # dictionary index -> unique node
+        uniq[rows[j].tobytes()] = u
+    node_of = np.array([uniq[rows[j].tobytes()] for j in range(rows.shape[0])])
+    nrm = np.linalg.norm(a, axis=1)
+    P = query_rows(Z, np.iscomplexobj(a))
+    n = Z.shape[0]
+    idx = np.zeros(n, dtype=np.int64)
+    evals = np.zeros(n, dtype=np.int64)
+    znorm = np.linalg.norm(Z, axis=1)
+    for v in range(n):
+        w = None if warm_idx is None else int(np.asarray(warm_idx)[v])
+        if znorm[v] == 0.0:
+            idx[v] = 0 if w is None else w
+            continue
+        qc, _, ev = search(t, P[v], eps, q_init=None if w is None else int(node_of[w]))
+        idx[v] = int(t.rep[qc])
+        evals[v] = ev
+    score = np.real(np.sum(Z * np.conj(a[idx]), axis=1)) / nrm[idx]
+    score = np.where(znorm == 0.0, 0.0, score)
+    gamma = np.maximum(score, 0.0) / nrm[idx]
+    X = gamma[:, None] * a[idx].astype(np.complex128)
+    return dict(idx=idx, gamma=gamma, score=score, X=X, evals=evals, znorm=znorm)

@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fourier, mf, nudft, phase, subspace
+from . import covertree, fourier, mf, nudft, phase, subspace
 
 
 class NoConvergence(RuntimeError):
@@ -36,13 +36,20 @@ def _weighted_sq(r: np.ndarray, w) -> float:
 
 
 def project(Z: np.ndarray, atoms: np.ndarray, warm_idx=None, X_prev=None,
-            nonexpansive: bool = False, u=None):
+            nonexpansive: bool = False, u=None, tree=None, eps: float = 0.0):
     """Cone projection of a frame-major image Z [S][L][ny][nx]; with a phase
-    vector u, the phase-aligned projection (atoms are then the aligned ones)."""
+    vector u, the phase-aligned projection (atoms are then the aligned ones);
+    with a cover tree (built from covertree.atom_rows(atoms)), CoverBLIP's
+    projection: Algorithm 1 at inaccuracy eps, warm-started at warm_idx."""
     S, L, ny, nx = Z.shape
     Zv = fourier.frame_to_voxel(Z)
-    res = (mf.exact_mf(Zv, atoms, warm_idx=warm_idx, want_X=True) if u is None
-           else phase.project_aligned(Zv, atoms, u, warm_idx=warm_idx))
+    if tree is not None:
+        if u is not None:
+            raise ValueError("the tree projection of a phase-aligned dictionary is not defined here")
+        res = covertree.tree_mf(Zv, atoms, tree, eps, warm_idx=warm_idx)
+    else:
+        res = (mf.exact_mf(Zv, atoms, warm_idx=warm_idx, want_X=True) if u is None
+               else phase.project_aligned(Zv, atoms, u, warm_idx=warm_idx))
     Xv = res["X"]
     if nonexpansive and X_prev is not None:
         Xp = fourier.frame_to_voxel(X_prev)
@@ -86,18 +93,21 @@ def gradient(X, Y, off, idx, w, V=None, smaps=None, coords=None):
 
 
 def ipg_step(Y, off, idx, atoms, X, mu: float, w=None, warm_idx=None,
-             nonexpansive: bool = False, V=None, smaps=None, u=None, coords=None):
+             nonexpansive: bool = False, V=None, smaps=None, u=None, coords=None, tree=None,
+             eps: float = 0.0):
     """One projected-gradient step at a fixed mu.  Returns (X', projection
     result, stats) with stats = dx2, adx2 (weighted), f_old, f_new.  With a
     temporal subspace V, X has s compressed frames, atoms are the compressed
     atoms and dx2 is the compressed norm (the compressed step rule).  With
     coil maps, Y is [c][M].  With a phase vector u the projection is the
-    phase-aligned one (complex PD) over aligned atoms."""
+    phase-aligned one (complex PD) over aligned atoms; with a cover tree it
+    is CoverBLIP's (Algorithm 1 at inaccuracy eps, warm-started at warm_idx)."""
     Y = np.asarray(Y, dtype=np.complex128)
     X = np.asarray(X, dtype=np.complex128)
     G, R = gradient(X, Y, off, idx, w, V, smaps, coords)
     Z = X - mu * G
-    Xn, res = project(Z, atoms, warm_idx=warm_idx, X_prev=X, nonexpansive=nonexpansive, u=u)
+    Xn, res = project(Z, atoms, warm_idx=warm_idx, X_prev=X, nonexpansive=nonexpansive, u=u, tree=tree,
+                      eps=eps)
     dX = Xn - X
     AdX = op_forward(dX, off, idx, V, smaps, coords)
     stats = dict(dx2=float(np.sum(np.abs(dX) ** 2)), adx2=_weighted_sq(AdX, w),
@@ -110,11 +120,15 @@ def ipg_step(Y, off, idx, atoms, X, mu: float, w=None, warm_idx=None,
 def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
               adaptive: bool = True, max_iter: int = 50, rel_tol: float = 1e-6,
               max_shrinks: int = 30, X0=None, w=None, kappa: bool = False,
-              nonexpansive: bool = False, V=None, smaps=None, u=None, coords=None):
+              nonexpansive: bool = False, V=None, smaps=None, u=None, coords=None, tree=None,
+              eps: float = 0.0):
     """Full reconstruction; dims = (S, L, ny, nx) (L = s compressed frames
-    when a temporal subspace V is given).  Returns (X, idx, gamma, history)
-    where history lists per accepted iteration: f (objective after the
-    step), mu, shrinks, dx2, adx2."""
+    when a temporal subspace V is given).  With a cover tree the projection
+    is CoverBLIP's: Algorithm 1 at inaccuracy eps, warm-started at the
+    previous iterate's atoms (the root at the first iteration).  Returns (X,
+    idx, gamma, history) where history lists per accepted iteration: f
+    (objective after the step), mu, shrinks, dx2, adx2 (and, with a tree,
+    evals: distance evaluations of the accepted projection)."""
     S, L, ny, nx = dims
     Y = np.asarray(Y, dtype=np.complex128)
     X = np.zeros(dims, dtype=np.complex128) if X0 is None else np.asarray(X0, dtype=np.complex128).copy()
@@ -129,7 +143,8 @@ def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
         shrinks = 0
         while True:
             Z = X - mu * G
-            Xn, res = project(Z, atoms, warm_idx=warm, X_prev=X, nonexpansive=nonexpansive, u=u)
+            Xn, res = project(Z, atoms, warm_idx=warm, X_prev=X, nonexpansive=nonexpansive, u=u, tree=tree,
+                              eps=eps)
             dX = Xn - X
             dx2 = float(np.sum(np.abs(dX) ** 2))
             adx2 = _weighted_sq(op_forward(dX, off, idx, V, smaps, coords), w)
@@ -150,6 +165,8 @@ def ipg_solve(Y, off, idx, dims, atoms, mu0: float, zeta: float = 2.0,
             mu_init *= kap
         f_new = _weighted_sq(op_forward(X, off, idx, V, smaps, coords) - Y, w)
         hist.append(dict(f=f_new, mu=mu, shrinks=shrinks, dx2=dx2, adx2=adx2))
+        if tree is not None:
+            hist[-1]["evals"] = int(np.sum(res["evals"]))
         if dx2 == 0.0:
             break
         if rel_tol and f > 0 and (f - f_new) / f < rel_tol:

@@ -836,6 +836,8 @@ extern "C" mrf_status mrf_ipg_step(mrf_dict D, const mrf_op *A, const void *Y, c
     HIP_TRY(hipEventCreate(&ev.a));
     HIP_TRY(hipEventCreate(&ev.b));
     HIP_TRY(hipEventRecord(ev.a, s));
+    TRY(grow(D->ts_evals, 64));
+    launch_zero(D->ts_evals.p, 8, s);
   }
   TRY(residual_and_gradient(D, A, static_cast<const float2 *>(X_in), static_cast<const float2 *>(Y),
                             true, s));
@@ -843,7 +845,10 @@ extern "C" mrf_status mrf_ipg_step(mrf_dict D, const mrf_op *A, const void *Y, c
             static_cast<float2 *>(X_out), idx_out, pd, nullptr, s));
   if (stats) {
     HIP_TRY(hipEventRecord(ev.b, s));
+    unsigned long long evals = 0;
+    HIP_TRY(hipMemcpyAsync(&evals, D->ts_evals.p, 8, hipMemcpyDeviceToHost, s));
     TRY(read_scalars(D, 4, s));
+    stats->distance_evals = (int64_t)evals;
     HIP_TRY(hipEventElapsedTime(&stats->ms, ev.a, ev.b));
     stats->dx2 = D->host_scal[0];
     stats->adx2 = D->host_scal[1];
@@ -896,6 +901,9 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
     stats->total_shrinks = 0;
     stats->f0 = f;
     stats->fallbacks = 0;
+    stats->distance_evals = 0;
+    TRY(grow(D->ts_evals, 64));
+    launch_zero(D->ts_evals.p, 8, s);
   }
   bool have_idx = false;
   float mu_init = o->mu0;
@@ -959,6 +967,10 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
       stats->iters = k + 1;
       stats->total_shrinks += shrinks;
       stats->fallbacks = D->fallback_total - fallback_start;
+      unsigned long long evals = 0;
+      HIP_TRY(hipMemcpyAsync(&evals, D->ts_evals.p, 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      stats->distance_evals = (int64_t)evals;
     }
     const double f_old = f;
     f = f_new;

@@ -646,7 +646,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
       LAUNCH_CHECK("fallback queries");
       const int cap = o->tree_capacity > 0 ? o->tree_capacity : 1024;
       TRY(grow(D->ts_evals, 64));
-      launch_zero(D->ts_evals.p, 8, s);
+      if (st) launch_zero(D->ts_evals.p, 8, s);
       tree_ran = true;
       TRY(tree_search(D, D->fb_rows.as<float>(), D->fb_norm.as<float>(), D->fb_warm.as<int32_t>(), nfb, o->eps, cap,
                       D->fb_s.as<float>(), D->fb_j.as<int32_t>(), D->list_c, D->rows, D->part_s, D->part_j, nullptr,

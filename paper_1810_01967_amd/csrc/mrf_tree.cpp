@@ -132,7 +132,9 @@ mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
     HIP_TRY(hipEventCreate(&ev.b));
     HIP_TRY(hipEventRecord(ev.a, s));
   }
-  launch_zero(D->ts_evals.p, 8, s);
+  // the counter accumulates over searches: reset here for a direct call with
+  // stats, by the projected-gradient entry points otherwise
+  if (st) launch_zero(D->ts_evals.p, 8, s);
   int64_t nfb = 0;
   TRY(tree_search(D, D->zp.as<float>(), D->znorm.as<float>(), warm, n, o->eps, cap, D->best_s.as<float>(),
                   D->best_j.as<int32_t>(), D->list_a, D->rows, D->part_s, D->part_j, &nfb, s));

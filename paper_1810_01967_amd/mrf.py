@@ -102,7 +102,7 @@ class Op(ctypes.Structure):
 
 class StepStats(ctypes.Structure):
     _fields_ = [("dx2", ctypes.c_double), ("adx2", ctypes.c_double), ("f_in", ctypes.c_double),
-                ("f_out", ctypes.c_double), ("ms", ctypes.c_float)]
+                ("f_out", ctypes.c_double), ("ms", ctypes.c_float), ("distance_evals", ctypes.c_int64)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -116,7 +116,7 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("total_shrinks", ctypes.c_int32),
                 ("cap", ctypes.c_int32), ("f", ctypes.c_void_p), ("mu", ctypes.c_void_p),
                 ("shrinks", ctypes.c_void_p), ("f0", ctypes.c_double), ("ms", ctypes.c_float),
-                ("fallbacks", ctypes.c_int64)]
+                ("fallbacks", ctypes.c_int64), ("distance_evals", ctypes.c_int64)]
 
 
 _LIB = None
@@ -695,7 +695,8 @@ def mrf_ipg_solve(D: Dictionary, A: Operator, Y, X0=None, mu0=1.0, zeta=2.0, ada
                                _dev(idx), _dev(pd), _dev(params), ctypes.byref(st), _stream(stream)))
     k = st.iters
     hist = dict(iters=k, total_shrinks=st.total_shrinks, f0=st.f0, f=f[:k].copy(), mu=mu[:k].copy(),
-                shrinks=sh[:k].copy(), ms=st.ms, fallbacks=st.fallbacks)
+                shrinks=sh[:k].copy(), ms=st.ms, fallbacks=st.fallbacks,
+                distance_evals=st.distance_evals)
     return X, idx, pd, params, hist
 
 

@@ -1,0 +1,117 @@
+"""GPU parity of CoverBLIP itself, Algorithm 2 with Algorithm 1 as its
+projection (Section "CoverBLIP algorithm"), against the FP64 oracle, through
+the C ABI, on the 64 x 64 FISP disc workload (L = 100, 2,000 real atoms, 6
+of 64 lines per frame, 30 dB): teacher-forced steps at eps = 0 and 0.4 (the
+same answers as the oracle's tree search outside FP32-vs-FP64 traversal
+flips, Definition 3.1 and the warm-start bound on every voxel, the same
+distance counts), and ten iterations at mu = 1 against the oracle's
+CoverBLIP solve (eps = 0.4) and against the exhaustive solve (eps = 0)."""
+import numpy as np
+import pytest
+
+from gpu_helpers import banner, c64, dev, host
+from oracle import covertree as ct
+from oracle import fourier, ipg
+from synth import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1810_01967_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def prob(m):
+    Dd = workloads.fisp_dictionary(L=100)
+    ph = workloads.disc_phantom(Dd, seed=1, size=64, snap=True)
+    smp = workloads.random_lines(1, 1, Dd.L, 64, 64, 6)
+    Y = c64(workloads.simulate_kspace(ph.X0, smp, 30.0, 1))
+    t = ct.build(ct.atom_rows(Dd.atoms))
+    D = m.Dictionary(Dd.atoms, Dd.params, cover_tree=True)
+    A = m.Operator.from_sampling(smp)
+    return Dd, ph, smp, Y, t, D, A
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.4])
+def test_coverblip_step_teacher_forced(m, prob, eps):
+    banner(f"coverblip step teacher-forced 64x64 L=100 FISP eps={eps}")
+    Dd, ph, smp, Y, t, D, A = prob
+    dims = (1, Dd.L, 64, 64)
+    X1, i1, _, _ = ipg.ipg_solve(Y, smp.off, smp.idx, dims, Dd.atoms, mu0=1.0, adaptive=False, max_iter=1,
+                                 rel_tol=0)
+    Xk = c64(X1)
+    warm = i1.astype(np.int32)
+    n = 64 * 64
+    for mu in (1.0, 2.0):
+        Xn, idx, pd, st = m.mrf_ipg_step(D, A, dev(Y), dev(Xk), mu, idx_in=dev(warm), eps=eps)
+        Xr, res, sr = ipg.ipg_step(Y, smp.off, smp.idx, Dd.atoms, Xk.astype(np.complex128), mu, warm_idx=i1,
+                                   tree=t, eps=eps)
+        gidx = host(idx).astype(np.int64)
+        diff = gidx != res["idx"]
+        ev_g, ev_o = st.distance_evals / n, res["evals"].mean()
+        print(f"mu={mu}: {int(diff.sum())} index differences of {n}; distance evaluations per voxel gpu {ev_g:.1f} "
+              f"oracle {ev_o:.1f} (d = {Dd.d}); f_in {st.f_in:.6e} / {sr['f_old']:.6e}")
+        assert abs(st.f_in - sr["f_old"]) <= 1e-5 * sr["f_old"]
+        assert diff.mean() <= 0.02
+        # every GPU answer: Definition 3.1 and no farther than the warm atom (FP64 distances)
+        Zv = fourier.frame_to_voxel(Xk.astype(np.complex128) - mu * ipg.gradient(
+            Xk.astype(np.complex128), Y.astype(np.complex128), smp.off, smp.idx, None)[0])
+        P = ct.query_rows(Zv, False)
+        Ar = ct.atom_rows(Dd.atoms)
+        dist = np.sqrt(np.maximum(np.sum(P ** 2, axis=1)[:, None] + 1.0 - 2.0 * (P @ Ar.T), 0.0))
+        got = dist[np.arange(n), gidx]
+        assert np.all(got <= (1 + eps) * dist.min(axis=1) * (1 + 1e-5) + 1e-5)
+        assert np.all(got <= dist[np.arange(n), i1] * (1 + 1e-5) + 1e-5)
+        assert abs(ev_g / ev_o - 1.0) < 0.05
+        np.testing.assert_allclose(host(pd)[~diff], res["gamma"][~diff], rtol=1e-4, atol=1e-6)
+        if not diff.any():
+            assert _rel(host(Xn), Xr) < 1e-5
+            for k, g in (("dx2", st.dx2), ("adx2", st.adx2), ("f_new", st.f_out)):
+                assert abs(g - sr[k]) <= 1e-4 * abs(sr[k]) + 1e-12, (k, g, sr[k])
+
+
+def test_coverblip_solve(m, prob):
+    """Ten iterations at mu = 1 (cfg1's schedule).  eps = 0.4: objective and
+    error against the oracle's CoverBLIP solve; eps = 0: the exhaustive
+    solve's trajectory."""
+    banner("coverblip solve 64x64 L=100 FISP 10 iterations mu=1, eps 0.4 and 0")
+    Dd, ph, smp, Y, t, D, A = prob
+    dims = (1, Dd.L, 64, 64)
+    n = 64 * 64
+    X, idx, pd, params, hist = m.mrf_ipg_solve(D, A, dev(Y), mu0=1.0, adaptive=False, max_iter=10, rel_tol=0.0,
+                                               eps=0.4)
+    Xr, idr, gr, hr = ipg.ipg_solve(Y, smp.off, smp.idx, dims, Dd.atoms, mu0=1.0, adaptive=False, max_iter=10,
+                                    rel_tol=0, tree=t, eps=0.4)
+    fr = np.array([h["f"] for h in hr])
+    inside = ph.idx >= 0
+    gidx = host(idx)
+    nm_g, nm_o = _rel(host(X), ph.X0), _rel(Xr, ph.X0)
+    ev_g = hist["distance_evals"] / (n * 10)
+    ev_o = sum(h["evals"] for h in hr) / (n * 10)
+    print(f"eps=0.4: f gpu {hist['f'][-1]:.5e} oracle {fr[-1]:.5e}; nmse gpu {nm_g:.4e} oracle {nm_o:.4e}; "
+          f"object agreement {np.mean(gidx[inside] == idr[inside]):.4f}; distance evaluations per voxel per "
+          f"iteration gpu {ev_g:.1f} oracle {ev_o:.1f} (d = {Dd.d}); {hist['ms']:.1f} ms")
+    assert hist["iters"] == 10
+    np.testing.assert_allclose(hist["f"], fr, rtol=0.02)
+    assert abs(nm_g - nm_o) < 0.05 * nm_o + 1e-4
+    assert np.mean(gidx[inside] == idr[inside]) > 0.95
+    assert abs(ev_g / ev_o - 1.0) < 0.1
+    X0, i0, _, _, h0 = m.mrf_ipg_solve(D, A, dev(Y), mu0=1.0, adaptive=False, max_iter=10, rel_tol=0.0, eps=0.0)
+    Xe, ie, _, _, he = m.mrf_ipg_solve(D, A, dev(Y), mu0=1.0, adaptive=False, max_iter=10, rel_tol=0.0)
+    agree = np.mean(host(i0)[inside] == host(ie)[inside])
+    print(f"eps=0: f {h0['f'][-1]:.6e} vs exhaustive {he['f'][-1]:.6e}; object agreement {agree:.4f}; "
+          f"{h0['distance_evals'] / (n * 10):.1f} distance evaluations per voxel per iteration; "
+          f"{h0['ms']:.1f} ms vs exhaustive {he['ms']:.1f} ms")
+    np.testing.assert_allclose(h0["f"], he["f"], rtol=1e-3)
+    assert agree > 0.98
+    assert he["distance_evals"] == 0
