@@ -22,12 +22,18 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // ---------------------------------------------------------------------------
 // grouping
 // ---------------------------------------------------------------------------
-__global__ void k_coarse_keys(const int32_t *__restrict__ list, int64_t cnt,
+// A list length on the device (dcnt, may be null) bounds the host's cnt, which
+// then only sizes the grid.
+__device__ __forceinline__ int64_t list_len(int64_t cnt, const unsigned int *dcnt) {
+  return dcnt ? min(cnt, (int64_t)*dcnt) : cnt;
+}
+
+__global__ void k_coarse_keys(const int32_t *__restrict__ list, int64_t cnt, const unsigned int *__restrict__ dcnt,
                               const int32_t *__restrict__ cells, int P, int shift,
                               GridDims g, int32_t *__restrict__ keys,
                               unsigned int *__restrict__ hist) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
+  if (i >= list_len(cnt, dcnt)) return;
   const int v = list[i];
   int key = 0;
   for (int p = 0; p < P; ++p) {
@@ -86,10 +92,10 @@ __global__ __launch_bounds__(1024) void k_scan(const unsigned int *__restrict__ 
 }
 
 __global__ void k_group_scatter(const int32_t *__restrict__ list, const int32_t *__restrict__ keys,
-                                int64_t cnt, unsigned int *__restrict__ cursor,
-                                int32_t *__restrict__ out) {
+                                int64_t cnt, const unsigned int *__restrict__ dcnt,
+                                unsigned int *__restrict__ cursor, int32_t *__restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
+  if (i >= list_len(cnt, dcnt)) return;
   const unsigned int pos = atomicAdd(&cursor[keys[i]], 1u);
   out[pos] = list[i];
 }
@@ -101,15 +107,16 @@ int coarse_key_count(const GridDims &g, int P, int shift) {
 }
 
 void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P, int shift,
-                  const GridDims &g, int32_t *keys, GroupBufs gb, int32_t *out, hipStream_t s) {
+                  const GridDims &g, int32_t *keys, GroupBufs gb, int32_t *out, hipStream_t s,
+                  const unsigned int *dcnt) {
   if (cnt <= 0) return;
   const int nkeys = coarse_key_count(g, P, shift);
   launch_zero(gb.hist, (int64_t)nkeys * 4, s);
   const unsigned blocks = (unsigned)((cnt + 255) / 256);
-  hipLaunchKernelGGL(k_coarse_keys, dim3(blocks), dim3(256), 0, s, list, cnt, cells, P, shift, g,
+  hipLaunchKernelGGL(k_coarse_keys, dim3(blocks), dim3(256), 0, s, list, cnt, dcnt, cells, P, shift, g,
                      keys, gb.hist);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, gb.hist, nkeys, gb.off, gb.cursor, gb.toff);
-  hipLaunchKernelGGL(k_group_scatter, dim3(blocks), dim3(256), 0, s, list, keys, cnt, gb.cursor, out);
+  hipLaunchKernelGGL(k_group_scatter, dim3(blocks), dim3(256), 0, s, list, keys, cnt, dcnt, gb.cursor, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -191,10 +198,11 @@ __device__ __forceinline__ unsigned long long pack_best(float s, int j) {
 
 // mode 0: keys of the listed voxels (all voxels if list is null) set to 0;
 // mode 1: keys unpacked into best_s / best_j (-inf / -1 for key 0).
-__global__ void k_best_keys(const int32_t *__restrict__ list, int64_t cnt, unsigned long long *__restrict__ keys,
-                            float *__restrict__ best_s, int32_t *__restrict__ best_j, int mode) {
+__global__ void k_best_keys(const int32_t *__restrict__ list, int64_t cnt, const unsigned int *__restrict__ dcnt,
+                            unsigned long long *__restrict__ keys, float *__restrict__ best_s,
+                            int32_t *__restrict__ best_j, int mode) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
+  if (i >= list_len(cnt, dcnt)) return;
   const int64_t v = list ? list[i] : i;
   if (mode == 0) {
     keys[v] = 0ull;
@@ -212,10 +220,10 @@ __global__ void k_best_keys(const int32_t *__restrict__ list, int64_t cnt, unsig
 }
 
 void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys, float *best_s, int32_t *best_j,
-                      int mode, hipStream_t s) {
+                      int mode, hipStream_t s, const unsigned int *dcnt) {
   if (cnt <= 0) return;
-  hipLaunchKernelGGL(k_best_keys, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, keys, best_s,
-                     best_j, mode);
+  hipLaunchKernelGGL(k_best_keys, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, dcnt, keys,
+                     best_s, best_j, mode);
 }
 
 // X3 = false: FP32 rows (pitch Kp), v_mfma_f32_32x32x2f32.
@@ -612,11 +620,11 @@ void launch_warm_best(const int32_t *warm, int64_t n, int d, const float *Zp, co
 // ---------------------------------------------------------------------------
 // For listed voxels: if the best atom lies on a box face that is not a grid
 // edge, append the voxel to `recentre` and move its cell to the best atom.
-__global__ void k_face(const int32_t *__restrict__ list, int64_t cnt, const int32_t *__restrict__ best_j,
-                       int32_t *__restrict__ cells, int P, GridDims g, int r,
+__global__ void k_face(const int32_t *__restrict__ list, int64_t cnt, const unsigned int *__restrict__ dcnt,
+                       const int32_t *__restrict__ best_j, int32_t *__restrict__ cells, int P, GridDims g, int r,
                        int32_t *__restrict__ out, unsigned int *__restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
+  if (i >= list_len(cnt, dcnt)) return;
   const int v = list[i];
   int j = best_j[v];
   if (j < 0) return;
@@ -636,9 +644,10 @@ __global__ void k_face(const int32_t *__restrict__ list, int64_t cnt, const int3
 }
 
 void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
-                 const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s) {
+                 const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s,
+                 const unsigned int *dcnt) {
   if (cnt <= 0) return;
-  hipLaunchKernelGGL(k_face, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, best_j,
+  hipLaunchKernelGGL(k_face, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, dcnt, best_j,
                      cells, P, g, r, out, count);
 }
 

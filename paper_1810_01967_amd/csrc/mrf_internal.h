@@ -234,8 +234,11 @@ struct GroupBufs {
   unsigned int *hist, *off, *cursor, *toff;
 };
 int coarse_key_count(const GridDims &g, int P, int shift);
+// dcnt (device, may be null) in the list kernels below: the list's length on
+// the device, bounded by cnt, which then only sizes the grid.
 void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P, int shift,
-                  const GridDims &g, int32_t *keys, GroupBufs gb, int32_t *out, hipStream_t s);
+                  const GridDims &g, int32_t *keys, GroupBufs gb, int32_t *out, hipStream_t s,
+                  const unsigned int *dcnt = nullptr);
 // Local search over the grouped list: one block per tile of <= 64 voxels of
 // one coarse key.  x3 = false: FP32 rows of pitch `pitch`; x3 = true:
 // split-BF16 rows of pitch/32 chunks [hi 32 | lo 32].
@@ -249,7 +252,7 @@ void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const
 // mode 0: zero the keys of the listed voxels (all if list is null); mode 1:
 // unpack them into best_s / best_j (-inf / -1 where no candidate).
 void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys, float *best_s, int32_t *best_j,
-                      int mode, hipStream_t s);
+                      int mode, hipStream_t s, const unsigned int *dcnt = nullptr);
 // Exhaustive split-BF16 scoring with fused argmax per atom split (Dx split
 // atoms [d_pad][2 Kx], Zx split voxels [n_pad][2 Kx]); merged by
 // launch_merge_argmax like the FP32 filter.
@@ -269,7 +272,8 @@ void launch_unsplit_x3(const uint16_t *src, int64_t rows, int Kx, int K, uint16_
 void launch_warm_best(const int32_t *warm, int64_t n, int d, const float *Zp, const float *Dhat, int Kp,
                       const float *znorm, float *best_s, int32_t *best_j, hipStream_t s);
 void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
-                 const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s);
+                 const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s,
+                 const unsigned int *dcnt = nullptr);
 void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,
                             float thr, int32_t *out, unsigned int *count, hipStream_t s);
 void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cnt, int64_t cnt_pad,

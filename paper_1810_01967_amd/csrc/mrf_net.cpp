@@ -527,7 +527,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   TRY(grow(D->list_b, (size_t)n * 4));
   TRY(grow(D->list_c, (size_t)n * 4));
   TRY(grow(D->keys, (size_t)n * 4));
-  TRY(grow(D->cnt, 64));
+  TRY(grow(D->cnt, 128));  // [0] fallback count, [1..16] re-centring rounds
   TRY(grow(D->counters, 64));
   int32_t *cells = cells_in;
   if (!cells) {
@@ -554,14 +554,25 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
 #ifndef MRF_LS_SHIFT
 #define MRF_LS_SHIFT 2
 #endif
+#ifndef MRF_LS_RC_SHIFT
+#define MRF_LS_RC_SHIFT 1
+#endif
   const int shift = MRF_LS_SHIFT;  // coarse cells of 2^shift grid steps per parameter (a tuning constant)
   const int nkeys = coarse_key_count(g, P, shift);
-  TRY(grow(D->hist, (size_t)(4 * nkeys + 8) * 4));
-  GroupBufs gb;
-  gb.hist = D->hist.as<unsigned int>();
-  gb.off = gb.hist + nkeys;
-  gb.cursor = gb.off + nkeys;
-  gb.toff = gb.cursor + nkeys;
+  // re-centring rounds take few, scattered voxels: finer cells keep each
+  // tile's bounding box close to its voxels' own boxes (also a tuning constant)
+  const int shift_rc = MRF_LS_RC_SHIFT;
+  const int nkeys_rc = coarse_key_count(g, P, shift_rc);
+  TRY(grow(D->hist, (size_t)(4 * std::max(nkeys, nkeys_rc) + 8) * 4));
+  auto group_bufs = [&](int nk) {
+    GroupBufs b;
+    b.hist = D->hist.as<unsigned int>();
+    b.off = b.hist + nk;
+    b.cursor = b.off + nk;
+    b.toff = b.cursor + nk;
+    return b;
+  };
+  const GroupBufs gb = group_bufs(nkeys), gb_rc = group_bufs(nkeys_rc);
   unsigned long long *work = D->counters.as<unsigned long long>() + 2;  // [0] scored rows, [1] first-launch boxes
   launch_zero(work, 16, s);
   // round 0: every voxel, grouped by coarse proposal cell
@@ -587,29 +598,28 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   launch_best_keys(nullptr, n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s);
   if (st) HIP_TRY(hipEventRecord(e_ls1, s));
   LAUNCH_CHECK("local search");
-  int64_t cnt = n;
-  int64_t recentred = 0;
   // re-centring rounds over the voxels whose best atom sits on an interior
   // face of their box: the face test writes the list into lc (and moves the
-  // cells), the grouping sorts it into whichever of la / lb was not scored last
+  // cells), the grouping sorts it into whichever of la / lb was not scored last.
+  // The list lengths stay on the device (round rd's in rcount[rd]); every
+  // grid is sized for all n voxels and its surplus exits at once, so the host
+  // enqueues the rounds without waiting for the first launch to finish.
+  unsigned int *rcount = D->cnt.as<unsigned int>() + 1;  // [0] is the fallback count
+  if (o->recentre > 0) launch_zero(rcount, 4 * o->recentre, s);
   int32_t *prev = lb;
-  for (int rd = 0; rd < o->recentre && cnt > 0; ++rd) {
-    unsigned int *count = D->cnt.as<unsigned int>();
-    launch_zero(count, 4, s);
-    launch_face(prev, cnt, D->best_j.as<int32_t>(), cells, P, g, r, lc, count, s);
-    unsigned int hc = 0;
-    HIP_TRY(hipMemcpyAsync(&hc, count, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    cnt = hc;
-    recentred += cnt;
-    if (cnt == 0) break;
+  const unsigned int *prev_cnt = nullptr;  // device length of prev (null: all n)
+  for (int rd = 0; rd < o->recentre; ++rd) {
+    unsigned int *count = rcount + rd;
+    launch_face(prev, n, D->best_j.as<int32_t>(), cells, P, g, r, lc, count, s, prev_cnt);
     int32_t *sorted = (prev == lb) ? la : lb;
-    launch_group(lc, cnt, cells, P, shift, g, D->keys.as<int32_t>(), gb, sorted, s);
-    launch_best_keys(sorted, cnt, bkey, nullptr, nullptr, 0, s);
-    launch_local_score(Dop, Zop, pitch, x3, sorted, cnt, gb, nkeys, cells, P, g, r, shift, bkey, work, nullptr, s);
-    launch_best_keys(sorted, cnt, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s);
+    launch_group(lc, n, cells, P, shift_rc, g, D->keys.as<int32_t>(), gb_rc, sorted, s, count);
+    launch_best_keys(sorted, n, bkey, nullptr, nullptr, 0, s, count);
+    launch_local_score(Dop, Zop, pitch, x3, sorted, n, gb_rc, nkeys_rc, cells, P, g, r, shift_rc, bkey, work,
+                       nullptr, s);
+    launch_best_keys(sorted, n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s, count);
     LAUNCH_CHECK("local search (re-centre)");
     prev = sorted;
+    prev_cnt = count;
   }
   // the previous atom competes (non-expansive safeguard of the inexact projection)
   launch_warm_best(warm, n, D->d, D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->znorm.as<float>(),
@@ -693,10 +703,14 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   LAUNCH_CHECK("merge");
   if (st) {
     unsigned long long wk[2] = {0, 0}, ev_count = 0;
+    unsigned int rc[16] = {0};
     HIP_TRY(hipMemcpyAsync(wk, work, 16, hipMemcpyDeviceToHost, s));
+    if (o->recentre > 0) HIP_TRY(hipMemcpyAsync(rc, rcount, 4 * o->recentre, hipMemcpyDeviceToHost, s));
     if (tree_ran) HIP_TRY(hipMemcpyAsync(&ev_count, D->ts_evals.p, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     st->fallbacks = nfb;
+    int64_t recentred = 0;
+    for (int rd = 0; rd < o->recentre; ++rd) recentred += rc[rd];
     st->recentred = recentred;
     st->local_atoms = (int64_t)wk[0];
     st->first_box_atoms = (int64_t)wk[1];
