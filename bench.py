@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--variants", type=int, default=1, help="also time BF16 / FP8 exhaustive scoring")
     ap.add_argument("--learned", type=int, default=1, help="train the network and time the learned path")
+    ap.add_argument("--net-cache", default="",
+                    help="network file: loaded if it exists (no training), else written after training; lets a "
+                         "profiled run time the very network of an earlier run")
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--recentre", type=int, default=1, help="re-centring rounds of the local search")
@@ -165,14 +168,21 @@ def main():
     learned = None
     if args.learned:
         t2 = time.time()
-        net = m.Net(K, Dd.params.shape[1], hidden=256, seed=11)
-        tr = m.mrf_net_train(net, D, samples=args.train_samples, batch=4096, epochs=args.train_epochs,
-                             lr=1e-3, lr_min=1e-5, snr_lo=15.0, snr_hi=40.0, seed=12)
-        log(f"network trained in {time.time() - t2:.1f}s ({tr['steps']} steps, loss "
-            f"{tr['first_loss']:.4f} -> {tr['last_loss']:.5f})")
-        learned = {"training": {"samples": args.train_samples, "epochs": args.train_epochs,
-                                "steps": tr["steps"], "seconds": tr["ms"] / 1e3,
-                                "loss_first": tr["first_loss"], "loss_last": tr["last_loss"]}}
+        if args.net_cache and os.path.exists(args.net_cache):
+            net = m.Net.load(args.net_cache)
+            log(f"network loaded from {args.net_cache}")
+            learned = {"training": {"loaded": args.net_cache}}
+        else:
+            net = m.Net(K, Dd.params.shape[1], hidden=256, seed=11)
+            tr = m.mrf_net_train(net, D, samples=args.train_samples, batch=4096, epochs=args.train_epochs,
+                                 lr=1e-3, lr_min=1e-5, snr_lo=15.0, snr_hi=40.0, seed=12)
+            log(f"network trained in {time.time() - t2:.1f}s ({tr['steps']} steps, loss "
+                f"{tr['first_loss']:.4f} -> {tr['last_loss']:.5f})")
+            learned = {"training": {"samples": args.train_samples, "epochs": args.train_epochs,
+                                    "steps": tr["steps"], "seconds": tr["ms"] / 1e3,
+                                    "loss_first": tr["first_loss"], "loss_last": tr["last_loss"]}}
+            if args.net_cache:
+                net.save(args.net_cache)
         fastest = min([ms32] + [v["ms_per_step"] for v in variants.values()
                                 if v["index_mismatch_vs_fp32"] <= 1e-3])
         for lp in args.learned_precisions.split(","):

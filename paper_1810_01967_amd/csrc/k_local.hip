@@ -262,15 +262,27 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
   // positions off[k] + 64 (T - toff[k]) .. (at most 64, never beyond key k)
   // Workgroups are dealt to the 8 XCDs round-robin (block b on XCD b % 8).
   // Block b = x + 8 j takes the q-th tile of XCD x, q = j / max_at, and its
-  // atom tile j % max_at; XCD x owns runs of LS_RUN consecutive tiles (runs
-  // x, x + 8, ...).  So all atom tiles of a tile run on one XCD one after the
-  // other (its voxel rows stay in that L2), and consecutive tiles there are
-  // neighbouring coarse cells whose bounding boxes share atom rows.
+  // atom tile j % max_at, so all atom tiles of a tile run on one XCD one after
+  // the other (its voxel rows stay in that L2).
+#ifndef MRF_LS_XCD_SLAB
+#define MRF_LS_XCD_SLAB 0
+#endif
   const unsigned int xcd = blockIdx.x & 7u, jx = blockIdx.x >> 3;
   const unsigned int q = jx / (unsigned)max_at;
-  const unsigned int T = ((q / LS_RUN) * 8u + xcd) * LS_RUN + q % LS_RUN;
   const int at = (int)(jx % (unsigned)max_at);
+#if MRF_LS_XCD_SLAB
+  // XCD x owns the x-th eighth of the tiles in key order (a slab of the
+  // slowest parameter's coarse cells), so the tiles resident on one XCD at a
+  // time are neighbouring cells whose bounding boxes share atom rows
+  const unsigned int ntile = gb.toff[nkeys];
+  const unsigned int per = (ntile + 7u) / 8u;
+  const unsigned int T = xcd * per + q;
+  if (q >= per || T >= ntile) return;
+#else
+  // XCD x owns runs of LS_RUN consecutive tiles (runs x, x + 8, ...)
+  const unsigned int T = ((q / LS_RUN) * 8u + xcd) * LS_RUN + q % LS_RUN;
   if (T >= gb.toff[nkeys]) return;
+#endif
   int lo_k = 0, hi_k = nkeys - 1;
   while (lo_k < hi_k) {
     const int mid = (lo_k + hi_k + 1) >> 1;
