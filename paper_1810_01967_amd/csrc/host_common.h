@@ -102,6 +102,9 @@ mrf_status tree_search(mrf_dict_s *D, const float *Q, const float *qnorm, const 
                        float eps, int cap, float *out_s, int32_t *out_j, DevBuf &ovf, DevBuf &rows, DevBuf &ps,
                        DevBuf &pj, int64_t *n_overflow, hipStream_t s);
 mrf_status ensure_x3(mrf_dict_s *D, hipStream_t s);
+// device counter of the learned path's fallback voxels: created zeroed / read (syncs s)
+mrf_status fallback_total_buf(mrf_dict_s *D, hipStream_t s);
+mrf_status read_fallback_total(mrf_dict_s *D, hipStream_t s, int64_t *out);
 int auto_splits_x3(const mrf_dict_s *D, int64_t n);
 bool net_bf16_ok(const mrf_net_s *net, int64_t K, int64_t ldx);
 mrf_status net_forward_bf16(mrf_net_s *net, const float *X, int64_t ldx, int64_t K, int64_t B,
@@ -121,7 +124,7 @@ struct mrf_dict_s {
   mrf::DevBuf dx3;                              // split-BF16 atoms [d_pad][Kx/32][hi 32 | lo 32] (built on first use)
   mrf::DevBuf axes, aoff, dims;                 // device copies of the grid axes
   int64_t bytes = 0;
-  int64_t fallback_total = 0;  // voxels sent to the exhaustive fallback by the learned path (all calls)
+  mrf::DevBuf fbtot;  // device u64: voxels sent to the fallback by the learned path (all calls)
   // workspace (grows lazily)
   mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j, zx3;
   bool zx3_fresh = false;  // zx3 holds the split rows of the current packing (written by the pack)

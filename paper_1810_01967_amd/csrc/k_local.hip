@@ -701,17 +701,56 @@ void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cn
                      cnt_pad, out);
 }
 
-// best[list[i]] = merged exhaustive result i (splits merged in order)
+// Rows list[i] of Zp (pitch Kp floats) into out[i] for i < the device count,
+// zero rows up to the next multiple of 128 (the voxel tile of the split-BF16
+// filter); a grid-stride loop, so the grid does not depend on the count.
+__global__ void k_gather_rows_dev(const float *__restrict__ Zp, int Kp, const int32_t *__restrict__ list,
+                                  int64_t cap, const unsigned int *__restrict__ dcnt, float *__restrict__ out) {
+  const int64_t c = min(cap, (int64_t)*dcnt);
+  const int64_t rows = (c + 127) / 128 * 128;
+  for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
+    const float4 *src = i < c ? reinterpret_cast<const float4 *>(Zp + (int64_t)list[i] * Kp) : nullptr;
+    float4 *dst = reinterpret_cast<float4 *>(out + i * Kp);
+    for (int k = threadIdx.x; k < Kp / 4; k += blockDim.x)
+      dst[k] = src ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+void launch_gather_rows_dev(const float *Zp, int Kp, const int32_t *list, int64_t cap, const unsigned int *dcnt,
+                            float *out, hipStream_t s) {
+  if (cap <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows_dev, dim3(1024), dim3(256), 0, s, Zp, Kp, list, cap, dcnt, out);
+}
+
+// total += *count (one thread)
+__global__ void k_add_count(unsigned long long *__restrict__ total, const unsigned int *__restrict__ count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *total += *count;
+}
+
+void launch_add_count(unsigned long long *total, const unsigned int *count, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_count, dim3(1), dim3(64), 0, s, total, count);
+}
+
+// best[list[i]] = merged exhaustive result i (splits merged in order).  With
+// a device count (dcnt), cnt is the capacity and the split count and part
+// stride are those of the device-sized split-BF16 filter (ntiles atom tiles).
 __global__ void k_scatter_best(const int32_t *__restrict__ list, int64_t cnt,
                                const float *__restrict__ part_s, const int *__restrict__ part_j,
-                               int splits, float *__restrict__ best_s, int32_t *__restrict__ best_j) {
+                               int splits, float *__restrict__ best_s, int32_t *__restrict__ best_j,
+                               const unsigned int *__restrict__ dcnt, int ntiles) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
+  int64_t c = cnt;
+  const int64_t stride = cnt;
+  if (dcnt) {
+    c = min(cnt, (int64_t)*dcnt);
+    splits = x3_device_splits((int)((c + 127) / 128), ntiles);
+  }
+  if (i >= c) return;
   float bs = -INFINITY;
   int bj = -1;
   for (int s = 0; s < splits; ++s) {
-    const float ps = part_s[(int64_t)s * cnt + i];
-    const int pj = part_j[(int64_t)s * cnt + i];
+    const float ps = part_s[(int64_t)s * stride + i];
+    const int pj = part_j[(int64_t)s * stride + i];
     if (pj >= 0 && lbetter(ps, pj, bs, bj)) {
       bs = ps;
       bj = pj;
@@ -723,10 +762,11 @@ __global__ void k_scatter_best(const int32_t *__restrict__ list, int64_t cnt,
 }
 
 void launch_scatter_best(const int32_t *list, int64_t cnt, const float *part_s, const int *part_j,
-                         int splits, float *best_s, int32_t *best_j, hipStream_t s) {
+                         int splits, float *best_s, int32_t *best_j, hipStream_t s, const unsigned int *dcnt,
+                         int ntiles) {
   if (cnt <= 0) return;
   hipLaunchKernelGGL(k_scatter_best, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt,
-                     part_s, part_j, splits, best_s, best_j);
+                     part_s, part_j, splits, best_s, best_j, dcnt, ntiles);
 }
 
 __global__ void k_iota(int32_t *x, int64_t n) {
@@ -742,13 +782,15 @@ void launch_iota(int32_t *x, int64_t n, hipStream_t s) {
 
 namespace mrf {
 
-__global__ void k_mark(const int32_t *__restrict__ list, int64_t cnt, int32_t *__restrict__ flags) {
+__global__ void k_mark(const int32_t *__restrict__ list, int64_t cnt, const unsigned int *__restrict__ dcnt,
+                       int32_t *__restrict__ flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) flags[list[i]] = 1;
+  if (i < list_len(cnt, dcnt)) flags[list[i]] = 1;
 }
 
-void launch_mark(const int32_t *list, int64_t cnt, int32_t *flags, hipStream_t s) {
-  if (cnt > 0) hipLaunchKernelGGL(k_mark, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, flags);
+void launch_mark(const int32_t *list, int64_t cnt, int32_t *flags, hipStream_t s, const unsigned int *dcnt) {
+  if (cnt > 0)
+    hipLaunchKernelGGL(k_mark, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, dcnt, flags);
 }
 
 }  // namespace mrf

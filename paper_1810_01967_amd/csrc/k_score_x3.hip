@@ -9,6 +9,7 @@
 // the B columns, so a lane folds the running maximum of one voxel column).
 // One 32-element chunk per stage, double-buffered in LDS (rows of 72 BF16:
 // the chunk plus 8 of padding).
+#include "k_split.h"
 #include "mrf_internal.h"
 
 namespace mrf {
@@ -26,147 +27,165 @@ __device__ __forceinline__ bool xbetter(float s1, int j1, float s0, int j0) {
 __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict__ Dx, const uint16_t *__restrict__ Zx,
                                                      int d, int ntiles_total, int64_t n, int nvt, int Kx,
                                                      int splits, int tiles_per_split, float *__restrict__ part_s,
-                                                     int *__restrict__ part_j) {
-  // block -> (voxel tile, atom split); all splits of a voxel tile on one XCD
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7, local = bid >> 3;
-  const int split = local % splits;
-  const int vt = (local / splits) * 8 + xcd;
-  if (vt >= nvt) return;
-  const int tb = split * tiles_per_split;
-  const int te = min(tb + tiles_per_split, ntiles_total);
+                                                     int *__restrict__ part_j, const unsigned int *__restrict__ dcnt,
+                                                     int64_t pstride) {
+  // Work item w -> (voxel tile, atom split); all splits of a voxel tile on one
+  // XCD (item w on XCD w % 8).  Launched by the host (dcnt null): one item per
+  // block, n voxels.  With the voxel count on the device (dcnt): n is only the
+  // capacity, the tiles and splits follow from the count, and a grid of a
+  // multiple of 8 blocks loops over the items (block b keeps XCD b % 8).
+  int64_t nvox = n;
+  int nvt_w = nvt, nsplit = splits, tps = tiles_per_split;
+  if (dcnt) {
+    nvox = min(n, (int64_t)*dcnt);
+    nvt_w = (int)((nvox + X_BV - 1) / X_BV);
+    nsplit = x3_device_splits(nvt_w, ntiles_total);
+    tps = (ntiles_total + nsplit - 1) / nsplit;
+  }
+  const int64_t nwork = (int64_t)((nvt_w + 7) / 8 * 8) * nsplit;
 
   __shared__ __attribute__((aligned(16))) uint16_t S[2 * X_STAGE];
   __shared__ float rs[4][X_BV];
   __shared__ int rj[4][X_BV];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wa = wave >> 1, wv = wave & 1;  // atom rows wa*64.., voxel columns wv*64..
-  const int h = lane >> 5, l32 = lane & 31;
-  const int64_t v0 = (int64_t)vt * X_BV;
-  const int nkc = Kx / 32;
-  const int nq = te > tb ? (te - tb) * nkc : 0;
-  const int64_t row = 2 * (int64_t)Kx;  // elements per split row
+  for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const int xcd = (int)(w & 7);
+    const int64_t local = w >> 3;
+    const int split = (int)(local % nsplit);
+    const int vt = (int)((local / nsplit) * 8 + xcd);
+    if (vt >= nvt_w) continue;
+    const int tb = split * tps;
+    const int te = min(tb + tps, ntiles_total);
 
-  // loader: 8 pieces of 16 B per stage row; piece = tid % 8, rows tid/8 + 64 i
-  const int lr = tid >> 3, piece = tid & 7;
-  const int lc = (piece >> 2) * 32 + (piece & 3) * 8;  // column within [hi 32 | lo 32]
-  uint4 ra[4], rz[2];
-  auto gload = [&](int q) {
-    const int tile = tb + q / nkc, kc = q - (q / nkc) * nkc;
-    const uint16_t *a = Dx + (int64_t)(tile * X_BA + lr) * row + kc * 64 + lc;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ra[i] = *reinterpret_cast<const uint4 *>(a + (int64_t)(64 * i) * row);
-    const uint16_t *z = Zx + (v0 + lr) * row + kc * 64 + lc;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) rz[i] = *reinterpret_cast<const uint4 *>(z + (int64_t)(64 * i) * row);
-  };
-  auto sstore = [&](int buf) {
-    uint16_t *B = S + buf * X_STAGE;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) *reinterpret_cast<uint4 *>(B + (lr + 64 * i) * X_LD + lc) = ra[i];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) *reinterpret_cast<uint4 *>(B + (X_BA + lr + 64 * i) * X_LD + lc) = rz[i];
-  };
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wa = wave >> 1, wv = wave & 1;  // atom rows wa*64.., voxel columns wv*64..
+    const int h = lane >> 5, l32 = lane & 31;
+    const int64_t v0 = (int64_t)vt * X_BV;
+    const int nkc = Kx / 32;
+    const int nq = te > tb ? (te - tb) * nkc : 0;
+    const int64_t row = 2 * (int64_t)Kx;  // elements per split row
 
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
-  float best[2] = {-INFINITY, -INFINITY};
-  int bidx[2] = {-1, -1};
+    // loader: 8 pieces of 16 B per stage row; piece = tid % 8, rows tid/8 + 64 i
+    const int lr = tid >> 3, piece = tid & 7;
+    const int lc = (piece >> 2) * 32 + (piece & 3) * 8;  // column within [hi 32 | lo 32]
+    uint4 ra[4], rz[2];
+    auto gload = [&](int q) {
+      const int tile = tb + q / nkc, kc = q - (q / nkc) * nkc;
+      const uint16_t *a = Dx + (int64_t)(tile * X_BA + lr) * row + kc * 64 + lc;
+  #pragma unroll
+      for (int i = 0; i < 4; ++i) ra[i] = *reinterpret_cast<const uint4 *>(a + (int64_t)(64 * i) * row);
+      const uint16_t *z = Zx + (v0 + lr) * row + kc * 64 + lc;
+  #pragma unroll
+      for (int i = 0; i < 2; ++i) rz[i] = *reinterpret_cast<const uint4 *>(z + (int64_t)(64 * i) * row);
+    };
+    auto sstore = [&](int buf) {
+      uint16_t *B = S + buf * X_STAGE;
+  #pragma unroll
+      for (int i = 0; i < 4; ++i) *reinterpret_cast<uint4 *>(B + (lr + 64 * i) * X_LD + lc) = ra[i];
+  #pragma unroll
+      for (int i = 0; i < 2; ++i) *reinterpret_cast<uint4 *>(B + (X_BA + lr + 64 * i) * X_LD + lc) = rz[i];
+    };
 
-  if (nq > 0) {
-    gload(0);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int q = 0; q < nq; ++q) {
-    const int buf = q & 1;
-    if (q + 1 < nq) gload(q + 1);
-    const __bf16 *B = reinterpret_cast<const __bf16 *>(S) + buf * X_STAGE;
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      bf16x8 ahi[2], alo[2], zhi[2], zlo[2];
-#pragma unroll
-      for (int ma = 0; ma < 2; ++ma) {
-        const __bf16 *p = B + (wa * 64 + ma * 32 + l32) * X_LD + ks * 16 + h * 8;
-        ahi[ma] = *reinterpret_cast<const bf16x8 *>(p);
-        alo[ma] = *reinterpret_cast<const bf16x8 *>(p + 32);
-      }
-#pragma unroll
-      for (int nv = 0; nv < 2; ++nv) {
-        const __bf16 *p = B + (X_BA + wv * 64 + nv * 32 + l32) * X_LD + ks * 16 + h * 8;
-        zhi[nv] = *reinterpret_cast<const bf16x8 *>(p);
-        zlo[nv] = *reinterpret_cast<const bf16x8 *>(p + 32);
-      }
-#pragma unroll
-      for (int ma = 0; ma < 2; ++ma)
-#pragma unroll
-        for (int nv = 0; nv < 2; ++nv) {
-          acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[ma], zhi[nv], acc[ma][nv], 0, 0, 0);
-          acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[ma], zlo[nv], acc[ma][nv], 0, 0, 0);
-          acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[ma], zhi[nv], acc[ma][nv], 0, 0, 0);
-        }
+    f32x16 acc[2][2];
+  #pragma unroll
+    for (int a = 0; a < 2; ++a)
+  #pragma unroll
+      for (int b = 0; b < 2; ++b)
+  #pragma unroll
+        for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+    float best[2] = {-INFINITY, -INFINITY};
+    int bidx[2] = {-1, -1};
+
+    if (nq > 0) {
+      gload(0);
+      sstore(0);
     }
-    const int kc = q % nkc;
-    if (kc == nkc - 1) {
-      // fold this atom tile: 32 atom rows per voxel column and tile
-      const int abase = (tb + q / nkc) * X_BA + wa * 64;
-#pragma unroll
-      for (int nv = 0; nv < 2; ++nv)
-#pragma unroll
-        for (int ma = 0; ma < 2; ++ma)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-            const float sc = acc[ma][nv][i];
-            if (j < d && sc > best[nv]) {  // atoms in increasing order: '>' keeps the lowest index
-              best[nv] = sc;
-              bidx[nv] = j;
-            }
-          }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
-    }
-    if (q + 1 < nq) sstore(buf ^ 1);
     __syncthreads();
-  }
-  // the two half-waves, then the four atom-row waves of each voxel column
-#pragma unroll
-  for (int nv = 0; nv < 2; ++nv) {
-    const float ps = __shfl_xor(best[nv], 32, 64);
-    const int pj = __shfl_xor(bidx[nv], 32, 64);
-    if (xbetter(ps, pj, best[nv], bidx[nv])) {
-      best[nv] = ps;
-      bidx[nv] = pj;
-    }
-    if (h == 0) {
-      rs[wa][wv * 64 + nv * 32 + l32] = best[nv];
-      rj[wa][wv * 64 + nv * 32 + l32] = bidx[nv];
-    }
-  }
-  __syncthreads();
-  if (tid < X_BV) {
-    float bs = rs[0][tid];
-    int bj = rj[0][tid];
-    for (int w = 1; w < 4; ++w)
-      if (xbetter(rs[w][tid], rj[w][tid], bs, bj)) {
-        bs = rs[w][tid];
-        bj = rj[w][tid];
+    for (int q = 0; q < nq; ++q) {
+      const int buf = q & 1;
+      if (q + 1 < nq) gload(q + 1);
+      const __bf16 *B = reinterpret_cast<const __bf16 *>(S) + buf * X_STAGE;
+  #pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        bf16x8 ahi[2], alo[2], zhi[2], zlo[2];
+  #pragma unroll
+        for (int ma = 0; ma < 2; ++ma) {
+          const __bf16 *p = B + (wa * 64 + ma * 32 + l32) * X_LD + ks * 16 + h * 8;
+          ahi[ma] = *reinterpret_cast<const bf16x8 *>(p);
+          alo[ma] = *reinterpret_cast<const bf16x8 *>(p + 32);
+        }
+  #pragma unroll
+        for (int nv = 0; nv < 2; ++nv) {
+          const __bf16 *p = B + (X_BA + wv * 64 + nv * 32 + l32) * X_LD + ks * 16 + h * 8;
+          zhi[nv] = *reinterpret_cast<const bf16x8 *>(p);
+          zlo[nv] = *reinterpret_cast<const bf16x8 *>(p + 32);
+        }
+  #pragma unroll
+        for (int ma = 0; ma < 2; ++ma)
+  #pragma unroll
+          for (int nv = 0; nv < 2; ++nv) {
+            acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[ma], zhi[nv], acc[ma][nv], 0, 0, 0);
+            acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[ma], zlo[nv], acc[ma][nv], 0, 0, 0);
+            acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[ma], zhi[nv], acc[ma][nv], 0, 0, 0);
+          }
       }
-    const int64_t v = v0 + tid;
-    if (v < n) {
-      part_s[(int64_t)split * n + v] = bs;
-      part_j[(int64_t)split * n + v] = bj;
+      const int kc = q % nkc;
+      if (kc == nkc - 1) {
+        // fold this atom tile: 32 atom rows per voxel column and tile
+        const int abase = (tb + q / nkc) * X_BA + wa * 64;
+  #pragma unroll
+        for (int nv = 0; nv < 2; ++nv)
+  #pragma unroll
+          for (int ma = 0; ma < 2; ++ma)
+  #pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+              const float sc = acc[ma][nv][i];
+              if (j < d && sc > best[nv]) {  // atoms in increasing order: '>' keeps the lowest index
+                best[nv] = sc;
+                bidx[nv] = j;
+              }
+            }
+  #pragma unroll
+        for (int a = 0; a < 2; ++a)
+  #pragma unroll
+          for (int b = 0; b < 2; ++b)
+  #pragma unroll
+            for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+      }
+      if (q + 1 < nq) sstore(buf ^ 1);
+      __syncthreads();
     }
+    // the two half-waves, then the four atom-row waves of each voxel column
+  #pragma unroll
+    for (int nv = 0; nv < 2; ++nv) {
+      const float ps = __shfl_xor(best[nv], 32, 64);
+      const int pj = __shfl_xor(bidx[nv], 32, 64);
+      if (xbetter(ps, pj, best[nv], bidx[nv])) {
+        best[nv] = ps;
+        bidx[nv] = pj;
+      }
+      if (h == 0) {
+        rs[wa][wv * 64 + nv * 32 + l32] = best[nv];
+        rj[wa][wv * 64 + nv * 32 + l32] = bidx[nv];
+      }
+    }
+    __syncthreads();
+    if (tid < X_BV) {
+      float bs = rs[0][tid];
+      int bj = rj[0][tid];
+      for (int w = 1; w < 4; ++w)
+        if (xbetter(rs[w][tid], rj[w][tid], bs, bj)) {
+          bs = rs[w][tid];
+          bj = rj[w][tid];
+        }
+      const int64_t v = v0 + tid;
+      if (v < nvox) {
+        part_s[(int64_t)split * pstride + v] = bs;
+        part_j[(int64_t)split * pstride + v] = bj;
+      }
+    }
+    __syncthreads();  // the next item reuses the LDS buffers and the reduction arrays
   }
 }
 
@@ -180,7 +199,16 @@ void launch_score_x3(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pa
   const int64_t nvt8 = (nvt + 7) / 8 * 8;
   const int64_t blocks = nvt8 * splits;
   hipLaunchKernelGGL(k_score_x3, dim3((unsigned)blocks), dim3(512), 0, s, Dx, Zx, d, ntiles, n, nvt, Kx, splits, tps,
-                     part_s, part_j);
+                     part_s, part_j, nullptr, n);
+}
+
+void launch_score_x3_dev(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t cap,
+                         const unsigned int *dcnt, int Kx, float *part_s, int *part_j, hipStream_t s) {
+  if (cap <= 0) return;
+  const int ntiles = (int)(d_pad / X_BA);
+  // one block per CU of the 256, each looping over the work items
+  hipLaunchKernelGGL(k_score_x3, dim3(256), dim3(512), 0, s, Dx, Zx, d, ntiles, cap, 0, Kx, 1, ntiles, part_s,
+                     part_j, dcnt, cap);
 }
 
 }  // namespace mrf

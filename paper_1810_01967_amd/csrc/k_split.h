@@ -22,4 +22,13 @@ __device__ __forceinline__ void split_bf16(float x, uint16_t &hi, uint16_t &lo) 
 // element offset of column k of a split row (hi; the lo value is 32 further)
 __device__ __forceinline__ int64_t split_off(int k) { return (int64_t)(k >> 5) * 64 + (k & 31); }
 
+// Atom splits of the split-BF16 exhaustive filter when its voxel count is only
+// known on the device (nvt tiles of 128 voxels, ntiles tiles of 256 atoms):
+// about 1,024 work items, at most 64 splits and one split per atom tile.
+__device__ __forceinline__ int x3_device_splits(int nvt, int ntiles) {
+  const int nvt8 = (nvt + 7) / 8 * 8;
+  const int s = nvt8 > 0 ? (1024 + nvt8 - 1) / nvt8 : 1;
+  return max(1, min(s, min(ntiles, 64)));
+}
+
 }  // namespace mrf

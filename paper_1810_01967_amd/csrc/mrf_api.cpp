@@ -895,7 +895,8 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
   TRY(residual_and_gradient(D, A, cur, Yc, false, s));
   TRY(read_scalars(D, 4, s));
   double f = D->host_scal[3];
-  const int64_t fallback_start = D->fallback_total;
+  int64_t fallback_start = 0;
+  if (stats) TRY(read_fallback_total(D, s, &fallback_start));
   if (stats) {
     stats->iters = 0;
     stats->total_shrinks = 0;
@@ -966,7 +967,9 @@ extern "C" mrf_status mrf_ipg_solve(mrf_dict D, const mrf_op *A, const void *Y,
       }
       stats->iters = k + 1;
       stats->total_shrinks += shrinks;
-      stats->fallbacks = D->fallback_total - fallback_start;
+      int64_t fallback_now = 0;
+      TRY(read_fallback_total(D, s, &fallback_now));
+      stats->fallbacks = fallback_now - fallback_start;
       unsigned long long evals = 0;
       HIP_TRY(hipMemcpyAsync(&evals, D->ts_evals.p, 8, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));

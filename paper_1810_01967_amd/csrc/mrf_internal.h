@@ -258,6 +258,11 @@ void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys
 // launch_merge_argmax like the FP32 filter.
 void launch_score_x3(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t n, int64_t n_pad,
                      int Kx, int splits, float *part_s, int *part_j, hipStream_t s);
+// The same filter over the first *dcnt (<= cap) rows of Zx ([round_up(cap,
+// 128)][2 Kx]), the count read on the device: one block per CU loops over the
+// (voxel tile, atom split) items; partial results at part[split * cap + i].
+void launch_score_x3_dev(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t cap,
+                         const unsigned int *dcnt, int Kx, float *part_s, int *part_j, hipStream_t s);
 // BF16 inference of a hidden-256 network (layer 1 writes BF16 H1 [B][256],
 // layer 2 fuses the output layer into Y [B][P]).
 void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t *dst, int ldd, hipStream_t s);
@@ -278,8 +283,15 @@ void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_
                             float thr, int32_t *out, unsigned int *count, hipStream_t s);
 void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cnt, int64_t cnt_pad,
                         float *out, hipStream_t s);
+// rows list[i] for i < *dcnt (<= cap), zero rows up to the next multiple of 128
+void launch_gather_rows_dev(const float *Zp, int Kp, const int32_t *list, int64_t cap, const unsigned int *dcnt,
+                            float *out, hipStream_t s);
+void launch_add_count(unsigned long long *total, const unsigned int *count, hipStream_t s);
+// With dcnt: cnt is the capacity (also the part stride) and the splits are
+// those launch_score_x3_dev chose for the device count (ntiles = d_pad / 256).
 void launch_scatter_best(const int32_t *list, int64_t cnt, const float *part_s, const int *part_j,
-                         int splits, float *best_s, int32_t *best_j, hipStream_t s);
+                         int splits, float *best_s, int32_t *best_j, hipStream_t s,
+                         const unsigned int *dcnt = nullptr, int ntiles = 0);
 void launch_iota(int32_t *x, int64_t n, hipStream_t s);
 }  // namespace mrf
 

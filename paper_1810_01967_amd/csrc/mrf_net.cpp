@@ -461,7 +461,8 @@ extern "C" mrf_status mrf_net_train(mrf_net net, mrf_dict D, const mrf_train_opt
 // ---------------------------------------------------------------------------
 namespace mrf {
 
-void launch_mark(const int32_t *list, int64_t cnt, int32_t *flags, hipStream_t s);
+void launch_mark(const int32_t *list, int64_t cnt, int32_t *flags, hipStream_t s,
+                 const unsigned int *dcnt = nullptr);
 
 mrf_status check_learned(const mrf_dict_s *D, const mrf_match_opts *o, bool need_net) {
   if (D->grid_dims.empty()) return fail(MRF_E_UNSUPPORTED, "local search needs a product-grid dictionary (grid_dims)");
@@ -479,6 +480,25 @@ mrf_status check_learned(const mrf_dict_s *D, const mrf_match_opts *o, bool need
                   o->net->I, o->net->P, D->K, D->nparam);
     if (!o->net->has_std) return fail(MRF_E_INVAL, "network has no target standardisation (train it first)");
   }
+  return MRF_OK;
+}
+
+// The device counter of fallback voxels (all calls), created zeroed.
+mrf_status fallback_total_buf(mrf_dict_s *D, hipStream_t s) {
+  if (D->fbtot.p) return MRF_OK;
+  TRY(grow(D->fbtot, 64));
+  launch_zero(D->fbtot.p, 8, s);
+  LAUNCH_CHECK("fallback counter");
+  return MRF_OK;
+}
+
+mrf_status read_fallback_total(mrf_dict_s *D, hipStream_t s, int64_t *out) {
+  *out = 0;
+  if (!D->fbtot.p) return MRF_OK;
+  unsigned long long v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, D->fbtot.p, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = (int64_t)v;
   return MRF_OK;
 }
 
@@ -631,16 +651,38 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   bool tree_ran = false;
   if (fallback_out) launch_zero(fallback_out, n * 4, s);
   if (st) HIP_TRY(hipEventRecord(ev.c, s));
+  bool nfb_on_device = false;  // the fallback count stayed on the device (read back only for stats)
+  unsigned int *count = D->cnt.as<unsigned int>();
   if (thr >= 0.f) {
-    unsigned int *count = D->cnt.as<unsigned int>();
     launch_zero(count, 4, s);
     launch_select_fallback(n, D->best_s.as<float>(), D->best_j.as<int32_t>(), D->znorm.as<float>(), thr,
                            la, count, s);
+    TRY(fallback_total_buf(D, s));
+    launch_add_count(D->fbtot.as<unsigned long long>(), count, s);
+    const bool tree_fb = D->has_tree && o->eps >= 0.f;
+    if (x3 && !tree_fb) {
+      // split-BF16 exhaustive fallback sized on the device (gather, filter and
+      // merge read the count there): the host does not wait for the count
+      const int64_t n_pad = round_up(n, kRowPad);
+      TRY(grow(D->rows, (size_t)n_pad * D->Kx * 4));
+      TRY(grow(D->part_s, (size_t)64 * n * 4));
+      TRY(grow(D->part_j, (size_t)64 * n * 4));
+      launch_gather_rows_dev(reinterpret_cast<const float *>(D->zx3.p), D->Kx, la, n, count, D->rows.as<float>(),
+                             s);
+      launch_score_x3_dev(D->dx3.as<uint16_t>(), D->rows.as<uint16_t>(), D->d, D->d_pad, n, count, D->Kx,
+                          D->part_s.as<float>(), D->part_j.as<int>(), s);
+      launch_scatter_best(la, n, D->part_s.as<float>(), D->part_j.as<int>(), 1, D->best_s.as<float>(),
+                          D->best_j.as<int32_t>(), s, count, (int)(D->d_pad / 256));
+      if (fallback_out) launch_mark(la, n, fallback_out, s, count);
+      LAUNCH_CHECK("fallback (sized on the device)");
+      nfb_on_device = true;
+    }
+  }
+  if (thr >= 0.f && !nfb_on_device) {
     unsigned int hc = 0;
     HIP_TRY(hipMemcpyAsync(&hc, count, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     nfb = hc;
-    D->fallback_total += nfb;
     if (nfb > 0 && D->has_tree && o->eps >= 0.f) {
       // the cover tree (Algorithm 1, inaccuracy eps; eps = 0 is exact)
       // warm-started at each voxel's local best, on the FP32 rows
@@ -703,12 +745,13 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   LAUNCH_CHECK("merge");
   if (st) {
     unsigned long long wk[2] = {0, 0}, ev_count = 0;
-    unsigned int rc[16] = {0};
+    unsigned int rc[16] = {0}, dev_nfb = 0;
     HIP_TRY(hipMemcpyAsync(wk, work, 16, hipMemcpyDeviceToHost, s));
+    if (nfb_on_device) HIP_TRY(hipMemcpyAsync(&dev_nfb, count, 4, hipMemcpyDeviceToHost, s));
     if (o->recentre > 0) HIP_TRY(hipMemcpyAsync(rc, rcount, 4 * o->recentre, hipMemcpyDeviceToHost, s));
     if (tree_ran) HIP_TRY(hipMemcpyAsync(&ev_count, D->ts_evals.p, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    st->fallbacks = nfb;
+    st->fallbacks = nfb_on_device ? (int64_t)dev_nfb : nfb;
     int64_t recentred = 0;
     for (int rd = 0; rd < o->recentre; ++rd) recentred += rc[rd];
     st->recentred = recentred;
