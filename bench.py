@@ -116,29 +116,28 @@ def main():
     flops = 2.0 * n * d * K               # algorithmic: one real MAC per (voxel, atom, real dim)
 
     def run(steps, warmup, D_=None, **kw):
-        """Time `steps` calls.  Per-call statistics (device-event stage and
-        kernel times) force a stream synchronisation, so only the last
-        min(3, steps) calls of the timed region request them; their kernel
-        times are averaged."""
+        """Time `steps` calls as a caller makes them (no per-call statistics:
+        those record device events and read them back, which synchronises the
+        stream).  Three more calls after the timed region request the
+        statistics (stage and kernel times, counts); they are averaged."""
         DD = D if D_ is None else D_
         o = {}
         for _ in range(warmup):
             o = m.mrf_match(DD, Zd, atom_splits=args.splits, want_corr=False, out=o, **kw)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        st = []
-        nstat = min(3, steps)
         ev0.record()
-        for i in range(steps):
-            want = i >= steps - nstat
-            o = m.mrf_match(DD, Zd, atom_splits=args.splits, want_corr=False, out=o, stats=want, **kw)
-            if want:
-                s = o["stats"]
-                st.append((s.score_ms, s.proposal_ms, s.fallback_ms, s.fallbacks, s.recentred, s.local_atoms,
-                           s.search_ms, s.first_box_atoms))
+        for _ in range(steps):
+            o = m.mrf_match(DD, Zd, atom_splits=args.splits, want_corr=False, out=o, **kw)
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / steps
+        st = []
+        for _ in range(3):
+            o = m.mrf_match(DD, Zd, atom_splits=args.splits, want_corr=False, out=o, stats=True, **kw)
+            s = o["stats"]
+            st.append((s.score_ms, s.proposal_ms, s.fallback_ms, s.fallbacks, s.recentred, s.local_atoms,
+                       s.search_ms, s.first_box_atoms))
         return ms, np.mean(np.array(st, dtype=np.float64), axis=0), o
 
     ms32, st32, o32 = run(args.steps, args.warmup, precision="fp32")
