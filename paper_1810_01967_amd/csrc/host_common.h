@@ -177,6 +177,8 @@ struct mrf_net_s {
   mrf::DevBuf a1, hb1, a2, hb2, y, dy, da, db, X, T, red, scal;
   mrf::DevBuf gpart;  // split-K partial sums of the weight gradients
   mrf::DevBuf wb;     // BF16 copies of W1 [H][round_up(I, 32)] and W2 [H][H] for inference
+  uint64_t wver = 1;  // bumped by every write of w
+  uint64_t wbver = 0; // the w version wb was made from
   double *host_scal = nullptr;
   ~mrf_net_s() {
     if (host_scal) (void)hipHostFree(host_scal);

@@ -46,49 +46,47 @@ __global__ void k_coarse_keys(const int32_t *__restrict__ list, int64_t cnt, con
   atomicAdd(&hist[key], 1u);
 }
 
-// Exclusive scans of hist[0..nkeys) (one block, chunks of 1024): off[k] (the
-// first sorted position of key k), cursor[k] = off[k] (consumed by the
-// scatter), and toff[k] = the first tile of key k, where key k owns
-// ceil(hist[k] / 64) tiles; toff[nkeys] = the number of tiles.
+// Exclusive scans of hist[0..nkeys) (one block): off[k] (the first sorted
+// position of key k), cursor[k] = off[k] (consumed by the scatter), and
+// toff[k] = the first tile of key k, where key k owns ceil(hist[k] / 64)
+// tiles; toff[nkeys] = the number of tiles.  Thread t sums its own run of
+// consecutive keys, one block-wide scan of the 1,024 run sums gives each run's
+// start, and the thread writes its run's prefixes.
 __global__ __launch_bounds__(1024) void k_scan(const unsigned int *__restrict__ hist, int nkeys,
                                                unsigned int *__restrict__ off,
                                                unsigned int *__restrict__ cursor,
                                                unsigned int *__restrict__ toff) {
   __shared__ unsigned int buf[1024], tbuf[1024];
-  __shared__ unsigned int carry, tcarry;
-  if (threadIdx.x == 0) {
-    carry = 0;
-    tcarry = 0;
+  const int t = threadIdx.x;
+  const int per = (nkeys + 1023) / 1024;
+  const int b = min(t * per, nkeys), e = min(b + per, nkeys);
+  unsigned int sum = 0, tsum = 0;
+  for (int i = b; i < e; ++i) {
+    const unsigned int x = hist[i];
+    sum += x;
+    tsum += (x + 63u) / 64u;
   }
+  buf[t] = sum;
+  tbuf[t] = tsum;
   __syncthreads();
-  for (int base = 0; base < nkeys; base += 1024) {
-    const int i = base + threadIdx.x;
-    const unsigned int x = i < nkeys ? hist[i] : 0u;
-    const unsigned int tx = (x + 63u) / 64u;
-    buf[threadIdx.x] = x;
-    tbuf[threadIdx.x] = tx;
+  for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan of the run sums
+    const unsigned int y = t >= o ? buf[t - o] : 0u;
+    const unsigned int ty = t >= o ? tbuf[t - o] : 0u;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const unsigned int y = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0u;
-      const unsigned int ty = threadIdx.x >= (unsigned)o ? tbuf[threadIdx.x - o] : 0u;
-      __syncthreads();
-      buf[threadIdx.x] += y;
-      tbuf[threadIdx.x] += ty;
-      __syncthreads();
-    }
-    if (i < nkeys) {
-      off[i] = carry + buf[threadIdx.x] - x;
-      cursor[i] = off[i];
-      toff[i] = tcarry + tbuf[threadIdx.x] - tx;
-    }
-    __syncthreads();
-    if (threadIdx.x == 1023) {
-      carry += buf[1023];
-      tcarry += tbuf[1023];
-    }
+    buf[t] += y;
+    tbuf[t] += ty;
     __syncthreads();
   }
-  if (threadIdx.x == 0) toff[nkeys] = tcarry;
+  unsigned int run = buf[t] - sum, trun = tbuf[t] - tsum;
+  for (int i = b; i < e; ++i) {
+    const unsigned int x = hist[i];
+    off[i] = run;
+    cursor[i] = run;
+    toff[i] = trun;
+    run += x;
+    trun += (x + 63u) / 64u;
+  }
+  if (t == 1023) toff[nkeys] = tbuf[1023];
 }
 
 __global__ void k_group_scatter(const int32_t *__restrict__ list, const int32_t *__restrict__ keys,
@@ -705,8 +703,10 @@ void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cn
 // zero rows up to the next multiple of 128 (the voxel tile of the split-BF16
 // filter); a grid-stride loop, so the grid does not depend on the count.
 __global__ void k_gather_rows_dev(const float *__restrict__ Zp, int Kp, const int32_t *__restrict__ list,
-                                  int64_t cap, const unsigned int *__restrict__ dcnt, float *__restrict__ out) {
+                                  int64_t cap, const unsigned int *__restrict__ dcnt, float *__restrict__ out,
+                                  unsigned long long *__restrict__ total) {
   const int64_t c = min(cap, (int64_t)*dcnt);
+  if (total && blockIdx.x == 0 && threadIdx.x == 0) *total += *dcnt;
   const int64_t rows = (c + 127) / 128 * 128;
   for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
     const float4 *src = i < c ? reinterpret_cast<const float4 *>(Zp + (int64_t)list[i] * Kp) : nullptr;
@@ -717,9 +717,9 @@ __global__ void k_gather_rows_dev(const float *__restrict__ Zp, int Kp, const in
 }
 
 void launch_gather_rows_dev(const float *Zp, int Kp, const int32_t *list, int64_t cap, const unsigned int *dcnt,
-                            float *out, hipStream_t s) {
+                            float *out, hipStream_t s, unsigned long long *total) {
   if (cap <= 0) return;
-  hipLaunchKernelGGL(k_gather_rows_dev, dim3(1024), dim3(256), 0, s, Zp, Kp, list, cap, dcnt, out);
+  hipLaunchKernelGGL(k_gather_rows_dev, dim3(1024), dim3(256), 0, s, Zp, Kp, list, cap, dcnt, out, total);
 }
 
 // total += *count (one thread)
@@ -767,6 +767,24 @@ void launch_scatter_best(const int32_t *list, int64_t cnt, const float *part_s, 
   if (cnt <= 0) return;
   hipLaunchKernelGGL(k_scatter_best, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt,
                      part_s, part_j, splits, best_s, best_j, dcnt, ntiles);
+}
+
+// Start of a learned call: list[i] = i and key[i] = 0 for i < n, and the
+// first nz words of z set to zero (work counters).
+__global__ void k_learned_prep(int32_t *__restrict__ list, unsigned long long *__restrict__ keys, int64_t n,
+                               unsigned int *__restrict__ z, int nz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    list[i] = (int32_t)i;
+    keys[i] = 0ull;
+  }
+  if (i < nz) z[i] = 0u;
+}
+
+void launch_learned_prep(int32_t *list, unsigned long long *keys, int64_t n, unsigned int *z, int nz, hipStream_t s) {
+  const int64_t m = std::max<int64_t>(n, nz);
+  if (m > 0)
+    hipLaunchKernelGGL(k_learned_prep, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, list, keys, n, z, nz);
 }
 
 __global__ void k_iota(int32_t *x, int64_t n) {

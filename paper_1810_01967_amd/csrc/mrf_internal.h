@@ -283,9 +283,12 @@ void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_
                             float thr, int32_t *out, unsigned int *count, hipStream_t s);
 void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cnt, int64_t cnt_pad,
                         float *out, hipStream_t s);
-// rows list[i] for i < *dcnt (<= cap), zero rows up to the next multiple of 128
+// rows list[i] for i < *dcnt (<= cap), zero rows up to the next multiple of
+// 128; total (device, may be null) += *dcnt
 void launch_gather_rows_dev(const float *Zp, int Kp, const int32_t *list, int64_t cap, const unsigned int *dcnt,
-                            float *out, hipStream_t s);
+                            float *out, hipStream_t s, unsigned long long *total = nullptr);
+// list[i] = i, keys[i] = 0 for i < n; z[0..nz) = 0
+void launch_learned_prep(int32_t *list, unsigned long long *keys, int64_t n, unsigned int *z, int nz, hipStream_t s);
 void launch_add_count(unsigned long long *total, const unsigned int *count, hipStream_t s);
 // With dcnt: cnt is the capacity (also the part stride) and the splits are
 // those launch_score_x3_dev chose for the device count (ntiles = d_pad / 256).

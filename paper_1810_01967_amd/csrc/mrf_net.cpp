@@ -200,6 +200,7 @@ extern "C" mrf_status mrf_net_create(int32_t in_dim, int32_t hidden, int32_t nou
   fill(net->oW2, (int64_t)hidden * hidden, hidden);
   fill(net->oW3, (int64_t)nout * hidden, hidden);
   HIP_TRY(hipMemcpy(net->w.p, h.data(), net->nw * 4, hipMemcpyHostToDevice));
+  ++net->wver;
   HIP_TRY(hipMemset(net->g.p, 0, net->nw * 4));
   HIP_TRY(hipMemset(net->m.p, 0, net->nw * 4));
   HIP_TRY(hipMemset(net->v.p, 0, net->nw * 4));
@@ -243,6 +244,7 @@ static mrf_status net_copy(mrf_net net, float *host, const float *src_host, int6
 extern "C" mrf_status mrf_net_set_params(mrf_net net, const float *host, int64_t count) {
   last_error().clear();
   TRY(net_copy(net, nullptr, host, count, net->w, true));
+  ++net->wver;
   return MRF_OK;
 }
 extern "C" mrf_status mrf_net_get_params(mrf_net net, float *host, int64_t count) {
@@ -308,8 +310,15 @@ mrf_status net_forward_bf16(mrf_net_s *net, const float *X, int64_t ldx, int64_t
   TRY(grow(net->wb, ((size_t)H * Kx + (size_t)H * H) * 2));
   const float *w = net->w.as<float>();
   uint16_t *w1b = net->wb.as<uint16_t>(), *w2b = w1b + (size_t)H * Kx;
-  launch_to_bf16(w + net->oW1, H, I, I, w1b, Kx, s);
-  launch_to_bf16(w + net->oW2, H, H, H, w2b, H, s);
+  if (net->wbver != net->wver) {
+    // BF16 weights made once per weight version; the wait lets later calls
+    // on any stream use them
+    launch_to_bf16(w + net->oW1, H, I, I, w1b, Kx, s);
+    launch_to_bf16(w + net->oW2, H, H, H, w2b, H, s);
+    LAUNCH_CHECK("network weights to bf16");
+    HIP_TRY(hipStreamSynchronize(s));
+    net->wbver = net->wver;
+  }
   launch_mlp_bf16(B, X, ldx, (int)K, Kx, rowscale, w1b, w + net->ob1, h1, w2b, w + net->ob2, w + net->oW3,
                   w + net->ob3, net->P, Y, s);
   LAUNCH_CHECK("net forward (bf16)");
@@ -358,6 +367,7 @@ extern "C" mrf_status mrf_net_adam(mrf_net net, float lr, float beta1, float bet
   if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
     return fail(MRF_E_INVAL, "mrf_net_adam: bad hyper-parameters");
   net->t += 1;
+  ++net->wver;
   launch_adam(net->w.as<float>(), net->g.as<float>(), net->m.as<float>(), net->v.as<float>(), net->nw,
               lr, beta1, beta2, eps, net->t, static_cast<hipStream_t>(stream));
   LAUNCH_CHECK("adam");
@@ -434,6 +444,7 @@ extern "C" mrf_status mrf_net_train(mrf_net net, mrf_dict D, const mrf_train_opt
     const double frac = (double)step / (double)std::max<int64_t>(1, total - 1);
     const float lr = (float)(o->lr_min + 0.5 * (o->lr - o->lr_min) * (1.0 + std::cos(M_PI * frac)));
     net->t += 1;
+    ++net->wver;
     launch_adam(net->w.as<float>(), net->g.as<float>(), net->m.as<float>(), net->v.as<float>(),
                 net->nw, lr, 0.9f, 0.999f, 1e-8f, net->t, s);
     LAUNCH_CHECK("train step");
@@ -593,11 +604,18 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     return b;
   };
   const GroupBufs gb = group_bufs(nkeys), gb_rc = group_bufs(nkeys_rc);
-  unsigned long long *work = D->counters.as<unsigned long long>() + 2;  // [0] scored rows, [1] first-launch boxes
-  launch_zero(work, 16, s);
+  // per-call counters, 32-bit words of D->cnt: [0] fallback count, [1..16]
+  // re-centring list lengths, [18..21] two 64-bit work counters (scored rows,
+  // first-launch box atoms); all cleared by the preparation kernel with the
+  // identity list and the per-voxel best keys
+  unsigned int *cntw = D->cnt.as<unsigned int>();
+  unsigned int *rcount = cntw + 1;
+  unsigned long long *work = reinterpret_cast<unsigned long long *>(cntw + 18);
+  TRY(grow(D->bestkey, (size_t)n * 8));
+  unsigned long long *bkey = D->bestkey.as<unsigned long long>();
   // round 0: every voxel, grouped by coarse proposal cell
   int32_t *la = D->list_a.as<int32_t>(), *lb = D->list_b.as<int32_t>(), *lc = D->list_c.as<int32_t>();
-  launch_iota(la, n, s);
+  launch_learned_prep(la, bkey, n, cntw, 22, s);
   const bool x3 = o->precision == MRF_BF16X3;
   if (x3) TRY(ensure_x3(D, s));
   if (st) HIP_TRY(hipEventRecord(ev.a, s));
@@ -611,9 +629,6 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   const int pitch = x3 ? D->Kx : D->Kp;
   launch_group(la, n, cells, P, shift, g, D->keys.as<int32_t>(), gb, lb, s);
   if (st) HIP_TRY(hipEventRecord(e_ls0, s));
-  TRY(grow(D->bestkey, (size_t)n * 8));
-  unsigned long long *bkey = D->bestkey.as<unsigned long long>();
-  launch_best_keys(nullptr, n, bkey, nullptr, nullptr, 0, s);
   launch_local_score(Dop, Zop, pitch, x3, lb, n, gb, nkeys, cells, P, g, r, shift, bkey, work, work + 1, s);
   launch_best_keys(nullptr, n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s);
   if (st) HIP_TRY(hipEventRecord(e_ls1, s));
@@ -624,8 +639,6 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   // The list lengths stay on the device (round rd's in rcount[rd]); every
   // grid is sized for all n voxels and its surplus exits at once, so the host
   // enqueues the rounds without waiting for the first launch to finish.
-  unsigned int *rcount = D->cnt.as<unsigned int>() + 1;  // [0] is the fallback count
-  if (o->recentre > 0) launch_zero(rcount, 4 * o->recentre, s);
   int32_t *prev = lb;
   const unsigned int *prev_cnt = nullptr;  // device length of prev (null: all n)
   for (int rd = 0; rd < o->recentre; ++rd) {
@@ -652,13 +665,11 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   if (fallback_out) launch_zero(fallback_out, n * 4, s);
   if (st) HIP_TRY(hipEventRecord(ev.c, s));
   bool nfb_on_device = false;  // the fallback count stayed on the device (read back only for stats)
-  unsigned int *count = D->cnt.as<unsigned int>();
+  unsigned int *count = cntw;  // cleared by the preparation kernel
   if (thr >= 0.f) {
-    launch_zero(count, 4, s);
     launch_select_fallback(n, D->best_s.as<float>(), D->best_j.as<int32_t>(), D->znorm.as<float>(), thr,
                            la, count, s);
     TRY(fallback_total_buf(D, s));
-    launch_add_count(D->fbtot.as<unsigned long long>(), count, s);
     const bool tree_fb = D->has_tree && o->eps >= 0.f;
     if (x3 && !tree_fb) {
       // split-BF16 exhaustive fallback sized on the device (gather, filter and
@@ -668,7 +679,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
       TRY(grow(D->part_s, (size_t)64 * n * 4));
       TRY(grow(D->part_j, (size_t)64 * n * 4));
       launch_gather_rows_dev(reinterpret_cast<const float *>(D->zx3.p), D->Kx, la, n, count, D->rows.as<float>(),
-                             s);
+                             s, D->fbtot.as<unsigned long long>());
       launch_score_x3_dev(D->dx3.as<uint16_t>(), D->rows.as<uint16_t>(), D->d, D->d_pad, n, count, D->Kx,
                           D->part_s.as<float>(), D->part_j.as<int>(), s);
       launch_scatter_best(la, n, D->part_s.as<float>(), D->part_j.as<int>(), 1, D->best_s.as<float>(),
@@ -679,6 +690,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     }
   }
   if (thr >= 0.f && !nfb_on_device) {
+    launch_add_count(D->fbtot.as<unsigned long long>(), count, s);
     unsigned int hc = 0;
     HIP_TRY(hipMemcpyAsync(&hc, count, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
