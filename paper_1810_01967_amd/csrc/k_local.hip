@@ -106,10 +106,10 @@ int coarse_key_count(const GridDims &g, int P, int shift) {
 
 void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P, int shift,
                   const GridDims &g, int32_t *keys, GroupBufs gb, int32_t *out, hipStream_t s,
-                  const unsigned int *dcnt) {
+                  const unsigned int *dcnt, bool hist_cleared) {
   if (cnt <= 0) return;
   const int nkeys = coarse_key_count(g, P, shift);
-  launch_zero(gb.hist, (int64_t)nkeys * 4, s);
+  if (!hist_cleared) launch_zero(gb.hist, (int64_t)nkeys * 4, s);
   const unsigned blocks = (unsigned)((cnt + 255) / 256);
   hipLaunchKernelGGL(k_coarse_keys, dim3(blocks), dim3(256), 0, s, list, cnt, dcnt, cells, P, shift, g,
                      keys, gb.hist);
@@ -632,8 +632,10 @@ void launch_warm_best(const int32_t *warm, int64_t n, int d, const float *Zp, co
 // edge, append the voxel to `recentre` and move its cell to the best atom.
 __global__ void k_face(const int32_t *__restrict__ list, int64_t cnt, const unsigned int *__restrict__ dcnt,
                        const int32_t *__restrict__ best_j, int32_t *__restrict__ cells, int P, GridDims g, int r,
-                       int32_t *__restrict__ out, unsigned int *__restrict__ count) {
+                       int32_t *__restrict__ out, unsigned int *__restrict__ count,
+                       unsigned long long *__restrict__ bkey, unsigned int *__restrict__ zero, int nzero) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nzero) zero[i] = 0u;
   if (i >= list_len(cnt, dcnt)) return;
   const int v = list[i];
   int j = best_j[v];
@@ -650,15 +652,17 @@ __global__ void k_face(const int32_t *__restrict__ list, int64_t cnt, const unsi
   }
   if (!face) return;
   for (int p = 0; p < P; ++p) cells[(int64_t)v * P + p] = sub[p];
+  if (bkey) bkey[v] = 0ull;  // its best key is searched again around the new cell
   out[atomicAdd(count, 1u)] = v;
 }
 
 void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
                  const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s,
-                 const unsigned int *dcnt) {
-  if (cnt <= 0) return;
-  hipLaunchKernelGGL(k_face, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt, dcnt, best_j,
-                     cells, P, g, r, out, count);
+                 const unsigned int *dcnt, unsigned long long *bkey, unsigned int *zero, int nzero) {
+  const int64_t m = std::max<int64_t>(cnt, nzero);
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_face, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, list, cnt, dcnt, best_j,
+                     cells, P, g, r, out, count, bkey, zero, nzero);
 }
 
 // Voxels with a finite, non-zero norm whose normalised correlation is below
@@ -770,21 +774,24 @@ void launch_scatter_best(const int32_t *list, int64_t cnt, const float *part_s, 
 }
 
 // Start of a learned call: list[i] = i and key[i] = 0 for i < n, and the
-// first nz words of z set to zero (work counters).
+// first nz words of z and nz2 words of z2 set to zero (counters, histogram).
 __global__ void k_learned_prep(int32_t *__restrict__ list, unsigned long long *__restrict__ keys, int64_t n,
-                               unsigned int *__restrict__ z, int nz) {
+                               unsigned int *__restrict__ z, int nz, unsigned int *__restrict__ z2, int nz2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     list[i] = (int32_t)i;
     keys[i] = 0ull;
   }
   if (i < nz) z[i] = 0u;
+  if (i < nz2) z2[i] = 0u;
 }
 
-void launch_learned_prep(int32_t *list, unsigned long long *keys, int64_t n, unsigned int *z, int nz, hipStream_t s) {
-  const int64_t m = std::max<int64_t>(n, nz);
+void launch_learned_prep(int32_t *list, unsigned long long *keys, int64_t n, unsigned int *z, int nz,
+                         unsigned int *z2, int nz2, hipStream_t s) {
+  const int64_t m = std::max<int64_t>(n, std::max(nz, nz2));
   if (m > 0)
-    hipLaunchKernelGGL(k_learned_prep, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, list, keys, n, z, nz);
+    hipLaunchKernelGGL(k_learned_prep, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, list, keys, n, z, nz,
+                       z2, nz2);
 }
 
 __global__ void k_iota(int32_t *x, int64_t n) {

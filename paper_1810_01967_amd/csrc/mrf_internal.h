@@ -238,7 +238,7 @@ int coarse_key_count(const GridDims &g, int P, int shift);
 // the device, bounded by cnt, which then only sizes the grid.
 void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P, int shift,
                   const GridDims &g, int32_t *keys, GroupBufs gb, int32_t *out, hipStream_t s,
-                  const unsigned int *dcnt = nullptr);
+                  const unsigned int *dcnt = nullptr, bool hist_cleared = false);
 // Local search over the grouped list: one block per tile of <= 64 voxels of
 // one coarse key.  x3 = false: FP32 rows of pitch `pitch`; x3 = true:
 // split-BF16 rows of pitch/32 chunks [hi 32 | lo 32].
@@ -276,9 +276,12 @@ void launch_unsplit_x3(const uint16_t *src, int64_t rows, int Kx, int K, uint16_
 // best <- the warm atom where it scores higher (ties: lower index).
 void launch_warm_best(const int32_t *warm, int64_t n, int d, const float *Zp, const float *Dhat, int Kp,
                       const float *znorm, float *best_s, int32_t *best_j, hipStream_t s);
+// Also resets the best key of each voxel it lists (bkey, may be null) and
+// clears zero[0..nzero) (the next grouping's histogram).
 void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
                  const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s,
-                 const unsigned int *dcnt = nullptr);
+                 const unsigned int *dcnt = nullptr, unsigned long long *bkey = nullptr,
+                 unsigned int *zero = nullptr, int nzero = 0);
 void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,
                             float thr, int32_t *out, unsigned int *count, hipStream_t s);
 void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cnt, int64_t cnt_pad,
@@ -287,8 +290,9 @@ void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cn
 // 128; total (device, may be null) += *dcnt
 void launch_gather_rows_dev(const float *Zp, int Kp, const int32_t *list, int64_t cap, const unsigned int *dcnt,
                             float *out, hipStream_t s, unsigned long long *total = nullptr);
-// list[i] = i, keys[i] = 0 for i < n; z[0..nz) = 0
-void launch_learned_prep(int32_t *list, unsigned long long *keys, int64_t n, unsigned int *z, int nz, hipStream_t s);
+// list[i] = i, keys[i] = 0 for i < n; z[0..nz) = 0, z2[0..nz2) = 0
+void launch_learned_prep(int32_t *list, unsigned long long *keys, int64_t n, unsigned int *z, int nz,
+                         unsigned int *z2, int nz2, hipStream_t s);
 void launch_add_count(unsigned long long *total, const unsigned int *count, hipStream_t s);
 // With dcnt: cnt is the capacity (also the part stride) and the splits are
 // those launch_score_x3_dev chose for the device count (ntiles = d_pad / 256).

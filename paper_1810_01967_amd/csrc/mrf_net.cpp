@@ -615,7 +615,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   unsigned long long *bkey = D->bestkey.as<unsigned long long>();
   // round 0: every voxel, grouped by coarse proposal cell
   int32_t *la = D->list_a.as<int32_t>(), *lb = D->list_b.as<int32_t>(), *lc = D->list_c.as<int32_t>();
-  launch_learned_prep(la, bkey, n, cntw, 22, s);
+  launch_learned_prep(la, bkey, n, cntw, 22, gb.hist, nkeys, s);
   const bool x3 = o->precision == MRF_BF16X3;
   if (x3) TRY(ensure_x3(D, s));
   if (st) HIP_TRY(hipEventRecord(ev.a, s));
@@ -627,7 +627,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   const void *Dop = x3 ? D->dx3.p : D->dhat.p;
   const void *Zop = x3 ? D->zx3.p : D->zp.p;
   const int pitch = x3 ? D->Kx : D->Kp;
-  launch_group(la, n, cells, P, shift, g, D->keys.as<int32_t>(), gb, lb, s);
+  launch_group(la, n, cells, P, shift, g, D->keys.as<int32_t>(), gb, lb, s, nullptr, true);
   if (st) HIP_TRY(hipEventRecord(e_ls0, s));
   launch_local_score(Dop, Zop, pitch, x3, lb, n, gb, nkeys, cells, P, g, r, shift, bkey, work, work + 1, s);
   launch_best_keys(nullptr, n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s);
@@ -643,10 +643,12 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   const unsigned int *prev_cnt = nullptr;  // device length of prev (null: all n)
   for (int rd = 0; rd < o->recentre; ++rd) {
     unsigned int *count = rcount + rd;
-    launch_face(prev, n, D->best_j.as<int32_t>(), cells, P, g, r, lc, count, s, prev_cnt);
+    // the face test also resets the listed voxels' best keys and clears the
+    // histogram of the grouping that follows
+    launch_face(prev, n, D->best_j.as<int32_t>(), cells, P, g, r, lc, count, s, prev_cnt, bkey, gb_rc.hist,
+                nkeys_rc);
     int32_t *sorted = (prev == lb) ? la : lb;
-    launch_group(lc, n, cells, P, shift_rc, g, D->keys.as<int32_t>(), gb_rc, sorted, s, count);
-    launch_best_keys(sorted, n, bkey, nullptr, nullptr, 0, s, count);
+    launch_group(lc, n, cells, P, shift_rc, g, D->keys.as<int32_t>(), gb_rc, sorted, s, count, true);
     launch_local_score(Dop, Zop, pitch, x3, sorted, n, gb_rc, nkeys_rc, cells, P, g, r, shift_rc, bkey, work,
                        nullptr, s);
     launch_best_keys(sorted, n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s, count);
