@@ -341,3 +341,36 @@ def test_learned_with_cover_tree_fallback(m, precision):
     same = ia == g["idx"]
     assert same.mean() > 0.99
     np.testing.assert_allclose(host(oa["pd"])[same], g["gamma"][same], rtol=1e-4, atol=1e-6)
+
+
+@pytest.mark.parametrize("n", [3000, 257])
+def test_device_sized_fallback_equals_exhaustive(m, n):
+    """The split-BF16 fallback reads its voxel count on the device (no host
+    read-back): with every voxel sent to it (threshold above 1) the learned
+    path returns exactly the exhaustive split-BF16 filter's answers (the same
+    scores, merged over any number of atom splits with the lowest index
+    winning ties), for ragged voxel counts; with none sent, the fallback
+    changes nothing."""
+    banner(f"device-sized split-BF16 fallback, n={n}")
+    Dd = workloads.bssfp_dictionary(L=100, n_t1=20, n_t2=20, n_df=9, seed=2)
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    net = m.Net(2 * Dd.L, 3, hidden=128, seed=5)
+    m.mrf_net_train(net, D, samples=100_000, batch=2048, epochs=1, lr=1e-3, lr_min=1e-5, snr_lo=20.0, snr_hi=40.0,
+                    seed=6)
+    Z, jt, pd, snr = workloads.random_voxels(Dd, n, seed=13, snr_db_range=(0.0, 30.0))
+    Zd = dev(c64(Z))
+    ex = m.mrf_match(D, Zd, precision="bf16x3")
+    for rep in range(2):  # the second call reuses the device buffers
+        oa = m.mrf_match(D, Zd, net=net, precision="bf16x3", recentre=1, fallback_corr=2.0, stats=True)
+        assert oa["stats"].fallbacks == n
+        np.testing.assert_array_equal(host(oa["idx"]), host(ex["idx"]))
+        np.testing.assert_array_equal(host(oa["pd"]), host(ex["pd"]))
+    on = m.mrf_match(D, Zd, net=net, precision="bf16x3", recentre=1, fallback_corr=-1.0, stats=True)
+    assert on["stats"].fallbacks == 0
+    o9 = m.mrf_match(D, Zd, net=net, precision="bf16x3", recentre=1, fallback_corr=0.98, stats=True)
+    fb = o9["stats"].fallbacks
+    print(f"fallbacks at 0.98: {fb} of {n}")
+    assert 0 < fb < n
+    i9, ion, iex = host(o9["idx"]), host(on["idx"]), host(ex["idx"])
+    # every voxel either keeps its local answer or takes the exhaustive one
+    assert np.all((i9 == ion) | (i9 == iex))
