@@ -704,14 +704,14 @@ void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cn
 }
 
 // Rows list[i] of Zp (pitch Kp floats) into out[i] for i < the device count,
-// zero rows up to the next multiple of 128 (the voxel tile of the split-BF16
-// filter); a grid-stride loop, so the grid does not depend on the count.
+// zero rows up to the next whole voxel tile of the split-BF16 filter; a
+// grid-stride loop, so the grid does not depend on the count.
 __global__ void k_gather_rows_dev(const float *__restrict__ Zp, int Kp, const int32_t *__restrict__ list,
                                   int64_t cap, const unsigned int *__restrict__ dcnt, float *__restrict__ out,
                                   unsigned long long *__restrict__ total) {
   const int64_t c = min(cap, (int64_t)*dcnt);
   if (total && blockIdx.x == 0 && threadIdx.x == 0) *total += *dcnt;
-  const int64_t rows = (c + 127) / 128 * 128;
+  const int64_t rows = (c + kX3VoxTile - 1) / kX3VoxTile * kX3VoxTile;
   for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
     const float4 *src = i < c ? reinterpret_cast<const float4 *>(Zp + (int64_t)list[i] * Kp) : nullptr;
     float4 *dst = reinterpret_cast<float4 *>(out + i * Kp);
@@ -747,7 +747,7 @@ __global__ void k_scatter_best(const int32_t *__restrict__ list, int64_t cnt,
   const int64_t stride = cnt;
   if (dcnt) {
     c = min(cnt, (int64_t)*dcnt);
-    splits = x3_device_splits((int)((c + 127) / 128), ntiles);
+    splits = x3_device_splits((int)((c + kX3VoxTile - 1) / kX3VoxTile), ntiles);
   }
   if (i >= c) return;
   float bs = -INFINITY;

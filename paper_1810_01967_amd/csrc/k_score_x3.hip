@@ -4,9 +4,10 @@
 // index among equal scores).  Operand rows are the split rows of k_split_x3:
 // Kx/32 chunks [hi 32 | lo 32].
 //
-// Block tile: 256 atoms x 128 voxels, eight waves in a 4 x 2 arrangement, each
-// owning 64 atoms x 64 voxels as 2 x 2 MFMA tiles (atoms are the A rows, voxels
-// the B columns, so a lane folds the running maximum of one voxel column).
+// Block tile: 256 atoms x X_BV voxels (X_BV = 128 or 256), eight waves in a
+// 4 x 2 arrangement, each owning 64 atoms x X_BV/2 voxels as 2 x X_NV MFMA tiles
+// (atoms are the A rows, voxels the B columns, so a lane folds the running
+// maximum of one voxel column per tile).
 // One 32-element chunk per stage, double-buffered in LDS (rows of 72 BF16:
 // the chunk plus 8 of padding).
 #include "k_split.h"
@@ -17,7 +18,11 @@ namespace mrf {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int X_BA = 256, X_BV = 128, X_LD = 72;
+#ifndef MRF_X3_LD
+#define MRF_X3_LD 72
+#endif
+constexpr int X_BA = 256, X_BV = kX3VoxTile, X_LD = MRF_X3_LD;  // LDS row pitch in BF16 (a tuning constant)
+constexpr int X_NV = X_BV / 64;  // 32-voxel tiles per wave
 constexpr int X_STAGE = (X_BA + X_BV) * X_LD;  // BF16 elements per stage buffer
 
 __device__ __forceinline__ bool xbetter(float s1, int j1, float s0, int j0) {
@@ -58,7 +63,7 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
     const int te = min(tb + tps, ntiles_total);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wa = wave >> 1, wv = wave & 1;  // atom rows wa*64.., voxel columns wv*64..
+    const int wa = wave >> 1, wv = wave & 1;  // atom rows wa*64.., voxel columns wv*X_BV/2..
     const int h = lane >> 5, l32 = lane & 31;
     const int64_t v0 = (int64_t)vt * X_BV;
     const int nkc = Kx / 32;
@@ -68,33 +73,38 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
     // loader: 8 pieces of 16 B per stage row; piece = tid % 8, rows tid/8 + 64 i
     const int lr = tid >> 3, piece = tid & 7;
     const int lc = (piece >> 2) * 32 + (piece & 3) * 8;  // column within [hi 32 | lo 32]
-    uint4 ra[4], rz[2];
+    uint4 ra[4], rz[X_NV];
     auto gload = [&](int q) {
       const int tile = tb + q / nkc, kc = q - (q / nkc) * nkc;
       const uint16_t *a = Dx + (int64_t)(tile * X_BA + lr) * row + kc * 64 + lc;
-  #pragma unroll
+      #pragma unroll
       for (int i = 0; i < 4; ++i) ra[i] = *reinterpret_cast<const uint4 *>(a + (int64_t)(64 * i) * row);
       const uint16_t *z = Zx + (v0 + lr) * row + kc * 64 + lc;
-  #pragma unroll
-      for (int i = 0; i < 2; ++i) rz[i] = *reinterpret_cast<const uint4 *>(z + (int64_t)(64 * i) * row);
+      #pragma unroll
+      for (int i = 0; i < X_NV; ++i) rz[i] = *reinterpret_cast<const uint4 *>(z + (int64_t)(64 * i) * row);
     };
     auto sstore = [&](int buf) {
       uint16_t *B = S + buf * X_STAGE;
-  #pragma unroll
+      #pragma unroll
       for (int i = 0; i < 4; ++i) *reinterpret_cast<uint4 *>(B + (lr + 64 * i) * X_LD + lc) = ra[i];
-  #pragma unroll
-      for (int i = 0; i < 2; ++i) *reinterpret_cast<uint4 *>(B + (X_BA + lr + 64 * i) * X_LD + lc) = rz[i];
+      #pragma unroll
+      for (int i = 0; i < X_NV; ++i) *reinterpret_cast<uint4 *>(B + (X_BA + lr + 64 * i) * X_LD + lc) = rz[i];
     };
 
-    f32x16 acc[2][2];
-  #pragma unroll
+    f32x16 acc[2][X_NV];
+    #pragma unroll
     for (int a = 0; a < 2; ++a)
-  #pragma unroll
-      for (int b = 0; b < 2; ++b)
-  #pragma unroll
+      #pragma unroll
+      for (int b = 0; b < X_NV; ++b)
+        #pragma unroll
         for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
-    float best[2] = {-INFINITY, -INFINITY};
-    int bidx[2] = {-1, -1};
+    float best[X_NV];
+    int bidx[X_NV];
+    #pragma unroll
+    for (int b = 0; b < X_NV; ++b) {
+      best[b] = -INFINITY;
+      bidx[b] = -1;
+    }
 
     if (nq > 0) {
       gload(0);
@@ -105,25 +115,25 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
       const int buf = q & 1;
       if (q + 1 < nq) gload(q + 1);
       const __bf16 *B = reinterpret_cast<const __bf16 *>(S) + buf * X_STAGE;
-  #pragma unroll
+      #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        bf16x8 ahi[2], alo[2], zhi[2], zlo[2];
-  #pragma unroll
+        bf16x8 ahi[2], alo[2], zhi[X_NV], zlo[X_NV];
+        #pragma unroll
         for (int ma = 0; ma < 2; ++ma) {
           const __bf16 *p = B + (wa * 64 + ma * 32 + l32) * X_LD + ks * 16 + h * 8;
           ahi[ma] = *reinterpret_cast<const bf16x8 *>(p);
           alo[ma] = *reinterpret_cast<const bf16x8 *>(p + 32);
         }
-  #pragma unroll
-        for (int nv = 0; nv < 2; ++nv) {
-          const __bf16 *p = B + (X_BA + wv * 64 + nv * 32 + l32) * X_LD + ks * 16 + h * 8;
+        #pragma unroll
+        for (int nv = 0; nv < X_NV; ++nv) {
+          const __bf16 *p = B + (X_BA + wv * (X_BV / 2) + nv * 32 + l32) * X_LD + ks * 16 + h * 8;
           zhi[nv] = *reinterpret_cast<const bf16x8 *>(p);
           zlo[nv] = *reinterpret_cast<const bf16x8 *>(p + 32);
         }
-  #pragma unroll
+        #pragma unroll
         for (int ma = 0; ma < 2; ++ma)
-  #pragma unroll
-          for (int nv = 0; nv < 2; ++nv) {
+          #pragma unroll
+          for (int nv = 0; nv < X_NV; ++nv) {
             acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[ma], zhi[nv], acc[ma][nv], 0, 0, 0);
             acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[ma], zlo[nv], acc[ma][nv], 0, 0, 0);
             acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[ma], zhi[nv], acc[ma][nv], 0, 0, 0);
@@ -133,11 +143,11 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
       if (kc == nkc - 1) {
         // fold this atom tile: 32 atom rows per voxel column and tile
         const int abase = (tb + q / nkc) * X_BA + wa * 64;
-  #pragma unroll
-        for (int nv = 0; nv < 2; ++nv)
-  #pragma unroll
+        #pragma unroll
+        for (int nv = 0; nv < X_NV; ++nv)
+          #pragma unroll
           for (int ma = 0; ma < 2; ++ma)
-  #pragma unroll
+            #pragma unroll
             for (int i = 0; i < 16; ++i) {
               const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
               const float sc = acc[ma][nv][i];
@@ -146,19 +156,19 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
                 bidx[nv] = j;
               }
             }
-  #pragma unroll
+        #pragma unroll
         for (int a = 0; a < 2; ++a)
-  #pragma unroll
-          for (int b = 0; b < 2; ++b)
-  #pragma unroll
+          #pragma unroll
+          for (int b = 0; b < X_NV; ++b)
+            #pragma unroll
             for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
       }
       if (q + 1 < nq) sstore(buf ^ 1);
       __syncthreads();
     }
     // the two half-waves, then the four atom-row waves of each voxel column
-  #pragma unroll
-    for (int nv = 0; nv < 2; ++nv) {
+    #pragma unroll
+    for (int nv = 0; nv < X_NV; ++nv) {
       const float ps = __shfl_xor(best[nv], 32, 64);
       const int pj = __shfl_xor(bidx[nv], 32, 64);
       if (xbetter(ps, pj, best[nv], bidx[nv])) {
@@ -166,8 +176,8 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
         bidx[nv] = pj;
       }
       if (h == 0) {
-        rs[wa][wv * 64 + nv * 32 + l32] = best[nv];
-        rj[wa][wv * 64 + nv * 32 + l32] = bidx[nv];
+        rs[wa][wv * (X_BV / 2) + nv * 32 + l32] = best[nv];
+        rj[wa][wv * (X_BV / 2) + nv * 32 + l32] = bidx[nv];
       }
     }
     __syncthreads();
@@ -190,7 +200,7 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
 }
 
 // Dx: split atoms [d_pad][2 Kx] (d_pad a multiple of 256); Zx: split voxels
-// [n_pad][2 Kx] (n_pad a multiple of 128, zero rows beyond n).
+// [n_pad][2 Kx] (n_pad a multiple of X_BV, zero rows beyond n).
 void launch_score_x3(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t n, int64_t n_pad,
                      int Kx, int splits, float *part_s, int *part_j, hipStream_t s) {
   const int ntiles = (int)(d_pad / X_BA);

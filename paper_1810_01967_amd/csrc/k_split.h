@@ -23,8 +23,8 @@ __device__ __forceinline__ void split_bf16(float x, uint16_t &hi, uint16_t &lo) 
 __device__ __forceinline__ int64_t split_off(int k) { return (int64_t)(k >> 5) * 64 + (k & 31); }
 
 // Atom splits of the split-BF16 exhaustive filter when its voxel count is only
-// known on the device (nvt tiles of 128 voxels, ntiles tiles of 256 atoms):
-// about 1,024 work items, at most 64 splits and one split per atom tile.
+// known on the device (nvt voxel tiles, ntiles tiles of 256 atoms): about
+// 1,024 work items, at most 64 splits and one split per atom tile.
 __device__ __forceinline__ int x3_device_splits(int nvt, int ntiles) {
   const int nvt8 = (nvt + 7) / 8 * 8;
   const int s = nvt8 > 0 ? (1024 + nvt8 - 1) / nvt8 : 1;

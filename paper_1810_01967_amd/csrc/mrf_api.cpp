@@ -284,10 +284,10 @@ int auto_splits(const mrf_dict_s *D, int64_t n) {
   return (int)s;
 }
 
-// Atom splits of the split-BF16 filter (256-atom tiles, 128-voxel tiles):
-// about 1,024 blocks.
+// Atom splits of the split-BF16 filter (256-atom tiles, kX3VoxTile-voxel
+// tiles): about 1,024 blocks.
 int auto_splits_x3(const mrf_dict_s *D, int64_t n) {
-  const int64_t nvt = (round_up(n, kRowPad) + 127) / 128;
+  const int64_t nvt = round_up(n, kRowPad) / kX3VoxTile;
   const int64_t nvt8 = (nvt + 7) / 8 * 8;
   const int64_t ntiles = D->d_pad / 256;
   int64_t s = (1024 + nvt8 - 1) / nvt8;

@@ -30,6 +30,13 @@ constexpr int kNufftBin = 8;
 // Atom / voxel row counts are padded to multiples of 256 so every tiling of
 // the scoring kernels reads inside the allocation.
 constexpr int kRowPad = 256;
+// voxels per tile of the split-BF16 exhaustive filter (128 or 256; a tuning
+// constant, a divisor of kRowPad)
+#ifndef MRF_X3_BV
+#define MRF_X3_BV 128
+#endif
+constexpr int kX3VoxTile = MRF_X3_BV;
+static_assert(kRowPad % kX3VoxTile == 0, "voxel rows are padded to whole tiles");
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
