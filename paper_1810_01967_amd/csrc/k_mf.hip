@@ -82,6 +82,80 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
   }
 }
 
+// The same with two complex values per lane and step, for even L and a
+// 16-byte aligned Z: 16-byte loads and FP32 stores, 8-byte split stores.
+__global__ __launch_bounds__(256) void k_pack_voxel_major2(const float2 *__restrict__ Z, int64_t n,
+                                                           int64_t n_pad, int L, int real_atoms,
+                                                           int Kp, float *__restrict__ Zp,
+                                                           float *__restrict__ znorm,
+                                                           unsigned long long *counters,
+                                                           const float2 *__restrict__ vphase,
+                                                           uint16_t *__restrict__ zx3, int Kx) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n_pad) return;
+  float *row = Zp + v * Kp;
+  uint16_t *xrow = zx3 ? zx3 + v * 2 * Kx : nullptr;
+  const int K = real_atoms ? L : 2 * L;
+  if (v >= n) {
+    for (int k = lane; k < Kp; k += 64) row[k] = 0.f;
+    if (xrow)
+      for (int k = lane; k < 2 * Kx; k += 64) xrow[k] = 0;
+    return;
+  }
+  const float4 *z = reinterpret_cast<const float4 *>(Z + v * (int64_t)L);
+  const float2 e = vphase ? vphase[v] : make_float2(1.f, 0.f);  // rotate by conj(e)
+  double acc = 0.0;
+  for (int u = lane; u < L / 2; u += 64) {  // complex values 2u and 2u + 1
+    const float4 q = z[u];
+    float2 a0 = make_float2(q.x, q.y), a1 = make_float2(q.z, q.w);
+    if (vphase) {
+      a0 = make_float2(e.x * q.x + e.y * q.y, e.x * q.y - e.y * q.x);
+      a1 = make_float2(e.x * q.z + e.y * q.w, e.x * q.w - e.y * q.z);
+    }
+    acc += (double)a0.x * a0.x + (double)a0.y * a0.y;
+    acc += (double)a1.x * a1.x + (double)a1.y * a1.y;
+    if (real_atoms) {
+      *reinterpret_cast<float2 *>(row + 2 * u) = make_float2(a0.x, a1.x);
+      if (xrow) {  // columns 2u, 2u + 1 share a 32-column chunk
+        uint16_t h0, l0, h1, l1;
+        split_bf16(a0.x, h0, l0);
+        split_bf16(a1.x, h1, l1);
+        const int64_t o = split_off(2 * u);
+        *reinterpret_cast<uint32_t *>(xrow + o) = h0 | ((uint32_t)h1 << 16);
+        *reinterpret_cast<uint32_t *>(xrow + o + 32) = l0 | ((uint32_t)l1 << 16);
+      }
+    } else {
+      *reinterpret_cast<float4 *>(row + 4 * u) = make_float4(a0.x, a0.y, a1.x, a1.y);
+      if (xrow) {  // columns 4u .. 4u + 3 share a 32-column chunk
+        uint16_t h[4], l[4];
+        split_bf16(a0.x, h[0], l[0]);
+        split_bf16(a0.y, h[1], l[1]);
+        split_bf16(a1.x, h[2], l[2]);
+        split_bf16(a1.y, h[3], l[3]);
+        const int64_t o = split_off(4 * u);
+        *reinterpret_cast<uint2 *>(xrow + o) =
+            make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+        *reinterpret_cast<uint2 *>(xrow + o + 32) =
+            make_uint2(l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16));
+      }
+    }
+  }
+  for (int k = K + lane; k < Kp; k += 64) row[k] = 0.f;
+  if (xrow)
+    for (int k = K + lane; k < Kx; k += 64) {
+      xrow[split_off(k)] = 0;
+      xrow[split_off(k) + 32] = 0;
+    }
+  acc = wave_sum_f64(acc);
+  if (lane == 0) {
+    const bool fin = isfinite(acc);
+    znorm[v] = fin ? (float)sqrt(acc) : -1.f;
+    if (!fin) atomicAdd(&counters[1], 1ull);
+    else if (acc == 0.0) atomicAdd(&counters[0], 1ull);
+  }
+}
+
 // 64 voxels per block; frame tiles of 16 staged in LDS for the transpose.
 template <bool HAS_G>
 __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restrict__ X,
@@ -193,8 +267,12 @@ void launch_pack_voxel_major(const float2 *Z, int64_t n, int64_t n_pad, int L, i
                              int Kp, float *Zp, float *znorm, unsigned long long *counters,
                              hipStream_t s, const float2 *vphase, uint16_t *zx3, int Kx) {
   const int64_t blocks = (n_pad + 3) / 4;
-  hipLaunchKernelGGL(k_pack_voxel_major, dim3((unsigned)blocks), dim3(256), 0, s, Z, n, n_pad, L,
-                     real_atoms, Kp, Zp, znorm, counters, vphase, zx3, Kx);
+  if (L % 2 == 0 && (reinterpret_cast<uintptr_t>(Z) & 15) == 0 && Kp % 4 == 0)
+    hipLaunchKernelGGL(k_pack_voxel_major2, dim3((unsigned)blocks), dim3(256), 0, s, Z, n, n_pad, L,
+                       real_atoms, Kp, Zp, znorm, counters, vphase, zx3, Kx);
+  else
+    hipLaunchKernelGGL(k_pack_voxel_major, dim3((unsigned)blocks), dim3(256), 0, s, Z, n, n_pad, L,
+                       real_atoms, Kp, Zp, znorm, counters, vphase, zx3, Kx);
 }
 
 void launch_pack_frame_major(const float2 *X, const float2 *G, float mu, int64_t n, int64_t n_pad,
