@@ -18,8 +18,9 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int MB_H = 256;   // hidden units (= block columns)
-constexpr int MB_BK = 32;   // K per stage
-constexpr int MB_LD = 40;   // LDS row pitch in BF16 (32 + 8 pad)
+constexpr int MB_BK = kMlpBK;    // K per stage
+constexpr int MB_LD = MB_BK + 8; // LDS row pitch in BF16 (8 of padding)
+constexpr int MB_PC = MB_BK / 32;  // 8-element pieces per thread and row per stage
 constexpr int MB_HLD = 260; // LDS row pitch of the FP32 h2 tile
 // rows per block of the two launches (tuning constants: 4 threads per row)
 #ifndef MRF_MLP_M1
@@ -75,39 +76,47 @@ __global__ __launch_bounds__(4 * MB_M) void k_mlp_bf16(int64_t B, const float *_
   const int nk = (LAYER1 ? Kx : MB_H) / MB_BK;
   const int ldw = LAYER1 ? Kx : MB_H;
 
-  // loader: thread t covers row t/4 (A) and rows t/4 + (NT/4) i (W), 8 elements at (t & 3) * 8
-  const int lr = tid >> 2, lc = (tid & 3) * 8;
+  // loader: thread t covers row t/4 (A) and rows t/4 + (NT/4) i (W), 8 MB_PC
+  // elements at (t & 3) * 8 MB_PC
+  const int lr = tid >> 2, lc = (tid & 3) * 8 * MB_PC;
   const int64_t arow = m0 + lr;
   const bool avalid = arow < B;
   const float sc = (LAYER1 && avalid) ? (rowscale ? rowscale[arow] : 1.f) : 0.f;
-  uint4 ra, rw[NW];
+  uint4 ra[MB_PC], rw[NW][MB_PC];
   auto gload = [&](int kc) {
-    const int k = kc * MB_BK + lc;
-    if constexpr (LAYER1) {
-      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (avalid && k < K) {
-        const float4 x0 = *reinterpret_cast<const float4 *>(X + arow * ldx + k);
-        const float4 x1 = *reinterpret_cast<const float4 *>(X + arow * ldx + k + 4);
-        v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
-        v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+#pragma unroll
+    for (int c = 0; c < MB_PC; ++c) {
+      const int k = kc * MB_BK + lc + 8 * c;
+      if constexpr (LAYER1) {
+        float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (avalid && k < K) {
+          const float4 x0 = *reinterpret_cast<const float4 *>(X + arow * ldx + k);
+          const float4 x1 = *reinterpret_cast<const float4 *>(X + arow * ldx + k + 4);
+          v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
+          v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+        }
+        uint32_t p[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          p[i] = (uint32_t)to_bf16(v[2 * i] * sc) | ((uint32_t)to_bf16(v[2 * i + 1] * sc) << 16);
+        ra[c] = make_uint4(p[0], p[1], p[2], p[3]);
+      } else {
+        ra[c] = avalid ? *reinterpret_cast<const uint4 *>(H1in + arow * MB_H + k) : make_uint4(0u, 0u, 0u, 0u);
       }
-      uint32_t p[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        p[i] = (uint32_t)to_bf16(v[2 * i] * sc) | ((uint32_t)to_bf16(v[2 * i + 1] * sc) << 16);
-      ra = make_uint4(p[0], p[1], p[2], p[3]);
-    } else {
-      ra = avalid ? *reinterpret_cast<const uint4 *>(H1in + arow * MB_H + k) : make_uint4(0u, 0u, 0u, 0u);
+      for (int i = 0; i < NW; ++i)
+        rw[i][c] = *reinterpret_cast<const uint4 *>(W + (int64_t)(lr + (NT / 4) * i) * ldw + k);
     }
-#pragma unroll
-    for (int i = 0; i < NW; ++i)
-      rw[i] = *reinterpret_cast<const uint4 *>(W + (int64_t)(lr + (NT / 4) * i) * ldw + k);
   };
   auto sstore = [&](int buf) {
     uint16_t *S = reinterpret_cast<uint16_t *>(smem) + buf * STAGE;
-    *reinterpret_cast<uint4 *>(S + lr * MB_LD + lc) = ra;
 #pragma unroll
-    for (int i = 0; i < NW; ++i) *reinterpret_cast<uint4 *>(S + (MB_M + lr + (NT / 4) * i) * MB_LD + lc) = rw[i];
+    for (int c = 0; c < MB_PC; ++c) {
+      *reinterpret_cast<uint4 *>(S + lr * MB_LD + lc + 8 * c) = ra[c];
+#pragma unroll
+      for (int i = 0; i < NW; ++i)
+        *reinterpret_cast<uint4 *>(S + (MB_M + lr + (NT / 4) * i) * MB_LD + lc + 8 * c) = rw[i][c];
+    }
   };
 
   f32x16 acc[2][2];
@@ -126,7 +135,7 @@ __global__ __launch_bounds__(4 * MB_M) void k_mlp_bf16(int64_t B, const float *_
     if (kc + 1 < nk) gload(kc + 1);
     const __bf16 *S = reinterpret_cast<const __bf16 *>(smem) + buf * STAGE;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
+    for (int ks = 0; ks < MB_BK / 16; ++ks) {
       bf16x8 a[2], w[2];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)

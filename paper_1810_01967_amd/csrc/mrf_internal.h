@@ -36,6 +36,12 @@ constexpr int kRowPad = 256;
 #define MRF_X3_BV 128
 #endif
 constexpr int kX3VoxTile = MRF_X3_BV;
+// K per stage of the BF16 network kernels (32 or 64; a tuning constant); the
+// first layer's BF16 weight rows are padded to a multiple of it
+#ifndef MRF_MLP_BK
+#define MRF_MLP_BK 32
+#endif
+constexpr int kMlpBK = MRF_MLP_BK;
 static_assert(kRowPad % kX3VoxTile == 0, "voxel rows are padded to whole tiles");
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }

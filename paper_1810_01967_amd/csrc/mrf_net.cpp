@@ -299,14 +299,14 @@ extern "C" mrf_status mrf_net_forward(mrf_net net, const float *X, int64_t B, fl
 namespace mrf {
 
 bool net_bf16_ok(const mrf_net_s *net, int64_t K, int64_t ldx) {
-  return net->H == 256 && net->P <= 8 && K % 8 == 0 && ldx % 4 == 0 && K <= round_up(net->I, 32);
+  return net->H == 256 && net->P <= 8 && K % 8 == 0 && ldx % 4 == 0 && K <= round_up(net->I, kMlpBK);
 }
 
 // X: [B][ldx] FP32 with K readable columns (columns >= I meet zero weights).
 mrf_status net_forward_bf16(mrf_net_s *net, const float *X, int64_t ldx, int64_t K, int64_t B,
                             const float *rowscale, float *Y, uint16_t *h1, hipStream_t s) {
   const int H = net->H, I = net->I;
-  const int Kx = (int)round_up(I, 32);
+  const int Kx = (int)round_up(I, kMlpBK);
   TRY(grow(net->wb, ((size_t)H * Kx + (size_t)H * H) * 2));
   const float *w = net->w.as<float>();
   uint16_t *w1b = net->wb.as<uint16_t>(), *w2b = w1b + (size_t)H * Kx;
