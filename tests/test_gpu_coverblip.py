@@ -4,14 +4,15 @@ the C ABI, on the 64 x 64 FISP disc workload (L = 100, 2,000 real atoms, 6
 of 64 lines per frame, 30 dB): teacher-forced steps at eps = 0 and 0.4 (the
 same answers as the oracle's tree search outside FP32-vs-FP64 traversal
 flips, Definition 3.1 and the warm-start bound on every voxel, the same
-distance counts), and ten iterations at mu = 1 against the oracle's
-CoverBLIP solve (eps = 0.4) and against the exhaustive solve (eps = 0)."""
+distance counts), ten iterations at mu = 1 against the oracle's CoverBLIP
+solve (eps = 0.4) and against the exhaustive solve (eps = 0), and CoverBLIP in
+the s = 10 temporal subspace (the tree built on the compressed atoms)."""
 import numpy as np
 import pytest
 
 from gpu_helpers import banner, c64, dev, host
 from oracle import covertree as ct
-from oracle import fourier, ipg
+from oracle import fourier, ipg, subspace
 from synth import workloads
 
 pytestmark = pytest.mark.gpu
@@ -115,3 +116,39 @@ def test_coverblip_solve(m, prob):
     np.testing.assert_allclose(h0["f"], he["f"], rtol=1e-3)
     assert agree > 0.98
     assert he["distance_evals"] == 0
+
+
+def test_coverblip_compressed(m, prob):
+    """CoverBLIP in the temporal subspace (the paper's compressed variants):
+    the cover tree of the s = 10 compressed atoms, ten iterations at mu = 1 with
+    eps = 0.4 against the oracle's compressed CoverBLIP solve (its own V, its
+    own tree over its compressed atoms); at a fixed mu both follow the same
+    path outside FP32-vs-FP64 traversal flips."""
+    banner("coverblip compressed s=10, 64x64 L=100 FISP, 10 iterations mu=1 eps=0.4")
+    Dd, ph, smp, Y, t, D, A = prob
+    s = 10
+    C = D.compress(s, cover_tree=True)
+    Vo, _ = subspace.dominant_subspace(Dd.atoms, s)
+    Dc = subspace.compress_atoms(Dd.atoms, Vo)
+    tc = ct.build(ct.atom_rows(Dc))
+    n = 64 * 64
+    Xc, idx, pd, params, hist = m.mrf_ipg_solve(C, A, dev(Y), mu0=1.0, adaptive=False, max_iter=10, rel_tol=0.0,
+                                                eps=0.4)
+    Xr, idr, gr, hr = ipg.ipg_solve(Y, smp.off, smp.idx, (1, s, 64, 64), Dc, mu0=1.0, adaptive=False, max_iter=10,
+                                    rel_tol=0, V=Vo, tree=tc, eps=0.4)
+    Vg, _ = C.subspace()
+    fr = np.array([h["f"] for h in hr])
+    inside = ph.idx >= 0
+    gidx = host(idx)
+    nm_g = _rel(subspace.expand(host(Xc).astype(np.complex128), Vg), ph.X0)
+    nm_o = _rel(subspace.expand(Xr, Vo), ph.X0)
+    ev_g = hist["distance_evals"] / (n * 10)
+    ev_o = sum(h["evals"] for h in hr) / (n * 10)
+    print(f"compressed coverblip: f gpu {hist['f'][-1]:.5e} oracle {fr[-1]:.5e}; nmse gpu {nm_g:.4e} oracle "
+          f"{nm_o:.4e}; object agreement {np.mean(gidx[inside] == idr[inside]):.4f}; distance evaluations per "
+          f"voxel per iteration gpu {ev_g:.1f} oracle {ev_o:.1f}; {hist['ms']:.1f} ms")
+    assert hist["iters"] == 10
+    np.testing.assert_allclose(hist["f"], fr, rtol=0.02)
+    assert abs(nm_g - nm_o) < 0.05 * nm_o + 1e-4
+    assert np.mean(gidx[inside] == idr[inside]) > 0.95
+    assert abs(ev_g / ev_o - 1.0) < 0.1
