@@ -382,6 +382,12 @@ def iteration_bench(m, torch, D, Dd, net, args, DT=None):
     if DT is not None:  # CoverBLIP: the cover tree as the projection (Algorithm 1 inside Algorithm 2)
         for eps in (0.0, 0.4):
             cases.append((f"cartesian_256_1coil_covertree_eps{eps:g}", DT, A1, Ycart, 256, Dd.L, {"eps": eps}))
+        # the paper's fast compressed setting (s = 20): exhaustive, and CoverBLIP on the compressed atoms' tree
+        t1 = time.time()
+        D20 = D.compress(20, cover_tree=True)
+        log(f"s = 20 dictionary with its cover tree built in {time.time() - t1:.1f}s")
+        cases.append(("cartesian_256_1coil_s20", D20, A1, Ycart, 256, 20, {}))
+        cases.append(("cartesian_256_1coil_s20_covertree_eps0.4", D20, A1, Ycart, 256, 20, {"eps": 0.4}))
     for name, DD, A, Y, size, F, kw in cases:
         Yd = torch.from_numpy(np.ascontiguousarray(Y.astype(np.complex64))).cuda()
         X = torch.zeros((1, F, size, size), dtype=torch.complex64, device="cuda")
