@@ -374,3 +374,8 @@ def test_device_sized_fallback_equals_exhaustive(m, n):
     i9, ion, iex = host(o9["idx"]), host(on["idx"]), host(ex["idx"])
     # every voxel either keeps its local answer or takes the exhaustive one
     assert np.all((i9 == ion) | (i9 == iex))
+    # a smaller call on the same dictionary (buffers sized by the larger one)
+    h = max(n // 3, 1)
+    oh = m.mrf_match(D, Zd[:h].contiguous(), net=net, precision="bf16x3", recentre=1, fallback_corr=2.0, stats=True)
+    assert oh["stats"].fallbacks == h
+    np.testing.assert_array_equal(host(oh["idx"]), iex[:h])
