@@ -52,19 +52,37 @@ __global__ void k_coarse_keys(const int32_t *__restrict__ list, int64_t cnt, con
 // tiles; toff[nkeys] = the number of tiles.  Thread t sums its own run of
 // consecutive keys, one block-wide scan of the 1,024 run sums gives each run's
 // start, and the thread writes its run's prefixes.
+// Up to kScanLds keys go through LDS: coalesced loads, each thread's run
+// prefixes kept in LDS, and coalesced writes of the outputs.
+constexpr int kScanLds = 16384;
 __global__ __launch_bounds__(1024) void k_scan(const unsigned int *__restrict__ hist, int nkeys,
                                                unsigned int *__restrict__ off,
                                                unsigned int *__restrict__ cursor,
                                                unsigned int *__restrict__ toff) {
   __shared__ unsigned int buf[1024], tbuf[1024];
+  __shared__ unsigned int hl[kScanLds], th[kScanLds];  // within-run prefixes (keys, tiles)
+  __shared__ unsigned int ttotal;
   const int t = threadIdx.x;
   const int per = (nkeys + 1023) / 1024;
   const int b = min(t * per, nkeys), e = min(b + per, nkeys);
+  const bool staged = nkeys <= kScanLds;
   unsigned int sum = 0, tsum = 0;
-  for (int i = b; i < e; ++i) {
-    const unsigned int x = hist[i];
-    sum += x;
-    tsum += (x + 63u) / 64u;
+  if (staged) {
+    for (int i = t; i < nkeys; i += 1024) hl[i] = hist[i];
+    __syncthreads();
+    for (int i = b; i < e; ++i) {
+      const unsigned int x = hl[i];
+      hl[i] = sum;
+      th[i] = tsum;
+      sum += x;
+      tsum += (x + 63u) / 64u;
+    }
+  } else {
+    for (int i = b; i < e; ++i) {
+      const unsigned int x = hist[i];
+      sum += x;
+      tsum += (x + 63u) / 64u;
+    }
   }
   buf[t] = sum;
   tbuf[t] = tsum;
@@ -77,16 +95,32 @@ __global__ __launch_bounds__(1024) void k_scan(const unsigned int *__restrict__ 
     tbuf[t] += ty;
     __syncthreads();
   }
-  unsigned int run = buf[t] - sum, trun = tbuf[t] - tsum;
-  for (int i = b; i < e; ++i) {
-    const unsigned int x = hist[i];
-    off[i] = run;
-    cursor[i] = run;
-    toff[i] = trun;
-    run += x;
-    trun += (x + 63u) / 64u;
+  unsigned int run = buf[t] - sum, trun = tbuf[t] - tsum;  // this run's starts
+  if (t == 1023) ttotal = tbuf[1023];
+  if (staged) {
+    __syncthreads();
+    buf[t] = run;
+    tbuf[t] = trun;
+    __syncthreads();
+    for (int i = t; i < nkeys; i += 1024) {
+      const int r = i / per;
+      const unsigned int o = buf[r] + hl[i];
+      off[i] = o;
+      cursor[i] = o;
+      toff[i] = tbuf[r] + th[i];
+    }
+  } else {
+    for (int i = b; i < e; ++i) {
+      const unsigned int x = hist[i];
+      off[i] = run;
+      cursor[i] = run;
+      toff[i] = trun;
+      run += x;
+      trun += (x + 63u) / 64u;
+    }
   }
-  if (t == 1023) toff[nkeys] = tbuf[1023];
+  __syncthreads();
+  if (t == 0) toff[nkeys] = ttotal;
 }
 
 __global__ void k_group_scatter(const int32_t *__restrict__ list, const int32_t *__restrict__ keys,
