@@ -379,3 +379,25 @@ def test_device_sized_fallback_equals_exhaustive(m, n):
     oh = m.mrf_match(D, Zd[:h].contiguous(), net=net, precision="bf16x3", recentre=1, fallback_corr=2.0, stats=True)
     assert oh["stats"].fallbacks == h
     np.testing.assert_array_equal(host(oh["idx"]), iex[:h])
+
+
+def test_recentre_rounds_never_lower_the_score(m, small_dict):
+    """Up to 16 re-centring rounds (each round's list length stays on the
+    device): a round keeps the previous best inside the new box, so more rounds
+    never lower a voxel's normalised correlation, and they re-centre at least
+    as many voxels."""
+    banner("re-centring rounds 0, 3, 16")
+    Dd = small_dict
+    Dg = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    n = 2000
+    Z, jt, pd, snr = workloads.random_voxels(Dd, n, seed=17, snr_db_range=(5.0, 30.0))
+    Zd = dev(c64(Z))
+    far = np.clip(grids.grid_sub(jt, Dd.grid_dims) + 4, 0, np.array(Dd.grid_dims) - 1).astype(np.int32)
+    res = {}
+    for rc in (0, 3, 16):
+        o = m.mrf_match_local(Dg, Zd, dev(far), box_radius=1, fallback_corr=-1.0, recentre=rc, stats=True)
+        res[rc] = (host(o["corr"]), o["stats"].recentred)
+        print(f"recentre={rc}: recentred {o['stats'].recentred}, mean corr {res[rc][0].mean():.6f}")
+    assert res[0][1] == 0
+    assert np.all(res[3][0] >= res[0][0]) and np.all(res[16][0] >= res[3][0])
+    assert res[16][1] >= res[3][1] > 0
