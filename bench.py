@@ -94,8 +94,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
-                                   "supported (DESIGN.md describes how the path would shard)",
+        print(json.dumps({"error": "the matched filter runs on one GPU; runs on several GPUs are not "
+                                   "supported",
                           "n_gpus": args.gpus}), flush=True)
         return 2
     import torch

@@ -51,7 +51,7 @@ typedef enum {
   MRF_E_INVAL = -1,       /* bad argument: null pointer, bad size, bad enum */
   MRF_E_NOMEM = -2,       /* device allocation failed */
   MRF_E_HIP = -3,         /* a HIP runtime call failed (message has the HIP error) */
-  MRF_E_UNSUPPORTED = -4, /* valid request this build does not implement */
+  MRF_E_UNSUPPORTED = -4, /* valid request the library does not implement */
   MRF_E_NUMERIC = -5,     /* non-finite input detected (only reported when stats are requested) */
   MRF_E_NOCONV = -6       /* step size not accepted within max_shrinks (solver) */
 } mrf_status;

@@ -613,7 +613,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   unsigned long long *work = reinterpret_cast<unsigned long long *>(cntw + 18);
   TRY(grow(D->bestkey, (size_t)n * 8));
   unsigned long long *bkey = D->bestkey.as<unsigned long long>();
-  // round 0: every voxel, grouped by coarse proposal cell
+  // first pass: every voxel, grouped by coarse proposal cell
   int32_t *la = D->list_a.as<int32_t>(), *lb = D->list_b.as<int32_t>(), *lc = D->list_c.as<int32_t>();
   launch_learned_prep(la, bkey, n, cntw, 22, gb.hist, nkeys, s);
   const bool x3 = o->precision == MRF_BF16X3;
