@@ -4,8 +4,8 @@
 // index among equal scores).  Operand rows are the split rows of k_split_x3:
 // Kx/32 chunks [hi 32 | lo 32].
 //
-// Block tile: 256 atoms x X_BV voxels (X_BV = 128 or 256), eight waves in a
-// 4 x 2 arrangement, each owning 64 atoms x X_BV/2 voxels as 2 x X_NV MFMA tiles
+// Block tile: 256 atoms x X_BV voxels (X_BV = 128 or 256), X_WAVES waves in a
+// X_WAVES/2 x 2 arrangement, each owning 256/(X_WAVES/2) atoms x X_BV/2 voxels as MFMA tiles
 // (atoms are the A rows, voxels the B columns, so a lane folds the running
 // maximum of one voxel column per tile).
 // One 32-element chunk per stage, double-buffered in LDS (rows of 72 BF16:
@@ -23,13 +23,25 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 #endif
 constexpr int X_BA = 256, X_BV = kX3VoxTile, X_LD = MRF_X3_LD;  // LDS row pitch in BF16 (a tuning constant)
 constexpr int X_NV = X_BV / 64;  // 32-voxel tiles per wave
+// waves per block (8 or 16, a tuning constant) in X_WAVES / 2 atom-row groups x
+// 2 voxel-column groups
+#ifndef MRF_X3_WAVES
+#define MRF_X3_WAVES 16
+#endif
+constexpr int X_WAVES = MRF_X3_WAVES, X_NT = 64 * X_WAVES;
+constexpr int X_WA = X_WAVES / 2;            // atom-row groups
+constexpr int X_AROWS = X_BA / X_WA;         // atom rows per wave
+constexpr int X_MA = X_AROWS / 32;           // 32-atom tiles per wave
+constexpr int X_LSTEP = X_NT / 8;            // rows per loader pass (8 pieces of 16 B per row)
+constexpr int X_LA = X_BA / X_LSTEP, X_LZ = X_BV / X_LSTEP;
+static_assert(X_MA >= 1 && X_LA >= 1 && X_LZ >= 1, "block shape");
 constexpr int X_STAGE = (X_BA + X_BV) * X_LD;  // BF16 elements per stage buffer
 
 __device__ __forceinline__ bool xbetter(float s1, int j1, float s0, int j0) {
   return (s1 > s0) || (s1 == s0 && j1 >= 0 && (j0 < 0 || j1 < j0));
 }
 
-__global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict__ Dx, const uint16_t *__restrict__ Zx,
+__global__ __launch_bounds__(X_NT, 1) void k_score_x3(const uint16_t *__restrict__ Dx, const uint16_t *__restrict__ Zx,
                                                      int d, int ntiles_total, int64_t n, int nvt, int Kx,
                                                      int splits, int tiles_per_split, float *__restrict__ part_s,
                                                      int *__restrict__ part_j, const unsigned int *__restrict__ dcnt,
@@ -50,8 +62,8 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
   const int64_t nwork = (int64_t)((nvt_w + 7) / 8 * 8) * nsplit;
 
   __shared__ __attribute__((aligned(16))) uint16_t S[2 * X_STAGE];
-  __shared__ float rs[4][X_BV];
-  __shared__ int rj[4][X_BV];
+  __shared__ float rs[X_WA][X_BV];
+  __shared__ int rj[X_WA][X_BV];
 
   for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int xcd = (int)(w & 7);
@@ -63,37 +75,38 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
     const int te = min(tb + tps, ntiles_total);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wa = wave >> 1, wv = wave & 1;  // atom rows wa*64.., voxel columns wv*X_BV/2..
+    const int wa = wave >> 1, wv = wave & 1;  // atom rows wa*X_AROWS.., voxel columns wv*X_BV/2..
     const int h = lane >> 5, l32 = lane & 31;
     const int64_t v0 = (int64_t)vt * X_BV;
     const int nkc = Kx / 32;
     const int nq = te > tb ? (te - tb) * nkc : 0;
     const int64_t row = 2 * (int64_t)Kx;  // elements per split row
 
-    // loader: 8 pieces of 16 B per stage row; piece = tid % 8, rows tid/8 + 64 i
+    // loader: 8 pieces of 16 B per stage row; piece = tid % 8, rows tid/8 + X_LSTEP i
     const int lr = tid >> 3, piece = tid & 7;
     const int lc = (piece >> 2) * 32 + (piece & 3) * 8;  // column within [hi 32 | lo 32]
-    uint4 ra[4], rz[X_NV];
+    uint4 ra[X_LA], rz[X_LZ];
     auto gload = [&](int q) {
       const int tile = tb + q / nkc, kc = q - (q / nkc) * nkc;
       const uint16_t *a = Dx + (int64_t)(tile * X_BA + lr) * row + kc * 64 + lc;
       #pragma unroll
-      for (int i = 0; i < 4; ++i) ra[i] = *reinterpret_cast<const uint4 *>(a + (int64_t)(64 * i) * row);
+      for (int i = 0; i < X_LA; ++i) ra[i] = *reinterpret_cast<const uint4 *>(a + (int64_t)(X_LSTEP * i) * row);
       const uint16_t *z = Zx + (v0 + lr) * row + kc * 64 + lc;
       #pragma unroll
-      for (int i = 0; i < X_NV; ++i) rz[i] = *reinterpret_cast<const uint4 *>(z + (int64_t)(64 * i) * row);
+      for (int i = 0; i < X_LZ; ++i) rz[i] = *reinterpret_cast<const uint4 *>(z + (int64_t)(X_LSTEP * i) * row);
     };
     auto sstore = [&](int buf) {
       uint16_t *B = S + buf * X_STAGE;
       #pragma unroll
-      for (int i = 0; i < 4; ++i) *reinterpret_cast<uint4 *>(B + (lr + 64 * i) * X_LD + lc) = ra[i];
+      for (int i = 0; i < X_LA; ++i) *reinterpret_cast<uint4 *>(B + (lr + X_LSTEP * i) * X_LD + lc) = ra[i];
       #pragma unroll
-      for (int i = 0; i < X_NV; ++i) *reinterpret_cast<uint4 *>(B + (X_BA + lr + 64 * i) * X_LD + lc) = rz[i];
+      for (int i = 0; i < X_LZ; ++i)
+        *reinterpret_cast<uint4 *>(B + (X_BA + lr + X_LSTEP * i) * X_LD + lc) = rz[i];
     };
 
-    f32x16 acc[2][X_NV];
+    f32x16 acc[X_MA][X_NV];
     #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < X_MA; ++a)
       #pragma unroll
       for (int b = 0; b < X_NV; ++b)
         #pragma unroll
@@ -117,10 +130,10 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
       const __bf16 *B = reinterpret_cast<const __bf16 *>(S) + buf * X_STAGE;
       #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        bf16x8 ahi[2], alo[2], zhi[X_NV], zlo[X_NV];
+        bf16x8 ahi[X_MA], alo[X_MA], zhi[X_NV], zlo[X_NV];
         #pragma unroll
-        for (int ma = 0; ma < 2; ++ma) {
-          const __bf16 *p = B + (wa * 64 + ma * 32 + l32) * X_LD + ks * 16 + h * 8;
+        for (int ma = 0; ma < X_MA; ++ma) {
+          const __bf16 *p = B + (wa * X_AROWS + ma * 32 + l32) * X_LD + ks * 16 + h * 8;
           ahi[ma] = *reinterpret_cast<const bf16x8 *>(p);
           alo[ma] = *reinterpret_cast<const bf16x8 *>(p + 32);
         }
@@ -131,7 +144,7 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
           zlo[nv] = *reinterpret_cast<const bf16x8 *>(p + 32);
         }
         #pragma unroll
-        for (int ma = 0; ma < 2; ++ma)
+        for (int ma = 0; ma < X_MA; ++ma)
           #pragma unroll
           for (int nv = 0; nv < X_NV; ++nv) {
             acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[ma], zhi[nv], acc[ma][nv], 0, 0, 0);
@@ -142,11 +155,11 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
       const int kc = q % nkc;
       if (kc == nkc - 1) {
         // fold this atom tile: 32 atom rows per voxel column and tile
-        const int abase = (tb + q / nkc) * X_BA + wa * 64;
+        const int abase = (tb + q / nkc) * X_BA + wa * X_AROWS;
         #pragma unroll
         for (int nv = 0; nv < X_NV; ++nv)
           #pragma unroll
-          for (int ma = 0; ma < 2; ++ma)
+          for (int ma = 0; ma < X_MA; ++ma)
             #pragma unroll
             for (int i = 0; i < 16; ++i) {
               const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
@@ -157,7 +170,7 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
               }
             }
         #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < X_MA; ++a)
           #pragma unroll
           for (int b = 0; b < X_NV; ++b)
             #pragma unroll
@@ -166,7 +179,7 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
       if (q + 1 < nq) sstore(buf ^ 1);
       __syncthreads();
     }
-    // the two half-waves, then the four atom-row waves of each voxel column
+    // the two half-waves, then the X_WA atom-row waves of each voxel column
     #pragma unroll
     for (int nv = 0; nv < X_NV; ++nv) {
       const float ps = __shfl_xor(best[nv], 32, 64);
@@ -184,7 +197,7 @@ __global__ __launch_bounds__(512, 1) void k_score_x3(const uint16_t *__restrict_
     if (tid < X_BV) {
       float bs = rs[0][tid];
       int bj = rj[0][tid];
-      for (int w = 1; w < 4; ++w)
+      for (int w = 1; w < X_WA; ++w)
         if (xbetter(rs[w][tid], rj[w][tid], bs, bj)) {
           bs = rs[w][tid];
           bj = rj[w][tid];
@@ -208,7 +221,7 @@ void launch_score_x3(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pa
   const int tps = (ntiles + splits - 1) / splits;
   const int64_t nvt8 = (nvt + 7) / 8 * 8;
   const int64_t blocks = nvt8 * splits;
-  hipLaunchKernelGGL(k_score_x3, dim3((unsigned)blocks), dim3(512), 0, s, Dx, Zx, d, ntiles, n, nvt, Kx, splits, tps,
+  hipLaunchKernelGGL(k_score_x3, dim3((unsigned)blocks), dim3(X_NT), 0, s, Dx, Zx, d, ntiles, n, nvt, Kx, splits, tps,
                      part_s, part_j, nullptr, n);
 }
 
@@ -217,7 +230,7 @@ void launch_score_x3_dev(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t 
   if (cap <= 0) return;
   const int ntiles = (int)(d_pad / X_BA);
   // one block per CU of the 256, each looping over the work items
-  hipLaunchKernelGGL(k_score_x3, dim3(256), dim3(512), 0, s, Dx, Zx, d, ntiles, cap, 0, Kx, 1, ntiles, part_s,
+  hipLaunchKernelGGL(k_score_x3, dim3(256), dim3(X_NT), 0, s, Dx, Zx, d, ntiles, cap, 0, Kx, 1, ntiles, part_s,
                      part_j, dcnt, cap);
 }
 
