@@ -56,31 +56,34 @@ void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t 
 // LAYER1 = true: A = FP32 rows X (pitch ldx, K valid columns, K % 8 == 0,
 // ldx % 4 == 0) times rowscale, W = W1 BF16 [256][Kx]; writes H1 BF16 [B][256].
 // LAYER1 = false: A = H1 BF16 [B][256], W = W2 BF16 [256][256]; writes Y [B][P].
-template <bool LAYER1, int MB_M>
-__global__ __launch_bounds__(4 * MB_M) void k_mlp_bf16(int64_t B, const float *__restrict__ X, int64_t ldx, int K,
+// WR: rows per wave (64, or 32 for twice the waves on the same row tile).
+template <bool LAYER1, int MB_M, int WR>
+__global__ __launch_bounds__(4 * MB_M * (64 / WR)) void k_mlp_bf16(int64_t B, const float *__restrict__ X, int64_t ldx, int K,
                                                      int Kx, const float *__restrict__ rowscale,
                                                      const uint16_t *__restrict__ H1in,
                                                      const uint16_t *__restrict__ W, const float *__restrict__ bias,
                                                      uint16_t *__restrict__ H1out, const float *__restrict__ W3,
                                                      const float *__restrict__ b3, int P, float *__restrict__ Y) {
-  // MB_M rows per block, one wave per 64 rows x 64 units
-  constexpr int NT = 4 * MB_M;                  // threads per block
+  // MB_M rows per block, one wave per WR rows x 64 units
+  constexpr int NT = 4 * MB_M * (64 / WR);      // threads per block
+  constexpr int MI = WR / 32;                   // 32-row tiles per wave
   constexpr int NW = MB_H * 4 / NT;             // W chunks of 8 per thread per stage
   constexpr int STAGE = (MB_M + MB_H) * MB_LD;  // BF16 elements per stage
   constexpr int SMEM = LAYER1 ? 2 * STAGE * 2 : (MB_M * MB_HLD * 4 > 2 * STAGE * 2 ? MB_M * MB_HLD * 4 : 2 * STAGE * 2);
   __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
-  const int wr = (wave >> 2) * 64, wn = (wave & 3) * 64;  // the wave's rows and units
+  const int wr = (wave >> 2) * WR, wn = (wave & 3) * 64;  // the wave's rows and units
   const int64_t m0 = (int64_t)blockIdx.x * MB_M;
   const int nk = (LAYER1 ? Kx : MB_H) / MB_BK;
   const int ldw = LAYER1 ? Kx : MB_H;
 
-  // loader: thread t covers row t/4 (A) and rows t/4 + (NT/4) i (W), 8 MB_PC
-  // elements at (t & 3) * 8 MB_PC
+  // loader: thread t covers row t/4 (A, the first 4 MB_M threads) and rows
+  // t/4 + (NT/4) i (W), 8 MB_PC elements at (t & 3) * 8 MB_PC
   const int lr = tid >> 2, lc = (tid & 3) * 8 * MB_PC;
+  const bool aload = lr < MB_M;
   const int64_t arow = m0 + lr;
-  const bool avalid = arow < B;
+  const bool avalid = aload && arow < B;
   const float sc = (LAYER1 && avalid) ? (rowscale ? rowscale[arow] : 1.f) : 0.f;
   uint4 ra[MB_PC], rw[NW][MB_PC];
   auto gload = [&](int kc) {
@@ -112,16 +115,16 @@ __global__ __launch_bounds__(4 * MB_M) void k_mlp_bf16(int64_t B, const float *_
     uint16_t *S = reinterpret_cast<uint16_t *>(smem) + buf * STAGE;
 #pragma unroll
     for (int c = 0; c < MB_PC; ++c) {
-      *reinterpret_cast<uint4 *>(S + lr * MB_LD + lc + 8 * c) = ra[c];
+      if (aload) *reinterpret_cast<uint4 *>(S + lr * MB_LD + lc + 8 * c) = ra[c];
 #pragma unroll
       for (int i = 0; i < NW; ++i)
         *reinterpret_cast<uint4 *>(S + (MB_M + lr + (NT / 4) * i) * MB_LD + lc + 8 * c) = rw[i][c];
     }
   };
 
-  f32x16 acc[2][2];
+  f32x16 acc[MI][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MI; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -136,15 +139,15 @@ __global__ __launch_bounds__(4 * MB_M) void k_mlp_bf16(int64_t B, const float *_
     const __bf16 *S = reinterpret_cast<const __bf16 *>(smem) + buf * STAGE;
 #pragma unroll
     for (int ks = 0; ks < MB_BK / 16; ++ks) {
-      bf16x8 a[2], w[2];
+      bf16x8 a[MI], w[2];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < MI; ++mi)
         a[mi] = *reinterpret_cast<const bf16x8 *>(S + (wr + mi * 32 + l32) * MB_LD + ks * 16 + h * 8);
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni)
         w[ni] = *reinterpret_cast<const bf16x8 *>(S + (MB_M + wn + ni * 32 + l32) * MB_LD + ks * 16 + h * 8);
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], w[ni], acc[mi][ni], 0, 0, 0);
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(4 * MB_M) void k_mlp_bf16(int64_t B, const float *_
       const int n = wn + ni * 32 + l32;
       const float bn = bias[n];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int64_t m = m0 + wr + mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
@@ -173,14 +176,15 @@ __global__ __launch_bounds__(4 * MB_M) void k_mlp_bf16(int64_t B, const float *_
       const int n = wn + ni * 32 + l32;
       const float bn = bias[n];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
           Hs[(wr + mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3)) * MB_HLD + n] = gelu_exact(acc[mi][ni][i] + bn);
     }
     __syncthreads();
-    // y[m][p]: thread t sums units [64 (t & 3), +64) of row t / 4 in a fixed
-    // order, then the four partial sums are added in a fixed order
+    // y[m][p]: thread t < 4 MB_M sums units [64 (t & 3), +64) of row t / 4 in
+    // a fixed order, then the four partial sums are added in a fixed order
+    if (tid >= 4 * MB_M) return;  // whole waves
     const int row = tid >> 2, part = tid & 3;
     float yp[8];
 #pragma unroll
@@ -210,9 +214,14 @@ void launch_mlp_bf16(int64_t B, const float *X, int64_t ldx, int K, int Kx, cons
                      const float *W3, const float *b3, int P, float *Y, hipStream_t s) {
   if (B <= 0) return;
   constexpr int M1 = MRF_MLP_M1, M2 = MRF_MLP_M2;
-  hipLaunchKernelGGL((k_mlp_bf16<true, M1>), dim3((unsigned)((B + M1 - 1) / M1)), dim3(4 * M1), 0, s, B, X, ldx, K,
+#ifndef MRF_MLP_WR2
+#define MRF_MLP_WR2 32
+#endif
+  constexpr int WR2 = MRF_MLP_WR2;  // rows per wave of the second layer (a tuning constant)
+  hipLaunchKernelGGL((k_mlp_bf16<true, M1, 64>), dim3((unsigned)((B + M1 - 1) / M1)), dim3(4 * M1), 0, s, B, X, ldx, K,
                      Kx, rowscale, nullptr, W1b, b1, H1, nullptr, nullptr, P, nullptr);
-  hipLaunchKernelGGL((k_mlp_bf16<false, M2>), dim3((unsigned)((B + M2 - 1) / M2)), dim3(4 * M2), 0, s, B, nullptr,
+  hipLaunchKernelGGL((k_mlp_bf16<false, M2, WR2>), dim3((unsigned)((B + M2 - 1) / M2)), dim3(4 * M2 * (64 / WR2)), 0,
+                     s, B, nullptr,
                      (int64_t)0, MB_H, MB_H, nullptr, H1, W2b, b2, nullptr, W3, b3, P, Y);
 }
 
