@@ -463,7 +463,10 @@ def cpu_baseline(Dd, Z, sample, answers):
         ok = c >= ref["corr"] - 1e-6
         tr = Dd.params[ref["idx"], :2]
         relp = np.abs(Dd.params[j, :2] - tr) / tr
-        pde = np.abs(pd[:sample].astype(np.float64) - ref["gamma"]) / np.maximum(ref["gamma"], 1e-12)
+        # a compressed handle's atoms are the compressed normalised atoms: its PD is the
+        # one of a unit-norm atom, max(score, 0), not that of the raw atom
+        gref = np.maximum(ref["score"], 0.0) if name.startswith("subspace") else ref["gamma"]
+        pde = np.abs(pd[:sample].astype(np.float64) - gref) / np.maximum(gref, 1e-12)
         grade[name] = {"index_mismatch": float(np.mean(j != ref["idx"])),
                        "index_mismatch_outside_near_ties": float(np.mean(~ok)),
                        "t1_rel_err_max": float(relp[:, 0].max()), "t2_rel_err_max": float(relp[:, 1].max()),

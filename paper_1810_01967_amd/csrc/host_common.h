@@ -87,8 +87,14 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
 mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
                       int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
                       hipEvent_t ev_s0, hipEvent_t ev_s1, int *splits_used, mrf_match_stats *st);
+// want_fp32 = false leaves out the FP32 rows of a voxel-major packing that
+// writes the split rows (see learned_split_rows_only)
 mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t slice_voxels,
-                       int64_t n, hipStream_t s, bool want_x3 = false);
+                       int64_t n, hipStream_t s, bool want_x3 = false, bool want_fp32 = true);
+// True when a learned match reads the voxels only as split-BF16 rows: split
+// BF16 scoring, no warm start, no cover-tree fallback, and (unless the
+// caller gives the cells) a network whose BF16 form reads the split rows.
+bool learned_split_rows_only(const mrf_dict_s *D, const mrf_match_opts *o, const int32_t *warm, bool cells_given);
 mrf_status check_opts(const mrf_dict_s *D, const mrf_match_opts *o);
 mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
                       int32_t *idx, float *pd, float *corr, float *params_out, mrf_match_stats *st,
@@ -128,6 +134,7 @@ struct mrf_dict_s {
   // workspace (grows lazily)
   mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j, zx3;
   bool zx3_fresh = false;  // zx3 holds the split rows of the current packing (written by the pack)
+  bool zp_fresh = false;   // zp holds the FP32 rows of the current packing
   mrf::DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;
   // temporal subspace (a compressed dictionary: atoms V^H Dhat_j of L = s frames)
   int Lfull = 0;                    // frames of the uncompressed dictionary, 0 if not compressed

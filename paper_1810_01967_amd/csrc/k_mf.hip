@@ -18,7 +18,8 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
   return x;
 }
 
-// One wave per voxel row (voxel-major input [n][L] complex64).
+// One wave per voxel row (voxel-major input [n][L] complex64).  Zp may be
+// null when only the split-BF16 rows are wanted.
 __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restrict__ Z, int64_t n,
                                                           int64_t n_pad, int L, int real_atoms,
                                                           int Kp, float *__restrict__ Zp,
@@ -29,11 +30,12 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
   const int lane = threadIdx.x & 63;
   const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (v >= n_pad) return;
-  float *row = Zp + v * Kp;
+  float *row = Zp ? Zp + v * Kp : nullptr;
   uint16_t *xrow = zx3 ? zx3 + v * 2 * Kx : nullptr;
   const int K = real_atoms ? L : 2 * L;
   if (v >= n) {
-    for (int k = lane; k < Kp; k += 64) row[k] = 0.f;
+    if (row)
+      for (int k = lane; k < Kp; k += 64) row[k] = 0.f;
     if (xrow)
       for (int k = lane; k < 2 * Kx; k += 64) xrow[k] = 0;
     return;
@@ -45,11 +47,13 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
     const float2 z0 = z[t];
     const float2 a = vphase ? make_float2(e.x * z0.x + e.y * z0.y, e.x * z0.y - e.y * z0.x) : z0;
     acc += (double)a.x * a.x + (double)a.y * a.y;
-    if (real_atoms) {
-      row[t] = a.x;
-    } else {
-      row[2 * t] = a.x;
-      row[2 * t + 1] = a.y;
+    if (row) {
+      if (real_atoms) {
+        row[t] = a.x;
+      } else {
+        row[2 * t] = a.x;
+        row[2 * t + 1] = a.y;
+      }
     }
     if (xrow) {  // split BF16 row, fused
       if (real_atoms) {
@@ -67,7 +71,8 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
       }
     }
   }
-  for (int k = K + lane; k < Kp; k += 64) row[k] = 0.f;
+  if (row)
+    for (int k = K + lane; k < Kp; k += 64) row[k] = 0.f;
   if (xrow)
     for (int k = K + lane; k < Kx; k += 64) {
       xrow[split_off(k)] = 0;
@@ -94,11 +99,12 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major2(const float2 *__restr
   const int lane = threadIdx.x & 63;
   const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (v >= n_pad) return;
-  float *row = Zp + v * Kp;
+  float *row = Zp ? Zp + v * Kp : nullptr;
   uint16_t *xrow = zx3 ? zx3 + v * 2 * Kx : nullptr;
   const int K = real_atoms ? L : 2 * L;
   if (v >= n) {
-    for (int k = lane; k < Kp; k += 64) row[k] = 0.f;
+    if (row)
+      for (int k = lane; k < Kp; k += 64) row[k] = 0.f;
     if (xrow)
       for (int k = lane; k < 2 * Kx; k += 64) xrow[k] = 0;
     return;
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major2(const float2 *__restr
     acc += (double)a0.x * a0.x + (double)a0.y * a0.y;
     acc += (double)a1.x * a1.x + (double)a1.y * a1.y;
     if (real_atoms) {
-      *reinterpret_cast<float2 *>(row + 2 * u) = make_float2(a0.x, a1.x);
+      if (row) *reinterpret_cast<float2 *>(row + 2 * u) = make_float2(a0.x, a1.x);
       if (xrow) {  // columns 2u, 2u + 1 share a 32-column chunk
         uint16_t h0, l0, h1, l1;
         split_bf16(a0.x, h0, l0);
@@ -126,7 +132,7 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major2(const float2 *__restr
         *reinterpret_cast<uint32_t *>(xrow + o + 32) = l0 | ((uint32_t)l1 << 16);
       }
     } else {
-      *reinterpret_cast<float4 *>(row + 4 * u) = make_float4(a0.x, a0.y, a1.x, a1.y);
+      if (row) *reinterpret_cast<float4 *>(row + 4 * u) = make_float4(a0.x, a0.y, a1.x, a1.y);
       if (xrow) {  // columns 4u .. 4u + 3 share a 32-column chunk
         uint16_t h[4], l[4];
         split_bf16(a0.x, h[0], l[0]);
@@ -141,7 +147,8 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major2(const float2 *__restr
       }
     }
   }
-  for (int k = K + lane; k < Kp; k += 64) row[k] = 0.f;
+  if (row)
+    for (int k = K + lane; k < Kp; k += 64) row[k] = 0.f;
   if (xrow)
     for (int k = K + lane; k < Kx; k += 64) {
       xrow[split_off(k)] = 0;

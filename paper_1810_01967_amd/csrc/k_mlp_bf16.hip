@@ -1,7 +1,11 @@
 // BF16 inference of the proposal network on gfx950 (v_mfma_f32_32x32x16_bf16,
 // FP32 accumulation), for hidden width 256:
 //   layer 1: h1 = GELU(x W1^T + b1), x = rowscale * X rounded to BF16, W1 in
-//            BF16; h1 is written in BF16;
+//            BF16; h1 is written in BF16.  The split-row form reads the BF16
+//            high parts of split voxel rows instead and scales the FP32
+//            accumulator: h1 = GELU(rowscale * (RNE_bf16(X) W1^T) + b1), the
+//            same network (linear in x before the bias) with the rounding
+//            taken before the scale;
 //   layer 2: h2 = GELU(h1 W2^T + b2) kept in FP32 and the output layer
 //            y = h2 W3^T + b3 (FP32 W3) fused into the same block.
 // A block computes all 256 hidden units of 256 rows (layer 1, sixteen waves)
@@ -10,6 +14,7 @@
 // chunks of 32.  Larger row tiles read the weights fewer times.
 #include <cmath>
 
+#include "k_split.h"
 #include "mrf_internal.h"
 
 namespace mrf {
@@ -55,9 +60,12 @@ void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t 
 
 // LAYER1 = true: A = FP32 rows X (pitch ldx, K valid columns, K % 8 == 0,
 // ldx % 4 == 0) times rowscale, W = W1 BF16 [256][Kx]; writes H1 BF16 [B][256].
+// LAYER1 and SPLIT: A = the high parts of split rows H1in (2 Kx BF16 per row,
+// pitch ldx elements; zero beyond the valid columns), rowscale applied to
+// the accumulator.
 // LAYER1 = false: A = H1 BF16 [B][256], W = W2 BF16 [256][256]; writes Y [B][P].
 // WR: rows per wave (64, or 32 for twice the waves on the same row tile).
-template <bool LAYER1, int MB_M, int WR>
+template <bool LAYER1, int MB_M, int WR, bool SPLIT = false>
 __global__ __launch_bounds__(4 * MB_M * (64 / WR)) void k_mlp_bf16(int64_t B, const float *__restrict__ X, int64_t ldx, int K,
                                                      int Kx, const float *__restrict__ rowscale,
                                                      const uint16_t *__restrict__ H1in,
@@ -84,13 +92,16 @@ __global__ __launch_bounds__(4 * MB_M * (64 / WR)) void k_mlp_bf16(int64_t B, co
   const bool aload = lr < MB_M;
   const int64_t arow = m0 + lr;
   const bool avalid = aload && arow < B;
-  const float sc = (LAYER1 && avalid) ? (rowscale ? rowscale[arow] : 1.f) : 0.f;
+  const float sc = (LAYER1 && !SPLIT && avalid) ? (rowscale ? rowscale[arow] : 1.f) : 0.f;
   uint4 ra[MB_PC], rw[NW][MB_PC];
   auto gload = [&](int kc) {
 #pragma unroll
     for (int c = 0; c < MB_PC; ++c) {
       const int k = kc * MB_BK + lc + 8 * c;
-      if constexpr (LAYER1) {
+      if constexpr (LAYER1 && SPLIT) {  // 8 high parts of one 32-column chunk
+        ra[c] = avalid ? *reinterpret_cast<const uint4 *>(H1in + arow * ldx + split_off(k))
+                       : make_uint4(0u, 0u, 0u, 0u);
+      } else if constexpr (LAYER1) {
         float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (avalid && k < K) {
           const float4 x0 = *reinterpret_cast<const float4 *>(X + arow * ldx + k);
@@ -166,7 +177,10 @@ __global__ __launch_bounds__(4 * MB_M * (64 / WR)) void k_mlp_bf16(int64_t B, co
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int64_t m = m0 + wr + mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-          if (m < B) H1out[m * MB_H + n] = to_bf16(gelu_exact(acc[mi][ni][i] + bn));
+          if (m < B) {
+            const float a = SPLIT ? acc[mi][ni][i] * (rowscale ? rowscale[m] : 1.f) : acc[mi][ni][i];
+            H1out[m * MB_H + n] = to_bf16(gelu_exact(a + bn));
+          }
         }
     }
   } else {
@@ -220,6 +234,18 @@ void launch_mlp_bf16(int64_t B, const float *X, int64_t ldx, int K, int Kx, cons
   constexpr int WR2 = MRF_MLP_WR2;  // rows per wave of the second layer (a tuning constant)
   hipLaunchKernelGGL((k_mlp_bf16<true, M1, 64>), dim3((unsigned)((B + M1 - 1) / M1)), dim3(4 * M1), 0, s, B, X, ldx, K,
                      Kx, rowscale, nullptr, W1b, b1, H1, nullptr, nullptr, P, nullptr);
+  hipLaunchKernelGGL((k_mlp_bf16<false, M2, WR2>), dim3((unsigned)((B + M2 - 1) / M2)), dim3(4 * M2 * (64 / WR2)), 0,
+                     s, B, nullptr,
+                     (int64_t)0, MB_H, MB_H, nullptr, H1, W2b, b2, nullptr, W3, b3, P, Y);
+}
+
+void launch_mlp_bf16_split(int64_t B, const uint16_t *Xs, int64_t ldxs, int Kx, const float *rowscale,
+                           const uint16_t *W1b, const float *b1, uint16_t *H1, const uint16_t *W2b, const float *b2,
+                           const float *W3, const float *b3, int P, float *Y, hipStream_t s) {
+  if (B <= 0) return;
+  constexpr int M1 = MRF_MLP_M1, M2 = MRF_MLP_M2, WR2 = MRF_MLP_WR2;
+  hipLaunchKernelGGL((k_mlp_bf16<true, M1, 64, true>), dim3((unsigned)((B + M1 - 1) / M1)), dim3(4 * M1), 0, s, B,
+                     nullptr, ldxs, Kx, Kx, rowscale, Xs, W1b, b1, H1, nullptr, nullptr, P, nullptr);
   hipLaunchKernelGGL((k_mlp_bf16<false, M2, WR2>), dim3((unsigned)((B + M2 - 1) / M2)), dim3(4 * M2 * (64 / WR2)), 0,
                      s, B, nullptr,
                      (int64_t)0, MB_H, MB_H, nullptr, H1, W2b, b2, nullptr, W3, b3, P, Y);

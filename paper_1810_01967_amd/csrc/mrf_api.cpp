@@ -377,10 +377,14 @@ mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
 }
 
 mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t slice_voxels,
-                       int64_t n, hipStream_t s, bool want_x3) {
+                       int64_t n, hipStream_t s, bool want_x3, bool want_fp32) {
   const int64_t n_pad = round_up(n, kRowPad);
-  TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
+  // the voxel-major packing may leave out the FP32 rows (split rows only);
+  // the frame-major one always writes them
+  if (!want_x3 || z_layout != MRF_VOXEL_MAJOR) want_fp32 = true;
+  if (want_fp32) TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
   D->zx3_fresh = false;
+  D->zp_fresh = false;
   uint16_t *zx3 = nullptr;
   if (want_x3) {  // split-BF16 rows written by the packing itself
     TRY(grow(D->zx3, (size_t)n_pad * 2 * D->Kx * 2));
@@ -403,7 +407,7 @@ mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t s
   }
   if (z_layout == MRF_VOXEL_MAJOR)
     launch_pack_voxel_major(static_cast<const float2 *>(Z), n, n_pad, D->L, real, D->Kp,
-                            D->zp.as<float>(), D->znorm.as<float>(),
+                            want_fp32 ? D->zp.as<float>() : nullptr, D->znorm.as<float>(),
                             D->counters.as<unsigned long long>(), s, vph, zx3, D->Kx);
   else
     launch_pack_frame_major(static_cast<const float2 *>(Z), nullptr, 0.f, n, n_pad, slice_voxels,
@@ -411,6 +415,7 @@ mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t s
                             D->counters.as<unsigned long long>(), s, vph, zx3, D->Kx);
   LAUNCH_CHECK("pack");
   D->zx3_fresh = want_x3;
+  D->zp_fresh = want_fp32;
   return MRF_OK;
 }
 
@@ -443,7 +448,7 @@ extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t 
   }
   const int real = D->is_complex ? 0 : 1;
   const bool want_x3 = opts && opts->precision == MRF_BF16X3 && opts->method != MRF_COVERTREE;
-  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s, want_x3));
+  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s, want_x3, !learned_split_rows_only(D, opts, warm_idx, false)));
   int splits_used = 0;
   TRY(match_core(D, opts, n, warm_idx, idx, pd, corr, params_out, s, ev.c, ev.d, &splits_used, stats));
   const float2 *vph = D->align ? D->vphase.as<float2>() : nullptr;
@@ -758,6 +763,7 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
                           want_x3 ? D->zx3.as<uint16_t>() : nullptr, D->Kx);
   LAUNCH_CHECK("grad_update_pack");
   D->zx3_fresh = want_x3;
+  D->zp_fresh = true;
   TRY(match_core(D, o, n, warm, idx, pd, nullptr, nullptr, s, nullptr, nullptr, nullptr, nullptr));
   double *red = D->red.as<double>();
   int nb = 0;

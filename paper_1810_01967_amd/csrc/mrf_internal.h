@@ -282,6 +282,12 @@ void launch_to_bf16(const float *src, int rows, int cols, int64_t lds, uint16_t 
 void launch_mlp_bf16(int64_t B, const float *X, int64_t ldx, int K, int Kx, const float *rowscale,
                      const uint16_t *W1b, const float *b1, uint16_t *H1, const uint16_t *W2b, const float *b2,
                      const float *W3, const float *b3, int P, float *Y, hipStream_t s);
+// The same network with layer 1 reading the high parts of split-BF16 rows Xs
+// (pitch ldxs elements, Kx columns, Kx a multiple of the K stage) and
+// applying rowscale to its accumulator.
+void launch_mlp_bf16_split(int64_t B, const uint16_t *Xs, int64_t ldxs, int Kx, const float *rowscale,
+                           const uint16_t *W1b, const float *b1, uint16_t *H1, const uint16_t *W2b, const float *b2,
+                           const float *W3, const float *b3, int P, float *Y, hipStream_t s);
 // FP32 rows [rows][Kp] -> split-BF16 rows of Kx/32 chunks [hi 32 | lo 32]
 // (hi = RNE(x), lo = RNE(x - hi), zero beyond Kp); and back to [rows][hi K | lo K].
 void launch_split_x3(const float *src, int Kp, int64_t rows, int Kx, uint16_t *dst, hipStream_t s);

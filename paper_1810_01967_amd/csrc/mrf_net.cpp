@@ -302,27 +302,61 @@ bool net_bf16_ok(const mrf_net_s *net, int64_t K, int64_t ldx) {
   return net->H == 256 && net->P <= 8 && K % 8 == 0 && ldx % 4 == 0 && K <= round_up(net->I, kMlpBK);
 }
 
-// X: [B][ldx] FP32 with K readable columns (columns >= I meet zero weights).
-mrf_status net_forward_bf16(mrf_net_s *net, const float *X, int64_t ldx, int64_t K, int64_t B,
-                            const float *rowscale, float *Y, uint16_t *h1, hipStream_t s) {
+// The network reads split-BF16 voxel rows of D directly: the BF16 form, and
+// W1's padded width within the split rows' columns.
+bool net_split_ok(const mrf_net_s *net, const mrf_dict_s *D) {
+  return net->H == 256 && net->P <= 8 && net->I == D->K && round_up(net->I, kMlpBK) <= D->Kx;
+}
+
+// BF16 copies of W1 ([H][Kx], Kx = I rounded up to the K stage) and W2, made
+// once per weight version; the wait lets later calls on any stream use them.
+static mrf_status net_bf16_weights(mrf_net_s *net, hipStream_t s, uint16_t **w1b, uint16_t **w2b, int *Kx) {
   const int H = net->H, I = net->I;
-  const int Kx = (int)round_up(I, kMlpBK);
-  TRY(grow(net->wb, ((size_t)H * Kx + (size_t)H * H) * 2));
+  *Kx = (int)round_up(I, kMlpBK);
+  TRY(grow(net->wb, ((size_t)H * *Kx + (size_t)H * H) * 2));
   const float *w = net->w.as<float>();
-  uint16_t *w1b = net->wb.as<uint16_t>(), *w2b = w1b + (size_t)H * Kx;
+  *w1b = net->wb.as<uint16_t>();
+  *w2b = *w1b + (size_t)H * *Kx;
   if (net->wbver != net->wver) {
-    // BF16 weights made once per weight version; the wait lets later calls
-    // on any stream use them
-    launch_to_bf16(w + net->oW1, H, I, I, w1b, Kx, s);
-    launch_to_bf16(w + net->oW2, H, H, H, w2b, H, s);
+    launch_to_bf16(w + net->oW1, H, I, I, *w1b, *Kx, s);
+    launch_to_bf16(w + net->oW2, H, H, H, *w2b, H, s);
     LAUNCH_CHECK("network weights to bf16");
     HIP_TRY(hipStreamSynchronize(s));
     net->wbver = net->wver;
   }
+  return MRF_OK;
+}
+
+// X: [B][ldx] FP32 with K readable columns (columns >= I meet zero weights).
+mrf_status net_forward_bf16(mrf_net_s *net, const float *X, int64_t ldx, int64_t K, int64_t B,
+                            const float *rowscale, float *Y, uint16_t *h1, hipStream_t s) {
+  uint16_t *w1b, *w2b;
+  int Kx;
+  TRY(net_bf16_weights(net, s, &w1b, &w2b, &Kx));
+  const float *w = net->w.as<float>();
   launch_mlp_bf16(B, X, ldx, (int)K, Kx, rowscale, w1b, w + net->ob1, h1, w2b, w + net->ob2, w + net->oW3,
                   w + net->ob3, net->P, Y, s);
   LAUNCH_CHECK("net forward (bf16)");
   return MRF_OK;
+}
+
+// Xs: split-BF16 rows of D ([B][2 D->Kx]); requires net_split_ok(net, D).
+static mrf_status net_forward_bf16_split(mrf_net_s *net, const mrf_dict_s *D, const uint16_t *Xs, int64_t B,
+                                         const float *rowscale, float *Y, uint16_t *h1, hipStream_t s) {
+  uint16_t *w1b, *w2b;
+  int Kx;
+  TRY(net_bf16_weights(net, s, &w1b, &w2b, &Kx));
+  const float *w = net->w.as<float>();
+  launch_mlp_bf16_split(B, Xs, 2 * (int64_t)D->Kx, Kx, rowscale, w1b, w + net->ob1, h1, w2b, w + net->ob2,
+                        w + net->oW3, w + net->ob3, net->P, Y, s);
+  LAUNCH_CHECK("net forward (bf16, split rows)");
+  return MRF_OK;
+}
+
+bool learned_split_rows_only(const mrf_dict_s *D, const mrf_match_opts *o, const int32_t *warm, bool cells_given) {
+  if (!D || !o || o->method != MRF_LEARNED || o->precision != MRF_BF16X3 || warm) return false;
+  if (D->has_tree && o->eps >= 0.f) return false;  // the cover-tree fallback reads the FP32 rows
+  return cells_given || (o->net && net_split_ok(o->net, D));
 }
 
 }  // namespace mrf
@@ -528,6 +562,9 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   const int P = D->nparam;
   const int r = o->box_radius > 0 ? o->box_radius : 3;
   const float thr = o->fallback_corr == 0.f ? 0.98f : o->fallback_corr;
+  // the packing leaves out the FP32 rows only where nothing below reads them
+  if (!D->zp_fresh && !learned_split_rows_only(D, o, warm, cells_in != nullptr))
+    return fail(MRF_E_UNSUPPORTED, "learned match: the voxels were packed without their FP32 rows");
   GridDims g;
   for (int p = 0; p < 4; ++p) g.dims[p] = p < P ? D->grid_dims[(size_t)p] : 1;
   EventPair ev;
@@ -571,7 +608,10 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     TRY(grow(D->yout, (size_t)n * P * 4));
     if (st) HIP_TRY(hipEventRecord(e_prop0, s));
     launch_inv_norm(D->znorm.as<float>(), n, D->inv.as<float>(), s);
-    if (net_bf16_ok(net, D->Kp, D->Kp))
+    if (o->precision == MRF_BF16X3 && D->zx3_fresh && net_split_ok(net, D))
+      TRY(net_forward_bf16_split(net, D, D->zx3.as<uint16_t>(), n, D->inv.as<float>(), D->yout.as<float>(),
+                                 D->h1.as<uint16_t>(), s));
+    else if (net_bf16_ok(net, D->Kp, D->Kp))
       TRY(net_forward_bf16(net, D->zp.as<float>(), D->Kp, D->Kp, n, D->inv.as<float>(), D->yout.as<float>(),
                            D->h1.as<uint16_t>(), s));
     else
@@ -808,7 +848,8 @@ extern "C" mrf_status mrf_match_local(mrf_dict D, const mrf_match_opts *opts, in
     HIP_TRY(hipEventCreate(&ev.b));
     HIP_TRY(hipEventRecord(ev.a, s));
   }
-  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s, opts && opts->precision == MRF_BF16X3));
+  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s, opts && opts->precision == MRF_BF16X3,
+                  !learned_split_rows_only(D, opts, warm_idx, true)));
   TRY(match_learned(D, opts, n, warm_idx, idx, pd, corr, params_out, cells, fallback, stats, s));
   if (X_out) {
     launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, D->is_complex ? 0 : 1, n, D->L,

@@ -401,3 +401,40 @@ def test_recentre_rounds_never_lower_the_score(m, small_dict):
     assert res[0][1] == 0
     assert np.all(res[3][0] >= res[0][0]) and np.all(res[16][0] >= res[3][0])
     assert res[16][1] >= res[3][1] > 0
+
+
+def test_split_row_proposal(m, small_dict):
+    """With split-BF16 scoring, no warm start and no cover tree, the learned
+    path packs only the split rows and the network reads their BF16 high
+    parts, scaling its first layer's accumulator by 1/||Z_v|| (the same network
+    with the input rounded before the scale).  Its proposals must serve as the
+    FP32-row form's do: the same fallback and re-centring counts up to a few
+    voxels, and every answer exact up to near-ties, on a ragged voxel count;
+    a warm-started call between two such calls packs the FP32 rows again."""
+    banner("learned split-BF16 path, network on split rows, n=3001")
+    Dd = small_dict
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    net = m.Net(D.info().K, 3, hidden=256, seed=21)
+    m.mrf_net_train(net, D, samples=262144, batch=4096, epochs=3, lr=1e-3, lr_min=1e-5, snr_lo=15.0, snr_hi=40.0,
+                    seed=22)
+    n = 3001
+    Z, jt, pd, snr = workloads.random_voxels(Dd, n, seed=23, snr_db_range=(10.0, 40.0))
+    Zd = dev(c64(Z))
+    Zc = c64(Z).astype(np.complex128)
+    o32 = m.mrf_match(D, Zd, net=net, precision="fp32", box_radius=3, fallback_corr=0.98, recentre=2, stats=True)
+    res = []
+    for rep in range(2):
+        ox = m.mrf_match(D, Zd, net=net, precision="bf16x3", box_radius=3, fallback_corr=0.98, recentre=2,
+                         stats=True)
+        res.append(host(ox["idx"]))
+        s32, sx = o32["stats"], ox["stats"]
+        print(f"fallbacks fp32 rows {s32.fallbacks} split rows {sx.fallbacks}; recentred {s32.recentred} / "
+              f"{sx.recentred}")
+        assert abs(sx.fallbacks - s32.fallbacks) <= max(3, s32.fallbacks // 20)
+        assert abs(sx.recentred - s32.recentred) <= max(3, s32.recentred // 20)
+        assert np.all(mf.index_ok(Zc, Dd.atoms, res[-1].astype(np.int64), tol=1e-5))
+        if rep == 0:  # warm-started: the FP32 rows are packed for the warm atom's score
+            ow = m.mrf_match(D, Zd, net=net, precision="bf16x3", box_radius=3, fallback_corr=0.98, recentre=2,
+                             warm_idx=ox["idx"])
+            assert np.all(mf.index_ok(Zc, Dd.atoms, host(ow["idx"]).astype(np.int64), tol=1e-5))
+    np.testing.assert_array_equal(res[0], res[1])
