@@ -26,7 +26,8 @@ constexpr int MB_H = 256;   // hidden units (= block columns)
 constexpr int MB_BK = kMlpBK;    // K per stage
 constexpr int MB_LD = MB_BK + 8; // LDS row pitch in BF16 (8 of padding)
 constexpr int MB_PC = MB_BK / 32;  // 8-element pieces per thread and row per stage
-constexpr int MB_HLD = 260; // LDS row pitch of the FP32 h2 tile
+constexpr int MB_HLD = 260; // LDS row pitch of the FP32 h2 tile: 4 quarters of 64 units at stride 65
+__device__ __forceinline__ int hq(int n) { return (n >> 6) * 65 + (n & 63); }  // unit n within a row
 // rows per block of the two launches (tuning constants: 4 threads per row)
 #ifndef MRF_MLP_M1
 #define MRF_MLP_M1 256
@@ -77,7 +78,9 @@ __global__ __launch_bounds__(4 * MB_M * (64 / WR)) void k_mlp_bf16(int64_t B, co
   constexpr int MI = WR / 32;                   // 32-row tiles per wave
   constexpr int NW = MB_H * 4 / NT;             // W chunks of 8 per thread per stage
   constexpr int STAGE = (MB_M + MB_H) * MB_LD;  // BF16 elements per stage
-  constexpr int SMEM = LAYER1 ? 2 * STAGE * 2 : (MB_M * MB_HLD * 4 > 2 * STAGE * 2 ? MB_M * MB_HLD * 4 : 2 * STAGE * 2);
+  // layer 2: the FP32 h2 tile and W3 (at most 8 rows) share the stage space
+  constexpr int SMEM = LAYER1 ? 2 * STAGE * 2
+                              : ((MB_M + 8) * MB_HLD * 4 > 2 * STAGE * 2 ? (MB_M + 8) * MB_HLD * 4 : 2 * STAGE * 2);
   __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
@@ -185,6 +188,8 @@ __global__ __launch_bounds__(4 * MB_M * (64 / WR)) void k_mlp_bf16(int64_t B, co
     }
   } else {
     float *Hs = reinterpret_cast<float *>(smem);
+    float *W3s = Hs + MB_M * MB_HLD;  // [P][MB_HLD], the h2 row layout
+    for (int e = tid; e < P * MB_H; e += NT) W3s[(e / MB_H) * MB_HLD + hq(e % MB_H)] = W3[e];
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) {
       const int n = wn + ni * 32 + l32;
@@ -193,22 +198,24 @@ __global__ __launch_bounds__(4 * MB_M * (64 / WR)) void k_mlp_bf16(int64_t B, co
       for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
-          Hs[(wr + mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3)) * MB_HLD + n] = gelu_exact(acc[mi][ni][i] + bn);
+          Hs[(wr + mi * 32 + 8 * (i >> 2) + 4 * h + (i & 3)) * MB_HLD + hq(n)] = gelu_exact(acc[mi][ni][i] + bn);
     }
     __syncthreads();
     // y[m][p]: thread t < 4 MB_M sums units [64 (t & 3), +64) of row t / 4 in
-    // a fixed order, then the four partial sums are added in a fixed order
+    // a fixed order, then the four partial sums are added in a fixed order;
+    // the 65-word quarter stride puts a wave's 16 rows x 4 quarters in 64
+    // distinct banks, and W3 reads are broadcasts
     if (tid >= 4 * MB_M) return;  // whole waves
     const int row = tid >> 2, part = tid & 3;
     float yp[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p) yp[p] = 0.f;
     for (int c = 0; c < 64; ++c) {
-      const int n = part * 64 + c;
-      const float hv = Hs[row * MB_HLD + n];
+      const int q = part * 65 + c;
+      const float hv = Hs[row * MB_HLD + q];
 #pragma unroll
       for (int p = 0; p < 8; ++p)
-        if (p < P) yp[p] = fmaf(hv, W3[p * MB_H + n], yp[p]);
+        if (p < P) yp[p] = fmaf(hv, W3s[p * MB_HLD + q], yp[p]);
     }
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
