@@ -326,7 +326,12 @@ mrf_status mrf_net_forward(mrf_net net, const float *X, int64_t B, float *Y, mrf
  * in_dim a multiple of 8, else MRF_E_UNSUPPORTED): X, W1 and W2 rounded to
  * BF16 (nearest, ties to even), products accumulated in FP32, the first
  * hidden layer rounded to BF16 after its GELU, the second kept in FP32, the
- * output layer in FP32.  Same arguments as mrf_net_forward. */
+ * output layer in FP32.  Inside mrf_match with MRF_FP32 scoring the network
+ * reads X = Z_v/||Z_v||, rounded after the scale; with MRF_BF16X3 scoring it
+ * reads the BF16 high parts of the split voxel rows, RNE(Z_v), and divides
+ * its first layer's FP32 accumulator by ||Z_v|| (the same network, the input
+ * rounded before the scale; the proposals differ by rounding only).  Same
+ * arguments as mrf_net_forward. */
 mrf_status mrf_net_forward_bf16(mrf_net net, const float *X, int64_t B, float *Y, mrf_stream stream);
 /* Mean-squared loss against T (DEVICE [B][nout]) and its gradients (kept in
  * the net; mrf_net_get_grads reads them).  loss (HOST, may be NULL) forces a
