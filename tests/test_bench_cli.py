@@ -43,3 +43,26 @@ def test_traffic_follows_the_counted_source(bench_module, tmp_path, monkeypatch)
     summary.unlink()
     assert b.measured_traffic("k.hip") is None
 
+
+
+def test_grading_of_compressed_pd(bench_module):
+    """The bench grades each path's PD against the oracle's: the full
+    dictionary's PD is that of the raw atom (eq. exactPs), a compressed
+    handle's is that of its unit-norm compressed atom, max(score, 0).  The
+    oracle's own answers in each convention grade as exact."""
+    import numpy as np
+    from oracle import mf
+    from synth import workloads
+    Dd = workloads.bssfp_dictionary(L=40, n_t1=8, n_t2=8, n_df=3, seed=2)
+    Z, _, _, _ = workloads.random_voxels(Dd, 64, seed=3)
+    ref = mf.exact_mf(Z.astype(np.complex128), Dd.atoms)
+    answers = {"exhaustive_fp32": (ref["idx"], ref["gamma"]),
+               "subspace20_fp32": (ref["idx"], np.maximum(ref["score"], 0.0)),
+               "subspace200_fp32": (ref["idx"], ref["gamma"])}
+    _, grade = bench_module.cpu_baseline(Dd, Z, 64, answers)
+    assert grade["exhaustive_fp32"]["pd_rel_err_max"] == 0.0
+    assert grade["subspace20_fp32"]["pd_rel_err_max"] == 0.0
+    # the raw atom's PD is not a compressed handle's: the atoms here are not unit-norm
+    assert grade["subspace200_fp32"]["pd_rel_err_median"] > 1e-3
+    for g in (grade["exhaustive_fp32"], grade["subspace20_fp32"]):
+        assert g["index_mismatch"] == 0.0 and g["t1_rel_err_max"] == 0.0
