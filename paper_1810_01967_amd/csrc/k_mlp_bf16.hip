@@ -35,6 +35,9 @@ __device__ __forceinline__ int hq(int n) { return (n >> 6) * 65 + (n & 63); }  /
 #ifndef MRF_MLP_M2
 #define MRF_MLP_M2 128
 #endif
+#ifndef MRF_MLP_WR1
+#define MRF_MLP_WR1 64
+#endif
 
 __device__ __forceinline__ uint16_t to_bf16(float x) {
   uint32_t u = __float_as_uint(x);
@@ -239,7 +242,8 @@ void launch_mlp_bf16(int64_t B, const float *X, int64_t ldx, int K, int Kx, cons
 #define MRF_MLP_WR2 32
 #endif
   constexpr int WR2 = MRF_MLP_WR2;  // rows per wave of the second layer (a tuning constant)
-  hipLaunchKernelGGL((k_mlp_bf16<true, M1, 64>), dim3((unsigned)((B + M1 - 1) / M1)), dim3(4 * M1), 0, s, B, X, ldx, K,
+  constexpr int WR1 = MRF_MLP_WR1;  // rows per wave of the first layer (a tuning constant)
+  hipLaunchKernelGGL((k_mlp_bf16<true, M1, WR1>), dim3((unsigned)((B + M1 - 1) / M1)), dim3(4 * M1 * (64 / WR1)), 0, s, B, X, ldx, K,
                      Kx, rowscale, nullptr, W1b, b1, H1, nullptr, nullptr, P, nullptr);
   hipLaunchKernelGGL((k_mlp_bf16<false, M2, WR2>), dim3((unsigned)((B + M2 - 1) / M2)), dim3(4 * M2 * (64 / WR2)), 0,
                      s, B, nullptr,
@@ -250,8 +254,8 @@ void launch_mlp_bf16_split(int64_t B, const uint16_t *Xs, int64_t ldxs, int Kx, 
                            const uint16_t *W1b, const float *b1, uint16_t *H1, const uint16_t *W2b, const float *b2,
                            const float *W3, const float *b3, int P, float *Y, hipStream_t s) {
   if (B <= 0) return;
-  constexpr int M1 = MRF_MLP_M1, M2 = MRF_MLP_M2, WR2 = MRF_MLP_WR2;
-  hipLaunchKernelGGL((k_mlp_bf16<true, M1, 64, true>), dim3((unsigned)((B + M1 - 1) / M1)), dim3(4 * M1), 0, s, B,
+  constexpr int M1 = MRF_MLP_M1, M2 = MRF_MLP_M2, WR2 = MRF_MLP_WR2, WR1 = MRF_MLP_WR1;
+  hipLaunchKernelGGL((k_mlp_bf16<true, M1, WR1, true>), dim3((unsigned)((B + M1 - 1) / M1)), dim3(4 * M1 * (64 / WR1)), 0, s, B,
                      nullptr, ldxs, Kx, Kx, rowscale, Xs, W1b, b1, H1, nullptr, nullptr, P, nullptr);
   hipLaunchKernelGGL((k_mlp_bf16<false, M2, WR2>), dim3((unsigned)((B + M2 - 1) / M2)), dim3(4 * M2 * (64 / WR2)), 0,
                      s, B, nullptr,
