@@ -95,8 +95,9 @@ typedef struct {
 } mrf_dict_desc;
 
 /* Upload and normalise a dictionary (eq. fingerprints; atoms normalised as
- * the search of eq. exactP requires).  An atom of zero norm is rejected
- * (MRF_E_INVAL).  On success *out is a new handle; the host arrays may be
+ * the search of eq. exactP requires).  An atom of zero or non-finite norm,
+ * or a non-finite parameter, is rejected (MRF_E_INVAL) before any device
+ * call.  On success *out is a new handle; the host arrays may be
  * freed after the call returns (the upload completes before return). */
 mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream stream, mrf_dict *out);
 /* Release the handle and all device memory it owns (NULL is accepted). */

@@ -84,6 +84,24 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
     }
     if (prod != q.d) return fail(MRF_E_INVAL, "mrf_dict_build: grid_dims product %lld != d %d", (long long)prod, q.d);
   }
+  // atom norms in FP64 first: a zero or non-finite atom is rejected before
+  // any device call
+  std::vector<double> anorm((size_t)q.d);
+  for (int64_t j = 0; j < q.d; ++j) {
+    double nrm2 = 0.0;
+    if (q.atoms_dtype == MRF_F64) {
+      const double *a = static_cast<const double *>(q.atoms) + j * K;
+      for (int64_t k = 0; k < K; ++k) nrm2 += a[k] * a[k];
+    } else {
+      const float *a = static_cast<const float *>(q.atoms) + j * K;
+      for (int64_t k = 0; k < K; ++k) nrm2 += (double)a[k] * a[k];
+    }
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+      return fail(MRF_E_INVAL, "mrf_dict_build: atom %lld has zero or non-finite norm", (long long)j);
+    anorm[(size_t)j] = std::sqrt(nrm2);
+  }
+  for (int64_t i = 0; i < (int64_t)q.d * q.nparam; ++i)
+    if (!std::isfinite(q.params[i])) return fail(MRF_E_INVAL, "mrf_dict_build: non-finite parameter %lld", (long long)i);
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto *D = new mrf_dict_s();
   std::unique_ptr<mrf_dict_s> guard(D);
@@ -117,23 +135,15 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
     std::fill(stage.begin(), stage.end(), 0.f);
     for (int64_t j = r0; j < r1; ++j) {
       if (j >= q.d) continue;
-      double nrm2 = 0.0;
+      const double nrm = anorm[(size_t)j];
       if (q.atoms_dtype == MRF_F64) {
         const double *a = static_cast<const double *>(q.atoms) + j * K;
-        for (int64_t k = 0; k < K; ++k) nrm2 += a[k] * a[k];
-        if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
-          return fail(MRF_E_INVAL, "mrf_dict_build: atom %lld has zero or non-finite norm", (long long)j);
-        const double nrm = std::sqrt(nrm2);
         for (int64_t k = 0; k < K; ++k) stage[(size_t)(j - r0) * D->Kp + k] = (float)(a[k] / nrm);
         if (tree)
           for (int64_t k = 0; k < K; ++k) xnorm[(size_t)(j * K + k)] = a[k] / nrm;
         inv[(size_t)j] = (float)(1.0 / nrm);
       } else {
         const float *a = static_cast<const float *>(q.atoms) + j * K;
-        for (int64_t k = 0; k < K; ++k) nrm2 += (double)a[k] * a[k];
-        if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
-          return fail(MRF_E_INVAL, "mrf_dict_build: atom %lld has zero or non-finite norm", (long long)j);
-        const double nrm = std::sqrt(nrm2);
         for (int64_t k = 0; k < K; ++k) stage[(size_t)(j - r0) * D->Kp + k] = (float)((double)a[k] / nrm);
         if (tree)
           for (int64_t k = 0; k < K; ++k) xnorm[(size_t)(j * K + k)] = (double)a[k] / nrm;

@@ -188,3 +188,98 @@ def test_ipg_solve_adaptive_dcf(m):
           f"f gpu {f[-1]:.5e} oracle {fr[-1]:.5e}, nmse gpu {nm_g:.4e} oracle {nm_o:.4e}")
     assert abs(f[-1] - fr[-1]) < 0.02 * fr[-1]
     assert abs(nm_g - nm_o) < 0.05 * nm_o
+
+
+def _robust_tolerance(r, m_min=2, margin=0.05):
+    """A relative-progress tolerance first met at iteration m with a relative
+    margin on both sides (FP32 objectives move r by ~1e-6), or None."""
+    for m in range(m_min, len(r)):
+        lo = float(np.min(r[:m]))
+        if r[m] > 0 and lo > r[m] * (1 + 4 * margin):
+            return m, r[m] * (1 + 2 * margin)
+    return None
+
+
+def test_ipg_solve_relative_progress_stop(m):
+    """The relative-progress stop (section "Numerical experiments"): the GPU
+    solve ends at the same iteration as the oracle's solve with the same
+    tolerance, with the same objective history."""
+    banner("ipg solve 64x64 L=100 adaptive rel_tol stop")
+    Dd, ph, smp, Y = _fisp_problem()
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    A = m.Operator.from_sampling(smp)
+    mu0 = 64 / 6
+    common = dict(mu0=mu0, zeta=2.0, adaptive=True)
+    _, _, _, full = ipg.ipg_solve(Y, smp.off, smp.idx, (1, Dd.L, 64, 64), Dd.atoms, max_iter=12, rel_tol=0,
+                                  **common)
+    f0 = float(np.sum(np.abs(Y.astype(np.complex128)) ** 2))
+    f = np.array([f0] + [h["f"] for h in full])
+    r = (f[:-1] - f[1:]) / f[:-1]
+    picked = _robust_tolerance(r)
+    assert picked is not None, r
+    mstop, tol = picked
+    _, _, _, ho = ipg.ipg_solve(Y, smp.off, smp.idx, (1, Dd.L, 64, 64), Dd.atoms, max_iter=12, rel_tol=tol,
+                                **common)
+    assert len(ho) == mstop + 1
+    X, idx, pd, params, hist = m.mrf_ipg_solve(D, A, dev(Y), max_iter=12, rel_tol=tol, **common)
+    print(f"rel_tol {tol:.4e}: oracle stops after {len(ho)}, gpu after {hist['iters']}; "
+          f"progress {np.array2string(r, precision=4)}")
+    assert hist["iters"] == len(ho)
+    np.testing.assert_allclose(hist["f"], [h["f"] for h in ho], rtol=2e-3)
+    np.testing.assert_allclose(hist["mu"], [h["mu"] for h in ho], rtol=1e-6)
+    # the library default (1e-6) ends by itself before a large iteration cap
+    _, _, _, _, hd = m.mrf_ipg_solve(D, A, dev(Y), max_iter=200, **common)
+    assert 1 <= hd["iters"] < 200
+
+
+def test_ipg_solve_kappa_rescaling(m):
+    """kappa = ||Y|| / ||A X^1|| with plain norms (section "CoverBLIP
+    algorithm", after eq. steprule) under DCF weights: the GPU solve's step
+    sizes and objective history against the oracle's."""
+    banner("ipg solve spiral DCF kappa")
+    Dd, ph, smp, Y = _spiral_problem()
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    A = m.Operator.from_sampling(smp)
+    for adaptive, mu0 in ((False, 1.0), (True, 4096 / 205)):
+        common = dict(mu0=mu0, zeta=2.0, adaptive=adaptive, max_iter=4, rel_tol=0)
+        _, _, _, hr = ipg.ipg_solve(Y, smp.off, smp.idx, (1, 100, 64, 64), Dd.atoms, w=smp.dcf, kappa=True,
+                                    **common)
+        X1, _, _, _ = ipg.ipg_solve(Y, smp.off, smp.idx, (1, 100, 64, 64), Dd.atoms, w=smp.dcf,
+                                    **dict(common, max_iter=1))
+        X1k, _, _, _ = ipg.ipg_solve(Y, smp.off, smp.idx, (1, 100, 64, 64), Dd.atoms, w=smp.dcf, kappa=True,
+                                     **dict(common, max_iter=1))
+        kap = np.vdot(X1, X1k).real / np.vdot(X1, X1).real
+        X, idx, pd, params, hist = m.mrf_ipg_solve(D, A, dev(Y), kappa=True, **common)
+        print(f"kappa (adaptive={adaptive}): oracle kappa {kap:.6f}; mu gpu {hist['mu']} oracle "
+              f"{[h['mu'] for h in hr]}; shrinks gpu {hist['shrinks']} oracle {[h['shrinks'] for h in hr]}")
+        assert hist["iters"] == len(hr) == 4
+        np.testing.assert_array_equal(hist["shrinks"], [h["shrinks"] for h in hr])
+        np.testing.assert_allclose(hist["mu"], [h["mu"] for h in hr], rtol=1e-5)
+        assert abs(hist["mu"][1] * 2.0 ** hist["shrinks"][1] / mu0 - kap) < 1e-5 * kap
+        np.testing.assert_allclose(hist["f"], [h["f"] for h in hr], rtol=2e-3)
+        # the first iterate carries the measurements' energy in the plain norm
+        if not adaptive:
+            _, _, _, _, h1 = m.mrf_ipg_solve(D, A, dev(Y), kappa=True, **dict(common, max_iter=1))
+            X1g = m.mrf_ipg_solve(D, A, dev(Y), kappa=True, **dict(common, max_iter=1))[0]
+            AX = fourier.forward(host(X1g).astype(np.complex128), smp.off, smp.idx)
+            ny = np.linalg.norm(Y.astype(np.complex128))
+            assert abs(np.linalg.norm(AX) - ny) < 1e-5 * ny
+
+
+def test_ipg_solve_shrink_cap_returns_noconv(m):
+    """max_shrinks = 0 with an oversized initial step: Algorithm 2's adaptive
+    rule cannot accept, and the call returns MRF_E_NOCONV (the oracle raises
+    NoConvergence on the same problem); the handle stays usable."""
+    banner("ipg solve shrink cap -> MRF_E_NOCONV")
+    Dd, ph, smp, Y = _fisp_problem()
+    with pytest.raises(ipg.NoConvergence):
+        ipg.ipg_solve(Y, smp.off, smp.idx, (1, Dd.L, 64, 64), Dd.atoms, mu0=1e6, adaptive=True, max_iter=2,
+                      rel_tol=0, max_shrinks=0)
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    A = m.Operator.from_sampling(smp)
+    with pytest.raises(m.MrfError) as ei:
+        m.mrf_ipg_solve(D, A, dev(Y), mu0=1e6, adaptive=True, max_iter=2, rel_tol=0.0, max_shrinks=0)
+    assert ei.value.status == m.MRF_E_NOCONV
+    assert "shrinks" in str(ei.value)
+    X, idx, pd, params, hist = m.mrf_ipg_solve(D, A, dev(Y), mu0=1.0, adaptive=False, max_iter=2, rel_tol=0.0)
+    assert hist["iters"] == 2

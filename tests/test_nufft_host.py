@@ -15,10 +15,16 @@ from synth import workloads
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.fixture(scope="module")
-def driver(tmp_path_factory):
+# the driver is built twice: optimised, and with the address and
+# undefined-behaviour sanitizers (any report aborts the run)
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+@pytest.fixture(scope="module", params=["O2", "asan-ubsan"])
+def driver(tmp_path_factory, request):
     exe = tmp_path_factory.mktemp("nufft") / "nufft_driver"
-    subprocess.run(["g++", "-O2", "-std=c++17", os.path.join(ROOT, "tests", "nufft_driver.cpp"), "-o", str(exe)],
+    opt = ["-O2"] if request.param == "O2" else SANITIZE
+    subprocess.run(["g++", *opt, "-std=c++17", os.path.join(ROOT, "tests", "nufft_driver.cpp"), "-o", str(exe)],
                    check=True)
     return str(exe)
 
