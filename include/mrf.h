@@ -241,6 +241,16 @@ typedef struct {
                             the complex PD rho_v on the normalised atom Dhat_j* with a
                             phase-aligned dictionary (mrf_dict_align), 0 otherwise; the
                             projected-gradient entry points ignore it (their X carries it) */
+  int32_t no_certificate; /* MRF_EXHAUSTIVE with MRF_FP32 or MRF_BF16X3.  0 (default): the
+                            exact argmax of eq. exactP over the FP32 normalised atoms,
+                            certified: the scoring pass keeps each voxel's 8 best atoms,
+                            whose scores are rescored exactly (FP64) while they lie within
+                            the pass's derived error bound of the best exact score; voxels
+                            whose 8 all lie within it are rescanned (every atom within the
+                            FP32 bound collected and rescored exactly, or, past 64 such
+                            atoms, all atoms rescored).  1: the scoring arithmetic's own
+                            argmax, uncertified (FP32 / split-BF16 rounding can pick an atom
+                            whose exact score is below the maximum by up to that bound). */
 } mrf_match_opts;
 
 typedef struct {
@@ -262,6 +272,9 @@ typedef struct {
   int32_t tree_levels;   /* MRF_COVERTREE: level launches */
   int64_t first_box_atoms; /* MRF_LEARNED: sum over the voxels of the first local-search
                               launch of their clipped box sizes (2 K flops each) */
+  int64_t cert_rescored;   /* certified exhaustive filter: atoms rescored exactly */
+  int64_t cert_rescanned;  /* ... voxels rescanned (all 8 listed atoms within the bound) */
+  int64_t cert_scanned;    /* ... voxels whose rescan exceeded 64 candidates (all atoms rescored) */
 } mrf_match_stats;
 
 /* Project n voxels onto cone(D).

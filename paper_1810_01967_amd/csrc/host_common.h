@@ -133,6 +133,10 @@ struct mrf_dict_s {
   mrf::DevBuf fbtot;  // device u64: voxels sent to the fallback by the learned path (all calls)
   // workspace (grows lazily)
   mrf::DevBuf zp, znorm, gamma, counters, part_s, part_j, zq, zscale, cand_s, cand_j, zx3;
+  // exactness certificate: counters (u32 queue, u32 scan, u64 rescored), queue
+  // (list, thr, candidate counts), scan list, candidates [n][kCertCap]
+  mrf::DevBuf cert, cert_list, cert_thr, cert_ccount, cert_scan, cert_cand;
+  bool cert_used = false;  // the last exhaustive match ran the certificate
   bool zx3_fresh = false;  // zx3 holds the split rows of the current packing (written by the pack)
   bool zp_fresh = false;   // zp holds the FP32 rows of the current packing
   mrf::DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;

@@ -4,6 +4,7 @@
 #include <cfloat>
 
 #include "k_split.h"
+#include "k_topk.h"
 #include "mrf_internal.h"
 
 namespace mrf {
@@ -296,15 +297,27 @@ void launch_pack_frame_major(const float2 *X, const float2 *G, float mu, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// exhaustive FP32 scoring with fused argmax
+// exhaustive FP32 scoring with a fused per-voxel epilogue
 // ---------------------------------------------------------------------------
 // Block tile: 128 atoms x 128 voxels, K chunks of 16, double-buffered LDS.
 // Four waves in a 2 x 2 arrangement, each owning 64 atoms x 64 voxels as
 // 2 x 2 MFMA 32x32x2 tiles.  Atoms are the MFMA rows (A operand) and voxels
 // the columns (B operand), so each lane accumulates one voxel column and 16
-// atom rows per tile: the running per-voxel maximum stays in registers and
-// atoms arrive in increasing index order, so a strict '>' keeps the lowest
-// index among equal scores.
+// atom rows per tile, and atoms reach a lane in increasing index order.
+// Epilogues (per voxel column, folded once per atom tile):
+//   SC_TOP1    the running maximum in registers (a strict '>' keeps the
+//              lowest index among equal scores);
+//   SC_TOPK    the kCertK best (score, atom) pairs among those within
+//              W_v = cw ||Z_v|| + wabs of the running maximum when they
+//              arrive (W_v > twice the scores' error bound, so every atom the
+//              exactness certificate needs is kept; the window makes
+//              insertions rare);
+//   SC_COLLECT every atom whose score reaches the voxel's threshold is
+//              appended to its candidate list (the certificate's rescan).
+// Work items (voxel tile, atom split) are dealt so all splits of a voxel tile
+// share an XCD (blocks are dealt to the 8 XCDs round-robin) and its L2.  With
+// the voxel count on the device (dcnt) a grid of a multiple of 8 blocks loops
+// over the items the count implies.
 constexpr int F_BA = 128, F_BV = 128, F_BK = 16, F_LDK = 20;
 
 __device__ __forceinline__ bool better(float s1, int j1, float s0, int j0) {
@@ -312,176 +325,307 @@ __device__ __forceinline__ bool better(float s1, int j1, float s0, int j0) {
   return (s1 > s0) || (s1 == s0 && j1 >= 0 && (j0 < 0 || j1 < j0));
 }
 
+// Atom splits of the FP32 filter for a device-side voxel count: about 2,048
+// work items, at most 256 splits and one split per 128-atom tile (a rescan of
+// a few voxel tiles still spreads over the whole chip).
+__device__ __forceinline__ int f32_device_splits(int nvt, int ntiles) {
+  const int nvt8 = (nvt + 7) / 8 * 8;
+  const int s = nvt8 > 0 ? (2048 + nvt8 - 1) / nvt8 : 1;
+  return max(1, min(s, min(ntiles, 256)));
+}
+
+struct CollectArgs {
+  const float *thr;     // [cap] per-voxel threshold
+  unsigned int *count;  // [cap] candidates found (may exceed ccap)
+  int32_t *cand;        // [cap][ccap] atom indices, unordered
+  int ccap;
+};
+
+template <int MODE>
 __global__ __launch_bounds__(256, 2) void k_score_f32(const float *__restrict__ D,
                                                       const float *__restrict__ Zp, int d,
                                                       int ntiles_total, int64_t n, int nvt,
                                                       int Kp, int splits, int tiles_per_split,
                                                       float *__restrict__ part_s,
-                                                      int *__restrict__ part_j) {
-  // block -> (voxel tile, atom split); all splits of one voxel tile land on
-  // the same XCD (blocks are dealt to the 8 XCDs round-robin), so they share
-  // the voxel tile through that XCD's L2.
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7, local = bid >> 3;
-  const int split = local % splits;
-  const int vt = (local / splits) * 8 + xcd;
-  if (vt >= nvt) return;
-  const int tb = split * tiles_per_split;
-  const int te = min(tb + tiles_per_split, ntiles_total);
+                                                      int *__restrict__ part_j, int64_t pstride,
+                                                      const unsigned int *__restrict__ dcnt,
+                                                      const int32_t *__restrict__ rowmap,
+                                                      CollectArgs col, const float *__restrict__ znorm,
+                                                      float cw, float wabs) {
+  int64_t nvox = n;
+  int nvt_w = nvt, nsplit = splits, tps = tiles_per_split;
+  if (dcnt) {
+    nvox = min(n, (int64_t)*dcnt);
+    nvt_w = (int)((nvox + F_BV - 1) / F_BV);
+    nsplit = f32_device_splits(nvt_w, ntiles_total);
+    tps = (ntiles_total + nsplit - 1) / nsplit;
+  }
+  const int64_t nwork = (int64_t)((nvt_w + 7) / 8 * 8) * nsplit;
 
   __shared__ float As[2][F_BA][F_LDK];
   __shared__ float Zs[2][F_BV][F_LDK];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wa = wave >> 1, wv = wave & 1;
-  const int h = lane >> 5, l32 = lane & 31;
-  const int64_t v0 = (int64_t)vt * F_BV;
-  const int nkc = Kp / F_BK;
-  const int nq = te > tb ? (te - tb) * nkc : 0;
+  for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const int xcd = (int)(w & 7);
+    const int64_t local = w >> 3;
+    const int split = (int)(local % nsplit);
+    const int vt = (int)((local / nsplit) * 8 + xcd);
+    if (vt >= nvt_w) continue;
+    const int tb = split * tps;
+    const int te = min(tb + tps, ntiles_total);
 
-  const int lr = tid >> 2, lc = (tid & 3) * 4;
-  float4 ra0, ra1, rz0, rz1;
-  auto gload = [&](int q) {
-    const int tile = tb + q / nkc, kc = q - (q / nkc) * nkc;
-    const float *a = D + (int64_t)(tile * F_BA + lr) * Kp + kc * F_BK + lc;
-    ra0 = *reinterpret_cast<const float4 *>(a);
-    ra1 = *reinterpret_cast<const float4 *>(a + (int64_t)64 * Kp);
-    const float *z = Zp + (v0 + lr) * Kp + kc * F_BK + lc;
-    rz0 = *reinterpret_cast<const float4 *>(z);
-    rz1 = *reinterpret_cast<const float4 *>(z + (int64_t)64 * Kp);
-  };
-  auto sstore = [&](int buf) {
-    *reinterpret_cast<float4 *>(&As[buf][lr][lc]) = ra0;
-    *reinterpret_cast<float4 *>(&As[buf][lr + 64][lc]) = ra1;
-    *reinterpret_cast<float4 *>(&Zs[buf][lr][lc]) = rz0;
-    *reinterpret_cast<float4 *>(&Zs[buf][lr + 64][lc]) = rz1;
-  };
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wa = wave >> 1, wv = wave & 1;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int64_t v0 = (int64_t)vt * F_BV;
+    const int nkc = Kp / F_BK;
+    const int nq = te > tb ? (te - tb) * nkc : 0;
 
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
-  float best[2] = {-INFINITY, -INFINITY};
-  int bidx[2] = {-1, -1};
-
-  if (nq > 0) {
-    gload(0);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int q = 0; q < nq; ++q) {
-    const int buf = q & 1;
-    if (q + 1 < nq) gload(q + 1);
-    float af[2][8], zf[2][8];
-#pragma unroll
-    for (int ma = 0; ma < 2; ++ma) {
-      const float *src = &As[buf][wa * 64 + ma * 32 + l32][h * 8];
-      const float4 x0 = *reinterpret_cast<const float4 *>(src);
-      const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
-      af[ma][0] = x0.x; af[ma][1] = x0.y; af[ma][2] = x0.z; af[ma][3] = x0.w;
-      af[ma][4] = x1.x; af[ma][5] = x1.y; af[ma][6] = x1.z; af[ma][7] = x1.w;
+    const int lr = tid >> 2, lc = (tid & 3) * 4;
+    // voxel rows of this thread's two loader rows: through the row map when
+    // given (rows past the count read the first listed row; their results
+    // are discarded)
+    int64_t zr0 = v0 + lr, zr1 = v0 + lr + 64;
+    if (rowmap) {
+      zr0 = rowmap[zr0 < nvox ? zr0 : 0];
+      zr1 = rowmap[zr1 < nvox ? zr1 : 0];
     }
-#pragma unroll
-    for (int nv = 0; nv < 2; ++nv) {
-      const float *src = &Zs[buf][wv * 64 + nv * 32 + l32][h * 8];
-      const float4 x0 = *reinterpret_cast<const float4 *>(src);
-      const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
-      zf[nv][0] = x0.x; zf[nv][1] = x0.y; zf[nv][2] = x0.z; zf[nv][3] = x0.w;
-      zf[nv][4] = x1.x; zf[nv][5] = x1.y; zf[nv][6] = x1.z; zf[nv][7] = x1.w;
-    }
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-#pragma unroll
-      for (int ma = 0; ma < 2; ++ma)
-#pragma unroll
-        for (int nv = 0; nv < 2; ++nv)
-          acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[ma][s], zf[nv][s], acc[ma][nv], 0, 0, 0);
+    const float *zp0 = Zp + zr0 * Kp + lc, *zp1 = Zp + zr1 * Kp + lc;
+    float4 ra0, ra1, rz0, rz1;
+    auto gload = [&](int q) {
+      const int tile = tb + q / nkc, kc = q - (q / nkc) * nkc;
+      const float *a = D + (int64_t)(tile * F_BA + lr) * Kp + kc * F_BK + lc;
+      ra0 = *reinterpret_cast<const float4 *>(a);
+      ra1 = *reinterpret_cast<const float4 *>(a + (int64_t)64 * Kp);
+      rz0 = *reinterpret_cast<const float4 *>(zp0 + kc * F_BK);
+      rz1 = *reinterpret_cast<const float4 *>(zp1 + kc * F_BK);
+    };
+    auto sstore = [&](int buf) {
+      *reinterpret_cast<float4 *>(&As[buf][lr][lc]) = ra0;
+      *reinterpret_cast<float4 *>(&As[buf][lr + 64][lc]) = ra1;
+      *reinterpret_cast<float4 *>(&Zs[buf][lr][lc]) = rz0;
+      *reinterpret_cast<float4 *>(&Zs[buf][lr + 64][lc]) = rz1;
+    };
 
-    const int kc = q % nkc;
-    if (kc == nkc - 1) {
-      // epilogue of one atom tile: fold 32 atom rows per voxel column
-      const int abase = (tb + q / nkc) * F_BA + wa * 64;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+    float best[2] = {-INFINITY, -INFINITY};
+    int bidx[2] = {-1, -1};
+    float ls[2][kCertK];
+    int lj[2][kCertK];
+    float vthr[2] = {INFINITY, INFINITY};  // SC_COLLECT: the line; SC_TOPK: the insertion bar
+    float win[2] = {0.f, 0.f};
+    if (MODE == SC_TOPK) {
+      topk_clear(ls[0], lj[0]);
+      topk_clear(ls[1], lj[1]);
 #pragma unroll
       for (int nv = 0; nv < 2; ++nv) {
+        const int64_t v = v0 + wv * 64 + nv * 32 + l32;
+        win[nv] = v < nvox ? cw * fmaxf(znorm[v], 0.f) + wabs : 0.f;
+        vthr[nv] = -INFINITY;
+      }
+    }
+    if (MODE == SC_COLLECT) {
 #pragma unroll
-        for (int ma = 0; ma < 2; ++ma) {
+      for (int nv = 0; nv < 2; ++nv) {
+        const int64_t v = v0 + wv * 64 + nv * 32 + l32;
+        if (v < nvox) vthr[nv] = col.thr[v];
+      }
+    }
+
+    if (nq > 0) {
+      gload(0);
+      sstore(0);
+    }
+    __syncthreads();
+    for (int q = 0; q < nq; ++q) {
+      const int buf = q & 1;
+      if (q + 1 < nq) gload(q + 1);
+      float af[2][8], zf[2][8];
 #pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-            const float sc = acc[ma][nv][i];
-            if (j < d && sc > best[nv]) {  // NaN never wins
-              best[nv] = sc;
-              bidx[nv] = j;
+      for (int ma = 0; ma < 2; ++ma) {
+        const float *src = &As[buf][wa * 64 + ma * 32 + l32][h * 8];
+        const float4 x0 = *reinterpret_cast<const float4 *>(src);
+        const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
+        af[ma][0] = x0.x; af[ma][1] = x0.y; af[ma][2] = x0.z; af[ma][3] = x0.w;
+        af[ma][4] = x1.x; af[ma][5] = x1.y; af[ma][6] = x1.z; af[ma][7] = x1.w;
+      }
+#pragma unroll
+      for (int nv = 0; nv < 2; ++nv) {
+        const float *src = &Zs[buf][wv * 64 + nv * 32 + l32][h * 8];
+        const float4 x0 = *reinterpret_cast<const float4 *>(src);
+        const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
+        zf[nv][0] = x0.x; zf[nv][1] = x0.y; zf[nv][2] = x0.z; zf[nv][3] = x0.w;
+        zf[nv][4] = x1.x; zf[nv][5] = x1.y; zf[nv][6] = x1.z; zf[nv][7] = x1.w;
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int ma = 0; ma < 2; ++ma)
+#pragma unroll
+          for (int nv = 0; nv < 2; ++nv)
+            acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[ma][s], zf[nv][s], acc[ma][nv], 0, 0, 0);
+
+      const int kc = q % nkc;
+      if (kc == nkc - 1) {
+        // epilogue of one atom tile: 32 atom rows per voxel column
+        const int abase = (tb + q / nkc) * F_BA + wa * 64;
+#pragma unroll
+        for (int nv = 0; nv < 2; ++nv) {
+#pragma unroll
+          for (int ma = 0; ma < 2; ++ma) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+              const float sc = acc[ma][nv][i];
+              if (MODE == SC_TOP1) {
+                if (j < d && sc > best[nv]) {  // NaN never wins
+                  best[nv] = sc;
+                  bidx[nv] = j;
+                }
+              } else if (MODE == SC_TOPK) {
+                if (j < d && sc > vthr[nv]) {
+                  topk_push_ordered(ls[nv], lj[nv], sc, j);
+                  vthr[nv] = fmaxf(ls[nv][kCertK - 1], ls[nv][0] - win[nv]);
+                }
+              } else {
+                const int64_t v = v0 + wv * 64 + nv * 32 + l32;
+                if (j < d && v < nvox && sc >= vthr[nv]) {
+                  const unsigned int pos = atomicAdd(&col.count[v], 1u);
+                  if ((int)pos < col.ccap) col.cand[v * col.ccap + pos] = j;
+                }
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+      }
+      if (q + 1 < nq) sstore(buf ^ 1);
+      __syncthreads();
+    }
+    if (MODE == SC_COLLECT) continue;  // the candidates are already written
+
+    // combine the two half-waves (rows 4h..4h+3 of each 8-row group), then
+    // the two atom halves of the block (wa = 0, 1) through LDS
+    if (MODE == SC_TOP1) {
+#pragma unroll
+      for (int nv = 0; nv < 2; ++nv) {
+        const float ps = __shfl_xor(best[nv], 32, 64);
+        const int pj = __shfl_xor(bidx[nv], 32, 64);
+        if (better(ps, pj, best[nv], bidx[nv])) {
+          best[nv] = ps;
+          bidx[nv] = pj;
+        }
+      }
+      float *rs = &As[0][0][0];
+      int *rj = reinterpret_cast<int *>(&Zs[0][0][0]);
+      if (wa == 1 && h == 0) {
+#pragma unroll
+        for (int nv = 0; nv < 2; ++nv) {
+          rs[wv * 64 + nv * 32 + l32] = best[nv];
+          rj[wv * 64 + nv * 32 + l32] = bidx[nv];
+        }
+      }
+      __syncthreads();
+      if (wa == 0 && h == 0) {
+#pragma unroll
+        for (int nv = 0; nv < 2; ++nv) {
+          const int c = wv * 64 + nv * 32 + l32;
+          const float ps = rs[c];
+          const int pj = rj[c];
+          // equal scores resolve to the lower atom index
+          if (better(ps, pj, best[nv], bidx[nv])) {
+            best[nv] = ps;
+            bidx[nv] = pj;
+          }
+          const int64_t v = v0 + c;
+          if (v < nvox) {
+            part_s[(int64_t)split * pstride + v] = best[nv];
+            part_j[(int64_t)split * pstride + v] = bidx[nv];
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int nv = 0; nv < 2; ++nv) topk_merge_xor(ls[nv], lj[nv], 32);
+      // 128 voxel columns x kCertK pairs fit in the stage buffers
+      float *rs = &As[0][0][0];
+      int *rj = reinterpret_cast<int *>(&Zs[0][0][0]);
+      static_assert(F_BV * kCertK <= 2 * F_BA * F_LDK, "LDS exchange");
+      if (wa == 1 && h == 0) {
+#pragma unroll
+        for (int nv = 0; nv < 2; ++nv) {
+          const int c = wv * 64 + nv * 32 + l32;
+#pragma unroll
+          for (int i = 0; i < kCertK; ++i) {
+            rs[i * F_BV + c] = ls[nv][i];
+            rj[i * F_BV + c] = lj[nv][i];
+          }
+        }
+      }
+      __syncthreads();
+      if (wa == 0 && h == 0) {
+#pragma unroll
+        for (int nv = 0; nv < 2; ++nv) {
+          const int c = wv * 64 + nv * 32 + l32;
+#pragma unroll
+          for (int i = 0; i < kCertK; ++i) topk_push(ls[nv], lj[nv], rs[i * F_BV + c], rj[i * F_BV + c]);
+          const int64_t v = v0 + c;
+          if (v < nvox) {
+            float *os = part_s + ((int64_t)split * pstride + v) * kCertK;
+            int *oj = part_j + ((int64_t)split * pstride + v) * kCertK;
+#pragma unroll
+            for (int i = 0; i < kCertK; ++i) {
+              os[i] = ls[nv][i];
+              oj[i] = lj[nv][i];
             }
           }
         }
       }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
     }
-    if (q + 1 < nq) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
-  // combine the two half-waves (rows 4h..4h+3 of each 8-row group)
-#pragma unroll
-  for (int nv = 0; nv < 2; ++nv) {
-    const float ps = __shfl_xor(best[nv], 32, 64);
-    const int pj = __shfl_xor(bidx[nv], 32, 64);
-    if (better(ps, pj, best[nv], bidx[nv])) {
-      best[nv] = ps;
-      bidx[nv] = pj;
-    }
-  }
-  // combine the two atom halves of the block (wa = 0, 1) through LDS
-  float *rs = &As[0][0][0];
-  int *rj = reinterpret_cast<int *>(&Zs[0][0][0]);
-  if (wa == 1 && h == 0) {
-#pragma unroll
-    for (int nv = 0; nv < 2; ++nv) {
-      rs[wv * 64 + nv * 32 + l32] = best[nv];
-      rj[wv * 64 + nv * 32 + l32] = bidx[nv];
-    }
-  }
-  __syncthreads();
-  if (wa == 0 && h == 0) {
-#pragma unroll
-    for (int nv = 0; nv < 2; ++nv) {
-      const int c = wv * 64 + nv * 32 + l32;
-      const float ps = rs[c];
-      const int pj = rj[c];
-      // equal scores resolve to the lower atom index
-      if (better(ps, pj, best[nv], bidx[nv])) {
-        best[nv] = ps;
-        bidx[nv] = pj;
-      }
-      const int64_t v = v0 + c;
-      if (v < n) {
-        part_s[(int64_t)split * n + v] = best[nv];
-        part_j[(int64_t)split * n + v] = bidx[nv];
-      }
-    }
+    __syncthreads();  // the next item reuses the LDS buffers
   }
 }
 
 void launch_score_f32(const float *D, const float *Zp, int d, int64_t d_pad, int64_t n,
                       int64_t n_pad, int Kp, int splits, float *part_s, int *part_j,
-                      hipStream_t s) {
+                      hipStream_t s, bool topk, const float *znorm, float cw, float wabs) {
   const int ntiles = (int)(d_pad / F_BA);
   const int nvt = (int)((n + F_BV - 1) / F_BV);
   (void)n_pad;
   const int tiles_per_split = (ntiles + splits - 1) / splits;
   const int nvt8 = (nvt + 7) / 8 * 8;
   const int64_t blocks = (int64_t)nvt8 * splits;
-  hipLaunchKernelGGL(k_score_f32, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, d, ntiles, n,
-                     nvt, Kp, splits, tiles_per_split, part_s, part_j);
+  if (blocks <= 0) return;
+  if (topk)
+    hipLaunchKernelGGL(k_score_f32<SC_TOPK>, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, d, ntiles, n,
+                       nvt, Kp, splits, tiles_per_split, part_s, part_j, n, nullptr, nullptr, CollectArgs{},
+                       znorm, cw, wabs);
+  else
+    hipLaunchKernelGGL(k_score_f32<SC_TOP1>, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, d, ntiles, n,
+                       nvt, Kp, splits, tiles_per_split, part_s, part_j, n, nullptr, nullptr, CollectArgs{},
+                       nullptr, 0.f, 0.f);
+}
+
+void launch_collect_f32_dev(const float *D, const float *Zp, const int32_t *rows, int d, int64_t d_pad,
+                            int64_t cap, const unsigned int *dcnt, int Kp, const float *thr, unsigned int *count,
+                            int32_t *cand, int ccap, hipStream_t s) {
+  if (cap <= 0) return;
+  const int ntiles = (int)(d_pad / F_BA);
+  // two blocks per CU, each looping over the work items of the device count
+  hipLaunchKernelGGL(k_score_f32<SC_COLLECT>, dim3(512), dim3(256), 0, s, D, Zp, d, ntiles, cap, 0, Kp, 1,
+                     ntiles, nullptr, nullptr, cap, dcnt, rows, CollectArgs{thr, count, cand, ccap}, nullptr, 0.f,
+                     0.f);
 }
 
 // ---------------------------------------------------------------------------

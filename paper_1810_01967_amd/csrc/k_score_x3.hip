@@ -11,6 +11,7 @@
 // One 32-element chunk per stage, double-buffered in LDS (rows of 72 BF16:
 // the chunk plus 8 of padding).
 #include "k_split.h"
+#include "k_topk.h"
 #include "mrf_internal.h"
 
 namespace mrf {
@@ -41,11 +42,26 @@ __device__ __forceinline__ bool xbetter(float s1, int j1, float s0, int j0) {
   return (s1 > s0) || (s1 == s0 && j1 >= 0 && (j0 < 0 || j1 < j0));
 }
 
+// MODE SC_TOP1: per-voxel argmax per atom split; SC_TOPK: the kCertK best
+// (score, atom) pairs per atom split [splits][pstride][kCertK] among the atoms
+// within cw ||Z_v|| + wabs of the running maximum when scored; SC_COLLECT:
+// every atom whose score reaches the voxel's line thr[i] appended to
+// cand[i][0..ccap) (count[i] counts them all), voxel rows through rowmap.
+struct CollectX3 {
+  const int32_t *rowmap;
+  const float *thr;
+  unsigned int *count;
+  int32_t *cand;
+  int ccap;
+};
+
+template <int MODE>
 __global__ __launch_bounds__(X_NT, 1) void k_score_x3(const uint16_t *__restrict__ Dx, const uint16_t *__restrict__ Zx,
                                                      int d, int ntiles_total, int64_t n, int nvt, int Kx,
                                                      int splits, int tiles_per_split, float *__restrict__ part_s,
                                                      int *__restrict__ part_j, const unsigned int *__restrict__ dcnt,
-                                                     int64_t pstride) {
+                                                     int64_t pstride, const float *__restrict__ znorm, float cw,
+                                                     float wabs, CollectX3 col) {
   // Work item w -> (voxel tile, atom split); all splits of a voxel tile on one
   // XCD (item w on XCD w % 8).  Launched by the host (dcnt null): one item per
   // block, n voxels.  With the voxel count on the device (dcnt): n is only the
@@ -56,7 +72,11 @@ __global__ __launch_bounds__(X_NT, 1) void k_score_x3(const uint16_t *__restrict
   if (dcnt) {
     nvox = min(n, (int64_t)*dcnt);
     nvt_w = (int)((nvox + X_BV - 1) / X_BV);
-    nsplit = x3_device_splits(nvt_w, ntiles_total);
+    // a rescan spreads its few voxel tiles over more splits (about 2,048
+    // items); the fallback's split count is the one its merge recomputes
+    nsplit = MODE == SC_COLLECT ? max(1, min(ntiles_total, min(256, (2048 + (nvt_w + 7) / 8 * 8 - 1) /
+                                                                        max(8, (nvt_w + 7) / 8 * 8))))
+                                : x3_device_splits(nvt_w, ntiles_total);
     tps = (ntiles_total + nsplit - 1) / nsplit;
   }
   const int64_t nwork = (int64_t)((nvt_w + 7) / 8 * 8) * nsplit;
@@ -64,6 +84,8 @@ __global__ __launch_bounds__(X_NT, 1) void k_score_x3(const uint16_t *__restrict
   __shared__ __attribute__((aligned(16))) uint16_t S[2 * X_STAGE];
   __shared__ float rs[X_WA][X_BV];
   __shared__ int rj[X_WA][X_BV];
+  // SC_TOPK: the waves' lists [X_WA][kCertK][X_BV] go through the stage buffers
+  static_assert(X_WA * kCertK * X_BV * 8 <= 2 * X_STAGE * 2, "LDS exchange of the candidate lists");
 
   for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int xcd = (int)(w & 7);
@@ -86,14 +108,22 @@ __global__ __launch_bounds__(X_NT, 1) void k_score_x3(const uint16_t *__restrict
     const int lr = tid >> 3, piece = tid & 7;
     const int lc = (piece >> 2) * 32 + (piece & 3) * 8;  // column within [hi 32 | lo 32]
     uint4 ra[X_LA], rz[X_LZ];
+    // voxel rows of this thread's loader rows (through the row map in
+    // SC_COLLECT; rows past the count read the first listed row, unused)
+    const uint16_t *zrow[X_LZ];
+    #pragma unroll
+    for (int i = 0; i < X_LZ; ++i) {
+      int64_t r = v0 + lr + X_LSTEP * i;
+      if (MODE == SC_COLLECT) r = col.rowmap[r < nvox ? r : 0];
+      zrow[i] = Zx + r * row + lc;
+    }
     auto gload = [&](int q) {
       const int tile = tb + q / nkc, kc = q - (q / nkc) * nkc;
       const uint16_t *a = Dx + (int64_t)(tile * X_BA + lr) * row + kc * 64 + lc;
       #pragma unroll
       for (int i = 0; i < X_LA; ++i) ra[i] = *reinterpret_cast<const uint4 *>(a + (int64_t)(X_LSTEP * i) * row);
-      const uint16_t *z = Zx + (v0 + lr) * row + kc * 64 + lc;
       #pragma unroll
-      for (int i = 0; i < X_LZ; ++i) rz[i] = *reinterpret_cast<const uint4 *>(z + (int64_t)(X_LSTEP * i) * row);
+      for (int i = 0; i < X_LZ; ++i) rz[i] = *reinterpret_cast<const uint4 *>(zrow[i] + kc * 64);
     };
     auto sstore = [&](int buf) {
       uint16_t *B = S + buf * X_STAGE;
@@ -113,10 +143,21 @@ __global__ __launch_bounds__(X_NT, 1) void k_score_x3(const uint16_t *__restrict
         for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
     float best[X_NV];
     int bidx[X_NV];
+    float ls[X_NV][kCertK];
+    int lj[X_NV][kCertK];
+    float vthr[X_NV], win[X_NV];  // SC_TOPK: insertion bar and window; SC_COLLECT: the line
     #pragma unroll
     for (int b = 0; b < X_NV; ++b) {
       best[b] = -INFINITY;
       bidx[b] = -1;
+      vthr[b] = MODE == SC_TOPK ? -INFINITY : INFINITY;
+      win[b] = 0.f;
+      const int64_t v = v0 + wv * (X_BV / 2) + b * 32 + l32;
+      if (MODE == SC_TOPK) {
+        topk_clear(ls[b], lj[b]);
+        if (v < nvox) win[b] = cw * fmaxf(znorm[v], 0.f) + wabs;
+      }
+      if (MODE == SC_COLLECT && v < nvox) vthr[b] = col.thr[v];
     }
 
     if (nq > 0) {
@@ -164,7 +205,18 @@ __global__ __launch_bounds__(X_NT, 1) void k_score_x3(const uint16_t *__restrict
             for (int i = 0; i < 16; ++i) {
               const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
               const float sc = acc[ma][nv][i];
-              if (j < d && sc > best[nv]) {  // atoms in increasing order: '>' keeps the lowest index
+              if (MODE == SC_TOPK) {
+                if (j < d && sc > vthr[nv]) {
+                  topk_push_ordered(ls[nv], lj[nv], sc, j);
+                  vthr[nv] = fmaxf(ls[nv][kCertK - 1], ls[nv][0] - win[nv]);
+                }
+              } else if (MODE == SC_COLLECT) {
+                const int64_t v = v0 + wv * (X_BV / 2) + nv * 32 + l32;
+                if (j < d && v < nvox && sc >= vthr[nv]) {
+                  const unsigned int pos = atomicAdd(&col.count[v], 1u);
+                  if ((int)pos < col.ccap) col.cand[v * col.ccap + pos] = j;
+                }
+              } else if (j < d && sc > best[nv]) {  // atoms in increasing order: '>' keeps the lowest index
                 best[nv] = sc;
                 bidx[nv] = j;
               }
@@ -178,6 +230,49 @@ __global__ __launch_bounds__(X_NT, 1) void k_score_x3(const uint16_t *__restrict
       }
       if (q + 1 < nq) sstore(buf ^ 1);
       __syncthreads();
+    }
+    if (MODE == SC_COLLECT) continue;  // the candidates are already written
+    if (MODE == SC_TOPK) {
+      // the two half-waves, then the X_WA atom-row waves' lists through LDS
+      float *ps = reinterpret_cast<float *>(S);
+      int *pj = reinterpret_cast<int *>(S) + X_WA * kCertK * X_BV;
+      #pragma unroll
+      for (int nv = 0; nv < X_NV; ++nv) {
+        topk_merge_xor(ls[nv], lj[nv], 32);
+        if (h == 0) {
+          const int c = wv * (X_BV / 2) + nv * 32 + l32;
+          #pragma unroll
+          for (int i = 0; i < kCertK; ++i) {
+            ps[(wa * kCertK + i) * X_BV + c] = ls[nv][i];
+            pj[(wa * kCertK + i) * X_BV + c] = lj[nv][i];
+          }
+        }
+      }
+      __syncthreads();
+      if (tid < X_BV) {
+        float ms[kCertK];
+        int mj[kCertK];
+        #pragma unroll
+        for (int i = 0; i < kCertK; ++i) {
+          ms[i] = ps[i * X_BV + tid];
+          mj[i] = pj[i * X_BV + tid];
+        }
+        for (int w = 1; w < X_WA; ++w)
+          #pragma unroll
+          for (int i = 0; i < kCertK; ++i) topk_push(ms, mj, ps[(w * kCertK + i) * X_BV + tid], pj[(w * kCertK + i) * X_BV + tid]);
+        const int64_t v = v0 + tid;
+        if (v < nvox) {
+          float *os = part_s + ((int64_t)split * pstride + v) * kCertK;
+          int *oj = part_j + ((int64_t)split * pstride + v) * kCertK;
+          #pragma unroll
+          for (int i = 0; i < kCertK; ++i) {
+            os[i] = ms[i];
+            oj[i] = mj[i];
+          }
+        }
+      }
+      __syncthreads();  // the next item reuses the LDS buffers
+      continue;
     }
     // the two half-waves, then the X_WA atom-row waves of each voxel column
     #pragma unroll
@@ -215,14 +310,19 @@ __global__ __launch_bounds__(X_NT, 1) void k_score_x3(const uint16_t *__restrict
 // Dx: split atoms [d_pad][2 Kx] (d_pad a multiple of 256); Zx: split voxels
 // [n_pad][2 Kx] (n_pad a multiple of X_BV, zero rows beyond n).
 void launch_score_x3(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t n, int64_t n_pad,
-                     int Kx, int splits, float *part_s, int *part_j, hipStream_t s) {
+                     int Kx, int splits, float *part_s, int *part_j, hipStream_t s, bool topk, const float *znorm,
+                     float cw, float wabs) {
   const int ntiles = (int)(d_pad / X_BA);
   const int nvt = (int)(n_pad / X_BV);
   const int tps = (ntiles + splits - 1) / splits;
   const int64_t nvt8 = (nvt + 7) / 8 * 8;
   const int64_t blocks = nvt8 * splits;
-  hipLaunchKernelGGL(k_score_x3, dim3((unsigned)blocks), dim3(X_NT), 0, s, Dx, Zx, d, ntiles, n, nvt, Kx, splits, tps,
-                     part_s, part_j, nullptr, n);
+  if (topk)
+    hipLaunchKernelGGL(k_score_x3<SC_TOPK>, dim3((unsigned)blocks), dim3(X_NT), 0, s, Dx, Zx, d, ntiles, n, nvt, Kx,
+                       splits, tps, part_s, part_j, nullptr, n, znorm, cw, wabs, CollectX3{});
+  else
+    hipLaunchKernelGGL(k_score_x3<SC_TOP1>, dim3((unsigned)blocks), dim3(X_NT), 0, s, Dx, Zx, d, ntiles, n, nvt, Kx,
+                       splits, tps, part_s, part_j, nullptr, n, nullptr, 0.f, 0.f, CollectX3{});
 }
 
 void launch_score_x3_dev(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t cap,
@@ -230,8 +330,17 @@ void launch_score_x3_dev(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t 
   if (cap <= 0) return;
   const int ntiles = (int)(d_pad / X_BA);
   // one block per CU of the 256, each looping over the work items
-  hipLaunchKernelGGL(k_score_x3, dim3(256), dim3(X_NT), 0, s, Dx, Zx, d, ntiles, cap, 0, Kx, 1, ntiles, part_s,
-                     part_j, dcnt, cap);
+  hipLaunchKernelGGL(k_score_x3<SC_TOP1>, dim3(256), dim3(X_NT), 0, s, Dx, Zx, d, ntiles, cap, 0, Kx, 1, ntiles,
+                     part_s, part_j, dcnt, cap, nullptr, 0.f, 0.f, CollectX3{});
+}
+
+void launch_collect_x3_dev(const uint16_t *Dx, const uint16_t *Zx, const int32_t *rows, int d, int64_t d_pad,
+                           int64_t cap, const unsigned int *dcnt, int Kx, const float *thr, unsigned int *count,
+                           int32_t *cand, int ccap, hipStream_t s) {
+  if (cap <= 0) return;
+  const int ntiles = (int)(d_pad / X_BA);
+  hipLaunchKernelGGL(k_score_x3<SC_COLLECT>, dim3(256), dim3(X_NT), 0, s, Dx, Zx, d, ntiles, cap, 0, Kx, 1, ntiles,
+                     nullptr, nullptr, dcnt, cap, nullptr, 0.f, 0.f, CollectX3{rows, thr, count, cand, ccap});
 }
 
 }  // namespace mrf

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "host_common.h"
+#include "k_topk.h"
 
 using namespace mrf;
 
@@ -307,11 +308,80 @@ int auto_splits_x3(const mrf_dict_s *D, int64_t n) {
   return (int)s;
 }
 
+// Error bound of a scoring pass, |s_hat - s| <= c ||Z_v|| + kCertAbs for every
+// atom, with s the exact score over the FP32 normalised atoms (unit norm up to
+// 2^-24 per element) and Z_v the packed FP32 row.  Each product and addition of
+// the matrix-core accumulation is taken to round with relative error at most
+// u = 2^-24 in any order of evaluation, so a sum of N terms is within
+// gamma_N = N u / (1 - N u) of exact times the sum of their magnitudes (the
+// standard bound of recursive or blocked summation), here at most ||Z_v||.
+//   FP32: K products of the exact operands, gamma_K.
+//   split BF16: z = hi + lo + e with |e| <= 2^-16 |z| (both operands), the
+//     dropped lo.lo term at most 2^-16 (1 + 2^-8)^2 |z a|, so the three exact
+//     BF16 products per element miss z a by at most 3.008 2^-16 |z a|; their
+//     3K-term FP32 sum adds gamma_3K times at most 1.016 sum |z a|.
+// The factor 1.01 covers the FP32 rounding of ||Z_v|| and of the unit norm;
+// kCertAbs covers flushed subnormal products.
+double gamma_n(double N) {
+  const double u = 0x1p-24;
+  return N * u / (1.0 - N * u);
+}
+float cert_coeff(int precision, int K) {
+  if (precision == MRF_BF16X3) return (float)(1.01 * (3.02 * 0x1p-16 + 1.016 * gamma_n(3.0 * K)));
+  return (float)(1.01 * gamma_n((double)K));
+}
+constexpr float kCertAbs = 1e-30f;
+
+// Window of the scoring passes' candidate lists: more than twice the bound.
+float cert_window(float cE) { return 2.02f * cE; }
+constexpr float kCertWinAbs = 3e-30f;
+
+// Certified finish of the exhaustive filter from the per-split lists in
+// part_s / part_j (see k_certify.hip) of the scoring pass in `precision`
+// (MRF_FP32 or MRF_BF16X3), whose arithmetic also rescans.
+mrf_status certify_exhaustive(mrf_dict_s *D, int64_t n, int splits, int precision, const int32_t *warm, int32_t *idx,
+                              float *pd, float *corr, float *params_out, hipStream_t s) {
+  const float cE = cert_coeff(precision, D->K);
+  TRY(grow(D->cert, 64));
+  TRY(grow(D->cert_list, (size_t)n * 4));
+  TRY(grow(D->cert_thr, (size_t)n * 4));
+  TRY(grow(D->cert_ccount, (size_t)n * 4));
+  TRY(grow(D->cert_scan, (size_t)n * 4));
+  TRY(grow(D->cert_cand, (size_t)n * kCertCap * 4));
+  launch_zero(D->cert.p, 64, s);
+  LAUNCH_CHECK("certificate counters");
+  unsigned int *cnt = D->cert.as<unsigned int>();
+  CertQueue q{cnt, D->cert_list.as<int32_t>(), D->cert_thr.as<float>(), D->cert_ccount.as<unsigned int>(), cnt + 1,
+              D->cert_scan.as<int32_t>(), reinterpret_cast<unsigned long long *>(cnt + 2)};
+  CertOut out{D->znorm.as<float>(), warm, D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr,
+              params_out, D->gamma.as<float>()};
+  launch_certify(D->part_s.as<float>(), D->part_j.as<int>(), splits, n, n, D->d, D->zp.as<float>(),
+                 D->dhat.as<float>(), D->Kp, D->K, cE, cE, kCertAbs, out, q, s);
+  LAUNCH_CHECK("certify");
+  if (precision == MRF_BF16X3)
+    launch_collect_x3_dev(D->dx3.as<uint16_t>(), D->zx3.as<uint16_t>(), q.list, D->d, D->d_pad, n, q.count, D->Kx,
+                          q.thr, q.ccount, D->cert_cand.as<int32_t>(), kCertCap, s);
+  else
+    launch_collect_f32_dev(D->dhat.as<float>(), D->zp.as<float>(), q.list, D->d, D->d_pad, n, q.count, D->Kp,
+                           q.thr, q.ccount, D->cert_cand.as<int32_t>(), kCertCap, s);
+  LAUNCH_CHECK("certificate rescan");
+  launch_rescore_collected(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n, q,
+                           D->cert_cand.as<int32_t>(), kCertCap, out, s);
+  LAUNCH_CHECK("certificate rescore");
+  launch_scan_exact(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n, q, out, s);
+  LAUNCH_CHECK("certificate scan");
+  D->cert_used = true;
+  return MRF_OK;
+}
+
 // Score + merge on already packed voxels (ws zp/znorm filled for n rows).
 mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
                             int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
                             hipEvent_t ev_s0, hipEvent_t ev_s1, int *splits_used) {
   const int precision = o ? o->precision : MRF_FP32;
+  const bool certify = !(o && o->no_certificate);
+  const size_t lw = certify ? kCertK : 1;  // list length per split and voxel
+  D->cert_used = false;
   int splits = (o && o->atom_splits > 0) ? o->atom_splits : auto_splits(D, n);
   const int64_t ntiles = D->d_pad / 128;
   if (splits > ntiles) splits = (int)ntiles;
@@ -324,14 +394,16 @@ mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, c
     int xs = (o && o->atom_splits > 0) ? o->atom_splits : auto_splits_x3(D, n);
     if (splits_used) *splits_used = xs;
     TRY(grow(D->zx3, (size_t)n_pad * 2 * D->Kx * 2));
-    TRY(grow(D->part_s, (size_t)xs * n * 4));
-    TRY(grow(D->part_j, (size_t)xs * n * 4));
+    TRY(grow(D->part_s, (size_t)xs * n * 4 * lw));
+    TRY(grow(D->part_j, (size_t)xs * n * 4 * lw));
     if (ev_s0) HIP_TRY(hipEventRecord(ev_s0, s));
     if (!D->zx3_fresh) launch_split_x3(D->zp.as<float>(), D->Kp, n_pad, D->Kx, D->zx3.as<uint16_t>(), s);
+    const float cw = cert_window(cert_coeff(MRF_BF16X3, D->K));
     launch_score_x3(D->dx3.as<uint16_t>(), D->zx3.as<uint16_t>(), D->d, D->d_pad, n, n_pad, D->Kx, xs,
-                    D->part_s.as<float>(), D->part_j.as<int>(), s);
+                    D->part_s.as<float>(), D->part_j.as<int>(), s, certify, D->znorm.as<float>(), cw, kCertWinAbs);
     LAUNCH_CHECK("score_x3");
     if (ev_s1) HIP_TRY(hipEventRecord(ev_s1, s));
+    if (certify) return certify_exhaustive(D, n, xs, MRF_BF16X3, warm, idx, pd, corr, params_out, s);
     launch_merge_argmax(D->part_s.as<float>(), D->part_j.as<int>(), xs, n, D->d, D->znorm.as<float>(), warm,
                         D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr, params_out,
                         D->gamma.as<float>(), s);
@@ -339,13 +411,15 @@ mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, c
     return MRF_OK;
   }
   if (precision == MRF_FP32) {
-    TRY(grow(D->part_s, (size_t)splits * n * 4));
-    TRY(grow(D->part_j, (size_t)splits * n * 4));
+    TRY(grow(D->part_s, (size_t)splits * n * 4 * lw));
+    TRY(grow(D->part_j, (size_t)splits * n * 4 * lw));
     if (ev_s0) HIP_TRY(hipEventRecord(ev_s0, s));
     launch_score_f32(D->dhat.as<float>(), D->zp.as<float>(), D->d, D->d_pad, n, n_pad, D->Kp,
-                     splits, D->part_s.as<float>(), D->part_j.as<int>(), s);
+                     splits, D->part_s.as<float>(), D->part_j.as<int>(), s, certify, D->znorm.as<float>(),
+                     cert_window(cert_coeff(MRF_FP32, D->K)), kCertWinAbs);
     LAUNCH_CHECK("score_f32");
     if (ev_s1) HIP_TRY(hipEventRecord(ev_s1, s));
+    if (certify) return certify_exhaustive(D, n, splits, MRF_FP32, warm, idx, pd, corr, params_out, s);
     launch_merge_argmax(D->part_s.as<float>(), D->part_j.as<int>(), splits, n, D->d,
                         D->znorm.as<float>(), warm, D->inv_norm.as<float>(),
                         D->params.as<float>(), D->nparam, idx, pd, corr, params_out,
@@ -482,6 +556,15 @@ extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t 
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipEventElapsedTime(&stats->ms, ev.a, ev.b));
     if (!opts || opts->method == MRF_EXHAUSTIVE) HIP_TRY(hipEventElapsedTime(&stats->score_ms, ev.c, ev.d));
+    if ((!opts || opts->method == MRF_EXHAUSTIVE) && D->cert_used) {
+      uint32_t c[4] = {0, 0, 0, 0};
+      HIP_TRY(hipMemcpy(c, D->cert.p, sizeof c, hipMemcpyDeviceToHost));
+      uint64_t r;
+      std::memcpy(&r, c + 2, sizeof r);
+      stats->cert_rescored = (int64_t)r;
+      stats->cert_rescanned = c[0];
+      stats->cert_scanned = c[1];
+    }
     stats->splits = splits_used;
     stats->n = n;
     stats->zero_voxels = (int64_t)cnt[0];

@@ -76,10 +76,20 @@ void launch_pd_phase(const int32_t *idx, const float2 *vphase, const float2 *afa
 
 // Exhaustive FP32 scoring with fused per-voxel argmax.  D: [d_pad][Kp] FP32
 // normalised atoms; Zp: [n_pad][Kp].  Writes per-split (score, index) partials
-// [splits][n].
+// [splits][n]; with topk, the kCertK best pairs per split and voxel
+// [splits][n][kCertK] (best first, empty slots (-inf, -1)) among the atoms
+// within cw znorm[v] + wabs of the voxel's running maximum when scored.
 void launch_score_f32(const float *D, const float *Zp, int d, int64_t d_pad, int64_t n,
                       int64_t n_pad, int Kp, int splits, float *part_s, int *part_j,
-                      hipStream_t s);
+                      hipStream_t s, bool topk = false, const float *znorm = nullptr, float cw = 0.f,
+                      float wabs = 0.f);
+// The same filter over the voxel rows Zp[rows[i]] for i < *dcnt (<= cap),
+// collecting every atom j with score >= thr[i] into cand[i][0..ccap)
+// (count[i] = number found, which may exceed ccap; counts zeroed by the
+// caller).
+void launch_collect_f32_dev(const float *D, const float *Zp, const int32_t *rows, int d, int64_t d_pad,
+                            int64_t cap, const unsigned int *dcnt, int Kp, const float *thr, unsigned int *count,
+                            int32_t *cand, int ccap, hipStream_t s);
 
 // Reduced-precision scoring with a fused per-voxel top-k (k <= 8).  Dq/Zq are
 // BF16 (uint16) or FP8-E4M3 (uint8) rows of pitch Kq; dscale (FP8 only) the
@@ -102,6 +112,44 @@ void launch_merge_rescore(const float *cand_s, const int *cand_j, int splits, in
                           const float *znorm, const int32_t *warm, const float *inv_norm,
                           const float *params, int nparam, int32_t *idx, float *pd, float *corr,
                           float *params_out, float *gamma_hat, hipStream_t s);
+
+// Exactness certificate of the exhaustive filter (k_certify.hip).  Outputs
+// and look-ups of the rescaling step, as the merge kernels take them.
+struct CertOut {
+  const float *znorm;
+  const int32_t *warm;
+  const float *inv_norm;
+  const float *params;
+  int nparam;
+  int32_t *idx;
+  float *pd;
+  float *corr;
+  float *params_out;
+  float *gamma_hat;
+};
+// Voxels queued for the rescan (list/thr, count on the device), those whose
+// rescan overflowed the candidate list (scan_list), and the number of exact
+// rescores (statistics).  Capacity n each.
+struct CertQueue {
+  unsigned int *count;
+  int32_t *list;
+  float *thr;
+  unsigned int *ccount;  // per queued voxel: candidates the rescan found (zeroed when queued)
+  unsigned int *scan_count;
+  int32_t *scan_list;
+  unsigned long long *rescored;
+};
+constexpr int kCertCap = 64;  // candidates per rescanned voxel
+// Merge the per-split lists [splits][pstride][kCertK], rescore exactly, finish
+// each voxel and queue the uncertified ones; E_v = cE ||Z_v|| + eabs bounds the
+// scoring pass's error, cE32 ||Z_v|| + eabs that of the FP32 rescan.
+void launch_certify(const float *part_s, const int *part_j, int splits, int64_t pstride, int64_t n, int d,
+                    const float *Zp, const float *D, int Kp, int K, float cE, float cE32, float eabs,
+                    const CertOut &o, const CertQueue &q, hipStream_t s);
+void launch_rescore_collected(const float *Zp, const float *D, int Kp, int K, int d, int64_t cap, const CertQueue &q,
+                              const int32_t *cand, int ccap, const CertOut &o, hipStream_t s);
+void launch_scan_exact(const float *Zp, const float *D, int Kp, int K, int d, int64_t cap, const CertQueue &q,
+                       const CertOut &o, hipStream_t s);
 
 // X_v = gamma_hat_v * Dhat_{idx_v} (zero where idx < 0), written voxel-major
 // [n][L] or frame-major [S][L][npix].  With X_prev != nullptr (frame-major only)
@@ -269,8 +317,15 @@ void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys
 // Exhaustive split-BF16 scoring with fused argmax per atom split (Dx split
 // atoms [d_pad][2 Kx], Zx split voxels [n_pad][2 Kx]); merged by
 // launch_merge_argmax like the FP32 filter.
+// With topk: the kCertK best pairs per split and voxel, as launch_score_f32.
 void launch_score_x3(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t n, int64_t n_pad,
-                     int Kx, int splits, float *part_s, int *part_j, hipStream_t s);
+                     int Kx, int splits, float *part_s, int *part_j, hipStream_t s, bool topk = false,
+                     const float *znorm = nullptr, float cw = 0.f, float wabs = 0.f);
+// The split-BF16 filter over the split rows Zx[rows[i]] for i < *dcnt (<= cap),
+// collecting atoms as launch_collect_f32_dev.
+void launch_collect_x3_dev(const uint16_t *Dx, const uint16_t *Zx, const int32_t *rows, int d, int64_t d_pad,
+                           int64_t cap, const unsigned int *dcnt, int Kx, const float *thr, unsigned int *count,
+                           int32_t *cand, int ccap, hipStream_t s);
 // The same filter over the first *dcnt (<= cap) rows of Zx ([round_up(cap,
 // 128)][2 Kx]), the count read on the device: one block per CU loops over the
 // (voxel tile, atom split) items; partial results at part[split * cap + i].

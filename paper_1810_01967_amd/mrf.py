@@ -62,7 +62,7 @@ class MatchOpts(ctypes.Structure):
                 ("net", ctypes.c_void_p), ("box_radius", ctypes.c_int32),
                 ("fallback_corr", ctypes.c_float), ("recentre", ctypes.c_int32),
                 ("eps", ctypes.c_float), ("tree_capacity", ctypes.c_int32),
-                ("pd_phase", ctypes.c_void_p)]
+                ("pd_phase", ctypes.c_void_p), ("no_certificate", ctypes.c_int32)]
 
 
 class MatchStats(ctypes.Structure):
@@ -73,7 +73,8 @@ class MatchStats(ctypes.Structure):
                 ("local_atoms", ctypes.c_int64), ("proposal_ms", ctypes.c_float),
                 ("fallback_ms", ctypes.c_float), ("search_ms", ctypes.c_float),
                 ("distance_evals", ctypes.c_int64), ("tree_levels", ctypes.c_int32),
-                ("first_box_atoms", ctypes.c_int64)]
+                ("first_box_atoms", ctypes.c_int64), ("cert_rescored", ctypes.c_int64),
+                ("cert_rescanned", ctypes.c_int64), ("cert_scanned", ctypes.c_int64)]
 
 
 class TreeInfo(ctypes.Structure):
@@ -346,7 +347,7 @@ def mrf_dict_copy_atoms(D: Dictionary, precision="fp32", stream=None):
 
 
 def match_opts(precision="fp32", topk=8, atom_splits=0, net=None, box_radius=3, fallback_corr=0.98,
-               recentre=0, eps=None, tree_capacity=0) -> MatchOpts:
+               recentre=0, eps=None, tree_capacity=0, certify=True) -> MatchOpts:
     # a network selects the learned path (a given eps then sends its fallback
     # voxels to the dictionary's cover tree, None keeps the exhaustive
     # fallback); eps alone selects the cover tree
@@ -358,17 +359,18 @@ def match_opts(precision="fp32", topk=8, atom_splits=0, net=None, box_radius=3, 
         e = float(eps or 0.0)
     return MatchOpts(method, PRECISION[precision], int(topk), int(atom_splits),
                      None if net is None else net.handle, int(box_radius), float(fallback_corr),
-                     int(recentre), e, int(tree_capacity), None)
+                     int(recentre), e, int(tree_capacity), None, 0 if certify else 1)
 
 
 # --------------------------------------------------------------------------- matched filter
 def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp32", topk=8,
               atom_splits=0, warm_idx=None, want_pd=True, want_corr=True, want_X=False,
               want_params=False, stats=False, out=None, stream=None, net=None, box_radius=3,
-              fallback_corr=0.98, recentre=0, eps=None, tree_capacity=0, want_pd_phase=False):
+              fallback_corr=0.98, recentre=0, eps=None, tree_capacity=0, want_pd_phase=False, certify=True):
     """Matched filter of the voxels in Z (complex64 CUDA tensor, [n][L] for
     layout 'voxel', [S][L][...] for 'frame').  Returns a dict of CUDA tensors
-    (idx, pd, corr, X, params, pd_phase) and, with stats=True, a MatchStats."""
+    (idx, pd, corr, X, params, pd_phase) and, with stats=True, a MatchStats.
+    certify=False skips the exhaustive filter's exactness certificate."""
     torch = _torch()
     if layout == "voxel":
         n = Z.shape[0]
@@ -390,7 +392,7 @@ def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp
     if want_params and "params" not in o:
         o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
     opts = match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre, eps,
-                      tree_capacity)
+                      tree_capacity, certify)
     if want_pd_phase:
         if "pd_phase" not in o:
             o["pd_phase"] = torch.empty(n, dtype=torch.float32, device=dev)

@@ -359,7 +359,7 @@ def test_device_sized_fallback_equals_exhaustive(m, n):
                     seed=6)
     Z, jt, pd, snr = workloads.random_voxels(Dd, n, seed=13, snr_db_range=(0.0, 30.0))
     Zd = dev(c64(Z))
-    ex = m.mrf_match(D, Zd, precision="bf16x3")
+    ex = m.mrf_match(D, Zd, precision="bf16x3", certify=False)  # the fallback is the uncertified pass
     for rep in range(2):  # the second call reuses the device buffers
         oa = m.mrf_match(D, Zd, net=net, precision="bf16x3", recentre=1, fallback_corr=2.0, stats=True)
         assert oa["stats"].fallbacks == n
