@@ -297,6 +297,25 @@ mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t n, const vo
                      int32_t *idx, float *pd, float *corr, void *X_out, float *params_out,
                      mrf_match_stats *stats, mrf_stream stream);
 
+/* mrf_match for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * the exhaustive MRF_FP32 filter (certified unless opts->no_certificate),
+ * with every intermediate in a fixed 32 MiB device workspace that the
+ * library holds per device until the process ends; the arguments are
+ * mrf_match's without the statistics.  opts NULL or method MRF_EXHAUSTIVE
+ * with precision MRF_FP32 (else MRF_E_UNSUPPORTED); the dictionary's device
+ * must be current (else MRF_E_INVAL).  A call whose workspace would exceed
+ * 32 MiB (n_pad*Kp*4 bytes of packed voxels, n_pad = n rounded up to 256,
+ * plus per voxel 64 to 512 bytes of candidate lists and 276 of the
+ * certificate: about 6,000 voxels at L = 500 complex) fails with
+ * MRF_E_INVAL before any device work.  Calls share the workspace: calls that
+ * overlap on one device race; results are complete when the stream reaches
+ * the call's end.  No hipMalloc, hipFree or allocating library call is made. */
+mrf_status mrf_match_noalloc(mrf_dict D, const mrf_match_opts *opts, int64_t n, const void *Z,
+                             int32_t z_layout, int64_t slice_voxels, const int32_t *warm_idx,
+                             int32_t *idx, float *pd, float *corr, void *X_out, float *params_out,
+                             mrf_stream stream);
+
 /* Local matched filter around given proposals (the search stage of
  * MRF_LEARNED): for voxel v the candidates are the atoms of the box
  * prod_p [cells[v][p] - r, cells[v][p] + r] clipped to the grid (the

@@ -96,6 +96,23 @@ mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t s
 // caller gives the cells) a network whose BF16 form reads the split rows.
 bool learned_split_rows_only(const mrf_dict_s *D, const mrf_match_opts *o, const int32_t *warm, bool cells_given);
 mrf_status check_opts(const mrf_dict_s *D, const mrf_match_opts *o);
+int auto_splits(const mrf_dict_s *D, int64_t n);
+// Exactness certificate of the exhaustive filter on caller-given buffers
+// (counters 64 bytes; list, thr, ccount, scan [n]; cand [n][kCertCap]).
+struct CertBufs {
+  unsigned int *counters;
+  int32_t *list;
+  float *thr;
+  unsigned int *ccount;
+  int32_t *scan;
+  int32_t *cand;
+};
+size_t cert_bytes(int64_t n);
+float cert_coeff(int precision, int K);
+float cert_window(float cE);
+mrf_status certify_run(mrf_dict_s *D, const CertBufs &b, const float *zp, const float *znorm, const uint16_t *zx3,
+                       float *gamma, const float *part_s, const int *part_j, int64_t n, int splits, int precision,
+                       const int32_t *warm, int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s);
 mrf_status match_tree(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const int32_t *warm,
                       int32_t *idx, float *pd, float *corr, float *params_out, mrf_match_stats *st,
                       hipStream_t s);

@@ -330,46 +330,56 @@ float cert_coeff(int precision, int K) {
   if (precision == MRF_BF16X3) return (float)(1.01 * (3.02 * 0x1p-16 + 1.016 * gamma_n(3.0 * K)));
   return (float)(1.01 * gamma_n((double)K));
 }
-constexpr float kCertAbs = 1e-30f;
 
 // Window of the scoring passes' candidate lists: more than twice the bound.
 float cert_window(float cE) { return 2.02f * cE; }
-constexpr float kCertWinAbs = 3e-30f;
 
-// Certified finish of the exhaustive filter from the per-split lists in
-// part_s / part_j (see k_certify.hip) of the scoring pass in `precision`
-// (MRF_FP32 or MRF_BF16X3), whose arithmetic also rescans.
+// Certified finish of the exhaustive filter from the per-split lists of the
+// scoring pass in `precision` (MRF_FP32 or MRF_BF16X3, whose arithmetic also
+// rescans; see k_certify.hip), on the buffers in b (capacity n each).
+mrf_status certify_run(mrf_dict_s *D, const CertBufs &b, const float *zp, const float *znorm, const uint16_t *zx3,
+                       float *gamma, const float *part_s, const int *part_j, int64_t n, int splits, int precision,
+                       const int32_t *warm, int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s) {
+  const float cE = cert_coeff(precision, D->K);
+  launch_zero(b.counters, 64, s);
+  LAUNCH_CHECK("certificate counters");
+  CertQueue q{b.counters, b.list, b.thr, b.ccount, b.counters + 1, b.scan,
+              reinterpret_cast<unsigned long long *>(b.counters + 2)};
+  CertOut out{znorm, warm, D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr, params_out,
+              gamma};
+  launch_certify(part_s, part_j, splits, n, n, D->d, zp, D->dhat.as<float>(), D->Kp, D->K, cE, cE, kCertAbs, out, q,
+                 s);
+  LAUNCH_CHECK("certify");
+  if (precision == MRF_BF16X3)
+    launch_collect_x3_dev(D->dx3.as<uint16_t>(), zx3, q.list, D->d, D->d_pad, n, q.count, D->Kx, q.thr, q.ccount,
+                          b.cand, kCertCap, s);
+  else
+    launch_collect_f32_dev(D->dhat.as<float>(), zp, q.list, D->d, D->d_pad, n, q.count, D->Kp, q.thr, q.ccount,
+                           b.cand, kCertCap, s);
+  LAUNCH_CHECK("certificate rescan");
+  launch_rescore_collected(zp, D->dhat.as<float>(), D->Kp, D->K, D->d, n, q, b.cand, kCertCap, out, s);
+  LAUNCH_CHECK("certificate rescore");
+  launch_scan_exact(zp, D->dhat.as<float>(), D->Kp, D->K, D->d, n, q, out, s);
+  LAUNCH_CHECK("certificate scan");
+  return MRF_OK;
+}
+
+size_t cert_bytes(int64_t n) { return 64 + (size_t)n * (4 * 5 + 4 * kCertCap); }
+
+// The same on the handle's workspace (grown to n).
 mrf_status certify_exhaustive(mrf_dict_s *D, int64_t n, int splits, int precision, const int32_t *warm, int32_t *idx,
                               float *pd, float *corr, float *params_out, hipStream_t s) {
-  const float cE = cert_coeff(precision, D->K);
   TRY(grow(D->cert, 64));
   TRY(grow(D->cert_list, (size_t)n * 4));
   TRY(grow(D->cert_thr, (size_t)n * 4));
   TRY(grow(D->cert_ccount, (size_t)n * 4));
   TRY(grow(D->cert_scan, (size_t)n * 4));
   TRY(grow(D->cert_cand, (size_t)n * kCertCap * 4));
-  launch_zero(D->cert.p, 64, s);
-  LAUNCH_CHECK("certificate counters");
-  unsigned int *cnt = D->cert.as<unsigned int>();
-  CertQueue q{cnt, D->cert_list.as<int32_t>(), D->cert_thr.as<float>(), D->cert_ccount.as<unsigned int>(), cnt + 1,
-              D->cert_scan.as<int32_t>(), reinterpret_cast<unsigned long long *>(cnt + 2)};
-  CertOut out{D->znorm.as<float>(), warm, D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr,
-              params_out, D->gamma.as<float>()};
-  launch_certify(D->part_s.as<float>(), D->part_j.as<int>(), splits, n, n, D->d, D->zp.as<float>(),
-                 D->dhat.as<float>(), D->Kp, D->K, cE, cE, kCertAbs, out, q, s);
-  LAUNCH_CHECK("certify");
-  if (precision == MRF_BF16X3)
-    launch_collect_x3_dev(D->dx3.as<uint16_t>(), D->zx3.as<uint16_t>(), q.list, D->d, D->d_pad, n, q.count, D->Kx,
-                          q.thr, q.ccount, D->cert_cand.as<int32_t>(), kCertCap, s);
-  else
-    launch_collect_f32_dev(D->dhat.as<float>(), D->zp.as<float>(), q.list, D->d, D->d_pad, n, q.count, D->Kp,
-                           q.thr, q.ccount, D->cert_cand.as<int32_t>(), kCertCap, s);
-  LAUNCH_CHECK("certificate rescan");
-  launch_rescore_collected(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n, q,
-                           D->cert_cand.as<int32_t>(), kCertCap, out, s);
-  LAUNCH_CHECK("certificate rescore");
-  launch_scan_exact(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n, q, out, s);
-  LAUNCH_CHECK("certificate scan");
+  CertBufs b{D->cert.as<unsigned int>(), D->cert_list.as<int32_t>(), D->cert_thr.as<float>(),
+             D->cert_ccount.as<unsigned int>(), D->cert_scan.as<int32_t>(), D->cert_cand.as<int32_t>()};
+  TRY(certify_run(D, b, D->zp.as<float>(), D->znorm.as<float>(), D->zx3.as<uint16_t>(), D->gamma.as<float>(),
+                  D->part_s.as<float>(), D->part_j.as<int>(), n, splits, precision, warm, idx, pd, corr, params_out,
+                  s));
   D->cert_used = true;
   return MRF_OK;
 }

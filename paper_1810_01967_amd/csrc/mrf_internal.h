@@ -140,6 +140,10 @@ struct CertQueue {
   unsigned long long *rescored;
 };
 constexpr int kCertCap = 64;  // candidates per rescanned voxel
+// absolute slack of the scoring passes' error bound (flushed subnormal
+// products) and of the candidate lists' window
+constexpr float kCertAbs = 1e-30f;
+constexpr float kCertWinAbs = 3e-30f;
 // Merge the per-split lists [splits][pstride][kCertK], rescore exactly, finish
 // each voxel and queue the uncertified ones; E_v = cE ||Z_v|| + eabs bounds the
 // scoring pass's error, cE32 ||Z_v|| + eabs that of the FP32 rescan.

@@ -25,7 +25,7 @@ MRF_VOXEL_MAJOR, MRF_FRAME_MAJOR = 0, 1
 PRECISION = {"fp32": MRF_FP32, "bf16": MRF_BF16, "fp8": MRF_FP8, "bf16x3": MRF_BF16X3}
 
 EXPORTS = ["mrf_last_error", "mrf_version", "mrf_dict_build", "mrf_dict_destroy", "mrf_dict_query",
-           "mrf_dict_copy_atoms", "mrf_dict_compress", "mrf_dict_subspace", "mrf_dict_align", "mrf_dict_tree_info", "mrf_dict_tree_export", "mrf_match", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
+           "mrf_dict_copy_atoms", "mrf_dict_compress", "mrf_dict_subspace", "mrf_dict_align", "mrf_dict_tree_info", "mrf_dict_tree_export", "mrf_match", "mrf_match_noalloc", "mrf_match_local", "mrf_net_create", "mrf_net_destroy",
            "mrf_net_size", "mrf_net_set_params", "mrf_net_get_params", "mrf_net_get_grads",
            "mrf_net_set_standardisation", "mrf_net_get_standardisation", "mrf_net_forward",
            "mrf_net_forward_bf16",
@@ -152,6 +152,10 @@ def lib():
                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.POINTER(MatchStats), ctypes.c_void_p]
+        L.mrf_match_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(MatchOpts), ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]
         L.mrf_dict_tree_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(TreeInfo)]
         L.mrf_dict_tree_export.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]
@@ -407,6 +411,25 @@ def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp
     if stats:
         o["stats"] = st
     return o
+
+
+def mrf_match_noalloc(D: Dictionary, Z, out, layout="voxel", slice_voxels=None, atom_splits=0, warm_idx=None,
+                      certify=True, stream=None):
+    """mrf_match_noalloc: the exhaustive FP32 filter on the library's fixed
+    workspace (no device allocation).  `out` holds the caller's CUDA tensors
+    idx (required), pd, corr, X, params (optional)."""
+    torch = _torch()
+    if layout == "voxel":
+        n, zl, sv = Z.shape[0], MRF_VOXEL_MAJOR, 0
+    else:
+        sv = int(slice_voxels) if slice_voxels is not None else int(np.prod(Z.shape[2:]))
+        n, zl = int(Z.numel() // D.L), MRF_FRAME_MAJOR
+    opts = match_opts("fp32", 8, atom_splits, certify=certify)
+    _check(lib().mrf_match_noalloc(D.handle, ctypes.byref(opts), n, _dev(Z, torch.complex64), zl, sv,
+                                   _dev(warm_idx, torch.int32), _dev(out["idx"]), _dev(out.get("pd")),
+                                   _dev(out.get("corr")), _dev(out.get("X")), _dev(out.get("params")),
+                                   _stream(stream)))
+    return out
 
 
 def mrf_match_local(D: Dictionary, Z, cells, layout="voxel", slice_voxels=None, box_radius=3,
