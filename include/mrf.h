@@ -218,12 +218,16 @@ typedef struct mrf_net_s *mrf_net; /* learned proposal network (see below) */
 
 typedef struct {
   int32_t method;      /* MRF_EXHAUSTIVE or MRF_LEARNED */
-  int32_t precision;   /* exhaustive scoring: MRF_FP32 or MRF_BF16X3 (exact argmax of
-                          the scores in that arithmetic), MRF_BF16 or MRF_FP8 (top-k
-                          by reduced-precision score, then FP32 rescore).
-                          MRF_LEARNED: local search and exhaustive fallback in
-                          MRF_FP32 or MRF_BF16X3. */
-  int32_t topk;        /* reduced-precision candidates rescored in FP32, 1..8 (0 = 8) */
+  int32_t precision;   /* exhaustive scoring arithmetic: MRF_FP32, MRF_BF16X3, MRF_BF16 or
+                          MRF_FP8 (FP32 accumulation on the matrix cores).  Certified (see
+                          no_certificate) every precision returns the exact argmax; the
+                          reduced-precision ones (BF16, FP8 with per-row scales) first take
+                          each voxel's maximum, then collect every atom whose score lies
+                          within the derived quantisation bound of the exactly rescored
+                          best (at most 256 per voxel, else the FP32 rescan) and rescore
+                          them exactly.  MRF_LEARNED: local search and exhaustive fallback
+                          in MRF_FP32 or MRF_BF16X3. */
+  int32_t topk;        /* unused (0..8 accepted) */
   int32_t atom_splits; /* 0 = automatic; else number of atom ranges scored in parallel */
   mrf_net net;         /* MRF_LEARNED: trained network (input length = the dictionary's K) */
   int32_t box_radius;  /* MRF_LEARNED: half-width of the local box per parameter (0 = 3) */
@@ -241,16 +245,18 @@ typedef struct {
                             the complex PD rho_v on the normalised atom Dhat_j* with a
                             phase-aligned dictionary (mrf_dict_align), 0 otherwise; the
                             projected-gradient entry points ignore it (their X carries it) */
-  int32_t no_certificate; /* MRF_EXHAUSTIVE with MRF_FP32 or MRF_BF16X3.  0 (default): the
-                            exact argmax of eq. exactP over the FP32 normalised atoms,
-                            certified: the scoring pass keeps each voxel's 8 best atoms,
-                            whose scores are rescored exactly (FP64) while they lie within
-                            the pass's derived error bound of the best exact score; voxels
-                            whose 8 all lie within it are rescanned (every atom within the
-                            FP32 bound collected and rescored exactly, or, past 64 such
-                            atoms, all atoms rescored).  1: the scoring arithmetic's own
-                            argmax, uncertified (FP32 / split-BF16 rounding can pick an atom
-                            whose exact score is below the maximum by up to that bound). */
+  int32_t no_certificate; /* MRF_EXHAUSTIVE.  0 (default): the exact argmax of eq. exactP over
+                            the FP32 normalised atoms, certified.  MRF_FP32 / MRF_BF16X3: the
+                            scoring pass keeps each voxel's 8 best atoms (among those within
+                            twice its derived error bound of the running maximum), rescored
+                            exactly (FP64) while they lie within the bound of the best exact
+                            score; voxels whose 8 all lie within it are rescanned (every atom
+                            within the bound collected and rescored exactly, or, past 64 such
+                            atoms, all atoms rescored).  MRF_BF16 / MRF_FP8: as described at
+                            `precision`.  1: the scoring arithmetic's own argmax, uncertified
+                            (its rounding can pick an atom whose exact score is below the
+                            maximum by up to that bound); PD and corr come from the exact
+                            score of the returned atom for BF16 / FP8. */
 } mrf_match_opts;
 
 typedef struct {

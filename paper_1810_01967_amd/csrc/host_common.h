@@ -153,6 +153,11 @@ struct mrf_dict_s {
   // exactness certificate: counters (u32 queue, u32 scan, u64 rescored), queue
   // (list, thr, candidate counts), scan list, candidates [n][kCertCap]
   mrf::DevBuf cert, cert_list, cert_thr, cert_ccount, cert_scan, cert_cand;
+  // reduced-precision certificate: per voxel the decoded row norms, line, exact
+  // best score, candidate count and candidates [n][kLowpCap]
+  mrf::DevBuf lp_qn, lp_thr, lp_b, lp_count, lp_cand;
+  // max over the atoms of ||r_j|| and ||d_j - r_j|| for the BF16 and FP8 copies r_j
+  double qn_bf16[2] = {0.0, 0.0}, qn_fp8[2] = {0.0, 0.0};
   bool cert_used = false;  // the last exhaustive match ran the certificate
   bool zx3_fresh = false;  // zx3 holds the split rows of the current packing (written by the pack)
   bool zp_fresh = false;   // zp holds the FP32 rows of the current packing

@@ -17,6 +17,7 @@
 // The answer is the lowest index among the exactly highest scores: the exact
 // argmax of eq. exactP over the FP32 normalised atoms, whatever the rounding
 // of the fast pass.
+#include <algorithm>
 #include <cfloat>
 
 #include "k_topk.h"
@@ -213,6 +214,123 @@ __global__ __launch_bounds__(256) void k_scan_exact(const float *__restrict__ Zp
     }
     __syncthreads();
   }
+}
+
+// Reduced-precision passes (BF16 / FP8).  One wave per voxel: merge the
+// pass's split maxima, rescore the best atom exactly (b), finish the voxel
+// with it, and (certified) write the voxel's line for the collect pass.
+// With q_v the decoded voxel row and r_j the atoms' decoded rows, the pass's
+// score (times the voxel's FP8 scale) differs from the exact one by at most
+//   E_v = (gq ||q_v|| + ||z_v - q_v||) max_j ||r_j|| + ||z_v|| max_j ||d_j - r_j||
+// (the products' quantisation errors by Cauchy-Schwarz, gq = gamma_{K+1}
+// the FP32 accumulation and scale multiply), so every atom that could beat or
+// tie b scores at least (b - E_v) / scale_v in the pass's unit.
+__global__ __launch_bounds__(256) void k_lowp_line(const float *__restrict__ part_s, const int *__restrict__ part_j,
+                                                   int splits, int64_t n, int d, const float *__restrict__ Zp,
+                                                   const float *__restrict__ D, int Kp, int K,
+                                                   const double2 *__restrict__ qnorm, const float *__restrict__ zscale,
+                                                   double gq, double Nq, double Ne, double eabs, CertOut o,
+                                                   float *__restrict__ thr, unsigned int *__restrict__ ccount,
+                                                   double *__restrict__ bex, int certify) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n) return;
+  float bs = -INFINITY;
+  int bj = -1;
+  for (int sp = 0; sp < splits; ++sp) {
+    const float ps = part_s[(int64_t)sp * n + v];
+    const int pj = part_j[(int64_t)sp * n + v];
+    if (rank_before(ps, pj, bs, bj)) {
+      bs = ps;
+      bj = pj;
+    }
+  }
+  const float zn = o.znorm[v];
+  if (!(zn > 0.f) || bj < 0) {  // zero or non-finite voxel
+    if (lane == 0) {
+      finish(v, 0.f, bj, d, o);
+      if (certify) {
+        thr[v] = INFINITY;
+        ccount[v] = 0u;
+      }
+    }
+    return;
+  }
+  const double b = dot64(Zp + v * Kp, D + (int64_t)bj * Kp, K, lane);
+  if (lane == 0) {
+    finish(v, (float)b, bj, d, o);
+    if (certify) {
+      const double2 qn = qnorm[v];
+      const double E = 1.01 * ((gq * qn.x + qn.y) * Nq + (double)zn * Ne) + eabs;
+      const double sc = zscale ? (double)zscale[v] : 1.0;
+      const double line = (b - E) / sc;
+      float t = (float)line;
+      if ((double)t > line) t = nextafterf(t, -INFINITY);
+      thr[v] = t;
+      ccount[v] = 0u;
+      bex[v] = b;
+    }
+  }
+}
+
+void launch_lowp_line(const float *part_s, const int *part_j, int splits, int64_t n, int d, const float *Zp,
+                      const float *D, int Kp, int K, const double2 *qnorm, const float *zscale, double gq, double Nq,
+                      double Ne, double eabs, const CertOut &o, float *thr, unsigned int *ccount, double *bex,
+                      int certify, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_lowp_line, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, part_s, part_j, splits, n, d, Zp,
+                     D, Kp, K, qnorm, zscale, gq, Nq, Ne, eabs, o, thr, ccount, bex, certify);
+}
+
+// One wave per voxel: exact rescore of the reduced-precision pass's collected
+// candidates; a voxel with more than ccap of them is queued for the FP32
+// rescan with the FP32 line b - (cE32 ||Z_v|| + eabs).
+__global__ __launch_bounds__(256) void k_rescore_lowp(const float *__restrict__ Zp, const float *__restrict__ D, int Kp,
+                                                      int K, int d, int64_t n, const unsigned int *__restrict__ ccount,
+                                                      const int32_t *__restrict__ cand, int ccap,
+                                                      const double *__restrict__ bex, float cE32, float eabs,
+                                                      CertOut o, CertQueue q) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < n; v += (int64_t)gridDim.x * 4) {
+    const unsigned int c = ccount[v];
+    if (c == 0) continue;  // zero or non-finite voxel, finished already
+    if ((int)c > ccap) {
+      if (lane == 0) {
+        const unsigned int pos = atomicAdd(q.count, 1u);
+        q.list[pos] = (int32_t)v;
+        q.ccount[pos] = 0u;
+        const double line = bex[v] - ((double)cE32 * o.znorm[v] + eabs);
+        float t = (float)line;
+        if ((double)t > line) t = nextafterf(t, -INFINITY);
+        q.thr[pos] = t;
+      }
+      continue;
+    }
+    const float *z = Zp + v * Kp;
+    double bs = -DBL_MAX;
+    int bj = INT32_MAX;
+    for (unsigned int t = 0; t < c; ++t) {
+      const int j = cand[v * ccap + t];
+      const double sc = dot64(z, D + (int64_t)j * Kp, K, lane);
+      if (exact_better(sc, j, bs, bj)) {
+        bs = sc;
+        bj = j;
+      }
+    }
+    if (lane == 0) {
+      atomicAdd(q.rescored, (unsigned long long)c);
+      finish(v, (float)bs, bj, d, o);
+    }
+  }
+}
+
+void launch_rescore_lowp(const float *Zp, const float *D, int Kp, int K, int d, int64_t n, const unsigned int *ccount,
+                         const int32_t *cand, int ccap, const double *bex, float cE32, float eabs, const CertOut &o,
+                         const CertQueue &q, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 3) / 4, 4096);
+  hipLaunchKernelGGL(k_rescore_lowp, dim3((unsigned)blocks), dim3(256), 0, s, Zp, D, Kp, K, d, n, ccount, cand, ccap,
+                     bex, cE32, eabs, o, q);
 }
 
 void launch_scan_exact(const float *Zp, const float *D, int Kp, int K, int d, int64_t cap, const CertQueue &q,

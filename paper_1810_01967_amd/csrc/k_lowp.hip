@@ -1,7 +1,9 @@
 // Reduced-precision matched filter for gfx950: BF16 / FP8-E4M3 row encoders
-// and candidate scoring on MFMA (v_mfma_f32_32x32x16_bf16,
-// v_mfma_scale_f32_32x32x64_f8f6f4) with FP32 accumulation and a fused
-// per-voxel top-8, whose candidates are rescored exactly in FP32 afterwards.
+// and scoring on MFMA (v_mfma_f32_32x32x16_bf16,
+// v_mfma_scale_f32_32x32x64_f8f6f4) with FP32 accumulation.  The scoring
+// kernel's epilogues: the per-voxel maximum, or every atom at or above a
+// per-voxel line (the candidates the exactness certificate rescores).
+#include "k_topk.h"
 #include "mrf_internal.h"
 
 namespace mrf {
@@ -40,18 +42,53 @@ __device__ __forceinline__ uint8_t e4m3_rne(float q) {
   return (uint8_t)(sign | ((e + 7) << 3) | ((int)r - 8));
 }
 
-// One block per row; FP8 rows first reduce amax for the scale.
+__device__ __forceinline__ double e4m3_to_double(uint8_t c) {
+  const int e = (c >> 3) & 0xF, m = c & 7;
+  const double mag = e == 0 ? ldexp((double)m, -9) : ldexp((double)(8 + m), e - 10);
+  return (c & 0x80) ? -mag : mag;
+}
+
+// ||q||^2 and ||x - q||^2 of one row in FP64 (q the decoded value), reduced
+// over the block in a fixed order; thread 0 writes their square roots.
+__device__ __forceinline__ void row_norms(double q2, double e2, double *red, double2 *out) {
+  red[threadIdx.x] = q2;
+  red[256 + threadIdx.x] = e2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      red[threadIdx.x] += red[threadIdx.x + o];
+      red[256 + threadIdx.x] += red[256 + threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = make_double2(sqrt(red[0]), sqrt(red[256]));
+}
+
+// One block per row; FP8 rows first reduce amax for the scale.  norms
+// (optional): per row (||q||, ||x - q||) of the decoded row q (FP8: scale *
+// E4M3 value), for the error bound of the reduced-precision scores.
 __global__ __launch_bounds__(256) void k_quantize_rows(const float *__restrict__ in, int64_t rows,
                                                        int K, int64_t in_pitch, int fp8,
                                                        void *__restrict__ out, int64_t out_pitch,
-                                                       float *__restrict__ scales) {
+                                                       float *__restrict__ scales, double2 *__restrict__ norms) {
   __shared__ float red[256];
+  __shared__ double dred[512];
   const int64_t r = blockIdx.x;
   if (r >= rows) return;
   const float *x = in + r * in_pitch;
   if (!fp8) {
     uint16_t *o = static_cast<uint16_t *>(out) + r * out_pitch;
-    for (int64_t k = threadIdx.x; k < out_pitch; k += 256) o[k] = k < K ? bf16_rne(x[k]) : 0;
+    double q2 = 0.0, e2 = 0.0;
+    for (int64_t k = threadIdx.x; k < out_pitch; k += 256) {
+      const uint16_t c = k < K ? bf16_rne(x[k]) : 0;
+      o[k] = c;
+      if (norms && k < K) {
+        const double q = (double)__uint_as_float((uint32_t)c << 16), e = (double)x[k] - q;
+        q2 += q * q;
+        e2 += e * e;
+      }
+    }
+    if (norms) row_norms(q2, e2, dred, norms + r);
     return;
   }
   float m = 0.f;
@@ -66,54 +103,55 @@ __global__ __launch_bounds__(256) void k_quantize_rows(const float *__restrict__
   const float sc = amax > 0.f ? __fdiv_rn(amax, 448.f) : 1.f;
   if (threadIdx.x == 0) scales[r] = sc;
   uint8_t *o = static_cast<uint8_t *>(out) + r * out_pitch;
-  for (int64_t k = threadIdx.x; k < out_pitch; k += 256)
-    o[k] = k < K ? e4m3_rne(__fdiv_rn(x[k], sc)) : (uint8_t)0;
+  double q2 = 0.0, e2 = 0.0;
+  for (int64_t k = threadIdx.x; k < out_pitch; k += 256) {
+    const uint8_t c = k < K ? e4m3_rne(__fdiv_rn(x[k], sc)) : (uint8_t)0;
+    o[k] = c;
+    if (norms && k < K) {
+      const double q = (double)sc * e4m3_to_double(c), e = (double)x[k] - q;
+      q2 += q * q;
+      e2 += e * e;
+    }
+  }
+  if (norms) row_norms(q2, e2, dred, norms + r);
 }
 
 void launch_quantize_rows(const float *in, int64_t rows, int K, int64_t in_pitch, int precision,
-                          void *out, int64_t out_pitch, float *scales, hipStream_t s) {
+                          void *out, int64_t out_pitch, float *scales, hipStream_t s, double2 *norms) {
   hipLaunchKernelGGL(k_quantize_rows, dim3((unsigned)rows), dim3(256), 0, s, in, rows, K, in_pitch,
-                     precision == MRF_FP8 ? 1 : 0, out, out_pitch, scales);
+                     precision == MRF_FP8 ? 1 : 0, out, out_pitch, scales, norms);
 }
 
 // ---------------------------------------------------------------------------
-// scoring with fused top-8
+// scoring
 // ---------------------------------------------------------------------------
 // Block tile 128 atoms x 128 voxels; K chunks of 128 bytes per row (64 BF16
 // or 128 FP8 values) double-buffered in LDS; four waves 2 x 2, each with
 // 2 x 2 MFMA 32x32 tiles (atoms = rows, voxels = columns, as in the FP32
-// kernel).  Each lane keeps, per voxel column, a sorted list of the 8 best
-// (score, atom) pairs it has seen; the lists of the two half-waves and the
-// two atom halves of the block are merged at the end.
+// kernel), so a lane folds one voxel column per tile.  FP8 scores are the
+// E4M3 products times the atom's scale (the voxel's scale, common to all its
+// scores, is left out: lines are given in the same unit).
+// MODE SC_TOP1: per split and voxel the best (score, atom), lowest atom on
+// equal scores; SC_COLLECT: every atom with score >= thr[v] appended to
+// cand[v][0..ccap) (count[v] counts them all).
 constexpr int Q_BA = 128, Q_BV = 128, Q_CB = 128, Q_LDB = 144;  // bytes per LDS row
 
-__device__ __forceinline__ bool qbetter(float s1, int j1, float s0, int j0) {
-  return (s1 > s0) || (s1 == s0 && j1 >= 0 && (j0 < 0 || j1 < j0));
-}
+struct LowpCollect {
+  const float *thr;
+  unsigned int *count;
+  int32_t *cand;
+  int ccap;
+};
 
-__device__ __forceinline__ void top8_insert(float (&ls)[8], int (&lj)[8], float s, int j) {
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    if (qbetter(s, j, ls[i], lj[i])) {
-      const float ts = ls[i];
-      const int tj = lj[i];
-      ls[i] = s;
-      lj[i] = j;
-      s = ts;
-      j = tj;
-    }
-  }
-}
-
-template <bool FP8>
+template <bool FP8, int MODE>
 __global__ __launch_bounds__(256, 2) void k_score_lowp(const uint8_t *__restrict__ Dq,
                                                        const float *__restrict__ dscale,
                                                        const uint8_t *__restrict__ Zq, int d,
                                                        int ntiles_total, int64_t n, int nvt,
                                                        int row_bytes, int splits,
                                                        int tiles_per_split,
-                                                       float *__restrict__ cand_s,
-                                                       int *__restrict__ cand_j) {
+                                                       float *__restrict__ part_s,
+                                                       int *__restrict__ part_j, LowpCollect col) {
   const int bid = blockIdx.x;
   const int xcd = bid & 7, local = bid >> 3;
   const int split = local % splits;
@@ -124,7 +162,7 @@ __global__ __launch_bounds__(256, 2) void k_score_lowp(const uint8_t *__restrict
 
   __shared__ __attribute__((aligned(16))) uint8_t As[2][Q_BA * Q_LDB];
   __shared__ __attribute__((aligned(16))) uint8_t Zs[2][Q_BV * Q_LDB];
-  __shared__ float tscale[Q_BA];
+  __shared__ float tscale[2][Q_BA];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wa = wave >> 1, wv = wave & 1;
@@ -160,15 +198,16 @@ __global__ __launch_bounds__(256, 2) void k_score_lowp(const uint8_t *__restrict
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
-  float ls[2][8];
-  int lj[2][8];
+  float best[2] = {-INFINITY, -INFINITY};
+  int bidx[2] = {-1, -1};
+  float vthr[2] = {INFINITY, INFINITY};
+  if (MODE == SC_COLLECT) {
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      ls[c][i] = -INFINITY;
-      lj[c][i] = -1;
+    for (int nv = 0; nv < 2; ++nv) {
+      const int64_t v = v0 + wv * 64 + nv * 32 + l32;
+      if (v < n) vthr[nv] = col.thr[v];
     }
+  }
 
   if (nq > 0) {
     gload(0);
@@ -178,9 +217,9 @@ __global__ __launch_bounds__(256, 2) void k_score_lowp(const uint8_t *__restrict
   for (int q = 0; q < nq; ++q) {
     const int buf = q & 1;
     const int kc = q % nkc;
-    if (FP8 && kc == 0) {
+    if (FP8 && kc == 0) {  // the tile's atom scales, double-buffered by tile parity
       const int tile = tb + q / nkc;
-      if (tid < Q_BA) tscale[tid] = dscale[tile * Q_BA + tid];
+      if (tid < Q_BA) tscale[tile & 1][tid] = dscale[tile * Q_BA + tid];
     }
     if (q + 1 < nq) gload(q + 1);
     if (FP8) {
@@ -232,11 +271,12 @@ __global__ __launch_bounds__(256, 2) void k_score_lowp(const uint8_t *__restrict
       }
     }
     if (kc == nkc - 1) {
-      if (FP8) __syncthreads();  // tscale visible (written this chunk by tid < 128)
+      if (FP8 && nkc == 1) __syncthreads();  // the scales written above, this same step
       const int tile = tb + q / nkc;
       const int abase = tile * Q_BA + wa * 64;
 #pragma unroll
       for (int nv = 0; nv < 2; ++nv) {
+        const int64_t v = v0 + wv * 64 + nv * 32 + l32;
 #pragma unroll
         for (int ma = 0; ma < 2; ++ma) {
 #pragma unroll
@@ -244,8 +284,16 @@ __global__ __launch_bounds__(256, 2) void k_score_lowp(const uint8_t *__restrict
             const int m = wa * 64 + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
             const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
             float sc = acc[ma][nv][i];
-            if (FP8) sc *= tscale[m];
-            if (j < d && sc > ls[nv][7]) top8_insert(ls[nv], lj[nv], sc, j);
+            if (FP8) sc *= tscale[tile & 1][m];
+            if (MODE == SC_TOP1) {
+              if (j < d && sc > best[nv]) {  // atoms in increasing order: '>' keeps the lowest index
+                best[nv] = sc;
+                bidx[nv] = j;
+              }
+            } else if (j < d && v < n && sc >= vthr[nv]) {
+              const unsigned int pos = atomicAdd(&col.count[v], 1u);
+              if ((int)pos < col.ccap) col.cand[v * col.ccap + pos] = j;
+            }
           }
         }
       }
@@ -259,77 +307,76 @@ __global__ __launch_bounds__(256, 2) void k_score_lowp(const uint8_t *__restrict
     if (q + 1 < nq) sstore(buf ^ 1);
     __syncthreads();
   }
+  if (MODE == SC_COLLECT) return;
 
-  // merge the half-waves' lists
+  // the half-waves, then the two atom halves of the block through LDS
 #pragma unroll
   for (int nv = 0; nv < 2; ++nv) {
-    float ps[8];
-    int pj[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      ps[i] = __shfl_xor(ls[nv][i], 32, 64);
-      pj[i] = __shfl_xor(lj[nv][i], 32, 64);
+    const float ps = __shfl_xor(best[nv], 32, 64);
+    const int pj = __shfl_xor(bidx[nv], 32, 64);
+    if (rank_before(ps, pj, best[nv], bidx[nv])) {
+      best[nv] = ps;
+      bidx[nv] = pj;
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (pj[i] >= 0) top8_insert(ls[nv], lj[nv], ps[i], pj[i]);
   }
-  // merge the two atom halves through LDS
   float *rs = reinterpret_cast<float *>(&As[0][0]);
   int *rj = reinterpret_cast<int *>(&Zs[0][0]);
   if (wa == 1 && h == 0) {
 #pragma unroll
-    for (int nv = 0; nv < 2; ++nv)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int c = wv * 64 + nv * 32 + l32;
-        rs[c * 8 + i] = ls[nv][i];
-        rj[c * 8 + i] = lj[nv][i];
-      }
+    for (int nv = 0; nv < 2; ++nv) {
+      rs[wv * 64 + nv * 32 + l32] = best[nv];
+      rj[wv * 64 + nv * 32 + l32] = bidx[nv];
+    }
   }
   __syncthreads();
   if (wa == 0 && h == 0) {
 #pragma unroll
     for (int nv = 0; nv < 2; ++nv) {
       const int c = wv * 64 + nv * 32 + l32;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int pj = rj[c * 8 + i];
-        if (pj >= 0) top8_insert(ls[nv], lj[nv], rs[c * 8 + i], pj);
+      if (rank_before(rs[c], rj[c], best[nv], bidx[nv])) {
+        best[nv] = rs[c];
+        bidx[nv] = rj[c];
       }
       const int64_t v = v0 + c;
       if (v < n) {
-        float *os = cand_s + ((int64_t)split * n + v) * 8;
-        int *oj = cand_j + ((int64_t)split * n + v) * 8;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          os[i] = ls[nv][i];
-          oj[i] = lj[nv][i];
-        }
+        part_s[(int64_t)split * n + v] = best[nv];
+        part_j[(int64_t)split * n + v] = bidx[nv];
       }
     }
   }
 }
 
-void launch_score_lowp(int precision, const void *Dq, const float *dscale, const void *Zq, int d,
-                       int64_t d_pad, int64_t n, int64_t n_pad, int Kq, int splits, float *cand_s,
-                       int *cand_j, hipStream_t s) {
+template <int MODE>
+void launch_lowp(int precision, const void *Dq, const float *dscale, const void *Zq, int d, int64_t d_pad, int64_t n,
+                 int Kq, int splits, float *part_s, int *part_j, LowpCollect col, hipStream_t s) {
   const int ntiles = (int)(d_pad / Q_BA);
   const int nvt = (int)((n + Q_BV - 1) / Q_BV);
-  (void)n_pad;
   const int tiles_per_split = (ntiles + splits - 1) / splits;
   const int nvt8 = (nvt + 7) / 8 * 8;
   const int64_t blocks = (int64_t)nvt8 * splits;
+  if (blocks <= 0) return;
   const bool fp8 = precision == MRF_FP8;
   const int row_bytes = fp8 ? Kq : 2 * Kq;
   if (fp8)
-    hipLaunchKernelGGL(k_score_lowp<true>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       static_cast<const uint8_t *>(Dq), dscale, static_cast<const uint8_t *>(Zq),
-                       d, ntiles, n, nvt, row_bytes, splits, tiles_per_split, cand_s, cand_j);
+    hipLaunchKernelGGL((k_score_lowp<true, MODE>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const uint8_t *>(Dq), dscale, static_cast<const uint8_t *>(Zq), d, ntiles, n, nvt,
+                       row_bytes, splits, tiles_per_split, part_s, part_j, col);
   else
-    hipLaunchKernelGGL(k_score_lowp<false>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       static_cast<const uint8_t *>(Dq), nullptr, static_cast<const uint8_t *>(Zq),
-                       d, ntiles, n, nvt, row_bytes, splits, tiles_per_split, cand_s, cand_j);
+    hipLaunchKernelGGL((k_score_lowp<false, MODE>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const uint8_t *>(Dq), nullptr, static_cast<const uint8_t *>(Zq), d, ntiles, n, nvt,
+                       row_bytes, splits, tiles_per_split, part_s, part_j, col);
+}
+
+void launch_score_lowp(int precision, const void *Dq, const float *dscale, const void *Zq, int d, int64_t d_pad,
+                       int64_t n, int Kq, int splits, float *part_s, int *part_j, hipStream_t s) {
+  launch_lowp<SC_TOP1>(precision, Dq, dscale, Zq, d, d_pad, n, Kq, splits, part_s, part_j, LowpCollect{}, s);
+}
+
+void launch_collect_lowp(int precision, const void *Dq, const float *dscale, const void *Zq, int d, int64_t d_pad,
+                         int64_t n, int Kq, int splits, const float *thr, unsigned int *count, int32_t *cand, int ccap,
+                         hipStream_t s) {
+  launch_lowp<SC_COLLECT>(precision, Dq, dscale, Zq, d, d_pad, n, Kq, splits, nullptr, nullptr,
+                          LowpCollect{thr, count, cand, ccap}, s);
 }
 
 }  // namespace mrf

@@ -688,79 +688,6 @@ void launch_merge_argmax(const float *part_s, const int *part_j, int splits, int
 }
 
 // ---------------------------------------------------------------------------
-// top-k merge + FP32 rescore
-// ---------------------------------------------------------------------------
-// One wave per voxel: merge the splits' candidate lists into the k best
-// (score desc, index asc), then the exact FP32 dot products of those k atoms
-// with the voxel, reduced across lanes in a fixed order.
-__global__ __launch_bounds__(256) void k_merge_rescore(
-    const float *__restrict__ cand_s, const int *__restrict__ cand_j, int splits, int topk,
-    int64_t n, int d, const float *__restrict__ Zp, const float *__restrict__ D, int Kp, int K,
-    const float *znorm, const int32_t *warm, const float *inv_norm, const float *params,
-    int nparam, int32_t *idx, float *pd, float *corr, float *params_out, float *gamma_hat) {
-  const int lane = threadIdx.x & 63;
-  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (v >= n) return;
-  // merged top-k held redundantly by every lane (k <= 8)
-  float ks[8];
-  int kj[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    ks[i] = -FLT_MAX;
-    kj[i] = -1;
-  }
-  for (int s = 0; s < splits; ++s) {
-    const float *cs = cand_s + ((int64_t)s * n + v) * 8;
-    const int *cj = cand_j + ((int64_t)s * n + v) * 8;
-    for (int c = 0; c < 8; ++c) {
-      const int j = cj[c];
-      if (j < 0) continue;
-      const float sc = cs[c];
-      if (!better(sc, j, ks[topk - 1], kj[topk - 1])) continue;
-      // insertion into the sorted list
-      int pos = topk - 1;
-      while (pos > 0 && better(sc, j, ks[pos - 1], kj[pos - 1])) {
-        ks[pos] = ks[pos - 1];
-        kj[pos] = kj[pos - 1];
-        --pos;
-      }
-      ks[pos] = sc;
-      kj[pos] = j;
-    }
-  }
-  // exact rescore of the candidates
-  const float *z = Zp + v * Kp;
-  float bs = -FLT_MAX;
-  int bj = -1;
-  for (int c = 0; c < topk; ++c) {
-    const int j = kj[c];
-    if (j < 0) continue;
-    const float *a = D + (int64_t)j * Kp;
-    float acc = 0.f;
-    for (int k = lane; k < K; k += 64) acc = fmaf(z[k], a[k], acc);
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (better(acc, j, bs, bj)) {
-      bs = acc;
-      bj = j;
-    }
-  }
-  if (lane == 0)
-    finish_voxel(v, bs, bj, d, znorm, warm, inv_norm, params, nparam, idx, pd, corr, params_out,
-                 gamma_hat);
-}
-
-void launch_merge_rescore(const float *cand_s, const int *cand_j, int splits, int topk, int64_t n,
-                          int d, const float *Zp, const float *D, int Kp, int K, const float *znorm,
-                          const int32_t *warm, const float *inv_norm, const float *params,
-                          int nparam, int32_t *idx, float *pd, float *corr, float *params_out,
-                          float *gamma_hat, hipStream_t s) {
-  const int64_t blocks = (n + 3) / 4;
-  hipLaunchKernelGGL(k_merge_rescore, dim3((unsigned)blocks), dim3(256), 0, s, cand_s, cand_j,
-                     splits, topk, n, d, Zp, D, Kp, K, znorm, warm, inv_norm, params, nparam, idx, pd,
-                     corr, params_out, gamma_hat);
-}
-
-// ---------------------------------------------------------------------------
 // X = gamma_hat * Dhat_idx
 // ---------------------------------------------------------------------------
 template <bool FRAME, bool DELTA>

@@ -183,19 +183,37 @@ extern "C" mrf_status mrf_dict_build(const mrf_dict_desc *desc, mrf_stream strea
   }
   HIP_TRY(hipMemcpy(D->params.p, pf.data(), pf.size() * sizeof(float), hipMemcpyHostToDevice));
   D->bytes = (int64_t)(D->dhat.cap + D->inv_norm.cap + D->params.cap);
+  // reduced-precision copies, with the largest decoded-row and quantisation
+  // error norms over the atoms (the certificate's per-dictionary constants)
+  DevBuf qn;
+  std::vector<double> qnh;
+  auto qmax = [&](double *out) -> mrf_status {
+    qnh.resize((size_t)2 * q.d);
+    HIP_TRY(hipMemcpyAsync(qnh.data(), qn.p, qnh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    out[0] = out[1] = 0.0;
+    for (int64_t j = 0; j < q.d; ++j) {
+      out[0] = std::max(out[0], qnh[(size_t)2 * j]);
+      out[1] = std::max(out[1], qnh[(size_t)2 * j + 1]);
+    }
+    return MRF_OK;
+  };
+  if (q.flags & (MRF_STORE_BF16 | MRF_STORE_FP8)) TRY(grow(qn, (size_t)D->d_pad * 16));
   if (q.flags & MRF_STORE_BF16) {
     TRY(grow(D->dbf16, (size_t)D->d_pad * D->Kq * 2));
     launch_quantize_rows(D->dhat.as<float>(), D->d_pad, D->K, D->Kp, MRF_BF16, D->dbf16.p, D->Kq,
-                         nullptr, s);
+                         nullptr, s, qn.as<double2>());
     LAUNCH_CHECK("quantize_rows(bf16)");
+    TRY(qmax(D->qn_bf16));
     D->bytes += (int64_t)D->dbf16.cap;
   }
   if (q.flags & MRF_STORE_FP8) {
     TRY(grow(D->dfp8, (size_t)D->d_pad * D->Kq));
     TRY(grow(D->fp8_scale, (size_t)D->d_pad * sizeof(float)));
     launch_quantize_rows(D->dhat.as<float>(), D->d_pad, D->K, D->Kp, MRF_FP8, D->dfp8.p, D->Kq,
-                         D->fp8_scale.as<float>(), s);
+                         D->fp8_scale.as<float>(), s, qn.as<double2>());
     LAUNCH_CHECK("quantize_rows(fp8)");
+    TRY(qmax(D->qn_fp8));
     D->bytes += (int64_t)(D->dfp8.cap + D->fp8_scale.cap);
   }
   if (tree) TRY(upload_tree(D, xnorm.data()));
@@ -437,26 +455,66 @@ mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, c
     LAUNCH_CHECK("merge_argmax");
     return MRF_OK;
   }
-  const int topk = (o && o->topk > 0) ? o->topk : 8;
+  // BF16 / FP8: the pass's per-voxel maximum, rescored exactly; certified,
+  // a second pass collects every atom at or above the voxel's line, all of
+  // them rescored exactly (an overflowing voxel goes to the FP32 rescan)
   const bool fp8 = precision == MRF_FP8;
   TRY(grow(D->zq, (size_t)n_pad * D->Kq * (fp8 ? 1 : 2)));
   if (fp8) TRY(grow(D->zscale, (size_t)n_pad * 4));
+  TRY(grow(D->lp_qn, (size_t)n_pad * 16));
   launch_quantize_rows(D->zp.as<float>(), n_pad, D->K, D->Kp, precision, D->zq.p, D->Kq,
-                       fp8 ? D->zscale.as<float>() : nullptr, s);
+                       fp8 ? D->zscale.as<float>() : nullptr, s, certify ? D->lp_qn.as<double2>() : nullptr);
   LAUNCH_CHECK("quantize_rows");
-  TRY(grow(D->cand_s, (size_t)splits * n * 8 * 4));
-  TRY(grow(D->cand_j, (size_t)splits * n * 8 * 4));
+  TRY(grow(D->part_s, (size_t)splits * n * 4));
+  TRY(grow(D->part_j, (size_t)splits * n * 4));
+  const void *Dq = fp8 ? D->dfp8.p : D->dbf16.p;
+  const float *dsc = fp8 ? D->fp8_scale.as<float>() : nullptr;
   if (ev_s0) HIP_TRY(hipEventRecord(ev_s0, s));
-  launch_score_lowp(precision, fp8 ? D->dfp8.p : D->dbf16.p, fp8 ? D->fp8_scale.as<float>() : nullptr,
-                    D->zq.p, D->d, D->d_pad, n, n_pad, D->Kq, splits, D->cand_s.as<float>(),
-                    D->cand_j.as<int>(), s);
+  launch_score_lowp(precision, Dq, dsc, D->zq.p, D->d, D->d_pad, n, D->Kq, splits, D->part_s.as<float>(),
+                    D->part_j.as<int>(), s);
   LAUNCH_CHECK("score_lowp");
   if (ev_s1) HIP_TRY(hipEventRecord(ev_s1, s));
-  launch_merge_rescore(D->cand_s.as<float>(), D->cand_j.as<int>(), splits, topk, n, D->d,
-                       D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->znorm.as<float>(),
-                       warm, D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd,
-                       corr, params_out, D->gamma.as<float>(), s);
-  LAUNCH_CHECK("merge_rescore");
+  CertOut out{D->znorm.as<float>(), warm, D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr,
+              params_out, D->gamma.as<float>()};
+  const double *qd = fp8 ? D->qn_fp8 : D->qn_bf16;
+  if (certify) {
+    TRY(grow(D->lp_thr, (size_t)n * 4));
+    TRY(grow(D->lp_b, (size_t)n * 8));
+    TRY(grow(D->lp_count, (size_t)n * 4));
+    TRY(grow(D->lp_cand, (size_t)n * kLowpCap * 4));
+  }
+  launch_lowp_line(D->part_s.as<float>(), D->part_j.as<int>(), splits, n, D->d, D->zp.as<float>(),
+                   D->dhat.as<float>(), D->Kp, D->K, D->lp_qn.as<double2>(), fp8 ? D->zscale.as<float>() : nullptr,
+                   gamma_n((double)D->K + 1.0), qd[0], qd[1], kCertAbs, out, D->lp_thr.as<float>(),
+                   D->lp_count.as<unsigned int>(), D->lp_b.as<double>(), certify ? 1 : 0, s);
+  LAUNCH_CHECK("lowp line");
+  if (!certify) return MRF_OK;
+  launch_collect_lowp(precision, Dq, dsc, D->zq.p, D->d, D->d_pad, n, D->Kq, splits, D->lp_thr.as<float>(),
+                      D->lp_count.as<unsigned int>(), D->lp_cand.as<int32_t>(), kLowpCap, s);
+  LAUNCH_CHECK("collect_lowp");
+  TRY(grow(D->cert, 64));
+  TRY(grow(D->cert_list, (size_t)n * 4));
+  TRY(grow(D->cert_thr, (size_t)n * 4));
+  TRY(grow(D->cert_ccount, (size_t)n * 4));
+  TRY(grow(D->cert_scan, (size_t)n * 4));
+  TRY(grow(D->cert_cand, (size_t)n * kCertCap * 4));
+  launch_zero(D->cert.p, 64, s);
+  unsigned int *cnt = D->cert.as<unsigned int>();
+  CertQueue q{cnt, D->cert_list.as<int32_t>(), D->cert_thr.as<float>(), D->cert_ccount.as<unsigned int>(), cnt + 1,
+              D->cert_scan.as<int32_t>(), reinterpret_cast<unsigned long long *>(cnt + 2)};
+  launch_rescore_lowp(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n, D->lp_count.as<unsigned int>(),
+                      D->lp_cand.as<int32_t>(), kLowpCap, D->lp_b.as<double>(), cert_coeff(MRF_FP32, D->K), kCertAbs,
+                      out, q, s);
+  LAUNCH_CHECK("rescore_lowp");
+  launch_collect_f32_dev(D->dhat.as<float>(), D->zp.as<float>(), q.list, D->d, D->d_pad, n, q.count, D->Kp, q.thr,
+                         q.ccount, D->cert_cand.as<int32_t>(), kCertCap, s);
+  LAUNCH_CHECK("certificate rescan");
+  launch_rescore_collected(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n, q,
+                           D->cert_cand.as<int32_t>(), kCertCap, out, s);
+  LAUNCH_CHECK("certificate rescore");
+  launch_scan_exact(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n, q, out, s);
+  LAUNCH_CHECK("certificate scan");
+  D->cert_used = true;
   return MRF_OK;
 }
 

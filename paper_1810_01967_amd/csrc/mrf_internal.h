@@ -91,13 +91,16 @@ void launch_collect_f32_dev(const float *D, const float *Zp, const int32_t *rows
                             int64_t cap, const unsigned int *dcnt, int Kp, const float *thr, unsigned int *count,
                             int32_t *cand, int ccap, hipStream_t s);
 
-// Reduced-precision scoring with a fused per-voxel top-k (k <= 8).  Dq/Zq are
-// BF16 (uint16) or FP8-E4M3 (uint8) rows of pitch Kq; dscale (FP8 only) the
-// per-atom scales.  Writes per-split candidate lists [splits][n][8]
-// (score, index), unused slots index -1.
-void launch_score_lowp(int precision, const void *Dq, const float *dscale, const void *Zq,
-                       int d, int64_t d_pad, int64_t n, int64_t n_pad, int Kq, int splits,
-                       float *cand_s, int *cand_j, hipStream_t s);
+// Reduced-precision scoring (BF16 / FP8-E4M3 rows Dq, Zq of pitch Kq; dscale
+// the FP8 atoms' scales): per split and voxel the best (score, atom)
+// [splits][n]; FP8 scores leave out the voxel's scale.
+void launch_score_lowp(int precision, const void *Dq, const float *dscale, const void *Zq, int d, int64_t d_pad,
+                       int64_t n, int Kq, int splits, float *part_s, int *part_j, hipStream_t s);
+// The same pass collecting every atom with score >= thr[v] into
+// cand[v][0..ccap) (count[v] counts them all; zeroed by the caller).
+void launch_collect_lowp(int precision, const void *Dq, const float *dscale, const void *Zq, int d, int64_t d_pad,
+                         int64_t n, int Kq, int splits, const float *thr, unsigned int *count, int32_t *cand, int ccap,
+                         hipStream_t s);
 
 // Merge the per-split partial argmax, then rescale (eq. exactPs) and look up.
 // gamma_hat[v] = max(score,0) is the multiplier of the normalised atom.
@@ -105,14 +108,6 @@ void launch_merge_argmax(const float *part_s, const int *part_j, int splits, int
                          const float *znorm, const int32_t *warm, const float *inv_norm,
                          const float *params, int nparam, int32_t *idx, float *pd, float *corr,
                          float *params_out, float *gamma_hat, hipStream_t s);
-// Merge per-split top-k candidate lists, rescore the k best in FP32 against
-// the FP32 normalised atoms, then rescale and look up as launch_merge_argmax.
-void launch_merge_rescore(const float *cand_s, const int *cand_j, int splits, int topk,
-                          int64_t n, int d, const float *Zp, const float *D, int Kp, int K,
-                          const float *znorm, const int32_t *warm, const float *inv_norm,
-                          const float *params, int nparam, int32_t *idx, float *pd, float *corr,
-                          float *params_out, float *gamma_hat, hipStream_t s);
-
 // Exactness certificate of the exhaustive filter (k_certify.hip).  Outputs
 // and look-ups of the rescaling step, as the merge kernels take them.
 struct CertOut {
@@ -154,6 +149,19 @@ void launch_rescore_collected(const float *Zp, const float *D, int Kp, int K, in
                               const int32_t *cand, int ccap, const CertOut &o, hipStream_t s);
 void launch_scan_exact(const float *Zp, const float *D, int Kp, int K, int d, int64_t cap, const CertQueue &q,
                        const CertOut &o, hipStream_t s);
+// Reduced-precision passes: merge the split maxima, rescore the best exactly,
+// finish every voxel and (certify) write its line thr[v] (in the pass's unit)
+// and exact best score bex[v], zeroing ccount[v] (see k_certify.hip).
+void launch_lowp_line(const float *part_s, const int *part_j, int splits, int64_t n, int d, const float *Zp,
+                      const float *D, int Kp, int K, const double2 *qnorm, const float *zscale, double gq, double Nq,
+                      double Ne, double eabs, const CertOut &o, float *thr, unsigned int *ccount, double *bex,
+                      int certify, hipStream_t s);
+// Exact rescore of the collected candidates of every voxel; overflowing voxels
+// (> ccap) are queued in q for the FP32 rescan.
+void launch_rescore_lowp(const float *Zp, const float *D, int Kp, int K, int d, int64_t n, const unsigned int *ccount,
+                         const int32_t *cand, int ccap, const double *bex, float cE32, float eabs, const CertOut &o,
+                         const CertQueue &q, hipStream_t s);
+constexpr int kLowpCap = 256;  // candidates per voxel of a reduced-precision collect pass
 
 // X_v = gamma_hat_v * Dhat_{idx_v} (zero where idx < 0), written voxel-major
 // [n][L] or frame-major [S][L][npix].  With X_prev != nullptr (frame-major only)
@@ -164,9 +172,10 @@ void launch_write_x(const int32_t *idx, const float *gamma_hat, const float *D, 
                     float2 *X, const float2 *X_prev, float2 *dX, double *part, int *nblocks_out,
                     hipStream_t s, const float2 *vphase = nullptr);
 
-// BF16 / FP8 row encoders (see mrf_quantize_rows).
+// BF16 / FP8 row encoders (see mrf_quantize_rows); norms (optional): per row
+// (||q||, ||x - q||) of the decoded row q, in FP64.
 void launch_quantize_rows(const float *in, int64_t rows, int K, int64_t in_pitch, int precision,
-                          void *out, int64_t out_pitch, float *scales, hipStream_t s);
+                          void *out, int64_t out_pitch, float *scales, hipStream_t s, double2 *norms = nullptr);
 
 // ---------------------------------------------------------------- Fourier operator
 // In-place unitary 2-D DFT of `nimg` frames of ny x nx complex64 (forward:

@@ -243,3 +243,40 @@ def test_quantised_match_recovers_noiseless_atoms():
     for prec in ("bf16", "fp8"):
         r = quant.quantised_match(quant.as_real_rows(Z), quant.as_real_rows(Dhat), prec, topk=8)
         assert np.array_equal(r["idx"], j)
+
+
+def test_quantised_score_error_bound():
+    """The certificate's bound on reduced-precision scores: with q the decoded
+    voxel row and r_j the decoded atom row, |<q, r_j> - <z, d_j>| <=
+    ||z - q|| ||r_j|| + ||z|| ||d_j - r_j|| (Cauchy-Schwarz on the two error
+    terms of q r - z d = (q - z) r + z (r - d)).  Checked on every pair of a
+    coherent dictionary; dropping either term is caught."""
+    D = workloads.bssfp_dictionary(L=60, n_t1=12, n_t2=12, n_df=7, seed=2)
+    Z, _, _, _ = workloads.random_voxels(D, 300, seed=14, snr_db_range=(10.0, 40.0))
+    zr = quant.as_real_rows(Z.astype(np.complex64)).astype(np.float32)
+    dr = quant.as_real_rows(mf.normalised_atoms_f32(D.atoms)).astype(np.float32)
+    s = zr.astype(np.float64) @ dr.astype(np.float64).T
+    for prec in ("bf16", "fp8"):
+        if prec == "bf16":
+            zq, dq = quant.bf16_round(zr).astype(np.float64), quant.bf16_round(dr).astype(np.float64)
+        else:
+            zq, dq = quant.quantise_rows_e4m3(zr)[2], quant.quantise_rows_e4m3(dr)[2]
+        err = np.abs(zq @ dq.T - s)
+        ez = np.linalg.norm(zr - zq, axis=1)[:, None]
+        qn = np.linalg.norm(dq, axis=1)[None, :]
+        zn = np.linalg.norm(zr, axis=1)[:, None]
+        ed = np.linalg.norm(dr - dq, axis=1)[None, :]
+        bound = ez * qn + zn * ed
+        assert np.all(err <= bound * (1 + 1e-12))
+        # the bound is not vacuous: it is within two orders of the worst error
+        assert np.max(err / bound) > 0.01
+    # each term is needed: with BF16-exact atoms (d = r) only the voxel term
+    # remains, with BF16-exact voxels (z = q) only the atom term, and both
+    # errors are non-zero
+    db = quant.bf16_round(dr)
+    zb = quant.bf16_round(zr)
+    err_v = np.abs(quant.bf16_round(zr).astype(np.float64) @ db.astype(np.float64).T
+                   - zr.astype(np.float64) @ db.astype(np.float64).T)
+    err_a = np.abs(zb.astype(np.float64) @ quant.bf16_round(dr).astype(np.float64).T
+                   - zb.astype(np.float64) @ dr.astype(np.float64).T)
+    assert np.max(err_v) > 0 and np.max(err_a) > 0
