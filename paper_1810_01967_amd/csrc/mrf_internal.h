@@ -334,6 +334,15 @@ void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys
 void launch_score_x3(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t n, int64_t n_pad,
                      int Kx, int splits, float *part_s, int *part_j, hipStream_t s, bool topk = false,
                      const float *znorm = nullptr, float cw = 0.f, float wabs = 0.f);
+// BF16 matrix-core scoring (k_score_mx.hip): atoms D [d_pad][Kq], voxels Z
+// [round_up(n, 256)][Kq]; per split and voxel the best (score, atom) [splits][n]
+// (lowest atom on equal scores), or every atom with score >= thr[v] collected
+// into cand[v][0..ccap) (count[v] counts them all; zeroed by the caller).
+int mx_auto_splits(int64_t d_pad, int64_t n);
+void launch_score_mx(const uint16_t *D, const uint16_t *Z, int Kq, int d, int64_t d_pad, int64_t n, int splits,
+                     float *part_s, int *part_j, hipStream_t s);
+void launch_collect_mx(const uint16_t *D, const uint16_t *Z, int Kq, int d, int64_t d_pad, int64_t n, int splits,
+                       const float *thr, unsigned int *count, int32_t *cand, int ccap, hipStream_t s);
 // The split-BF16 filter over the split rows Zx[rows[i]] for i < *dcnt (<= cap),
 // collecting atoms as launch_collect_f32_dev.
 void launch_collect_x3_dev(const uint16_t *Dx, const uint16_t *Zx, const int32_t *rows, int d, int64_t d_pad,
