@@ -129,18 +129,33 @@ def bssfp(T1, T2, df, alpha_deg, phase_rad, TR: float, TE: float, TI: float,
     return out
 
 
+def _bssfp_rows(p, alpha_deg, phase_rad, TR, TE, TI, has_b1):
+    if has_b1:
+        return bssfp(p[:, 0], p[:, 1], p[:, 3], alpha_deg, phase_rad, TR, TE, TI, B1=p[:, 2])
+    return bssfp(p[:, 0], p[:, 1], p[:, 2], alpha_deg, phase_rad, TR, TE, TI)
+
+
+def _bssfp_chunk_job(args):
+    p, alpha_deg, phase_rad, TR, TE, TI, has_b1, dtype = args
+    return _bssfp_rows(p, alpha_deg, phase_rad, TR, TE, TI, has_b1).astype(dtype)
+
+
 def bssfp_chunked(params: np.ndarray, alpha_deg, phase_rad, TR, TE, TI,
-                  has_b1: bool = False, chunk: int = 65536, dtype=np.complex128):
-    """bssfp over a params table [d][P] (T1, T2, [B1,] df), in atom chunks."""
+                  has_b1: bool = False, chunk: int = 65536, dtype=np.complex128, workers: int = 1):
+    """bssfp over a params table [d][P] (T1, T2, [B1,] df), in atom chunks;
+    workers > 1 computes the chunks in forked processes (the same values: each
+    atom's recursion is independent of the chunking)."""
     d = params.shape[0]
     L = len(alpha_deg)
     out = np.empty((d, L), dtype=dtype)
-    for s in range(0, d, chunk):
-        p = params[s:s + chunk]
-        if has_b1:
-            out[s:s + chunk] = bssfp(p[:, 0], p[:, 1], p[:, 3], alpha_deg, phase_rad,
-                                     TR, TE, TI, B1=p[:, 2])
-        else:
-            out[s:s + chunk] = bssfp(p[:, 0], p[:, 1], p[:, 2], alpha_deg, phase_rad,
-                                     TR, TE, TI)
+    starts = list(range(0, d, chunk))
+    if workers > 1 and len(starts) > 1:
+        import multiprocessing
+        jobs = [(params[s:s + chunk], alpha_deg, phase_rad, TR, TE, TI, has_b1, dtype) for s in starts]
+        with multiprocessing.get_context("fork").Pool(min(workers, len(starts))) as pool:
+            for s, rows in zip(starts, pool.imap(_bssfp_chunk_job, jobs)):
+                out[s:s + chunk] = rows
+        return out
+    for s in starts:
+        out[s:s + chunk] = _bssfp_rows(params[s:s + chunk], alpha_deg, phase_rad, TR, TE, TI, has_b1)
     return out

@@ -66,7 +66,7 @@ def bssfp_dictionary(L: int = 500, n_t1: int = 60, n_t2: int = 60, n_df: int = 2
                      t1_range=(100.0, 4000.0), t2_range=(10.0, 600.0),
                      df_range=(-40.0, 40.0), b1_axis=None, seed: int = 2,
                      t2_lt_t1: bool = False, TR=10.0, TE=5.0, TI=10.0,
-                     dtype=np.complex128) -> Dictionary:
+                     dtype=np.complex128, workers: int = 1) -> Dictionary:
     """Complex IR-bSSFP dictionary on T1 x T2 [x B1] x df (256x256 workload:
     L=500, 60 x 60 x 28 = 100,800 atoms)."""
     t1 = grids.log_grid(*t1_range, n_t1)
@@ -78,7 +78,7 @@ def bssfp_dictionary(L: int = 500, n_t1: int = 60, n_t2: int = 60, n_df: int = 2
     alpha = sequences.halfsine_train(L, seed)
     phase = sequences.alternating_phase(L)
     atoms = bloch.bssfp_chunked(params, alpha, phase, TR, TE, TI,
-                                has_b1=b1_axis is not None, dtype=dtype)
+                                has_b1=b1_axis is not None, dtype=dtype, workers=workers)
     dims = None if t2_lt_t1 else tuple(len(a) for a in axes)
     return Dictionary(atoms, params, dims, axes, names,
                       dict(kind="bssfp", alpha=alpha, phase=phase, TR=TR, TE=TE, TI=TI))
@@ -172,7 +172,7 @@ def _smooth_field(seed: int, tag: str, S: int, ny: int, nx: int, width: float) -
 
 
 def smooth_phantom(D: Dictionary, seed: int = 4, S: int = 8, size: int = 256,
-                   n_tissue: int = 6, pd_range=(0.3, 1.0)) -> Phantom:
+                   n_tissue: int = 6, pd_range=(0.3, 1.0), dtype=np.complex128) -> Phantom:
     """Multi-slice phantom on grid atoms (multi-slice IPG workloads).
 
     Per slice: an elliptical head region split into ``n_tissue`` smooth random
@@ -207,7 +207,7 @@ def smooth_phantom(D: Dictionary, seed: int = 4, S: int = 8, size: int = 256,
     pd = np.where(head, pd, 0.0)
     idx = np.where(head, idx, -1)
     params = np.where(head[:, None], D.params[np.maximum(idx, 0)], np.nan)
-    vox = np.zeros((n, D.L), dtype=np.complex128)
+    vox = np.zeros((n, D.L), dtype=dtype)
     sel = head
     vox[sel] = pd[sel, None] * D.atoms[idx[sel]]
     return Phantom(_to_frame_major(vox, S, size, size), idx, pd, params, S, size, size)
