@@ -4,17 +4,22 @@ T1 (80) x T2 (80) x B1 in [0.6, 1.4] (17) x df in [-40, 40] Hz (11) =
 network and a 7^4 = 2,401-atom local box.
 
 * standalone: 4,096 noisy atoms, the learned path (split-BF16 local search)
-  against the exhaustive BF16 filter with top-8 FP32 rescore, both graded on
-  sampled voxels against the FP64 oracle over all 1.2 M atoms;
+  against the certified exhaustive split-BF16 filter (the exact argmax over
+  all 1.2 M atoms), at most 0.1 % index mismatch, the certified answers
+  checked against the FP64 oracle on sampled voxels and on every voxel
+  where the two paths disagree (near-tie rule, gap 1e-6);
 * one projected-gradient step batched over 16 slices of 32 x 32 with uneven
   masks (2 + s/2 of 32 lines per frame in slice s): learned against the
-  exhaustive BF16 projection (same objective), both graded on sampled voxels
-  and on the voxels where they disagree against the oracle's projection of
-  the oracle's gradient step.
+  certified exhaustive projection (same objective; at most 0.1 % of the
+  tissue voxels where the learned atom's FP64 correlation falls more than
+  1e-6 below the certified one), the certified answers graded on sampled
+  voxels against the oracle's projection of the oracle's gradient step.
 
-The voxel counts are reduced from the 256 x 256 x 16 workload: at 9.6 MFLOP
-per voxel for the 4-D box and 4.8 GFLOP per voxel for the exhaustive BF16
-filter, a million voxels would take minutes (learned) to hours (exhaustive)."""
+The voxel counts are reduced from the 256 x 256 x 16 workload to keep the
+oracle's share (2.4 GFLOP per voxel in FP64 over all atoms) small; the
+device side at the full shape (1,048,576 voxels: 16.5 s for the uncertified
+split-BF16 filter, 0.13 s for the learned path) is timed by the bench's
+multi-parametric rows."""
 import numpy as np
 import pytest
 
@@ -66,18 +71,19 @@ def _corr(Z, atoms, idx):
 
 def test_bigdict_learned_vs_bf16(big):
     m, Dd, D, net = big
-    banner("1.2M atoms: learned (split BF16) vs exhaustive BF16 + FP32 rescore, 4,096 voxels")
+    banner("1.2M atoms: learned (split BF16) vs the certified exhaustive filter, 4,096 voxels")
     n = 4096
     Z, j, pd, snr = workloads.random_voxels(Dd, n, seed=5)
     Z = c64(Z)
     Zd = dev(Z)
-    ob = m.mrf_match(D, Zd, precision="bf16", topk=8, stats=True)
+    ob = m.mrf_match(D, Zd, precision="bf16x3", stats=True)  # certified: the exact argmax
     ol = m.mrf_match(D, Zd, net=net, precision="bf16x3", box_radius=3, fallback_corr=0.98, recentre=2,
                      stats=True)
     ib, il = host(ob["idx"]).astype(np.int64), host(ol["idx"]).astype(np.int64)
     st = ol["stats"]
     mism = float(np.mean(ib != il))
-    print(f"exhaustive BF16 {ob['stats'].ms:.1f} ms; learned {st.ms:.2f} ms ({st.first_box_atoms / n:.0f} box "
+    print(f"certified exhaustive {ob['stats'].ms:.1f} ms ({ob['stats'].cert_rescanned} rescanned, "
+          f"{ob['stats'].cert_scanned} scanned); learned {st.ms:.2f} ms ({st.first_box_atoms / n:.0f} box "
           f"atoms per voxel, {st.fallbacks} fallbacks, {st.recentred} re-centred); index mismatch {mism:.4f}")
     # grade on the FP64 oracle over all atoms: 48 random voxels and every
     # voxel where the two paths disagree
@@ -85,21 +91,16 @@ def test_bigdict_learned_vs_bf16(big):
     Zs = Z[sample].astype(np.complex128)
     best, arg = _exact(Zs, Dd.atoms)
     cl, cb = _corr(Zs, Dd.atoms, il[sample]), _corr(Zs, Dd.atoms, ib[sample])
-    ok_l, ok_b = cl >= best - 4.6e-5, cb >= best - 1e-6
+    ok_l, ok_b = cl >= best - 1e-6, cb >= best - 1e-6
     dis = np.isin(sample, np.flatnonzero(ib != il))
     print(f"FP64 oracle on {len(sample)} voxels ({int(dis.sum())} where the paths disagree): learned exact on "
-          f"{ok_l.mean():.3f} (disagreements {ok_l[dis].mean() if dis.any() else 1:.3f}), BF16 + rescore on "
-          f"{ok_b.mean():.3f} (disagreements {ok_b[dis].mean() if dis.any() else 1:.3f})")
-    assert mism <= 0.02
-    # The learned path is exact within its box; a voxel whose best atom lies
+          f"{ok_l.mean():.3f} (disagreements {ok_l[dis].mean() if dis.any() else 1:.3f}), certified on "
+          f"{ok_b.mean():.3f}")
+    assert np.all(ok_b)        # the certified filter is exact (near-tie rule)
+    # the learned path is exact within its box; a voxel whose best atom lies
     # outside the box while its correlation stays above the fallback
-    # threshold keeps the box's best (a box miss).  Every miss where the BF16
-    # filter is right is a disagreement and so is graded here: bound the
-    # misses over all 4,096 voxels (at most 1 in 2,048) rather than their
-    # share of the graded sample, which would forbid even one.
-    misses = int(np.sum(~ok_l))
-    print(f"learned misses among the 4,096 voxels: {misses}")
-    assert misses <= 2
+    # threshold keeps the box's best: at most 0.1 % of the voxels
+    assert mism <= 0.001
 
 
 def test_bigdict_batched_step_uneven_masks(big):
@@ -113,7 +114,7 @@ def test_bigdict_batched_step_uneven_masks(big):
     A = m.Operator.from_sampling(smp)
     Yd = dev(c64(Y))
     X0 = torch.zeros((S, L, size, size), dtype=torch.complex64, device="cuda")
-    Xe, ie, pde, ste = m.mrf_ipg_step(D, A, Yd, X0, 1.0, precision="bf16", topk=8)
+    Xe, ie, pde, ste = m.mrf_ipg_step(D, A, Yd, X0, 1.0, precision="bf16x3")  # certified
     Xl, il, pdl, stl = m.mrf_ipg_step(D, A, Yd, X0, 1.0, net=net, precision="bf16x3", recentre=2)
     ie, il = host(ie).astype(np.int64), host(il).astype(np.int64)
     head = ph.idx >= 0
@@ -129,11 +130,21 @@ def test_bigdict_batched_step_uneven_masks(big):
     vox = np.union1d(tissue[rng.permutation(6, "sample", tissue.size)[:32]],
                      dis[rng.permutation(6, "dis", dis.size)[:64]])
     best, arg = _exact(Zv[vox], Dd.atoms)
-    ok_l = _corr(Zv[vox], Dd.atoms, il[vox]) >= best - 4.6e-5
+    ok_l = _corr(Zv[vox], Dd.atoms, il[vox]) >= best - 1e-6
     ok_b = _corr(Zv[vox], Dd.atoms, ie[vox]) >= best - 1e-6
     isdis = np.isin(vox, dis)
     print(f"FP64 oracle on {vox.size} voxels ({int(isdis.sum())} disagreements): learned exact on {ok_l.mean():.3f} "
-          f"(disagreements {ok_l[isdis].mean() if isdis.any() else 1:.3f}), BF16 + rescore on {ok_b.mean():.3f} "
-          f"(disagreements {ok_b[isdis].mean() if isdis.any() else 1:.3f})")
-    assert abs(stl.f_out - ste.f_out) <= 0.02 * ste.f_out
-    assert ok_l.mean() >= 0.97
+          f"(disagreements {ok_l[isdis].mean() if isdis.any() else 1:.3f}), certified on {ok_b.mean():.3f}")
+    # the device's gradient step is FP32: its Z differs from the oracle's by
+    # ~1e-7 relative, so a certified index may differ from the oracle's where
+    # the oracle's own gap is below that; count only larger gaps
+    assert np.mean(ok_b) >= 0.99
+    assert abs(stl.f_out - ste.f_out) <= 0.001 * ste.f_out
+    # from X = 0 the correlation landscape is flat and many voxels hold
+    # near-ties: every tissue voxel where the two projections disagree is
+    # graded in FP64 (the learned atom against the certified one), and at
+    # most 0.1 % of the tissue may fall more than 1e-6 below it
+    c_l, c_e = _corr(Zv[dis], Dd.atoms, il[dis]), _corr(Zv[dis], Dd.atoms, ie[dis])
+    below = int(np.sum(c_l < c_e - 1e-6))
+    print(f"tissue voxels {tissue.size}: {dis.size} disagreements, {below} more than 1e-6 below the certified atom")
+    assert below <= 0.001 * tissue.size
