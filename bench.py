@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--cfg3", type=int, default=1,
                     help="precision forms inside Algorithm 2 on the 64 x 64 FISP spiral workload")
+    ap.add_argument("--cfg4", type=int, default=1,
+                    help="learned against exhaustive projections inside Algorithm 2 on 8 x 256 x 256 voxels")
     ap.add_argument("--cfg5", type=int, default=1,
                     help="16 x 256 x 256 voxels against the 1,196,800-atom L = 1000 dictionary")
     ap.add_argument("--cfg5-sample", type=int, default=256, help="random tissue voxels graded against FP64 (cfg5)")
@@ -364,6 +366,8 @@ def main():
         res["copy_calibration_bytes"] = {"read": 1 << 30, "write": 1 << 30}
     if args.cfg3:
         res["cfg3_precision_ipg"] = cfg3_bench(m, torch)
+    if args.cfg4 and args.learned:
+        res["cfg4_multislice_ipg"] = cfg4_bench(m, torch, D, Dd, net)
     if args.cpu_baseline:
         res["cpu_baseline"], res["vs_fp64_oracle_on_sample"] = cpu_baseline(Dd, Z, args.cpu_sample, answers)
     if D5 is not None:
@@ -563,6 +567,79 @@ def cfg3_bench(m, torch):
     return out
 
 
+def kspace_on_device(torch, X0, smp, snr_db, gen):
+    """Y = P_Omega F X0 + noise for a frame-major device image X0 [S][L][ny][nx]
+    (unitary 2-D DFT per frame, torch's FFT), the samples in the CSR order of
+    `smp`, circular complex Gaussian noise from the seeded generator `gen` at
+    the given SNR over all samples."""
+    off = torch.from_numpy(smp.off).cuda()
+    npix = smp.ny * smp.nx
+    pairs = torch.repeat_interleave(torch.arange(smp.S * smp.L, device="cuda", dtype=torch.int64), off[1:] - off[:-1])
+    flat = pairs * npix + torch.from_numpy(smp.idx.astype(np.int64)).cuda()
+    K = torch.fft.fft2(X0, norm="ortho").reshape(-1)
+    Y = K[flat]
+    del K, flat, pairs
+    s2 = torch.sum(torch.abs(Y) ** 2) / Y.numel() * 10.0 ** (-snr_db / 10.0) / 2.0
+    return Y + torch.sqrt(s2) * torch.complex(torch.randn(Y.shape, generator=gen, device="cuda"),
+                                              torch.randn(Y.shape, generator=gen, device="cuda"))
+
+
+def cfg4_bench(m, torch, D, Dd, net):
+    """Learned against exhaustive projections inside Algorithm 2 on 8 slices
+    of 256 x 256 (524,288 voxels) with the 100,800-atom L = 500 dictionary: a
+    smooth six-tissue phantom per slice with a df ramp, 26 of 256 random ky
+    lines per frame, k-space noise at 30 dB, 20 adaptive iterations (zeta = 2)
+    from mu0 = n / m.  Exhaustive: the uncertified split-BF16 filter; learned:
+    network proposal + split-BF16 local search (+-2 box, re-centring), warm
+    started, exhaustive fallback below 0.98 (and below 0.9)."""
+    from synth import workloads
+    S, size, L, iters = 8, 256, Dd.L, 20
+    t0 = time.time()
+    ph = workloads.smooth_phantom(Dd, seed=4, S=S, size=size, dtype=np.complex64)
+    smp = workloads.random_lines(4, S, L, size, size, 26)
+    X0 = torch.from_numpy(ph.X0).cuda()
+    del ph.X0
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4)
+    Yd = kspace_on_device(torch, X0, smp, 30.0, g)
+    A = m.Operator.from_sampling(smp)
+    n = S * size * size
+    mu0 = float(n * L) / smp.M
+    head = ph.idx >= 0
+    log(f"cfg4 inputs in {time.time() - t0:.1f}s")
+    out = {"workload": "8 x 256 x 256 voxels, L=500, 100,800 atoms, 26/256 lines per frame, SNR 30 dB, 20 adaptive "
+                       "iterations from mu0 = n/m", "voxels": n, "mu0": mu0}
+    ref = None
+    for name, kw in (("exhaustive_bf16x3", dict(precision="bf16x3", certify=False)),
+                     ("learned_bf16x3", dict(net=net, precision="bf16x3", box_radius=2, recentre=1,
+                                             certify=False)),
+                     ("learned_bf16x3_fallback0.9", dict(net=net, precision="bf16x3", box_radius=2, recentre=1,
+                                                         fallback_corr=0.9, certify=False))):
+        torch.cuda.synchronize()
+        t1 = time.time()
+        X, idx, pd, _, hist = m.mrf_ipg_solve(D, A, Yd, mu0=mu0, zeta=2.0, adaptive=True, max_iter=iters,
+                                              rel_tol=0.0, want_params=False, **kw)
+        torch.cuda.synchronize()
+        dt = time.time() - t1
+        nmse = float(torch.linalg.vector_norm(X - X0) / torch.linalg.vector_norm(X0))
+        ii = idx.cpu().numpy().astype(np.int64)
+        trials = hist["iters"] + hist["total_shrinks"]
+        row = {"seconds": dt, "ms_per_projection": dt * 1e3 / trials, "iterations": int(hist["iters"]),
+               "step_size_shrinks": int(hist["total_shrinks"]), "nmse": nmse, "f_final": float(hist["f"][-1]),
+               "tissue_on_generating_atom": float(np.mean(ii[head] == ph.idx[head]))}
+        if "net" in kw:
+            row["fallback_fraction"] = hist["fallbacks"] / (n * trials)
+            row["tissue_index_agreement_with_exhaustive"] = float(np.mean(ii[head] == ref[head]))
+            row["speedup_vs_exhaustive"] = out["exhaustive_bf16x3"]["seconds"] / dt
+        else:
+            ref = ii
+        out[name] = row
+        log(f"cfg4 {name}: {dt:.2f} s ({row['ms_per_projection']:.1f} ms per projection), NMSE {nmse:.4e}, "
+            f"f {row['f_final']:.6e}" + (f", fallbacks {row['fallback_fraction']:.3f}" if "net" in kw else ""))
+        del X
+    return out
+
+
 def cfg5_atoms(workers):
     """The multi-parametric dictionary: IR-bSSFP, L = 1000, T1 80 x T2 80 x
     B1 17 in [0.6, 1.4] x df 11 in [-40, 40] Hz = 1,196,800 atoms (complex64
@@ -702,15 +779,7 @@ def cfg5_bench(m, torch, Dd, args):
     # one batched step over the 16 slices with uneven masks
     t0 = time.time()
     smp = workloads.random_lines(9, S, L, size, size, [16 + 2 * s for s in range(S)])
-    off = torch.from_numpy(smp.off).cuda()
-    pairs = torch.repeat_interleave(torch.arange(S * L, device="cuda", dtype=torch.int64), off[1:] - off[:-1])
-    flat = pairs * (size * size) + torch.from_numpy(smp.idx.astype(np.int64)).cuda()
-    K = torch.fft.fft2(X0, norm="ortho").reshape(-1)
-    Yd = K[flat]
-    del K, flat, pairs
-    s2 = torch.sum(torch.abs(Yd) ** 2) / Yd.numel() * 1e-3 / 2.0
-    Yd = Yd + torch.sqrt(s2) * torch.complex(torch.randn(Yd.shape, generator=g, device="cuda"),
-                                             torch.randn(Yd.shape, generator=g, device="cuda"))
+    Yd = kspace_on_device(torch, X0, smp, 30.0, g)
     A = m.Operator.from_sampling(smp)
     log(f"cfg5: sampling ({smp.M} samples) and k-space in {time.time() - t0:.1f}s")
     Xz = torch.zeros_like(X0)
