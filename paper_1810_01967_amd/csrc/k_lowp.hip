@@ -11,6 +11,9 @@ namespace mrf {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+// staging registers are native vectors: a struct type (uint4) is copied
+// through private memory, which serialises every load on its own wait
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // encoders
@@ -173,21 +176,21 @@ __global__ __launch_bounds__(256, 2) void k_score_lowp(const uint8_t *__restrict
 
   // global -> LDS: 128 rows x 128 bytes per operand = 1024 x 16 B, 4 per thread
   const int lr = tid >> 3, lc = (tid & 7) * 16;
-  uint4 ra[4], rz[4];
+  u32x4 ra[4], rz[4];
   auto gload = [&](int q) {
     const int tile = tb + q / nkc, kc = q - (q / nkc) * nkc;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      ra[i] = *reinterpret_cast<const uint4 *>(Dq + (int64_t)(tile * Q_BA + lr + 32 * i) * row_bytes +
+      ra[i] = *reinterpret_cast<const u32x4 *>(Dq + (int64_t)(tile * Q_BA + lr + 32 * i) * row_bytes +
                                                kc * Q_CB + lc);
-      rz[i] = *reinterpret_cast<const uint4 *>(Zq + (v0 + lr + 32 * i) * row_bytes + kc * Q_CB + lc);
+      rz[i] = *reinterpret_cast<const u32x4 *>(Zq + (v0 + lr + 32 * i) * row_bytes + kc * Q_CB + lc);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      *reinterpret_cast<uint4 *>(&As[buf][(lr + 32 * i) * Q_LDB + lc]) = ra[i];
-      *reinterpret_cast<uint4 *>(&Zs[buf][(lr + 32 * i) * Q_LDB + lc]) = rz[i];
+      *reinterpret_cast<u32x4 *>(&As[buf][(lr + 32 * i) * Q_LDB + lc]) = ra[i];
+      *reinterpret_cast<u32x4 *>(&Zs[buf][(lr + 32 * i) * Q_LDB + lc]) = rz[i];
     }
   };
 
@@ -230,16 +233,16 @@ __global__ __launch_bounds__(256, 2) void k_score_lowp(const uint8_t *__restrict
 #pragma unroll
         for (int ma = 0; ma < 2; ++ma) {
           const uint8_t *src = &As[buf][(wa * 64 + ma * 32 + l32) * Q_LDB + ks * 64 + h * 32];
-          const uint4 x0 = *reinterpret_cast<const uint4 *>(src);
-          const uint4 x1 = *reinterpret_cast<const uint4 *>(src + 16);
+          const u32x4 x0 = *reinterpret_cast<const u32x4 *>(src);
+          const u32x4 x1 = *reinterpret_cast<const u32x4 *>(src + 16);
           af[ma] = i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w,
                          (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
         }
 #pragma unroll
         for (int nv = 0; nv < 2; ++nv) {
           const uint8_t *src = &Zs[buf][(wv * 64 + nv * 32 + l32) * Q_LDB + ks * 64 + h * 32];
-          const uint4 x0 = *reinterpret_cast<const uint4 *>(src);
-          const uint4 x1 = *reinterpret_cast<const uint4 *>(src + 16);
+          const u32x4 x0 = *reinterpret_cast<const u32x4 *>(src);
+          const u32x4 x1 = *reinterpret_cast<const u32x4 *>(src + 16);
           zf[nv] = i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w,
                          (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
         }

@@ -20,6 +20,9 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// staging registers are native vectors: a struct type (uint4) is copied
+// through private memory, which serialises every load on its own wait
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // wave grid (atom-row groups x voxel-column groups; tuning constants)
 // (4 x 4 = 16 waves of 64 x 64 measured best: 31.8 ms per 65,536 x 100,800 x
@@ -92,21 +95,21 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
       int64_t r = v0 + lr + M_LROWS * i;
       zrow[i] = g.Z + r * g.row + lc;
     }
-    uint4 ra[M_LA], rz[M_LZ];
+    u32x4 ra[M_LA], rz[M_LZ];
     auto gload = [&](int q) {
       const int tile = tb + q / g.nstage, st = q - (q / g.nstage) * g.nstage;
       const uint16_t *a = g.D + (int64_t)(tile * M_BA + lr) * g.row + st * 64 + lc;
 #pragma unroll
-      for (int i = 0; i < M_LA; ++i) ra[i] = *reinterpret_cast<const uint4 *>(a + (int64_t)(M_LROWS * i) * g.row);
+      for (int i = 0; i < M_LA; ++i) ra[i] = *reinterpret_cast<const u32x4 *>(a + (int64_t)(M_LROWS * i) * g.row);
 #pragma unroll
-      for (int i = 0; i < M_LZ; ++i) rz[i] = *reinterpret_cast<const uint4 *>(zrow[i] + st * 64);
+      for (int i = 0; i < M_LZ; ++i) rz[i] = *reinterpret_cast<const u32x4 *>(zrow[i] + st * 64);
     };
     auto sstore = [&](int buf) {
       uint16_t *B = S + buf * M_STAGE;
 #pragma unroll
-      for (int i = 0; i < M_LA; ++i) *reinterpret_cast<uint4 *>(B + (lr + M_LROWS * i) * M_LD + lc) = ra[i];
+      for (int i = 0; i < M_LA; ++i) *reinterpret_cast<u32x4 *>(B + (lr + M_LROWS * i) * M_LD + lc) = ra[i];
 #pragma unroll
-      for (int i = 0; i < M_LZ; ++i) *reinterpret_cast<uint4 *>(B + (M_BA + lr + M_LROWS * i) * M_LD + lc) = rz[i];
+      for (int i = 0; i < M_LZ; ++i) *reinterpret_cast<u32x4 *>(B + (M_BA + lr + M_LROWS * i) * M_LD + lc) = rz[i];
     };
 
     f32x16 acc[M_MA][M_NV];
