@@ -1,16 +1,26 @@
-// Exhaustive matched-filter scoring of BF16 rows on the matrix cores of gfx950
-// (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with the per-voxel epilogues
-// of the reduced-precision filter fused (eq. exactP): the maximum, or every
-// atom at or above a per-voxel line.
+// Exhaustive matched-filter scoring of reduced-precision rows on the matrix
+// cores of gfx950, FP32 accumulation, with the per-voxel epilogues of the
+// reduced-precision filter fused (eq. exactP): the maximum, or every atom at
+// or above a per-voxel line.
+//   BF16: v_mfma_f32_32x32x16_bf16 (8 values of a row per lane and k-step);
+//   FP8 E4M3: v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales
+//   (32 values per lane and k-step); an atom's score is the E4M3 product
+//   times the atom's row scale (the voxel's scale, common to all its scores,
+//   is left out: lines are given in the same unit).
 //
 // Block tile: 256 atoms x 256 voxels, MRF_MX_WA x MRF_MX_WV waves, each
 // owning a (256 / WA) x (256 / WV) sub-tile of MFMA 32x32 tiles (atoms are the
 // A rows, voxels the B columns, so a lane folds one voxel column per tile and
-// atoms reach it in increasing order).  Every stage is 128 bytes (64 BF16) of
-// each of the 512 rows, double-buffered in LDS with a 144-byte pitch.  Work items are
-// (voxel tile, atom split) pairs; the splits of a voxel tile run on one XCD
-// (item w on XCD w % 8), so its blocks share the voxel tile and, across the
-// voxel tiles in flight, the atom tiles through that XCD's L2.
+// atoms reach it in increasing order).  A stage is 128 bytes of each of the
+// 512 rows (64 BF16 or 128 FP8 values), double-buffered in LDS.  Stages go
+// straight from global memory to LDS (global_load_lds_dwordx4: a wave's 64
+// lanes write 16 bytes each at the wave's LDS base + 16 x lane, i.e. eight
+// 128-byte rows), with the eight 16-byte chunks of row r stored at slot
+// chunk ^ (r % 8), so 32 lanes reading one chunk of 32 consecutive rows hit
+// distinct banks.  Work items are (voxel tile, atom split) pairs; the splits
+// of a voxel tile run on one XCD (item w on XCD w % 8), so its blocks share
+// the voxel tile and, across the voxel tiles in flight, the atom tiles through
+// that XCD's L2.
 #include "k_topk.h"
 #include "mrf_internal.h"
 
@@ -20,37 +30,47 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-// staging registers are native vectors: a struct type (uint4) is copied
-// through private memory, which serialises every load on its own wait
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
 
 // wave grid (atom-row groups x voxel-column groups; tuning constants)
-// (4 x 4 = 16 waves of 64 x 64 measured best: 31.8 ms per 65,536 x 100,800 x
-// 1,000 against 33.1-33.7 ms for 2 x 4, 4 x 2 and 8 x 2)
+// (8 waves of 128 atoms x 64 voxels: BF16 12.5 ms per 65,536 x 100,800 x
+// 1,000, against 12.4 for 64 x 128 and 12.9 for 16 waves of 64 x 64; the FP8
+// form needs 128 x 64 to keep its operands in registers)
 #ifndef MRF_MX_WA
-#define MRF_MX_WA 4
+#define MRF_MX_WA 2
 #endif
 #ifndef MRF_MX_WV
 #define MRF_MX_WV 4
 #endif
+#ifndef MRF_MX_SCHED
+#define MRF_MX_SCHED 1
+#endif
 constexpr int M_BA = 256, M_BV = 256;
 constexpr int M_WA = MRF_MX_WA, M_WV = MRF_MX_WV, M_NT = 64 * M_WA * M_WV;
-constexpr int M_LD = 72;                       // LDS row pitch in BF16 (128 bytes + 16 of padding)
-constexpr int M_STAGE = (M_BA + M_BV) * M_LD;  // BF16 per stage buffer
+constexpr int M_ROWB = 128;                            // bytes of a row per stage
+constexpr int M_STAGE = (M_BA + M_BV) * M_ROWB;        // bytes per stage buffer
 constexpr int M_AROWS = M_BA / M_WA, M_VCOLS = M_BV / M_WV;  // per wave
-constexpr int M_MA = M_AROWS / 32;             // 32-atom MFMA tiles per wave
-constexpr int M_NV = M_VCOLS / 32;             // 32-voxel MFMA tiles per wave
-constexpr int M_LROWS = M_NT / 8;              // rows per loader pass (8 pieces of 16 B per row)
-constexpr int M_LA = M_BA / M_LROWS, M_LZ = M_BV / M_LROWS;
-static_assert(M_MA >= 1 && M_NV >= 1 && M_LA >= 1 && M_LZ >= 1, "block shape");
-static_assert(2 * M_STAGE * 2 <= 160 * 1024, "LDS");
+constexpr int M_MA = M_AROWS / 32;                     // 32-atom MFMA tiles per wave
+constexpr int M_NV = M_VCOLS / 32;                     // 32-voxel MFMA tiles per wave
+constexpr int M_NW = M_NT / 64;                        // waves
+constexpr int M_DI = (M_BA + M_BV) / 8 / M_NW;         // 8-row loads per wave and stage
+constexpr int M_DIA = M_BA / 8 / M_NW;                 // of which atom rows
+static_assert(M_MA >= 1 && M_NV >= 1, "block shape");
+static_assert(M_DI * M_NW * 8 == M_BA + M_BV && (M_BA / 8) % M_NW == 0, "loader shape");
+static_assert(2 * M_STAGE <= 160 * 1024, "LDS");
+
+// byte offset of the 16-byte chunk c in a stage row r (r % 8 == rm)
+__device__ __forceinline__ int chunk_at(int c, int rm) { return (c ^ rm) * 16; }
 
 }  // namespace
 
 struct MxArgs {
-  const uint16_t *D;       // atom rows, pitch `row` BF16 (d_pad rows, zero padded)
-  const uint16_t *Z;       // voxel rows, same pitch (rows up to the voxel-tile multiple readable)
-  int64_t row;             // row pitch in BF16
+  const uint8_t *D;        // atom rows, pitch `row` bytes (d_pad rows, zero padded)
+  const uint8_t *Z;        // voxel rows, same pitch (rows up to the voxel-tile multiple readable)
+  const float *dscale;     // FP8: the atoms' row scales
+  int64_t row;             // row pitch in bytes
   int nstage;              // 128-byte stages per row
   int d, ntiles;           // atoms; 256-atom tiles
   int64_t n;               // voxels (device count: the capacity)
@@ -64,19 +84,23 @@ struct MxArgs {
   int ccap;
 };
 
-template <int MODE>
+template <bool F8, int MODE>
 __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
   const int64_t nvox = g.n;
   const int nsplit = g.splits, tps = g.tps;
   const int nvt = (int)((nvox + M_BV - 1) / M_BV);
   const int64_t nwork = (int64_t)((nvt + 7) / 8 * 8) * nsplit;
 
-  __shared__ __attribute__((aligned(16))) uint16_t S[2 * M_STAGE];
+  __shared__ __attribute__((aligned(16))) uint8_t S[2 * M_STAGE];
+  __shared__ __attribute__((aligned(16))) float SCL[F8 ? 2 : 1][M_BA];  // FP8: atom scales by tile parity
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wa = wave / M_WV, wv = wave % M_WV;
-  const int h = lane >> 5, l32 = lane & 31;
-  const int lr = tid >> 3, lc = (tid & 7) * 8;  // loader row, BF16 column of the 16-byte piece
+  const int h = lane >> 5, l32 = lane & 31, rm = l32 & 7;  // every row this lane reads is rm modulo 8
+  // loader: load i of wave w covers stage rows R = (i M_NW + w) 8 + lane / 8
+  // (atom rows below M_BA, then voxel rows: M_NW divides M_BA / 8); the lane
+  // fetches the chunk that belongs in its slot lane % 8
+  const int drow = lane >> 3, dchunk = chunk_at(lane & 7, drow);
 
   for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int xcd = (int)(w & 7);
@@ -89,27 +113,37 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
     const int64_t v0 = (int64_t)vt * M_BV;
     const int nq = te > tb ? (te - tb) * g.nstage : 0;
 
-    const uint16_t *zrow[M_LZ];
+    // loads i < M_DIA fetch atom rows, the rest voxel rows; row R of load i is
+    // i M_NW 8 rows after the wave's first, a uniform step
+    const uint8_t *a0 = g.D + (int64_t)(tb * M_BA + wave * 8 + drow) * g.row + dchunk;
+    const uint8_t *z0 = g.Z + (v0 + wave * 8 + drow) * g.row + dchunk;
+    const int64_t istep = (int64_t)M_NW * 8 * g.row;
+    // FP8: a tile's 256 atom scales go to LDS through registers of wave 0
+    // (loaded after the stage's DMA loads and stored at the end of the stage,
+    // where those are waited for anyway), in the slot of the tile's parity
+    u32x4 sreg = {0u, 0u, 0u, 0u};
+    int stile = -1;
+    auto dload = [&](int q, int buf) {
+      const int tq = q / g.nstage;
+      const int64_t aoff = (int64_t)tq * M_BA * g.row + (q - tq * g.nstage) * M_ROWB;
+      const int64_t zoff = (q - tq * g.nstage) * M_ROWB;
 #pragma unroll
-    for (int i = 0; i < M_LZ; ++i) {
-      int64_t r = v0 + lr + M_LROWS * i;
-      zrow[i] = g.Z + r * g.row + lc;
-    }
-    u32x4 ra[M_LA], rz[M_LZ];
-    auto gload = [&](int q) {
-      const int tile = tb + q / g.nstage, st = q - (q / g.nstage) * g.nstage;
-      const uint16_t *a = g.D + (int64_t)(tile * M_BA + lr) * g.row + st * 64 + lc;
-#pragma unroll
-      for (int i = 0; i < M_LA; ++i) ra[i] = *reinterpret_cast<const u32x4 *>(a + (int64_t)(M_LROWS * i) * g.row);
-#pragma unroll
-      for (int i = 0; i < M_LZ; ++i) rz[i] = *reinterpret_cast<const u32x4 *>(zrow[i] + st * 64);
+      for (int i = 0; i < M_DI; ++i) {
+        const uint8_t *src = i < M_DIA ? a0 + i * istep + aoff : z0 + (i - M_DIA) * istep + zoff;
+        __builtin_amdgcn_global_load_lds((const void *)src,
+                                         (lds_void *)(S + buf * M_STAGE + (i * M_NW + wave) * 8 * M_ROWB), 16, 0, 0);
+      }
+      if (F8 && wave == 0 && q == tq * g.nstage) {
+        stile = tb + tq;
+        sreg = *reinterpret_cast<const u32x4 *>(g.dscale + stile * M_BA + lane * 4);
+      }
     };
-    auto sstore = [&](int buf) {
-      uint16_t *B = S + buf * M_STAGE;
-#pragma unroll
-      for (int i = 0; i < M_LA; ++i) *reinterpret_cast<u32x4 *>(B + (lr + M_LROWS * i) * M_LD + lc) = ra[i];
-#pragma unroll
-      for (int i = 0; i < M_LZ; ++i) *reinterpret_cast<u32x4 *>(B + (M_BA + lr + M_LROWS * i) * M_LD + lc) = rz[i];
+    // the slot's previous tile was folded before an earlier barrier
+    auto sflush = [&]() {
+      if (F8 && stile >= 0) {
+        *reinterpret_cast<u32x4 *>(&SCL[stile & 1][lane * 4]) = sreg;
+        stile = -1;
+      }
     };
 
     f32x16 acc[M_MA][M_NV];
@@ -131,33 +165,79 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
     }
 
     if (nq > 0) {
-      gload(0);
-      sstore(0);
+      dload(0, 0);
+      sflush();
+      __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
     for (int q = 0; q < nq; ++q) {
       const int buf = q & 1;
-      if (q + 1 < nq) gload(q + 1);
-      const __bf16 *B = reinterpret_cast<const __bf16 *>(S) + buf * M_STAGE;
-      const __bf16 *Ab = B + (wa * M_AROWS + l32) * M_LD + h * 8;
-      const __bf16 *Zb = B + (M_BA + wv * M_VCOLS + l32) * M_LD + h * 8;
+      if (q + 1 < nq) dload(q + 1, buf ^ 1);  // every wave finished reading that buffer before the last barrier
+      const uint8_t *B = S + buf * M_STAGE;
+      const uint8_t *Ab = B + (wa * M_AROWS + l32) * M_ROWB;
+      const uint8_t *Zb = B + (M_BA + wv * M_VCOLS + l32) * M_ROWB;
+      if constexpr (F8) {
+        // two k-steps of 64: the lane supplies 32 bytes (chunks 4 ks + 2 h, + 1)
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        bf16x8 zf[M_NV];
+        for (int ks = 0; ks < 2; ++ks) {
+          const int o0 = chunk_at(4 * ks + 2 * h, rm), o1 = chunk_at(4 * ks + 2 * h + 1, rm);
+          i32x8 zf[M_NV];
 #pragma unroll
-        for (int nv = 0; nv < M_NV; ++nv) zf[nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_LD + ks * 16);
+          for (int nv = 0; nv < M_NV; ++nv) {
+            const u32x4 x0 = *reinterpret_cast<const u32x4 *>(Zb + nv * 32 * M_ROWB + o0);
+            const u32x4 x1 = *reinterpret_cast<const u32x4 *>(Zb + nv * 32 * M_ROWB + o1);
+            zf[nv] = i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+          }
 #pragma unroll
-        for (int ma = 0; ma < M_MA; ++ma) {
-          const bf16x8 af = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_LD + ks * 16);
+          for (int ma = 0; ma < M_MA; ++ma) {
+            const u32x4 x0 = *reinterpret_cast<const u32x4 *>(Ab + ma * 32 * M_ROWB + o0);
+            const u32x4 x1 = *reinterpret_cast<const u32x4 *>(Ab + ma * 32 * M_ROWB + o1);
+            const i32x8 af{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
 #pragma unroll
-          for (int nv = 0; nv < M_NV; ++nv)
-            acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, zf[nv], acc[ma][nv], 0, 0, 0);
+            for (int nv = 0; nv < M_NV; ++nv)
+              acc[ma][nv] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af, zf[nv], acc[ma][nv], 0, 0, 0, 0x7F,
+                                                                            0, 0x7F);
+          }
         }
+      } else {
+        // four k-steps of 16: the lane supplies 8 BF16 (chunk 2 ks + h); the
+        // fragments of step ks + 1 are read while step ks multiplies
+        bf16x8 af[2][M_MA], zf[2][M_NV];
+        auto frag = [&](int ks, int set) {
+          const int ko = chunk_at(2 * ks + h, rm);
+#pragma unroll
+          for (int nv = 0; nv < M_NV; ++nv) zf[set][nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + ko);
+#pragma unroll
+          for (int ma = 0; ma < M_MA; ++ma) af[set][ma] = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + ko);
+        };
+        frag(0, 0);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          if (ks + 1 < 4) frag(ks + 1, (ks + 1) & 1);
+#pragma unroll
+          for (int ma = 0; ma < M_MA; ++ma)
+#pragma unroll
+            for (int nv = 0; nv < M_NV; ++nv)
+              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ks & 1][ma], zf[ks & 1][nv], acc[ma][nv], 0, 0, 0);
+        }
+#if MRF_MX_SCHED
+        // issue order: the reads of step 0, then (reads of step ks + 1,
+        // products of step ks) for ks < 3, then the products of step 3
+        __builtin_amdgcn_sched_group_barrier(0x100, M_MA + M_NV, 0);
+#pragma unroll
+        for (int ks = 0; ks < 3; ++ks) {
+          __builtin_amdgcn_sched_group_barrier(0x100, M_MA + M_NV, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, M_MA * M_NV, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, M_MA * M_NV, 0);
+#endif
       }
       const int st = q % g.nstage;
       if (st == g.nstage - 1) {
-        // fold this atom tile: 64 atom rows per voxel column and lane
-        const int abase = (tb + q / g.nstage) * M_BA + wa * M_AROWS;
+        // fold this atom tile: M_AROWS atom rows per voxel column and lane
+        const int tile = tb + q / g.nstage;
+        const int abase = tile * M_BA + wa * M_AROWS;
+        const float *scl = &SCL[F8 ? (tile & 1) : 0][wa * M_AROWS];
 #pragma unroll
         for (int nv = 0; nv < M_NV; ++nv) {
           const int64_t v = v0 + wv * M_VCOLS + nv * 32 + l32;
@@ -166,7 +246,7 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
               const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-              const float sc = acc[ma][nv][i];
+              const float sc = F8 ? acc[ma][nv][i] * scl[ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3)] : acc[ma][nv][i];
               if (MODE == SC_TOP1) {
                 if (j < g.d && sc > best[nv]) {  // atoms in increasing order: '>' keeps the lowest index
                   best[nv] = sc;
@@ -185,7 +265,8 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
       }
-      if (q + 1 < nq) sstore(buf ^ 1);
+      sflush();
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next stage are in LDS
       __syncthreads();
     }
     if (MODE == SC_COLLECT) continue;  // the candidates are already written
@@ -231,16 +312,31 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
 
 namespace {
 
-MxArgs mx_args(const uint16_t *D, const uint16_t *Z, int Kq, int d, int64_t d_pad, int64_t n) {
+MxArgs mx_args(bool fp8, const void *D, const float *dscale, const void *Z, int Kq, int d, int64_t d_pad,
+               int64_t n, int splits) {
   MxArgs a{};
-  a.D = D;
-  a.Z = Z;
-  a.row = Kq;
-  a.nstage = Kq / 64;
+  a.D = static_cast<const uint8_t *>(D);
+  a.Z = static_cast<const uint8_t *>(Z);
+  a.dscale = dscale;
+  a.row = (int64_t)Kq * (fp8 ? 1 : 2);
+  a.nstage = (int)(a.row / M_ROWB);
   a.d = d;
   a.ntiles = (int)(d_pad / M_BA);
   a.n = n;
+  a.splits = splits;
+  a.tps = (a.ntiles + splits - 1) / splits;
   return a;
+}
+
+template <int MODE>
+void launch_mx(bool fp8, const MxArgs &a, hipStream_t s) {
+  const int64_t nvt = (a.n + M_BV - 1) / M_BV;
+  const int64_t blocks = (nvt + 7) / 8 * 8 * a.splits;
+  if (blocks <= 0) return;
+  if (fp8)
+    hipLaunchKernelGGL((k_score_mx<true, MODE>), dim3((unsigned)blocks), dim3(M_NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_score_mx<false, MODE>), dim3((unsigned)blocks), dim3(M_NT), 0, s, a);
 }
 
 }  // namespace
@@ -249,38 +345,31 @@ int mx_auto_splits(int64_t d_pad, int64_t n) {
   const int64_t nvt = (n + M_BV - 1) / M_BV;
   const int64_t nvt8 = (nvt + 7) / 8 * 8;
   const int64_t ntiles = d_pad / M_BA;
-  // 16 splits per voxel tile (measured: 31.8 ms against 33.0 with 8 and 35.1
-  // with 4 at 65,536 x 100,800), more to fill the chip for few voxels
-  int64_t s = std::max<int64_t>(16, (512 + nvt8 - 1) / nvt8);
+  // 8 splits per voxel tile (measured: 12.4 ms against 12.6 with 16 at
+  // 65,536 x 100,800, BF16), more to fill the chip for few voxels
+  int64_t s = std::max<int64_t>(8, (512 + nvt8 - 1) / nvt8);
   s = std::min<int64_t>(s, std::min<int64_t>(ntiles, 256));
   return (int)std::max<int64_t>(s, 1);
 }
 
-void launch_score_mx(const uint16_t *D, const uint16_t *Z, int Kq, int d, int64_t d_pad, int64_t n, int splits,
-                     float *part_s, int *part_j, hipStream_t s) {
-  MxArgs a = mx_args(D, Z, Kq, d, d_pad, n);
-  a.splits = splits;
-  a.tps = (a.ntiles + splits - 1) / splits;
+void launch_score_mx(bool fp8, const void *D, const float *dscale, const void *Z, int Kq, int d, int64_t d_pad,
+                     int64_t n, int splits, float *part_s, int *part_j, hipStream_t s) {
+  MxArgs a = mx_args(fp8, D, dscale, Z, Kq, d, d_pad, n, splits);
   a.part_s = part_s;
   a.part_j = part_j;
   a.pstride = n;
-  const int64_t nvt = (n + M_BV - 1) / M_BV;
-  const int64_t blocks = (nvt + 7) / 8 * 8 * splits;
-  if (blocks > 0) hipLaunchKernelGGL(k_score_mx<SC_TOP1>, dim3((unsigned)blocks), dim3(M_NT), 0, s, a);
+  launch_mx<SC_TOP1>(fp8, a, s);
 }
 
-void launch_collect_mx(const uint16_t *D, const uint16_t *Z, int Kq, int d, int64_t d_pad, int64_t n, int splits,
-                       const float *thr, unsigned int *count, int32_t *cand, int ccap, hipStream_t s) {
-  MxArgs a = mx_args(D, Z, Kq, d, d_pad, n);
-  a.splits = splits;
-  a.tps = (a.ntiles + splits - 1) / splits;
+void launch_collect_mx(bool fp8, const void *D, const float *dscale, const void *Z, int Kq, int d, int64_t d_pad,
+                       int64_t n, int splits, const float *thr, unsigned int *count, int32_t *cand, int ccap,
+                       hipStream_t s) {
+  MxArgs a = mx_args(fp8, D, dscale, Z, Kq, d, d_pad, n, splits);
   a.thr = thr;
   a.count = count;
   a.cand = cand;
   a.ccap = ccap;
-  const int64_t nvt = (n + M_BV - 1) / M_BV;
-  const int64_t blocks = (nvt + 7) / 8 * 8 * splits;
-  if (blocks > 0) hipLaunchKernelGGL(k_score_mx<SC_COLLECT>, dim3((unsigned)blocks), dim3(M_NT), 0, s, a);
+  launch_mx<SC_COLLECT>(fp8, a, s);
 }
 
 }  // namespace mrf

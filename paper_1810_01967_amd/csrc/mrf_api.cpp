@@ -466,21 +466,17 @@ mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, c
   launch_quantize_rows(D->zp.as<float>(), n_pad, D->K, D->Kp, precision, D->zq.p, D->Kq,
                        fp8 ? D->zscale.as<float>() : nullptr, s, certify ? D->lp_qn.as<double2>() : nullptr);
   LAUNCH_CHECK("quantize_rows");
-  // BF16 on the 256 x 256 matrix-core tiles, FP8 on the 128 x 128 ones
-  if (!fp8 && !(o && o->atom_splits > 0)) splits = mx_auto_splits(D->d_pad, n);
-  if (!fp8) splits = (int)std::min<int64_t>(splits, D->d_pad / 256);
+  // 256 x 256 matrix-core tiles
+  if (!(o && o->atom_splits > 0)) splits = mx_auto_splits(D->d_pad, n);
+  splits = (int)std::min<int64_t>(splits, D->d_pad / 256);
   if (splits_used) *splits_used = splits;
   TRY(grow(D->part_s, (size_t)splits * n * 4));
   TRY(grow(D->part_j, (size_t)splits * n * 4));
   const void *Dq = fp8 ? D->dfp8.p : D->dbf16.p;
   const float *dsc = fp8 ? D->fp8_scale.as<float>() : nullptr;
   if (ev_s0) HIP_TRY(hipEventRecord(ev_s0, s));
-  if (fp8)
-    launch_score_lowp(precision, Dq, dsc, D->zq.p, D->d, D->d_pad, n, D->Kq, splits, D->part_s.as<float>(),
-                      D->part_j.as<int>(), s);
-  else
-    launch_score_mx(static_cast<const uint16_t *>(Dq), static_cast<const uint16_t *>(D->zq.p), D->Kq, D->d, D->d_pad,
-                    n, splits, D->part_s.as<float>(), D->part_j.as<int>(), s);
+  launch_score_mx(fp8, Dq, dsc, D->zq.p, D->Kq, D->d, D->d_pad, n, splits, D->part_s.as<float>(),
+                  D->part_j.as<int>(), s);
   LAUNCH_CHECK("score_lowp");
   if (ev_s1) HIP_TRY(hipEventRecord(ev_s1, s));
   CertOut out{D->znorm.as<float>(), warm, D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr,
@@ -498,13 +494,8 @@ mrf_status match_exhaustive(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, c
                    D->lp_count.as<unsigned int>(), D->lp_b.as<double>(), certify ? 1 : 0, s);
   LAUNCH_CHECK("lowp line");
   if (!certify) return MRF_OK;
-  if (fp8)
-    launch_collect_lowp(precision, Dq, dsc, D->zq.p, D->d, D->d_pad, n, D->Kq, splits, D->lp_thr.as<float>(),
-                        D->lp_count.as<unsigned int>(), D->lp_cand.as<int32_t>(), kLowpCap, s);
-  else
-    launch_collect_mx(static_cast<const uint16_t *>(Dq), static_cast<const uint16_t *>(D->zq.p), D->Kq, D->d,
-                      D->d_pad, n, splits, D->lp_thr.as<float>(), D->lp_count.as<unsigned int>(),
-                      D->lp_cand.as<int32_t>(), kLowpCap, s);
+  launch_collect_mx(fp8, Dq, dsc, D->zq.p, D->Kq, D->d, D->d_pad, n, splits, D->lp_thr.as<float>(),
+                    D->lp_count.as<unsigned int>(), D->lp_cand.as<int32_t>(), kLowpCap, s);
   LAUNCH_CHECK("collect_lowp");
   TRY(grow(D->cert, 64));
   TRY(grow(D->cert_list, (size_t)n * 4));

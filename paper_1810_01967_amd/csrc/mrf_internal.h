@@ -91,17 +91,6 @@ void launch_collect_f32_dev(const float *D, const float *Zp, const int32_t *rows
                             int64_t cap, const unsigned int *dcnt, int Kp, const float *thr, unsigned int *count,
                             int32_t *cand, int ccap, hipStream_t s);
 
-// Reduced-precision scoring (BF16 / FP8-E4M3 rows Dq, Zq of pitch Kq; dscale
-// the FP8 atoms' scales): per split and voxel the best (score, atom)
-// [splits][n]; FP8 scores leave out the voxel's scale.
-void launch_score_lowp(int precision, const void *Dq, const float *dscale, const void *Zq, int d, int64_t d_pad,
-                       int64_t n, int Kq, int splits, float *part_s, int *part_j, hipStream_t s);
-// The same pass collecting every atom with score >= thr[v] into
-// cand[v][0..ccap) (count[v] counts them all; zeroed by the caller).
-void launch_collect_lowp(int precision, const void *Dq, const float *dscale, const void *Zq, int d, int64_t d_pad,
-                         int64_t n, int Kq, int splits, const float *thr, unsigned int *count, int32_t *cand, int ccap,
-                         hipStream_t s);
-
 // Merge the per-split partial argmax, then rescale (eq. exactPs) and look up.
 // gamma_hat[v] = max(score,0) is the multiplier of the normalised atom.
 void launch_merge_argmax(const float *part_s, const int *part_j, int splits, int64_t n, int d,
@@ -334,15 +323,17 @@ void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys
 void launch_score_x3(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t n, int64_t n_pad,
                      int Kx, int splits, float *part_s, int *part_j, hipStream_t s, bool topk = false,
                      const float *znorm = nullptr, float cw = 0.f, float wabs = 0.f);
-// BF16 matrix-core scoring (k_score_mx.hip): atoms D [d_pad][Kq], voxels Z
-// [round_up(n, 256)][Kq]; per split and voxel the best (score, atom) [splits][n]
-// (lowest atom on equal scores), or every atom with score >= thr[v] collected
-// into cand[v][0..ccap) (count[v] counts them all; zeroed by the caller).
+// BF16 / FP8 matrix-core scoring (k_score_mx.hip): atoms D [d_pad][Kq], voxels
+// Z [round_up(n, 256)][Kq] (BF16 or E4M3 values; FP8 atom scores are scaled by
+// dscale[j]); per split and voxel the best (score, atom) [splits][n] (lowest
+// atom on equal scores), or every atom with score >= thr[v] collected into
+// cand[v][0..ccap) (count[v] counts them all; zeroed by the caller).
 int mx_auto_splits(int64_t d_pad, int64_t n);
-void launch_score_mx(const uint16_t *D, const uint16_t *Z, int Kq, int d, int64_t d_pad, int64_t n, int splits,
-                     float *part_s, int *part_j, hipStream_t s);
-void launch_collect_mx(const uint16_t *D, const uint16_t *Z, int Kq, int d, int64_t d_pad, int64_t n, int splits,
-                       const float *thr, unsigned int *count, int32_t *cand, int ccap, hipStream_t s);
+void launch_score_mx(bool fp8, const void *D, const float *dscale, const void *Z, int Kq, int d, int64_t d_pad,
+                     int64_t n, int splits, float *part_s, int *part_j, hipStream_t s);
+void launch_collect_mx(bool fp8, const void *D, const float *dscale, const void *Z, int Kq, int d, int64_t d_pad,
+                       int64_t n, int splits, const float *thr, unsigned int *count, int32_t *cand, int ccap,
+                       hipStream_t s);
 // The split-BF16 filter over the split rows Zx[rows[i]] for i < *dcnt (<= cap),
 // collecting atoms as launch_collect_f32_dev.
 void launch_collect_x3_dev(const uint16_t *Dx, const uint16_t *Zx, const int32_t *rows, int d, int64_t d_pad,
