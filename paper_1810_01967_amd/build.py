@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmrf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["mrf_api.cpp", "mrf_net.cpp", "mrf_tree.cpp", "covertree.cpp", "k_tree.hip", "k_mf.hip", "k_lowp.hip", "k_fft.hip", "k_mlp.hip", "k_mlp_bf16.hip", "k_local.hip", "k_score_x3.hip", "k_score_mx.hip", "k_certify.hip", "k_subspace.hip", "k_phase.hip", "k_nufft.hip",
+SOURCES = ["mrf_api.cpp", "mrf_net.cpp", "mrf_tree.cpp", "covertree.cpp", "k_tree.hip", "k_mf.hip", "k_lowp.hip", "k_fft.hip", "k_mlp.hip", "k_mlp_bf16.hip", "k_local.hip", "k_score_mx.hip", "k_certify.hip", "k_subspace.hip", "k_phase.hip", "k_nufft.hip",
            "mrf_subspace.cpp", "mrf_nufft.cpp", "mrf_noalloc.cpp"]
 ARCH = os.environ.get("MRF_OFFLOAD_ARCH", "gfx950")
 

@@ -1,26 +1,31 @@
-// Exhaustive matched-filter scoring of reduced-precision rows on the matrix
-// cores of gfx950, FP32 accumulation, with the per-voxel epilogues of the
-// reduced-precision filter fused (eq. exactP): the maximum, or every atom at
-// or above a per-voxel line.
-//   BF16: v_mfma_f32_32x32x16_bf16 (8 values of a row per lane and k-step);
-//   FP8 E4M3: v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales
-//   (32 values per lane and k-step); an atom's score is the E4M3 product
-//   times the atom's row scale (the voxel's scale, common to all its scores,
-//   is left out: lines are given in the same unit).
+// Exhaustive matched-filter scoring on the matrix cores of gfx950, FP32
+// accumulation, with the per-voxel epilogues of the filter fused (eq.
+// exactP).  Three row encodings:
+//   BF16: v_mfma_f32_32x32x16_bf16, 8 values of a row per lane and k-step;
+//   FP8 E4M3: v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales, 32
+//     values per lane and k-step; an atom's score is the E4M3 product times
+//     the atom's row scale (the voxel's scale, common to all its scores, is
+//     left out: lines are given in the same unit);
+//   split BF16: rows of k_split_x3 (per 32 values a 128-byte chunk
+//     [hi 32 | lo 32]); a score is hi.hi + hi.lo + lo.hi, three
+//     v_mfma_f32_32x32x16_bf16 per k-step.
+// Epilogues: the per-voxel maximum (SC_TOP1), the kCertK best within a window
+// of the running maximum (SC_TOPK, the exactness certificate's lists), or
+// every atom at or above a per-voxel line (SC_COLLECT).
 //
 // Block tile: 256 atoms x 256 voxels, MRF_MX_WA x MRF_MX_WV waves, each
 // owning a (256 / WA) x (256 / WV) sub-tile of MFMA 32x32 tiles (atoms are the
 // A rows, voxels the B columns, so a lane folds one voxel column per tile and
 // atoms reach it in increasing order).  A stage is 128 bytes of each of the
-// 512 rows (64 BF16 or 128 FP8 values), double-buffered in LDS.  Stages go
-// straight from global memory to LDS (global_load_lds_dwordx4: a wave's 64
-// lanes write 16 bytes each at the wave's LDS base + 16 x lane, i.e. eight
-// 128-byte rows), with the eight 16-byte chunks of row r stored at slot
-// chunk ^ (r % 8), so 32 lanes reading one chunk of 32 consecutive rows hit
-// distinct banks.  Work items are (voxel tile, atom split) pairs; the splits
-// of a voxel tile run on one XCD (item w on XCD w % 8), so its blocks share
-// the voxel tile and, across the voxel tiles in flight, the atom tiles through
-// that XCD's L2.
+// 512 rows, double-buffered in LDS.  Stages go straight from global memory to
+// LDS (global_load_lds_dwordx4: a wave's 64 lanes write 16 bytes each at the
+// wave's LDS base + 16 x lane, i.e. eight 128-byte rows), with the eight
+// 16-byte chunks of row r stored at slot chunk ^ (r % 8), so 32 lanes reading
+// one chunk of 32 consecutive rows hit distinct banks.  Work items are (voxel
+// tile, atom split) pairs; the splits of a voxel tile run on one XCD (item w
+// on XCD w % 8), so its blocks share the voxel tile and, across the voxel
+// tiles in flight, the atom tiles through that XCD's L2.
+#include "k_split.h"
 #include "k_topk.h"
 #include "mrf_internal.h"
 
@@ -34,18 +39,17 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
+enum { E_BF16 = 0, E_FP8 = 1, E_X3 = 2 };
+
 // wave grid (atom-row groups x voxel-column groups; tuning constants)
 // (8 waves of 128 atoms x 64 voxels: BF16 12.5 ms per 65,536 x 100,800 x
 // 1,000, against 12.4 for 64 x 128 and 12.9 for 16 waves of 64 x 64; the FP8
-// form needs 128 x 64 to keep its operands in registers)
+// and split forms need 128 x 64 to keep their operands in registers)
 #ifndef MRF_MX_WA
 #define MRF_MX_WA 2
 #endif
 #ifndef MRF_MX_WV
 #define MRF_MX_WV 4
-#endif
-#ifndef MRF_MX_SCHED
-#define MRF_MX_SCHED 1
 #endif
 constexpr int M_BA = 256, M_BV = 256;
 constexpr int M_WA = MRF_MX_WA, M_WV = MRF_MX_WV, M_NT = 64 * M_WA * M_WV;
@@ -57,9 +61,12 @@ constexpr int M_NV = M_VCOLS / 32;                     // 32-voxel MFMA tiles pe
 constexpr int M_NW = M_NT / 64;                        // waves
 constexpr int M_DI = (M_BA + M_BV) / 8 / M_NW;         // 8-row loads per wave and stage
 constexpr int M_DIA = M_BA / 8 / M_NW;                 // of which atom rows
+constexpr int M_DIZ = M_DI - M_DIA;
 static_assert(M_MA >= 1 && M_NV >= 1, "block shape");
 static_assert(M_DI * M_NW * 8 == M_BA + M_BV && (M_BA / 8) % M_NW == 0, "loader shape");
 static_assert(2 * M_STAGE <= 160 * 1024, "LDS");
+static_assert(M_BV == kX3VoxTile, "split-BF16 voxel tiles (gathered rows, device-side splits)");
+static_assert(M_WA * kCertK * M_BV * 8 <= 2 * M_STAGE, "LDS exchange of the candidate lists");
 
 // byte offset of the 16-byte chunk c in a stage row r (r % 8 == rm)
 __device__ __forceinline__ int chunk_at(int c, int rm) { return (c ^ rm) * 16; }
@@ -73,26 +80,44 @@ struct MxArgs {
   int64_t row;             // row pitch in bytes
   int nstage;              // 128-byte stages per row
   int d, ntiles;           // atoms; 256-atom tiles
-  int64_t n;               // voxels (device count: the capacity)
-  int splits, tps;         // atom splits and 256-atom tiles per split
-  float *part_s;           // SC_TOP1 [splits][pstride]
+  int64_t n;               // voxels (with dcnt: the capacity)
+  const unsigned int *dcnt;  // voxel count on the device (null: n)
+  int splits, tps;         // atom splits and 256-atom tiles per split (dcnt: chosen on the device)
+  float *part_s;           // SC_TOP1 [splits][pstride], SC_TOPK [splits][pstride][kCertK]
   int *part_j;
   int64_t pstride;
+  const float *znorm;      // SC_TOPK: window cw ||Z_v|| + wabs
+  float cw, wabs;
+  const int32_t *rowmap;   // SC_COLLECT, split rows: voxel i is row rowmap[i] of Z
   const float *thr;        // SC_COLLECT: per-voxel line
   unsigned int *count;
   int32_t *cand;
   int ccap;
 };
 
-template <bool F8, int MODE>
+template <int E, int MODE>
 __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
-  const int64_t nvox = g.n;
-  const int nsplit = g.splits, tps = g.tps;
-  const int nvt = (int)((nvox + M_BV - 1) / M_BV);
+  constexpr bool F8 = E == E_FP8, X3 = E == E_X3;
+  constexpr bool RMAP = X3 && MODE == SC_COLLECT;
+  // work items; with the voxel count on the device the tiles and splits
+  // follow from it and the grid loops over the items
+  int64_t nvox = g.n;
+  int nsplit = g.splits, tps = g.tps;
+  int nvt = (int)((nvox + M_BV - 1) / M_BV);
+  if (g.dcnt) {
+    nvox = min(g.n, (int64_t)*g.dcnt);
+    nvt = (int)((nvox + M_BV - 1) / M_BV);
+    const int nvt8 = (nvt + 7) / 8 * 8;
+    // a rescan spreads its few voxel tiles over more splits (about 2,048
+    // items); the fallback's split count is the one its merge recomputes
+    nsplit = MODE == SC_COLLECT ? max(1, min(g.ntiles, min(256, (2048 + nvt8 - 1) / max(8, nvt8))))
+                                : x3_device_splits(nvt, g.ntiles);
+    tps = (g.ntiles + nsplit - 1) / nsplit;
+  }
   const int64_t nwork = (int64_t)((nvt + 7) / 8 * 8) * nsplit;
 
   __shared__ __attribute__((aligned(16))) uint8_t S[2 * M_STAGE];
-  __shared__ __attribute__((aligned(16))) float SCL[F8 ? 2 : 1][M_BA];  // FP8: atom scales by tile parity
+  __shared__ __attribute__((aligned(16))) float SCL[F8 ? 2 : 1][F8 ? M_BA : 4];  // FP8: atom scales by tile parity
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wa = wave / M_WV, wv = wave % M_WV;
@@ -114,10 +139,17 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
     const int nq = te > tb ? (te - tb) * g.nstage : 0;
 
     // loads i < M_DIA fetch atom rows, the rest voxel rows; row R of load i is
-    // i M_NW 8 rows after the wave's first, a uniform step
+    // i M_NW 8 rows after the wave's first, a uniform step (voxel rows of a
+    // rescan through the row map; rows past the count read the first listed row)
     const uint8_t *a0 = g.D + (int64_t)(tb * M_BA + wave * 8 + drow) * g.row + dchunk;
-    const uint8_t *z0 = g.Z + (v0 + wave * 8 + drow) * g.row + dchunk;
     const int64_t istep = (int64_t)M_NW * 8 * g.row;
+    const uint8_t *zr[RMAP ? M_DIZ : 1];
+#pragma unroll
+    for (int i = 0; i < (RMAP ? M_DIZ : 1); ++i) {
+      int64_t r = v0 + i * M_NW * 8 + wave * 8 + drow;
+      if (RMAP) r = g.rowmap[r < nvox ? r : 0];
+      zr[i] = g.Z + r * g.row + dchunk;
+    }
     // FP8: a tile's 256 atom scales go to LDS through registers of wave 0
     // (loaded after the stage's DMA loads and stored at the end of the stage,
     // where those are waited for anyway), in the slot of the tile's parity
@@ -125,11 +157,12 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
     int stile = -1;
     auto dload = [&](int q, int buf) {
       const int tq = q / g.nstage;
-      const int64_t aoff = (int64_t)tq * M_BA * g.row + (q - tq * g.nstage) * M_ROWB;
-      const int64_t zoff = (q - tq * g.nstage) * M_ROWB;
+      const int64_t soff = (q - tq * g.nstage) * M_ROWB;
+      const int64_t aoff = (int64_t)tq * M_BA * g.row + soff;
 #pragma unroll
       for (int i = 0; i < M_DI; ++i) {
-        const uint8_t *src = i < M_DIA ? a0 + i * istep + aoff : z0 + (i - M_DIA) * istep + zoff;
+        const uint8_t *src = i < M_DIA ? a0 + i * istep + aoff
+                                       : (RMAP ? zr[RMAP ? i - M_DIA : 0] : zr[0] + (i - M_DIA) * istep) + soff;
         __builtin_amdgcn_global_load_lds((const void *)src,
                                          (lds_void *)(S + buf * M_STAGE + (i * M_NW + wave) * 8 * M_ROWB), 16, 0, 0);
       }
@@ -153,14 +186,21 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
       for (int b = 0; b < M_NV; ++b)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
-    float best[M_NV], vthr[M_NV];
+    float best[M_NV], vthr[M_NV], win[M_NV];  // SC_TOPK: insertion bar and window; SC_COLLECT: the line
     int bidx[M_NV];
+    float ls[MODE == SC_TOPK ? M_NV : 1][kCertK];
+    int lj[MODE == SC_TOPK ? M_NV : 1][kCertK];
 #pragma unroll
     for (int b = 0; b < M_NV; ++b) {
       best[b] = -INFINITY;
       bidx[b] = -1;
-      vthr[b] = INFINITY;
+      vthr[b] = MODE == SC_TOPK ? -INFINITY : INFINITY;
+      win[b] = 0.f;
       const int64_t v = v0 + wv * M_VCOLS + b * 32 + l32;
+      if constexpr (MODE == SC_TOPK) {
+        topk_clear(ls[b], lj[b]);
+        if (v < nvox) win[b] = g.cw * fmaxf(g.znorm[v], 0.f) + g.wabs;
+      }
       if (MODE == SC_COLLECT && v < nvox) vthr[b] = g.thr[v];
     }
 
@@ -199,38 +239,46 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
                                                                             0, 0x7F);
           }
         }
+      } else if constexpr (X3) {
+        // two k-steps of 16: the lane supplies 8 values of each plane (hi
+        // chunk 2 ks + h, lo chunk 4 + 2 ks + h)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const int oh = chunk_at(2 * ks + h, rm), ol = chunk_at(4 + 2 * ks + h, rm);
+          bf16x8 zh[M_NV], zl[M_NV];
+#pragma unroll
+          for (int nv = 0; nv < M_NV; ++nv) {
+            zh[nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + oh);
+            zl[nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + ol);
+          }
+#pragma unroll
+          for (int ma = 0; ma < M_MA; ++ma) {
+            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + oh);
+            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + ol);
+#pragma unroll
+            for (int nv = 0; nv < M_NV; ++nv) {
+              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zh[nv], acc[ma][nv], 0, 0, 0);
+              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zl[nv], acc[ma][nv], 0, 0, 0);
+              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, zh[nv], acc[ma][nv], 0, 0, 0);
+            }
+          }
+        }
       } else {
-        // four k-steps of 16: the lane supplies 8 BF16 (chunk 2 ks + h); the
-        // fragments of step ks + 1 are read while step ks multiplies
-        bf16x8 af[2][M_MA], zf[2][M_NV];
-        auto frag = [&](int ks, int set) {
-          const int ko = chunk_at(2 * ks + h, rm);
-#pragma unroll
-          for (int nv = 0; nv < M_NV; ++nv) zf[set][nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + ko);
-#pragma unroll
-          for (int ma = 0; ma < M_MA; ++ma) af[set][ma] = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + ko);
-        };
-        frag(0, 0);
+        // four k-steps of 16: the lane supplies 8 BF16 (chunk 2 ks + h)
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-          if (ks + 1 < 4) frag(ks + 1, (ks + 1) & 1);
+          const int ko = chunk_at(2 * ks + h, rm);
+          bf16x8 zf[M_NV];
 #pragma unroll
-          for (int ma = 0; ma < M_MA; ++ma)
+          for (int nv = 0; nv < M_NV; ++nv) zf[nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + ko);
+#pragma unroll
+          for (int ma = 0; ma < M_MA; ++ma) {
+            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + ko);
 #pragma unroll
             for (int nv = 0; nv < M_NV; ++nv)
-              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ks & 1][ma], zf[ks & 1][nv], acc[ma][nv], 0, 0, 0);
+              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, zf[nv], acc[ma][nv], 0, 0, 0);
+          }
         }
-#if MRF_MX_SCHED
-        // issue order: the reads of step 0, then (reads of step ks + 1,
-        // products of step ks) for ks < 3, then the products of step 3
-        __builtin_amdgcn_sched_group_barrier(0x100, M_MA + M_NV, 0);
-#pragma unroll
-        for (int ks = 0; ks < 3; ++ks) {
-          __builtin_amdgcn_sched_group_barrier(0x100, M_MA + M_NV, 0);
-          __builtin_amdgcn_sched_group_barrier(0x008, M_MA * M_NV, 0);
-        }
-        __builtin_amdgcn_sched_group_barrier(0x008, M_MA * M_NV, 0);
-#endif
       }
       const int st = q % g.nstage;
       if (st == g.nstage - 1) {
@@ -245,16 +293,22 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
           for (int ma = 0; ma < M_MA; ++ma)
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-              const int j = abase + ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-              const float sc = F8 ? acc[ma][nv][i] * scl[ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3)] : acc[ma][nv][i];
-              if (MODE == SC_TOP1) {
-                if (j < g.d && sc > best[nv]) {  // atoms in increasing order: '>' keeps the lowest index
-                  best[nv] = sc;
-                  bidx[nv] = j;
+              const int r = ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+              const int j = abase + r;
+              const float sc = F8 ? acc[ma][nv][i] * scl[r] : acc[ma][nv][i];
+              if constexpr (MODE == SC_TOPK) {
+                if (j < g.d && sc > vthr[nv]) {
+                  topk_push_ordered(ls[nv], lj[nv], sc, j);
+                  vthr[nv] = fmaxf(ls[nv][kCertK - 1], ls[nv][0] - win[nv]);
                 }
-              } else if (j < g.d && v < nvox && sc >= vthr[nv]) {
-                const unsigned int pos = atomicAdd(&g.count[v], 1u);
-                if ((int)pos < g.ccap) g.cand[v * g.ccap + pos] = j;
+              } else if constexpr (MODE == SC_COLLECT) {
+                if (j < g.d && v < nvox && sc >= vthr[nv]) {
+                  const unsigned int pos = atomicAdd(&g.count[v], 1u);
+                  if ((int)pos < g.ccap) g.cand[v * g.ccap + pos] = j;
+                }
+              } else if (j < g.d && sc > best[nv]) {  // atoms in increasing order: '>' keeps the lowest index
+                best[nv] = sc;
+                bidx[nv] = j;
               }
             }
         }
@@ -271,8 +325,48 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
     }
     if (MODE == SC_COLLECT) continue;  // the candidates are already written
 
-    // the two half-waves, then the M_WA atom-row groups of the block through LDS
-    {
+    if constexpr (MODE == SC_TOPK) {
+      // the two half-waves, then the M_WA atom-row groups' lists through LDS
+      float *ps = reinterpret_cast<float *>(S);
+      int *pj = reinterpret_cast<int *>(S) + M_WA * kCertK * M_BV;
+#pragma unroll
+      for (int nv = 0; nv < M_NV; ++nv) {
+        topk_merge_xor(ls[nv], lj[nv], 32);
+        if (h == 0) {
+          const int c = wv * M_VCOLS + nv * 32 + l32;
+#pragma unroll
+          for (int i = 0; i < kCertK; ++i) {
+            ps[(wa * kCertK + i) * M_BV + c] = ls[nv][i];
+            pj[(wa * kCertK + i) * M_BV + c] = lj[nv][i];
+          }
+        }
+      }
+      __syncthreads();
+      if (tid < M_BV) {
+        float ms[kCertK];
+        int mj[kCertK];
+#pragma unroll
+        for (int i = 0; i < kCertK; ++i) {
+          ms[i] = ps[i * M_BV + tid];
+          mj[i] = pj[i * M_BV + tid];
+        }
+        for (int w2 = 1; w2 < M_WA; ++w2)
+#pragma unroll
+          for (int i = 0; i < kCertK; ++i)
+            topk_push(ms, mj, ps[(w2 * kCertK + i) * M_BV + tid], pj[(w2 * kCertK + i) * M_BV + tid]);
+        const int64_t v = v0 + tid;
+        if (v < nvox) {
+          float *os = g.part_s + ((int64_t)split * g.pstride + v) * kCertK;
+          int *oj = g.part_j + ((int64_t)split * g.pstride + v) * kCertK;
+#pragma unroll
+          for (int i = 0; i < kCertK; ++i) {
+            os[i] = ms[i];
+            oj[i] = mj[i];
+          }
+        }
+      }
+    } else {
+      // the two half-waves, then the M_WA atom-row groups of the block through LDS
       float *ps = reinterpret_cast<float *>(S);
       int *pj = reinterpret_cast<int *>(S) + M_WA * M_BV;
 #pragma unroll
@@ -312,32 +406,29 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
 
 namespace {
 
-MxArgs mx_args(bool fp8, const void *D, const float *dscale, const void *Z, int Kq, int d, int64_t d_pad,
-               int64_t n, int splits) {
+MxArgs mx_args(int e, const void *D, const void *Z, int row_bytes, int d, int64_t d_pad, int64_t n, int splits) {
   MxArgs a{};
   a.D = static_cast<const uint8_t *>(D);
   a.Z = static_cast<const uint8_t *>(Z);
-  a.dscale = dscale;
-  a.row = (int64_t)Kq * (fp8 ? 1 : 2);
-  a.nstage = (int)(a.row / M_ROWB);
+  a.row = row_bytes;
+  a.nstage = row_bytes / M_ROWB;
   a.d = d;
   a.ntiles = (int)(d_pad / M_BA);
   a.n = n;
   a.splits = splits;
   a.tps = (a.ntiles + splits - 1) / splits;
+  a.pstride = n;
+  (void)e;
   return a;
 }
 
-template <int MODE>
-void launch_mx(bool fp8, const MxArgs &a, hipStream_t s) {
-  const int64_t nvt = (a.n + M_BV - 1) / M_BV;
-  const int64_t blocks = (nvt + 7) / 8 * 8 * a.splits;
-  if (blocks <= 0) return;
-  if (fp8)
-    hipLaunchKernelGGL((k_score_mx<true, MODE>), dim3((unsigned)blocks), dim3(M_NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_score_mx<false, MODE>), dim3((unsigned)blocks), dim3(M_NT), 0, s, a);
+template <int E, int MODE>
+void launch_mx(const MxArgs &a, int64_t blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL((k_score_mx<E, MODE>), dim3((unsigned)blocks), dim3(M_NT), 0, s, a);
 }
+
+// one block per work item (voxel tiles rounded to whole XCD rounds)
+int64_t item_blocks(const MxArgs &a) { return ((a.n + M_BV - 1) / M_BV + 7) / 8 * 8 * a.splits; }
 
 }  // namespace
 
@@ -354,22 +445,72 @@ int mx_auto_splits(int64_t d_pad, int64_t n) {
 
 void launch_score_mx(bool fp8, const void *D, const float *dscale, const void *Z, int Kq, int d, int64_t d_pad,
                      int64_t n, int splits, float *part_s, int *part_j, hipStream_t s) {
-  MxArgs a = mx_args(fp8, D, dscale, Z, Kq, d, d_pad, n, splits);
+  MxArgs a = mx_args(fp8 ? E_FP8 : E_BF16, D, Z, Kq * (fp8 ? 1 : 2), d, d_pad, n, splits);
+  a.dscale = dscale;
   a.part_s = part_s;
   a.part_j = part_j;
-  a.pstride = n;
-  launch_mx<SC_TOP1>(fp8, a, s);
+  if (fp8)
+    launch_mx<E_FP8, SC_TOP1>(a, item_blocks(a), s);
+  else
+    launch_mx<E_BF16, SC_TOP1>(a, item_blocks(a), s);
 }
 
 void launch_collect_mx(bool fp8, const void *D, const float *dscale, const void *Z, int Kq, int d, int64_t d_pad,
                        int64_t n, int splits, const float *thr, unsigned int *count, int32_t *cand, int ccap,
                        hipStream_t s) {
-  MxArgs a = mx_args(fp8, D, dscale, Z, Kq, d, d_pad, n, splits);
+  MxArgs a = mx_args(fp8 ? E_FP8 : E_BF16, D, Z, Kq * (fp8 ? 1 : 2), d, d_pad, n, splits);
+  a.dscale = dscale;
   a.thr = thr;
   a.count = count;
   a.cand = cand;
   a.ccap = ccap;
-  launch_mx<SC_COLLECT>(fp8, a, s);
+  if (fp8)
+    launch_mx<E_FP8, SC_COLLECT>(a, item_blocks(a), s);
+  else
+    launch_mx<E_BF16, SC_COLLECT>(a, item_blocks(a), s);
+}
+
+// Dx: split atoms [d_pad][2 Kx] (d_pad a multiple of 256); Zx: split voxels
+// [n_pad][2 Kx] (n_pad a multiple of 256, zero rows beyond n).
+void launch_score_x3(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t n, int64_t n_pad,
+                     int Kx, int splits, float *part_s, int *part_j, hipStream_t s, bool topk, const float *znorm,
+                     float cw, float wabs) {
+  (void)n_pad;
+  MxArgs a = mx_args(E_X3, Dx, Zx, 4 * Kx, d, d_pad, n, splits);
+  a.part_s = part_s;
+  a.part_j = part_j;
+  a.znorm = znorm;
+  a.cw = cw;
+  a.wabs = wabs;
+  if (topk)
+    launch_mx<E_X3, SC_TOPK>(a, item_blocks(a), s);
+  else
+    launch_mx<E_X3, SC_TOP1>(a, item_blocks(a), s);
+}
+
+// device-sized forms: one block per CU of the 256, each looping over the items
+void launch_score_x3_dev(const uint16_t *Dx, const uint16_t *Zx, int d, int64_t d_pad, int64_t cap,
+                         const unsigned int *dcnt, int Kx, float *part_s, int *part_j, hipStream_t s) {
+  if (cap <= 0) return;
+  MxArgs a = mx_args(E_X3, Dx, Zx, 4 * Kx, d, d_pad, cap, 1);
+  a.dcnt = dcnt;
+  a.part_s = part_s;
+  a.part_j = part_j;
+  launch_mx<E_X3, SC_TOP1>(a, 256, s);
+}
+
+void launch_collect_x3_dev(const uint16_t *Dx, const uint16_t *Zx, const int32_t *rows, int d, int64_t d_pad,
+                           int64_t cap, const unsigned int *dcnt, int Kx, const float *thr, unsigned int *count,
+                           int32_t *cand, int ccap, hipStream_t s) {
+  if (cap <= 0) return;
+  MxArgs a = mx_args(E_X3, Dx, Zx, 4 * Kx, d, d_pad, cap, 1);
+  a.dcnt = dcnt;
+  a.rowmap = rows;
+  a.thr = thr;
+  a.count = count;
+  a.cand = cand;
+  a.ccap = ccap;
+  launch_mx<E_X3, SC_COLLECT>(a, 256, s);
 }
 
 }  // namespace mrf

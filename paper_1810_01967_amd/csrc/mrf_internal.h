@@ -30,10 +30,10 @@ constexpr int kNufftBin = 8;
 // Atom / voxel row counts are padded to multiples of 256 so every tiling of
 // the scoring kernels reads inside the allocation.
 constexpr int kRowPad = 256;
-// voxels per tile of the split-BF16 exhaustive filter (128 or 256; a tuning
-// constant, a divisor of kRowPad)
+// voxels per tile of the split-BF16 exhaustive filter (the matrix-core
+// kernel's voxel tile; gathered fallback rows are padded to it)
 #ifndef MRF_X3_BV
-#define MRF_X3_BV 128
+#define MRF_X3_BV 256
 #endif
 constexpr int kX3VoxTile = MRF_X3_BV;
 // K per stage of the BF16 network kernels (32 or 64; a tuning constant); the

@@ -5,7 +5,6 @@ every entry point, the host passes over the caller's arrays that precede any
 device call, and the error paths a machine without a GPU takes.  Any
 sanitizer report aborts the driver (no recovery)."""
 import concurrent.futures
-import glob
 import os
 import subprocess
 
@@ -29,7 +28,10 @@ def _hipcc():
 
 @pytest.fixture(scope="module")
 def driver(tmp_path_factory):
-    kernels = sorted(glob.glob(os.path.join(ROOT, "paper_1810_01967_amd", "_build", "k_*.o")))
+    from paper_1810_01967_amd import build as lib_build
+    kernels = [os.path.join(ROOT, "paper_1810_01967_amd", "_build", os.path.splitext(s)[0] + ".o")
+               for s in lib_build.SOURCES if s.startswith("k_")]
+    kernels = [k for k in kernels if os.path.exists(k)]
     assert kernels, "build the library first (paper_1810_01967_amd.build.build())"
     out = tmp_path_factory.mktemp("abi_san")
     hipcc = _hipcc()
