@@ -291,7 +291,9 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
           const int64_t v = v0 + wv * M_VCOLS + nv * 32 + l32;
 #pragma unroll
           for (int ma = 0; ma < M_MA; ++ma)
-#pragma unroll
+            // the list insertion is long and rare: one copy per tile of the
+            // accumulators, its element picked by the (uniform) loop index
+#pragma unroll(MODE == SC_TOPK ? 1 : 16)
             for (int i = 0; i < 16; ++i) {
               const int r = ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
               const int j = abase + r;
