@@ -204,12 +204,14 @@ def main():
                 net.save(args.net_cache)
         fastest = min([ms32] + [v["ms_per_step"] for v in variants.values()
                                 if v["index_mismatch_vs_fp32"] <= 1e-3])
-        cases = [(lp, args.box_radius, lp) for lp in args.learned_precisions.split(",")]
+        cases = [(lp, args.box_radius, lp, False) for lp in args.learned_precisions.split(",")]
         if args.box_radius != 3:  # the +-3 box the learned form names, beside the default one
-            cases.append(("bf16x3", 3, "bf16x3_r3"))
-        for lp, radius, key in cases:
+            cases.append(("bf16x3", 3, "bf16x3_r3", False))
+        # certified local search: exact (FP64) argmax over each box and warm atom
+        cases += [(lp, args.box_radius, f"{lp}_certified", True) for lp in args.learned_precisions.split(",")]
+        for lp, radius, key, cl in cases:
             lms, lst, lo = run(args.steps, args.warmup, net=net, box_radius=radius, fallback_corr=0.98,
-                               recentre=args.recentre, precision=lp)
+                               recentre=args.recentre, precision=lp, certify_local=cl)
             lidx = lo["idx"].cpu().numpy()
             answers[f"learned_{key}"] = (lidx, lo["pd"].cpu().numpy())
             mism = float(np.mean(lidx != idx32))
@@ -217,6 +219,7 @@ def main():
             # (voxel, atom of its clipped box)
             box_flops = 2.0 * K * float(lst[7])
             learned[key] = {"voxels_per_s": n / (lms * 1e-3), "ms_per_step": lms, "box_radius": radius,
+                            "certified_local": cl,
                            "index_mismatch_vs_exhaustive_fp32": mism,
                            "local_score_kernel_ms": float(lst[0]), "local_search_ms": float(lst[6]),
                            "proposal_ms": float(lst[1]),
@@ -225,7 +228,8 @@ def main():
                            "first_launch_box_atoms": float(lst[7]),
                            "speedup_vs_exhaustive_fp32": ms32 / lms,
                            "speedup_vs_fastest_exhaustive_within_0.1pct": fastest / lms,
-                           "box_flop_first_launch": box_flops}
+                           "box_flop_first_launch": box_flops,
+                           "rescored_per_voxel": float(lst[8]) / n, "rescanned": float(lst[9])}
             log(f"learned ({key}, radius {radius}): {lms:.3f} ms/step (local search {lst[6]:.3f}, first scoring kernel "
                 f"{lst[0]:.3f}, proposal {lst[1]:.3f}, fallback {lst[2]:.3f} ms, {lst[3]:.0f} fallbacks, "
                 f"{lst[4]:.0f} re-centred, {lst[7] / n:.1f} box atoms per voxel), mismatch {mism:.5f}")

@@ -257,6 +257,15 @@ typedef struct {
                             (its rounding can pick an atom whose exact score is below the
                             maximum by up to that bound); PD and corr come from the exact
                             score of the returned atom for BF16 / FP8. */
+  int32_t certify_local;  /* MRF_LEARNED.  0 (default): the local search's own argmax over the
+                            box (and the warm atom), in the arithmetic of `precision`.  1: that
+                            argmax made exact (eq. exactP restricted to the box): the answer's
+                            exact (FP64) score b is computed, a second pass over the boxes
+                            collects every atom whose score reaches b minus the pass's error
+                            bound, and those (and the warm atom) are rescored exactly; a voxel
+                            with more than 64 such atoms, and every exhaustive fallback, takes
+                            the exhaustive certificate's rescan.  Needs the voxels' FP32 rows
+                            (packed whenever it is set). */
 } mrf_match_opts;
 
 typedef struct {

@@ -156,6 +156,9 @@ struct mrf_dict_s {
   // reduced-precision certificate: per voxel the decoded row norms, line, exact
   // best score, candidate count and candidates [n][kLowpCap]
   mrf::DevBuf lp_qn, lp_thr, lp_b, lp_count, lp_cand;
+  // certified local search: per-voxel line, candidate count and list, exact
+  // score and index of the local answer, exhaustive-fallback flags
+  mrf::DevBuf lc_thr, lc_count, lc_cand, lc_bex, lc_bjx, lc_fb;
   // max over the atoms of ||r_j|| and ||d_j - r_j|| for the BF16 and FP8 copies r_j
   double qn_bf16[2] = {0.0, 0.0}, qn_fp8[2] = {0.0, 0.0};
   bool cert_used = false;  // the last exhaustive match ran the certificate

@@ -33,11 +33,35 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 // Exact (FP64) <z, a> over K FP32 values; every lane returns the same value
-// (fixed reduction order).
+// (fixed reduction order).  Rows are 16-byte aligned and zero from K up to
+// their pitch (a multiple of 16), so the lanes read 16-byte pieces up to K
+// rounded to 4: every product of two FP32 values is exact in FP64, and the
+// loads of a lane are independent of its two running sums.
 __device__ __forceinline__ double dot64(const float *__restrict__ z, const float *__restrict__ a, int K, int lane) {
-  double acc = 0.0;
-  for (int k = lane; k < K; k += 64) acc = fma((double)z[k], (double)a[k], acc);
-  return wave_sum(acc);
+  const int K4 = (K + 3) & ~3;
+  double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll 4
+  for (int k = 4 * lane; k < K4; k += 256) {
+    const float4 x = *reinterpret_cast<const float4 *>(z + k);
+    const float4 y = *reinterpret_cast<const float4 *>(a + k);
+    acc0 = fma((double)x.x, (double)y.x, acc0);
+    acc1 = fma((double)x.y, (double)y.y, acc1);
+    acc0 = fma((double)x.z, (double)y.z, acc0);
+    acc1 = fma((double)x.w, (double)y.w, acc1);
+  }
+  return wave_sum(acc0 + acc1);
+}
+
+// Adds each thread's x to *dst with one global atomic per block (every
+// thread of the block calls it): one atomic per voxel on a single counter
+// serialises at its L2 channel.
+__device__ __forceinline__ void block_add(unsigned long long *dst, unsigned long long x) {
+  __shared__ unsigned long long acc;
+  if (threadIdx.x == 0) acc = 0ull;
+  __syncthreads();
+  if (x) atomicAdd(&acc, x);
+  __syncthreads();
+  if (threadIdx.x == 0 && acc) atomicAdd(dst, acc);
 }
 
 __device__ __forceinline__ bool exact_better(double s1, int j1, double s0, int j0) {
@@ -77,55 +101,59 @@ __global__ __launch_bounds__(256) void k_certify(const float *__restrict__ part_
                                                  int K, float cE, float cE32, float eabs, CertOut o, CertQueue q) {
   const int lane = threadIdx.x & 63;
   const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (v >= n) return;
-  float ls[kCertK];
-  int lj[kCertK];
-  topk_clear(ls, lj);
-  for (int sp = 0; sp < splits; ++sp) {
-    const float *cs = part_s + ((int64_t)sp * pstride + v) * kCertK;
-    const int *cj = part_j + ((int64_t)sp * pstride + v) * kCertK;
+  unsigned long long counted = 0;
+  do {
+    if (v >= n) break;
+    float ls[kCertK];
+    int lj[kCertK];
+    topk_clear(ls, lj);
+    for (int sp = 0; sp < splits; ++sp) {
+      const float *cs = part_s + ((int64_t)sp * pstride + v) * kCertK;
+      const int *cj = part_j + ((int64_t)sp * pstride + v) * kCertK;
 #pragma unroll
-    for (int i = 0; i < kCertK; ++i) topk_push(ls, lj, cs[i], cj[i]);
-  }
-  const float zn = o.znorm[v];
-  if (!(zn > 0.f) || lj[0] < 0) {  // zero or non-finite voxel: nothing to certify
-    if (lane == 0) finish(v, ls[0], lj[0], d, o);
-    return;
-  }
-  const float *z = Zp + v * Kp;
-  const double E = (double)cE * zn + eabs;
-  double bs = dot64(z, D + (int64_t)lj[0] * Kp, K, lane);
-  int bj = lj[0];
-  int rescored = 1;
-  bool full = true;  // every listed pair lies on or above the line
-#pragma unroll
-  for (int c = 1; c < kCertK; ++c) {
-    if (lj[c] < 0 || (double)ls[c] < bs - E) {
-      full = false;
+      for (int i = 0; i < kCertK; ++i) topk_push(ls, lj, cs[i], cj[i]);
+    }
+    const float zn = o.znorm[v];
+    if (!(zn > 0.f) || lj[0] < 0) {  // zero or non-finite voxel: nothing to certify
+      if (lane == 0) finish(v, ls[0], lj[0], d, o);
       break;
     }
-    const double sc = dot64(z, D + (int64_t)lj[c] * Kp, K, lane);
-    ++rescored;
-    if (exact_better(sc, lj[c], bs, bj)) {
-      bs = sc;
-      bj = lj[c];
+    const float *z = Zp + v * Kp;
+    const double E = (double)cE * zn + eabs;
+    double bs = dot64(z, D + (int64_t)lj[0] * Kp, K, lane);
+    int bj = lj[0];
+    int rescored = 1;
+    bool full = true;  // every listed pair lies on or above the line
+#pragma unroll
+    for (int c = 1; c < kCertK; ++c) {
+      if (lj[c] < 0 || (double)ls[c] < bs - E) {
+        full = false;
+        break;
+      }
+      const double sc = dot64(z, D + (int64_t)lj[c] * Kp, K, lane);
+      ++rescored;
+      if (exact_better(sc, lj[c], bs, bj)) {
+        bs = sc;
+        bj = lj[c];
+      }
     }
-  }
-  if (full && (double)ls[kCertK - 1] < bs - E) full = false;  // the line rose above the last pair
-  if (lane == 0) {
-    finish(v, (float)bs, bj, d, o);
-    atomicAdd(q.rescored, (unsigned long long)rescored);
-    if (full) {
-      const unsigned int pos = atomicAdd(q.count, 1u);
-      q.list[pos] = (int32_t)v;
-      q.ccount[pos] = 0u;
-      // the rescan's line in FP32 scores (rounded down); b itself lies on or above it
-      const double line = bs - ((double)cE32 * zn + eabs);
-      float t = (float)line;
-      if ((double)t > line) t = nextafterf(t, -INFINITY);
-      q.thr[pos] = t;
+    if (full && (double)ls[kCertK - 1] < bs - E) full = false;  // the line rose above the last pair
+    if (lane == 0) {
+      finish(v, (float)bs, bj, d, o);
+      counted = (unsigned long long)rescored;
+      if (full) {
+        const unsigned int pos = atomicAdd(q.count, 1u);
+        q.list[pos] = (int32_t)v;
+        q.ccount[pos] = 0u;
+        // the rescan's line in FP32 scores (rounded down); b itself lies on or above it
+        const double line = bs - ((double)cE32 * zn + eabs);
+        float t = (float)line;
+        if ((double)t > line) t = nextafterf(t, -INFINITY);
+        q.thr[pos] = t;
+      }
     }
-  }
+  } while (false);
+  block_add(q.rescored, counted);
 }
 
 void launch_certify(const float *part_s, const int *part_j, int splits, int64_t pstride, int64_t n, int d,
@@ -144,6 +172,7 @@ __global__ __launch_bounds__(256) void k_rescore_collected(const float *__restri
                                                            const int32_t *__restrict__ cand, int ccap, CertOut o) {
   const int lane = threadIdx.x & 63;
   const int64_t nq = min(cap, (int64_t)*q.count);
+  unsigned long long counted = 0;
   for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < nq; i += (int64_t)gridDim.x * 4) {
     const int64_t v = q.list[i];
     const unsigned int c = q.ccount[i];
@@ -166,10 +195,11 @@ __global__ __launch_bounds__(256) void k_rescore_collected(const float *__restri
       }
     }
     if (lane == 0) {
-      atomicAdd(q.rescored, (unsigned long long)c);
+      counted += c;
       if (c > 0) finish(v, (float)bs, bj, d, o);
     }
   }
+  block_add(q.rescored, counted);
 }
 
 void launch_rescore_collected(const float *Zp, const float *D, int Kp, int K, int d, int64_t cap, const CertQueue &q,
@@ -291,6 +321,7 @@ __global__ __launch_bounds__(256) void k_rescore_lowp(const float *__restrict__ 
                                                       const double *__restrict__ bex, float cE32, float eabs,
                                                       CertOut o, CertQueue q) {
   const int lane = threadIdx.x & 63;
+  unsigned long long counted = 0;
   for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < n; v += (int64_t)gridDim.x * 4) {
     const unsigned int c = ccount[v];
     if (c == 0) continue;  // zero or non-finite voxel, finished already
@@ -318,10 +349,11 @@ __global__ __launch_bounds__(256) void k_rescore_lowp(const float *__restrict__ 
       }
     }
     if (lane == 0) {
-      atomicAdd(q.rescored, (unsigned long long)c);
+      counted += c;
       finish(v, (float)bs, bj, d, o);
     }
   }
+  block_add(q.rescored, counted);
 }
 
 void launch_rescore_lowp(const float *Zp, const float *D, int Kp, int K, int d, int64_t n, const unsigned int *ccount,
@@ -331,6 +363,122 @@ void launch_rescore_lowp(const float *Zp, const float *D, int Kp, int K, int d, 
   const int64_t blocks = std::min<int64_t>((n + 3) / 4, 4096);
   hipLaunchKernelGGL(k_rescore_lowp, dim3((unsigned)blocks), dim3(256), 0, s, Zp, D, Kp, K, d, n, ccount, cand, ccap,
                      bex, cE32, eabs, o, q);
+}
+
+// Certified local search (the learned path's answer made exact within its
+// box).  With b the exact score of the local search's answer, every box atom
+// that could beat or tie b scores at least b - E_v in the local pass (E_v its
+// error bound), so the collect pass gathers them and they are rescored
+// exactly here; the warm atom (outside the box in general) is rescored too.
+// Exhaustive fallbacks go to the FP32 rescan of the exhaustive certificate.
+__device__ __forceinline__ void queue_rescan(int64_t v, double b, float cE32, float eabs, const CertOut &o,
+                                             const CertQueue &q) {
+  const unsigned int pos = atomicAdd(q.count, 1u);
+  q.list[pos] = (int32_t)v;
+  q.ccount[pos] = 0u;
+  const double line = b - ((double)cE32 * o.znorm[v] + eabs);
+  float t = (float)line;
+  if ((double)t > line) t = nextafterf(t, -INFINITY);
+  q.thr[pos] = t;
+}
+
+__global__ __launch_bounds__(256) void k_local_line(const float *__restrict__ best_s,
+                                                    const int32_t *__restrict__ best_j,
+                                                    const int32_t *__restrict__ fbflag, int64_t n, int d,
+                                                    const float *__restrict__ Zp, const float *__restrict__ D, int Kp,
+                                                    int K, float cE, float cE32, float eabs, CertOut o,
+                                                    float *__restrict__ thr, unsigned int *__restrict__ ccount,
+                                                    double *__restrict__ bex, int32_t *__restrict__ bjx,
+                                                    CertQueue q) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int bj = v < n ? best_j[v] : -1;
+  const float zn = v < n ? o.znorm[v] : 0.f;
+  const bool live = v < n && zn > 0.f && bj >= 0 && bj < d;
+  if (v < n && !live && lane == 0) {  // zero or non-finite voxel: nothing to certify
+    finish(v, best_s[v], bj, d, o);
+    thr[v] = INFINITY;
+    ccount[v] = 0u;
+    bex[v] = 0.0;
+    bjx[v] = -1;
+  }
+  block_add(q.rescored, live && lane == 0 ? 1ull : 0ull);
+  if (!live) return;
+  const double b = dot64(Zp + v * Kp, D + (int64_t)bj * Kp, K, lane);
+  if (lane == 0) {
+    finish(v, (float)b, bj, d, o);
+    ccount[v] = 0u;
+    bex[v] = b;
+    bjx[v] = bj;
+    if (fbflag && fbflag[v]) {
+      thr[v] = INFINITY;  // no box: the exhaustive certificate's rescan
+      queue_rescan(v, b, cE32, eabs, o, q);
+    } else {
+      const double line = b - ((double)cE * zn + eabs);
+      float t = (float)line;
+      if ((double)t > line) t = nextafterf(t, -INFINITY);
+      thr[v] = t;
+    }
+  }
+}
+
+void launch_local_line(const float *best_s, const int32_t *best_j, const int32_t *fbflag, int64_t n, int d,
+                       const float *Zp, const float *D, int Kp, int K, float cE, float cE32, float eabs,
+                       const CertOut &o, float *thr, unsigned int *ccount, double *bex, int32_t *bjx,
+                       const CertQueue &q, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_local_line, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, best_s, best_j, fbflag, n, d, Zp,
+                     D, Kp, K, cE, cE32, eabs, o, thr, ccount, bex, bjx, q);
+}
+
+__global__ __launch_bounds__(256) void k_rescore_local(const float *__restrict__ Zp, const float *__restrict__ D,
+                                                       int Kp, int K, int d, int64_t n,
+                                                       const unsigned int *__restrict__ ccount,
+                                                       const int32_t *__restrict__ cand, int ccap,
+                                                       const double *__restrict__ bex, const int32_t *__restrict__ bjx,
+                                                       const int32_t *__restrict__ warm,
+                                                       const int32_t *__restrict__ fbflag, float cE32, float eabs,
+                                                       CertOut o, CertQueue q) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long counted = 0;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < n; v += (int64_t)gridDim.x * 4) {
+    int bj = bjx[v];
+    if (bj < 0 || (fbflag && fbflag[v])) continue;  // finished already, or in the rescan queue
+    double bs = bex[v];
+    const unsigned int c = ccount[v];
+    if ((int)c > ccap) {
+      if (lane == 0) queue_rescan(v, bs, cE32, eabs, o, q);
+      continue;
+    }
+    const float *z = Zp + v * Kp;
+    const int w = warm ? warm[v] : -1;
+    unsigned int rescored = 0;
+    for (unsigned int t = 0; t <= c; ++t) {
+      const int j = t < c ? cand[v * ccap + t] : w;
+      if (j < 0 || j >= d || j == bjx[v]) continue;
+      const double sc = dot64(z, D + (int64_t)j * Kp, K, lane);
+      ++rescored;
+      if (exact_better(sc, j, bs, bj)) {
+        bs = sc;
+        bj = j;
+      }
+    }
+    if (lane == 0) {
+      counted += rescored;
+      if (bj != bjx[v]) finish(v, (float)bs, bj, d, o);
+    }
+  }
+  block_add(q.rescored, counted);
+}
+
+void launch_rescore_local(const float *Zp, const float *D, int Kp, int K, int d, int64_t n,
+                          const unsigned int *ccount, const int32_t *cand, int ccap, const double *bex,
+                          const int32_t *bjx, const int32_t *warm, const int32_t *fbflag, float cE32, float eabs,
+                          const CertOut &o, const CertQueue &q, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 3) / 4, 4096);
+  hipLaunchKernelGGL(k_rescore_local, dim3((unsigned)blocks), dim3(256), 0, s, Zp, D, Kp, K, d, n, ccount, cand,
+                     ccap, bex, bjx, warm, fbflag, cE32, eabs, o, q);
 }
 
 void launch_scan_exact(const float *Zp, const float *D, int Kp, int K, int d, int64_t cap, const CertQueue &q,

@@ -261,12 +261,15 @@ void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys
 // X3 = false: FP32 rows (pitch Kp), v_mfma_f32_32x32x2f32.
 // X3 = true: split-BF16 rows of chunks [hi 32 | lo 32] (pitch 2 Kx), three v_mfma_f32_32x32x16_bf16
 // per step (hi.hi + hi.lo + lo.hi) accumulated in FP32.
-template <bool X3>
+// COLLECT: instead of each voxel's best, every atom of its box whose score
+// reaches the voxel's line col.thr[v] is appended to col.cand[v][0..ccap)
+// (col.count[v] counts them all): the candidates of the certified local search.
+template <bool X3, bool COLLECT>
 __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
     const void *__restrict__ Dv, const void *__restrict__ Zv, int pitch,
     const int32_t *__restrict__ order, GroupBufs gb, int nkeys, const int32_t *__restrict__ cells,
     int P, GridDims g, int r, int max_at, unsigned long long *__restrict__ bestkey,
-    unsigned long long *__restrict__ work, unsigned long long *__restrict__ boxsum) {
+    unsigned long long *__restrict__ work, unsigned long long *__restrict__ boxsum, LocalCollect col) {
   constexpr int BK = X3 ? LS_BKX : LS_BK32;
   constexpr int A_ELEMS = X3 ? LS_BA * LS_LDX : LS_BA * LS_LD32;  // per buffer, in operand units
   constexpr int Z_ELEMS = X3 ? LS_BV * LS_LDX : LS_BV * LS_LD32;
@@ -551,6 +554,8 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
           lo[p] = vlo[c][p];
           hi[p] = vhi[c][p];
         }
+        const int vv = COLLECT ? vid[c] : -1;
+        const float line = (COLLECT && vv >= 0) ? col.thr[vv] : INFINITY;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int row = wave * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
@@ -559,7 +564,12 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
           bool in = j >= 0;
 #pragma unroll
           for (int p = 0; p < 4; ++p) in = in && acoord[row][p] >= lo[p] && acoord[row][p] <= hi[p];
-          if (in && sc > best[nv]) {
+          if constexpr (COLLECT) {
+            if (in && sc >= line) {
+              const unsigned int pos = atomicAdd(&col.count[vv], 1u);
+              if ((int)pos < col.ccap) col.cand[(int64_t)vv * col.ccap + pos] = j;
+            }
+          } else if (in && sc > best[nv]) {
             best[nv] = sc;
             bidx[nv] = j;
           }
@@ -574,6 +584,7 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
     if (q + 1 < nq) sstore(NBUF == 2 ? buf ^ 1 : 0);
     __syncthreads();
   }
+  if constexpr (COLLECT) return;  // the candidates are already written
 #pragma unroll
   for (int nv = 0; nv < 2; ++nv) {
     const float ps = __shfl_xor(best[nv], 32, 64);
@@ -604,7 +615,7 @@ __global__ __launch_bounds__(256, X3 ? 3 : 2) void k_local_score(
 void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const int32_t *order, int64_t cnt,
                         GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r, int shift,
                         unsigned long long *bestkey, unsigned long long *work, unsigned long long *boxsum,
-                        hipStream_t s) {
+                        hipStream_t s, const LocalCollect *collect) {
   if (cnt <= 0) return;
   // tiles = sum_k ceil(hist[k]/64) <= ceil(cnt/64) + min(nkeys, cnt); a tile's
   // voxels share a coarse cell, so its bounding box spans at most 2^shift + 2r
@@ -614,12 +625,19 @@ void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const
   for (int p = 0; p < P; ++p) bbox *= std::min<int64_t>(g.dims[p], (1 << shift) + 2 * (int64_t)r);
   const int max_at = (int)((bbox + LS_BA - 1) / LS_BA);
   const int64_t blocks = (tiles + 8 * LS_RUN - 1) / (8 * LS_RUN) * (8 * LS_RUN) * max_at;  // whole runs on all XCDs
-  if (x3)
-    hipLaunchKernelGGL(k_local_score<true>, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order, gb,
-                       nkeys, cells, P, g, r, max_at, bestkey, work, boxsum);
+  const LocalCollect lc = collect ? *collect : LocalCollect{};
+  if (x3 && collect)
+    hipLaunchKernelGGL((k_local_score<true, true>), dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order, gb,
+                       nkeys, cells, P, g, r, max_at, bestkey, work, boxsum, lc);
+  else if (x3)
+    hipLaunchKernelGGL((k_local_score<true, false>), dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order,
+                       gb, nkeys, cells, P, g, r, max_at, bestkey, work, boxsum, lc);
+  else if (collect)
+    hipLaunchKernelGGL((k_local_score<false, true>), dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order,
+                       gb, nkeys, cells, P, g, r, max_at, bestkey, work, boxsum, lc);
   else
-    hipLaunchKernelGGL(k_local_score<false>, dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order, gb,
-                       nkeys, cells, P, g, r, max_at, bestkey, work, boxsum);
+    hipLaunchKernelGGL((k_local_score<false, false>), dim3((unsigned)blocks), dim3(256), 0, s, D, Zp, pitch, order,
+                       gb, nkeys, cells, P, g, r, max_at, bestkey, work, boxsum, lc);
 }
 
 // Non-expansive safeguard of the inexact projection: the previous iterate's

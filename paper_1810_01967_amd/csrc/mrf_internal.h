@@ -150,6 +150,24 @@ void launch_lowp_line(const float *part_s, const int *part_j, int splits, int64_
 void launch_rescore_lowp(const float *Zp, const float *D, int Kp, int K, int d, int64_t n, const unsigned int *ccount,
                          const int32_t *cand, int ccap, const double *bex, float cE32, float eabs, const CertOut &o,
                          const CertQueue &q, hipStream_t s);
+// Certified local search.  One wave per voxel: the exact (FP64) score b of
+// the local search's answer best_j[v] (box maximum, the warm atom or the
+// exhaustive fallback's), the voxel finished with it; voxels flagged in
+// fbflag (exhaustive fallbacks) go to the FP32 rescan queue with the line
+// b - (cE32 ||Z_v|| + eabs), the others get the line thr[v] = b - (cE ||Z_v||
+// + eabs) in the local pass's scores (every box atom that could beat or tie b
+// reaches it) and ccount[v] = 0; bex / bjx keep (b, best_j).
+void launch_local_line(const float *best_s, const int32_t *best_j, const int32_t *fbflag, int64_t n, int d,
+                       const float *Zp, const float *D, int Kp, int K, float cE, float cE32, float eabs,
+                       const CertOut &o, float *thr, unsigned int *ccount, double *bex, int32_t *bjx,
+                       const CertQueue &q, hipStream_t s);
+// One wave per voxel: exact rescore of the box candidates the collect pass
+// found (and of the warm atom), starting from (bex, bjx); a voxel with more
+// than ccap candidates goes to the FP32 rescan queue.
+void launch_rescore_local(const float *Zp, const float *D, int Kp, int K, int d, int64_t n,
+                          const unsigned int *ccount, const int32_t *cand, int ccap, const double *bex,
+                          const int32_t *bjx, const int32_t *warm, const int32_t *fbflag, float cE32, float eabs,
+                          const CertOut &o, const CertQueue &q, hipStream_t s);
 constexpr int kLowpCap = 256;  // candidates per voxel of a reduced-precision collect pass
 
 // X_v = gamma_hat_v * Dhat_{idx_v} (zero where idx < 0), written voxel-major
@@ -308,10 +326,19 @@ void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P,
 // One block per (tile, atom tile of the tile's bounding box); per-voxel
 // maxima merge into `bestkey` by atomicMax on (score, lower atom) keys (zero
 // them first, unpack after with launch_best_keys).
+// Candidates of the certified local search: every atom of a voxel's box whose
+// score reaches thr[v] goes to cand[v][0..ccap) (count[v] counts them all;
+// zeroed by the caller).
+struct LocalCollect {
+  const float *thr;
+  unsigned int *count;
+  int32_t *cand;
+  int ccap;
+};
 void launch_local_score(const void *D, const void *Zp, int pitch, bool x3, const int32_t *order, int64_t cnt,
                         GroupBufs gb, int nkeys, const int32_t *cells, int P, const GridDims &g, int r, int shift,
                         unsigned long long *bestkey, unsigned long long *work, unsigned long long *boxsum,
-                        hipStream_t s);
+                        hipStream_t s, const LocalCollect *collect = nullptr);
 // mode 0: zero the keys of the listed voxels (all if list is null); mode 1:
 // unpack them into best_s / best_j (-inf / -1 where no candidate).
 void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys, float *best_s, int32_t *best_j,

@@ -355,6 +355,7 @@ static mrf_status net_forward_bf16_split(mrf_net_s *net, const mrf_dict_s *D, co
 
 bool learned_split_rows_only(const mrf_dict_s *D, const mrf_match_opts *o, const int32_t *warm, bool cells_given) {
   if (!D || !o || o->method != MRF_LEARNED || o->precision != MRF_BF16X3 || warm) return false;
+  if (o->certify_local) return false;  // the certificate rescores on the FP32 rows
   if (D->has_tree && o->eps >= 0.f) return false;  // the cover-tree fallback reads the FP32 rows
   return cells_given || (o->net && net_split_ok(o->net, D));
 }
@@ -705,6 +706,13 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   int64_t nfb = 0;
   bool tree_ran = false;
   if (fallback_out) launch_zero(fallback_out, n * 4, s);
+  const bool cert = o->certify_local != 0;
+  int32_t *fbflag = nullptr;  // certified: the exhaustive fallbacks, for the rescan
+  if (cert) {
+    TRY(grow(D->lc_fb, (size_t)n * 4));
+    fbflag = D->lc_fb.as<int32_t>();
+    launch_zero(fbflag, n * 4, s);
+  }
   if (st) HIP_TRY(hipEventRecord(ev.c, s));
   bool nfb_on_device = false;  // the fallback count stayed on the device (read back only for stats)
   unsigned int *count = cntw;  // cleared by the preparation kernel
@@ -727,6 +735,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
       launch_scatter_best(la, n, D->part_s.as<float>(), D->part_j.as<int>(), 1, D->best_s.as<float>(),
                           D->best_j.as<int32_t>(), s, count, (int)(D->d_pad / 256));
       if (fallback_out) launch_mark(la, n, fallback_out, s, count);
+      if (fbflag) launch_mark(la, n, fbflag, s, count);
       LAUNCH_CHECK("fallback (sized on the device)");
       nfb_on_device = true;
     }
@@ -760,6 +769,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
       launch_scatter_best(la, nfb, D->fb_s.as<float>(), D->fb_j.as<int>(), 1, D->best_s.as<float>(),
                           D->best_j.as<int32_t>(), s);
       if (fallback_out) launch_mark(la, nfb, fallback_out, s);
+      if (fbflag) launch_mark(la, nfb, fbflag, s);
       LAUNCH_CHECK("fallback (cover tree)");
     } else if (nfb > 0) {
       const int64_t cnt_pad = round_up(nfb, kRowPad);
@@ -789,18 +799,67 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
       launch_scatter_best(la, nfb, D->part_s.as<float>(), D->part_j.as<int>(), splits,
                           D->best_s.as<float>(), D->best_j.as<int32_t>(), s);
       if (fallback_out) launch_mark(la, nfb, fallback_out, s);
+      if (fbflag) launch_mark(la, nfb, fbflag, s);
       LAUNCH_CHECK("fallback");
     }
   }
   if (st) HIP_TRY(hipEventRecord(ev.d, s));
-  launch_merge_argmax(D->best_s.as<float>(), D->best_j.as<int>(), 1, n, D->d, D->znorm.as<float>(), warm,
-                      D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr, params_out,
-                      D->gamma.as<float>(), s);
-  LAUNCH_CHECK("merge");
+  if (cert) {
+    // Certified local search: the answer's exact score b, every box atom
+    // whose local-pass score reaches b minus the pass's error bound (a second
+    // pass over every voxel's final box, grouped afresh as the re-centring
+    // moved the cells), all of them and the warm atom rescored exactly;
+    // overflowing voxels and the exhaustive fallbacks go to the rescan of the
+    // exhaustive certificate (FP32 collect, exact rescore, full exact scan).
+    TRY(grow(D->cert, 64));
+    TRY(grow(D->cert_list, (size_t)n * 4));
+    TRY(grow(D->cert_thr, (size_t)n * 4));
+    TRY(grow(D->cert_ccount, (size_t)n * 4));
+    TRY(grow(D->cert_scan, (size_t)n * 4));
+    TRY(grow(D->cert_cand, (size_t)n * kCertCap * 4));
+    TRY(grow(D->lc_thr, (size_t)n * 4));
+    TRY(grow(D->lc_count, (size_t)n * 4));
+    TRY(grow(D->lc_cand, (size_t)n * kCertCap * 4));
+    TRY(grow(D->lc_bex, (size_t)n * 8));
+    TRY(grow(D->lc_bjx, (size_t)n * 4));
+    launch_zero(D->cert.p, 64, s);
+    unsigned int *cq = D->cert.as<unsigned int>();
+    const CertQueue q{cq, D->cert_list.as<int32_t>(), D->cert_thr.as<float>(), D->cert_ccount.as<unsigned int>(),
+                      cq + 1, D->cert_scan.as<int32_t>(), reinterpret_cast<unsigned long long *>(cq + 2)};
+    const CertOut out{D->znorm.as<float>(), warm, D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx,
+                      pd, corr, params_out, D->gamma.as<float>()};
+    const float cE = cert_coeff(o->precision, D->K), cE32 = cert_coeff(MRF_FP32, D->K);
+    launch_local_line(D->best_s.as<float>(), D->best_j.as<int32_t>(), fbflag, n, D->d, D->zp.as<float>(),
+                      D->dhat.as<float>(), D->Kp, D->K, cE, cE32, kCertAbs, out, D->lc_thr.as<float>(),
+                      D->lc_count.as<unsigned int>(), D->lc_bex.as<double>(), D->lc_bjx.as<int32_t>(), q, s);
+    LAUNCH_CHECK("local certificate line");
+    launch_iota(lc, n, s);
+    launch_group(lc, n, cells, P, shift, g, D->keys.as<int32_t>(), gb, lb, s, nullptr, false);
+    const LocalCollect lcol{D->lc_thr.as<float>(), D->lc_count.as<unsigned int>(), D->lc_cand.as<int32_t>(),
+                            kCertCap};
+    launch_local_score(Dop, Zop, pitch, x3, lb, n, gb, nkeys, cells, P, g, r, shift, nullptr, nullptr, nullptr, s,
+                       &lcol);
+    LAUNCH_CHECK("local certificate collect");
+    launch_rescore_local(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n,
+                         D->lc_count.as<unsigned int>(), D->lc_cand.as<int32_t>(), kCertCap, D->lc_bex.as<double>(),
+                         D->lc_bjx.as<int32_t>(), warm, fbflag, cE32, kCertAbs, out, q, s);
+    launch_collect_f32_dev(D->dhat.as<float>(), D->zp.as<float>(), q.list, D->d, D->d_pad, n, q.count, D->Kp, q.thr,
+                           q.ccount, D->cert_cand.as<int32_t>(), kCertCap, s);
+    launch_rescore_collected(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n, q,
+                             D->cert_cand.as<int32_t>(), kCertCap, out, s);
+    launch_scan_exact(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n, q, out, s);
+    LAUNCH_CHECK("local certificate rescore");
+  } else {
+    launch_merge_argmax(D->best_s.as<float>(), D->best_j.as<int>(), 1, n, D->d, D->znorm.as<float>(), warm,
+                        D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr, params_out,
+                        D->gamma.as<float>(), s);
+    LAUNCH_CHECK("merge");
+  }
   if (st) {
     unsigned long long wk[2] = {0, 0}, ev_count = 0;
-    unsigned int rc[16] = {0}, dev_nfb = 0;
+    unsigned int rc[16] = {0}, dev_nfb = 0, cc[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(wk, work, 16, hipMemcpyDeviceToHost, s));
+    if (cert) HIP_TRY(hipMemcpyAsync(cc, D->cert.p, 16, hipMemcpyDeviceToHost, s));
     if (nfb_on_device) HIP_TRY(hipMemcpyAsync(&dev_nfb, count, 4, hipMemcpyDeviceToHost, s));
     if (o->recentre > 0) HIP_TRY(hipMemcpyAsync(rc, rcount, 4 * o->recentre, hipMemcpyDeviceToHost, s));
     if (tree_ran) HIP_TRY(hipMemcpyAsync(&ev_count, D->ts_evals.p, 8, hipMemcpyDeviceToHost, s));
@@ -812,6 +871,11 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     st->local_atoms = (int64_t)wk[0];
     st->first_box_atoms = (int64_t)wk[1];
     st->distance_evals = (int64_t)ev_count;
+    if (cert) {
+      st->cert_rescanned = cc[0];
+      st->cert_scanned = cc[1];
+      st->cert_rescored = (int64_t)(cc[2] | ((unsigned long long)cc[3] << 32));
+    }
     HIP_TRY(hipEventElapsedTime(&st->search_ms, ev.a, ev.b));
     HIP_TRY(hipEventElapsedTime(&st->score_ms, e_ls0, e_ls1));
     HIP_TRY(hipEventElapsedTime(&st->fallback_ms, ev.c, ev.d));

@@ -62,7 +62,8 @@ class MatchOpts(ctypes.Structure):
                 ("net", ctypes.c_void_p), ("box_radius", ctypes.c_int32),
                 ("fallback_corr", ctypes.c_float), ("recentre", ctypes.c_int32),
                 ("eps", ctypes.c_float), ("tree_capacity", ctypes.c_int32),
-                ("pd_phase", ctypes.c_void_p), ("no_certificate", ctypes.c_int32)]
+                ("pd_phase", ctypes.c_void_p), ("no_certificate", ctypes.c_int32),
+                ("certify_local", ctypes.c_int32)]
 
 
 class MatchStats(ctypes.Structure):
@@ -351,7 +352,7 @@ def mrf_dict_copy_atoms(D: Dictionary, precision="fp32", stream=None):
 
 
 def match_opts(precision="fp32", topk=8, atom_splits=0, net=None, box_radius=3, fallback_corr=0.98,
-               recentre=0, eps=None, tree_capacity=0, certify=True) -> MatchOpts:
+               recentre=0, eps=None, tree_capacity=0, certify=True, certify_local=False) -> MatchOpts:
     # a network selects the learned path (a given eps then sends its fallback
     # voxels to the dictionary's cover tree, None keeps the exhaustive
     # fallback); eps alone selects the cover tree
@@ -363,18 +364,21 @@ def match_opts(precision="fp32", topk=8, atom_splits=0, net=None, box_radius=3, 
         e = float(eps or 0.0)
     return MatchOpts(method, PRECISION[precision], int(topk), int(atom_splits),
                      None if net is None else net.handle, int(box_radius), float(fallback_corr),
-                     int(recentre), e, int(tree_capacity), None, 0 if certify else 1)
+                     int(recentre), e, int(tree_capacity), None, 0 if certify else 1, 1 if certify_local else 0)
 
 
 # --------------------------------------------------------------------------- matched filter
 def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp32", topk=8,
               atom_splits=0, warm_idx=None, want_pd=True, want_corr=True, want_X=False,
               want_params=False, stats=False, out=None, stream=None, net=None, box_radius=3,
-              fallback_corr=0.98, recentre=0, eps=None, tree_capacity=0, want_pd_phase=False, certify=True):
+              fallback_corr=0.98, recentre=0, eps=None, tree_capacity=0, want_pd_phase=False, certify=True,
+              certify_local=False):
     """Matched filter of the voxels in Z (complex64 CUDA tensor, [n][L] for
     layout 'voxel', [S][L][...] for 'frame').  Returns a dict of CUDA tensors
     (idx, pd, corr, X, params, pd_phase) and, with stats=True, a MatchStats.
-    certify=False skips the exhaustive filter's exactness certificate."""
+    certify=False skips the exhaustive filter's exactness certificate;
+    certify_local=True makes the learned path's local search exact (FP64
+    argmax over each voxel's box and warm atom)."""
     torch = _torch()
     if layout == "voxel":
         n = Z.shape[0]
@@ -396,7 +400,7 @@ def mrf_match(D: Dictionary, Z, layout="voxel", slice_voxels=None, precision="fp
     if want_params and "params" not in o:
         o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
     opts = match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre, eps,
-                      tree_capacity, certify)
+                      tree_capacity, certify, certify_local)
     if want_pd_phase:
         if "pd_phase" not in o:
             o["pd_phase"] = torch.empty(n, dtype=torch.float32, device=dev)
@@ -434,9 +438,10 @@ def mrf_match_noalloc(D: Dictionary, Z, out, layout="voxel", slice_voxels=None, 
 
 def mrf_match_local(D: Dictionary, Z, cells, layout="voxel", slice_voxels=None, box_radius=3,
                     fallback_corr=0.98, recentre=0, warm_idx=None, want_X=False, want_params=False,
-                    stats=False, stream=None, precision="fp32"):
+                    stats=False, stream=None, precision="fp32", certify_local=False):
     """Local matched filter around given proposal cells (int32 CUDA tensor
-    [n][nparam], modified in place by re-centring)."""
+    [n][nparam], modified in place by re-centring); certify_local=True makes
+    it exact (FP64 argmax over each box and warm atom)."""
     torch = _torch()
     if layout == "voxel":
         n, zl, sv = Z.shape[0], MRF_VOXEL_MAJOR, 0
@@ -452,7 +457,8 @@ def mrf_match_local(D: Dictionary, Z, cells, layout="voxel", slice_voxels=None, 
         o["X"] = torch.empty_like(Z)
     if want_params:
         o["params"] = torch.empty((n, D.nparam), dtype=torch.float32, device=dev)
-    opts = match_opts(precision, 8, 0, None, box_radius, fallback_corr, recentre, None, 0)
+    opts = match_opts(precision, 8, 0, None, box_radius, fallback_corr, recentre, None, 0,
+                      certify_local=certify_local)
     st = MatchStats() if stats else None
     _check(lib().mrf_match_local(D.handle, ctypes.byref(opts), n, _dev(Z, torch.complex64), zl, sv,
                                  _dev(cells, torch.int32), _dev(warm_idx, torch.int32), _dev(o["idx"]), _dev(o["pd"]), _dev(o["corr"]),

@@ -219,6 +219,65 @@ def test_local_search_vs_oracle(m, small_dict, recentre, precision):
     assert gidx[5] == 0 and host(out["pd"])[5] == 0.0
 
 
+@pytest.mark.parametrize("recentre", [0, 1])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_certified_local_search_vs_oracle(m, small_dict, recentre, precision):
+    """certify_local: the answer is the exact (FP64) argmax over the box and
+    the warm atom, so it equals the oracle's wherever the two take the same
+    box and the same fallback decision, up to ties of the FP32 normalised
+    atoms (gap < 1e-6 in normalised correlation); fallbacks are the exact
+    exhaustive argmax.  Warm indices: the exact answer for a third of the
+    voxels, random atoms for another third."""
+    banner(f"certified local search vs oracle recentre={recentre} precision={precision}")
+    Dd = small_dict
+    D = m.Dictionary(Dd.atoms, Dd.params, grid_dims=Dd.grid_dims)
+    n = 1500
+    Z, j, pd, snr = workloads.random_voxels(Dd, n, seed=41, snr_db_range=(5.0, 40.0))
+    Z = c64(Z)
+    Zc = Z.astype(np.complex128)
+    ex = mf.exact_mf(Zc, Dd.atoms)
+    sub = grids.grid_sub(j, Dd.grid_dims)
+    shift = np.stack([rng.randint(41, f"sh{p}", n, 9) - 4 for p in range(3)], axis=1)
+    cells = np.clip(sub + shift, 0, np.array(Dd.grid_dims) - 1).astype(np.int32)
+    third = np.arange(n) % 3
+    warm = np.where(third == 0, ex["idx"], np.where(third == 1, rng.randint(41, "w", n, Dd.d), -1)).astype(np.int32)
+    Z[7] = 0.0
+    Zc[7] = 0.0
+    out = m.mrf_match_local(D, dev(Z), dev(cells), box_radius=3, fallback_corr=0.98, recentre=recentre,
+                            warm_idx=dev(warm), stats=True, precision=precision, certify_local=True)
+    st = out["stats"]
+    ref = local.local_match(Zc, Dd.atoms, Dd.grid_dims, cells, r=3, threshold=0.98, recentre=recentre,
+                            warm=np.where(warm >= 0, warm, -1))
+    gidx = host(out["idx"]).astype(np.int64)
+    fb = host(out["fallback"]).astype(bool)
+    nz = np.arange(n) != 7
+    diff = (gidx != ref["idx"]) & nz
+    nrm = np.linalg.norm(Dd.atoms, axis=1)
+    zn = np.linalg.norm(Zc, axis=1)
+    gaps = []
+    for v in np.flatnonzero(diff):
+        cg = np.real(np.vdot(Dd.atoms[gidx[v]], Zc[v])) / nrm[gidx[v]] / zn[v]
+        cr = np.real(np.vdot(Dd.atoms[ref["idx"][v]], Zc[v])) / nrm[ref["idx"][v]] / zn[v]
+        if fb[v] != ref["fallback"][v]:
+            assert abs(max(cg, cr) - 0.98) < 1e-4, (v, cg, cr)  # one side fell back at the threshold
+            continue
+        gaps.append(abs(cg - cr))
+        assert abs(cg - cr) < 1e-6, (v, cg, cr)
+    print(f"certified {precision} recentre={recentre}: {diff.sum()} differences (gaps {np.round(gaps, 9)[:6]}), "
+          f"fallbacks {fb.sum()}, rescored {st.cert_rescored} ({st.cert_rescored / n:.2f} per voxel), "
+          f"rescanned {st.cert_rescanned}, scanned {st.cert_scanned}")
+    assert diff.sum() <= max(2, n // 500)
+    # the exhaustive fallbacks are the exact argmax
+    f = fb & nz
+    np.testing.assert_array_equal(gidx[f & ~diff], ex["idx"][f & ~diff])
+    assert st.cert_rescanned >= int((fb & nz).sum())
+    assert gidx[7] == (warm[7] if 0 <= warm[7] < Dd.d else 0) and host(out["pd"])[7] == 0.0  # zero voxel
+    # PD and corr from the exact score of the returned atom
+    keep = nz & ~diff & ~fb
+    cr = np.real(np.sum(np.conj(Dd.atoms[gidx[keep]]) * Zc[keep], axis=1)) / nrm[gidx[keep]]
+    np.testing.assert_allclose(host(out["corr"])[keep], cr / zn[keep], rtol=1e-6, atol=1e-7)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_local_search_warm_start_vs_oracle(m, small_dict, precision):
     """The warm atom competes with the box's best (non-expansive safeguard):
