@@ -687,13 +687,13 @@ def mrf_op_adjoint(A: Operator, R, apply_dcf=True, stream=None):
 # --------------------------------------------------------------------------- projected gradient
 def mrf_ipg_step(D: Dictionary, A: Operator, Y, X_in, mu, idx_in=None, precision="fp32", topk=8,
                  atom_splits=0, stats=True, stream=None, net=None, box_radius=3, fallback_corr=0.98,
-                 recentre=0, eps=None, tree_capacity=0, certify=True):
+                 recentre=0, eps=None, tree_capacity=0, certify=True, certify_local=False):
     torch = _torch()
     X_out = torch.empty_like(X_in)
     idx = torch.empty(A.n, dtype=torch.int32, device="cuda")
     pd = torch.empty(A.n, dtype=torch.float32, device="cuda")
     opts = match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre, eps, tree_capacity,
-                      certify)
+                      certify, certify_local)
     st = StepStats() if stats else None
     _check(lib().mrf_ipg_step(D.handle, ctypes.byref(A.c), _dev(Y), _dev(X_in), _dev(X_out),
                               _dev(idx_in), _dev(idx), _dev(pd), float(mu), ctypes.byref(opts),
@@ -704,7 +704,7 @@ def mrf_ipg_step(D: Dictionary, A: Operator, Y, X_in, mu, idx_in=None, precision
 def mrf_ipg_solve(D: Dictionary, A: Operator, Y, X0=None, mu0=1.0, zeta=2.0, adaptive=True,
                   max_iter=50, rel_tol=1e-6, max_shrinks=30, kappa=False, precision="fp32",
                   topk=8, atom_splits=0, want_params=True, stream=None, net=None, box_radius=3,
-                  fallback_corr=0.98, recentre=0, eps=None, tree_capacity=0, certify=True):
+                  fallback_corr=0.98, recentre=0, eps=None, tree_capacity=0, certify=True, certify_local=False):
     """Algorithm 2.  The projection is exhaustive (default), learned (net
     given: proposal + local search + fallback, warm-started by the previous
     iterate's atoms) or the cover tree (eps given)."""
@@ -717,7 +717,7 @@ def mrf_ipg_solve(D: Dictionary, A: Operator, Y, X0=None, mu0=1.0, zeta=2.0, ada
     o = SolveOpts(float(mu0), float(zeta), int(bool(adaptive)), int(max_iter), float(rel_tol),
                   int(max_shrinks), int(bool(kappa)),
                   match_opts(precision, topk, atom_splits, net, box_radius, fallback_corr, recentre, eps,
-                             tree_capacity, certify))
+                             tree_capacity, certify, certify_local))
     cap = int(max_iter)
     f = np.zeros(cap, dtype=np.float64)
     mu = np.zeros(cap, dtype=np.float32)
