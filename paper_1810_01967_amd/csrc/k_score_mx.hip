@@ -20,8 +20,10 @@
 // 512 rows, double-buffered in LDS.  Stages go straight from global memory to
 // LDS (global_load_lds_dwordx4: a wave's 64 lanes write 16 bytes each at the
 // wave's LDS base + 16 x lane, i.e. eight 128-byte rows), with the eight
-// 16-byte chunks of row r stored at slot chunk ^ (r % 8), so 32 lanes reading
-// one chunk of 32 consecutive rows hit distinct banks.  Work items are (voxel
+// 16-byte chunks of row r stored at slot chunk ^ s(r), s(r) = (r / 2 % 8) ^
+// 4 (r % 2): the 16 lanes of one LDS access reading one chunk of 16
+// consecutive rows hit 16 distinct 16-byte bank groups (and any 8 of them
+// 8 distinct slots of a 128-byte line).  Work items are (voxel
 // tile, atom split) pairs; the splits of a voxel tile run on one XCD (item w
 // on XCD w % 8), so its blocks share the voxel tile and, across the voxel
 // tiles in flight, the atom tiles through that XCD's L2.
@@ -53,45 +55,23 @@ enum { E_BF16 = 0, E_FP8 = 1, E_X3 = 2 };
 #endif
 constexpr int M_BA = 256, M_BV = 256;
 constexpr int M_WA = MRF_MX_WA, M_WV = MRF_MX_WV, M_NT = 64 * M_WA * M_WV;
-// stage rows of MRF_MX_ROWB bytes (128 or 64) in MRF_MX_NB LDS buffers,
-// NB - 1 stages in flight (tuning constants)
-#ifndef MRF_MX_ROWB
-#define MRF_MX_ROWB 128
-#endif
-#ifndef MRF_MX_NB
-#define MRF_MX_NB 2
-#endif
-constexpr int M_ROWB = MRF_MX_ROWB;                    // bytes of a row per stage
-constexpr int M_NB = MRF_MX_NB;
-constexpr int M_CPR = M_ROWB / 16;                     // 16-byte chunks per stage row
-constexpr int M_RPL = 1024 / M_ROWB;                   // stage rows per 64-lane load
+constexpr int M_ROWB = 128;                            // bytes of a row per stage
 constexpr int M_STAGE = (M_BA + M_BV) * M_ROWB;        // bytes per stage buffer
-static_assert(M_ROWB == 128 || M_ROWB == 64, "stage row");
 constexpr int M_AROWS = M_BA / M_WA, M_VCOLS = M_BV / M_WV;  // per wave
 constexpr int M_MA = M_AROWS / 32;                     // 32-atom MFMA tiles per wave
 constexpr int M_NV = M_VCOLS / 32;                     // 32-voxel MFMA tiles per wave
 constexpr int M_NW = M_NT / 64;                        // waves
-constexpr int M_DI = (M_BA + M_BV) / M_RPL / M_NW;    // loads per wave and stage
-constexpr int M_DIA = M_BA / M_RPL / M_NW;             // of which atom rows
+constexpr int M_DI = (M_BA + M_BV) / 8 / M_NW;         // 8-row loads per wave and stage
+constexpr int M_DIA = M_BA / 8 / M_NW;                 // of which atom rows
 constexpr int M_DIZ = M_DI - M_DIA;
 static_assert(M_MA >= 1 && M_NV >= 1, "block shape");
-static_assert(M_DI * M_NW * M_RPL == M_BA + M_BV && (M_BA / M_RPL) % M_NW == 0, "loader shape");
-static_assert(M_NB * M_STAGE + 2048 <= 160 * 1024 && M_NB >= 2 && M_NB <= 4, "LDS");
+static_assert(M_DI * M_NW * 8 == M_BA + M_BV && (M_BA / 8) % M_NW == 0 && M_NW % 2 == 0, "loader shape");
+static_assert(2 * M_STAGE <= 160 * 1024, "LDS");
 static_assert(M_BV == kX3VoxTile, "split-BF16 voxel tiles (gathered rows, device-side splits)");
-static_assert(M_WA * kCertK * M_BV * 8 <= M_NB * M_STAGE, "LDS exchange of the candidate lists");
+static_assert(M_WA * kCertK * M_BV * 8 <= 2 * M_STAGE, "LDS exchange of the candidate lists");
 
-// LDS slot of the 16-byte chunk c of stage row r: c XOR a function of the
-// row's low bits, so 32 lanes reading one chunk of 32 consecutive rows hit
-// distinct banks (128-byte rows: r % 8; 64-byte rows: r / 2 % 4)
-__device__ __forceinline__ int swz(int r) { return M_ROWB == 128 ? (r & 7) : ((r >> 1) & 3); }
-__device__ __forceinline__ int chunk_at(int c, int r) { return (c ^ swz(r)) * 16; }
-
-// vmcnt(n) with the other counters left alone (gfx9 encoding)
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
+// byte offset of the 16-byte chunk c in stage row r (only r % 16 matters)
+__device__ __forceinline__ int chunk_at(int c, int r) { return (c ^ ((r >> 1) & 7) ^ ((r & 1) << 2)) * 16; }
 
 }  // namespace
 
@@ -138,23 +118,17 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
   }
   const int64_t nwork = (int64_t)((nvt + 7) / 8 * 8) * nsplit;
 
-  __shared__ __attribute__((aligned(16))) uint8_t S[M_NB * M_STAGE];
+  __shared__ __attribute__((aligned(16))) uint8_t S[2 * M_STAGE];
   __shared__ __attribute__((aligned(16))) float SCL[F8 ? 2 : 1][F8 ? M_BA : 4];  // FP8: atom scales by tile parity
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wa = wave / M_WV, wv = wave % M_WV;
-  const int h = lane >> 5, l32 = lane & 31, rm = l32;  // every row this lane reads is l32 modulo 32
-  // loader: load i of wave w covers stage rows R = (i M_NW + w) M_RPL + lane /
-  // M_CPR (atom rows below M_BA, then voxel rows: M_NW divides M_BA / M_RPL);
-  // the lane fetches the chunk that belongs in its slot lane % M_CPR.  Split
-  // rows with 64-byte stages: stage st holds k 16 (st % 2) .. + 15 of the
-  // 32-value chunk st / 2, i.e. chunks 0-1 its hi values, 2-3 its lo values.
-  const int drow = lane / M_CPR;
-  const int dc = (lane % M_CPR) ^ swz(drow);
-  const int dchunk = (X3 && M_ROWB == 64) ? (dc >> 1) * 64 + (dc & 1) * 16 : dc * 16;
-  auto stage_off = [&](int st) -> int64_t {
-    return (X3 && M_ROWB == 64) ? (int64_t)(st >> 1) * 128 + (st & 1) * 32 : (int64_t)st * M_ROWB;
-  };
+  const int h = lane >> 5, l32 = lane & 31, rm = l32 & 15;  // every row this lane reads is rm modulo 16
+  // loader: load i of wave w covers stage rows R = (i M_NW + w) 8 + lane / 8
+  // (atom rows below M_BA, then voxel rows: M_NW divides M_BA / 8), R % 16 =
+  // 8 (w % 2) + lane / 8 as M_NW is even; the lane fetches the chunk that
+  // belongs in its slot lane % 8
+  const int drow = lane >> 3, dchunk = chunk_at(lane & 7, 8 * (wave & 1) + drow);
 
   for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int xcd = (int)(w & 7);
@@ -170,12 +144,12 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
     // loads i < M_DIA fetch atom rows, the rest voxel rows; row R of load i is
     // i M_NW 8 rows after the wave's first, a uniform step (voxel rows of a
     // rescan through the row map; rows past the count read the first listed row)
-    const uint8_t *a0 = g.D + (int64_t)(tb * M_BA + wave * M_RPL + drow) * g.row + dchunk;
-    const int64_t istep = (int64_t)M_NW * M_RPL * g.row;
+    const uint8_t *a0 = g.D + (int64_t)(tb * M_BA + wave * 8 + drow) * g.row + dchunk;
+    const int64_t istep = (int64_t)M_NW * 8 * g.row;
     const uint8_t *zr[RMAP ? M_DIZ : 1];
 #pragma unroll
     for (int i = 0; i < (RMAP ? M_DIZ : 1); ++i) {
-      int64_t r = v0 + i * M_NW * M_RPL + wave * M_RPL + drow;
+      int64_t r = v0 + i * M_NW * 8 + wave * 8 + drow;
       if (RMAP) r = g.rowmap[r < nvox ? r : 0];
       zr[i] = g.Z + r * g.row + dchunk;
     }
@@ -186,15 +160,14 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
     int stile = -1;
     auto dload = [&](int q, int buf) {
       const int tq = q / g.nstage;
-      const int64_t soff = stage_off(q - tq * g.nstage);
+      const int64_t soff = (q - tq * g.nstage) * M_ROWB;
       const int64_t aoff = (int64_t)tq * M_BA * g.row + soff;
 #pragma unroll
       for (int i = 0; i < M_DI; ++i) {
         const uint8_t *src = i < M_DIA ? a0 + i * istep + aoff
                                        : (RMAP ? zr[RMAP ? i - M_DIA : 0] : zr[0] + (i - M_DIA) * istep) + soff;
         __builtin_amdgcn_global_load_lds((const void *)src,
-                                         (lds_void *)(S + buf * M_STAGE + (i * M_NW + wave) * M_RPL * M_ROWB), 16,
-                                         0, 0);
+                                         (lds_void *)(S + buf * M_STAGE + (i * M_NW + wave) * 8 * M_ROWB), 16, 0, 0);
       }
       if (F8 && wave == 0 && q == tq * g.nstage) {
         stile = tb + tq;
@@ -234,25 +207,22 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
       if (MODE == SC_COLLECT && v < nvox) vthr[b] = g.thr[v];
     }
 
-    // the first M_NB - 1 stages in flight; stage 0 waited for
-#pragma unroll
-    for (int p = 0; p < M_NB - 1; ++p)
-      if (p < nq) dload(p, p);
-    sflush();
-    __builtin_amdgcn_s_waitcnt(0);
+    if (nq > 0) {
+      dload(0, 0);
+      sflush();
+      __builtin_amdgcn_s_waitcnt(0);
+    }
     __syncthreads();
     for (int q = 0; q < nq; ++q) {
-      const int buf = q % M_NB;
-      // stage q + M_NB - 1 into the buffer read at stage q - 1: every wave
-      // finished reading it before the last barrier
-      if (q + M_NB - 1 < nq) dload(q + M_NB - 1, (q + M_NB - 1) % M_NB);
+      const int buf = q & 1;
+      if (q + 1 < nq) dload(q + 1, buf ^ 1);  // every wave finished reading that buffer before the last barrier
       const uint8_t *B = S + buf * M_STAGE;
       const uint8_t *Ab = B + (wa * M_AROWS + l32) * M_ROWB;
       const uint8_t *Zb = B + (M_BA + wv * M_VCOLS + l32) * M_ROWB;
       if constexpr (F8) {
-        // k-steps of 64: the lane supplies 32 bytes (chunks 4 ks + 2 h, + 1)
+        // two k-steps of 64: the lane supplies 32 bytes (chunks 4 ks + 2 h, + 1)
 #pragma unroll
-        for (int ks = 0; ks < M_ROWB / 64; ++ks) {
+        for (int ks = 0; ks < 2; ++ks) {
           const int o0 = chunk_at(4 * ks + 2 * h, rm), o1 = chunk_at(4 * ks + 2 * h + 1, rm);
           i32x8 zf[M_NV];
 #pragma unroll
@@ -273,11 +243,11 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
           }
         }
       } else if constexpr (X3) {
-        // k-steps of 16: the lane supplies 8 values of each plane (hi chunk
-        // 2 ks + h, lo chunk M_CPR / 2 + 2 ks + h)
+        // two k-steps of 16: the lane supplies 8 values of each plane (hi
+        // chunk 2 ks + h, lo chunk 4 + 2 ks + h)
 #pragma unroll
-        for (int ks = 0; ks < M_ROWB / 64; ++ks) {
-          const int oh = chunk_at(2 * ks + h, rm), ol = chunk_at(M_CPR / 2 + 2 * ks + h, rm);
+        for (int ks = 0; ks < 2; ++ks) {
+          const int oh = chunk_at(2 * ks + h, rm), ol = chunk_at(4 + 2 * ks + h, rm);
           bf16x8 zh[M_NV], zl[M_NV];
 #pragma unroll
           for (int nv = 0; nv < M_NV; ++nv) {
@@ -297,9 +267,9 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
           }
         }
       } else {
-        // k-steps of 16: the lane supplies 8 BF16 (chunk 2 ks + h)
+        // four k-steps of 16: the lane supplies 8 BF16 (chunk 2 ks + h)
 #pragma unroll
-        for (int ks = 0; ks < M_ROWB / 32; ++ks) {
+        for (int ks = 0; ks < 4; ++ks) {
           const int ko = chunk_at(2 * ks + h, rm);
           bf16x8 zf[M_NV];
 #pragma unroll
@@ -355,15 +325,7 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
             for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
       }
       sflush();
-      // this wave's loads of stage q + 1 are in LDS: the loads of the later
-      // stages issued so far may stay in flight
-      const int later = min(nq - 1, q + M_NB - 1) - (q + 1);
-      if (M_NB >= 4 && later >= 2)
-        wait_vm<(M_NB >= 4 ? 2 : 0) * M_DI>();
-      else if (M_NB >= 3 && later >= 1)
-        wait_vm<M_DI>();
-      else
-        wait_vm<0>();
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next stage are in LDS
       __syncthreads();
     }
     if (MODE == SC_COLLECT) continue;  // the candidates are already written
@@ -454,7 +416,7 @@ MxArgs mx_args(int e, const void *D, const void *Z, int row_bytes, int d, int64_
   a.D = static_cast<const uint8_t *>(D);
   a.Z = static_cast<const uint8_t *>(Z);
   a.row = row_bytes;
-  a.nstage = row_bytes / M_ROWB;  // split rows: 4 Kx bytes, Kx a multiple of 32
+  a.nstage = row_bytes / M_ROWB;
   a.d = d;
   a.ntiles = (int)(d_pad / M_BA);
   a.n = n;
