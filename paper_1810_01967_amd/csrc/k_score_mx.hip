@@ -18,8 +18,8 @@
 // A rows, voxels the B columns, so a lane folds one voxel column per tile and
 // atoms reach it in increasing order).  A stage is 128 bytes of each of the
 // 512 rows, double-buffered in LDS.  Stages go straight from global memory to
-// LDS (global_load_lds_dwordx4: a wave's 64 lanes write 16 bytes each at the
-// wave's LDS base + 16 x lane, i.e. eight 128-byte rows), with the eight
+// LDS (buffer_load_dwordx4 ... lds: a wave's 64 lanes write 16 bytes each at
+// the wave's LDS base + 16 x lane, i.e. eight 128-byte rows), with the eight
 // 16-byte chunks of row r stored at slot chunk ^ s(r), s(r) = (r / 2 % 8) ^
 // 4 (r % 2): the 16 lanes of one LDS access reading one chunk of 16
 // consecutive rows hit 16 distinct 16-byte bank groups (and any 8 of them
@@ -30,6 +30,8 @@
 #include "k_split.h"
 #include "k_topk.h"
 #include "mrf_internal.h"
+
+#include <type_traits>
 
 namespace mrf {
 
@@ -66,7 +68,7 @@ constexpr int M_DIA = M_BA / 8 / M_NW;                 // of which atom rows
 constexpr int M_DIZ = M_DI - M_DIA;
 static_assert(M_MA >= 1 && M_NV >= 1, "block shape");
 static_assert(M_DI * M_NW * 8 == M_BA + M_BV && (M_BA / 8) % M_NW == 0 && M_NW % 2 == 0, "loader shape");
-static_assert(2 * M_STAGE <= 160 * 1024, "LDS");
+static_assert(2 * M_STAGE + 2 * M_BA * 4 <= 160 * 1024, "LDS");
 static_assert(M_BV == kX3VoxTile, "split-BF16 voxel tiles (gathered rows, device-side splits)");
 static_assert(M_WA * kCertK * M_BV * 8 <= 2 * M_STAGE, "LDS exchange of the candidate lists");
 
@@ -118,10 +120,12 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
   }
   const int64_t nwork = (int64_t)((nvt + 7) / 8 * 8) * nsplit;
 
-  __shared__ __attribute__((aligned(16))) uint8_t S[2 * M_STAGE];
-  __shared__ __attribute__((aligned(16))) float SCL[F8 ? 2 : 1][F8 ? M_BA : 4];  // FP8: atom scales by tile parity
+  // two stage buffers, then (FP8) the atom scales of two tiles by tile parity
+  __shared__ __attribute__((aligned(16))) uint8_t S[2 * M_STAGE + (F8 ? 2 * M_BA * 4 : 0)];
+  float(*SCL)[M_BA] = reinterpret_cast<float(*)[M_BA]>(S + 2 * M_STAGE);
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index made wave-uniform for the compiler (scalar branches on it)
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wa = wave / M_WV, wv = wave % M_WV;
   const int h = lane >> 5, l32 = lane & 31, rm = l32 & 15;  // every row this lane reads is rm modulo 16
   // loader: load i of wave w covers stage rows R = (i M_NW + w) 8 + lane / 8
@@ -144,8 +148,6 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
     // loads i < M_DIA fetch atom rows, the rest voxel rows; row R of load i is
     // i M_NW 8 rows after the wave's first, a uniform step (voxel rows of a
     // rescan through the row map; rows past the count read the first listed row)
-    const uint8_t *a0 = g.D + (int64_t)(tb * M_BA + wave * 8 + drow) * g.row + dchunk;
-    const int64_t istep = (int64_t)M_NW * 8 * g.row;
     const uint8_t *zr[RMAP ? M_DIZ : 1];
 #pragma unroll
     for (int i = 0; i < (RMAP ? M_DIZ : 1); ++i) {
@@ -153,32 +155,39 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
       if (RMAP) r = g.rowmap[r < nvox ? r : 0];
       zr[i] = g.Z + r * g.row + dchunk;
     }
-    // FP8: a tile's 256 atom scales go to LDS through registers of wave 0
-    // (loaded after the stage's DMA loads and stored at the end of the stage,
-    // where those are waited for anyway), in the slot of the tile's parity
-    u32x4 sreg = {0u, 0u, 0u, 0u};
-    int stile = -1;
+    // The stage loads go through buffer resources (buffer_load_dwordx4 ...
+    // lds) built per stage on the tile's first row, with 32-bit lane offsets
+    // inside the tile: unlike the flat-segment form, these leave the LDS
+    // counter in order, so the waits for the fragment reads below stay
+    // partial while a stage's loads are in flight.  A rescan's voxel rows
+    // (through the row map, anywhere in Z) keep the flat form.
+    const uint32_t lrow = (uint32_t)((wave * 8 + drow) * g.row + dchunk);
+    const uint32_t lstep = (uint32_t)(M_NW * 8 * g.row);
     auto dload = [&](int q, int buf) {
       const int tq = q / g.nstage;
       const int64_t soff = (q - tq * g.nstage) * M_ROWB;
-      const int64_t aoff = (int64_t)tq * M_BA * g.row + soff;
+      const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(g.D + (int64_t)(tb + tq) * M_BA * g.row + soff), 0, (int)(M_BA * g.row), 0x00020000);
+      const __amdgpu_buffer_rsrc_t rz =
+          __builtin_amdgcn_make_buffer_rsrc((void *)(g.Z + v0 * g.row + soff), 0, (int)(M_BV * g.row), 0x00020000);
 #pragma unroll
       for (int i = 0; i < M_DI; ++i) {
-        const uint8_t *src = i < M_DIA ? a0 + i * istep + aoff
-                                       : (RMAP ? zr[RMAP ? i - M_DIA : 0] : zr[0] + (i - M_DIA) * istep) + soff;
-        __builtin_amdgcn_global_load_lds((const void *)src,
-                                         (lds_void *)(S + buf * M_STAGE + (i * M_NW + wave) * 8 * M_ROWB), 16, 0, 0);
+        lds_void *dst = (lds_void *)(S + buf * M_STAGE + (i * M_NW + wave) * 8 * M_ROWB);
+        if (i < M_DIA)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, dst, 16, lrow + i * lstep, 0, 0, 0);
+        else if constexpr (RMAP)
+          __builtin_amdgcn_global_load_lds((const void *)(zr[RMAP ? i - M_DIA : 0] + soff), dst, 16, 0, 0);
+        else
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rz, dst, 16, lrow + (i - M_DIA) * lstep, 0, 0, 0);
       }
+      // FP8: wave 0 loads a tile's 256 atom scales with its first stage, into
+      // the LDS slot of the tile's parity (that slot's previous tile was
+      // folded before an earlier barrier; the fold of this one follows the
+      // stage-end wait and barrier)
       if (F8 && wave == 0 && q == tq * g.nstage) {
-        stile = tb + tq;
-        sreg = *reinterpret_cast<const u32x4 *>(g.dscale + stile * M_BA + lane * 4);
-      }
-    };
-    // the slot's previous tile was folded before an earlier barrier
-    auto sflush = [&]() {
-      if (F8 && stile >= 0) {
-        *reinterpret_cast<u32x4 *>(&SCL[stile & 1][lane * 4]) = sreg;
-        stile = -1;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(g.dscale + (int64_t)(tb + tq) * M_BA), 0, M_BA * 4, 0x00020000);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)&SCL[(tb + tq) & 1][0], 16, lane * 16, 0, 0, 0);
       }
     };
 
@@ -209,7 +218,6 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
 
     if (nq > 0) {
       dload(0, 0);
-      sflush();
       __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
@@ -219,103 +227,177 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
       const uint8_t *B = S + buf * M_STAGE;
       const uint8_t *Ab = B + (wa * M_AROWS + l32) * M_ROWB;
       const uint8_t *Zb = B + (M_BA + wv * M_VCOLS + l32) * M_ROWB;
+      // The fragments of the next group of products are read from LDS before
+      // the products of the current group issue (scheduling barriers keep
+      // the compiler from sinking the reads next to their use), so a wave's
+      // LDS latency overlaps its own MFMAs.
       if constexpr (F8) {
-        // two k-steps of 64: the lane supplies 32 bytes (chunks 4 ks + 2 h, + 1)
+        // two k-steps of 64: the lane supplies 32 bytes (chunks 4 ks + 2 h,
+        // + 1); groups (ks, ma), A fragments one group ahead, voxel
+        // fragments one k-step ahead
+        i32x8 zf[2][M_NV], af[2];
+        auto rd2 = [&](const uint8_t *base, int ks) {
+          const u32x4 x0 = *reinterpret_cast<const u32x4 *>(base + chunk_at(4 * ks + 2 * h, rm));
+          const u32x4 x1 = *reinterpret_cast<const u32x4 *>(base + chunk_at(4 * ks + 2 * h + 1, rm));
+          return i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+        };
+        auto rdz = [&](int ks) {
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-          const int o0 = chunk_at(4 * ks + 2 * h, rm), o1 = chunk_at(4 * ks + 2 * h + 1, rm);
-          i32x8 zf[M_NV];
+          for (int nv = 0; nv < M_NV; ++nv) zf[ks & 1][nv] = rd2(Zb + nv * 32 * M_ROWB, ks);
+        };
+        rdz(0);
+        af[0] = rd2(Ab, 0);
 #pragma unroll
-          for (int nv = 0; nv < M_NV; ++nv) {
-            const u32x4 x0 = *reinterpret_cast<const u32x4 *>(Zb + nv * 32 * M_ROWB + o0);
-            const u32x4 x1 = *reinterpret_cast<const u32x4 *>(Zb + nv * 32 * M_ROWB + o1);
-            zf[nv] = i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
-          }
+        for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
           for (int ma = 0; ma < M_MA; ++ma) {
-            const u32x4 x0 = *reinterpret_cast<const u32x4 *>(Ab + ma * 32 * M_ROWB + o0);
-            const u32x4 x1 = *reinterpret_cast<const u32x4 *>(Ab + ma * 32 * M_ROWB + o1);
-            const i32x8 af{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+            const int gi = ks * M_MA + ma;
+            if (ma + 1 < M_MA) {
+              af[(gi + 1) & 1] = rd2(Ab + (ma + 1) * 32 * M_ROWB, ks);
+            } else if (ks + 1 < 2) {
+              rdz(ks + 1);
+              af[(gi + 1) & 1] = rd2(Ab, ks + 1);
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int nv = 0; nv < M_NV; ++nv)
-              acc[ma][nv] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af, zf[nv], acc[ma][nv], 0, 0, 0, 0x7F,
-                                                                            0, 0x7F);
+              acc[ma][nv] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[gi & 1], zf[ks & 1][nv], acc[ma][nv], 0,
+                                                                            0, 0, 0x7F, 0, 0x7F);
+            __builtin_amdgcn_sched_barrier(0);
           }
-        }
       } else if constexpr (X3) {
         // two k-steps of 16: the lane supplies 8 values of each plane (hi
-        // chunk 2 ks + h, lo chunk 4 + 2 ks + h)
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
+        // chunk 2 ks + h, lo chunk 4 + 2 ks + h); groups (ks, ma), A
+        // fragments one group ahead, voxel fragments one k-step ahead
+        bf16x8 zh[2][M_NV], zl[2][M_NV], ah[2], al[2];
+        auto rdz = [&](int ks) {
           const int oh = chunk_at(2 * ks + h, rm), ol = chunk_at(4 + 2 * ks + h, rm);
-          bf16x8 zh[M_NV], zl[M_NV];
 #pragma unroll
           for (int nv = 0; nv < M_NV; ++nv) {
-            zh[nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + oh);
-            zl[nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + ol);
+            zh[ks & 1][nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + oh);
+            zl[ks & 1][nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + ol);
           }
+        };
+        auto rda = [&](int ks, int ma, int sl) {
+          ah[sl] = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + chunk_at(2 * ks + h, rm));
+          al[sl] = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + chunk_at(4 + 2 * ks + h, rm));
+        };
+        rdz(0);
+        rda(0, 0, 0);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
           for (int ma = 0; ma < M_MA; ++ma) {
-            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + oh);
-            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + ol);
+            const int gi = ks * M_MA + ma, sl = gi & 1, zs = ks & 1;
+            if (ma + 1 < M_MA) {
+              rda(ks, ma + 1, (gi + 1) & 1);
+            } else if (ks + 1 < 2) {
+              rdz(ks + 1);
+              rda(ks + 1, 0, (gi + 1) & 1);
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int nv = 0; nv < M_NV; ++nv) {
-              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zh[nv], acc[ma][nv], 0, 0, 0);
-              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zl[nv], acc[ma][nv], 0, 0, 0);
-              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, zh[nv], acc[ma][nv], 0, 0, 0);
+              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[sl], zh[zs][nv], acc[ma][nv], 0, 0, 0);
+              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[sl], zl[zs][nv], acc[ma][nv], 0, 0, 0);
+              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[sl], zh[zs][nv], acc[ma][nv], 0, 0, 0);
             }
+            __builtin_amdgcn_sched_barrier(0);
           }
-        }
       } else {
-        // four k-steps of 16: the lane supplies 8 BF16 (chunk 2 ks + h)
+        // four k-steps of 16: the lane supplies 8 BF16 (chunk 2 ks + h); all
+        // fragments one k-step ahead
+        bf16x8 zf[2][M_NV], af[2][M_MA];
+        auto rd = [&](int ks) {
+          const int ko = chunk_at(2 * ks + h, rm);
+#pragma unroll
+          for (int nv = 0; nv < M_NV; ++nv)
+            zf[ks & 1][nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + ko);
+#pragma unroll
+          for (int ma = 0; ma < M_MA; ++ma)
+            af[ks & 1][ma] = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + ko);
+        };
+        rd(0);
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-          const int ko = chunk_at(2 * ks + h, rm);
-          bf16x8 zf[M_NV];
+          if (ks + 1 < 4) rd(ks + 1);
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int nv = 0; nv < M_NV; ++nv) zf[nv] = *reinterpret_cast<const bf16x8 *>(Zb + nv * 32 * M_ROWB + ko);
-#pragma unroll
-          for (int ma = 0; ma < M_MA; ++ma) {
-            const bf16x8 af = *reinterpret_cast<const bf16x8 *>(Ab + ma * 32 * M_ROWB + ko);
+          for (int ma = 0; ma < M_MA; ++ma)
 #pragma unroll
             for (int nv = 0; nv < M_NV; ++nv)
-              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, zf[nv], acc[ma][nv], 0, 0, 0);
-          }
+              acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ks & 1][ma], zf[ks & 1][nv], acc[ma][nv], 0,
+                                                                    0, 0);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
       const int st = q % g.nstage;
       if (st == g.nstage - 1) {
-        // fold this atom tile: M_AROWS atom rows per voxel column and lane
+        // fold this atom tile: M_AROWS atom rows per voxel column and lane,
+        // row jb + ro with ro = 32 ma + 8 (i / 4) + i % 4.  jb is made opaque
+        // here so that the compiler forms the row numbers at the fold instead
+        // of keeping all 64 live across the stage loop, where the products
+        // need the registers for their fragments
         const int tile = tb + q / g.nstage;
         const int abase = tile * M_BA + wa * M_AROWS;
-        const float *scl = &SCL[F8 ? (tile & 1) : 0][wa * M_AROWS];
+        int jb = abase + 4 * h;
+        asm volatile("" : "+v"(jb));
+        const bool full = abase + M_AROWS <= g.d;  // no padding rows in this wave's rows
+        const float *sclh = &SCL[F8 ? (tile & 1) : 0][(F8 ? wa * M_AROWS : 0) + 4 * h];
 #pragma unroll
         for (int nv = 0; nv < M_NV; ++nv) {
-          const int64_t v = v0 + wv * M_VCOLS + nv * 32 + l32;
+          if constexpr (MODE == SC_TOP1) {
+            // the tile's maximum with its position p = 16 ma + i (a constant
+            // per candidate), then one compare with the running maximum:
+            // atoms in increasing order, '>' keeps the lowest index
+            float tbv = -INFINITY;
+            int tp = 0;
+            auto scan = [&](auto chk) {
 #pragma unroll
-          for (int ma = 0; ma < M_MA; ++ma)
-            // the list insertion is long and rare: one copy per tile of the
-            // accumulators, its element picked by the (uniform) loop index
-#pragma unroll(MODE == SC_TOPK ? 1 : 16)
-            for (int i = 0; i < 16; ++i) {
-              const int r = ma * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-              const int j = abase + r;
-              const float sc = F8 ? acc[ma][nv][i] * scl[r] : acc[ma][nv][i];
-              if constexpr (MODE == SC_TOPK) {
-                if (j < g.d && sc > vthr[nv]) {
-                  topk_push_ordered(ls[nv], lj[nv], sc, j);
-                  vthr[nv] = fmaxf(ls[nv][kCertK - 1], ls[nv][0] - win[nv]);
+              for (int ma = 0; ma < M_MA; ++ma)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                  const int ro = ma * 32 + 8 * (i >> 2) + (i & 3);
+                  float sc = F8 ? acc[ma][nv][i] * sclh[ro] : acc[ma][nv][i];
+                  if (decltype(chk)::value && jb + ro >= g.d) sc = -INFINITY;
+                  if (sc > tbv) {
+                    tbv = sc;
+                    tp = ma * 16 + i;
+                  }
                 }
-              } else if constexpr (MODE == SC_COLLECT) {
-                if (j < g.d && v < nvox && sc >= vthr[nv]) {
-                  const unsigned int pos = atomicAdd(&g.count[v], 1u);
-                  if ((int)pos < g.ccap) g.cand[v * g.ccap + pos] = j;
-                }
-              } else if (j < g.d && sc > best[nv]) {  // atoms in increasing order: '>' keeps the lowest index
-                best[nv] = sc;
-                bidx[nv] = j;
-              }
+            };
+            if (full)
+              scan(std::false_type{});
+            else
+              scan(std::true_type{});
+            if (tbv > best[nv]) {
+              best[nv] = tbv;
+              bidx[nv] = jb + (tp >> 4) * 32 + 8 * ((tp >> 2) & 3) + (tp & 3);
             }
+          } else {
+            const int64_t v = v0 + wv * M_VCOLS + nv * 32 + l32;
+#pragma unroll
+            for (int ma = 0; ma < M_MA; ++ma)
+              // the list insertion is long and rare: one copy per tile of the
+              // accumulators, its element picked by the (uniform) loop index
+#pragma unroll(MODE == SC_TOPK ? 1 : 16)
+              for (int i = 0; i < 16; ++i) {
+                const int ro = ma * 32 + 8 * (i >> 2) + (i & 3);
+                const int j = jb + ro;
+                const float sc = F8 ? acc[ma][nv][i] * sclh[ro] : acc[ma][nv][i];
+                if constexpr (MODE == SC_TOPK) {
+                  if (j < g.d && sc > vthr[nv]) {
+                    topk_push_ordered(ls[nv], lj[nv], sc, j);
+                    vthr[nv] = fmaxf(ls[nv][kCertK - 1], ls[nv][0] - win[nv]);
+                  }
+                } else {
+                  if (j < g.d && v < nvox && sc >= vthr[nv]) {
+                    const unsigned int pos = atomicAdd(&g.count[v], 1u);
+                    if ((int)pos < g.ccap) g.cand[v * g.ccap + pos] = j;
+                  }
+                }
+              }
+          }
         }
 #pragma unroll
         for (int a = 0; a < M_MA; ++a)
@@ -324,7 +406,6 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
       }
-      sflush();
       __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next stage are in LDS
       __syncthreads();
     }
