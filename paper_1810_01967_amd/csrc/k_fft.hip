@@ -92,6 +92,97 @@ __global__ __launch_bounds__(256) void k_fft_lines(float2 *__restrict__ data, in
   }
 }
 
+// 256-point lines as 16 x 16 (four-step Cooley-Tukey): with n = 16 n1 + q
+// and k = k1 + 16 k2, X[k] = sum_q W256^(q k1) W16^(q k2) sum_n1 x[n] W16^(n1 k1).
+// Thread q of a line holds x[16 n1 + q] for all n1, takes the inner 16-point
+// DFT in registers, applies W256^(q k1), and the line is transposed once
+// through LDS so that thread k1 takes the outer 16-point DFT over q and holds
+// X[k1 + 16 k2].  A 16-point DFT is itself 4 x 4 (n = 4 a + b, k = c + 4 d).
+// One LDS round trip per element instead of log2(256) = 8 radix-2 stages.
+__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
+  return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// 4-point DFT in place, W4 = exp(-+ i pi / 2): u = +1 forward (multiply by
+// -i), u = -1 inverse (by +i)
+__device__ __forceinline__ void dft4(float2 &x0, float2 &x1, float2 &x2, float2 &x3, float u) {
+  const float2 a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3), d = csub(x1, x3);
+  const float2 dm = make_float2(u * d.y, -u * d.x);  // d W4 (= -i d forward)
+  x0 = cadd(a, c);
+  x2 = csub(a, c);
+  x1 = cadd(b, dm);
+  x3 = csub(b, dm);
+}
+// 16-point DFT of v[0..15] (natural order in and out); w16[m] = W16^m
+__device__ __forceinline__ void dft16(float2 *v, const float2 *w16, float u) {
+  float2 t[4][4];  // t[b][c]
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    float2 x0 = v[b], x1 = v[4 + b], x2 = v[8 + b], x3 = v[12 + b];
+    dft4(x0, x1, x2, x3, u);
+    t[b][0] = x0;
+    t[b][1] = cmul(x1, w16[b]);
+    t[b][2] = cmul(x2, w16[2 * b]);
+    t[b][3] = cmul(x3, w16[3 * b]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float2 x0 = t[0][c], x1 = t[1][c], x2 = t[2][c], x3 = t[3][c];
+    dft4(x0, x1, x2, x3, u);
+    v[c] = x0;
+    v[c + 4] = x1;
+    v[c + 8] = x2;
+    v[c + 12] = x3;
+  }
+}
+
+template <bool COLS>
+__global__ __launch_bounds__(256) void k_fft256(float2 *__restrict__ data, int64_t nimg, int ny, int nx,
+                                                int inverse) {
+  constexpr int N = 256;
+  __shared__ float2 tw[N];               // W256^m
+  __shared__ float2 buf[16][16][17];     // [line][k1][q], padded
+  const int tid = threadIdx.x;
+  {
+    double sn, cs;
+    sincospi(-2.0 * tid / N, &sn, &cs);
+    tw[tid] = make_float2((float)cs, inverse ? -(float)sn : (float)sn);
+  }
+  const float u = inverse ? -1.f : 1.f;
+  // thread (c, q): line c of the block, position q in it; consecutive
+  // threads take consecutive elements (rows) or consecutive columns
+  const int c = COLS ? (tid & 15) : (tid >> 4), q = COLS ? (tid >> 4) : (tid & 15);
+  const int lpi = COLS ? nx : ny;
+  const int64_t nlines = nimg * lpi;
+  const int64_t l = (int64_t)blockIdx.x * 16 + c;
+  const bool live = l < nlines;
+  const int64_t img = live ? l / lpi : 0;
+  const int j = live ? (int)(l - img * lpi) : 0;
+  float2 *base = data + img * (int64_t)nx * ny + (COLS ? j : (int64_t)j * nx);
+  const int64_t es = COLS ? nx : 1;  // element stride
+  float2 v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) v[n1] = live ? base[(16 * n1 + q) * es] : make_float2(0.f, 0.f);
+  __syncthreads();  // the twiddle table
+  float2 w16[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) w16[m] = tw[16 * m];
+  dft16(v, w16, u);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) buf[c][k1][q] = cmul(v[k1], tw[(q * k1) & (N - 1)]);
+  __syncthreads();
+  // now thread (c, q) takes k1 = q
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) v[n2] = buf[c][q][n2];
+  dft16(v, w16, u);
+  if (live) {
+    const float sc = 1.f / 16.f;  // 1 / sqrt(256)
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) base[(q + 16 * k2) * es] = make_float2(v[k2].x * sc, v[k2].y * sc);
+  }
+}
+
 template <int N, bool COLS>
 static void fft_pass(float2 *data, int64_t nimg, int ny, int nx, int inverse, hipStream_t s) {
   constexpr int C = FftCfg<N>::C;
@@ -104,6 +195,12 @@ static void fft_pass(float2 *data, int64_t nimg, int ny, int nx, int inverse, hi
 template <bool COLS>
 static void fft_pass_n(int N, float2 *data, int64_t nimg, int ny, int nx, int inverse,
                        hipStream_t s) {
+  if (N == 256) {
+    const int64_t lines = nimg * (COLS ? nx : ny);
+    hipLaunchKernelGGL(k_fft256<COLS>, dim3((unsigned)((lines + 15) / 16)), dim3(256), 0, s, data, nimg, ny, nx,
+                       inverse);
+    return;
+  }
   switch (N) {
     case 16: fft_pass<16, COLS>(data, nimg, ny, nx, inverse, s); break;
     case 32: fft_pass<32, COLS>(data, nimg, ny, nx, inverse, s); break;
