@@ -230,7 +230,9 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
       // The fragments of the next group of products are read from LDS before
       // the products of the current group issue (scheduling barriers keep
       // the compiler from sinking the reads next to their use), so a wave's
-      // LDS latency overlaps its own MFMAs.
+      // LDS latency overlaps its own MFMAs.  A wave raises its priority while
+      // it issues products, so that the two waves of a SIMD alternate the
+      // matrix pipe and their reads rather than both waiting on LDS at once.
       if constexpr (F8) {
         // two k-steps of 64: the lane supplies 32 bytes (chunks 4 ks + 2 h,
         // + 1); groups (ks, ma), A fragments one group ahead, voxel
@@ -259,11 +261,13 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
               af[(gi + 1) & 1] = rd2(Ab, ks + 1);
             }
             __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int nv = 0; nv < M_NV; ++nv)
               acc[ma][nv] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[gi & 1], zf[ks & 1][nv], acc[ma][nv], 0,
                                                                             0, 0, 0x7F, 0, 0x7F);
             __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(0);
           }
       } else if constexpr (X3) {
         // two k-steps of 16: the lane supplies 8 values of each plane (hi
@@ -296,6 +300,7 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
               rda(ks + 1, 0, (gi + 1) & 1);
             }
             __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int nv = 0; nv < M_NV; ++nv) {
               acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[sl], zh[zs][nv], acc[ma][nv], 0, 0, 0);
@@ -303,6 +308,7 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
               acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[sl], zh[zs][nv], acc[ma][nv], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(0);
           }
       } else {
         // four k-steps of 16: the lane supplies 8 BF16 (chunk 2 ks + h); all
@@ -322,6 +328,7 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
         for (int ks = 0; ks < 4; ++ks) {
           if (ks + 1 < 4) rd(ks + 1);
           __builtin_amdgcn_sched_barrier(0);
+          __builtin_amdgcn_s_setprio(1);
 #pragma unroll
           for (int ma = 0; ma < M_MA; ++ma)
 #pragma unroll
@@ -329,6 +336,7 @@ __global__ __launch_bounds__(M_NT, 1) void k_score_mx(MxArgs g) {
               acc[ma][nv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ks & 1][ma], zf[ks & 1][nv], acc[ma][nv], 0,
                                                                     0, 0);
           __builtin_amdgcn_sched_barrier(0);
+          __builtin_amdgcn_s_setprio(0);
         }
       }
       const int st = q % g.nstage;
