@@ -164,6 +164,7 @@ struct mrf_dict_s {
   bool cert_used = false;  // the last exhaustive match ran the certificate
   bool zx3_fresh = false;  // zx3 holds the split rows of the current packing (written by the pack)
   bool zp_fresh = false;   // zp holds the FP32 rows of the current packing
+  bool inv_fresh = false;  // inv holds 1/znorm of the current packing (written by the pack)
   mrf::DevBuf kbuf, gbuf, xbuf, rbuf, abuf, red, scal, idxbuf, pdbuf;
   // temporal subspace (a compressed dictionary: atoms V^H Dhat_j of L = s frames)
   int Lfull = 0;                    // frames of the uncompressed dictionary, 0 if not compressed

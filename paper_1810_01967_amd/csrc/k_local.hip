@@ -28,13 +28,10 @@ __device__ __forceinline__ int64_t list_len(int64_t cnt, const unsigned int *dcn
   return dcnt ? min(cnt, (int64_t)*dcnt) : cnt;
 }
 
-__global__ void k_coarse_keys(const int32_t *__restrict__ list, int64_t cnt, const unsigned int *__restrict__ dcnt,
-                              const int32_t *__restrict__ cells, int P, int shift,
-                              GridDims g, int32_t *__restrict__ keys,
-                              unsigned int *__restrict__ hist) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= list_len(cnt, dcnt)) return;
-  const int v = list[i];
+// coarse cell of voxel v: its cell's index per parameter (clamped to the
+// grid) shifted down by `shift`, mixed in row-major order
+__device__ __forceinline__ int coarse_key_of(int v, const int32_t *__restrict__ cells, int P, int shift,
+                                             const GridDims &g) {
   int key = 0;
   for (int p = 0; p < P; ++p) {
     const int cd = ((g.dims[p] - 1) >> shift) + 1;
@@ -42,8 +39,64 @@ __global__ void k_coarse_keys(const int32_t *__restrict__ list, int64_t cnt, con
     c = c < 0 ? 0 : (c >= g.dims[p] ? g.dims[p] - 1 : c);
     key = key * cd + (c >> shift);
   }
+  return key;
+}
+
+__global__ void k_coarse_keys(const int32_t *__restrict__ list, int64_t cnt, const unsigned int *__restrict__ dcnt,
+                              const int32_t *__restrict__ cells, int P, int shift,
+                              GridDims g, int32_t *__restrict__ keys,
+                              unsigned int *__restrict__ hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= list_len(cnt, dcnt)) return;
+  const int key = coarse_key_of(list[i], cells, P, shift, g);
   keys[i] = key;
   atomicAdd(&hist[key], 1u);
+}
+
+// Block-aggregated forms for nkeys <= kGroupLds: a block counts its voxels
+// per key in LDS and makes one global atomic per key present in it, instead of
+// one per voxel (the voxels of a key all hit one address).
+constexpr int kGroupLds = 4096;
+__global__ __launch_bounds__(256) void k_coarse_keys_lds(const int32_t *__restrict__ list, int64_t cnt,
+                                                         const unsigned int *__restrict__ dcnt,
+                                                         const int32_t *__restrict__ cells, int P, int shift,
+                                                         GridDims g, int32_t *__restrict__ keys,
+                                                         unsigned int *__restrict__ hist, int nkeys) {
+  __shared__ unsigned int h[kGroupLds];
+  for (int k = threadIdx.x; k < nkeys; k += 256) h[k] = 0u;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < list_len(cnt, dcnt)) {
+    const int key = coarse_key_of(list[i], cells, P, shift, g);
+    keys[i] = key;
+    atomicAdd(&h[key], 1u);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nkeys; k += 256)
+    if (h[k]) atomicAdd(&hist[k], h[k]);
+}
+
+__global__ __launch_bounds__(256) void k_group_scatter_lds(const int32_t *__restrict__ list,
+                                                           const int32_t *__restrict__ keys, int64_t cnt,
+                                                           const unsigned int *__restrict__ dcnt,
+                                                           unsigned int *__restrict__ cursor,
+                                                           int32_t *__restrict__ out, int nkeys) {
+  __shared__ unsigned int h[kGroupLds];  // the block's count per key, then its first position
+  for (int k = threadIdx.x; k < nkeys; k += 256) h[k] = 0u;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool valid = i < list_len(cnt, dcnt);
+  int key = 0;
+  unsigned int rank = 0;
+  if (valid) {
+    key = keys[i];
+    rank = atomicAdd(&h[key], 1u);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nkeys; k += 256)
+    if (h[k]) h[k] = atomicAdd(&cursor[k], h[k]);
+  __syncthreads();
+  if (valid) out[h[key] + rank] = list[i];
 }
 
 // Exclusive scans of hist[0..nkeys) (one block): off[k] (the first sorted
@@ -145,10 +198,19 @@ void launch_group(const int32_t *list, int64_t cnt, const int32_t *cells, int P,
   const int nkeys = coarse_key_count(g, P, shift);
   if (!hist_cleared) launch_zero(gb.hist, (int64_t)nkeys * 4, s);
   const unsigned blocks = (unsigned)((cnt + 255) / 256);
-  hipLaunchKernelGGL(k_coarse_keys, dim3(blocks), dim3(256), 0, s, list, cnt, dcnt, cells, P, shift, g,
-                     keys, gb.hist);
+  const bool lds = nkeys <= kGroupLds;
+  if (lds)
+    hipLaunchKernelGGL(k_coarse_keys_lds, dim3(blocks), dim3(256), 0, s, list, cnt, dcnt, cells, P, shift, g,
+                       keys, gb.hist, nkeys);
+  else
+    hipLaunchKernelGGL(k_coarse_keys, dim3(blocks), dim3(256), 0, s, list, cnt, dcnt, cells, P, shift, g,
+                       keys, gb.hist);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, gb.hist, nkeys, gb.off, gb.cursor, gb.toff);
-  hipLaunchKernelGGL(k_group_scatter, dim3(blocks), dim3(256), 0, s, list, keys, cnt, dcnt, gb.cursor, out);
+  if (lds)
+    hipLaunchKernelGGL(k_group_scatter_lds, dim3(blocks), dim3(256), 0, s, list, keys, cnt, dcnt, gb.cursor, out,
+                       nkeys);
+  else
+    hipLaunchKernelGGL(k_group_scatter, dim3(blocks), dim3(256), 0, s, list, keys, cnt, dcnt, gb.cursor, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -228,6 +290,18 @@ __device__ __forceinline__ unsigned long long pack_best(float s, int j) {
   return ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned int)j);
 }
 
+// (score, atom) of a best key; -inf / -1 for key 0 (no candidate)
+__device__ __forceinline__ void unpack_best(unsigned long long k, float &s, int32_t &j) {
+  if (k == 0ull) {
+    s = -INFINITY;
+    j = -1;
+    return;
+  }
+  const unsigned int u = (unsigned int)(k >> 32);
+  s = __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+  j = (int32_t)(0xFFFFFFFFu - (unsigned int)(k & 0xFFFFFFFFull));
+}
+
 // mode 0: keys of the listed voxels (all voxels if list is null) set to 0;
 // mode 1: keys unpacked into best_s / best_j (-inf / -1 for key 0).
 __global__ void k_best_keys(const int32_t *__restrict__ list, int64_t cnt, const unsigned int *__restrict__ dcnt,
@@ -240,15 +314,11 @@ __global__ void k_best_keys(const int32_t *__restrict__ list, int64_t cnt, const
     keys[v] = 0ull;
     return;
   }
-  const unsigned long long k = keys[v];
-  if (k == 0ull) {
-    best_s[v] = -INFINITY;
-    best_j[v] = -1;
-    return;
-  }
-  const unsigned int u = (unsigned int)(k >> 32);
-  best_s[v] = __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
-  best_j[v] = (int32_t)(0xFFFFFFFFu - (unsigned int)(k & 0xFFFFFFFFull));
+  float bs;
+  int32_t bj;
+  unpack_best(keys[v], bs, bj);
+  best_s[v] = bs;
+  best_j[v] = bj;
 }
 
 void launch_best_keys(const int32_t *list, int64_t cnt, unsigned long long *keys, float *best_s, int32_t *best_j,
@@ -688,6 +758,8 @@ void launch_warm_best(const int32_t *warm, int64_t n, int d, const float *Zp, co
 // ---------------------------------------------------------------------------
 // For listed voxels: if the best atom lies on a box face that is not a grid
 // edge, append the voxel to `recentre` and move its cell to the best atom.
+// The best atom is best_j[v], or read from the voxel's best key where best_j
+// is null (the keys then hold the current answers).
 __global__ void k_face(const int32_t *__restrict__ list, int64_t cnt, const unsigned int *__restrict__ dcnt,
                        const int32_t *__restrict__ best_j, int32_t *__restrict__ cells, int P, GridDims g, int r,
                        int32_t *__restrict__ out, unsigned int *__restrict__ count,
@@ -696,7 +768,13 @@ __global__ void k_face(const int32_t *__restrict__ list, int64_t cnt, const unsi
   if (i < nzero) zero[i] = 0u;
   if (i >= list_len(cnt, dcnt)) return;
   const int v = list[i];
-  int j = best_j[v];
+  int j;
+  if (best_j) {
+    j = best_j[v];
+  } else {
+    float bs;
+    unpack_best(bkey[v], bs, j);
+  }
   if (j < 0) return;
   int sub[4];
   for (int p = P - 1; p >= 0; --p) {
@@ -725,15 +803,40 @@ void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_
 
 // Voxels with a finite, non-zero norm whose normalised correlation is below
 // the threshold (or with no candidate) go to the exhaustive fallback list.
+__device__ __forceinline__ bool needs_fallback(float bs, int32_t bj, float zn, float thr) {
+  if (!(zn > 0.f)) return false;
+  const float corr = bs / zn;
+  return bj < 0 || !(corr >= thr);
+}
+
 __global__ void k_select_fallback(int64_t n, const float *__restrict__ best_s,
                                   const int32_t *__restrict__ best_j, const float *__restrict__ znorm,
                                   float thr, int32_t *__restrict__ out, unsigned int *__restrict__ count) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const float zn = znorm[v];
-  if (!(zn > 0.f)) return;
-  const float corr = best_s[v] / zn;
-  if (best_j[v] < 0 || !(corr >= thr)) out[atomicAdd(count, 1u)] = (int32_t)v;
+  if (needs_fallback(best_s[v], best_j[v], znorm[v], thr)) out[atomicAdd(count, 1u)] = (int32_t)v;
+}
+
+// Every voxel's best key unpacked (k_best_keys, mode 1, over all voxels) and,
+// in the same pass, the fallback selection of k_select_fallback.
+__global__ void k_best_select(int64_t n, const unsigned long long *__restrict__ keys, float *__restrict__ best_s,
+                              int32_t *__restrict__ best_j, const float *__restrict__ znorm, float thr,
+                              int32_t *__restrict__ out, unsigned int *__restrict__ count) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  float bs;
+  int32_t bj;
+  unpack_best(keys[v], bs, bj);
+  best_s[v] = bs;
+  best_j[v] = bj;
+  if (needs_fallback(bs, bj, znorm[v], thr)) out[atomicAdd(count, 1u)] = (int32_t)v;
+}
+
+void launch_best_select(int64_t n, const unsigned long long *keys, float *best_s, int32_t *best_j,
+                        const float *znorm, float thr, int32_t *out, unsigned int *count, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_best_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, keys, best_s, best_j,
+                     znorm, thr, out, count);
 }
 
 void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,
@@ -831,25 +934,14 @@ void launch_scatter_best(const int32_t *list, int64_t cnt, const float *part_s, 
                      part_s, part_j, splits, best_s, best_j, dcnt, ntiles);
 }
 
-// Start of a learned call: list[i] = i and key[i] = 0 for i < n, and the
-// first nz words of z and nz2 words of z2 set to zero (counters, histogram).
-__global__ void k_learned_prep(int32_t *__restrict__ list, unsigned long long *__restrict__ keys, int64_t n,
-                               unsigned int *__restrict__ z, int nz, unsigned int *__restrict__ z2, int nz2) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    list[i] = (int32_t)i;
-    keys[i] = 0ull;
-  }
-  if (i < nz) z[i] = 0u;
-  if (i < nz2) z2[i] = 0u;
+// Start of a learned call (learned_prep_at for every thread).
+__global__ void k_learned_prep(LearnedPrep p, int64_t n) {
+  learned_prep_at((int64_t)blockIdx.x * blockDim.x + threadIdx.x, p, n);
 }
 
-void launch_learned_prep(int32_t *list, unsigned long long *keys, int64_t n, unsigned int *z, int nz,
-                         unsigned int *z2, int nz2, hipStream_t s) {
-  const int64_t m = std::max<int64_t>(n, std::max(nz, nz2));
-  if (m > 0)
-    hipLaunchKernelGGL(k_learned_prep, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, list, keys, n, z, nz,
-                       z2, nz2);
+void launch_learned_prep(const LearnedPrep &p, int64_t n, hipStream_t s) {
+  const int64_t m = std::max<int64_t>(n, std::max(p.nz, p.nz2));
+  if (m > 0) hipLaunchKernelGGL(k_learned_prep, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, p, n);
 }
 
 __global__ void k_iota(int32_t *x, int64_t n) {

@@ -27,7 +27,8 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
                                                           float *__restrict__ znorm,
                                                           unsigned long long *counters,
                                                           const float2 *__restrict__ vphase,
-                                                          uint16_t *__restrict__ zx3, int Kx) {
+                                                          uint16_t *__restrict__ zx3, int Kx,
+                                                          float *__restrict__ inv) {
   const int lane = threadIdx.x & 63;
   const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (v >= n_pad) return;
@@ -82,7 +83,9 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
   acc = wave_sum_f64(acc);
   if (lane == 0) {
     const bool fin = isfinite(acc);
-    znorm[v] = fin ? (float)sqrt(acc) : -1.f;
+    const float zn = fin ? (float)sqrt(acc) : -1.f;
+    znorm[v] = zn;
+    if (inv) inv[v] = zn > 0.f ? 1.f / zn : 0.f;  // as k_inv_norm
     if (!fin) atomicAdd(&counters[1], 1ull);
     else if (acc == 0.0) atomicAdd(&counters[0], 1ull);
   }
@@ -96,7 +99,8 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major2(const float2 *__restr
                                                            float *__restrict__ znorm,
                                                            unsigned long long *counters,
                                                            const float2 *__restrict__ vphase,
-                                                           uint16_t *__restrict__ zx3, int Kx) {
+                                                           uint16_t *__restrict__ zx3, int Kx,
+                                                           float *__restrict__ inv) {
   const int lane = threadIdx.x & 63;
   const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (v >= n_pad) return;
@@ -158,7 +162,9 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major2(const float2 *__restr
   acc = wave_sum_f64(acc);
   if (lane == 0) {
     const bool fin = isfinite(acc);
-    znorm[v] = fin ? (float)sqrt(acc) : -1.f;
+    const float zn = fin ? (float)sqrt(acc) : -1.f;
+    znorm[v] = zn;
+    if (inv) inv[v] = zn > 0.f ? 1.f / zn : 0.f;  // as k_inv_norm
     if (!fin) atomicAdd(&counters[1], 1ull);
     else if (acc == 0.0) atomicAdd(&counters[0], 1ull);
   }
@@ -273,14 +279,14 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
 
 void launch_pack_voxel_major(const float2 *Z, int64_t n, int64_t n_pad, int L, int real_atoms,
                              int Kp, float *Zp, float *znorm, unsigned long long *counters,
-                             hipStream_t s, const float2 *vphase, uint16_t *zx3, int Kx) {
+                             hipStream_t s, const float2 *vphase, uint16_t *zx3, int Kx, float *inv) {
   const int64_t blocks = (n_pad + 3) / 4;
   if (L % 2 == 0 && (reinterpret_cast<uintptr_t>(Z) & 15) == 0 && Kp % 4 == 0)
     hipLaunchKernelGGL(k_pack_voxel_major2, dim3((unsigned)blocks), dim3(256), 0, s, Z, n, n_pad, L,
-                       real_atoms, Kp, Zp, znorm, counters, vphase, zx3, Kx);
+                       real_atoms, Kp, Zp, znorm, counters, vphase, zx3, Kx, inv);
   else
     hipLaunchKernelGGL(k_pack_voxel_major, dim3((unsigned)blocks), dim3(256), 0, s, Z, n, n_pad, L,
-                       real_atoms, Kp, Zp, znorm, counters, vphase, zx3, Kx);
+                       real_atoms, Kp, Zp, znorm, counters, vphase, zx3, Kx, inv);
 }
 
 void launch_pack_frame_major(const float2 *X, const float2 *G, float mu, int64_t n, int64_t n_pad,

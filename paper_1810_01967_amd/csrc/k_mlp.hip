@@ -307,11 +307,14 @@ void launch_noisy_batch(const float *Dhat, int Kp, int L, int real_atoms, int d,
 // axes: concatenated per-parameter grid values (ascending), axis p at
 // axes[aoff[p] .. aoff[p] + dims[p]); comparisons in the transformed space
 // (log where logm[p]), ties to the lower index.
+// prep (optional): the start-of-call initialisation of k_learned_prep done by
+// the same threads (the grid then covers its counter ranges too).
 __global__ void k_cells(const float *__restrict__ Y, int64_t n, int P, const float *__restrict__ mean,
                         const float *__restrict__ stdv, const int *__restrict__ logm,
                         const float *__restrict__ axes, const int *__restrict__ aoff,
-                        const int *__restrict__ dims, int32_t *__restrict__ cells) {
+                        const int *__restrict__ dims, int32_t *__restrict__ cells, LearnedPrep prep) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (prep.list) learned_prep_at(v, prep, n);
   if (v >= n) return;
   for (int p = 0; p < P; ++p) {
     const float val = Y[v * P + p] * stdv[p] + mean[p];
@@ -339,10 +342,12 @@ __global__ void k_cells(const float *__restrict__ Y, int64_t n, int P, const flo
 
 void launch_cells(const float *Y, int64_t n, int P, const float *mean, const float *stdv,
                   const int *logm, const float *axes, const int *aoff, const int *dims, int32_t *cells,
-                  hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Y, n, P, mean,
-                     stdv, logm, axes, aoff, dims, cells);
+                  hipStream_t s, const LearnedPrep *prep) {
+  const LearnedPrep pp = prep ? *prep : LearnedPrep{};
+  const int64_t m = prep ? std::max<int64_t>(n, std::max(pp.nz, pp.nz2)) : n;
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_cells, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, Y, n, P, mean,
+                     stdv, logm, axes, aoff, dims, cells, pp);
 }
 
 }  // namespace mrf

@@ -542,6 +542,7 @@ mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t s
   if (want_fp32) TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
   D->zx3_fresh = false;
   D->zp_fresh = false;
+  D->inv_fresh = false;
   uint16_t *zx3 = nullptr;
   if (want_x3) {  // split-BF16 rows written by the packing itself
     TRY(grow(D->zx3, (size_t)n_pad * 2 * D->Kx * 2));
@@ -562,17 +563,20 @@ mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t s
     LAUNCH_CHECK("voxel phase");
     vph = D->vphase.as<float2>();
   }
-  if (z_layout == MRF_VOXEL_MAJOR)
+  if (z_layout == MRF_VOXEL_MAJOR) {
+    // the network's row scale comes with the norms (learned matching reads it)
+    TRY(grow(D->inv, (size_t)n * 4));
     launch_pack_voxel_major(static_cast<const float2 *>(Z), n, n_pad, D->L, real, D->Kp,
                             want_fp32 ? D->zp.as<float>() : nullptr, D->znorm.as<float>(),
-                            D->counters.as<unsigned long long>(), s, vph, zx3, D->Kx);
-  else
+                            D->counters.as<unsigned long long>(), s, vph, zx3, D->Kx, D->inv.as<float>());
+  } else
     launch_pack_frame_major(static_cast<const float2 *>(Z), nullptr, 0.f, n, n_pad, slice_voxels,
                             D->L, real, D->Kp, D->zp.as<float>(), D->znorm.as<float>(),
                             D->counters.as<unsigned long long>(), s, vph, zx3, D->Kx);
   LAUNCH_CHECK("pack");
   D->zx3_fresh = want_x3;
   D->zp_fresh = want_fp32;
+  D->inv_fresh = z_layout == MRF_VOXEL_MAJOR;
   return MRF_OK;
 }
 
@@ -930,6 +934,7 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
   LAUNCH_CHECK("grad_update_pack");
   D->zx3_fresh = want_x3;
   D->zp_fresh = true;
+  D->inv_fresh = false;
   TRY(match_core(D, o, n, warm, idx, pd, nullptr, nullptr, s, nullptr, nullptr, nullptr, nullptr));
   double *red = D->red.as<double>();
   int nb = 0;

@@ -56,10 +56,12 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // vphase (optional, [n]): unit factors e^{i theta_v}; each voxel is packed
 // rotated by conj(vphase[v]) (phase-aligned projection).  zx3 (optional):
 // also the split-BF16 rows [n_pad][2 Kx] of the packed rows (the encoding of
-// k_split_x3, zero beyond K and for rows n..n_pad).
+// k_split_x3, zero beyond K and for rows n..n_pad).  inv (optional, [n]):
+// 1/znorm (0 for zero or non-finite rows), the network's row scale.
 void launch_pack_voxel_major(const float2 *Z, int64_t n, int64_t n_pad, int L, int real_atoms,
                              int Kp, float *Zp, float *znorm, unsigned long long *counters,
-                             hipStream_t s, const float2 *vphase = nullptr, uint16_t *zx3 = nullptr, int Kx = 0);
+                             hipStream_t s, const float2 *vphase = nullptr, uint16_t *zx3 = nullptr, int Kx = 0,
+                             float *inv = nullptr);
 void launch_pack_frame_major(const float2 *X, const float2 *G, float mu, int64_t n, int64_t n_pad,
                              int64_t npix, int L, int real_atoms, int Kp, float *Zp, float *znorm,
                              unsigned long long *counters, hipStream_t s, const float2 *vphase = nullptr,
@@ -300,9 +302,28 @@ void launch_noisy_batch(const float *Dhat, int Kp, int L, int real_atoms, int d,
                         uint64_t key_atom, uint64_t key_snr, uint64_t key_noise, int64_t offset,
                         int64_t B, float snr_lo, float snr_hi, float *X, int ldx, float *T,
                         int32_t *atom_out, hipStream_t s);
+// Start of a learned call: list[i] = i and keys[i] = 0 for i < n, the first
+// nz words of z and nz2 words of z2 set to zero (counters, histogram).
+struct LearnedPrep {
+  int32_t *list;
+  unsigned long long *keys;
+  unsigned int *z;
+  int nz;
+  unsigned int *z2;
+  int nz2;
+};
+__device__ __forceinline__ void learned_prep_at(int64_t i, const LearnedPrep &p, int64_t n) {
+  if (i < n) {
+    p.list[i] = (int32_t)i;
+    p.keys[i] = 0ull;
+  }
+  if (i < p.nz) p.z[i] = 0u;
+  if (i < p.nz2) p.z2[i] = 0u;
+}
+// prep (optional): that initialisation folded into the same launch.
 void launch_cells(const float *Y, int64_t n, int P, const float *mean, const float *stdv,
                   const int *logm, const float *axes, const int *aoff, const int *dims, int32_t *cells,
-                  hipStream_t s);
+                  hipStream_t s, const LearnedPrep *prep = nullptr);
 
 // ---------------------------------------------------------------- local search
 struct GridDims {
@@ -391,22 +412,24 @@ void launch_unsplit_x3(const uint16_t *src, int64_t rows, int Kx, int K, uint16_
 void launch_warm_best(const int32_t *warm, int64_t n, int d, const float *Zp, const float *Dhat, int Kp,
                       const float *znorm, float *best_s, int32_t *best_j, hipStream_t s);
 // Also resets the best key of each voxel it lists (bkey, may be null) and
-// clears zero[0..nzero) (the next grouping's histogram).
+// clears zero[0..nzero) (the next grouping's histogram).  With best_j null
+// the best atoms are read from bkey (then required).
 void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_t *cells, int P,
                  const GridDims &g, int r, int32_t *out, unsigned int *count, hipStream_t s,
                  const unsigned int *dcnt = nullptr, unsigned long long *bkey = nullptr,
                  unsigned int *zero = nullptr, int nzero = 0);
 void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,
                             float thr, int32_t *out, unsigned int *count, hipStream_t s);
+// launch_best_keys (mode 1, every voxel) and launch_select_fallback in one pass.
+void launch_best_select(int64_t n, const unsigned long long *keys, float *best_s, int32_t *best_j,
+                        const float *znorm, float thr, int32_t *out, unsigned int *count, hipStream_t s);
 void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cnt, int64_t cnt_pad,
                         float *out, hipStream_t s);
 // rows list[i] for i < *dcnt (<= cap), zero rows up to the next multiple of
 // 128; total (device, may be null) += *dcnt
 void launch_gather_rows_dev(const float *Zp, int Kp, const int32_t *list, int64_t cap, const unsigned int *dcnt,
                             float *out, hipStream_t s, unsigned long long *total = nullptr);
-// list[i] = i, keys[i] = 0 for i < n; z[0..nz) = 0, z2[0..nz2) = 0
-void launch_learned_prep(int32_t *list, unsigned long long *keys, int64_t n, unsigned int *z, int nz,
-                         unsigned int *z2, int nz2, hipStream_t s);
+void launch_learned_prep(const LearnedPrep &p, int64_t n, hipStream_t s);
 void launch_add_count(unsigned long long *total, const unsigned int *count, hipStream_t s);
 // With dcnt: cnt is the capacity (also the part stride) and the splits are
 // those launch_score_x3_dev chose for the device count (ntiles = d_pad / 256).

@@ -598,31 +598,6 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   TRY(grow(D->keys, (size_t)n * 4));
   TRY(grow(D->cnt, 128));  // [0] fallback count, [1..16] re-centring rounds
   TRY(grow(D->counters, 64));
-  int32_t *cells = cells_in;
-  if (!cells) {
-    TRY(grow(D->cells, (size_t)n * P * 4));
-    cells = D->cells.as<int32_t>();
-    mrf_net_s *net = o->net;
-    TRY(grow(D->inv, (size_t)n * 4));
-    TRY(grow(D->h1, (size_t)n * net->H * 4));
-    TRY(grow(D->h2, (size_t)n * net->H * 4));
-    TRY(grow(D->yout, (size_t)n * P * 4));
-    if (st) HIP_TRY(hipEventRecord(e_prop0, s));
-    launch_inv_norm(D->znorm.as<float>(), n, D->inv.as<float>(), s);
-    if (o->precision == MRF_BF16X3 && D->zx3_fresh && net_split_ok(net, D))
-      TRY(net_forward_bf16_split(net, D, D->zx3.as<uint16_t>(), n, D->inv.as<float>(), D->yout.as<float>(),
-                                 D->h1.as<uint16_t>(), s));
-    else if (net_bf16_ok(net, D->Kp, D->Kp))
-      TRY(net_forward_bf16(net, D->zp.as<float>(), D->Kp, D->Kp, n, D->inv.as<float>(), D->yout.as<float>(),
-                           D->h1.as<uint16_t>(), s));
-    else
-      TRY(net_forward_rows(net, D->zp.as<float>(), D->Kp, n, D->inv.as<float>(), D->yout.as<float>(),
-                           D->h1.as<float>(), D->h2.as<float>(), s));
-    launch_cells(D->yout.as<float>(), n, P, dmean(net), dstdv(net), dlogm(net), D->axes.as<float>(),
-                 D->aoff.as<int>(), D->dims.as<int>(), cells, s);
-    LAUNCH_CHECK("cells");
-    if (st) HIP_TRY(hipEventRecord(e_prop1, s));
-  }
 #ifndef MRF_LS_SHIFT
 #define MRF_LS_SHIFT 2
 #endif
@@ -656,7 +631,37 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   unsigned long long *bkey = D->bestkey.as<unsigned long long>();
   // first pass: every voxel, grouped by coarse proposal cell
   int32_t *la = D->list_a.as<int32_t>(), *lb = D->list_b.as<int32_t>(), *lc = D->list_c.as<int32_t>();
-  launch_learned_prep(la, bkey, n, cntw, 22, gb.hist, nkeys, s);
+  // start of the call (identity list, best keys, counters, histogram),
+  // folded into the cells launch where the network runs
+  const LearnedPrep prep{la, bkey, cntw, 22, gb.hist, nkeys};
+  bool prepped = false;
+  int32_t *cells = cells_in;
+  if (!cells) {
+    TRY(grow(D->cells, (size_t)n * P * 4));
+    cells = D->cells.as<int32_t>();
+    mrf_net_s *net = o->net;
+    TRY(grow(D->inv, (size_t)n * 4));
+    TRY(grow(D->h1, (size_t)n * net->H * 4));
+    TRY(grow(D->h2, (size_t)n * net->H * 4));
+    TRY(grow(D->yout, (size_t)n * P * 4));
+    if (st) HIP_TRY(hipEventRecord(e_prop0, s));
+    if (!D->inv_fresh) launch_inv_norm(D->znorm.as<float>(), n, D->inv.as<float>(), s);
+    if (o->precision == MRF_BF16X3 && D->zx3_fresh && net_split_ok(net, D))
+      TRY(net_forward_bf16_split(net, D, D->zx3.as<uint16_t>(), n, D->inv.as<float>(), D->yout.as<float>(),
+                                 D->h1.as<uint16_t>(), s));
+    else if (net_bf16_ok(net, D->Kp, D->Kp))
+      TRY(net_forward_bf16(net, D->zp.as<float>(), D->Kp, D->Kp, n, D->inv.as<float>(), D->yout.as<float>(),
+                           D->h1.as<uint16_t>(), s));
+    else
+      TRY(net_forward_rows(net, D->zp.as<float>(), D->Kp, n, D->inv.as<float>(), D->yout.as<float>(),
+                           D->h1.as<float>(), D->h2.as<float>(), s));
+    launch_cells(D->yout.as<float>(), n, P, dmean(net), dstdv(net), dlogm(net), D->axes.as<float>(),
+                 D->aoff.as<int>(), D->dims.as<int>(), cells, s, &prep);
+    prepped = true;
+    LAUNCH_CHECK("cells");
+    if (st) HIP_TRY(hipEventRecord(e_prop1, s));
+  }
+  if (!prepped) launch_learned_prep(prep, n, s);
   const bool x3 = o->precision == MRF_BF16X3;
   if (x3) TRY(ensure_x3(D, s));
   if (st) HIP_TRY(hipEventRecord(ev.a, s));
@@ -671,7 +676,8 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   launch_group(la, n, cells, P, shift, g, D->keys.as<int32_t>(), gb, lb, s, nullptr, true);
   if (st) HIP_TRY(hipEventRecord(e_ls0, s));
   launch_local_score(Dop, Zop, pitch, x3, lb, n, gb, nkeys, cells, P, g, r, shift, bkey, work, work + 1, s);
-  launch_best_keys(nullptr, n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s);
+  // the best keys stay packed until every round is done: the face test reads
+  // them, and one pass unpacks them all at the end
   if (st) HIP_TRY(hipEventRecord(e_ls1, s));
   LAUNCH_CHECK("local search");
   // re-centring rounds over the voxels whose best atom sits on an interior
@@ -686,17 +692,18 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
     unsigned int *count = rcount + rd;
     // the face test also resets the listed voxels' best keys and clears the
     // histogram of the grouping that follows
-    launch_face(prev, n, D->best_j.as<int32_t>(), cells, P, g, r, lc, count, s, prev_cnt, bkey, gb_rc.hist,
-                nkeys_rc);
+    launch_face(prev, n, nullptr, cells, P, g, r, lc, count, s, prev_cnt, bkey, gb_rc.hist, nkeys_rc);
     int32_t *sorted = (prev == lb) ? la : lb;
     launch_group(lc, n, cells, P, shift_rc, g, D->keys.as<int32_t>(), gb_rc, sorted, s, count, true);
     launch_local_score(Dop, Zop, pitch, x3, sorted, n, gb_rc, nkeys_rc, cells, P, g, r, shift_rc, bkey, work,
                        nullptr, s);
-    launch_best_keys(sorted, n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s, count);
     LAUNCH_CHECK("local search (re-centre)");
     prev = sorted;
     prev_cnt = count;
   }
+  // unpacked here, or by the fallback selection below in the same pass
+  const bool unpack_with_select = !warm && thr >= 0.f;
+  if (!unpack_with_select) launch_best_keys(nullptr, n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s);
   // the previous atom competes (non-expansive safeguard of the inexact projection)
   launch_warm_best(warm, n, D->d, D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->znorm.as<float>(),
                    D->best_s.as<float>(), D->best_j.as<int32_t>(), s);
@@ -717,8 +724,12 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   bool nfb_on_device = false;  // the fallback count stayed on the device (read back only for stats)
   unsigned int *count = cntw;  // cleared by the preparation kernel
   if (thr >= 0.f) {
-    launch_select_fallback(n, D->best_s.as<float>(), D->best_j.as<int32_t>(), D->znorm.as<float>(), thr,
-                           la, count, s);
+    if (unpack_with_select)
+      launch_best_select(n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), D->znorm.as<float>(), thr, la,
+                         count, s);
+    else
+      launch_select_fallback(n, D->best_s.as<float>(), D->best_j.as<int32_t>(), D->znorm.as<float>(), thr,
+                             la, count, s);
     TRY(fallback_total_buf(D, s));
     const bool tree_fb = D->has_tree && o->eps >= 0.f;
     if (x3 && !tree_fb) {
