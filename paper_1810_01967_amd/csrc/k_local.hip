@@ -121,7 +121,15 @@ __global__ __launch_bounds__(1024) void k_scan(const unsigned int *__restrict__ 
   const bool staged = nkeys <= kScanLds;
   unsigned int sum = 0, tsum = 0;
   if (staged) {
-    for (int i = t; i < nkeys; i += 1024) hl[i] = hist[i];
+    // four loads in flight per thread: one memory round trip per four keys
+    for (int i0 = t; i0 < nkeys; i0 += 4096) {
+      unsigned int x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = i0 + 1024 * u < nkeys ? hist[i0 + 1024 * u] : 0u;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + 1024 * u < nkeys) hl[i0 + 1024 * u] = x[u];
+    }
     __syncthreads();
     for (int i = b; i < e; ++i) {
       const unsigned int x = hl[i];
@@ -819,9 +827,10 @@ __global__ void k_select_fallback(int64_t n, const float *__restrict__ best_s,
 
 // Every voxel's best key unpacked (k_best_keys, mode 1, over all voxels) and,
 // in the same pass, the fallback selection of k_select_fallback.
+// With fin.idx, a voxel that does not fall back is finished here as well.
 __global__ void k_best_select(int64_t n, const unsigned long long *__restrict__ keys, float *__restrict__ best_s,
                               int32_t *__restrict__ best_j, const float *__restrict__ znorm, float thr,
-                              int32_t *__restrict__ out, unsigned int *__restrict__ count) {
+                              int32_t *__restrict__ out, unsigned int *__restrict__ count, FinishArgs fin) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   float bs;
@@ -829,14 +838,19 @@ __global__ void k_best_select(int64_t n, const unsigned long long *__restrict__ 
   unpack_best(keys[v], bs, bj);
   best_s[v] = bs;
   best_j[v] = bj;
-  if (needs_fallback(bs, bj, znorm[v], thr)) out[atomicAdd(count, 1u)] = (int32_t)v;
+  if (needs_fallback(bs, bj, znorm[v], thr))
+    out[atomicAdd(count, 1u)] = (int32_t)v;
+  else if (fin.idx)
+    finish_single(v, bs, bj, fin);
 }
 
 void launch_best_select(int64_t n, const unsigned long long *keys, float *best_s, int32_t *best_j,
-                        const float *znorm, float thr, int32_t *out, unsigned int *count, hipStream_t s) {
+                        const float *znorm, float thr, int32_t *out, unsigned int *count, hipStream_t s,
+                        const FinishArgs *fin) {
   if (n <= 0) return;
+  const FinishArgs f = fin ? *fin : FinishArgs{};
   hipLaunchKernelGGL(k_best_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, keys, best_s, best_j,
-                     znorm, thr, out, count);
+                     znorm, thr, out, count, f);
 }
 
 void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,
@@ -902,7 +916,7 @@ void launch_add_count(unsigned long long *total, const unsigned int *count, hipS
 __global__ void k_scatter_best(const int32_t *__restrict__ list, int64_t cnt,
                                const float *__restrict__ part_s, const int *__restrict__ part_j,
                                int splits, float *__restrict__ best_s, int32_t *__restrict__ best_j,
-                               const unsigned int *__restrict__ dcnt, int ntiles) {
+                               const unsigned int *__restrict__ dcnt, int ntiles, FinishArgs fin) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t c = cnt;
   const int64_t stride = cnt;
@@ -924,14 +938,16 @@ __global__ void k_scatter_best(const int32_t *__restrict__ list, int64_t cnt,
   const int v = list[i];
   best_s[v] = bs;
   best_j[v] = bj;
+  if (fin.idx) finish_single(v, bs, bj, fin);
 }
 
 void launch_scatter_best(const int32_t *list, int64_t cnt, const float *part_s, const int *part_j,
                          int splits, float *best_s, int32_t *best_j, hipStream_t s, const unsigned int *dcnt,
-                         int ntiles) {
+                         int ntiles, const FinishArgs *fin) {
   if (cnt <= 0) return;
+  const FinishArgs f = fin ? *fin : FinishArgs{};
   hipLaunchKernelGGL(k_scatter_best, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, list, cnt,
-                     part_s, part_j, splits, best_s, best_j, dcnt, ntiles);
+                     part_s, part_j, splits, best_s, best_j, dcnt, ntiles, f);
 }
 
 // Start of a learned call (learned_prep_at for every thread).

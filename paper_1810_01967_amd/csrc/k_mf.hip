@@ -4,6 +4,7 @@
 #include <cfloat>
 
 #include "k_split.h"
+#include "k_finish.h"
 #include "k_topk.h"
 #include "mrf_internal.h"
 
@@ -637,31 +638,6 @@ void launch_collect_f32_dev(const float *D, const float *Zp, const int32_t *rows
 // ---------------------------------------------------------------------------
 // merge + rescale + look-up
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void finish_voxel(int64_t v, float sc, int j, int d, const float *znorm,
-                                             const int32_t *warm, const float *inv_norm,
-                                             const float *params, int nparam, int32_t *idx,
-                                             float *pd, float *corr, float *params_out,
-                                             float *gamma_hat) {
-  const float zn = znorm[v];
-  float g = 0.f, c = 0.f;
-  if (zn < 0.f || j < 0) {
-    j = -1;  // non-finite voxel
-  } else if (zn == 0.f) {
-    j = warm ? warm[v] : 0;
-    if (j < 0 || j >= d) j = 0;  // an out-of-range warm index is not trusted
-  } else {
-    g = fmaxf(sc, 0.f);
-    c = sc / zn;
-  }
-  idx[v] = j;
-  if (pd) pd[v] = j >= 0 ? g * inv_norm[j] : 0.f;
-  if (corr) corr[v] = c;
-  gamma_hat[v] = g;
-  if (params_out)
-    for (int p = 0; p < nparam; ++p)
-      params_out[v * nparam + p] = j >= 0 ? params[(int64_t)j * nparam + p] : 0.f;
-}
-
 __global__ void k_merge_argmax(const float *__restrict__ part_s, const int *__restrict__ part_j,
                                int splits, int64_t n, int d, const float *znorm, const int32_t *warm,
                                const float *inv_norm, const float *params, int nparam,

@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "../../include/mrf.h"
+#include "k_finish.h"
 
 namespace mrf {
 
@@ -420,9 +421,12 @@ void launch_face(const int32_t *list, int64_t cnt, const int32_t *best_j, int32_
                  unsigned int *zero = nullptr, int nzero = 0);
 void launch_select_fallback(int64_t n, const float *best_s, const int32_t *best_j, const float *znorm,
                             float thr, int32_t *out, unsigned int *count, hipStream_t s);
-// launch_best_keys (mode 1, every voxel) and launch_select_fallback in one pass.
+// launch_best_keys (mode 1, every voxel) and launch_select_fallback in one
+// pass; with fin, the voxels that do not fall back are also finished
+// (finish_single; the fallbacks are finished by launch_scatter_best).
 void launch_best_select(int64_t n, const unsigned long long *keys, float *best_s, int32_t *best_j,
-                        const float *znorm, float thr, int32_t *out, unsigned int *count, hipStream_t s);
+                        const float *znorm, float thr, int32_t *out, unsigned int *count, hipStream_t s,
+                        const FinishArgs *fin = nullptr);
 void launch_gather_rows(const float *Zp, int Kp, const int32_t *list, int64_t cnt, int64_t cnt_pad,
                         float *out, hipStream_t s);
 // rows list[i] for i < *dcnt (<= cap), zero rows up to the next multiple of
@@ -433,9 +437,11 @@ void launch_learned_prep(const LearnedPrep &p, int64_t n, hipStream_t s);
 void launch_add_count(unsigned long long *total, const unsigned int *count, hipStream_t s);
 // With dcnt: cnt is the capacity (also the part stride) and the splits are
 // those launch_score_x3_dev chose for the device count (ntiles = d_pad / 256).
+// fin (optional): each listed voxel also finished (finish_single) from its
+// merged best, in place of a later merge pass.
 void launch_scatter_best(const int32_t *list, int64_t cnt, const float *part_s, const int *part_j,
                          int splits, float *best_s, int32_t *best_j, hipStream_t s,
-                         const unsigned int *dcnt = nullptr, int ntiles = 0);
+                         const unsigned int *dcnt = nullptr, int ntiles = 0, const FinishArgs *fin = nullptr);
 void launch_iota(int32_t *x, int64_t n, hipStream_t s);
 }  // namespace mrf
 

@@ -703,6 +703,14 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   }
   // unpacked here, or by the fallback selection below in the same pass
   const bool unpack_with_select = !warm && thr >= 0.f;
+  // without a warm start or the certificate, the selection finishes the
+  // voxels that do not fall back and the fallback's scatter the others, in
+  // place of the closing merge pass
+  const bool cert = o->certify_local != 0;
+  const bool finish_early = unpack_with_select && !cert;
+  const FinishArgs fin{D->d, D->znorm.as<float>(), warm, D->inv_norm.as<float>(), D->params.as<float>(),
+                       D->nparam, idx, pd, corr, params_out, D->gamma.as<float>()};
+  const FinishArgs *fe = finish_early ? &fin : nullptr;
   if (!unpack_with_select) launch_best_keys(nullptr, n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), 1, s);
   // the previous atom competes (non-expansive safeguard of the inexact projection)
   launch_warm_best(warm, n, D->d, D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->znorm.as<float>(),
@@ -713,7 +721,6 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   int64_t nfb = 0;
   bool tree_ran = false;
   if (fallback_out) launch_zero(fallback_out, n * 4, s);
-  const bool cert = o->certify_local != 0;
   int32_t *fbflag = nullptr;  // certified: the exhaustive fallbacks, for the rescan
   if (cert) {
     TRY(grow(D->lc_fb, (size_t)n * 4));
@@ -726,7 +733,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
   if (thr >= 0.f) {
     if (unpack_with_select)
       launch_best_select(n, bkey, D->best_s.as<float>(), D->best_j.as<int32_t>(), D->znorm.as<float>(), thr, la,
-                         count, s);
+                         count, s, fe);
     else
       launch_select_fallback(n, D->best_s.as<float>(), D->best_j.as<int32_t>(), D->znorm.as<float>(), thr,
                              la, count, s);
@@ -744,7 +751,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
       launch_score_x3_dev(D->dx3.as<uint16_t>(), D->rows.as<uint16_t>(), D->d, D->d_pad, n, count, D->Kx,
                           D->part_s.as<float>(), D->part_j.as<int>(), s);
       launch_scatter_best(la, n, D->part_s.as<float>(), D->part_j.as<int>(), 1, D->best_s.as<float>(),
-                          D->best_j.as<int32_t>(), s, count, (int)(D->d_pad / 256));
+                          D->best_j.as<int32_t>(), s, count, (int)(D->d_pad / 256), fe);
       if (fallback_out) launch_mark(la, n, fallback_out, s, count);
       if (fbflag) launch_mark(la, n, fbflag, s, count);
       LAUNCH_CHECK("fallback (sized on the device)");
@@ -778,7 +785,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
                       D->fb_s.as<float>(), D->fb_j.as<int32_t>(), D->list_c, D->rows, D->part_s, D->part_j, nullptr,
                       s));
       launch_scatter_best(la, nfb, D->fb_s.as<float>(), D->fb_j.as<int>(), 1, D->best_s.as<float>(),
-                          D->best_j.as<int32_t>(), s);
+                          D->best_j.as<int32_t>(), s, nullptr, 0, fe);
       if (fallback_out) launch_mark(la, nfb, fallback_out, s);
       if (fbflag) launch_mark(la, nfb, fbflag, s);
       LAUNCH_CHECK("fallback (cover tree)");
@@ -808,7 +815,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
                          splits, D->part_s.as<float>(), D->part_j.as<int>(), s);
       }
       launch_scatter_best(la, nfb, D->part_s.as<float>(), D->part_j.as<int>(), splits,
-                          D->best_s.as<float>(), D->best_j.as<int32_t>(), s);
+                          D->best_s.as<float>(), D->best_j.as<int32_t>(), s, nullptr, 0, fe);
       if (fallback_out) launch_mark(la, nfb, fallback_out, s);
       if (fbflag) launch_mark(la, nfb, fbflag, s);
       LAUNCH_CHECK("fallback");
@@ -860,7 +867,7 @@ mrf_status match_learned(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, cons
                              D->cert_cand.as<int32_t>(), kCertCap, out, s);
     launch_scan_exact(D->zp.as<float>(), D->dhat.as<float>(), D->Kp, D->K, D->d, n, q, out, s);
     LAUNCH_CHECK("local certificate rescore");
-  } else {
+  } else if (!finish_early) {
     launch_merge_argmax(D->best_s.as<float>(), D->best_j.as<int>(), 1, n, D->d, D->znorm.as<float>(), warm,
                         D->inv_norm.as<float>(), D->params.as<float>(), D->nparam, idx, pd, corr, params_out,
                         D->gamma.as<float>(), s);
