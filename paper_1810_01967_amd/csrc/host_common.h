@@ -88,9 +88,11 @@ mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
                       int32_t *idx, float *pd, float *corr, float *params_out, hipStream_t s,
                       hipEvent_t ev_s0, hipEvent_t ev_s1, int *splits_used, mrf_match_stats *st);
 // want_fp32 = false leaves out the FP32 rows of a voxel-major packing that
-// writes the split rows (see learned_split_rows_only)
+// writes the split rows (see learned_split_rows_only); want_counts: the zero
+// and non-finite rows counted into D->counters (read back for statistics)
 mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t slice_voxels,
-                       int64_t n, hipStream_t s, bool want_x3 = false, bool want_fp32 = true);
+                       int64_t n, hipStream_t s, bool want_x3 = false, bool want_fp32 = true,
+                       bool want_counts = true);
 // True when a learned match reads the voxels only as split-BF16 rows: split
 // BF16 scoring, no warm start, no cover-tree fallback, and (unless the
 // caller gives the cells) a network whose BF16 form reads the split rows.

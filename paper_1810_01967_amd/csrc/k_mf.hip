@@ -87,8 +87,10 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major(const float2 *__restri
     const float zn = fin ? (float)sqrt(acc) : -1.f;
     znorm[v] = zn;
     if (inv) inv[v] = zn > 0.f ? 1.f / zn : 0.f;  // as k_inv_norm
-    if (!fin) atomicAdd(&counters[1], 1ull);
-    else if (acc == 0.0) atomicAdd(&counters[0], 1ull);
+    if (counters) {  // counted only where the caller reads the counts
+      if (!fin) atomicAdd(&counters[1], 1ull);
+      else if (acc == 0.0) atomicAdd(&counters[0], 1ull);
+    }
   }
 }
 
@@ -166,8 +168,10 @@ __global__ __launch_bounds__(256) void k_pack_voxel_major2(const float2 *__restr
     const float zn = fin ? (float)sqrt(acc) : -1.f;
     znorm[v] = zn;
     if (inv) inv[v] = zn > 0.f ? 1.f / zn : 0.f;  // as k_inv_norm
-    if (!fin) atomicAdd(&counters[1], 1ull);
-    else if (acc == 0.0) atomicAdd(&counters[0], 1ull);
+    if (counters) {  // counted only where the caller reads the counts
+      if (!fin) atomicAdd(&counters[1], 1ull);
+      else if (acc == 0.0) atomicAdd(&counters[0], 1ull);
+    }
   }
 }
 
@@ -273,8 +277,10 @@ __global__ __launch_bounds__(256) void k_pack_frame_major(const float2 *__restri
     const double s = red[0][vi] + red[1][vi] + red[2][vi] + red[3][vi];
     const bool fin = isfinite(s);
     znorm[v] = fin ? (float)sqrt(s) : -1.f;
-    if (!fin) atomicAdd(&counters[1], 1ull);
-    else if (s == 0.0) atomicAdd(&counters[0], 1ull);
+    if (counters) {  // counted only where the caller reads the counts
+      if (!fin) atomicAdd(&counters[1], 1ull);
+      else if (s == 0.0) atomicAdd(&counters[0], 1ull);
+    }
   }
 }
 

@@ -534,7 +534,7 @@ mrf_status match_core(mrf_dict_s *D, const mrf_match_opts *o, int64_t n, const i
 }
 
 mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t slice_voxels,
-                       int64_t n, hipStream_t s, bool want_x3, bool want_fp32) {
+                       int64_t n, hipStream_t s, bool want_x3, bool want_fp32, bool want_counts) {
   const int64_t n_pad = round_up(n, kRowPad);
   // the voxel-major packing may leave out the FP32 rows (split rows only);
   // the frame-major one always writes them
@@ -549,8 +549,9 @@ mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t s
     zx3 = D->zx3.as<uint16_t>();
   }
   TRY(grow(D->znorm, (size_t)n_pad * 4));
-  TRY(grow(D->counters, 64));  // [0] zero rows, [1] non-finite rows, [2] local-search work
-  launch_zero(D->counters.p, 16, s);
+  TRY(grow(D->counters, 64));  // [0] zero rows, [1] non-finite rows
+  unsigned long long *counters = want_counts ? D->counters.as<unsigned long long>() : nullptr;
+  if (counters) launch_zero(counters, 16, s);
   const int real = D->is_complex ? 0 : 1;
   const float2 *vph = nullptr;
   if (D->align) {  // phase-aligned dictionary: voxel phases first, packed rotated
@@ -567,12 +568,12 @@ mrf_status pack_voxels(mrf_dict_s *D, const void *Z, int32_t z_layout, int64_t s
     // the network's row scale comes with the norms (learned matching reads it)
     TRY(grow(D->inv, (size_t)n * 4));
     launch_pack_voxel_major(static_cast<const float2 *>(Z), n, n_pad, D->L, real, D->Kp,
-                            want_fp32 ? D->zp.as<float>() : nullptr, D->znorm.as<float>(),
-                            D->counters.as<unsigned long long>(), s, vph, zx3, D->Kx, D->inv.as<float>());
+                            want_fp32 ? D->zp.as<float>() : nullptr, D->znorm.as<float>(), counters, s, vph,
+                            zx3, D->Kx, D->inv.as<float>());
   } else
     launch_pack_frame_major(static_cast<const float2 *>(Z), nullptr, 0.f, n, n_pad, slice_voxels,
-                            D->L, real, D->Kp, D->zp.as<float>(), D->znorm.as<float>(),
-                            D->counters.as<unsigned long long>(), s, vph, zx3, D->Kx);
+                            D->L, real, D->Kp, D->zp.as<float>(), D->znorm.as<float>(), counters, s, vph, zx3,
+                            D->Kx);
   LAUNCH_CHECK("pack");
   D->zx3_fresh = want_x3;
   D->zp_fresh = want_fp32;
@@ -609,7 +610,8 @@ extern "C" mrf_status mrf_match(mrf_dict D, const mrf_match_opts *opts, int64_t 
   }
   const int real = D->is_complex ? 0 : 1;
   const bool want_x3 = opts && opts->precision == MRF_BF16X3 && opts->method != MRF_COVERTREE;
-  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s, want_x3, !learned_split_rows_only(D, opts, warm_idx, false)));
+  TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s, want_x3, !learned_split_rows_only(D, opts, warm_idx, false),
+                  stats != nullptr));
   int splits_used = 0;
   TRY(match_core(D, opts, n, warm_idx, idx, pd, corr, params_out, s, ev.c, ev.d, &splits_used, stats));
   const float2 *vph = D->align ? D->vphase.as<float2>() : nullptr;
@@ -911,12 +913,10 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
   const int real = D->is_complex ? 0 : 1;
   TRY(grow(D->zp, (size_t)n_pad * D->Kp * 4));
   TRY(grow(D->znorm, (size_t)n_pad * 4));
-  TRY(grow(D->counters, 64));
   TRY(grow(D->kbuf, (size_t)nimg * npix * 8));
   TRY(grow(D->abuf, (size_t)(od.nsamp > 0 ? od.nsamp : 1) * 8));
   TRY(grow(D->red, (size_t)(8192 + 2 * nvp + 8) * 8));
   TRY(grow(D->scal, 64));
-  launch_zero(D->counters.p, 16, s);
   const float2 *vph = nullptr;
   if (D->align) {  // phase-aligned projection of Z = X - mu G
     TRY(grow(D->vphase, (size_t)n * 8));
@@ -928,9 +928,8 @@ mrf_status trial(mrf_dict_s *D, const mrf_op *A, const mrf_match_opts *o, const 
   const bool want_x3 = o && o->precision == MRF_BF16X3 && o->method != MRF_COVERTREE;
   if (want_x3) TRY(grow(D->zx3, (size_t)n_pad * 2 * D->Kx * 2));
   launch_pack_frame_major(X, D->gbuf.as<float2>(), mu, n, n_pad, npix, D->L, real, D->Kp,
-                          D->zp.as<float>(), D->znorm.as<float>(),
-                          D->counters.as<unsigned long long>(), s, vph,
-                          want_x3 ? D->zx3.as<uint16_t>() : nullptr, D->Kx);
+                          D->zp.as<float>(), D->znorm.as<float>(), nullptr, s, vph,
+                          want_x3 ? D->zx3.as<uint16_t>() : nullptr, D->Kx);  // row counts not read here
   LAUNCH_CHECK("grad_update_pack");
   D->zx3_fresh = want_x3;
   D->zp_fresh = true;

@@ -51,7 +51,8 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // Pack voxel rows into the padded FP32 contraction layout [n_pad][Kp]:
 // complex atoms -> interleaved (re, im) rows of length 2L; real atoms -> Re(Z)
 // rows of length L.  znorm[v] = ||Z_v|| (complex norm, FP64 accumulation),
-// -1 for a non-finite row.  counters[0] += zero rows, counters[1] += non-finite.
+// -1 for a non-finite row.  counters (may be null: not counted)[0] += zero rows,
+// counters[1] += non-finite.
 // Frame-major input: Zf[s][L][npix]; with G != nullptr the packed value is
 // X - mu*G (the gradient update of eq. blip), G in the same layout as X.
 // vphase (optional, [n]): unit factors e^{i theta_v}; each voxel is packed

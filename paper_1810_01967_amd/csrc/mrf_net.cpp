@@ -931,7 +931,7 @@ extern "C" mrf_status mrf_match_local(mrf_dict D, const mrf_match_opts *opts, in
     HIP_TRY(hipEventRecord(ev.a, s));
   }
   TRY(pack_voxels(D, Z, z_layout, slice_voxels, n, s, opts && opts->precision == MRF_BF16X3,
-                  !learned_split_rows_only(D, opts, warm_idx, true)));
+                  !learned_split_rows_only(D, opts, warm_idx, true), stats != nullptr));
   TRY(match_learned(D, opts, n, warm_idx, idx, pd, corr, params_out, cells, fallback, stats, s));
   if (X_out) {
     launch_write_x(idx, D->gamma.as<float>(), D->dhat.as<float>(), D->Kp, D->is_complex ? 0 : 1, n, D->L,
